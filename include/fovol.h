@@ -1,0 +1,248 @@
+/*
+ * fovol.h -- C ABI of libfovol.so: foveated sparse direct volume rendering
+ * with neural full-frame reconstruction on AMD Instinct MI355X (gfx950).
+ *
+ * Method: FoVolNet (Bauer, Wu, Ma; arXiv 2209.09965).  The pipeline renders
+ * only the pixels selected by a fovea-weighted sample map, packs them with
+ * stream compaction, ray-marches the packed list, scatters the results back
+ * to the full frame and lets a small network reconstruct the missing pixels
+ * (paper: Methods, "Foveated Rendering", "Sample Maps", "Stream Compaction",
+ * "Reconstruction Network").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Plain C: no C++ types, no exceptions cross this boundary.
+ *  - Every data pointer documented "dev" is caller-owned device memory
+ *    (hipMalloc or a framework allocator).  The library never frees or keeps
+ *    a caller pointer beyond the work it enqueues.  "host" pointers are read
+ *    (or written) synchronously during the call.
+ *  - `stream` is a hipStream_t passed as void*; NULL is the null stream.
+ *    All compute calls only enqueue work and return; results are valid after
+ *    the caller synchronises that stream.
+ *  - Argument errors are detected on the host before anything is enqueued;
+ *    the call then returns a negative fv_status and fv_last_error() holds a
+ *    message.  A launch failure reported by the HIP runtime returns
+ *    FV_ERR_DEVICE.
+ *  - Pixel index convention: a pixel (x, y) of view v in a views x H x W
+ *    frame stack has linear index  idx = v*W*H + y*W + x.  Frame buffers are
+ *    "pixel-major": frame_rgba[idx*4 + c], frame_depth[idx].
+ *  - Thread safety: separate handles may be used from different host
+ *    threads; one handle must not be used by two calls at the same time.
+ */
+#ifndef FOVOL_H
+#define FOVOL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FV_ABI_VERSION 1
+
+typedef enum {
+  FV_OK = 0,
+  FV_ERR_INVALID_ARG = -1, /* null pointer, bad size, out-of-range parameter */
+  FV_ERR_CAPACITY = -2,    /* an output capacity is too small                 */
+  FV_ERR_UNSUPPORTED = -3, /* unknown dtype / mode / precision                */
+  FV_ERR_DEVICE = -4,      /* the HIP runtime reported an error               */
+  FV_ERR_NOMEM = -5        /* a library-owned allocation failed               */
+} fv_status;
+
+/* Message for the last failing call on this host thread ("" if none).  The
+ * pointer stays valid until the next call on the same thread. */
+const char* fv_last_error(void);
+int fv_abi_version(void);
+
+typedef enum { FV_U8 = 0, FV_F16 = 1, FV_F32 = 2 } fv_dtype;
+
+/* ------------------------------------------------------------------------
+ * 1. Sample map and stream compaction
+ *    (paper: "Sample Maps", Eq. (1) and (2); "Stream Compaction")
+ * ------------------------------------------------------------------------
+ * The sample map is M(x,y) = [N(x,y) < tau(x,y)].
+ *
+ *  N   Seeded white noise: u = H32(seed, frame, view, y, x) >> 8, a 24-bit
+ *      integer, where H32 chains the MurmurHash3 32-bit finaliser over the
+ *      key words (seed low, seed high, frame, view, y, x), starting from
+ *      0x6A09E667: h = fmix32(h ^ word) for each word in that order.  The
+ *      paper draws N from pre-computed spatio-temporal blue-noise tiles; a
+ *      counter-based hash stands in for them (random access, reproducible
+ *      from the seed, a new pattern every frame).
+ *  tau The fovea density (Eq. 1) is read as a Gaussian fall-off of the
+ *      pixel's distance r to the focal point, g = exp(-r^2 / (2 s^2)) with
+ *      s = sigma_px.  It is combined with the base density p = p_floor by
+ *      either  FV_FOVEA_LERP:  tau = (1 - p) g + p      (Eq. 2), or
+ *              FV_FOVEA_CLAMP: tau = max(g, p).
+ *  Quantisation (makes the mask bit-reproducible on host and device):
+ *      distances use doubled pixel coordinates, R = (2x+1-F2x)^2 +
+ *      (2y+1-F2y)^2 with F2 = llround(2*focus) (R/4 = r^2 in px^2).
+ *      T(R) = min(2^24, floor(tau(R) * 2^24)) evaluated in IEEE double,
+ *      T_inf = min(2^24, floor(p * 2^24)).  The table holds T_k = T(k << sh)
+ *      for k < n; bins k >= n use T_inf.  sh is the smallest shift for which
+ *      n <= FV_LUT_MAX, where n = the first k with T(k << sh) == T_inf,
+ *      capped at (R_max >> sh) + 1 and R_max is the largest R in the frame.
+ *      M = [u < T_{R >> sh}]   (strict, as in the paper's N < tau).
+ *  Compaction order: view-major, then 8x8 screen tiles in row-major tile
+ *      order, then row-major inside a tile (edge tiles are clipped to the
+ *      frame).  ray_idx[i] is the linear pixel index of the i-th selected
+ *      pixel in that order; count = number of selected pixels.
+ */
+#define FV_LUT_MAX 16384
+
+typedef enum { FV_FOVEA_CLAMP = 0, FV_FOVEA_LERP = 1 } fv_fovea_mode;
+
+typedef struct {
+  uint64_t seed;
+  uint32_t frame;   /* animation frame, part of the noise key              */
+  int32_t mode;     /* fv_fovea_mode                                       */
+  float focus_x;    /* focal point in pixels; pixel (x,y) spans [x,x+1)    */
+  float focus_y;    /*   x [y,y+1); the frame centre is (W/2, H/2)         */
+  float sigma_px;   /* s > 0, Gaussian fall-off in pixels                  */
+  float p_floor;    /* base density p in [0, 1]                            */
+} fv_fovea_params;
+
+/* Threshold table of the sample map (host; a test hook and a diagnostic).
+ * host_lut must hold FV_LUT_MAX entries; n_entries, shift and t_inf receive
+ * n, sh and T_inf.  Errors: FV_ERR_INVALID_ARG for null pointers, width or
+ * height <= 0, sigma_px <= 0 or not finite, p_floor outside [0,1], focus not
+ * finite or outside [0,W]x[0,H]; FV_ERR_UNSUPPORTED for an unknown mode. */
+fv_status fv_fovea_lut(const fv_fovea_params* p, int width, int height,
+                       uint32_t* host_lut, int* n_entries, int* shift,
+                       uint32_t* t_inf);
+
+/* Bytes of device workspace fv_fovea_mask needs for this frame stack. */
+fv_status fv_fovea_mask_workspace(int width, int height, int views,
+                                  size_t* bytes);
+
+/* Sample map + ordered stream compaction for `views` frames of W x H that
+ * share the fovea parameters (the view index is part of the noise key).
+ *   mask      dev uint8 [views*H*W] (1 = sampled) or NULL to skip
+ *   ray_idx   dev uint32 [capacity]; entries [0, count) are written
+ *   capacity  must be >= views*W*H (so the device can never overflow it);
+ *             otherwise FV_ERR_CAPACITY
+ *   count     dev uint32 [1]; written, stays on the device
+ *   workspace dev, >= fv_fovea_mask_workspace() bytes, 256-byte aligned;
+ *             contents on entry are ignored
+ * Errors: as fv_fovea_lut, plus views <= 0, views*W*H >= 2^32, null ray_idx,
+ * count or workspace, and a workspace that is too small (FV_ERR_CAPACITY). */
+fv_status fv_fovea_mask(const fv_fovea_params* p, int width, int height,
+                        int views, uint8_t* mask, uint32_t* ray_idx,
+                        uint32_t capacity, uint32_t* count, void* workspace,
+                        size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * 2. Volume
+ * ------------------------------------------------------------------------
+ * World space: the volume's box is centred at the origin and its longest
+ * side has length 1, so a voxel has edge h = 1/max(nx,ny,nz); voxel (i,j,k)
+ * has its centre at ((i+0.5)h - nx*h/2, (j+0.5)h - ny*h/2, (k+0.5)h - nz*h/2).
+ * Scalars: u8 maps to v/255, f16 and f32 are taken as they are.
+ *
+ * fv_volume_create copies a caller-owned linear device array (x fastest,
+ * then y, then z; nx*ny*nz elements of `dt`) into a library-owned
+ * layout on the stream, then synchronises that stream.  The handle owns that copy until
+ * fv_volume_destroy.  Errors: null pointers, any dimension < 1 or > 4096,
+ * unknown dtype (FV_ERR_UNSUPPORTED), allocation failure (FV_ERR_NOMEM). */
+typedef struct fv_volume fv_volume;
+
+fv_status fv_volume_create(const void* dev_data, int nx, int ny, int nz,
+                           fv_dtype dt, void* stream, fv_volume** out);
+fv_status fv_volume_destroy(fv_volume* v);
+
+/* ------------------------------------------------------------------------
+ * 3. Ray marching (paper: "Foveated Rendering", "Rendering", "Stream
+ *    Compaction" -- the renderer that samples the packed pixel list)
+ * ------------------------------------------------------------------------
+ * Per pixel ray (pinhole camera):
+ *   f = normalize(target-eye), r = normalize(f x up), u = r x f,
+ *   px = (2(x+0.5)/W - 1) tan(fovy/2) W/H,  py = (1 - 2(y+0.5)/H) tan(fovy/2),
+ *   d = normalize(f + px r + py u),  origin = eye + eye_offset * r.
+ * Box entry/exit by the slab method: [t0, t1], t0 clamped to >= 0; a miss
+ * (t1 <= t0) gives RGB = bg, A = 0, depth = 0.
+ * Segments: L = (t1-t0)/h voxel lengths are cut into N = ceil(L/step_vox)
+ * segments [k*step, min((k+1)*step, L)]; segment k (length l_k) is sampled at
+ * its midpoint.  Sampling: clamp-to-edge trilinear interpolation in voxel
+ * index space.  Transfer function: 256 x (r, g, b, sigma) float entries,
+ * looked up with linear interpolation at x = clamp(v,0,1)*255; sigma is an
+ * extinction per voxel length and the segment opacity is
+ * alpha_k = 1 - exp(-sigma * l_k).
+ * Shading (shading != 0): gradient by one-voxel central differences of the
+ * interpolated field, n = -grad / max(|grad|, 1e-4), L = normalize(light_dir),
+ * V = -d, Hv = normalize(L + V),
+ * c = rgb (ka + kd |n.L|) + ks |n.Hv|^shininess.
+ * Compositing front to back in FP32 with early termination:
+ *   w = T alpha_k; C += w c; D += w t_k; T *= (1 - alpha_k);
+ *   stop once 1 - T >= alpha_stop.
+ * Output RGB = C + T bg, A = 1 - T, depth = D (world units, premultiplied by
+ * opacity).
+ *
+ * The dense and the sparse march run the same per-ray device code, so a
+ * sparse pixel equals the dense pixel at the same index bit for bit.
+ */
+typedef struct {
+  float eye[3];
+  float target[3];
+  float up[3];
+  float fovy_deg;    /* vertical field of view, (0, 180)                  */
+  float eye_offset;  /* origin shift along the camera's right axis        */
+} fv_camera;
+
+typedef struct {
+  float step_vox;    /* segment length in voxels, > 0                     */
+  float alpha_stop;  /* early-termination opacity, in (0, 1]              */
+  int32_t shading;   /* 0 = emission-absorption only, 1 = Blinn-Phong     */
+  float light_dir[3];/* direction towards the light (non-zero)            */
+  float ka, kd, ks, shininess;
+  float bg[3];       /* background colour                                 */
+} fv_march_params;
+
+#define FV_TF_ENTRIES 256
+
+/* Full-frame march: every pixel of `views` frames.
+ *   tf_rgba      dev float [256*4]  (r, g, b, sigma) per entry
+ *   cams         host [views] cameras
+ *   frame_rgba   dev float [views*H*W*4]
+ *   frame_depth  dev float [views*H*W] or NULL
+ *   sample_count dev uint64 [1] or NULL; if given, the number of composited
+ *                samples (segments, counting the terminating one) is ADDED
+ *                to it (the caller clears it)
+ * Errors: null v/tf/cams/params/frame_rgba, width/height/views <= 0,
+ * views*W*H >= 2^32, tf_n != 256, step_vox <= 0 or > 64, alpha_stop outside
+ * (0,1], a zero light_dir with shading, non-finite camera, fovy outside
+ * (0,180) or eye == target. */
+fv_status fv_raymarch_dense(const fv_volume* v, const float* tf_rgba, int tf_n,
+                            const fv_camera* cams, int views, int width,
+                            int height, const fv_march_params* mp,
+                            float* frame_rgba, float* frame_depth,
+                            uint64_t* sample_count, void* stream);
+
+/* Bytes of device workspace fv_raymarch_sparse needs. */
+fv_status fv_raymarch_sparse_workspace(size_t* bytes);
+
+/* Sparse march over the compacted list written by fv_fovea_mask.  `count`
+ * is read on the device (no host synchronisation).  For i < *count the ray
+ * of pixel ray_idx[i] is marched; its result goes to
+ *   rgba_compact[i*4..]/depth_compact[i]   (dev, [capacity*4]/[capacity], or NULL)
+ *   frame_rgba[ray_idx[i]*4..]/frame_depth[ray_idx[i]]  (dev, full frame, or NULL)
+ * (back-projection).  Frame pixels not in the list are left untouched: clear
+ * the frame first to get the sparse image.  Entries of ray_idx must be
+ * < views*W*H (they are checked on the device; a bad entry is skipped).
+ *   workspace  dev, >= fv_raymarch_sparse_workspace() bytes, 256-byte aligned
+ * Errors: as fv_raymarch_dense, plus null ray_idx/count/workspace, capacity
+ * == 0 or > views*W*H, and all four outputs NULL. */
+fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba,
+                             int tf_n, const fv_camera* cams, int views,
+                             int width, int height, const fv_march_params* mp,
+                             const uint32_t* ray_idx, const uint32_t* count,
+                             uint32_t capacity, float* rgba_compact,
+                             float* depth_compact, float* frame_rgba,
+                             float* frame_depth, uint64_t* sample_count,
+                             void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FOVOL_H */
