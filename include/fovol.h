@@ -82,7 +82,9 @@ typedef enum { FV_U8 = 0, FV_F16 = 1, FV_F32 = 2 } fv_dtype;
  *      T_inf = min(2^24, floor(p * 2^24)).  The table holds T_k = T(k << sh)
  *      for k < n; bins k >= n use T_inf.  sh is the smallest shift for which
  *      n <= FV_LUT_MAX, where n = the first k with T(k << sh) == T_inf,
- *      capped at (R_max >> sh) + 1 and R_max is the largest R in the frame.
+ *      capped at (R_max >> sh) + 1 with R_max = (2W-1)^2 + (2H-1)^2 (the
+ *      largest R of any pixel for any focus in the frame).  The table thus
+ *      depends on (sigma_px, p_floor, mode, W, H) and not on the focus.
  *      M = [u < T_{R >> sh}]   (strict, as in the paper's N < tau).
  *  Compaction order: view-major, then 8x8 screen tiles in row-major tile
  *      order, then row-major inside a tile (edge tiles are clipped to the
@@ -190,7 +192,7 @@ typedef struct {
 } fv_camera;
 
 typedef struct {
-  float step_vox;    /* segment length in voxels, > 0                     */
+  float step_vox;    /* segment length in voxels, in [1/64, 64]           */
   float alpha_stop;  /* early-termination opacity, in (0, 1]              */
   int32_t shading;   /* 0 = emission-absorption only, 1 = Blinn-Phong     */
   float light_dir[3];/* direction towards the light (non-zero)            */
@@ -209,9 +211,10 @@ typedef struct {
  *                samples (segments, counting the terminating one) is ADDED
  *                to it (the caller clears it)
  * Errors: null v/tf/cams/params/frame_rgba, width/height/views <= 0,
- * views*W*H >= 2^32, tf_n != 256, step_vox <= 0 or > 64, alpha_stop outside
- * (0,1], a zero light_dir with shading, non-finite camera, fovy outside
- * (0,180) or eye == target. */
+ * views > 8, views*W*H >= 2^32, W or H > 65535, tf_n != 256, step_vox
+ * outside [1/64, 64], alpha_stop outside (0,1], a zero light_dir with
+ * shading, shading not 0/1 (FV_ERR_UNSUPPORTED), non-finite camera, fovy
+ * outside (0,180), eye == target or up parallel to the view direction. */
 fv_status fv_raymarch_dense(const fv_volume* v, const float* tf_rgba, int tf_n,
                             const fv_camera* cams, int views, int width,
                             int height, const fv_march_params* mp,

@@ -77,11 +77,10 @@ static uint32_t or_tau_q(double R, double sigma, double p_floor, int mode) {
 
 static int64_t or_round_half_away(double v) { return (int64_t)llround(v); }
 
-/* Largest R over the pixel centres of a W x H frame. */
-static int64_t or_rmax(int W, int H, int64_t f2x, int64_t f2y) {
-  int64_t ax = llabs(1 - f2x), bx = llabs((int64_t)2 * W - 1 - f2x);
-  int64_t ay = llabs(1 - f2y), by = llabs((int64_t)2 * H - 1 - f2y);
-  int64_t mx = ax > bx ? ax : bx, my = ay > by ? ay : by;
+/* Bound on R for any pixel centre of a W x H frame and any focus inside
+ * [0,W]x[0,H]: |2x+1-F2x| <= 2W-1 and |2y+1-F2y| <= 2H-1. */
+static int64_t or_rmax(int W, int H) {
+  int64_t mx = (int64_t)2 * W - 1, my = (int64_t)2 * H - 1;
   return mx * mx + my * my;
 }
 
@@ -91,9 +90,9 @@ static int64_t or_rmax(int W, int H, int64_t f2x, int64_t f2y) {
 int or_fovea_lut(int W, int H, double focus_x, double focus_y, double sigma,
                  double p_floor, int mode, uint32_t* lut, int* n_out,
                  int* sh_out, uint32_t* tinf_out) {
-  int64_t f2x = or_round_half_away(2.0 * focus_x);
-  int64_t f2y = or_round_half_away(2.0 * focus_y);
-  int64_t rmax = or_rmax(W, H, f2x, f2y);
+  (void)focus_x;
+  (void)focus_y; /* the table does not depend on the focus */
+  int64_t rmax = or_rmax(W, H);
   double tinf_d = floor(p_floor * OR_ONE24);
   if (tinf_d > OR_ONE24) tinf_d = OR_ONE24;
   uint32_t tinf = (uint32_t)tinf_d;

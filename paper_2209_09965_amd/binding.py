@@ -1,0 +1,229 @@
+"""Thin ctypes binding of libfovol.so (argument marshalling only).
+
+Every function here forwards to the C ABI declared in ``include/fovol.h``;
+device buffers are torch tensors (PyTorch supplies device memory and
+streams), passed by ``data_ptr()``.  The library must be built
+(``python -m paper_2209_09965_amd._build``); importing this module without it
+raises: there is no fallback path.
+"""
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfovol.so")
+
+FV_OK = 0
+FV_ERR_INVALID_ARG = -1
+FV_ERR_CAPACITY = -2
+FV_ERR_UNSUPPORTED = -3
+FV_ERR_DEVICE = -4
+FV_ERR_NOMEM = -5
+DTYPE_CODES = {torch.uint8: 0, torch.float16: 1, torch.float32: 2}
+
+
+class FvError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("fovol status %d: %s" % (status, msg))
+        self.status = status
+
+
+class FoveaParams(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("frame", ctypes.c_uint32), ("mode", ctypes.c_int32),
+                ("focus_x", ctypes.c_float), ("focus_y", ctypes.c_float),
+                ("sigma_px", ctypes.c_float), ("p_floor", ctypes.c_float)]
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("eye", ctypes.c_float * 3), ("target", ctypes.c_float * 3),
+                ("up", ctypes.c_float * 3), ("fovy_deg", ctypes.c_float),
+                ("eye_offset", ctypes.c_float)]
+
+
+class MarchParams(ctypes.Structure):
+    _fields_ = [("step_vox", ctypes.c_float), ("alpha_stop", ctypes.c_float),
+                ("shading", ctypes.c_int32), ("light_dir", ctypes.c_float * 3),
+                ("ka", ctypes.c_float), ("kd", ctypes.c_float), ("ks", ctypes.c_float),
+                ("shininess", ctypes.c_float), ("bg", ctypes.c_float * 3)]
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libfovol.so is not built (run python -m paper_2209_09965_amd._build); "
+                      "there is no fallback implementation")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_i = ctypes.c_int
+_u32 = ctypes.c_uint32
+
+_SIGS = {
+    "fv_last_error": (ctypes.c_char_p, []),
+    "fv_abi_version": (_i, []),
+    "fv_fovea_lut": (_i, [ctypes.POINTER(FoveaParams), _i, _i, _vp, ctypes.POINTER(_i),
+                          ctypes.POINTER(_i), ctypes.POINTER(_u32)]),
+    "fv_fovea_mask_workspace": (_i, [_i, _i, _i, ctypes.POINTER(_sz)]),
+    "fv_fovea_mask": (_i, [ctypes.POINTER(FoveaParams), _i, _i, _i, _vp, _vp, _u32, _vp, _vp, _sz,
+                           _vp]),
+    "fv_volume_create": (_i, [_vp, _i, _i, _i, _i, _vp, ctypes.POINTER(_vp)]),
+    "fv_volume_destroy": (_i, [_vp]),
+    "fv_raymarch_dense": (_i, [_vp, _vp, _i, ctypes.POINTER(Camera), _i, _i, _i,
+                               ctypes.POINTER(MarchParams), _vp, _vp, _vp, _vp]),
+    "fv_raymarch_sparse_workspace": (_i, [ctypes.POINTER(_sz)]),
+    "fv_raymarch_sparse": (_i, [_vp, _vp, _i, ctypes.POINTER(Camera), _i, _i, _i,
+                                ctypes.POINTER(MarchParams), _vp, _vp, _u32, _vp, _vp, _vp, _vp,
+                                _vp, _vp, _sz, _vp]),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def lib():
+    return _lib
+
+
+def last_error():
+    return _lib.fv_last_error().decode()
+
+
+def check(status):
+    if status != FV_OK:
+        raise FvError(status, last_error())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def fovea_params(p):
+    return FoveaParams(int(p.get("seed", 0)), int(p.get("frame", 0)), int(p.get("mode", 0)),
+                       float(p["focus_x"]), float(p["focus_y"]), float(p["sigma_px"]),
+                       float(p["p_floor"]))
+
+
+def camera(c):
+    cam = Camera()
+    for k in ("eye", "target", "up"):
+        getattr(cam, k)[:] = [float(v) for v in c[k]]
+    cam.fovy_deg = float(c["fovy_deg"])
+    cam.eye_offset = float(c.get("eye_offset", 0.0))
+    return cam
+
+
+def march_params(m):
+    mp = MarchParams()
+    mp.step_vox = float(m["step_vox"])
+    mp.alpha_stop = float(m["alpha_stop"])
+    mp.shading = int(m.get("shading", 0))
+    mp.light_dir[:] = [float(v) for v in m.get("light_dir", (1.0, 1.0, 1.0))]
+    mp.ka, mp.kd, mp.ks = float(m.get("ka", 0.2)), float(m.get("kd", 0.7)), float(m.get("ks", 0.3))
+    mp.shininess = float(m.get("shininess", 32.0))
+    mp.bg[:] = [float(v) for v in m.get("bg", (0.0, 0.0, 0.0))]
+    return mp
+
+
+# ------------------------------------------------------------------ sample map
+
+def fovea_lut(params, width, height):
+    """Host threshold table: (lut[n] uint32 numpy-compatible list, shift, t_inf)."""
+    import numpy as np
+    buf = np.zeros(16384, dtype=np.uint32)
+    n, sh, ti = _i(), _i(), _u32()
+    check(_lib.fv_fovea_lut(ctypes.byref(fovea_params(params)), width, height,
+                            ctypes.c_void_p(buf.ctypes.data), ctypes.byref(n), ctypes.byref(sh),
+                            ctypes.byref(ti)))
+    return buf[: n.value].copy(), sh.value, ti.value
+
+
+def fovea_mask_workspace(width, height, views):
+    b = _sz()
+    check(_lib.fv_fovea_mask_workspace(width, height, views, ctypes.byref(b)))
+    return b.value
+
+
+def fovea_mask(params, width, height, views, ray_idx, count, mask=None, workspace=None,
+               stream=None):
+    """Sample map + ordered compaction into ray_idx (uint32, capacity = its numel) and
+    count (uint32 [1]); optional mask (uint8 [views*H*W])."""
+    if workspace is None:
+        workspace = torch.empty(fovea_mask_workspace(width, height, views), dtype=torch.uint8,
+                                device=ray_idx.device)
+    check(_lib.fv_fovea_mask(ctypes.byref(fovea_params(params)), width, height, views,
+                             _ptr(mask), _ptr(ray_idx), ray_idx.numel(), _ptr(count),
+                             _ptr(workspace), workspace.numel(), _stream(stream)))
+
+
+# ---------------------------------------------------------------------- volume
+
+class Volume:
+    """Library-owned copy of a [nz, ny, nx] device tensor (uint8 / float16 / float32)."""
+
+    def __init__(self, data, stream=None):
+        if data.dim() != 3 or not data.is_cuda or data.dtype not in DTYPE_CODES:
+            raise ValueError("volume must be a 3-D uint8/float16/float32 CUDA tensor")
+        data = data.contiguous()
+        nz, ny, nx = data.shape
+        h = ctypes.c_void_p()
+        check(_lib.fv_volume_create(_ptr(data), nx, ny, nz, DTYPE_CODES[data.dtype],
+                                    _stream(stream), ctypes.byref(h)))
+        self.handle = h
+        self.shape = (nz, ny, nx)
+        self.dtype = data.dtype
+
+    def close(self):
+        if self.handle:
+            _lib.fv_volume_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _cams(cams):
+    arr = (Camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = camera(c)
+    return arr
+
+
+def raymarch_dense(vol, tf, cams, width, height, mp, frame_rgba, frame_depth=None,
+                   sample_count=None, stream=None):
+    """Full-frame march of len(cams) views into frame_rgba [views*H*W*4] f32."""
+    arr = _cams(cams)
+    check(_lib.fv_raymarch_dense(vol.handle, _ptr(tf), tf.numel() // 4, arr, len(cams), width,
+                                 height, ctypes.byref(march_params(mp)), _ptr(frame_rgba),
+                                 _ptr(frame_depth), _ptr(sample_count), _stream(stream)))
+
+
+def raymarch_sparse_workspace():
+    b = _sz()
+    check(_lib.fv_raymarch_sparse_workspace(ctypes.byref(b)))
+    return b.value
+
+
+def raymarch_sparse(vol, tf, cams, width, height, mp, ray_idx, count, rgba_compact=None,
+                    depth_compact=None, frame_rgba=None, frame_depth=None, sample_count=None,
+                    workspace=None, stream=None, capacity=None):
+    """March the compacted list (ray_idx, count) and back-project to the frame."""
+    if workspace is None:
+        workspace = torch.empty(raymarch_sparse_workspace(), dtype=torch.uint8,
+                                device=ray_idx.device)
+    arr = _cams(cams)
+    cap = ray_idx.numel() if capacity is None else capacity
+    check(_lib.fv_raymarch_sparse(vol.handle, _ptr(tf), tf.numel() // 4, arr, len(cams), width,
+                                  height, ctypes.byref(march_params(mp)), _ptr(ray_idx),
+                                  _ptr(count), cap, _ptr(rgba_compact), _ptr(depth_compact),
+                                  _ptr(frame_rgba), _ptr(frame_depth), _ptr(sample_count),
+                                  _ptr(workspace), workspace.numel(), _stream(stream)))

@@ -1,0 +1,54 @@
+// Internal helpers of libfovol (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+
+#include "fovol.h"
+
+namespace fv {
+
+// Records a message for fv_last_error() on this thread and returns `s`.
+fv_status fail(fv_status s, const char* fmt, ...);
+// Clears the thread's error message (start of every entry point).
+void clear_error();
+// Maps a HIP error to FV_ERR_DEVICE with a message, FV_OK otherwise.
+fv_status hip_status(hipError_t e, const char* what);
+// Checks the launch that was just enqueued.
+inline fv_status launch_status(const char* what) { return hip_status(hipGetLastError(), what); }
+
+constexpr int kWave = 64;
+
+// Voxel element conversion to float: u8 -> v/255, f16 and f32 as stored.
+template <int DT> struct Voxel;
+template <> struct Voxel<FV_U8> {
+  using T = uint8_t;
+  static __device__ __forceinline__ float f(T v) { return (float)v * (1.0f / 255.0f); }
+};
+template <> struct Voxel<FV_F16> {
+  using T = _Float16;
+  static __device__ __forceinline__ float f(T v) { return (float)v; }
+};
+template <> struct Voxel<FV_F32> {
+  using T = float;
+  static __device__ __forceinline__ float f(T v) { return v; }
+};
+
+inline size_t dtype_bytes(fv_dtype d) { return d == FV_U8 ? 1 : d == FV_F16 ? 2 : 4; }
+
+}  // namespace fv
+
+// Library-owned volume copy.  Storage: the scalar grid with a 2-voxel apron
+// of replicated edge voxels on every side (so clamp-to-edge sampling needs no
+// index clamps), x fastest.  Element (i, j, k) for i in [-2, nx+1] lives at
+// data[((k + 2) * py + (j + 2)) * px + (i + 2)], px = nx + 4, py = ny + 4.
+struct fv_volume {
+  int n[3];
+  fv_dtype dt;
+  int device;
+  void* data;
+  int64_t px, py, pz;
+};

@@ -1,0 +1,90 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared entry
+point, and rejects bad arguments on the host before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if h.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", h)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            names |= set(re.findall(r"\b(fv_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2209_09965_amd import binding
+    names = _declared()
+    assert len(names) >= 10
+    for n in sorted(names):
+        assert hasattr(binding.lib(), n), n
+
+
+def test_abi_version():
+    from paper_2209_09965_amd import binding
+    assert binding.lib().fv_abi_version() == 1
+
+
+def _fp(**kw):
+    d = dict(seed=1, frame=0, mode=0, focus_x=8.0, focus_y=8.0, sigma_px=4.0, p_floor=0.1)
+    d.update(kw)
+    return d
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(mode=7), -3), (dict(sigma_px=0.0), -1), (dict(sigma_px=float("nan")), -1),
+    (dict(p_floor=1.5), -1), (dict(p_floor=-0.1), -1), (dict(focus_x=-1.0), -1),
+    (dict(focus_y=17.0), -1),
+])
+def test_fovea_param_errors(kw, code):
+    from paper_2209_09965_amd import binding as b
+    lut = np.zeros(16384, np.uint32)
+    n, sh, ti = ctypes.c_int(), ctypes.c_int(), ctypes.c_uint32()
+    rc = b.lib().fv_fovea_lut(ctypes.byref(b.fovea_params(_fp(**kw))), 16, 16,
+                              ctypes.c_void_p(lut.ctypes.data), ctypes.byref(n), ctypes.byref(sh),
+                              ctypes.byref(ti))
+    assert rc == code
+    assert b.last_error()
+
+
+def test_fovea_mask_host_errors():
+    """Null pointers, capacity and workspace checks return before any device work."""
+    from paper_2209_09965_amd import binding as b
+    L = b.lib()
+    p = ctypes.byref(b.fovea_params(_fp()))
+    fake = ctypes.c_void_p(0x1000)
+    # null ray_idx
+    assert L.fv_fovea_mask(p, 16, 16, 1, None, None, 256, fake, fake, 4096, None) == -1
+    # capacity too small
+    assert L.fv_fovea_mask(p, 16, 16, 1, None, fake, 255, fake, fake, 4096, None) == -2
+    assert "capacity" in b.last_error()
+    # workspace too small
+    need = b.fovea_mask_workspace(16, 16, 1)
+    assert L.fv_fovea_mask(p, 16, 16, 1, None, fake, 256, fake, fake, need - 1, None) == -2
+    # bad sizes
+    assert L.fv_fovea_mask(p, 0, 16, 1, None, fake, 256, fake, fake, 4096, None) == -1
+    assert L.fv_fovea_mask(p, 16, 16, 0, None, fake, 256, fake, fake, 4096, None) == -1
+    assert L.fv_fovea_mask(p, 65535, 65535, 2, None, fake, 0xffffffff, fake, fake, 1 << 40,
+                           None) == -1  # views*W*H >= 2^32
+
+
+def test_march_host_errors():
+    from paper_2209_09965_amd import binding as b
+    L = b.lib()
+    cams = (b.Camera * 1)()
+    mp = ctypes.byref(b.march_params(dict(step_vox=0.5, alpha_stop=0.99)))
+    fake = ctypes.c_void_p(0x1000)
+    assert L.fv_raymarch_dense(None, fake, 256, cams, 1, 8, 8, mp, fake, None, None, None) == -1
+    assert L.fv_raymarch_sparse(None, fake, 256, cams, 1, 8, 8, mp, fake, fake, 64, None, None,
+                                fake, None, None, fake, 256, None) == -1
+    assert L.fv_volume_create(None, 8, 8, 8, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
+    assert L.fv_volume_create(fake, 0, 8, 8, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
+    assert L.fv_volume_create(fake, 8, 8, 8, 9, None, ctypes.byref(ctypes.c_void_p())) == -3

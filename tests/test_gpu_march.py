@@ -1,0 +1,203 @@
+"""GPU ray marcher (dense and sparse) vs the FP64 oracle, through the C ABI.
+
+Bar: every RGBA channel within 1e-5 absolute of the oracle, or of the hull of
+the two early-termination branches where the oracle flags the stopping
+decision as lying within 1e-6 of alpha_stop.  Sparse pixels equal dense
+pixels bit for bit.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic
+from tests.gpuhelp import f32, gpu_dense, hull_ok, report
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+DEPTH_TOL = 1e-5  # depth is premultiplied by opacity, world units (<= ~3)
+
+
+def _tf_t(tf, dev):
+    return torch.from_numpy(np.ascontiguousarray(tf, np.float32)).reshape(-1).to(dev)
+
+
+def _check(gpu_rgba, gpu_depth, ora, label):
+    ok = hull_ok(gpu_rgba, ora, TOL)
+    rep = report(gpu_rgba, ora)
+    print(label, rep, flush=True)
+    assert ok.all(), (label, rep, np.argwhere(~ok)[:5])
+    flagged = ora["flags"].astype(bool)
+    d_err = np.abs(gpu_depth - ora["depth"])[~flagged]
+    assert d_err.size == 0 or d_err.max() <= DEPTH_TOL * 4, d_err.max()
+    # ambiguous early-termination decisions are rare (the opacity jump per step near
+    # alpha_stop is ~1e-4..1e-3, so a 2e-6 window catches well under 1% of rays)
+    assert flagged.mean() < 1e-2
+
+
+def test_empty_volume_background_exact(dev):
+    from paper_2209_09965_amd import binding as b
+    vol = torch.zeros((20, 17, 23), dtype=torch.uint8, device=dev)
+    tf = synthetic.tf_blob(1)
+    mp = synthetic.march_params(shading=True, bg=(0.1, 0.2, 0.3))
+    cams = [synthetic.orbit_camera(0), synthetic.orbit_camera(31)]
+    rgba, depth, cnt = gpu_dense(b, vol, _tf_t(tf, dev), cams, 33, 19, mp, dev)
+    assert np.all(rgba[:, :3] == np.array([f32(0.1), f32(0.2), f32(0.3)], np.float32))
+    assert np.all(rgba[:, 3] == 0.0) and np.all(depth == 0.0)
+
+
+@pytest.mark.parametrize("k", [0, 17, 41])
+def test_dense_blob64_256(k, dev):
+    """64^3 uint8 blobs, 256x256, 45 deg orbit at radius 2, step 0.5, stop 0.99, no shading."""
+    from paper_2209_09965_amd import binding as b
+    vol = synthetic.blob_volume(1000 + k % 5, 64)
+    tf = synthetic.tf_blob(1000 + k % 5)
+    cams = [synthetic.orbit_camera(k)]
+    mp = synthetic.march_params()
+    rgba, depth, cnt = gpu_dense(b, torch.from_numpy(vol).to(dev), _tf_t(tf, dev), cams, 256,
+                                 256, mp, dev)
+    ora = oracle.march(vol, tf, cams, 256, 256, mp, alts=True)
+    _check(rgba, depth, ora, "blob64 k=%d" % k)
+    flagged = ora["flags"].astype(bool)
+    if not flagged.any():
+        assert cnt == int(ora["samples"].sum())
+
+
+def _random_case(seed):
+    rng = np.random.default_rng(seed)
+    n = [int(rng.choice([5, 8, 13, 24, 32])) for _ in range(3)]
+    dt = [np.uint8, np.float16, np.float32][seed % 3]
+    if dt == np.uint8:
+        vol = rng.integers(0, 256, n[::-1]).astype(np.uint8)
+    else:
+        vol = synthetic.value_noise_volume(seed, n=max(n), octaves=3, base_period=8)
+        vol = vol[: n[2], : n[1], : n[0]].astype(dt)
+    tf = synthetic.tf_blob(seed) if seed % 2 else synthetic.tf_noise(seed)
+    tf[:, 3] *= float(rng.uniform(1, 30))
+    inside = seed % 7 == 0
+    if inside:  # camera inside the box
+        cam = dict(eye=tuple(rng.uniform(-0.1, 0.1, 3)), target=(0.3, -0.2, 0.1),
+                   up=(0.0, 1.0, 0.0), fovy_deg=70.0, eye_offset=0.0)
+    else:
+        cam = synthetic.random_camera(rng)
+        cam["fovy_deg"] = float(rng.uniform(20, 60))
+    mp = synthetic.march_params(shading=bool(seed % 2 == 0), step_vox=float(rng.uniform(0.25, 1.5)),
+                                alpha_stop=float(rng.uniform(0.5, 1.0)),
+                                bg=tuple(rng.uniform(0, 1, 3)), light_dir=tuple(rng.normal(size=3)),
+                                shininess=float(rng.choice([8.0, 32.0, 13.5])))
+    W, H = (32, 32) if seed % 3 else (29, 17)
+    return vol, tf, [cam], W, H, mp
+
+
+@pytest.mark.parametrize("seed", list(range(48)))
+def test_dense_random_small(seed, dev):
+    from paper_2209_09965_amd import binding as b
+    vol, tf, cams, W, H, mp = _random_case(seed)
+    rgba, depth, cnt = gpu_dense(b, torch.from_numpy(vol).to(dev), _tf_t(tf, dev), cams, W, H,
+                                 mp, dev)
+    ora = oracle.march(vol, tf, cams, W, H, mp, alts=True)
+    ok = hull_ok(rgba, ora, TOL)
+    print("random", seed, vol.dtype, vol.shape, mp["shading"], report(rgba, ora), flush=True)
+    assert ok.all()
+
+
+def test_stereo_two_views_ragged(dev):
+    from paper_2209_09965_amd import binding as b
+    vol = synthetic.value_noise_volume(5000, n=48, octaves=4, base_period=16).astype(np.float16)
+    tf = synthetic.tf_noise(5000)
+    cams = [synthetic.orbit_camera(3, eye_offset=-0.032), synthetic.orbit_camera(3, eye_offset=0.032)]
+    mp = synthetic.march_params(shading=True)
+    W, H = 45, 31
+    rgba, depth, cnt = gpu_dense(b, torch.from_numpy(vol).to(dev), _tf_t(tf, dev), cams, W, H,
+                                 mp, dev)
+    ora = oracle.march(vol, tf, cams, W, H, mp, alts=True)
+    _check(rgba, depth, ora, "stereo")
+
+
+def _noise_workload(dev):
+    vol = synthetic.value_noise_volume(3000, n=256)
+    tf = synthetic.tf_noise(3000)
+    return vol, tf
+
+
+@pytest.fixture(scope="module")
+def noise256():
+    return _noise_workload(None)
+
+
+def _sparse_run(b, vol_t, tf_t, cams, W, H, mp, fp, dev, sentinel=-7.0):
+    views = len(cams)
+    total = views * W * H
+    ray_idx = torch.empty(total, dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    mask = torch.empty(total, dtype=torch.uint8, device=dev)
+    b.fovea_mask(fp, W, H, views, ray_idx, count, mask=mask)
+    frame = torch.full((total * 4,), sentinel, dtype=torch.float32, device=dev)
+    fdepth = torch.full((total,), sentinel, dtype=torch.float32, device=dev)
+    rc = torch.full((total * 4,), sentinel, dtype=torch.float32, device=dev)
+    dc = torch.full((total,), sentinel, dtype=torch.float32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    vol = b.Volume(vol_t)
+    b.raymarch_sparse(vol, tf_t, cams, W, H, mp, ray_idx, count, rgba_compact=rc, depth_compact=dc,
+                      frame_rgba=frame, frame_depth=fdepth, sample_count=cnt)
+    torch.cuda.synchronize()
+    vol.close()
+    n = int(count.item())
+    return dict(n=n, idx=ray_idx[:n].cpu().numpy().view(np.uint32),
+                mask=mask.cpu().numpy(), frame=frame.cpu().numpy().reshape(-1, 4),
+                fdepth=fdepth.cpu().numpy(), rc=rc.cpu().numpy().reshape(-1, 4)[:n],
+                dc=dc.cpu().numpy()[:n], samples=int(cnt.item()))
+
+
+def test_sparse_equals_dense_bitwise_1080p(noise256, dev):
+    """256^3 f32 value noise, 1920x1080, Phong, fovea s = 162 px / floor 0.05."""
+    from paper_2209_09965_amd import binding as b
+    vol, tf = noise256
+    W, H = 1920, 1080
+    cams = [synthetic.orbit_camera(7)]
+    mp = synthetic.march_params(shading=True)
+    fp = synthetic.fovea_params(W, H)
+    vol_t, tf_t = torch.from_numpy(vol).to(dev), _tf_t(tf, dev)
+    sp = _sparse_run(b, vol_t, tf_t, cams, W, H, mp, fp, dev)
+    rgba, depth, cnt_dense = gpu_dense(b, vol_t, tf_t, cams, W, H, mp, dev)
+    idx = sp["idx"]
+    assert sp["n"] == int(sp["mask"].sum()) > 200000
+    assert np.array_equal(sp["frame"][idx], rgba[idx])
+    assert np.array_equal(sp["rc"], rgba[idx])
+    assert np.array_equal(sp["fdepth"][idx], depth[idx])
+    assert np.array_equal(sp["dc"], depth[idx])
+    untouched = np.ones(W * H, bool)
+    untouched[idx] = False
+    assert np.all(sp["frame"][untouched] == -7.0) and np.all(sp["fdepth"][untouched] == -7.0)
+    assert sp["samples"] < cnt_dense
+
+
+def test_sparse_vs_oracle_1080p_sampled(noise256, dev):
+    """Full-size sparse launch (the benchmarked configuration); 20 000 of its rays,
+    chosen at random, are recomputed by the oracle one by one."""
+    from paper_2209_09965_amd import binding as b
+    vol, tf = noise256
+    W, H = 1920, 1080
+    cams = [synthetic.orbit_camera(0)]
+    mp = synthetic.march_params(shading=True)
+    fp = synthetic.fovea_params(W, H)
+    sp = _sparse_run(b, torch.from_numpy(vol).to(dev), _tf_t(tf, dev), cams, W, H, mp, fp, dev)
+    rng = np.random.default_rng(1)
+    pick = rng.choice(sp["n"], size=20000, replace=False)
+    ora = oracle.march(vol, tf, cams, W, H, mp, idx=sp["idx"][pick], alts=True)
+    _check(sp["rc"][pick], sp["dc"][pick], ora, "noise256 1080p sparse")
+
+
+def test_dense_vs_oracle_1080p_sampled(noise256, dev):
+    from paper_2209_09965_amd import binding as b
+    vol, tf = noise256
+    W, H = 1920, 1080
+    cams = [synthetic.orbit_camera(13)]
+    mp = synthetic.march_params(shading=True)
+    rgba, depth, _ = gpu_dense(b, torch.from_numpy(vol).to(dev), _tf_t(tf, dev), cams, W, H, mp,
+                               dev)
+    rng = np.random.default_rng(2)
+    pick = rng.choice(W * H, size=20000, replace=False).astype(np.uint32)
+    ora = oracle.march(vol, tf, cams, W, H, mp, idx=pick, alts=True)
+    _check(rgba[pick], depth[pick], ora, "noise256 1080p dense")
