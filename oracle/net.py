@@ -1,0 +1,334 @@
+"""FP64 numpy oracle of the reconstruction network, its loss and its optimiser.
+
+TEST INFRASTRUCTURE ONLY (tests, smoke check, CPU baseline of the benchmark).
+Shares no code with the HIP library.
+
+Network (paper: "Reconstruction Network"; the direct-prediction stage D and a
+kernel-prediction head in the single-U-Net form used here):
+  input  I = [M*r, M*g, M*b, M, M*depth/2]            (5 channels, sparse frame)
+  encoder 5->32->32 | pool | 32->48->48 | pool | 48->64->64 | pool | 64->96->96
+  decoder up(96)+64 -> 64->64 | up(64)+48 -> 48->48 | up(48)+32 -> 32->32
+  every conv is 3x3, zero padding 1, stride 1, bias, ReLU after each conv
+  ("two convolutional layers ... followed by a ReLU" read as after each);
+  pool = 2x2 average ("average pooling layer"), up = bilinear x2
+  ("Upsample2D ... bilinear"), half-pixel centres, edge clamp; skips concat
+  [upsampled, encoder] along channels.
+  heads on the last decoder state H_d (32 ch):
+    O_d    = 1x1 conv 32->3, linear             (direct prediction)
+    logits = 1x1 conv 32->25                    (kernel prediction, 1x1 as K)
+    w = softmax over the 25 logits; out(p) = sum_k w_k(p) O_d(clamp(p + delta_k)),
+    delta_k = (dy, dx) in [-2, 2]^2, k = 5 (dy+2) + (dx+2), replicate border
+    (predicted kernels applied to D's output O_d).
+Loss: 0.9 (1 - SSIM) + 0.1 L1 (the paper's lambda_1 = 0.9 on the perceptual
+term and lambda_2 = 0.1 on L1, Eq. (5); SSIM stands in for LPIPS, whose VGG19
+weights are not available).  SSIM: Wang et al. 2004, 11x11 Gaussian window
+sigma 1.5, K1 = 0.01, K2 = 0.03, L = 1, valid region, mean over the map and
+channels.  Optimiser: Adam (beta 0.9 / 0.999, eps 1e-8).
+
+Arrays are NCHW float64.  Parameters are one flat vector in the canonical
+order of LAYERS, each layer's weight [Co, Ci, k, k] followed by its bias [Co].
+"""
+import numpy as np
+
+# (name, Ci, Co, k)
+LAYERS = [
+    ("e0a", 5, 32, 3), ("e0b", 32, 32, 3),
+    ("e1a", 32, 48, 3), ("e1b", 48, 48, 3),
+    ("e2a", 48, 64, 3), ("e2b", 64, 64, 3),
+    ("e3a", 64, 96, 3), ("e3b", 96, 96, 3),
+    ("d2a", 96 + 64, 64, 3), ("d2b", 64, 64, 3),
+    ("d1a", 64 + 48, 48, 3), ("d1b", 48, 48, 3),
+    ("d0a", 48 + 32, 32, 3), ("d0b", 32, 32, 3),
+    ("hd", 32, 3, 1), ("hk", 32, 25, 1),
+]
+N_PARAMS = sum(co * ci * k * k + co for _, ci, co, k in LAYERS)
+MACS_PER_PX = sum(co * ci * k * k / (4 ** lvl) for (name, ci, co, k), lvl in
+                  zip(LAYERS, [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0, 0]))
+
+
+def unflatten(theta, n_layers=None):
+    out, off = {}, 0
+    for name, ci, co, k in LAYERS:
+        nw = co * ci * k * k
+        out[name] = (theta[off:off + nw].reshape(co, ci, k, k), theta[off + nw:off + nw + co])
+        off += nw + co
+    return out
+
+
+def flatten(d):
+    parts = []
+    for name, ci, co, k in LAYERS:
+        w, b = d[name]
+        parts += [np.asarray(w, np.float64).reshape(-1), np.asarray(b, np.float64).reshape(-1)]
+    return np.concatenate(parts)
+
+
+# --------------------------------------------------------------- primitives
+
+def conv2d(x, w, b):
+    """Cross-correlation, stride 1, zero 'same' padding (k // 2), plus bias."""
+    n, ci, h, wd = x.shape
+    co, _, k, _ = w.shape
+    p = k // 2
+    xp = np.pad(x, ((0, 0), (0, 0), (p, p), (p, p)))
+    y = np.zeros((n, co, h, wd))
+    for ky in range(k):
+        for kx in range(k):
+            y += np.einsum("oc,nchw->nohw", w[:, :, ky, kx], xp[:, :, ky:ky + h, kx:kx + wd])
+    return y + b[None, :, None, None]
+
+
+def conv2d_bwd(x, w, dy):
+    n, ci, h, wd = x.shape
+    co, _, k, _ = w.shape
+    p = k // 2
+    xp = np.pad(x, ((0, 0), (0, 0), (p, p), (p, p)))
+    dxp = np.zeros_like(xp)
+    dw = np.zeros_like(w)
+    for ky in range(k):
+        for kx in range(k):
+            dw[:, :, ky, kx] = np.einsum("nohw,nchw->oc", dy, xp[:, :, ky:ky + h, kx:kx + wd])
+            dxp[:, :, ky:ky + h, kx:kx + wd] += np.einsum("oc,nohw->nchw", w[:, :, ky, kx], dy)
+    db = dy.sum(axis=(0, 2, 3))
+    return dxp[:, :, p:p + h, p:p + wd], dw, db
+
+
+def relu(x):
+    return np.maximum(x, 0.0)
+
+
+def avgpool2(x):
+    n, c, h, w = x.shape
+    return x.reshape(n, c, h // 2, 2, w // 2, 2).mean(axis=(3, 5))
+
+
+def avgpool2_bwd(dy):
+    return np.repeat(np.repeat(dy, 2, axis=2), 2, axis=3) / 4.0
+
+
+def _up_axis(n):
+    """Source indices and weights of bilinear x2 along one axis: output i samples
+    the input at (i + 0.5) / 2 - 0.5, clamped to the edge."""
+    i = np.arange(2 * n)
+    s = (i + 0.5) / 2.0 - 0.5
+    s = np.clip(s, 0.0, n - 1)
+    i0 = np.floor(s).astype(int)
+    i1 = np.minimum(i0 + 1, n - 1)
+    f = s - i0
+    return i0, i1, f
+
+
+def upsample2(x):
+    n, c, h, w = x.shape
+    y0, y1, fy = _up_axis(h)
+    x0, x1, fx = _up_axis(w)
+    rows = x[:, :, y0, :] * (1 - fy)[None, None, :, None] + x[:, :, y1, :] * fy[None, None, :, None]
+    return rows[:, :, :, x0] * (1 - fx) + rows[:, :, :, x1] * fx
+
+
+def upsample2_bwd(dy, h, w):
+    n, c = dy.shape[:2]
+    y0, y1, fy = _up_axis(h)
+    x0, x1, fx = _up_axis(w)
+    drows = np.zeros((n, c, 2 * h, w))
+    np.add.at(drows, (slice(None), slice(None), slice(None), x0), dy * (1 - fx))
+    np.add.at(drows, (slice(None), slice(None), slice(None), x1), dy * fx)
+    dx = np.zeros((n, c, h, w))
+    np.add.at(dx, (slice(None), slice(None), y0, slice(None)),
+              drows * (1 - fy)[None, None, :, None])
+    np.add.at(dx, (slice(None), slice(None), y1, slice(None)), drows * fy[None, None, :, None])
+    return dx
+
+
+def softmax_c(z):
+    m = z.max(axis=1, keepdims=True)
+    e = np.exp(z - m)
+    return e / e.sum(axis=1, keepdims=True)
+
+
+def _shift_idx(n, d):
+    return np.clip(np.arange(n) + d, 0, n - 1)
+
+
+def kpn_apply(wk, od):
+    """out(p) = sum_k wk[k](p) * od(clamp(p + delta_k)), 5x5 taps, replicate border."""
+    n, _, h, w = od.shape
+    out = np.zeros_like(od)
+    for dy in range(-2, 3):
+        for dx in range(-2, 3):
+            k = 5 * (dy + 2) + (dx + 2)
+            sh = od[:, :, _shift_idx(h, dy)][:, :, :, _shift_idx(w, dx)]
+            out += wk[:, k:k + 1] * sh
+    return out
+
+
+def kpn_apply_bwd(wk, od, dout):
+    n, _, h, w = od.shape
+    dwk = np.zeros_like(wk)
+    dod = np.zeros_like(od)
+    for dy in range(-2, 3):
+        for dx in range(-2, 3):
+            k = 5 * (dy + 2) + (dx + 2)
+            iy, ix = _shift_idx(h, dy), _shift_idx(w, dx)
+            sh = od[:, :, iy][:, :, :, ix]
+            dwk[:, k] = (dout * sh).sum(axis=1)
+            contrib = dout * wk[:, k:k + 1]
+            tmp = np.zeros((n, 3, h, w))
+            np.add.at(tmp, (slice(None), slice(None), slice(None), ix), contrib)
+            np.add.at(dod, (slice(None), slice(None), iy, slice(None)), tmp)
+    return dwk, dod
+
+
+# ------------------------------------------------------------------ network
+
+def forward(theta, x, keep=False):
+    """Returns (out, O_d) and, with keep=True, the cache for backward()."""
+    P = unflatten(np.asarray(theta, np.float64))
+    c = {"x": x}
+
+    def block(name_a, name_b, inp):
+        a = relu(conv2d(inp, *P[name_a]))
+        bb = relu(conv2d(a, *P[name_b]))
+        c[name_a + "_in"], c[name_a], c[name_b] = inp, a, bb
+        return bb
+
+    e0 = block("e0a", "e0b", x)
+    e1 = block("e1a", "e1b", avgpool2(e0))
+    e2 = block("e2a", "e2b", avgpool2(e1))
+    e3 = block("e3a", "e3b", avgpool2(e2))
+    d2 = block("d2a", "d2b", np.concatenate([upsample2(e3), e2], axis=1))
+    d1 = block("d1a", "d1b", np.concatenate([upsample2(d2), e1], axis=1))
+    d0 = block("d0a", "d0b", np.concatenate([upsample2(d1), e0], axis=1))
+    od = conv2d(d0, *P["hd"])
+    logits = conv2d(d0, *P["hk"])
+    wk = softmax_c(logits)
+    out = kpn_apply(wk, od)
+    c.update(od=od, wk=wk, d0=d0)
+    if keep:
+        return out, od, c
+    return out, od
+
+
+def backward(theta, c, dout):
+    """Gradient of sum(dout * out) w.r.t. theta (flat, canonical order)."""
+    P = unflatten(np.asarray(theta, np.float64))
+    g = {}
+    dwk, dod = kpn_apply_bwd(c["wk"], c["od"], dout)
+    wk = c["wk"]
+    dlogits = wk * (dwk - (dwk * wk).sum(axis=1, keepdims=True))
+    dd0_a, *gd = conv2d_bwd(c["d0"], P["hd"][0], dod)
+    g["hd"] = tuple(gd)
+    dd0_b, *gk = conv2d_bwd(c["d0"], P["hk"][0], dlogits)
+    g["hk"] = tuple(gk)
+    dd0 = dd0_a + dd0_b
+
+    def block_bwd(name_a, name_b, dout_b):
+        dz = dout_b * (c[name_b] > 0)
+        da, *gb = conv2d_bwd(c[name_a], P[name_b][0], dz)
+        g[name_b] = tuple(gb)
+        dz = da * (c[name_a] > 0)
+        dinp, *ga = conv2d_bwd(c[name_a + "_in"], P[name_a][0], dz)
+        g[name_a] = tuple(ga)
+        return dinp
+
+    def split_up(dinp, c_up, low):
+        return upsample2_bwd(dinp[:, :c_up], low.shape[2], low.shape[3]), dinp[:, c_up:]
+
+    din = block_bwd("d0a", "d0b", dd0)
+    dd1, de0 = split_up(din, 48, c["d1b"])
+    din = block_bwd("d1a", "d1b", dd1)
+    dd2, de1 = split_up(din, 64, c["d2b"])
+    din = block_bwd("d2a", "d2b", dd2)
+    de3, de2 = split_up(din, 96, c["e3b"])
+    dp = block_bwd("e3a", "e3b", de3)
+    de2 = de2 + avgpool2_bwd(dp)
+    dp = block_bwd("e2a", "e2b", de2)
+    de1 = de1 + avgpool2_bwd(dp)
+    dp = block_bwd("e1a", "e1b", de1)
+    de0 = de0 + avgpool2_bwd(dp)
+    block_bwd("e0a", "e0b", de0)
+    return flatten(g)
+
+
+# --------------------------------------------------------- loss and metrics
+
+def gaussian_window(size=11, sigma=1.5):
+    x = np.arange(size) - (size - 1) / 2.0
+    g = np.exp(-x * x / (2 * sigma * sigma))
+    return g / g.sum()
+
+
+def _filt(img, g):
+    """Valid separable correlation over the last two axes."""
+    k = g.size
+    h, w = img.shape[-2:]
+    t = sum(g[i] * img[..., i:i + h - k + 1, :] for i in range(k))
+    return sum(g[i] * t[..., :, i:i + w - k + 1] for i in range(k))
+
+
+def _filt_adj(m, g, h, w):
+    """Adjoint of _filt: spreads a valid-region map back onto h x w."""
+    k = g.size
+    t = np.zeros(m.shape[:-1] + (w,))
+    for i in range(k):
+        t[..., :, i:i + m.shape[-1]] += g[i] * m
+    out = np.zeros(m.shape[:-2] + (h, w))
+    for i in range(k):
+        out[..., i:i + t.shape[-2], :] += g[i] * t
+    return out
+
+
+C1 = 0.01 ** 2
+C2 = 0.03 ** 2
+
+
+def ssim(x, y, grad=False):
+    """Mean SSIM of x against y (NCHW), and optionally d(mean SSIM)/dx."""
+    g = gaussian_window()
+    mx, my = _filt(x, g), _filt(y, g)
+    sxx, syy, sxy = _filt(x * x, g), _filt(y * y, g), _filt(x * y, g)
+    vx, vy, cxy = sxx - mx * mx, syy - my * my, sxy - mx * my
+    A1, A2 = 2 * mx * my + C1, 2 * cxy + C2
+    B1, B2 = mx * mx + my * my + C1, vx + vy + C2
+    S = A1 * A2 / (B1 * B2)
+    val = S.mean()
+    if not grad:
+        return val
+    scale = 1.0 / S.size
+    dmx = (2 * my * A2 - 2 * my * A1) / (B1 * B2) - S * (2 * mx / B1 - 2 * mx / B2)
+    dsxx = -S / B2
+    dsxy = 2 * A1 / (B1 * B2)
+    h, w = x.shape[-2:]
+    dx = (_filt_adj(dmx * scale, g, h, w) + 2 * x * _filt_adj(dsxx * scale, g, h, w) +
+          y * _filt_adj(dsxy * scale, g, h, w))
+    return val, dx
+
+
+def loss(out, target, grad=False):
+    """0.9 (1 - SSIM) + 0.1 mean |out - target| (and d loss / d out)."""
+    l1 = np.abs(out - target).mean()
+    if not grad:
+        return 0.9 * (1 - ssim(out, target)) + 0.1 * l1
+    s, ds = ssim(out, target, grad=True)
+    dl1 = np.sign(out - target) / out.size
+    return 0.9 * (1 - s) + 0.1 * l1, -0.9 * ds + 0.1 * dl1
+
+
+def psnr(x, ref):
+    """10 log10(1 / MSE) over values clamped to [0, 1]."""
+    mse = np.mean((np.clip(x, 0, 1) - np.clip(ref, 0, 1)) ** 2)
+    return float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
+
+
+def ssim_metric(x, ref):
+    return ssim(np.clip(x, 0, 1), np.clip(ref, 0, 1))
+
+
+def adam(theta, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (step counts from 1); returns new (theta, m, v)."""
+    m = b1 * m + (1 - b1) * grad
+    v = b2 * v + (1 - b2) * grad * grad
+    mh = m / (1 - b1 ** step)
+    vh = v / (1 - b2 ** step)
+    return theta - lr * mh / (np.sqrt(vh) + eps), m, v
+

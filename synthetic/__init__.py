@@ -16,7 +16,7 @@ import numpy as np
 
 __all__ = [
     "blob_volume", "value_noise_volume", "tf_blob", "tf_noise", "orbit_camera",
-    "random_camera", "march_params", "fovea_params", "WORKLOADS",
+    "random_camera", "march_params", "fovea_params", "WORKLOADS", "NET_SHAPES", "net_init",
 ]
 
 
@@ -191,3 +191,31 @@ WORKLOADS = {
                                  tf="noise", shading=True, seeds=(5000,), sigma_frac=0.12,
                                  eye_offset=0.032),
 }
+
+
+# ------------------------------------------------------- network parameters
+
+# (Ci, Co, k) of the reconstruction network's layers in canonical order
+NET_SHAPES = [
+    (5, 32, 3), (32, 32, 3), (32, 48, 3), (48, 48, 3), (48, 64, 3), (64, 64, 3),
+    (64, 96, 3), (96, 96, 3), (160, 64, 3), (64, 64, 3), (112, 48, 3), (48, 48, 3),
+    (80, 32, 3), (32, 32, 3), (32, 3, 1), (32, 25, 1),
+]
+
+
+def net_init(seed):
+    """Initial parameters (flat float32, each layer's [Co, Ci, k, k] weight then its
+    bias): He-normal 3x3 convs with zero bias; direct head N(0, 1/fan_in); kernel
+    head N(0, 0.01^2) with a +2 bias on the centre tap."""
+    r = _rng(seed, 5)
+    parts = []
+    for i, (ci, co, k) in enumerate(NET_SHAPES):
+        fan = ci * k * k
+        std = math.sqrt(2.0 / fan) if k == 3 else (math.sqrt(1.0 / fan) if co == 3 else 0.01)
+        parts.append(r.normal(0.0, std, size=co * ci * k * k))
+        b = np.zeros(co)
+        if co == 25:
+            b[12] = 2.0
+        parts.append(b)
+    return np.concatenate(parts).astype(np.float32)
+
