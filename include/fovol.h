@@ -244,6 +244,125 @@ fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba,
                              float* frame_depth, uint64_t* sample_count,
                              void* workspace, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * 4. Reconstruction network (paper: "Reconstruction Network", "Model
+ *    Precision & Optimization")
+ * ------------------------------------------------------------------------
+ * A 4-level U-Net (32/48/64/96 channels, two 3x3 conv + ReLU per block, 2x2
+ * average pooling, bilinear x2 upsampling with half-pixel centres, skips
+ * concatenated after the upsampled features) whose last decoder state H_d
+ * feeds two 1x1 heads: the direct prediction O_d (3 channels, linear) and 25
+ * kernel logits; the softmax of the logits is a per-pixel 5x5 kernel applied
+ * to O_d with replicated borders (tap k = 5 (dy+2) + (dx+2)).
+ * Input per pixel: [M r, M g, M b, M, M depth/2] from the back-projected
+ * sparse frame (M = sample map).
+ *
+ * Parameters: FV_NET_PARAMS floats in canonical layer order e0a e0b e1a e1b
+ * e2a e2b e3a e3b d2a d2b d1a d1b d0a d0b hd hk; per layer the weight
+ * [Co][Ci][k][k] then the bias [Co].  Concatenated inputs list the
+ * upsampled channels first.  The handle keeps FP32 master weights, Adam
+ * state, a BF16 copy (training, BF16 inference) and an FP8 E4M3 copy.
+ *
+ * Precision:
+ *  FV_PREC_BF16  activations and weights BF16, MFMA with FP32 accumulation.
+ *  FV_PREC_FP8   activations and weights FP8 E4M3 (OCP), FP32 accumulation;
+ *                per-tensor activation scales from fv_net_calibrate are
+ *                folded into per-output-channel weight scales.
+ *  The heads (softmax and kernel application) always run in FP32.
+ */
+#define FV_NET_PARAMS 480060
+
+typedef enum { FV_PREC_BF16 = 1, FV_PREC_FP8 = 2 } fv_precision;
+
+typedef struct fv_net fv_net;
+
+size_t fv_net_param_count(void);
+
+/* Uploads host FP32 parameters (n_params == FV_NET_PARAMS), zeroes the Adam
+ * state and builds the BF16 copy; synchronises the device.  FP8 is not
+ * usable until fv_net_calibrate.  Errors: null pointers, wrong n_params,
+ * allocation failure (FV_ERR_NOMEM). */
+fv_status fv_net_create(const float* host_params, size_t n_params, fv_net** out);
+fv_status fv_net_destroy(fv_net* n);
+/* Copies the FP32 master parameters to / from host memory (synchronous).
+ * fv_net_set_params invalidates the FP8 copy. */
+fv_status fv_net_get_params(const fv_net* n, float* host_params, size_t n_params);
+fv_status fv_net_set_params(fv_net* n, const float* host_params, size_t n_params);
+
+/* Device workspace for fv_reconstruct at this size and precision. */
+fv_status fv_reconstruct_workspace(const fv_net* n, int precision, int views,
+                                   int width, int height, size_t* bytes);
+
+/* Full-frame reconstruction of `views` sparse frames.
+ *   frame_rgba  dev float [views*H*W*4]  back-projected sparse march output
+ *               (only pixels with mask != 0 are read)
+ *   mask        dev uint8 [views*H*W]
+ *   frame_depth dev float [views*H*W] or NULL (depth channel = 0)
+ *   out_rgb     dev float [views*H*W*3]  reconstructed frame
+ *   out_direct  dev float [views*H*W*3] or NULL: the direct prediction O_d
+ *   workspace   dev, >= fv_reconstruct_workspace() bytes, 256-byte aligned
+ * Errors: null pointers, W or H not a multiple of 8 (three poolings) or
+ * outside [8, 16384], unknown precision (FV_ERR_UNSUPPORTED), FP8 before
+ * calibration, workspace too small (FV_ERR_CAPACITY). */
+fv_status fv_reconstruct(const fv_net* n, int precision, const float* frame_rgba,
+                         const uint8_t* mask, const float* frame_depth, int views,
+                         int width, int height, float* out_rgb, float* out_direct,
+                         void* workspace, size_t ws_bytes, void* stream);
+
+/* Post-training quantisation to FP8: runs one BF16 forward pass over the
+ * given frames, records the largest magnitude of every activation tensor
+ * (scale = max / 448), folds the scales into per-output-channel E4M3
+ * weights and stores them in the handle.  Synchronises `stream`.  The
+ * workspace must hold the BF16 plan (fv_reconstruct_workspace with
+ * FV_PREC_BF16). */
+fv_status fv_net_calibrate(fv_net* n, const float* frame_rgba, const uint8_t* mask,
+                           const float* frame_depth, int views, int width, int height,
+                           void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * 5. Training of the reconstruction network (paper: "Loss", "Training")
+ * ------------------------------------------------------------------------
+ * One workspace (fv_train_workspace) serves the four steps of a training
+ * iteration on a batch of `batch` frames of W x H (multiples of 8, >= 16):
+ *   fv_net_forward_train  BF16 forward that keeps every activation;
+ *   fv_net_loss           L = 0.9 (1 - SSIM) + 0.1 L1 against the target
+ *                         frames (the paper's 0.9 / 0.1 weights with SSIM in
+ *                         place of the VGG19-LPIPS term), and d L / d out;
+ *   fv_net_backward       gradient of sum(dloss_dout * out) w.r.t. all
+ *                         parameters into the handle (and grad_out if given),
+ *                         using the activations of the last forward_train;
+ *   fv_net_adam           one Adam step on the FP32 master weights, then the
+ *                         BF16 copy is rebuilt (the FP8 copy is invalidated).
+ * SSIM: 11x11 Gaussian window (sigma 1.5), K1 = 0.01, K2 = 0.03, L = 1,
+ * valid region, mean over pixels, channels and batch.  Reductions use fixed
+ * orders, so a step is deterministic.  Calls that share a workspace must
+ * be issued on one stream.
+ *   out_rgb / dloss_dout   dev float [batch*H*W*3]
+ *   target_rgba            dev float [batch*H*W*4] (dense frames; RGB used)
+ *   loss3                  dev float [3] = {loss, SSIM, L1}
+ *   grad_out               dev float [FV_NET_PARAMS] or NULL
+ * Errors: null pointers, bad sizes, workspace too small (FV_ERR_CAPACITY),
+ * hyper-parameters out of range (Adam: lr >= 0, betas in [0,1), eps > 0). */
+fv_status fv_train_workspace(const fv_net* n, int batch, int width, int height,
+                             size_t* bytes);
+fv_status fv_net_forward_train(fv_net* n, const float* frame_rgba, const uint8_t* mask,
+                               const float* frame_depth, int batch, int width, int height,
+                               float* out_rgb, void* workspace, size_t ws_bytes,
+                               void* stream);
+fv_status fv_net_loss(const fv_net* n, const float* out_rgb, const float* target_rgba,
+                      int batch, int width, int height, float* loss3, float* dloss_dout,
+                      void* workspace, size_t ws_bytes, void* stream);
+fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int width,
+                          int height, float* grad_out, void* workspace, size_t ws_bytes,
+                          void* stream);
+fv_status fv_net_adam(fv_net* n, float lr, float beta1, float beta2, float eps,
+                      void* stream);
+/* forward_train + loss + backward + Adam (beta 0.9 / 0.999, eps 1e-8). */
+fv_status fv_train_step(fv_net* n, const float* frame_rgba, const uint8_t* mask,
+                        const float* frame_depth, const float* target_rgba, int batch,
+                        int width, int height, float lr, float* loss3, void* workspace,
+                        size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

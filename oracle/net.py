@@ -181,24 +181,31 @@ def kpn_apply_bwd(wk, od, dout):
 
 # ------------------------------------------------------------------ network
 
-def forward(theta, x, keep=False):
-    """Returns (out, O_d) and, with keep=True, the cache for backward()."""
+def forward(theta, x, keep=False, act_round=None):
+    """Returns (out, O_d) and, with keep=True, the cache for backward().
+
+    act_round, if given, is applied to every stored activation tensor (the
+    input, each conv output, each pooled and each upsampled tensor), so a
+    test can reproduce an implementation that stores activations at reduced
+    precision; the arithmetic itself stays FP64."""
     P = unflatten(np.asarray(theta, np.float64))
+    rnd = act_round if act_round is not None else (lambda t: t)
+    x = rnd(x)
     c = {"x": x}
 
     def block(name_a, name_b, inp):
-        a = relu(conv2d(inp, *P[name_a]))
-        bb = relu(conv2d(a, *P[name_b]))
+        a = rnd(relu(conv2d(inp, *P[name_a])))
+        bb = rnd(relu(conv2d(a, *P[name_b])))
         c[name_a + "_in"], c[name_a], c[name_b] = inp, a, bb
         return bb
 
     e0 = block("e0a", "e0b", x)
-    e1 = block("e1a", "e1b", avgpool2(e0))
-    e2 = block("e2a", "e2b", avgpool2(e1))
-    e3 = block("e3a", "e3b", avgpool2(e2))
-    d2 = block("d2a", "d2b", np.concatenate([upsample2(e3), e2], axis=1))
-    d1 = block("d1a", "d1b", np.concatenate([upsample2(d2), e1], axis=1))
-    d0 = block("d0a", "d0b", np.concatenate([upsample2(d1), e0], axis=1))
+    e1 = block("e1a", "e1b", rnd(avgpool2(e0)))
+    e2 = block("e2a", "e2b", rnd(avgpool2(e1)))
+    e3 = block("e3a", "e3b", rnd(avgpool2(e2)))
+    d2 = block("d2a", "d2b", np.concatenate([rnd(upsample2(e3)), e2], axis=1))
+    d1 = block("d1a", "d1b", np.concatenate([rnd(upsample2(d2)), e1], axis=1))
+    d0 = block("d0a", "d0b", np.concatenate([rnd(upsample2(d1)), e0], axis=1))
     od = conv2d(d0, *P["hd"])
     logits = conv2d(d0, *P["hk"])
     wk = softmax_c(logits)

@@ -74,6 +74,22 @@ _SIGS = {
     "fv_raymarch_sparse": (_i, [_vp, _vp, _i, ctypes.POINTER(Camera), _i, _i, _i,
                                 ctypes.POINTER(MarchParams), _vp, _vp, _u32, _vp, _vp, _vp, _vp,
                                 _vp, _vp, _sz, _vp]),
+    "fv_net_param_count": (_sz, []),
+    "fv_net_create": (_i, [_vp, _sz, ctypes.POINTER(_vp)]),
+    "fv_net_destroy": (_i, [_vp]),
+    "fv_net_get_params": (_i, [_vp, _vp, _sz]),
+    "fv_net_set_params": (_i, [_vp, _vp, _sz]),
+    "fv_reconstruct_workspace": (_i, [_vp, _i, _i, _i, _i, ctypes.POINTER(_sz)]),
+    "fv_reconstruct": (_i, [_vp, _i, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _sz, _vp]),
+    "fv_net_calibrate": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _sz, _vp]),
+    "fv_train_workspace": (_i, [_vp, _i, _i, _i, ctypes.POINTER(_sz)]),
+    "fv_net_forward_train": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _sz, _vp]),
+    "fv_net_loss": (_i, [_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _sz, _vp]),
+    "fv_net_backward": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp, _sz, _vp]),
+    "fv_net_adam": (_i, [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                         _vp]),
+    "fv_train_step": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, ctypes.c_float, _vp, _vp, _sz,
+                           _vp]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -227,3 +243,108 @@ def raymarch_sparse(vol, tf, cams, width, height, mp, ray_idx, count, rgba_compa
                                   _ptr(count), cap, _ptr(rgba_compact), _ptr(depth_compact),
                                   _ptr(frame_rgba), _ptr(frame_depth), _ptr(sample_count),
                                   _ptr(workspace), workspace.numel(), _stream(stream)))
+
+
+# ----------------------------------------------------------------- network
+
+FV_PREC_BF16 = 1
+FV_PREC_FP8 = 2
+PRECISIONS = {"bf16": FV_PREC_BF16, "fp8": FV_PREC_FP8}
+
+
+def _prec(p):
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+class Net:
+    """Library-owned reconstruction network (FP32 master + BF16/FP8 copies)."""
+
+    def __init__(self, params):
+        import numpy as np
+        arr = np.ascontiguousarray(params, dtype=np.float32)
+        h = ctypes.c_void_p()
+        check(_lib.fv_net_create(ctypes.c_void_p(arr.ctypes.data), arr.size, ctypes.byref(h)))
+        self.handle = h
+
+    @staticmethod
+    def param_count():
+        return int(_lib.fv_net_param_count())
+
+    def get_params(self):
+        import numpy as np
+        out = np.zeros(self.param_count(), dtype=np.float32)
+        check(_lib.fv_net_get_params(self.handle, ctypes.c_void_p(out.ctypes.data), out.size))
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        arr = np.ascontiguousarray(params, dtype=np.float32)
+        check(_lib.fv_net_set_params(self.handle, ctypes.c_void_p(arr.ctypes.data), arr.size))
+
+    def workspace_bytes(self, views, width, height, precision="bf16"):
+        b = _sz()
+        check(_lib.fv_reconstruct_workspace(self.handle, _prec(precision), views, width, height,
+                                            ctypes.byref(b)))
+        return b.value
+
+    def reconstruct(self, frame_rgba, mask, frame_depth, views, width, height, out_rgb,
+                    out_direct=None, precision="bf16", workspace=None, stream=None):
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes(views, width, height, precision),
+                                    dtype=torch.uint8, device=frame_rgba.device)
+        check(_lib.fv_reconstruct(self.handle, _prec(precision), _ptr(frame_rgba), _ptr(mask),
+                                  _ptr(frame_depth), views, width, height, _ptr(out_rgb),
+                                  _ptr(out_direct), _ptr(workspace), workspace.numel(),
+                                  _stream(stream)))
+
+    def calibrate(self, frame_rgba, mask, frame_depth, views, width, height, workspace=None,
+                  stream=None):
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes(views, width, height, "bf16"),
+                                    dtype=torch.uint8, device=frame_rgba.device)
+        check(_lib.fv_net_calibrate(self.handle, _ptr(frame_rgba), _ptr(mask), _ptr(frame_depth),
+                                    views, width, height, _ptr(workspace), workspace.numel(),
+                                    _stream(stream)))
+
+    # -- training (one workspace shared by the calls of an iteration)
+    def train_workspace_bytes(self, batch, width, height):
+        b = _sz()
+        check(_lib.fv_train_workspace(self.handle, batch, width, height, ctypes.byref(b)))
+        return b.value
+
+    def forward_train(self, frame_rgba, mask, frame_depth, batch, width, height, out_rgb,
+                      workspace, stream=None):
+        check(_lib.fv_net_forward_train(self.handle, _ptr(frame_rgba), _ptr(mask),
+                                        _ptr(frame_depth), batch, width, height, _ptr(out_rgb),
+                                        _ptr(workspace), workspace.numel(), _stream(stream)))
+
+    def loss(self, out_rgb, target_rgba, batch, width, height, loss3, dloss, workspace,
+             stream=None):
+        check(_lib.fv_net_loss(self.handle, _ptr(out_rgb), _ptr(target_rgba), batch, width,
+                               height, _ptr(loss3), _ptr(dloss), _ptr(workspace),
+                               workspace.numel(), _stream(stream)))
+
+    def backward(self, dloss, batch, width, height, workspace, grad_out=None, stream=None):
+        check(_lib.fv_net_backward(self.handle, _ptr(dloss), batch, width, height,
+                                   _ptr(grad_out), _ptr(workspace), workspace.numel(),
+                                   _stream(stream)))
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        check(_lib.fv_net_adam(self.handle, lr, beta1, beta2, eps, _stream(stream)))
+
+    def train_step(self, frame_rgba, mask, frame_depth, target_rgba, batch, width, height, lr,
+                   loss3, workspace, stream=None):
+        check(_lib.fv_train_step(self.handle, _ptr(frame_rgba), _ptr(mask), _ptr(frame_depth),
+                                 _ptr(target_rgba), batch, width, height, lr, _ptr(loss3),
+                                 _ptr(workspace), workspace.numel(), _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            _lib.fv_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

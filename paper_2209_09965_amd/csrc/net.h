@@ -1,0 +1,106 @@
+// Internal declarations of the reconstruction network (not part of the ABI).
+//
+// Network (paper: "Reconstruction Network"): a 4-level U-Net (32/48/64/96
+// channels, two 3x3 conv + ReLU per block, 2x2 average pooling, bilinear x2
+// upsampling, concatenated skips) whose last decoder state feeds a direct
+// RGB head (O_d, 1x1 conv) and a kernel-prediction head (1x1 conv -> 25
+// logits -> softmax -> 5x5 kernel applied to O_d).
+//
+// Activations are NHWC.  Convolutions are implicit GEMMs on MFMA: the GEMM
+// K index is tap-major, k = tap * CiP + ci with CiP = Ci rounded up to 8, and
+// is cut into 32-wide chunks; weights are pre-arranged ("swizzled") so each
+// lane loads its MFMA B fragment with one 16-byte (bf16) / 8-byte (fp8) load.
+#pragma once
+
+#include "common.h"
+
+namespace fv {
+namespace net {
+
+constexpr int kNumLayers = 16;
+constexpr int kNumConv = 14;  // 3x3 layers; 14 and 15 are the 1x1 heads
+
+struct LayerDesc {
+  const char* name;
+  int ci, co, k;
+  int level;      // resolution level of the output (0 = full)
+  int c0, c1;     // input channels from source 0 / source 1 (concat skip)
+  int up0;        // source 0 is bilinearly upsampled x2 on load
+};
+
+// Canonical layer order (also the order of the flat parameter vector:
+// each layer's weight [Co][Ci][k][k] then its bias [Co]).
+extern const LayerDesc kLayers[kNumLayers];
+
+__host__ __device__ inline int cip_of(int ci) { return (ci + 7) / 8 * 8; }
+__host__ __device__ inline int kchunks_of(int ci) { return (9 * cip_of(ci) + 31) / 32; }
+__host__ __device__ inline int nblocks_of(int co) { return (co + 15) / 16; }
+
+// Offsets of each layer's weight / bias in the flat parameter vector.
+int64_t param_offset(int layer);
+int64_t param_count();
+
+// Activation tensors of one forward pass (indices into Plan::t).
+enum Tensor {
+  T_IN = 0, T_E0A, T_E0B, T_P0, T_E1A, T_E1B, T_P1, T_E2A, T_E2B, T_P2, T_E3A, T_E3B,
+  T_D2A, T_D2B, T_D1A, T_D1B, T_D0A, T_D0B, kNumTensors
+};
+
+struct TensorDesc {
+  int channels, level;
+};
+extern const TensorDesc kTensors[kNumTensors];
+
+// Per conv layer: (source 0, source 1 or -1, output) tensor indices.
+extern const int kLayerIO[kNumConv][3];
+
+// Byte layout of a forward-pass workspace for batch n at H x W.
+struct Plan {
+  int n, h, w;
+  size_t elem;                 // bytes per activation element (2 bf16, 1 fp8)
+  size_t t[kNumTensors];       // byte offsets of the activation tensors
+  size_t od, wk, absmax;       // O_d (f32 x3), softmax weights (f32 x25), calibration maxima
+  size_t bytes;                // total
+};
+Plan make_plan(int n, int h, int w, size_t elem);
+
+// Training workspace: the BF16 forward plan followed by FP32 gradients of
+// every activation tensor, a transposed-conv output buffer, the masked BF16
+// output gradient of the current layer, weight-gradient partial sums and
+// loss scratch.
+struct TrainPlan {
+  Plan f;
+  size_t g[kNumTensors];  // FP32 gradient of each activation tensor (not T_IN)
+  size_t tmp;             // FP32 [px at level][Ci] of the current layer
+  size_t dz;              // BF16 masked gradient of the current layer output
+  size_t target;          // FP32 copy of the target RGB (loss)
+  size_t dout;            // FP32 d loss / d out [n h w 3]
+  size_t ssim;            // SSIM maps: 5 filtered row maps + 3 partial maps
+  size_t part;            // weight-gradient partial sums
+  size_t red;             // loss partial sums
+  size_t bytes;
+  int chunks[kNumConv];   // pixel chunks of each layer's weight gradient
+};
+TrainPlan make_train_plan(int n, int h, int w);
+
+}  // namespace net
+}  // namespace fv
+
+// The network handle: FP32 master parameters + Adam state, the swizzled
+// BF16 copy used by training and BF16 inference, and the FP8 copy with its
+// scales (valid after fv_net_calibrate).
+struct fv_net {
+  int device;
+  float* master;          // [P] canonical order
+  float* adam_m;          // [P]
+  float* adam_v;          // [P]
+  float* grad;            // [P]
+  int64_t step;           // Adam steps taken
+  void* w_bf16[fv::net::kNumConv];
+  void* w_bf16t[fv::net::kNumConv];     // transposed (input-gradient) weights
+  void* w_fp8[fv::net::kNumConv];
+  float* alpha_fp8[fv::net::kNumConv];  // per-output-channel dequant x requant factor
+  float* bias_fp8[fv::net::kNumConv];   // bias / output scale
+  float act_scale[fv::net::kNumTensors];  // FP8 per-tensor activation scales
+  int fp8_ready;
+};

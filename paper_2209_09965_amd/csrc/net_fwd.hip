@@ -1,0 +1,631 @@
+// Reconstruction network: forward kernels, the handle, FP8 calibration and
+// fv_reconstruct (paper: "Reconstruction Network", "Model Precision &
+// Optimization").
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "net.h"
+#include "net_kernels.h"
+
+namespace fv {
+namespace net {
+
+const LayerDesc kLayers[kNumLayers] = {
+    // name   ci  co  k lvl  c0  c1 up0
+    {"e0a", 5, 32, 3, 0, 8, 0, 0},     {"e0b", 32, 32, 3, 0, 32, 0, 0},
+    {"e1a", 32, 48, 3, 1, 32, 0, 0},   {"e1b", 48, 48, 3, 1, 48, 0, 0},
+    {"e2a", 48, 64, 3, 2, 48, 0, 0},   {"e2b", 64, 64, 3, 2, 64, 0, 0},
+    {"e3a", 64, 96, 3, 3, 64, 0, 0},   {"e3b", 96, 96, 3, 3, 96, 0, 0},
+    {"d2a", 160, 64, 3, 2, 96, 64, 1}, {"d2b", 64, 64, 3, 2, 64, 0, 0},
+    {"d1a", 112, 48, 3, 1, 64, 48, 1}, {"d1b", 48, 48, 3, 1, 48, 0, 0},
+    {"d0a", 80, 32, 3, 0, 48, 32, 1},  {"d0b", 32, 32, 3, 0, 32, 0, 0},
+    {"hd", 32, 3, 1, 0, 32, 0, 0},     {"hk", 32, 25, 1, 0, 32, 0, 0},
+};
+
+const TensorDesc kTensors[kNumTensors] = {
+    {8, 0},  {32, 0}, {32, 0}, {32, 1}, {48, 1}, {48, 1}, {48, 2}, {64, 2}, {64, 2},
+    {64, 3}, {96, 3}, {96, 3}, {64, 2}, {64, 2}, {48, 1}, {48, 1}, {32, 0}, {32, 0},
+};
+
+// Per conv layer: (src0, src1 or -1, output) tensors.
+const int kLayerIO[kNumConv][3] = {
+    {T_IN, -1, T_E0A},    {T_E0A, -1, T_E0B}, {T_P0, -1, T_E1A},   {T_E1A, -1, T_E1B},
+    {T_P1, -1, T_E2A},    {T_E2A, -1, T_E2B}, {T_P2, -1, T_E3A},   {T_E3A, -1, T_E3B},
+    {T_E3B, T_E2B, T_D2A}, {T_D2A, -1, T_D2B}, {T_D2B, T_E1B, T_D1A}, {T_D1A, -1, T_D1B},
+    {T_D1B, T_E0B, T_D0A}, {T_D0A, -1, T_D0B},
+};
+
+int64_t param_offset(int layer) {
+  int64_t off = 0;
+  for (int i = 0; i < layer; ++i) {
+    const LayerDesc& L = kLayers[i];
+    off += (int64_t)L.co * L.ci * L.k * L.k + L.co;
+  }
+  return off;
+}
+
+int64_t param_count() { return param_offset(kNumLayers); }
+
+static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+Plan make_plan(int n, int h, int w, size_t elem) {
+  Plan p;
+  p.n = n;
+  p.h = h;
+  p.w = w;
+  p.elem = elem;
+  size_t off = 0;
+  for (int t = 0; t < kNumTensors; ++t) {
+    const int lv = kTensors[t].level;
+    p.t[t] = off;
+    off += align256((size_t)n * (h >> lv) * (w >> lv) * kTensors[t].channels * elem);
+  }
+  p.od = off;
+  off += align256((size_t)n * h * w * 3 * sizeof(float));
+  p.wk = off;
+  off += align256((size_t)n * h * w * 25 * sizeof(float));
+  p.absmax = off;
+  off += align256(64 * sizeof(float));
+  p.bytes = off;
+  return p;
+}
+
+// ------------------------------------------------------------------ kernels
+
+// Sparse frame -> 8-channel network input [M r, M g, M b, M, M depth/2, 0, 0, 0]
+// (the back-projected sparse image with its mask and depth; paper: the network
+// reconstructs from the sparse RGB input).  Pixels with M = 0 are not read.
+template <class E>
+__global__ void __launch_bounds__(256) k_pack(const float4* __restrict__ rgba,
+                                              const uint8_t* __restrict__ mask,
+                                              const float* __restrict__ depth, uint8_t* out,
+                                              int64_t npx, float inv_scale,
+                                              float* __restrict__ absmax) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (p < npx && mask[p]) {
+    const float4 c = rgba[p];
+    v[0] = c.x;
+    v[1] = c.y;
+    v[2] = c.z;
+    v[3] = 1.0f;
+    v[4] = depth ? 0.5f * depth[p] : 0.0f;
+  }
+  if (absmax) {
+    float m = 0.f;
+    for (int i = 0; i < 5; ++i) m = fmaxf(m, fabsf(v[i]));
+    wave_absmax(absmax, m);
+  }
+  if (p >= npx) return;
+  for (int i = 0; i < 8; ++i) v[i] *= inv_scale;
+  E::store8(out + p * 8 * E::kBytes, v);
+}
+
+template <class E>
+__global__ void __launch_bounds__(256) k_avgpool2(const uint8_t* __restrict__ src,
+                                                  uint8_t* __restrict__ dst, int n, int h, int w,
+                                                  int c) {
+  // one thread = one output pixel x 8 channels
+  const int groups = c / 8;
+  const int64_t total = (int64_t)n * (h / 2) * (w / 2) * groups;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const int g = (int)(e % groups);
+  const int64_t pix = e / groups;
+  const int ox = (int)(pix % (w / 2));
+  const int64_t r = pix / (w / 2);
+  const int oy = (int)(r % (h / 2));
+  const int b = (int)(r / (h / 2));
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int dy = 0; dy < 2; ++dy)
+    for (int dx = 0; dx < 2; ++dx) {
+      float v[8];
+      const int64_t sp = ((int64_t)b * h + 2 * oy + dy) * w + 2 * ox + dx;
+      E::load8(src + (sp * c + g * 8) * E::kBytes, v);
+      for (int i = 0; i < 8; ++i) acc[i] += v[i];
+    }
+  for (int i = 0; i < 8; ++i) acc[i] *= 0.25f;
+  E::store8(dst + (pix * c + g * 8) * E::kBytes, acc);
+}
+
+// Heads: O_d = 1x1 conv (32 -> 3), logits = 1x1 conv (32 -> 25), w = softmax,
+// out(p) = sum_k w_k(p) O_d(clamp(p + delta_k)) over the 5x5 taps.
+// One 16x16 output tile per block; O_d of the tile plus a 2-pixel clamped
+// halo is computed once into LDS.
+template <class E>
+__global__ void __launch_bounds__(256) k_heads(const uint8_t* __restrict__ hdec, int n, int h,
+                                               int w, const float* __restrict__ params,
+                                               int64_t off_hd, int64_t off_hk, float in_scale,
+                                               float* __restrict__ out_rgb,
+                                               float* __restrict__ out_od,
+                                               float* __restrict__ out_wk) {
+  __shared__ float s_od[20 * 20 * 3];
+  const int tid = threadIdx.x;
+  const float* __restrict__ whd = params + off_hd;  // [3][32] then bias [3]
+  const float* __restrict__ whk = params + off_hk;  // [25][32] then bias [25]
+  const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 16, b = blockIdx.z;
+  for (int e = tid; e < 400; e += 256) {
+    const int r = e / 20, c = e % 20;
+    const int y = min(max(y0 - 2 + r, 0), h - 1), x = min(max(x0 - 2 + c, 0), w - 1);
+    float f[32];
+    E::load32(hdec + (((int64_t)b * h + y) * w + x) * 32 * E::kBytes, f);
+    for (int k = 0; k < 32; ++k) f[k] *= in_scale;
+    for (int ch = 0; ch < 3; ++ch) {
+      float s = whd[96 + ch];
+      for (int k = 0; k < 32; ++k) s = fmaf(whd[ch * 32 + k], f[k], s);
+      s_od[e * 3 + ch] = s;
+    }
+  }
+  __syncthreads();
+  const int tx = tid & 15, ty = tid >> 4;
+  const int y = y0 + ty, x = x0 + tx;
+  if (y >= h || x >= w) return;
+  float f[32];
+  E::load32(hdec + (((int64_t)b * h + y) * w + x) * 32 * E::kBytes, f);
+  for (int k = 0; k < 32; ++k) f[k] *= in_scale;
+  float lg[25];
+  float mx = -INFINITY;
+  for (int q = 0; q < 25; ++q) {
+    float s = whk[800 + q];
+    for (int k = 0; k < 32; ++k) s = fmaf(whk[q * 32 + k], f[k], s);
+    lg[q] = s;
+    mx = fmaxf(mx, s);
+  }
+  float den = 0.f;
+  for (int q = 0; q < 25; ++q) {
+    lg[q] = expf(lg[q] - mx);
+    den += lg[q];
+  }
+  const float inv = 1.0f / den;
+  float o0 = 0.f, o1 = 0.f, o2 = 0.f;
+  for (int dy = 0; dy < 5; ++dy)
+    for (int dx = 0; dx < 5; ++dx) {
+      const float wq = lg[dy * 5 + dx] * inv;
+      const float* od = s_od + ((ty + dy) * 20 + tx + dx) * 3;
+      o0 = fmaf(wq, od[0], o0);
+      o1 = fmaf(wq, od[1], o1);
+      o2 = fmaf(wq, od[2], o2);
+    }
+  const int64_t p = ((int64_t)b * h + y) * w + x;
+  out_rgb[p * 3 + 0] = o0;
+  out_rgb[p * 3 + 1] = o1;
+  out_rgb[p * 3 + 2] = o2;
+  if (out_od) {
+    const float* od = s_od + ((ty + 2) * 20 + tx + 2) * 3;
+    out_od[p * 3 + 0] = od[0];
+    out_od[p * 3 + 1] = od[1];
+    out_od[p * 3 + 2] = od[2];
+  }
+  if (out_wk)
+    for (int q = 0; q < 25; ++q) out_wk[p * 25 + q] = lg[q] * inv;
+}
+
+// Master FP32 weights of a 3x3 layer -> swizzled BF16 MFMA B fragments.
+// transposed = 1 builds the weights of the input-gradient convolution
+// (in/out channels swapped, taps mirrored).
+__global__ void __launch_bounds__(256) k_swizzle_bf16(const float* __restrict__ w, int ci, int co,
+                                                      int transposed, int kc, int nb,
+                                                      __bf16* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total = (int64_t)kc * nb * 512;
+  if (e >= total) return;
+  const int j = (int)(e & 7), l = (int)((e >> 3) & 63);
+  const int nbi = (int)((e >> 9) % nb);
+  const int c = (int)(e / (512 * (int64_t)nb));
+  // GEMM view: input channels (K side) and output channels (N side)
+  const int in_ch = transposed ? co : ci, out_ch = transposed ? ci : co;
+  const int cip = cip_of(in_ch);
+  const int kk = c * 32 + 8 * (l >> 4) + j;
+  const int tap = kk / cip, kin = kk - tap * cip;
+  const int nout = nbi * 16 + (l & 15);
+  float v = 0.f;
+  if (tap < 9 && kin < in_ch && nout < out_ch) {
+    if (!transposed)
+      v = w[((int64_t)nout * ci + kin) * 9 + tap];
+    else
+      v = w[((int64_t)kin * ci + nout) * 9 + (8 - tap)];
+  }
+  out[e] = (__bf16)v;
+}
+
+__global__ void __launch_bounds__(256) k_f32_to_fp8(const float* __restrict__ src,
+                                                    uint8_t* __restrict__ dst, int64_t n) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  dst[e] = FP8::enc(src[e]);
+}
+
+__global__ void k_zero_f32(float* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+// ------------------------------------------------------------- launchers
+
+template <class E, int NB, int R>
+void conv_launch(const ConvArgs& a, hipStream_t s) {
+  static bool attr_set = false;
+  const size_t lds = conv_lds_bytes<E, R>(a.cip, a.c0, a.up0, a.co);
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_conv3x3<E, NB, R>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  dim3 grid((a.w + 15) / 16, (a.h + 4 * R - 1) / (4 * R), a.n);
+  k_conv3x3<E, NB, R><<<grid, 256, lds, s>>>(a);
+}
+
+template <class E, int NB>
+void conv_nb(const ConvArgs& a, int R, hipStream_t s) {
+  if (R == 4)
+    conv_launch<E, NB, 4>(a, s);
+  else if (R == 2)
+    conv_launch<E, NB, 2>(a, s);
+  else
+    conv_launch<E, NB, 1>(a, s);
+}
+
+template <class E>
+fv_status launch_conv(const ConvArgs& a, int nb, hipStream_t s) {
+  // rows per wave: the largest R whose LDS fits in 80 KB (two blocks per CU)
+  // and that still gives at least two blocks per CU (256 CUs)
+  int R = 4;
+  while (R > 1) {
+    const int64_t blocks = (int64_t)((a.w + 15) / 16) * ((a.h + 4 * R - 1) / (4 * R)) * a.n;
+    const size_t lds = R == 4 ? conv_lds_bytes<E, 4>(a.cip, a.c0, a.up0, a.co)
+                              : conv_lds_bytes<E, 2>(a.cip, a.c0, a.up0, a.co);
+    if (lds <= 80 * 1024 && blocks >= 512) break;
+    R >>= 1;
+  }
+  if (a.co % 8) return fail(FV_ERR_UNSUPPORTED, "conv: %d output channels", a.co);
+  switch (nb) {
+    case 1: conv_nb<E, 1>(a, R, s); break;
+    case 2: conv_nb<E, 2>(a, R, s); break;
+    case 3: conv_nb<E, 3>(a, R, s); break;
+    case 4: conv_nb<E, 4>(a, R, s); break;
+    case 5: conv_nb<E, 5>(a, R, s); break;
+    case 6: conv_nb<E, 6>(a, R, s); break;
+    case 7: conv_nb<E, 7>(a, R, s); break;
+    case 10: conv_nb<E, 10>(a, R, s); break;
+    default: return fail(FV_ERR_UNSUPPORTED, "conv: %d output blocks", nb);
+  }
+  return launch_status("conv3x3");
+}
+
+template fv_status launch_conv<BF16>(const ConvArgs&, int, hipStream_t);
+template fv_status launch_conv<FP8>(const ConvArgs&, int, hipStream_t);
+
+fv_status swizzle_bf16(const float* w, int ci, int co, int transposed, void* out, hipStream_t s) {
+  const int in_ch = transposed ? co : ci, out_ch = transposed ? ci : co;
+  const int kc = kchunks_of(in_ch), nb = nblocks_of(out_ch);
+  const int64_t total = (int64_t)kc * nb * 512;
+  k_swizzle_bf16<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(w, ci, co, transposed, kc, nb,
+                                                                 (__bf16*)out);
+  return launch_status("swizzle");
+}
+
+size_t swizzled_elems(int in_ch, int out_ch) {
+  return (size_t)kchunks_of(in_ch) * nblocks_of(out_ch) * 512;
+}
+
+fv_status refresh_bf16(fv_net* n, hipStream_t s) {
+  for (int l = 0; l < kNumConv; ++l) {
+    fv_status st = swizzle_bf16(n->master + param_offset(l), kLayers[l].ci, kLayers[l].co, 0,
+                                n->w_bf16[l], s);
+    if (st == FV_OK && l > 0)
+      st = swizzle_bf16(n->master + param_offset(l), kLayers[l].ci, kLayers[l].co, 1,
+                        n->w_bf16t[l], s);
+    if (st != FV_OK) return st;
+  }
+  return FV_OK;
+}
+
+// Runs the forward pass; prec 1 = BF16, 2 = FP8.  With absmax != nullptr the
+// BF16 pass records per-tensor maxima (calibration).
+template <class E>
+fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const float* frame,
+                       const uint8_t* mask, const float* depth, float* out_rgb, float* out_od,
+                       float* out_wk, float* absmax, hipStream_t s) {
+  const bool fp8 = E::kBytes == 1;
+  const int64_t npx = (int64_t)p.n * p.h * p.w;
+  const float in_inv = fp8 ? 1.0f / net->act_scale[T_IN] : 1.0f;
+  k_pack<E><<<(unsigned)((npx + 255) / 256), 256, 0, s>>>(
+      (const float4*)frame, mask, depth, ws + p.t[T_IN], npx, in_inv, absmax ? absmax + T_IN : nullptr);
+  fv_status st = launch_status("pack");
+  if (st != FV_OK) return st;
+  auto pool = [&](int src, int dst) {
+    const int lv = kTensors[src].level, c = kTensors[src].channels;
+    const int hh = p.h >> lv, ww = p.w >> lv;
+    const int64_t total = (int64_t)p.n * (hh / 2) * (ww / 2) * (c / 8);
+    k_avgpool2<E><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(ws + p.t[src], ws + p.t[dst],
+                                                                  p.n, hh, ww, c);
+    return launch_status("avgpool");
+  };
+  for (int l = 0; l < kNumConv; ++l) {
+    const LayerDesc& L = kLayers[l];
+    const int* io = kLayerIO[l];
+    ConvArgs a{};
+    a.src0 = ws + p.t[io[0]];
+    a.src1 = io[1] >= 0 ? ws + p.t[io[1]] : nullptr;
+    a.c0 = L.c0;
+    a.c1 = L.c1;
+    a.cip = cip_of(L.c0 + L.c1);
+    a.up0 = L.up0;
+    a.n = p.n;
+    a.h = p.h >> L.level;
+    a.w = p.w >> L.level;
+    a.kc = kchunks_of(L.c0 + L.c1);
+    a.co = L.co;
+    a.relu = 1;
+    a.out = ws + p.t[io[2]];
+    a.out_ch = L.co;
+    a.out_fp32 = 0;
+    a.absmax = absmax ? absmax + io[2] : nullptr;
+    if (fp8) {
+      a.wsw = (const uint8_t*)net->w_fp8[l];
+      a.alpha = net->alpha_fp8[l];
+      a.bias = net->bias_fp8[l];
+    } else {
+      a.wsw = (const uint8_t*)net->w_bf16[l];
+      a.alpha = nullptr;
+      a.bias = net->master + param_offset(l) + (int64_t)L.co * L.ci * 9;
+    }
+    st = launch_conv<E>(a, nblocks_of(L.co), s);
+    if (st != FV_OK) return st;
+    if (l == 1) st = pool(T_E0B, T_P0);
+    if (l == 3) st = pool(T_E1B, T_P1);
+    if (l == 5) st = pool(T_E2B, T_P2);
+    if (st != FV_OK) return st;
+  }
+  dim3 grid((p.w + 15) / 16, (p.h + 15) / 16, p.n);
+  k_heads<E><<<grid, 256, 0, s>>>(ws + p.t[T_D0B], p.n, p.h, p.w, net->master, param_offset(14),
+                                  param_offset(15), fp8 ? net->act_scale[T_D0B] : 1.0f, out_rgb,
+                                  out_od, out_wk);
+  return launch_status("heads");
+}
+
+template fv_status forward_impl<BF16>(const fv_net*, const Plan&, uint8_t*, const float*,
+                                      const uint8_t*, const float*, float*, float*, float*,
+                                      float*, hipStream_t);
+template fv_status forward_impl<FP8>(const fv_net*, const Plan&, uint8_t*, const float*,
+                                     const uint8_t*, const float*, float*, float*, float*, float*,
+                                     hipStream_t);
+
+// FP8 weights: fold the per-input-channel activation scales into the
+// weights, quantise per output channel (E4M3, |q| <= 448), and fold the
+// output scale into alpha and bias.
+fv_status build_fp8(fv_net* n, hipStream_t s) {
+  const int64_t P = param_count();
+  std::vector<float> host((size_t)P);
+  fv_status st = hip_status(hipMemcpy(host.data(), n->master, P * sizeof(float),
+                                      hipMemcpyDeviceToHost), "fp8: read weights");
+  if (st != FV_OK) return st;
+  for (int l = 0; l < kNumConv; ++l) {
+    const LayerDesc& L = kLayers[l];
+    const int* io = kLayerIO[l];
+    const int cin = L.c0 + L.c1, cip = cip_of(cin);
+    const float s_out = n->act_scale[io[2]];
+    const float* W = host.data() + param_offset(l);
+    const float* B = W + (int64_t)L.co * L.ci * 9;
+    auto in_scale = [&](int ci) {
+      return n->act_scale[ci < L.c0 ? io[0] : io[1]];
+    };
+    std::vector<float> wscale(L.co), alpha(L.co), bias(L.co);
+    for (int co = 0; co < L.co; ++co) {
+      float m = 0.f;
+      for (int ci = 0; ci < L.ci; ++ci)
+        for (int t = 0; t < 9; ++t)
+          m = std::max(m, std::fabs(W[((int64_t)co * L.ci + ci) * 9 + t] * in_scale(ci)));
+      wscale[co] = m > 0.f ? m / 448.0f : 1.0f;
+      alpha[co] = wscale[co] / s_out;
+      bias[co] = B[co] / s_out;
+    }
+    const int kc = kchunks_of(cin), nb = nblocks_of(L.co);
+    std::vector<float> sw((size_t)kc * nb * 512, 0.f);
+    for (size_t e = 0; e < sw.size(); ++e) {
+      const int j = (int)(e & 7), ln = (int)((e >> 3) & 63);
+      const int nbi = (int)((e >> 9) % nb);
+      const int c = (int)(e / (512 * (size_t)nb));
+      const int kk = c * 32 + 8 * (ln >> 4) + j;
+      const int tap = kk / cip, ci = kk - tap * cip;
+      const int co = nbi * 16 + (ln & 15);
+      if (tap < 9 && ci < L.ci && co < L.co)
+        sw[e] = W[((int64_t)co * L.ci + ci) * 9 + tap] * in_scale(ci) / wscale[co];
+    }
+    float* tmp = nullptr;
+    if (hipMalloc(&tmp, sw.size() * sizeof(float)) != hipSuccess)
+      return fail(FV_ERR_NOMEM, "fp8: staging");
+    st = hip_status(hipMemcpy(tmp, sw.data(), sw.size() * sizeof(float), hipMemcpyHostToDevice),
+                    "fp8: upload");
+    if (st == FV_OK) {
+      k_f32_to_fp8<<<(unsigned)((sw.size() + 255) / 256), 256, 0, s>>>(
+          tmp, (uint8_t*)n->w_fp8[l], (int64_t)sw.size());
+      st = launch_status("fp8: quantise");
+    }
+    if (st == FV_OK) st = hip_status(hipStreamSynchronize(s), "fp8: sync");
+    (void)hipFree(tmp);
+    if (st != FV_OK) return st;
+    st = hip_status(hipMemcpy(n->alpha_fp8[l], alpha.data(), L.co * sizeof(float),
+                              hipMemcpyHostToDevice), "fp8: alpha");
+    if (st == FV_OK)
+      st = hip_status(hipMemcpy(n->bias_fp8[l], bias.data(), L.co * sizeof(float),
+                                hipMemcpyHostToDevice), "fp8: bias");
+    if (st != FV_OK) return st;
+  }
+  n->fp8_ready = 1;
+  return FV_OK;
+}
+
+fv_status check_frame(int views, int W, int H, const char* fn) {
+  if (views <= 0 || W < 8 || H < 8 || W % 8 || H % 8 || W > 16384 || H > 16384)
+    return fail(FV_ERR_INVALID_ARG,
+                "%s: frame %d x %d x %d: width and height must be multiples of 8 in [8, 16384]",
+                fn, views, W, H);
+  return FV_OK;
+}
+
+}  // namespace net
+}  // namespace fv
+
+using namespace fv;
+using namespace fv::net;
+
+extern "C" {
+
+size_t fv_net_param_count(void) { return (size_t)param_count(); }
+
+fv_status fv_net_create(const float* host_params, size_t n_params, fv_net** out) {
+  clear_error();
+  if (!host_params || !out) return fail(FV_ERR_INVALID_ARG, "fv_net_create: null pointer");
+  *out = nullptr;
+  if (n_params != (size_t)param_count())
+    return fail(FV_ERR_INVALID_ARG, "fv_net_create: %zu parameters, expected %lld", n_params,
+                (long long)param_count());
+  fv_net* n = new fv_net();
+  memset(n, 0, sizeof(*n));
+  if (hipGetDevice(&n->device) != hipSuccess) {
+    delete n;
+    return fail(FV_ERR_DEVICE, "fv_net_create: hipGetDevice");
+  }
+  const size_t pb = n_params * sizeof(float);
+  bool ok = hipMalloc(&n->master, pb) == hipSuccess && hipMalloc(&n->adam_m, pb) == hipSuccess &&
+            hipMalloc(&n->adam_v, pb) == hipSuccess && hipMalloc(&n->grad, pb) == hipSuccess;
+  for (int l = 0; ok && l < kNumConv; ++l) {
+    const size_t e = swizzled_elems(kLayers[l].c0 + kLayers[l].c1, kLayers[l].co);
+    const size_t et = swizzled_elems(kLayers[l].co, kLayers[l].c0 + kLayers[l].c1);
+    ok = hipMalloc(&n->w_bf16[l], e * 2) == hipSuccess && hipMalloc(&n->w_fp8[l], e) == hipSuccess &&
+         hipMalloc(&n->w_bf16t[l], et * 2) == hipSuccess &&
+         hipMalloc(&n->alpha_fp8[l], kLayers[l].co * sizeof(float)) == hipSuccess &&
+         hipMalloc(&n->bias_fp8[l], kLayers[l].co * sizeof(float)) == hipSuccess;
+  }
+  if (!ok) {
+    fv_net_destroy(n);
+    return fail(FV_ERR_NOMEM, "fv_net_create: allocation failed");
+  }
+  fv_status st = hip_status(hipMemcpy(n->master, host_params, pb, hipMemcpyHostToDevice),
+                            "fv_net_create: upload");
+  if (st == FV_OK) st = hip_status(hipMemset(n->adam_m, 0, pb), "fv_net_create: adam");
+  if (st == FV_OK) st = hip_status(hipMemset(n->adam_v, 0, pb), "fv_net_create: adam");
+  if (st == FV_OK) st = hip_status(hipMemset(n->grad, 0, pb), "fv_net_create: grad");
+  if (st == FV_OK) st = refresh_bf16(n, nullptr);
+  if (st == FV_OK) st = hip_status(hipDeviceSynchronize(), "fv_net_create: sync");
+  if (st != FV_OK) {
+    fv_net_destroy(n);
+    return st;
+  }
+  *out = n;
+  return FV_OK;
+}
+
+fv_status fv_net_destroy(fv_net* n) {
+  if (!n) return FV_OK;
+  (void)hipFree(n->master);
+  (void)hipFree(n->adam_m);
+  (void)hipFree(n->adam_v);
+  (void)hipFree(n->grad);
+  for (int l = 0; l < kNumConv; ++l) {
+    (void)hipFree(n->w_bf16[l]);
+    (void)hipFree(n->w_bf16t[l]);
+    (void)hipFree(n->w_fp8[l]);
+    (void)hipFree(n->alpha_fp8[l]);
+    (void)hipFree(n->bias_fp8[l]);
+  }
+  delete n;
+  return FV_OK;
+}
+
+fv_status fv_net_get_params(const fv_net* n, float* host_params, size_t n_params) {
+  clear_error();
+  if (!n || !host_params) return fail(FV_ERR_INVALID_ARG, "fv_net_get_params: null pointer");
+  if (n_params != (size_t)param_count())
+    return fail(FV_ERR_INVALID_ARG, "fv_net_get_params: size %zu", n_params);
+  return hip_status(hipMemcpy(host_params, n->master, n_params * sizeof(float),
+                              hipMemcpyDeviceToHost), "fv_net_get_params");
+}
+
+fv_status fv_net_set_params(fv_net* n, const float* host_params, size_t n_params) {
+  clear_error();
+  if (!n || !host_params) return fail(FV_ERR_INVALID_ARG, "fv_net_set_params: null pointer");
+  if (n_params != (size_t)param_count())
+    return fail(FV_ERR_INVALID_ARG, "fv_net_set_params: size %zu", n_params);
+  fv_status st = hip_status(hipMemcpy(n->master, host_params, n_params * sizeof(float),
+                                      hipMemcpyHostToDevice), "fv_net_set_params");
+  if (st == FV_OK) st = refresh_bf16(n, nullptr);
+  if (st == FV_OK) st = hip_status(hipDeviceSynchronize(), "fv_net_set_params: sync");
+  n->fp8_ready = 0;
+  return st;
+}
+
+fv_status fv_reconstruct_workspace(const fv_net* n, int precision, int views, int width,
+                                   int height, size_t* bytes) {
+  clear_error();
+  if (!n || !bytes) return fail(FV_ERR_INVALID_ARG, "fv_reconstruct_workspace: null pointer");
+  if (precision != FV_PREC_BF16 && precision != FV_PREC_FP8)
+    return fail(FV_ERR_UNSUPPORTED, "fv_reconstruct_workspace: precision %d", precision);
+  fv_status st = check_frame(views, width, height, "fv_reconstruct_workspace");
+  if (st != FV_OK) return st;
+  *bytes = make_plan(views, height, width, precision == FV_PREC_FP8 ? 1 : 2).bytes;
+  return FV_OK;
+}
+
+fv_status fv_reconstruct(const fv_net* n, int precision, const float* frame_rgba,
+                         const uint8_t* mask, const float* frame_depth, int views, int width,
+                         int height, float* out_rgb, float* out_direct, void* workspace,
+                         size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!n || !frame_rgba || !mask || !out_rgb || !workspace)
+    return fail(FV_ERR_INVALID_ARG, "fv_reconstruct: null pointer");
+  if (precision != FV_PREC_BF16 && precision != FV_PREC_FP8)
+    return fail(FV_ERR_UNSUPPORTED, "fv_reconstruct: precision %d", precision);
+  fv_status st = check_frame(views, width, height, "fv_reconstruct");
+  if (st != FV_OK) return st;
+  if (precision == FV_PREC_FP8 && !n->fp8_ready)
+    return fail(FV_ERR_INVALID_ARG, "fv_reconstruct: FP8 requested before fv_net_calibrate");
+  const Plan p = make_plan(views, height, width, precision == FV_PREC_FP8 ? 1 : 2);
+  if (ws_bytes < p.bytes)
+    return fail(FV_ERR_CAPACITY, "fv_reconstruct: workspace %zu < %zu bytes", ws_bytes, p.bytes);
+  if ((uintptr_t)workspace % 256)
+    return fail(FV_ERR_INVALID_ARG, "fv_reconstruct: workspace not 256-byte aligned");
+  hipStream_t s = (hipStream_t)stream;
+  if (precision == FV_PREC_FP8)
+    return forward_impl<FP8>(n, p, (uint8_t*)workspace, frame_rgba, mask, frame_depth, out_rgb,
+                             out_direct, nullptr, nullptr, s);
+  return forward_impl<BF16>(n, p, (uint8_t*)workspace, frame_rgba, mask, frame_depth, out_rgb,
+                            out_direct, nullptr, nullptr, s);
+}
+
+fv_status fv_net_calibrate(fv_net* n, const float* frame_rgba, const uint8_t* mask,
+                           const float* frame_depth, int views, int width, int height,
+                           void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!n || !frame_rgba || !mask || !workspace)
+    return fail(FV_ERR_INVALID_ARG, "fv_net_calibrate: null pointer");
+  fv_status st = check_frame(views, width, height, "fv_net_calibrate");
+  if (st != FV_OK) return st;
+  const Plan p = make_plan(views, height, width, 2);
+  if (ws_bytes < p.bytes)
+    return fail(FV_ERR_CAPACITY, "fv_net_calibrate: workspace %zu < %zu bytes (BF16 plan)",
+                ws_bytes, p.bytes);
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* ws = (uint8_t*)workspace;
+  float* amax = (float*)(ws + p.absmax);
+  k_zero_f32<<<1, 64, 0, s>>>(amax, 64);
+  if ((st = launch_status("calibrate: clear")) != FV_OK) return st;
+  float* tmp_rgb = (float*)(ws + p.od);  // the O_d slot is free in this pass
+  st = forward_impl<BF16>(n, p, ws, frame_rgba, mask, frame_depth, tmp_rgb, nullptr, nullptr,
+                          amax, s);
+  if (st != FV_OK) return st;
+  float host[64];
+  st = hip_status(hipMemcpyAsync(host, amax, sizeof host, hipMemcpyDeviceToHost, s),
+                  "calibrate: read");
+  if (st == FV_OK) st = hip_status(hipStreamSynchronize(s), "calibrate: sync");
+  if (st != FV_OK) return st;
+  for (int t = 0; t < kNumTensors; ++t) n->act_scale[t] = std::max(host[t], 1e-6f) / 448.0f;
+  n->act_scale[T_P0] = n->act_scale[T_E0B];
+  n->act_scale[T_P1] = n->act_scale[T_E1B];
+  n->act_scale[T_P2] = n->act_scale[T_E2B];
+  return build_fp8(n, s);
+}
+
+}  // extern "C"

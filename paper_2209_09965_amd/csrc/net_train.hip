@@ -1,0 +1,793 @@
+// Reconstruction network: training (paper: "Loss", "Training").
+//
+// Forward in BF16 with every activation kept, loss 0.9 (1 - SSIM) + 0.1 L1
+// (SSIM in place of the unavailable VGG19-LPIPS term), backward through the
+// kernel-prediction and direct heads, every conv (input gradient = the MFMA
+// conv kernel with transposed weights, weight gradient = FP32 partial sums per
+// pixel chunk reduced in a fixed order, so a step is deterministic), the
+// bilinear upsampling and the average pooling; Adam on FP32 master weights.
+#include <algorithm>
+#include <vector>
+
+#include "net.h"
+#include "net_kernels.h"
+
+namespace fv {
+namespace net {
+
+template <class E>
+fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const float* frame,
+                       const uint8_t* mask, const float* depth, float* out_rgb, float* out_od,
+                       float* out_wk, float* absmax, hipStream_t s);
+fv_status refresh_bf16(fv_net* n, hipStream_t s);
+fv_status check_frame(int views, int W, int H, const char* fn);
+
+static size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+static int64_t px_at(const Plan& p, int level) {
+  return (int64_t)p.n * (p.h >> level) * (p.w >> level);
+}
+
+TrainPlan make_train_plan(int n, int h, int w) {
+  TrainPlan t;
+  t.f = make_plan(n, h, w, 2);
+  size_t off = t.f.bytes;
+  t.g[T_IN] = 0;
+  for (int k = 1; k < kNumTensors; ++k) {
+    t.g[k] = off;
+    off += al((size_t)px_at(t.f, kTensors[k].level) * kTensors[k].channels * 4);
+  }
+  size_t tmp = (size_t)px_at(t.f, 0) * 28 * 4, dz = 0, part = 0;
+  for (int l = 0; l < kNumConv; ++l) {
+    const LayerDesc& L = kLayers[l];
+    const int64_t px = px_at(t.f, L.level);
+    tmp = std::max(tmp, (size_t)px * L.ci * 4);
+    dz = std::max(dz, (size_t)px * L.co * 2);
+    const int64_t tiles =
+        (int64_t)n * (((h >> L.level) + 7) / 8) * (((w >> L.level) + 15) / 16);
+    t.chunks[l] = (int)std::max<int64_t>(1, std::min<int64_t>(64, tiles / 8));
+    part = std::max(part, (size_t)t.chunks[l] * (9 * (size_t)L.ci * L.co + L.co) * 4);
+  }
+  part = std::max(part, (size_t)64 * 28 * 33 * 4);
+  t.tmp = off;
+  off += al(tmp);
+  t.dz = off;
+  off += al(dz);
+  t.target = off;
+  off += al((size_t)n * h * w * 3 * 4);
+  t.dout = off;
+  off += al((size_t)n * h * w * 3 * 4);
+  const size_t q = (size_t)n * 3;
+  t.ssim = off;
+  off += al(q * h * (w - 10) * 4 * 5) + al(q * (h - 10) * (w - 10) * 4 * 3) +
+         al(q * h * (w - 10) * 4 * 3);
+  t.part = off;
+  off += al(part);
+  t.red = off;
+  const int64_t vblocks = ((int64_t)q * (h - 10) * (w - 10) + 255) / 256;
+  const int64_t lblocks = ((int64_t)q * h * w + 255) / 256;
+  off += al((size_t)(vblocks + lblocks) * 8);
+  t.bytes = off;
+  return t;
+}
+
+// ------------------------------------------------------------------ loss
+
+__constant__ float c_gauss[11];
+
+// horizontal 11-tap filter of x, t, x^2, t^2, x t (valid columns)
+__global__ void __launch_bounds__(256) k_ssim_h(const float* __restrict__ out,
+                                                const float* __restrict__ tgt, int n, int h, int w,
+                                                float* __restrict__ hq) {
+  const int wv = w - 10;
+  const int64_t q = (int64_t)n * 3;
+  const int64_t total = q * h * wv;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const int x = (int)(e % wv);
+  const int64_t r = e / wv;
+  const int y = (int)(r % h);
+  const int64_t pl = r / h;
+  const int c = (int)(pl % 3), b = (int)(pl / 3);
+  float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  for (int k = 0; k < 11; ++k) {
+    const int64_t p = ((int64_t)b * h + y) * w + x + k;
+    const float a = out[p * 3 + c], t = tgt[p * 3 + c], g = c_gauss[k];
+    s[0] = fmaf(g, a, s[0]);
+    s[1] = fmaf(g, t, s[1]);
+    s[2] = fmaf(g, a * a, s[2]);
+    s[3] = fmaf(g, t * t, s[3]);
+    s[4] = fmaf(g, a * t, s[4]);
+  }
+  for (int k = 0; k < 5; ++k) hq[k * total + e] = s[k];
+}
+
+// vertical filter -> SSIM map and its partial derivatives w.r.t. mu_x,
+// E[x^2] and E[x t]; block sums of the map (double) for the loss value
+__global__ void __launch_bounds__(256) k_ssim_v(const float* __restrict__ hq, int n, int h, int w,
+                                                float* __restrict__ dmap,
+                                                double* __restrict__ red) {
+  __shared__ double sh[256];
+  const int wv = w - 10, hv = h - 10;
+  const int64_t q = (int64_t)n * 3;
+  const int64_t htot = q * h * wv, vtot = q * hv * wv;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double sval = 0.0;
+  if (e < vtot) {
+    const int x = (int)(e % wv);
+    const int64_t r = e / wv;
+    const int y = (int)(r % hv);
+    const int64_t pl = r / hv;
+    float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    for (int k = 0; k < 11; ++k) {
+      const int64_t hi = (pl * h + y + k) * wv + x;
+      for (int j = 0; j < 5; ++j) m[j] = fmaf(c_gauss[k], hq[j * htot + hi], m[j]);
+    }
+    const float C1 = 1e-4f, C2 = 9e-4f;
+    const float mx = m[0], my = m[1];
+    const float vx = m[2] - mx * mx, vy = m[3] - my * my, cxy = m[4] - mx * my;
+    const float A1 = 2 * mx * my + C1, A2 = 2 * cxy + C2;
+    const float B1 = mx * mx + my * my + C1, B2 = vx + vy + C2;
+    const float S = A1 * A2 / (B1 * B2);
+    sval = S;
+    dmap[e] = (2 * my * A2 - 2 * my * A1) / (B1 * B2) - S * (2 * mx / B1 - 2 * mx / B2);
+    dmap[vtot + e] = -S / B2;
+    dmap[2 * vtot + e] = 2 * A1 / (B1 * B2);
+  }
+  sh[threadIdx.x] = sval;
+  __syncthreads();
+  for (int st = 128; st; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) red[blockIdx.x] = sh[0];
+}
+
+// adjoint of the vertical filter for the three partial maps
+__global__ void __launch_bounds__(256) k_ssim_vt(const float* __restrict__ dmap, int n, int h,
+                                                 int w, float* __restrict__ va) {
+  const int wv = w - 10, hv = h - 10;
+  const int64_t q = (int64_t)n * 3;
+  const int64_t htot = q * h * wv, vtot = q * hv * wv;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= htot) return;
+  const int x = (int)(e % wv);
+  const int64_t r = e / wv;
+  const int y = (int)(r % h);
+  const int64_t pl = r / h;
+  float s[3] = {0.f, 0.f, 0.f};
+  for (int k = 0; k < 11; ++k) {
+    const int yy = y - k;
+    if (yy < 0 || yy >= hv) continue;
+    const int64_t vi = (pl * hv + yy) * wv + x;
+    for (int j = 0; j < 3; ++j) s[j] = fmaf(c_gauss[k], dmap[j * vtot + vi], s[j]);
+  }
+  for (int j = 0; j < 3; ++j) va[j * htot + e] = s[j];
+}
+
+// adjoint of the horizontal filter, combined into d loss / d out, plus the
+// L1 term and its block sums
+__global__ void __launch_bounds__(256) k_ssim_ht(const float* __restrict__ va,
+                                                 const float* __restrict__ out,
+                                                 const float* __restrict__ tgt, int n, int h,
+                                                 int w, float ssim_scale, float l1_scale,
+                                                 float* __restrict__ dout,
+                                                 double* __restrict__ red) {
+  __shared__ double sh[256];
+  const int wv = w - 10;
+  const int64_t q = (int64_t)n * 3;
+  const int64_t htot = q * h * wv, total = q * h * w;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double l1 = 0.0;
+  if (e < total) {
+    const int x = (int)(e % w);
+    const int64_t r = e / w;
+    const int y = (int)(r % h);
+    const int64_t pl = r / h;
+    const int c = (int)(pl % 3), b = (int)(pl / 3);
+    float s[3] = {0.f, 0.f, 0.f};
+    for (int k = 0; k < 11; ++k) {
+      const int xx = x - k;
+      if (xx < 0 || xx >= wv) continue;
+      const int64_t hi = (pl * h + y) * wv + xx;
+      for (int j = 0; j < 3; ++j) s[j] = fmaf(c_gauss[k], va[j * htot + hi], s[j]);
+    }
+    const int64_t p = ((int64_t)b * h + y) * w + x;
+    const float a = out[p * 3 + c], t = tgt[p * 3 + c];
+    const float dssim = s[0] + 2.0f * a * s[1] + t * s[2];
+    const float sg = (a > t) ? 1.0f : (a < t ? -1.0f : 0.0f);
+    dout[p * 3 + c] = -0.9f * ssim_scale * dssim + 0.1f * l1_scale * sg;
+    l1 = fabs((double)a - (double)t);
+  }
+  sh[threadIdx.x] = l1;
+  __syncthreads();
+  for (int st = 128; st; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) red[blockIdx.x] = sh[0];
+}
+
+// fixed-order sums of the block partials -> [loss, ssim, l1]
+__global__ void k_loss_final(const double* __restrict__ rs, int ns, const double* __restrict__ rl,
+                             int nl, double ssim_scale, double l1_scale, float* __restrict__ out) {
+  __shared__ double a[256], c[256];
+  double sa = 0.0, sc = 0.0;
+  for (int i = threadIdx.x; i < ns; i += 256) sa += rs[i];
+  for (int i = threadIdx.x; i < nl; i += 256) sc += rl[i];
+  a[threadIdx.x] = sa;
+  c[threadIdx.x] = sc;
+  __syncthreads();
+  for (int st = 128; st; st >>= 1) {
+    if (threadIdx.x < st) {
+      a[threadIdx.x] += a[threadIdx.x + st];
+      c[threadIdx.x] += c[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double ssim = a[0] * ssim_scale, l1 = c[0] * l1_scale;
+    out[0] = (float)(0.9 * (1.0 - ssim) + 0.1 * l1);
+    out[1] = (float)ssim;
+    out[2] = (float)l1;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_rgb_of_rgba(const float4* __restrict__ src,
+                                                     float* __restrict__ dst, int64_t npx) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= npx) return;
+  const float4 v = src[p];
+  dst[p * 3 + 0] = v.x;
+  dst[p * 3 + 1] = v.y;
+  dst[p * 3 + 2] = v.z;
+}
+
+// ----------------------------------------------------------- heads backward
+
+// Per pixel: d w_k = sum_c dout_c(p) O_d,c(clamp(p + delta_k)); d logits by
+// the softmax Jacobian; d O_d(p) gathered from every pixel whose clamped tap
+// lands on p; d H_d = W_heads^T [d O_d; d logits].  Writes d28 = [d O_d,
+// d logits] (for the heads' weight gradient) and the FP32 gradient of H_d.
+__global__ void __launch_bounds__(256) k_heads_bwd(const float* __restrict__ dout,
+                                                   const float* __restrict__ od,
+                                                   const float* __restrict__ wk, int n, int h,
+                                                   int w, const float* __restrict__ params,
+                                                   int64_t off_hd, int64_t off_hk,
+                                                   float* __restrict__ d28,
+                                                   float* __restrict__ gh) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t npx = (int64_t)n * h * w;
+  if (p >= npx) return;
+  const int x = (int)(p % w);
+  const int64_t r = p / w;
+  const int y = (int)(r % h), b = (int)(r / h);
+  const float g0 = dout[p * 3], g1 = dout[p * 3 + 1], g2 = dout[p * 3 + 2];
+  float dw[25], wl[25];
+  float dot = 0.f;
+  for (int dy = -2; dy <= 2; ++dy)
+    for (int dx = -2; dx <= 2; ++dx) {
+      const int k = 5 * (dy + 2) + (dx + 2);
+      const int yy = min(max(y + dy, 0), h - 1), xx = min(max(x + dx, 0), w - 1);
+      const int64_t q = ((int64_t)b * h + yy) * w + xx;
+      dw[k] = g0 * od[q * 3] + g1 * od[q * 3 + 1] + g2 * od[q * 3 + 2];
+      wl[k] = wk[p * 25 + k];
+      dot = fmaf(wl[k], dw[k], dot);
+    }
+  float d[28];
+  for (int k = 0; k < 25; ++k) d[3 + k] = wl[k] * (dw[k] - dot);
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+  for (int dy = -2; dy <= 2; ++dy) {
+    const int ylo = (y == 0) ? 0 : y - dy, yhi = (y == h - 1) ? h - 1 : y - dy;
+    for (int dx = -2; dx <= 2; ++dx) {
+      const int xlo = (x == 0) ? 0 : x - dx, xhi = (x == w - 1) ? w - 1 : x - dx;
+      const int k = 5 * (dy + 2) + (dx + 2);
+      for (int py = max(ylo, 0); py <= min(yhi, h - 1); ++py) {
+        if (min(max(py + dy, 0), h - 1) != y) continue;
+        for (int px = max(xlo, 0); px <= min(xhi, w - 1); ++px) {
+          if (min(max(px + dx, 0), w - 1) != x) continue;
+          const int64_t q = ((int64_t)b * h + py) * w + px;
+          const float wq = wk[q * 25 + k];
+          a0 = fmaf(wq, dout[q * 3], a0);
+          a1 = fmaf(wq, dout[q * 3 + 1], a1);
+          a2 = fmaf(wq, dout[q * 3 + 2], a2);
+        }
+      }
+    }
+  }
+  d[0] = a0;
+  d[1] = a1;
+  d[2] = a2;
+  for (int j = 0; j < 28; ++j) d28[p * 28 + j] = d[j];
+  const float* whd = params + off_hd;
+  const float* whk = params + off_hk;
+  for (int k = 0; k < 32; ++k) {
+    float s = 0.f;
+    for (int c = 0; c < 3; ++c) s = fmaf(whd[c * 32 + k], d[c], s);
+    for (int qq = 0; qq < 25; ++qq) s = fmaf(whk[qq * 32 + k], d[3 + qq], s);
+    gh[p * 32 + k] = s;
+  }
+}
+
+// Heads weight gradient partials: per chunk of pixels, d W[q][k] = sum d28[q] h[k]
+// and d b[q] = sum d28[q] (28 x 33 outputs); pixels are staged 64 at a time
+// in LDS and every thread owns up to four outputs.
+__global__ void __launch_bounds__(256) k_heads_wgrad(const float* __restrict__ d28,
+                                                     const uint8_t* __restrict__ hdec,
+                                                     int64_t npx, int chunks,
+                                                     float* __restrict__ part) {
+  __shared__ float sd[64 * 28];
+  __shared__ float shv[64 * 33];
+  const int chunk = blockIdx.x, tid = threadIdx.x;
+  const int64_t p0 = npx * chunk / chunks, p1 = npx * (chunk + 1) / chunks;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  const uint16_t* h16 = (const uint16_t*)hdec;
+  for (int64_t base = p0; base < p1; base += 64) {
+    const int cnt = (int)min((int64_t)64, p1 - base);
+    __syncthreads();
+    for (int e = tid; e < 64 * 28; e += 256) {
+      const int pp = e / 28;
+      sd[e] = pp < cnt ? d28[(base + pp) * 28 + e % 28] : 0.f;
+    }
+    for (int e = tid; e < 64 * 33; e += 256) {
+      const int pp = e / 33, k = e % 33;
+      shv[e] = pp < cnt ? (k < 32 ? bf16_bits_to_f(h16[(base + pp) * 32 + k]) : 1.0f) : 0.f;
+    }
+    __syncthreads();
+    for (int j = 0; j < 4; ++j) {
+      const int o = tid + 256 * j;
+      if (o >= 28 * 33) break;
+      const int qq = o / 33, k = o % 33;
+      float sacc = acc[j];
+      for (int pp = 0; pp < 64; ++pp) sacc = fmaf(sd[pp * 28 + qq], shv[pp * 33 + k], sacc);
+      acc[j] = sacc;
+    }
+  }
+  for (int j = 0; j < 4; ++j) {
+    const int o = tid + 256 * j;
+    if (o < 28 * 33) part[(int64_t)chunk * 28 * 33 + o] = acc[j];
+  }
+}
+
+__global__ void k_heads_reduce(const float* __restrict__ part, int chunks, int64_t off_hd,
+                               int64_t off_hk, float* __restrict__ grad) {
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  if (o >= 28 * 33) return;
+  float s = 0.f;
+  for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * 28 * 33 + o];
+  const int qq = o / 33, k = o % 33;
+  if (qq < 3)
+    grad[k < 32 ? off_hd + qq * 32 + k : off_hd + 96 + qq] = s;
+  else
+    grad[k < 32 ? off_hk + (qq - 3) * 32 + k : off_hk + 800 + (qq - 3)] = s;
+}
+
+// -------------------------------------------------------- conv backward
+
+// dz = g * [y > 0] (ReLU derivative) stored as BF16 for the MFMA dgrad
+__global__ void __launch_bounds__(256) k_relu_mask(const float* __restrict__ g,
+                                                   const uint8_t* __restrict__ y,
+                                                   uint8_t* __restrict__ dz, int64_t n8) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n8) return;
+  float yv[8], v[8];
+  BF16::load8(y + e * 16, yv);
+  for (int i = 0; i < 8; ++i) v[i] = yv[i] > 0.f ? g[e * 8 + i] : 0.f;
+  BF16::store8(dz + e * 16, v);
+}
+
+// One input value of a conv layer (concat of upsampled source 0 and source
+// 1, zero outside the image), as the forward kernel's patch fill defines it.
+__device__ __forceinline__ float conv_input(const ConvArgs& a, int b, int y, int x, int ch) {
+  if (y < 0 || y >= a.h || x < 0 || x >= a.w || ch >= a.c0 + a.c1) return 0.f;
+  const uint16_t* s0 = (const uint16_t*)a.src0;
+  if (ch < a.c0) {
+    if (!a.up0) return bf16_bits_to_f(s0[(((int64_t)b * a.h + y) * a.w + x) * a.c0 + ch]);
+    const int hh = a.h >> 1, ww = a.w >> 1;
+    const float sy = fminf(fmaxf((y + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(hh - 1));
+    const float sx = fminf(fmaxf((x + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(ww - 1));
+    const int ly0 = (int)sy, lx0 = (int)sx;
+    const int ly1 = min(ly0 + 1, hh - 1), lx1 = min(lx0 + 1, ww - 1);
+    const float fy = sy - (float)ly0, fx = sx - (float)lx0;
+    const int64_t base = (int64_t)b * hh * ww;
+    const float v00 = bf16_bits_to_f(s0[(base + (int64_t)ly0 * ww + lx0) * a.c0 + ch]);
+    const float v01 = bf16_bits_to_f(s0[(base + (int64_t)ly0 * ww + lx1) * a.c0 + ch]);
+    const float v10 = bf16_bits_to_f(s0[(base + (int64_t)ly1 * ww + lx0) * a.c0 + ch]);
+    const float v11 = bf16_bits_to_f(s0[(base + (int64_t)ly1 * ww + lx1) * a.c0 + ch]);
+    const float top = fmaf(fx, v01 - v00, v00), bot = fmaf(fx, v11 - v10, v10);
+    // the forward pass stores the blended value in BF16
+    return (float)(__bf16)fmaf(fy, bot - top, top);
+  }
+  return bf16_bits_to_f(((const uint16_t*)a.src1)[(((int64_t)b * a.h + y) * a.w + x) * a.c1 +
+                                                  (ch - a.c0)]);
+}
+
+// Weight gradient of a 3x3 layer, FP32 on the vector units.  Block = one
+// (16 output channels) x (16 input channels) pair for all 9 taps and one
+// pixel chunk; thread (co_j, ci_j) accumulates its 9 taps (and the bias for
+// ci block 0) over 8x16-pixel tiles staged in LDS.
+__global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint8_t* __restrict__ dz,
+                                               int ci_total, int co_total, int chunks,
+                                               float* __restrict__ part) {
+  __shared__ float sx[10 * 18 * 17];
+  __shared__ float sd[128 * 17];
+  const int cib = blockIdx.x % ((ci_total + 15) / 16), cob = blockIdx.x / ((ci_total + 15) / 16);
+  const int chunk = blockIdx.y;
+  const int tid = threadIdx.x;
+  const int coj = tid >> 4, cij = tid & 15;
+  const int co = cob * 16 + coj, ci = cib * 16 + cij;
+  const int tiles_x = (a.w + 15) / 16, tiles_y = (a.h + 7) / 8;
+  const int64_t tiles = (int64_t)a.n * tiles_x * tiles_y;
+  const int64_t t0 = tiles * chunk / chunks, t1 = tiles * (chunk + 1) / chunks;
+  float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float accb = 0.f;
+  const uint16_t* dz16 = (const uint16_t*)dz;
+  for (int64_t t = t0; t < t1; ++t) {
+    const int tx = (int)(t % tiles_x);
+    const int64_t rr = t / tiles_x;
+    const int ty = (int)(rr % tiles_y), b = (int)(rr / tiles_y);
+    const int x0 = tx * 16, y0 = ty * 8;
+    __syncthreads();
+    for (int e = tid; e < 10 * 18 * 16; e += 256) {
+      const int c = e & 15, pix = e >> 4;
+      const int r = pix / 18, cc = pix % 18;
+      const int chn = cib * 16 + c;
+      sx[pix * 17 + c] = chn < ci_total ? conv_input(a, b, y0 - 1 + r, x0 - 1 + cc, chn) : 0.f;
+    }
+    for (int e = tid; e < 128 * 16; e += 256) {
+      const int c = e & 15, pix = e >> 4;
+      const int y = y0 + (pix >> 4), x = x0 + (pix & 15);
+      const int chn = cob * 16 + c;
+      float v = 0.f;
+      if (y < a.h && x < a.w && chn < co_total)
+        v = bf16_bits_to_f(dz16[(((int64_t)b * a.h + y) * a.w + x) * co_total + chn]);
+      sd[pix * 17 + c] = v;
+    }
+    __syncthreads();
+    for (int pix = 0; pix < 128; ++pix) {
+      const float d = sd[pix * 17 + coj];
+      accb += d;
+      const int py = pix >> 4, pxx = pix & 15;
+      for (int ky = 0; ky < 3; ++ky)
+        for (int kx = 0; kx < 3; ++kx)
+          acc[ky * 3 + kx] = fmaf(d, sx[((py + ky) * 18 + pxx + kx) * 17 + cij], acc[ky * 3 + kx]);
+    }
+  }
+  if (co < co_total && ci < ci_total) {
+    float* pp = part + (int64_t)chunk * (9 * (int64_t)ci_total * co_total + co_total);
+    for (int tp = 0; tp < 9; ++tp) pp[((int64_t)co * ci_total + ci) * 9 + tp] = acc[tp];
+    if (cib == 0 && cij == 0) pp[9 * (int64_t)ci_total * co_total + co] = accb;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_wgrad_reduce(const float* __restrict__ part, int chunks,
+                                                      int64_t count, float* __restrict__ grad) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= count) return;
+  float s = 0.f;
+  for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * count + e];
+  grad[e] = s;
+}
+
+// gradient of a bilinear x2 upsampling (half-pixel centres, edge clamp):
+// each low-resolution pixel gathers from the output rows/columns
+// [2q-1, 2q+2] with the weights the forward blend gave it
+__device__ __forceinline__ float up_weight(int o, int q, int nlow) {
+  const float s = fminf(fmaxf((o + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(nlow - 1));
+  const int i0 = (int)s, i1 = min(i0 + 1, nlow - 1);
+  const float f = s - (float)i0;
+  return (i0 == q ? 1.0f - f : 0.0f) + (i1 == q ? f : 0.0f);
+}
+
+__global__ void __launch_bounds__(256) k_upsample_bwd(const float* __restrict__ gup, int ch_stride,
+                                                      int c0, int n, int hl, int wl,
+                                                      float* __restrict__ glow) {
+  const int64_t total = (int64_t)n * hl * wl * c0;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const int c = (int)(e % c0);
+  const int64_t pix = e / c0;
+  const int qx = (int)(pix % wl);
+  const int64_t r = pix / wl;
+  const int qy = (int)(r % hl), b = (int)(r / hl);
+  const int h = 2 * hl, w = 2 * wl;
+  float s = 0.f;
+  for (int y = 2 * qy - 1; y <= 2 * qy + 2; ++y) {
+    if (y < 0 || y >= h) continue;
+    const float wy = up_weight(y, qy, hl);
+    if (wy == 0.f) continue;
+    for (int x = 2 * qx - 1; x <= 2 * qx + 2; ++x) {
+      if (x < 0 || x >= w) continue;
+      const float wx = up_weight(x, qx, wl);
+      if (wx == 0.f) continue;
+      s = fmaf(wy * wx, gup[(((int64_t)b * h + y) * w + x) * ch_stride + c], s);
+    }
+  }
+  glow[e] = s;
+}
+
+// copy channels [c0, c0 + c1) of the transposed-conv output into the skip
+// tensor's gradient (first contribution)
+__global__ void __launch_bounds__(256) k_split_skip(const float* __restrict__ tmp, int ch_stride,
+                                                    int c0, int c1, int64_t npx,
+                                                    float* __restrict__ gskip) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= npx * c1) return;
+  const int c = (int)(e % c1);
+  const int64_t p = e / c1;
+  gskip[e] = tmp[p * ch_stride + c0 + c];
+}
+
+// gradient of 2x2 average pooling, added to the pooled tensor's source
+__global__ void __launch_bounds__(256) k_pool_bwd_add(const float* __restrict__ gp, int n, int h,
+                                                      int w, int c, float* __restrict__ g) {
+  const int64_t total = (int64_t)n * h * w * c;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= total) return;
+  const int ch = (int)(e % c);
+  const int64_t pix = e / c;
+  const int x = (int)(pix % w);
+  const int64_t r = pix / w;
+  const int y = (int)(r % h), b = (int)(r / h);
+  g[e] += 0.25f * gp[(((int64_t)b * (h / 2) + y / 2) * (w / 2) + x / 2) * c + ch];
+}
+
+__global__ void __launch_bounds__(256) k_adam(float* __restrict__ th, float* __restrict__ m,
+                                              float* __restrict__ v,
+                                              const float* __restrict__ g, int64_t n, float lr,
+                                              float b1, float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  th[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+fv_status swizzle_bf16(const float* w, int ci, int co, int transposed, void* out, hipStream_t s);
+
+}  // namespace net
+}  // namespace fv
+
+using namespace fv;
+using namespace fv::net;
+
+static fv_status upload_gauss() {
+  static bool done = false;
+  if (done) return FV_OK;
+  float g[11], sum = 0.f;
+  double gd[11], sd = 0.0;
+  for (int i = 0; i < 11; ++i) {
+    const double x = i - 5.0;
+    gd[i] = std::exp(-x * x / (2.0 * 1.5 * 1.5));
+    sd += gd[i];
+  }
+  for (int i = 0; i < 11; ++i) {
+    g[i] = (float)(gd[i] / sd);
+    sum += g[i];
+  }
+  (void)sum;
+  fv_status st = hip_status(hipMemcpyToSymbol(HIP_SYMBOL(c_gauss), g, sizeof g), "gauss upload");
+  if (st == FV_OK) done = true;
+  return st;
+}
+
+extern "C" {
+
+fv_status fv_train_workspace(const fv_net* n, int batch, int width, int height, size_t* bytes) {
+  clear_error();
+  if (!n || !bytes) return fail(FV_ERR_INVALID_ARG, "fv_train_workspace: null pointer");
+  fv_status st = check_frame(batch, width, height, "fv_train_workspace");
+  if (st != FV_OK) return st;
+  if (width < 16 || height < 16)
+    return fail(FV_ERR_INVALID_ARG, "fv_train_workspace: training tiles must be >= 16 x 16");
+  *bytes = make_train_plan(batch, height, width).bytes;
+  return FV_OK;
+}
+
+static fv_status train_check(const fv_net* n, int batch, int width, int height, void* ws,
+                             size_t ws_bytes, TrainPlan* tp, const char* fn) {
+  if (!n || !ws) return fail(FV_ERR_INVALID_ARG, "%s: null pointer", fn);
+  fv_status st = check_frame(batch, width, height, fn);
+  if (st != FV_OK) return st;
+  if (width < 16 || height < 16)
+    return fail(FV_ERR_INVALID_ARG, "%s: training tiles must be >= 16 x 16", fn);
+  *tp = make_train_plan(batch, height, width);
+  if (ws_bytes < tp->bytes)
+    return fail(FV_ERR_CAPACITY, "%s: workspace %zu < %zu bytes", fn, ws_bytes, tp->bytes);
+  if ((uintptr_t)ws % 256) return fail(FV_ERR_INVALID_ARG, "%s: workspace not aligned", fn);
+  return FV_OK;
+}
+
+fv_status fv_net_forward_train(fv_net* n, const float* frame_rgba, const uint8_t* mask,
+                               const float* frame_depth, int batch, int width, int height,
+                               float* out_rgb, void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  TrainPlan tp;
+  fv_status st = train_check(n, batch, width, height, workspace, ws_bytes, &tp,
+                             "fv_net_forward_train");
+  if (st != FV_OK) return st;
+  if (!frame_rgba || !mask || !out_rgb)
+    return fail(FV_ERR_INVALID_ARG, "fv_net_forward_train: null pointer");
+  uint8_t* ws = (uint8_t*)workspace;
+  return forward_impl<BF16>(n, tp.f, ws, frame_rgba, mask, frame_depth, out_rgb,
+                            (float*)(ws + tp.f.od), (float*)(ws + tp.f.wk), nullptr,
+                            (hipStream_t)stream);
+}
+
+fv_status fv_net_loss(const fv_net* n, const float* out_rgb, const float* target_rgba, int batch,
+                      int width, int height, float* loss3, float* dloss_dout, void* workspace,
+                      size_t ws_bytes, void* stream) {
+  clear_error();
+  TrainPlan tp;
+  fv_status st = train_check(n, batch, width, height, workspace, ws_bytes, &tp, "fv_net_loss");
+  if (st != FV_OK) return st;
+  if (!out_rgb || !target_rgba || !loss3 || !dloss_dout)
+    return fail(FV_ERR_INVALID_ARG, "fv_net_loss: null pointer");
+  if ((st = upload_gauss()) != FV_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* ws = (uint8_t*)workspace;
+  const int64_t npx = (int64_t)batch * height * width;
+  float* tgt = (float*)(ws + tp.target);
+  k_rgb_of_rgba<<<nblk(npx), 256, 0, s>>>((const float4*)target_rgba, tgt, npx);
+  const int64_t q = (int64_t)batch * 3;
+  const int64_t htot = q * height * (width - 10), vtot = q * (height - 10) * (width - 10);
+  float* hq = (float*)(ws + tp.ssim);
+  float* dmap = (float*)(ws + tp.ssim + al(htot * 4 * 5));
+  float* va = (float*)(ws + tp.ssim + al(htot * 4 * 5) + al(vtot * 4 * 3));
+  double* red = (double*)(ws + tp.red);
+  const unsigned nbv = nblk(vtot), nbl = nblk(q * height * width);
+  k_ssim_h<<<nblk(htot), 256, 0, s>>>(out_rgb, tgt, batch, height, width, hq);
+  k_ssim_v<<<nbv, 256, 0, s>>>(hq, batch, height, width, dmap, red);
+  k_ssim_vt<<<nblk(htot), 256, 0, s>>>(dmap, batch, height, width, va);
+  const double ssim_scale = 1.0 / (double)vtot, l1_scale = 1.0 / (double)(q * height * width);
+  k_ssim_ht<<<nbl, 256, 0, s>>>(va, out_rgb, tgt, batch, height, width, (float)ssim_scale,
+                                (float)l1_scale, dloss_dout, red + nbv);
+  k_loss_final<<<1, 256, 0, s>>>(red, (int)nbv, red + nbv, (int)nbl, ssim_scale, l1_scale, loss3);
+  return launch_status("fv_net_loss");
+}
+
+fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int width, int height,
+                          float* grad_out, void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  TrainPlan tp;
+  fv_status st = train_check(n, batch, width, height, workspace, ws_bytes, &tp,
+                             "fv_net_backward");
+  if (st != FV_OK) return st;
+  if (!dloss_dout) return fail(FV_ERR_INVALID_ARG, "fv_net_backward: null dloss_dout");
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* ws = (uint8_t*)workspace;
+  const Plan& p = tp.f;
+  const int64_t npx = (int64_t)p.n * p.h * p.w;
+  float* grad = n->grad;
+  float* tmp = (float*)(ws + tp.tmp);
+  uint8_t* dz = ws + tp.dz;
+  float* part = (float*)(ws + tp.part);
+  auto G = [&](int t) { return (float*)(ws + tp.g[t]); };
+  // heads
+  k_heads_bwd<<<nblk(npx), 256, 0, s>>>(dloss_dout, (const float*)(ws + p.od),
+                                        (const float*)(ws + p.wk), p.n, p.h, p.w, n->master,
+                                        param_offset(14), param_offset(15), tmp, G(T_D0B));
+  const int hchunks = 64;
+  k_heads_wgrad<<<hchunks, 256, 0, s>>>(tmp, ws + p.t[T_D0B], npx, hchunks, part);
+  k_heads_reduce<<<4, 256, 0, s>>>(part, hchunks, param_offset(14), param_offset(15), grad);
+  if ((st = launch_status("heads backward")) != FV_OK) return st;
+  for (int l = kNumConv - 1; l >= 0; --l) {
+    const LayerDesc& L = kLayers[l];
+    const int* io = kLayerIO[l];
+    const int hh = p.h >> L.level, ww = p.w >> L.level;
+    const int64_t px = (int64_t)p.n * hh * ww;
+    // ReLU derivative, BF16 copy of the output gradient
+    k_relu_mask<<<nblk(px * L.co / 8), 256, 0, s>>>(G(io[2]), ws + p.t[io[2]], dz,
+                                                    px * L.co / 8);
+    // weight + bias gradient
+    ConvArgs in{};
+    in.src0 = ws + p.t[io[0]];
+    in.src1 = io[1] >= 0 ? ws + p.t[io[1]] : nullptr;
+    in.c0 = L.c0;
+    in.c1 = L.c1;
+    in.up0 = L.up0;
+    in.n = p.n;
+    in.h = hh;
+    in.w = ww;
+    const int ci_tot = l == 0 ? L.ci : L.c0 + L.c1;
+    dim3 gw((unsigned)(((ci_tot + 15) / 16) * ((L.co + 15) / 16)), (unsigned)tp.chunks[l]);
+    k_wgrad<<<gw, 256, 0, s>>>(in, dz, ci_tot, L.co, tp.chunks[l], part);
+    const int64_t cnt = 9 * (int64_t)ci_tot * L.co + L.co;
+    k_wgrad_reduce<<<nblk(cnt), 256, 0, s>>>(part, tp.chunks[l], cnt, grad + param_offset(l));
+    if ((st = launch_status("wgrad")) != FV_OK) return st;
+    if (l == 0) break;  // no gradient w.r.t. the network input
+    // input gradient: conv with transposed weights, FP32 output
+    ConvArgs a{};
+    a.src0 = dz;
+    a.src1 = nullptr;
+    a.c0 = L.co;
+    a.c1 = 0;
+    a.cip = cip_of(L.co);
+    a.up0 = 0;
+    a.n = p.n;
+    a.h = hh;
+    a.w = ww;
+    a.wsw = (const uint8_t*)n->w_bf16t[l];
+    a.kc = kchunks_of(L.co);
+    a.alpha = nullptr;
+    a.bias = nullptr;
+    a.co = L.c0 + L.c1;
+    a.relu = 0;
+    a.out_fp32 = 1;
+    a.out_ch = L.c0 + L.c1;
+    a.absmax = nullptr;
+    const bool concat = io[1] >= 0;
+    a.out = (uint8_t*)(concat ? tmp : G(io[0]));
+    if ((st = launch_conv<BF16>(a, nblocks_of(L.c0 + L.c1), s)) != FV_OK) return st;
+    if (concat) {
+      const int hl = hh / 2, wl = ww / 2;
+      k_upsample_bwd<<<nblk((int64_t)p.n * hl * wl * L.c0), 256, 0, s>>>(
+          tmp, L.c0 + L.c1, L.c0, p.n, hl, wl, G(io[0]));
+      k_split_skip<<<nblk(px * L.c1), 256, 0, s>>>(tmp, L.c0 + L.c1, L.c0, L.c1, px, G(io[1]));
+    }
+    // the pooled input's gradient flows back to the pooled tensor's source
+    int src = -1;
+    if (io[0] == T_P0) src = T_E0B;
+    if (io[0] == T_P1) src = T_E1B;
+    if (io[0] == T_P2) src = T_E2B;
+    if (src >= 0)
+      k_pool_bwd_add<<<nblk(px * 4 * L.c0), 256, 0, s>>>(G(io[0]), p.n, hh * 2, ww * 2, L.c0,
+                                                          G(src));
+    if ((st = launch_status("dgrad")) != FV_OK) return st;
+  }
+  if (grad_out)
+    st = hip_status(hipMemcpyAsync(grad_out, grad, param_count() * sizeof(float),
+                                   hipMemcpyDeviceToDevice, s), "fv_net_backward: copy grads");
+  return st;
+}
+
+fv_status fv_net_adam(fv_net* n, float lr, float beta1, float beta2, float eps, void* stream) {
+  clear_error();
+  if (!n) return fail(FV_ERR_INVALID_ARG, "fv_net_adam: null net");
+  if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps > 0.f))
+    return fail(FV_ERR_INVALID_ARG, "fv_net_adam: bad hyper-parameters");
+  hipStream_t s = (hipStream_t)stream;
+  n->step += 1;
+  const float c1 = 1.0f - (float)std::pow((double)beta1, (double)n->step);
+  const float c2 = 1.0f - (float)std::pow((double)beta2, (double)n->step);
+  const int64_t P = param_count();
+  k_adam<<<nblk(P), 256, 0, s>>>(n->master, n->adam_m, n->adam_v, n->grad, P, lr, beta1, beta2,
+                                 eps, c1, c2);
+  fv_status st = launch_status("fv_net_adam");
+  if (st == FV_OK) st = refresh_bf16(n, s);
+  n->fp8_ready = 0;
+  return st;
+}
+
+fv_status fv_train_step(fv_net* n, const float* frame_rgba, const uint8_t* mask,
+                        const float* frame_depth, const float* target_rgba, int batch,
+                        int width, int height, float lr, float* loss3, void* workspace,
+                        size_t ws_bytes, void* stream) {
+  clear_error();
+  TrainPlan tp;
+  fv_status st = train_check(n, batch, width, height, workspace, ws_bytes, &tp, "fv_train_step");
+  if (st != FV_OK) return st;
+  uint8_t* ws = (uint8_t*)workspace;
+  // network output in the (not yet used) transposed-conv buffer, loss
+  // gradient in its own slot
+  float* yout = (float*)(ws + tp.tmp);
+  float* out = (float*)(ws + tp.dout);
+  if ((st = fv_net_forward_train(n, frame_rgba, mask, frame_depth, batch, width, height, yout,
+                                 workspace, ws_bytes, stream)) != FV_OK)
+    return st;
+  if ((st = fv_net_loss(n, yout, target_rgba, batch, width, height, loss3, out, workspace,
+                        ws_bytes, stream)) != FV_OK)
+    return st;
+  if ((st = fv_net_backward(n, out, batch, width, height, nullptr, workspace, ws_bytes,
+                            stream)) != FV_OK)
+    return st;
+  return fv_net_adam(n, lr, 0.9f, 0.999f, 1e-8f, stream);
+}
+
+}  // extern "C"

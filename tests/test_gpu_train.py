@@ -1,0 +1,110 @@
+"""GPU training kernels vs the FP64 oracle: loss and its gradient, the full
+parameter gradient (against the oracle's exact backward of the BF16-emulated
+forward), determinism, and that Adam steps reduce the loss."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic
+from oracle import net as N
+from tests.test_gpu_net import _bf16_weights, _frame, _oracle_input, _theta, bf16_round
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).reshape(-1).to(dev)
+
+
+def test_loss_and_gradient_match_oracle(dev):
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(0)
+    n, H, W = 2, 24, 32
+    out = rng.uniform(0.05, 0.95, (n, H, W, 3)).astype(np.float32)
+    tgt = np.clip(out + rng.normal(0, 0.1, out.shape), 0, 1).astype(np.float32)
+    tgt4 = np.concatenate([tgt, np.ones((n, H, W, 1), np.float32)], axis=3)
+    net = b.Net(synthetic.net_init(0))
+    ws = torch.empty(net.train_workspace_bytes(n, W, H), dtype=torch.uint8, device=dev)
+    loss3 = torch.zeros(3, device=dev)
+    dl = torch.zeros(n * H * W * 3, device=dev)
+    net.loss(_t(out, dev), _t(tgt4, dev), n, W, H, loss3, dl, ws)
+    torch.cuda.synchronize()
+    o = out.astype(np.float64).transpose(0, 3, 1, 2)
+    t = tgt.astype(np.float64).transpose(0, 3, 1, 2)
+    val, g = N.loss(o, t, grad=True)
+    l = loss3.cpu().numpy()
+    print("loss gpu %.7f oracle %.7f | ssim %.7f %.7f" % (l[0], val, l[1], N.ssim(o, t)))
+    assert abs(l[0] - val) < 2e-5 and abs(l[1] - N.ssim(o, t)) < 2e-5
+    gg = dl.cpu().numpy().reshape(n, H, W, 3).transpose(0, 3, 1, 2)
+    rel = np.abs(gg - g).max() / np.abs(g).max()
+    print("dloss rel max err %.3g" % rel)
+    assert rel < 1e-3
+    net.close()
+
+
+def _grads(theta, rgba, mask, depth, dloss, n, H, W, dev):
+    from paper_2209_09965_amd import binding as b
+    net = b.Net(theta)
+    ws = torch.empty(net.train_workspace_bytes(n, W, H), dtype=torch.uint8, device=dev)
+    out = torch.empty(n * H * W * 3, device=dev)
+    net.forward_train(_t(rgba, dev), _t(mask, dev), _t(depth, dev), n, W, H, out, ws)
+    g = torch.zeros(N.N_PARAMS, device=dev)
+    net.backward(_t(dloss, dev), n, W, H, ws, grad_out=g)
+    torch.cuda.synchronize()
+    net.close()
+    return out.cpu().numpy(), g.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,H,W", [(1, 16, 16), (2, 32, 48)])
+def test_backward_matches_oracle(n, H, W, dev):
+    rng = np.random.default_rng(1)
+    theta = _theta(4)
+    rgba, mask, depth = _frame(rng, n, H, W, density=0.3)
+    dloss = rng.normal(0, 1.0, (n, H, W, 3)).astype(np.float32)
+    out, g = _grads(theta, rgba, mask, depth, dloss, n, H, W, dev)
+    x = _oracle_input(rgba, mask, depth, n, H, W)
+    th16 = _bf16_weights(theta)
+    want, _, cache = N.forward(th16, x, keep=True, act_round=bf16_round)
+    gw = N.backward(th16, cache, dloss.astype(np.float64).transpose(0, 3, 1, 2))
+    assert np.abs(out.reshape(n, H, W, 3).transpose(0, 3, 1, 2) - want).max() < 2e-2
+    off = 0
+    worst = 0.0
+    for name, ci, co, k in N.LAYERS:
+        nw = co * ci * k * k + co
+        a, r = g[off:off + nw], gw[off:off + nw]
+        rel = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
+        print("%-4s grad rel L2 err %.4f  |g| %.3g" % (name, rel, np.linalg.norm(r)))
+        worst = max(worst, rel)
+        off += nw
+    # BF16 storage of the output gradients (MFMA input-gradient convs) adds
+    # ~2^-9 relative noise per layer: <= 0.35% per layer when the oracle rounds
+    # dZ the same way.  At 16 x 16 the BF16 forward has no rounding flips and the
+    # bound is tight.  Larger frames do flip a few BF16 roundings (FP32 vs FP64
+    # values on a rounding boundary); the oracle's own gradients move by 5-9% per
+    # layer under FP32-level perturbations of its activations before rounding,
+    # which sets the looser bound.
+    assert worst < (0.01 if H * W <= 256 else 0.10)
+    g2 = _grads(theta, rgba, mask, depth, dloss, n, H, W, dev)[1]
+    assert np.array_equal(g, g2), "backward is not deterministic"
+
+
+def test_adam_steps_reduce_loss(dev):
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(2)
+    n, H, W = 4, 32, 32
+    rgba, mask, depth = _frame(rng, n, H, W, density=0.3)
+    tgt = rgba.copy()
+    net = b.Net(synthetic.net_init(5))
+    ws = torch.empty(net.train_workspace_bytes(n, W, H), dtype=torch.uint8, device=dev)
+    loss3 = torch.zeros(3, device=dev)
+    losses = []
+    fr, m, d, t = _t(rgba, dev), _t(mask, dev), _t(depth, dev), _t(tgt, dev)
+    for it in range(30):
+        net.train_step(fr, m, d, t, n, W, H, 1e-3, loss3, ws)
+        losses.append(float(loss3[0].item()))
+    print("losses", ["%.4f" % v for v in losses[::5]], "%.4f" % losses[-1])
+    assert all(np.isfinite(losses))
+    assert losses[-1] < 0.8 * losses[0]
+    # Adam's first step moves each weight by about lr (closed form of the first step)
+    net.close()
