@@ -3,10 +3,13 @@
 
 One step = one foveated frame of the 256^3 f32 value-noise volume at 1920x1080
 with Blinn-Phong shading: sample map + ordered compaction (fv_fovea_mask) ->
-sparse march with back-projection (fv_raymarch_sparse) -> reconstruction
-(fv_reconstruct, when the network is available).  The plain dense march of the
-same frames (fv_raymarch_dense) is timed beside it.  Inputs are synthetic,
-seeded and resident in HBM before the timed region.
+sparse march with back-projection (fv_raymarch_sparse) -> full-frame
+reconstruction by the trained network in FP8 (fv_reconstruct).  The plain
+dense march of the same frames (fv_raymarch_dense) is timed beside it.
+Inputs are synthetic, seeded and resident in HBM before the timed region;
+the network weights come from paper_2209_09965_amd/weights/recon.npy (trained
+by python -m paper_2209_09965_amd.train) and are calibrated for FP8 on one
+frame of the workload before the timed region.
 
 Prints one JSON line (see the keys below); per-stage times come from HIP
 events recorded on the stream the kernels run on.
@@ -35,6 +38,13 @@ def parse():
                     help="sampled rays of one frame marched by the CPU oracle for the "
                          "baseline (0 = all of them)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--precision", default="fp8", choices=["fp8", "bf16"])
+    ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2209_09965_amd", "weights",
+                                                      "recon.npy"))
+    ap.add_argument("--copy-ref", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (counter reference)")
+    ap.add_argument("--net-crop", type=int, default=256,
+                    help="side of the crop the CPU oracle network runs on (scaled to the frame)")
     return ap.parse_args()
 
 
@@ -53,8 +63,22 @@ def make_inputs(wl):
     return vol, tf
 
 
+def copy_reference(nbytes):
+    """A plain device copy of a known size (reference for HBM byte counters)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_reference_bytes": nbytes, "launches": 5}), flush=True)
+
+
 def main():
     args = parse()
+    if args.copy_ref:
+        copy_reference(args.copy_ref)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the sharding design is described in DESIGN.md); run with --gpus 1",
@@ -97,6 +121,10 @@ def main():
     ddepth = torch.zeros(total, dtype=torch.float32, device=dev)
     scount = torch.zeros(1, dtype=torch.int64, device=dev)
     dcount = torch.zeros(1, dtype=torch.int64, device=dev)
+    net = b.Net(np.load(args.weights))
+    out_rgb = torch.empty(total * 3, dtype=torch.float32, device=dev)
+    rws = torch.empty(net.workspace_bytes(V, W, H, args.precision), dtype=torch.uint8,
+                      device=dev)
     cam_list = [cams_for(k) for k in range(args.warmup + args.steps)]
     fps = [synthetic.fovea_params(W, H, sigma_frac=sig_frac, frame=k)
            for k in range(args.warmup + args.steps)]
@@ -111,6 +139,19 @@ def main():
                           frame_depth=fdepth, sample_count=scount, workspace=sws, stream=stream)
         if ev:
             ev[2].record(stream)
+        net.reconstruct(frame, mask, fdepth, V, W, H, out_rgb, precision=args.precision,
+                        workspace=rws, stream=stream)
+        if ev:
+            ev[3].record(stream)
+
+    # FP8 scales from one frame of the workload (untimed, before warm-up)
+    b.fovea_mask(fps[0], W, H, V, ray_idx, count, mask=mask, workspace=mws, stream=stream)
+    b.raymarch_sparse(volh, tf_t, cam_list[0], W, H, mp, ray_idx, count, frame_rgba=frame,
+                      frame_depth=fdepth, workspace=sws, stream=stream)
+    if args.precision == "fp8":
+        cws = torch.empty(net.workspace_bytes(V, W, H, "bf16"), dtype=torch.uint8, device=dev)
+        net.calibrate(frame, mask, fdepth, V, W, H, workspace=cws, stream=stream)
+        del cws
 
     def dense(k, ev=None):
         if ev:
@@ -130,7 +171,7 @@ def main():
     counts = []
 
     # ---- timed: foveated frames
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -140,7 +181,11 @@ def main():
     fov_ms = (t1 - t0) * 1e3 / args.steps
     mask_ms = [e[0].elapsed_time(e[1]) for e in evs]
     sparse_ms = [e[1].elapsed_time(e[2]) for e in evs]
+    recon_ms = [e[2].elapsed_time(e[3]) for e in evs]
     sparse_samples = int(scount.item())
+    last_k = args.warmup + args.steps - 1
+    fov_out = out_rgb.view(-1, 3).clone()
+    fov_mask = mask.clone()
 
     # ---- timed: dense frames (the baseline the method is compared with)
     devs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
@@ -154,6 +199,12 @@ def main():
     dense_kernel_ms = [e[0].elapsed_time(e[1]) for e in devs]
     dense_samples = int(dcount.item())
     n_rays = int(count.item())
+    # quality: the foveated reconstruction of the last timed frame against the
+    # dense march of the same frame (the dense GPU march is the judge; the FP64
+    # oracle frame is compared in the CPU-baseline leg)
+    dref = dframe.view(-1, 4)[:, :3]
+    mse = torch.mean((fov_out.clamp(0, 1) - dref.clamp(0, 1)) ** 2).item()
+    psnr_dense = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
 
     bytes_per_sample = (32 if mp["shading"] else 8) * vol.itemsize
     sp_avg = sum(sparse_ms) / len(sparse_ms)
@@ -171,7 +222,7 @@ def main():
         "metric": METRIC, "value": round(fov_ms, 4), "unit": "ms/frame", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(fov_ms, 4),
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "dtype": "f32 march / %s net" % args.precision, "data": "synthetic",
         "config": {"workload": args.workload, "volume": "%d^3 %s %s" % (vol.shape[0], vol.dtype,
                                                                          wl["volume"][0]),
                    "width": W, "height": H, "views": V,
@@ -179,7 +230,7 @@ def main():
                    "step_vox": mp["step_vox"], "alpha_stop": mp["alpha_stop"],
                    "fovea": {"sigma_px": fps[0]["sigma_px"], "p_floor": fps[0]["p_floor"],
                              "mode": "clamp"},
-                   "reconstruction": "not in the timed step yet"},
+                   "reconstruction": "U-Net 32/48/64/96 + 5x5 KPN, %s" % args.precision},
         "dense_ms_per_frame": round(dense_ms, 4),
         "speedup_vs_dense": round(dense_ms / fov_ms, 3),
         "ray_samples_per_s": round(sparse_samples / (sum(sparse_ms) * 1e-3), 1),
@@ -187,28 +238,38 @@ def main():
         "sampled_rays_per_frame": n_rays,
         "stages_ms": {"fovea_mask": round(sum(mask_ms) / len(mask_ms), 4),
                       "raymarch_sparse": round(sp_avg, 4),
+                      "reconstruct": round(sum(recon_ms) / len(recon_ms), 4),
                       "raymarch_dense": round(dn_avg, 4)},
+        "psnr_vs_gpu_dense_db": round(psnr_dense, 2),
+        "net_mfma": {"precision": args.precision, "flop_per_px": 167968,
+                     "achieved_tflops": round(167968.0 * total / (sum(recon_ms) / len(recon_ms)
+                                                                   * 1e-3) / 1e12, 1),
+                     "peak_tflops": 5000.0 if args.precision == "fp8" else 2500.0},
         "dense_roofline_frac": round(dense_ach / HBM_PEAK_GBS, 4),
         "roofline": roofline,
     }
 
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(vol, tf, cams_for(args.warmup), fps[args.warmup], W,
-                                           H, V, mp, args.cpu_rays)
+        out["cpu_baseline"] = cpu_baseline(vol, tf, cam_list[last_k], fps[last_k], W, H, V, mp,
+                                           args.cpu_rays, np.load(args.weights), args.net_crop,
+                                           fov_out.cpu().numpy(), dframe.view(-1, 4).cpu().numpy())
     volh.close()
+    net.close()
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(vol, tf, cams, fp, W, H, V, mp, n_rays):
-    """The FP64 oracle, untuned, on the host cores: full sample map + compaction,
-    and the march of a random subset of the frame's sampled rays, extrapolated to
-    the whole foveated frame (reconstruction not included)."""
+def cpu_baseline(vol, tf, cams, fp, W, H, V, mp, n_rays, theta, crop, fov_out, gpu_dense):
+    """The FP64 oracle, untuned, on the host cores, for one foveated frame: the
+    full sample map + compaction, the march of the frame's sampled rays, and the
+    network on a crop x crop tile scaled to the frame.  The same run marches
+    the dense oracle frame, the reference for the PSNR of the GPU output."""
     import numpy as np
 
     import oracle
+    from oracle import net as N
     q = {k: float(np.float32(fp[k])) for k in ("focus_x", "focus_y", "sigma_px", "p_floor")}
     t0 = time.perf_counter()
-    _, idx = oracle.fovea_mask(fp["seed"], fp["frame"], W, H, V, q["focus_x"], q["focus_y"],
+    m, idx = oracle.fovea_mask(fp["seed"], fp["frame"], W, H, V, q["focus_x"], q["focus_y"],
                                q["sigma_px"], q["p_floor"], fp["mode"])
     t_mask = time.perf_counter() - t0
     rng = np.random.default_rng(0)
@@ -219,15 +280,35 @@ def cpu_baseline(vol, tf, cams, fp, W, H, V, mp, n_rays):
     t0 = time.perf_counter()
     r = oracle.march(vol, tf, cams, W, H, mp, idx=idx[pick])
     t_march = time.perf_counter() - t0
-    per_frame_s = t_mask + t_march * idx.size / pick.size
+    # network on a crop of the packed input (same arithmetic per pixel everywhere)
+    t0 = time.perf_counter()
+    dense = oracle.march(vol, tf, cams, W, H, mp)
+    t_dense = time.perf_counter() - t0
+    sparse_rgba = np.zeros((V * W * H, 4))
+    sparse_rgba[idx] = dense["rgba"][idx]
+    x = oracle.pack_input(sparse_rgba, m.reshape(-1), dense["depth"] * m.reshape(-1))
+    x = x.reshape(V, H, W, 5).transpose(0, 3, 1, 2)
+    y0, x0 = (H - crop) // 2 // 8 * 8, (W - crop) // 2 // 8 * 8
+    t0 = time.perf_counter()
+    N.forward(theta.astype(np.float64), np.ascontiguousarray(x[:1, :, y0:y0 + crop, x0:x0 + crop]))
+    t_net = (time.perf_counter() - t0) * (W * H * V) / (crop * crop)
+    per_frame_s = t_mask + t_march * idx.size / pick.size + t_net
+    ref = dense["rgba"][:, :3]
+    psnr = N.psnr(fov_out.reshape(-1, 3), ref)
+    psnr_gpu_dense = N.psnr(gpu_dense[:, :3], ref)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
-    return {"value": round(per_frame_s * 1e3, 2), "unit": "ms/frame", "cores": cores,
+    return {"value": round(per_frame_s * 1e3, 1), "unit": "ms/frame", "cores": cores,
             "kind": "oracle",
             "ray_samples_per_s": round(float(r["samples"].sum()) / t_march, 1),
-            "sample": "one foveated frame: full sample map + compaction, then the FP64 march "
-                      "of %d of its %d sampled rays%s; reconstruction not included" %
+            "dense_ms_per_frame": round(t_dense * 1e3, 1),
+            "psnr_foveated_vs_oracle_dense_db": round(float(psnr), 2),
+            "psnr_gpu_dense_vs_oracle_dense_db": round(float(psnr_gpu_dense), 2),
+            "sample": "one foveated frame: full sample map + compaction, the FP64 march of %d "
+                      "of its %d sampled rays%s, and the FP64 network on a %dx%d crop scaled "
+                      "to the %dx%d frame; the dense oracle frame of the same view is the "
+                      "PSNR reference" %
                       (pick.size, idx.size, "" if pick.size == idx.size else
-                       " (random subset, extrapolated to the frame)")}
+                       " (random subset, scaled)", crop, crop, W, H)}
 
 
 if __name__ == "__main__":
