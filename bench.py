@@ -211,7 +211,7 @@ def main():
     ach = sparse_samples / args.steps * bytes_per_sample / (sp_avg * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": "k_march_sparse", "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": None,
+                "traffic": measured_traffic(args.workload),
                 "model": "%d B/sample = %d unique stencil voxels x %d B; %.4g samples/launch" %
                          (bytes_per_sample, bytes_per_sample // vol.itemsize, vol.itemsize,
                           sparse_samples / args.steps)}
@@ -256,6 +256,31 @@ def main():
     volh.close()
     net.close()
     print(json.dumps(out), flush=True)
+
+
+def march_source_hash():
+    """SHA-256 of the sources the sparse march kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("march.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_2209_09965_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per k_march_sparse launch from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter reads for
+    a plain device copy), or None when there is none for this workload or the
+    kernel's sources changed after the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "k_march_sparse_%s_traffic.json" % workload)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != march_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(vol, tf, cams, fp, W, H, V, mp, n_rays, theta, crop, fov_out, gpu_dense):

@@ -146,7 +146,9 @@ fv_status fv_fovea_mask(const fv_fovea_params* p, int width, int height,
  * then y, then z; nx*ny*nz elements of `dt`) into a library-owned
  * layout on the stream, then synchronises that stream.  The handle owns that copy until
  * fv_volume_destroy.  Errors: null pointers, any dimension < 1 or > 4096,
- * unknown dtype (FV_ERR_UNSUPPORTED), allocation failure (FV_ERR_NOMEM). */
+ * unknown dtype or a padded copy of 4 GiB or more, i.e.
+ * (nx+4)(ny+4)(nz+4) x bytes per voxel >= 2^32 (FV_ERR_UNSUPPORTED),
+ * allocation failure (FV_ERR_NOMEM). */
 typedef struct fv_volume fv_volume;
 
 fv_status fv_volume_create(const void* dev_data, int nx, int ny, int nz,
@@ -268,7 +270,9 @@ fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba,
  *  FV_PREC_FP8   activations and weights FP8 E4M3 (OCP), FP32 accumulation;
  *                per-tensor activation scales from fv_net_calibrate are
  *                folded into per-output-channel weight scales.
- *  The heads (softmax and kernel application) always run in FP32.
+ *  The two 1x1 heads run on MFMA with BF16 operands (FP8 activations are
+ *  widened) and FP32 accumulation; softmax and the kernel application run
+ *  in FP32.
  */
 #define FV_NET_PARAMS 480060
 

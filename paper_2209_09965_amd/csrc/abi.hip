@@ -73,6 +73,12 @@ fv_status fv_volume_create(const void* dev_data, int nx, int ny, int nz, fv_dtyp
   }
   int64_t total = v->px * v->py * v->pz;
   size_t bytes = (size_t)total * fv::dtype_bytes(dt);
+  if (bytes >= ((size_t)1 << 32) - 1) {
+    delete v;
+    return fv::fail(FV_ERR_UNSUPPORTED,
+                    "fv_volume_create: the padded copy must be < 4 GiB "
+                    "((nx+4)(ny+4)(nz+4) x bytes per voxel)");
+  }
   if (hipMalloc(&v->data, bytes) != hipSuccess) {
     delete v;
     return fv::fail(FV_ERR_NOMEM, "fv_volume_create: cannot allocate %zu bytes", bytes);

@@ -24,6 +24,7 @@ struct CamD {
 
 struct MarchArgs {
   const void* vol;
+  uint32_t vol_bytes;  // size of the padded copy (< 2^32)
   int64_t px, py;  // padded row / slice pitch in elements
   int n[3];
   double h;        // voxel edge in world units
@@ -61,19 +62,50 @@ __device__ __forceinline__ float pow_small(float x, int n, float p) {
   return r;
 }
 
+template <typename VT>
+__device__ __forceinline__ VT buffer_voxel(__amdgpu_buffer_rsrc_t rs, int voff, int soff);
+template <>
+__device__ __forceinline__ float buffer_voxel<float>(__amdgpu_buffer_rsrc_t rs, int voff,
+                                                     int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rs, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ _Float16 buffer_voxel<_Float16>(__amdgpu_buffer_rsrc_t rs, int voff,
+                                                           int soff) {
+  return __builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(rs, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ uint8_t buffer_voxel<uint8_t>(__amdgpu_buffer_rsrc_t rs, int voff,
+                                                         int soff) {
+  return __builtin_amdgcn_raw_buffer_load_b8(rs, voff, soff, 0);
+}
+
 struct RayOut {
   float4 rgba;
   float depth;
   uint32_t samples;
 };
 
-template <int DT, bool SHADE>
-__device__ __forceinline__ RayOut march_ray(const MarchArgs& a, const float4* __restrict__ tfs,
-                                            int view, int x, int y) {
-  using VT = typename Voxel<DT>::T;
-  RayOut out;
-  out.depth = 0.0f;
-  out.samples = 0;
+// Per-ray marching state.  Full segments k sample at m_k = (k + 1/2) step
+// voxel lengths from the entry, so the sample position in voxel index space
+// is q_k = q0 + k qs with q0 = qe + d step/2 and qs = d step (FP64); only the
+// last segment may be shorter (length last_len): its midpoint is
+// q0 + klast qs with klast = N - 3/2 + last_len / (2 step).
+struct RayState {
+  double q0[3], qs[3];
+  double klast;
+  float t0, tstep, tlast;  // world-space distance of full / last samples
+  float last_len;
+  float hv[3];
+  int N, k;
+  float C0, C1, C2, T, D;
+};
+
+// Ray set-up: camera ray through the pixel centre, slab test, segment count.
+// Returns false on a miss.
+template <bool SHADE>
+__device__ __forceinline__ bool ray_setup(const MarchArgs& a, int view, int x, int y,
+                                          RayState& s) {
   const CamD& c = a.cam[view];
   const double pxn = (2.0 * ((double)x + 0.5) / a.W - 1.0) * c.sx;
   const double pyn = (1.0 - 2.0 * ((double)y + 0.5) / a.H) * c.sy;
@@ -81,7 +113,6 @@ __device__ __forceinline__ RayOut march_ray(const MarchArgs& a, const float4* __
   for (int i = 0; i < 3; ++i) d[i] = c.f[i] + pxn * c.r[i] + pyn * c.u[i];
   const double dl = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
   for (int i = 0; i < 3; ++i) d[i] /= dl;
-  // slab test
   double tn = -INFINITY, tf = INFINITY;
   bool miss = false;
   for (int i = 0; i < 3; ++i) {
@@ -94,103 +125,215 @@ __device__ __forceinline__ RayOut march_ray(const MarchArgs& a, const float4* __
     tf = fmin(tf, fmax(ta, tb));
   }
   tn = fmax(tn, 0.0);
-  if (miss || !(tf > tn)) {
-    out.rgba = make_float4(a.bg[0], a.bg[1], a.bg[2], 0.0f);
-    return out;
-  }
+  if (miss || !(tf > tn)) return false;
   const double L = (tf - tn) / a.h;
-  const int64_t N = (int64_t)ceil(L / a.step);
-  double qe[3];
-  for (int i = 0; i < 3; ++i) qe[i] = (c.o[i] + d[i] * tn + a.half[i]) / a.h - 0.5;
-  float hv[3] = {0.f, 0.f, 0.f};
+  s.N = (int)ceil(L / a.step);
+  const double mh = 0.5 * a.step;
+  const double la = (double)(s.N - 1) * a.step;  // start of the last segment
+  const double lm = 0.5 * (la + L);                // its midpoint
+  for (int i = 0; i < 3; ++i) {
+    const double qe = (c.o[i] + d[i] * tn + a.half[i]) / a.h - 0.5;
+    s.q0[i] = qe + d[i] * mh;
+    s.qs[i] = d[i] * a.step;
+  }
+  s.klast = (double)s.N - 1.5 + (L - la) / (2.0 * a.step);
+  s.t0 = (float)(tn + a.h * mh);
+  s.tstep = (float)(a.h * a.step);
+  s.tlast = (float)(tn + a.h * lm);
+  s.last_len = (float)(L - la);
   if (SHADE) {
     double hd[3];
     for (int i = 0; i < 3; ++i) hd[i] = (double)a.light[i] - d[i];
     double hl = sqrt(hd[0] * hd[0] + hd[1] * hd[1] + hd[2] * hd[2]);
     hl = fmax(hl, 1e-30);
-    for (int i = 0; i < 3; ++i) hv[i] = (float)(hd[i] / hl);
+    for (int i = 0; i < 3; ++i) s.hv[i] = (float)(hd[i] / hl);
   }
-  const VT* __restrict__ vol = (const VT*)a.vol;
-  const int64_t sy = a.px, sz = a.px * a.py;
-  float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.0f, D = 0.0f;
-  uint32_t ns = 0;
-  for (int64_t k = 0; k < N; ++k) {
-    const double a0 = (double)k * a.step;
-    const double b0 = fmin((double)(k + 1) * a.step, L);
-    const double m = 0.5 * (a0 + b0);
-    const float len = (float)(b0 - a0);
-    const float t = (float)(tn + a.h * m);
-    int ii[3];
-    float w[3];
-    for (int i = 0; i < 3; ++i) {
-      const double q = qe[i] + d[i] * m;
-      const double fq = floor(q);
-      int iq = (int)fq;
-      w[i] = (float)(q - fq);
-      iq = min(max(iq, -1), a.n[i] - 1);
-      ii[i] = iq;
-    }
-    const VT* b = vol + ((int64_t)(ii[2] + 2) * sz + (int64_t)(ii[1] + 2) * sy + (ii[0] + 2));
-    const float v000 = Voxel<DT>::f(b[0]), v100 = Voxel<DT>::f(b[1]);
-    const float v010 = Voxel<DT>::f(b[sy]), v110 = Voxel<DT>::f(b[sy + 1]);
-    const float v001 = Voxel<DT>::f(b[sz]), v101 = Voxel<DT>::f(b[sz + 1]);
-    const float v011 = Voxel<DT>::f(b[sz + sy]), v111 = Voxel<DT>::f(b[sz + sy + 1]);
-    const float v = tri(v000, v100, v010, v110, v001, v101, v011, v111, w[0], w[1], w[2]);
-    // transfer function: linear interpolation between the 256 entries
-    const float xv = fminf(fmaxf(v, 0.0f), 1.0f) * 255.0f;
-    const int j = min((int)xv, 254);
-    const float fr = xv - (float)j;
-    const float4 e0 = tfs[j], e1 = tfs[j + 1];
-    float r = lerpf(e0.x, e1.x, fr), g = lerpf(e0.y, e1.y, fr), bl = lerpf(e0.z, e1.z, fr);
-    const float sig = lerpf(e0.w, e1.w, fr);
-    const float alpha = -expm1f(-sig * len);
-    if (SHADE) {
-      // one-voxel central differences of the interpolated field
-      const float xm00 = Voxel<DT>::f(b[-1]), xm10 = Voxel<DT>::f(b[sy - 1]);
-      const float xm01 = Voxel<DT>::f(b[sz - 1]), xm11 = Voxel<DT>::f(b[sz + sy - 1]);
-      const float xp00 = Voxel<DT>::f(b[2]), xp10 = Voxel<DT>::f(b[sy + 2]);
-      const float xp01 = Voxel<DT>::f(b[sz + 2]), xp11 = Voxel<DT>::f(b[sz + sy + 2]);
-      const float ym00 = Voxel<DT>::f(b[-sy]), ym10 = Voxel<DT>::f(b[-sy + 1]);
-      const float ym01 = Voxel<DT>::f(b[sz - sy]), ym11 = Voxel<DT>::f(b[sz - sy + 1]);
-      const float yp00 = Voxel<DT>::f(b[2 * sy]), yp10 = Voxel<DT>::f(b[2 * sy + 1]);
-      const float yp01 = Voxel<DT>::f(b[sz + 2 * sy]), yp11 = Voxel<DT>::f(b[sz + 2 * sy + 1]);
-      const float zm00 = Voxel<DT>::f(b[-sz]), zm10 = Voxel<DT>::f(b[-sz + 1]);
-      const float zm01 = Voxel<DT>::f(b[-sz + sy]), zm11 = Voxel<DT>::f(b[-sz + sy + 1]);
-      const float zp00 = Voxel<DT>::f(b[2 * sz]), zp10 = Voxel<DT>::f(b[2 * sz + 1]);
-      const float zp01 = Voxel<DT>::f(b[2 * sz + sy]), zp11 = Voxel<DT>::f(b[2 * sz + sy + 1]);
-      const float gx = 0.5f * tri(v100 - xm00, xp00 - v000, v110 - xm10, xp10 - v010,
-                                  v101 - xm01, xp01 - v001, v111 - xm11, xp11 - v011, w[0], w[1],
-                                  w[2]);
-      const float gy = 0.5f * tri(v010 - ym00, v110 - ym10, yp00 - v000, yp10 - v100,
-                                  v011 - ym01, v111 - ym11, yp01 - v001, yp11 - v101, w[0], w[1],
-                                  w[2]);
-      const float gz = 0.5f * tri(v001 - zm00, v101 - zm10, v011 - zm01, v111 - zm11,
-                                  zp00 - v000, zp10 - v100, zp01 - v010, zp11 - v110, w[0], w[1],
-                                  w[2]);
-      const float inv = rsqrtf(fmaxf(gx * gx + gy * gy + gz * gz, 1e-8f));
-      const float nx = -gx * inv, ny = -gy * inv, nz = -gz * inv;
-      const float ndl = fabsf(nx * a.light[0] + ny * a.light[1] + nz * a.light[2]);
-      const float ndh = fabsf(nx * hv[0] + ny * hv[1] + nz * hv[2]);
-      const float spec = a.ks * pow_small(ndh, a.ipow, a.shininess);
-      const float diff = a.ka + a.kd * ndl;
-      r = r * diff + spec;
-      g = g * diff + spec;
-      bl = bl * diff + spec;
-    }
-    const float wgt = T * alpha;
-    C0 = fmaf(wgt, r, C0);
-    C1 = fmaf(wgt, g, C1);
-    C2 = fmaf(wgt, bl, C2);
-    D = fmaf(wgt, t, D);
-    T *= (1.0f - alpha);
-    ++ns;
-    if (1.0f - T >= a.alpha_stop) break;
+  s.k = 0;
+  s.C0 = s.C1 = s.C2 = 0.f;
+  s.T = 1.0f;
+  s.D = 0.0f;
+  return true;
+}
+
+// The voxels one sample reads, as stored (converted to float when used):
+// the 8 corners of its cell and, when shading, the 24 more voxels of the
+// one-voxel central differences (the 4 x 2 x 2, 2 x 4 x 2 and 2 x 2 x 4 arms).
+// Stencil voxel (x, y, z) is at offset (x - 1, y - 1, z - 1) from the cell's
+// minimum corner.
+template <int DT, bool SHADE>
+struct Stencil {
+  typename Voxel<DT>::T c[8];            // centre cell, index x + 2 y + 4 z
+  typename Voxel<DT>::T g[SHADE ? 24 : 1];  // arms: x-, x+, y-, y+, z-, z+ (4 each)
+  float w[3];                            // trilinear weights
+};
+
+// Issues the voxel loads of sample k of the ray (k = N - 1 is the last,
+// possibly shorter, segment).  Nothing here waits for the loads, so the
+// caller can composite the previous sample while they are in flight.  A lane
+// with live == false issues its loads at an offset past the end of the
+// buffer: the hardware range check returns zeros without touching memory,
+// which lets a wave run the pipelined loop without branching around idle
+// lanes.
+template <int DT, bool SHADE>
+__device__ __forceinline__ void gather(const MarchArgs& a, const RayState& s, int k,
+                                       Stencil<DT, SHADE>& st, bool live = true) {
+  using VT = typename Voxel<DT>::T;
+  const double kk = k == s.N - 1 ? s.klast : (double)k;
+  int ii[3];
+  for (int i = 0; i < 3; ++i) {
+    const double q = fma(kk, s.qs[i], s.q0[i]);
+    const double fq = floor(q);
+    st.w[i] = (float)(q - fq);
+    ii[i] = min(max((int)fq, -1), a.n[i] - 1);
   }
-  out.rgba = make_float4(fmaf(T, a.bg[0], C0), fmaf(T, a.bg[1], C1), fmaf(T, a.bg[2], C2),
-                         1.0f - T);
-  out.depth = D;
-  out.samples = ns;
-  return out;
+  // Voxel gathers as buffer loads: the VGPR offset addresses the stencil's
+  // minimum corner (i0-1, j0-1, k0-1); the (y, z) row offsets are uniform
+  // (SGPR) and x is the immediate, so a gather costs no vector ALU work.
+  // Reads outside the buffer return 0 (hardware range check).
+  constexpr int EB = (int)sizeof(VT);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.vol, (short)0, (int)a.vol_bytes, 0x00020000);
+  const int sy = (int)a.px * EB, sz = (int)(a.px * a.py) * EB;
+  const uint32_t oi = ((uint32_t)(ii[2] + 1) * (uint32_t)(a.px * a.py) +
+                       (uint32_t)(ii[1] + 1) * (uint32_t)a.px + (uint32_t)(ii[0] + 1)) * EB;
+  const int o = (int)(live ? oi : a.vol_bytes);
+#define FV_V(x, y, z) buffer_voxel<VT>(rs, o + (x) * EB, (y) * sy + (z) * sz)
+  for (int z = 0; z < 2; ++z)
+    for (int y = 0; y < 2; ++y)
+      for (int x = 0; x < 2; ++x) st.c[x + 2 * y + 4 * z] = FV_V(1 + x, 1 + y, 1 + z);
+  if (SHADE) {
+    for (int j = 0; j < 4; ++j) {
+      const int u = 1 + (j & 1), v = 1 + (j >> 1);
+      st.g[0 + j] = FV_V(0, u, v);    // x - 1
+      st.g[4 + j] = FV_V(3, u, v);    // x + 2
+      st.g[8 + j] = FV_V(u, 0, v);    // y - 1
+      st.g[12 + j] = FV_V(u, 3, v);   // y + 2
+      st.g[16 + j] = FV_V(u, v, 0);   // z - 1
+      st.g[20 + j] = FV_V(u, v, 3);   // z + 2
+    }
+  }
+#undef FV_V
+}
+
+// dst = c ? src : dst, element by element.
+template <int DT, bool SHADE>
+__device__ __forceinline__ void select_stencil(bool c, const Stencil<DT, SHADE>& src,
+                                               Stencil<DT, SHADE>& dst) {
+  for (int i = 0; i < 8; ++i) dst.c[i] = c ? src.c[i] : dst.c[i];
+  if (SHADE)
+    for (int i = 0; i < 24; ++i) dst.g[i] = c ? src.g[i] : dst.g[i];
+  for (int i = 0; i < 3; ++i) dst.w[i] = c ? src.w[i] : dst.w[i];
+}
+
+// One segment from its gathered voxels: trilinear sample (plus the
+// central-difference gradient and Blinn-Phong when shading), TF lookup,
+// front-to-back compositing.  Advances k; returns true when the ray is
+// finished (last segment or early termination).
+template <int DT, bool SHADE>
+__device__ __forceinline__ bool composite(const MarchArgs& a, const float4* __restrict__ tfs,
+                                          RayState& s, const Stencil<DT, SHADE>& st) {
+  const bool last = s.k == s.N - 1;
+  float len, t;
+  if (last) {
+    len = s.last_len;
+    t = s.tlast;
+  } else {
+    len = (float)a.step;
+    t = fmaf((float)s.k, s.tstep, s.t0);
+  }
+  const float wx = st.w[0], wy = st.w[1], wz = st.w[2];
+#define FV_C(x, y, z) Voxel<DT>::f(st.c[(x) + 2 * (y) + 4 * (z)])
+  const float v000 = FV_C(0, 0, 0), v100 = FV_C(1, 0, 0);
+  const float v010 = FV_C(0, 1, 0), v110 = FV_C(1, 1, 0);
+  const float v001 = FV_C(0, 0, 1), v101 = FV_C(1, 0, 1);
+  const float v011 = FV_C(0, 1, 1), v111 = FV_C(1, 1, 1);
+#undef FV_C
+  const float v = tri(v000, v100, v010, v110, v001, v101, v011, v111, wx, wy, wz);
+  // transfer function: linear interpolation between the 256 entries
+  const float xv = fminf(fmaxf(v, 0.0f), 1.0f) * 255.0f;
+  const int j = min((int)xv, 254);
+  const float fr = xv - (float)j;
+  const float4 e0 = tfs[j], e1 = tfs[j + 1];
+  float r = lerpf(e0.x, e1.x, fr), g = lerpf(e0.y, e1.y, fr), bl = lerpf(e0.z, e1.z, fr);
+  const float sig = lerpf(e0.w, e1.w, fr);
+  // segment transmittance exp(-sigma l) (hardware exp), opacity 1 - that
+  const float tr = __expf(-sig * len);
+  const float alpha = 1.0f - tr;
+  if (SHADE) {
+    // one-voxel central differences of the interpolated field; arm entry j
+    // holds the voxel at (u, v) = (j & 1, j >> 1) across the arm's axis
+#define FV_G(i) Voxel<DT>::f(st.g[i])
+    const float xm00 = FV_G(0), xm10 = FV_G(1), xm01 = FV_G(2), xm11 = FV_G(3);
+    const float xp00 = FV_G(4), xp10 = FV_G(5), xp01 = FV_G(6), xp11 = FV_G(7);
+    const float ym00 = FV_G(8), ym10 = FV_G(9), ym01 = FV_G(10), ym11 = FV_G(11);
+    const float yp00 = FV_G(12), yp10 = FV_G(13), yp01 = FV_G(14), yp11 = FV_G(15);
+    const float zm00 = FV_G(16), zm10 = FV_G(17), zm01 = FV_G(18), zm11 = FV_G(19);
+    const float zp00 = FV_G(20), zp10 = FV_G(21), zp01 = FV_G(22), zp11 = FV_G(23);
+#undef FV_G
+    // x arms: (u, v) = (y, z); y arms: (x, z); z arms: (x, y)
+    const float gx = 0.5f * tri(v100 - xm00, xp00 - v000, v110 - xm10, xp10 - v010, v101 - xm01,
+                                xp01 - v001, v111 - xm11, xp11 - v011, wx, wy, wz);
+    const float gy = 0.5f * tri(v010 - ym00, v110 - ym10, yp00 - v000, yp10 - v100, v011 - ym01,
+                                v111 - ym11, yp01 - v001, yp11 - v101, wx, wy, wz);
+    const float gz = 0.5f * tri(v001 - zm00, v101 - zm10, v011 - zm01, v111 - zm11, zp00 - v000,
+                                zp10 - v100, zp01 - v010, zp11 - v110, wx, wy, wz);
+    const float inv = rsqrtf(fmaxf(gx * gx + gy * gy + gz * gz, 1e-8f));
+    const float nx = -gx * inv, ny = -gy * inv, nz = -gz * inv;
+    const float ndl = fabsf(nx * a.light[0] + ny * a.light[1] + nz * a.light[2]);
+    const float ndh = fabsf(nx * s.hv[0] + ny * s.hv[1] + nz * s.hv[2]);
+    const float spec = a.ks * pow_small(ndh, a.ipow, a.shininess);
+    const float diff = a.ka + a.kd * ndl;
+    r = r * diff + spec;
+    g = g * diff + spec;
+    bl = bl * diff + spec;
+  }
+  const float wgt = s.T * alpha;
+  s.C0 = fmaf(wgt, r, s.C0);
+  s.C1 = fmaf(wgt, g, s.C1);
+  s.C2 = fmaf(wgt, bl, s.C2);
+  s.D = fmaf(wgt, t, s.D);
+  s.T *= tr;
+  ++s.k;
+  return last || 1.0f - s.T >= a.alpha_stop;
+}
+
+__device__ __forceinline__ RayOut ray_finish(const MarchArgs& a, const RayState& s) {
+  RayOut o;
+  o.rgba = make_float4(fmaf(s.T, a.bg[0], s.C0), fmaf(s.T, a.bg[1], s.C1),
+                       fmaf(s.T, a.bg[2], s.C2), 1.0f - s.T);
+  o.depth = s.D;
+  o.samples = (uint32_t)s.k;
+  return o;
+}
+
+__device__ __forceinline__ RayOut ray_miss(const MarchArgs& a) {
+  RayOut o;
+  o.rgba = make_float4(a.bg[0], a.bg[1], a.bg[2], 0.0f);
+  o.depth = 0.0f;
+  o.samples = 0;
+  return o;
+}
+
+// The march loop is software-pipelined: the gathers of sample k + 1 are
+// issued before sample k is composited (two stencil buffers, A and B), so the
+// memory latency of one sample overlaps the arithmetic of the previous one.
+// The sample after the last is never read: its index is clamped to N - 1.
+template <int DT, bool SHADE>
+__device__ __forceinline__ RayOut march_ray(const MarchArgs& a, const float4* __restrict__ tfs,
+                                            int view, int x, int y) {
+  RayState s;
+  if (!ray_setup<SHADE>(a, view, x, y, s)) return ray_miss(a);
+  if (s.N > 0) {
+    Stencil<DT, SHADE> A, B;
+    gather(a, s, 0, A);
+    while (true) {
+      gather(a, s, min(s.k + 1, s.N - 1), B);
+      if (composite(a, tfs, s, A)) break;
+      gather(a, s, min(s.k + 1, s.N - 1), A);
+      if (composite(a, tfs, s, B)) break;
+    }
+  }
+  return ray_finish(a, s);
 }
 
 __device__ __forceinline__ void add_samples(unsigned long long* nsamp, uint32_t ns) {
@@ -222,33 +365,104 @@ __global__ void __launch_bounds__(256) k_march_dense(MarchArgs a, float4* __rest
   if (nsamp) add_samples(nsamp, ns);
 }
 
-// Sparse: grid-stride over the compacted list; results go to the compact
-// buffers and/or back to their pixels in the full frame.
+__global__ void k_clear_queue(uint32_t* q) {
+  if (threadIdx.x == 0) q[0] = 0u;
+}
+
+// Sparse, persistent: every wave claims rays from a global queue (one atomic
+// per refill round) in list order; every kStepsPerRefill segments, lanes whose
+// ray has finished (or missed the box) take the next rays, so long and short
+// rays of the sparse periphery do not leave lanes idle.  Results go to the
+// compact buffers and/or back to their pixels (back-projection).
+constexpr int kStepsPerRefill = 8;
+
 template <int DT, bool SHADE>
 __global__ void __launch_bounds__(256) k_march_sparse(
     MarchArgs a, const uint32_t* __restrict__ ray_idx, const uint32_t* __restrict__ count,
     uint32_t capacity, float4* __restrict__ rgba_c, float* __restrict__ depth_c,
     float4* __restrict__ rgba_f, float* __restrict__ depth_f,
-    unsigned long long* __restrict__ nsamp) {
+    unsigned long long* __restrict__ nsamp, uint32_t* __restrict__ queue) {
   __shared__ float4 tfs[FV_TF_ENTRIES];
   tfs[threadIdx.x] = a.tf[threadIdx.x];
   __syncthreads();
   const uint32_t n = min(*count, capacity);
   const uint32_t wh = (uint32_t)a.W * (uint32_t)a.H;
+  const int lane = threadIdx.x & 63;
+  const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
+  // Idle lanes run the loop body too, so their state and buffers start
+  // defined (zero) rather than uninitialised.
+  RayState s{};
+  s.N = 1;
+  Stencil<DT, SHADE> A{}, B{};
+  bool active = false, exhausted = false;
+  uint32_t slot = 0, lin = 0;
   uint32_t ns = 0;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t lin = ray_idx[i];
-    if (lin >= a.total) continue;
-    const int view = (int)(lin / wh);
-    const uint32_t rem = lin - (uint32_t)view * wh;
-    const int y = (int)(rem / (uint32_t)a.W), x = (int)(rem - (uint32_t)y * a.W);
-    const RayOut r = march_ray<DT, SHADE>(a, tfs, view, x, y);
-    if (rgba_c) rgba_c[i] = r.rgba;
-    if (depth_c) depth_c[i] = r.depth;
-    if (rgba_f) rgba_f[lin] = r.rgba;
-    if (depth_f) depth_f[lin] = r.depth;
-    ns += r.samples;
+  while (true) {
+    const bool want = !active && !exhausted;
+    const uint64_t m = __ballot(want);
+    bool fresh = false;  // claimed a ray this round that needs marching
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      uint32_t base = 0;
+      if (lane == leader) base = atomicAdd(queue, (uint32_t)__popcll(m));
+      base = __shfl(base, leader, 64);
+      if (want) {
+        slot = base + (uint32_t)__popcll(m & lt);
+        if (slot >= n) {
+          exhausted = true;
+        } else {
+          lin = ray_idx[slot];
+          if (lin < a.total) {
+            const int view = (int)(lin / wh);
+            const uint32_t rem = lin - (uint32_t)view * wh;
+            const int y = (int)(rem / (uint32_t)a.W), x = (int)(rem - (uint32_t)y * a.W);
+            const bool hit = ray_setup<SHADE>(a, view, x, y, s);
+            active = hit && s.N > 0;
+            fresh = active;
+            if (!active) {
+              // a miss, or a zero-length ray inside the box
+              const RayOut o = hit ? ray_finish(a, s) : ray_miss(a);
+              if (rgba_c) rgba_c[slot] = o.rgba;
+              if (depth_c) depth_c[slot] = o.depth;
+              if (rgba_f) rgba_f[lin] = o.rgba;
+              if (depth_f) depth_f[lin] = o.depth;
+            }
+          }
+        }
+      }
+    }
+    // first gathers of the new rays, outside the divergent claim code (so the
+    // stencil registers are not copied around it)
+    if (__ballot(fresh)) {
+      Stencil<DT, SHADE> F;
+      gather(a, s, 0, F, fresh);
+      select_stencil(fresh, F, A);
+    }
+    if (!__ballot(active)) {
+      if (!__ballot(!exhausted)) break;
+      continue;
+    }
+    // pipelined as in march_ray; an even number of steps per round leaves the
+    // next sample's voxels in A, where a newly claimed ray also starts
+    auto finish = [&]() {
+      const RayOut o = ray_finish(a, s);
+      if (rgba_c) rgba_c[slot] = o.rgba;
+      if (depth_c) depth_c[slot] = o.depth;
+      if (rgba_f) rgba_f[lin] = o.rgba;
+      if (depth_f) depth_f[lin] = o.depth;
+      ns += o.samples;
+      active = false;
+    };
+    static_assert(kStepsPerRefill % 2 == 0, "steps per refill round must be even");
+    // Every lane runs the loop body (idle lanes gather nothing and their
+    // state is discarded); only active lanes commit a finished ray.
+#pragma unroll 1
+    for (int it = 0; it < kStepsPerRefill; it += 2) {
+      gather(a, s, min(s.k + 1, s.N - 1), B, active);
+      if (composite(a, tfs, s, A) && active) finish();
+      gather(a, s, min(s.k + 1, s.N - 1), A, active);
+      if (composite(a, tfs, s, B) && active) finish();
+    }
   }
   if (nsamp) add_samples(nsamp, ns);
 }
@@ -274,6 +488,7 @@ fv_status fill_args(const fv_volume* v, const float* tf, int tf_n, const fv_came
   if (mp->shading != 0 && mp->shading != 1)
     return fail(FV_ERR_UNSUPPORTED, "%s: shading must be 0 or 1", fn);
   a->vol = v->data;
+  a->vol_bytes = (uint32_t)((uint64_t)v->px * v->py * v->pz * dtype_bytes(v->dt));
   a->px = v->px;
   a->py = v->py;
   int nmax = 0;
@@ -350,11 +565,25 @@ void launch_dense(const MarchArgs& a, float* rgba, float* depth, uint64_t* ns, h
 template <int DT, bool SHADE>
 void launch_sparse(const MarchArgs& a, const uint32_t* idx, const uint32_t* count,
                    uint32_t capacity, float* rc, float* dc, float* rf, float* df, uint64_t* ns,
-                   hipStream_t s) {
-  const uint64_t blocks = ((uint64_t)capacity + 255) / 256;
-  const unsigned grid = (unsigned)(blocks < 8192 ? blocks : 8192);
-  k_march_sparse<DT, SHADE><<<grid, 256, 0, s>>>(a, idx, count, capacity, (float4*)rc, dc,
-                                                 (float4*)rf, df, (unsigned long long*)ns);
+                   uint32_t* queue, hipStream_t s) {
+  // persistent grid: as many blocks as can be resident at once
+  static int per_cu = 0, cus = 0;
+  if (!per_cu) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march_sparse<DT, SHADE>, 256,
+                                                     0) != hipSuccess || per_cu < 1)
+      per_cu = 4;
+    if (cus < 1) cus = 256;
+  }
+  const uint64_t need = ((uint64_t)capacity + 255) / 256;
+  uint64_t grid = (uint64_t)per_cu * cus;
+  if (grid > need) grid = need;
+  k_clear_queue<<<1, 64, 0, s>>>(queue);
+  k_march_sparse<DT, SHADE><<<(unsigned)grid, 256, 0, s>>>(a, idx, count, capacity, (float4*)rc,
+                                                           dc, (float4*)rf, df,
+                                                           (unsigned long long*)ns, queue);
 }
 
 }  // namespace
@@ -420,11 +649,13 @@ fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba, int tf_n,
     return fv::fail(FV_ERR_INVALID_ARG, "fv_raymarch_sparse: no output given");
   hipStream_t s = (hipStream_t)stream;
   const bool sh = mp->shading != 0;
+  uint32_t* queue = (uint32_t*)workspace;
 #define FV_SPARSE(DT)                                                                          \
   (sh ? fv::launch_sparse<DT, true>(a, ray_idx, count, capacity, rgba_compact, depth_compact, \
-                                    frame_rgba, frame_depth, sample_count, s)                 \
+                                    frame_rgba, frame_depth, sample_count, queue, s)          \
       : fv::launch_sparse<DT, false>(a, ray_idx, count, capacity, rgba_compact,               \
-                                     depth_compact, frame_rgba, frame_depth, sample_count, s))
+                                     depth_compact, frame_rgba, frame_depth, sample_count,    \
+                                     queue, s))
   switch (v->dt) {
     case FV_U8:
       FV_SPARSE(FV_U8);

@@ -131,74 +131,162 @@ __global__ void __launch_bounds__(256) k_avgpool2(const uint8_t* __restrict__ sr
 
 // Heads: O_d = 1x1 conv (32 -> 3), logits = 1x1 conv (32 -> 25), w = softmax,
 // out(p) = sum_k w_k(p) O_d(clamp(p + delta_k)) over the 5x5 taps.
-// One 16x16 output tile per block; O_d of the tile plus a 2-pixel clamped
-// halo is computed once into LDS.
+// One 16x16 output tile per block.  The two 1x1 convs are one MFMA GEMM
+// [400 halo pixels x 32] x [32 x 32] (BF16 operands, FP32 accumulation; FP8
+// activations are widened in registers) whose 28 used columns land in LDS;
+// softmax and the kernel application run in FP32.
+// 8 stored channels of one pixel (FP8 times its tensor scale) as BF16.
+template <class E>
+__device__ __forceinline__ bf16x8_t heads_frag(const typename Chunk8<E>::T& raw, float in_scale) {
+  float v[8];
+  E::load8((const uint8_t*)&raw, v);
+  bf16x8_t f;
+  for (int j = 0; j < 8; ++j) f[j] = (__bf16)(v[j] * in_scale);
+  return f;
+}
+
+template <>
+__device__ __forceinline__ bf16x8_t heads_frag<BF16>(const uint4& raw, float) {
+  return __builtin_bit_cast(bf16x8_t, raw);
+}
+
+// The two 1x1 heads and the kernel-prediction output (Sec. 3.2, "Direct
+// Prediction" and "Kernel Prediction"): per pixel
+// O_d = hd . h + b_d and logits = hk . h + b_k (h = the 32 decoder channels),
+// w = softmax(logits) over the 25 taps, O = sum_q w_q O_d(pixel + offset_q)
+// with edge-replicated O_d.  Block = 16 x 16 output pixels.  Both heads run
+// on MFMA with the head weights as the A operand, so a lane holds 4 output
+// channels of one pixel: O_d of the 20 x 20 halo goes to LDS, while the
+// logits of a tile pixel stay in the registers of the 4 lanes that own it
+// and the softmax and the 5 x 5 sum reduce across those lanes.  All global
+// loads of a wave are issued before the first MFMA.
 template <class E>
 __global__ void __launch_bounds__(256) k_heads(const uint8_t* __restrict__ hdec, int n, int h,
                                                int w, const float* __restrict__ params,
+                                               const __bf16* __restrict__ whs,
                                                int64_t off_hd, int64_t off_hk, float in_scale,
                                                float* __restrict__ out_rgb,
                                                float* __restrict__ out_od,
                                                float* __restrict__ out_wk) {
-  __shared__ float s_od[20 * 20 * 3];
-  const int tid = threadIdx.x;
-  const float* __restrict__ whd = params + off_hd;  // [3][32] then bias [3]
-  const float* __restrict__ whk = params + off_hk;  // [25][32] then bias [25]
+  constexpr int HW = 20, HB = HW * HW / 16;  // halo width, halo blocks of 16 pixels
+  constexpr int KH = (HB + 3) / 4;           // halo blocks per wave (at most)
+  using Raw = typename Chunk8<E>::T;
+  __shared__ float4 s_od[HW * HW];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, grp = lane >> 4;
   const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 16, b = blockIdx.z;
-  for (int e = tid; e < 400; e += 256) {
-    const int r = e / 20, c = e % 20;
-    const int y = min(max(y0 - 2 + r, 0), h - 1), x = min(max(x0 - 2 + c, 0), w - 1);
-    float f[32];
-    E::load32(hdec + (((int64_t)b * h + y) * w + x) * 32 * E::kBytes, f);
-    for (int k = 0; k < 32; ++k) f[k] *= in_scale;
-    for (int ch = 0; ch < 3; ++ch) {
-      float s = whd[96 + ch];
-      for (int k = 0; k < 32; ++k) s = fmaf(whd[ch * 32 + k], f[k], s);
-      s_od[e * 3 + ch] = s;
+  const uint8_t* img = hdec + (int64_t)b * h * w * 32 * E::kBytes + 8 * grp * E::kBytes;
+  Raw rh[KH], rc[4];
+  for (int k = 0; k < KH; ++k) {
+    const int hb = wave + 4 * k;
+    if (hb < HB) {
+      const int hp = hb * 16 + col, r = hp / HW, c = hp - r * HW;
+      const int y = min(max(y0 - 2 + r, 0), h - 1), x = min(max(x0 - 2 + c, 0), w - 1);
+      rh[k] = *(const Raw*)(img + ((int64_t)y * w + x) * 32 * E::kBytes);
+    }
+  }
+  for (int m = 0; m < 4; ++m) {
+    const int y = min(y0 + wave * 4 + m, h - 1), x = min(x0 + col, w - 1);
+    rc[m] = *(const Raw*)(img + ((int64_t)y * w + x) * 32 * E::kBytes);
+  }
+  // A operands: rows 0-15 = [hd 0-2, hk 0-12], rows 16-31 = [hk 13-24, 4 zero]
+  const bf16x8_t w0 = *(const bf16x8_t*)(whs + (size_t)lane * 8);
+  const bf16x8_t w1 = *(const bf16x8_t*)(whs + (size_t)(64 + lane) * 8);
+  // this lane's 8 output channels: 4 grp + i (block 0) and 16 + 4 grp + i
+  // (block 1); channel c < 3 is O_d, 3 <= c < 28 is the logit of tap c - 3
+  float bias[8];
+  int tap_off[8];
+  bool is_tap[8];
+  for (int j = 0; j < 8; ++j) {
+    const int c = (j < 4 ? 0 : 16) + 4 * grp + (j & 3);
+    is_tap[j] = c >= 3 && c < 28;
+    bias[j] = c < 3 ? params[off_hd + 96 + c] : (c < 28 ? params[off_hk + 800 + c - 3] : 0.f);
+    const int q = is_tap[j] ? c - 3 : 0;
+    tap_off[j] = (q / 5) * HW + q % 5;
+  }
+  for (int k = 0; k < KH; ++k) {
+    const int hb = wave + 4 * k;
+    if (hb < HB) {
+      const f32x4_t d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+          w0, heads_frag<E>(rh[k], in_scale), f32x4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+      if (grp == 0) s_od[hb * 16 + col] = make_float4(d[0] + bias[0], d[1] + bias[1],
+                                                      d[2] + bias[2], 0.f);
     }
   }
   __syncthreads();
-  const int tx = tid & 15, ty = tid >> 4;
-  const int y = y0 + ty, x = x0 + tx;
-  if (y >= h || x >= w) return;
-  float f[32];
-  E::load32(hdec + (((int64_t)b * h + y) * w + x) * 32 * E::kBytes, f);
-  for (int k = 0; k < 32; ++k) f[k] *= in_scale;
-  float lg[25];
-  float mx = -INFINITY;
-  for (int q = 0; q < 25; ++q) {
-    float s = whk[800 + q];
-    for (int k = 0; k < 32; ++k) s = fmaf(whk[q * 32 + k], f[k], s);
-    lg[q] = s;
-    mx = fmaxf(mx, s);
-  }
-  float den = 0.f;
-  for (int q = 0; q < 25; ++q) {
-    lg[q] = expf(lg[q] - mx);
-    den += lg[q];
-  }
-  const float inv = 1.0f / den;
-  float o0 = 0.f, o1 = 0.f, o2 = 0.f;
-  for (int dy = 0; dy < 5; ++dy)
-    for (int dx = 0; dx < 5; ++dx) {
-      const float wq = lg[dy * 5 + dx] * inv;
-      const float* od = s_od + ((ty + dy) * 20 + tx + dx) * 3;
-      o0 = fmaf(wq, od[0], o0);
-      o1 = fmaf(wq, od[1], o1);
-      o2 = fmaf(wq, od[2], o2);
+  for (int m = 0; m < 4; ++m) {
+    const int ty = wave * 4 + m, y = y0 + ty, x = x0 + col;
+    const bf16x8_t f = heads_frag<E>(rc[m], in_scale);
+    const f32x4_t d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, f, f32x4_t{0.f, 0.f, 0.f, 0.f},
+                                                               0, 0, 0);
+    const f32x4_t d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, f, f32x4_t{0.f, 0.f, 0.f, 0.f},
+                                                               0, 0, 0);
+    float lg[8];
+    float mx = -INFINITY;
+    for (int j = 0; j < 8; ++j) {
+      lg[j] = (j < 4 ? d0[j] : d1[j - 4]) + bias[j];
+      if (is_tap[j]) mx = fmaxf(mx, lg[j]);
     }
-  const int64_t p = ((int64_t)b * h + y) * w + x;
-  out_rgb[p * 3 + 0] = o0;
-  out_rgb[p * 3 + 1] = o1;
-  out_rgb[p * 3 + 2] = o2;
-  if (out_od) {
-    const float* od = s_od + ((ty + 2) * 20 + tx + 2) * 3;
-    out_od[p * 3 + 0] = od[0];
-    out_od[p * 3 + 1] = od[1];
-    out_od[p * 3 + 2] = od[2];
+    mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
+    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    float den = 0.f;
+    for (int j = 0; j < 8; ++j) {
+      lg[j] = is_tap[j] ? expf(lg[j] - mx) : 0.f;
+      den += lg[j];
+    }
+    den += __shfl_xor(den, 16, 64);
+    den += __shfl_xor(den, 32, 64);
+    const float inv = 1.0f / den;
+    const float4* win = s_od + ty * HW + col;  // top-left of this pixel's 5 x 5 window
+    float o0 = 0.f, o1 = 0.f, o2 = 0.f;
+    for (int j = 0; j < 8; ++j) {
+      if (!is_tap[j]) continue;
+      lg[j] *= inv;
+      const float4 od = win[tap_off[j]];
+      o0 = fmaf(lg[j], od.x, o0);
+      o1 = fmaf(lg[j], od.y, o1);
+      o2 = fmaf(lg[j], od.z, o2);
+    }
+    o0 += __shfl_xor(o0, 16, 64);
+    o1 += __shfl_xor(o1, 16, 64);
+    o2 += __shfl_xor(o2, 16, 64);
+    o0 += __shfl_xor(o0, 32, 64);
+    o1 += __shfl_xor(o1, 32, 64);
+    o2 += __shfl_xor(o2, 32, 64);
+    if (y >= h || x >= w) continue;
+    const int64_t p = ((int64_t)b * h + y) * w + x;
+    if (grp == 0) {
+      out_rgb[p * 3 + 0] = o0;
+      out_rgb[p * 3 + 1] = o1;
+      out_rgb[p * 3 + 2] = o2;
+      if (out_od) {
+        out_od[p * 3 + 0] = d0[0] + bias[0];
+        out_od[p * 3 + 1] = d0[1] + bias[1];
+        out_od[p * 3 + 2] = d0[2] + bias[2];
+      }
+    }
+    if (out_wk)
+      for (int j = 0; j < 8; ++j) {
+        const int c = (j < 4 ? 0 : 16) + 4 * grp + (j & 3);
+        if (is_tap[j]) out_wk[p * 25 + c - 3] = lg[j];
+      }
   }
-  if (out_wk)
-    for (int q = 0; q < 25; ++q) out_wk[p * 25 + q] = lg[q] * inv;
+}
+
+// Head weights [hd (3 rows); hk (25 rows); 4 zero rows] x 32 inputs as the
+// two BF16 MFMA B fragments (n block 0: rows 0-15, n block 1: rows 16-31).
+__global__ void k_swizzle_heads(const float* __restrict__ hd, const float* __restrict__ hk,
+                                __bf16* __restrict__ out) {
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= 2 * 512) return;
+  const int j = e & 7, l = (e >> 3) & 63, nb = e >> 9;
+  const int nrow = nb * 16 + (l & 15), k = 8 * (l >> 4) + j;
+  float v = 0.f;
+  if (nrow < 3)
+    v = hd[nrow * 32 + k];
+  else if (nrow < 28)
+    v = hk[(nrow - 3) * 32 + k];
+  out[e] = (__bf16)v;
 }
 
 // Master FP32 weights of a 3x3 layer -> swizzled BF16 MFMA B fragments.
@@ -267,7 +355,25 @@ void conv_nb(const ConvArgs& a, int R, hipStream_t s) {
 }
 
 template <class E>
-fv_status launch_conv(const ConvArgs& a, int nb, hipStream_t s) {
+fv_status launch_conv(const ConvArgs& args, int nb, hipStream_t s) {
+  ConvArgs a = args;
+  // source sizes for the kernel's buffer-load range checks (loads outside the
+  // image use an offset of 2 GiB, so every source must stay below that)
+  const int64_t px = (int64_t)a.n * a.h * a.w;
+  const int64_t b0 = (a.up0 ? (int64_t)a.n * (a.h >> 1) * (a.w >> 1) : px) * a.c0 * E::kBytes;
+  const int64_t b1 = a.src1 ? px * a.c1 * E::kBytes : 0;
+  if (b0 >= ((int64_t)1 << 31) - 64 || b1 >= ((int64_t)1 << 31) - 64)
+    return fail(FV_ERR_UNSUPPORTED, "conv: an input tensor of %lld bytes (limit 2 GiB)",
+                (long long)(b0 > b1 ? b0 : b1));
+  a.src0_bytes = (uint32_t)b0;
+  a.src1_bytes = (uint32_t)b1;
+  auto magic = [](uint32_t d) { return d > 1 ? (uint32_t)(((uint64_t)1 << 32) / d + 1) : 0u; };
+  if (a.up0 && (a.c0 % 8 || a.c0 < 16 || (a.h | a.w) & 1))
+    return fail(FV_ERR_UNSUPPORTED, "conv: upsampled source with %d channels at %d x %d", a.c0,
+                a.w, a.h);
+  const uint32_t g0 = a.up0 ? (uint32_t)(a.c0 >> 3) : 0u;
+  a.gmagic = magic((uint32_t)(a.cip >> 3) - g0);
+  a.umagic = magic(g0);
   // rows per wave: the largest R whose LDS fits in 80 KB (two blocks per CU)
   // and that still gives at least two blocks per CU (256 CUs)
   int R = 4;
@@ -278,7 +384,11 @@ fv_status launch_conv(const ConvArgs& a, int nb, hipStream_t s) {
     if (lds <= 80 * 1024 && blocks >= 512) break;
     R >>= 1;
   }
+  if (nb >= 10 && R == 4) R = 2;  // 160 accumulators per lane would spill
   if (a.co % 8) return fail(FV_ERR_UNSUPPORTED, "conv: %d output channels", a.co);
+  // the fused 2x2 pooling needs both rows of a pair in one wave
+  uint8_t* pool_out = a.pool_out;
+  if (pool_out && (R == 1 || a.out_fp32 || a.out_ch != a.co || (a.h | a.w) & 1)) a.pool_out = nullptr;
   switch (nb) {
     case 1: conv_nb<E, 1>(a, R, s); break;
     case 2: conv_nb<E, 2>(a, R, s); break;
@@ -289,6 +399,11 @@ fv_status launch_conv(const ConvArgs& a, int nb, hipStream_t s) {
     case 7: conv_nb<E, 7>(a, R, s); break;
     case 10: conv_nb<E, 10>(a, R, s); break;
     default: return fail(FV_ERR_UNSUPPORTED, "conv: %d output blocks", nb);
+  }
+  if (pool_out && !a.pool_out) {
+    const int64_t total = (int64_t)a.n * (a.h / 2) * (a.w / 2) * (a.co / 8);
+    k_avgpool2<E><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(a.out, pool_out, a.n, a.h,
+                                                                  a.w, a.co);
   }
   return launch_status("conv3x3");
 }
@@ -310,6 +425,8 @@ size_t swizzled_elems(int in_ch, int out_ch) {
 }
 
 fv_status refresh_bf16(fv_net* n, hipStream_t s) {
+  k_swizzle_heads<<<4, 256, 0, s>>>(n->master + param_offset(14), n->master + param_offset(15),
+                                    (__bf16*)n->w_heads);
   for (int l = 0; l < kNumConv; ++l) {
     fv_status st = swizzle_bf16(n->master + param_offset(l), kLayers[l].ci, kLayers[l].co, 0,
                                 n->w_bf16[l], s);
@@ -334,14 +451,6 @@ fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const floa
       (const float4*)frame, mask, depth, ws + p.t[T_IN], npx, in_inv, absmax ? absmax + T_IN : nullptr);
   fv_status st = launch_status("pack");
   if (st != FV_OK) return st;
-  auto pool = [&](int src, int dst) {
-    const int lv = kTensors[src].level, c = kTensors[src].channels;
-    const int hh = p.h >> lv, ww = p.w >> lv;
-    const int64_t total = (int64_t)p.n * (hh / 2) * (ww / 2) * (c / 8);
-    k_avgpool2<E><<<(unsigned)((total + 255) / 256), 256, 0, s>>>(ws + p.t[src], ws + p.t[dst],
-                                                                  p.n, hh, ww, c);
-    return launch_status("avgpool");
-  };
   for (int l = 0; l < kNumConv; ++l) {
     const LayerDesc& L = kLayers[l];
     const int* io = kLayerIO[l];
@@ -371,15 +480,15 @@ fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const floa
       a.alpha = nullptr;
       a.bias = net->master + param_offset(l) + (int64_t)L.co * L.ci * 9;
     }
+    // the encoder's second conv of levels 0-2 also writes the pooled input
+    // of the next level
+    a.pool_out = l == 1 ? ws + p.t[T_P0] : l == 3 ? ws + p.t[T_P1] : l == 5 ? ws + p.t[T_P2] : nullptr;
     st = launch_conv<E>(a, nblocks_of(L.co), s);
-    if (st != FV_OK) return st;
-    if (l == 1) st = pool(T_E0B, T_P0);
-    if (l == 3) st = pool(T_E1B, T_P1);
-    if (l == 5) st = pool(T_E2B, T_P2);
     if (st != FV_OK) return st;
   }
   dim3 grid((p.w + 15) / 16, (p.h + 15) / 16, p.n);
-  k_heads<E><<<grid, 256, 0, s>>>(ws + p.t[T_D0B], p.n, p.h, p.w, net->master, param_offset(14),
+  k_heads<E><<<grid, 256, 0, s>>>(ws + p.t[T_D0B], p.n, p.h, p.w, net->master,
+                                  (const __bf16*)net->w_heads, param_offset(14),
                                   param_offset(15), fp8 ? net->act_scale[T_D0B] : 1.0f, out_rgb,
                                   out_od, out_wk);
   return launch_status("heads");
@@ -490,6 +599,7 @@ fv_status fv_net_create(const float* host_params, size_t n_params, fv_net** out)
   }
   const size_t pb = n_params * sizeof(float);
   bool ok = hipMalloc(&n->master, pb) == hipSuccess && hipMalloc(&n->adam_m, pb) == hipSuccess &&
+            hipMalloc(&n->w_heads, 2 * 512 * 2) == hipSuccess &&
             hipMalloc(&n->adam_v, pb) == hipSuccess && hipMalloc(&n->grad, pb) == hipSuccess;
   for (int l = 0; ok && l < kNumConv; ++l) {
     const size_t e = swizzled_elems(kLayers[l].c0 + kLayers[l].c1, kLayers[l].co);
@@ -524,6 +634,7 @@ fv_status fv_net_destroy(fv_net* n) {
   (void)hipFree(n->adam_m);
   (void)hipFree(n->adam_v);
   (void)hipFree(n->grad);
+  (void)hipFree(n->w_heads);
   for (int l = 0; l < kNumConv; ++l) {
     (void)hipFree(n->w_bf16[l]);
     (void)hipFree(n->w_bf16t[l]);

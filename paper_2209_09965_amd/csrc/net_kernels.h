@@ -57,6 +57,12 @@ struct BF16 {
   static __device__ __forceinline__ void store1(uint8_t* p, float v) {
     *(uint16_t*)p = (uint16_t)enc_bits(v);
   }
+  static __device__ __forceinline__ void store4(uint8_t* p, const float v[4]) {
+    *(uint2*)p = make_uint2(enc_bits(v[0]) | (enc_bits(v[1]) << 16),
+                            enc_bits(v[2]) | (enc_bits(v[3]) << 16));
+  }
+  // the value as stored and read back
+  static __device__ __forceinline__ float rnd(float v) { return bf16_bits_to_f(enc_bits(v)); }
 };
 
 struct FP8 {
@@ -99,6 +105,15 @@ struct FP8 {
     for (int g = 0; g < 4; ++g) load8(p + g * 8, v + 8 * g);
   }
   static __device__ __forceinline__ void store1(uint8_t* p, float v) { *p = enc(v); }
+  static __device__ __forceinline__ void store4(uint8_t* p, const float v[4]) {
+    int w = 0;
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(sat(v[0]), sat(v[1]), w, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(sat(v[2]), sat(v[3]), w, true);
+    *(uint32_t*)p = (uint32_t)w;
+  }
+  static __device__ __forceinline__ float rnd(float v) {
+    return __builtin_amdgcn_cvt_f32_fp8(__builtin_amdgcn_cvt_pk_fp8_f32(sat(v), 0.0f, 0, false), 0);
+  }
 };
 
 __device__ __forceinline__ void wave_absmax(float* dst, float m) {
@@ -106,8 +121,8 @@ __device__ __forceinline__ void wave_absmax(float* dst, float m) {
   if ((threadIdx.x & 63) == 0 && m > 0.f) atomicMax((unsigned int*)dst, __float_as_uint(m));
 }
 
-// One 3x3 convolution as an implicit GEMM: M = output pixels, N = output
-// channels, K = 9 taps x input channels.
+// One 3x3 convolution as an implicit GEMM: M = output channels, N = output
+// pixels, K = 9 taps x input channels.
 struct ConvArgs {
   const uint8_t* src0;  // NHWC, c0 channels; half resolution if up0
   const uint8_t* src1;  // NHWC, c1 channels (concatenated after src0), or null
@@ -122,7 +137,39 @@ struct ConvArgs {
   uint8_t* out;         // NHWC, out_ch channel stride
   int out_ch, out_fp32;
   float* absmax;        // per-tensor running maximum (calibration), or null
+  uint8_t* pool_out;    // 2x2 average of the stored output (half resolution,
+                        // out_ch stride), or null
+  uint32_t src0_bytes, src1_bytes;  // sizes for the buffer-load range checks
+  // set by launch_conv: e / ng == umulhi(e, gmagic) for ng = cip / 8 groups
+  // copied from memory (0: ng == 1); umagic likewise for the c0 / 8
+  // upsampled groups
+  uint32_t gmagic, umagic;
 };
+
+template <class E>
+struct Chunk8;  // 8 elements: 16 bytes (BF16) or 8 bytes (FP8)
+template <>
+struct Chunk8<BF16> {
+  typedef uint4 T;
+  static __device__ __forceinline__ T load(__amdgpu_buffer_rsrc_t r, int off) {
+    typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i4;
+    const i4 v = __builtin_bit_cast(i4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    return make_uint4((uint32_t)v[0], (uint32_t)v[1], (uint32_t)v[2], (uint32_t)v[3]);
+  }
+};
+template <>
+struct Chunk8<FP8> {
+  typedef uint2 T;
+  static __device__ __forceinline__ T load(__amdgpu_buffer_rsrc_t r, int off) {
+    typedef __attribute__((__vector_size__(2 * sizeof(int)))) int i2;
+    const i2 v = __builtin_bit_cast(i2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+    return make_uint2((uint32_t)v[0], (uint32_t)v[1]);
+  }
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)p, (short)0, (int)bytes, 0x00020000);
+}
 
 // Low-resolution staging for an upsampled source 0: the tile's output rows
 // [y0-1, y0+4R] and columns [x0-1, x0+16] read low-resolution rows
@@ -133,67 +180,23 @@ struct LowPatch {
   static constexpr int kRows = 2 * R + 2, kCols = 10;
 };
 
-// 8 channels [ch, ch+8) of one patch pixel (output coordinates y, x):
-// zero outside the image; else source 0 (bilinear x2 from the staged
-// low-resolution patch when up0), then source 1, then zero up to cip.
-template <class E, int R>
-__device__ __forceinline__ void fill_group(const ConvArgs& a, const uint8_t* low, int b, int y0,
-                                           int x0, int y, int x, int ch, uint8_t* dst) {
-  if (y < 0 || y >= a.h || x < 0 || x >= a.w) {
-    E::zero8(dst);
-    return;
-  }
-  if (ch < a.c0) {
-    if (!a.up0) {
-      E::copy8(dst, a.src0 + ((((int64_t)b * a.h + y) * a.w + x) * a.c0 + ch) * E::kBytes);
-      return;
-    }
-    const int hh = a.h >> 1, ww = a.w >> 1;
-    const float sy = fminf(fmaxf((y + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(hh - 1));
-    const float sx = fminf(fmaxf((x + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(ww - 1));
-    const int ly0 = (int)sy, lx0 = (int)sx;
-    const int ly1 = min(ly0 + 1, hh - 1), lx1 = min(lx0 + 1, ww - 1);
-    const float fy = sy - (float)ly0, fx = sx - (float)lx0;
-    const int oy = (y0 >> 1) - 1, ox = (x0 >> 1) - 1;
-    const int rs = LowPatch<R>::kCols * a.c0;
-    const uint8_t* p = low + ch * E::kBytes;
-    float v00[8], v01[8], v10[8], v11[8], r[8];
-    E::load8(p + ((ly0 - oy) * rs + (lx0 - ox) * a.c0) * E::kBytes, v00);
-    E::load8(p + ((ly0 - oy) * rs + (lx1 - ox) * a.c0) * E::kBytes, v01);
-    E::load8(p + ((ly1 - oy) * rs + (lx0 - ox) * a.c0) * E::kBytes, v10);
-    E::load8(p + ((ly1 - oy) * rs + (lx1 - ox) * a.c0) * E::kBytes, v11);
-    for (int i = 0; i < 8; ++i) {
-      const float top = fmaf(fx, v01[i] - v00[i], v00[i]);
-      const float bot = fmaf(fx, v11[i] - v10[i], v10[i]);
-      r[i] = fmaf(fy, bot - top, top);
-    }
-    E::store8(dst, r);
-    return;
-  }
-  if (ch < a.c0 + a.c1) {
-    E::copy8(dst, a.src1 + ((((int64_t)b * a.h + y) * a.w + x) * a.c1 + (ch - a.c0)) * E::kBytes);
-    return;
-  }
-  E::zero8(dst);
-}
-
 // Bytes of dynamic LDS k_conv3x3<E, NB, R> needs.
 template <class E, int R>
 __host__ __device__ inline size_t conv_lds_bytes(int cip, int c0, int up0, int co) {
   size_t patch = (size_t)(4 * R + 2) * 18 * (cip + E::kPad) * E::kBytes;
   size_t low = up0 ? (size_t)LowPatch<R>::kRows * LowPatch<R>::kCols * c0 * E::kBytes : 0;
-  size_t outt = (size_t)4 * R * 16 * (co + E::kPad) * E::kBytes;
-  size_t a = patch + low;
-  return a > outt ? a : outt;
+  (void)co;
+  return patch + low;
 }
 
 // Block = 4 waves; output tile = (4 R) rows x 16 columns of one image; wave w
-// owns rows [w R, w R + R), each row one 16-pixel M block.  The input patch
+// owns rows [w R, w R + R), each row one 16-pixel N block.  The input patch
 // (tile + 1-pixel halo, all cip channels) is staged in LDS once; per 32-wide
-// K chunk each lane reads its A fragment (8 channels of one pixel at one tap)
-// from LDS; B fragments (pre-swizzled weights) come from global memory one
-// chunk ahead of their use.  The epilogue transposes the tile through LDS
-// and writes whole 16-byte channel groups.
+// K chunk each lane reads its pixel fragment (8 channels of one pixel at one
+// tap) from LDS; weight fragments (pre-swizzled) come from global memory one
+// chunk ahead of their use.  With the weights as the A operand each lane's
+// accumulator holds 4 consecutive channels of one pixel, so the epilogue
+// writes them straight to global memory as one packed store.
 template <class E, int NB, int R>
 __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
@@ -202,73 +205,115 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a) {
   const int x0 = blockIdx.x * 16, y0 = blockIdx.y * (4 * R), b = blockIdx.z;
   const int tid = threadIdx.x;
   uint8_t* low = smem + (size_t)PR * PC * S * E::kBytes;
+  using C8 = Chunk8<E>;
+  const int groups = a.cip >> 3, g0 = a.up0 ? a.c0 >> 3 : 0;
   if (a.up0) {
-    const int hh = a.h >> 1, ww = a.w >> 1, g0 = a.c0 >> 3;
-    const int tot = LowPatch<R>::kRows * LowPatch<R>::kCols * g0;
+    // the low-resolution source patch, rows/columns clamped to the image
+    // (which is what the clamped bilinear taps read at the borders)
+    constexpr int LR = LowPatch<R>::kRows, LC = LowPatch<R>::kCols;
+    const int hh = a.h >> 1, ww = a.w >> 1;
+    const int tot = LR * LC * g0;
     constexpr int kB = 4;
-    using V = typename std::conditional<E::kBytes == 2, uint4, uint2>::type;
+    const __amdgpu_buffer_rsrc_t rl = make_rsrc(a.src0, a.src0_bytes);
     for (int base = tid; base < tot; base += 256 * kB) {
-      V v[kB];
+      typename C8::T v[kB];
+      #pragma unroll
       for (int u = 0; u < kB; ++u) {
         const int e = base + u * 256;
         if (e >= tot) continue;
-        const int g = e % g0, pix = e / g0;
-        const int r = pix / LowPatch<R>::kCols, c = pix - r * LowPatch<R>::kCols;
+        const int pix = (int)__umulhi((uint32_t)e, a.umagic), g = e - pix * g0;
+        const int r = pix / LC, c = pix - r * LC;
         const int ly = min(max((y0 >> 1) - 1 + r, 0), hh - 1);
         const int lx = min(max((x0 >> 1) - 1 + c, 0), ww - 1);
-        v[u] = *(const V*)(a.src0 + ((((int64_t)b * hh + ly) * ww + lx) * a.c0 + g * 8) * E::kBytes);
+        const uint32_t p = ((uint32_t)b * (uint32_t)hh + (uint32_t)ly) * (uint32_t)ww + (uint32_t)lx;
+        v[u] = C8::load(rl, (int)((p * (uint32_t)a.c0 + g * 8) * E::kBytes));
       }
+      #pragma unroll
       for (int u = 0; u < kB; ++u) {
         const int e = base + u * 256;
-        if (e < tot) *(V*)(low + (size_t)e * 8 * E::kBytes) = v[u];
+        if (e < tot) *(typename C8::T*)(low + (size_t)e * 8 * E::kBytes) = v[u];
       }
     }
-    __syncthreads();
   }
-  const int groups = a.cip >> 3;
-  const int total = PR * PC * groups;
-  if (!a.up0) {
-    // plain copy: issue a batch of global loads before the LDS stores so
-    // several loads per thread are in flight
+  {
+    // channels copied from memory: all of them, or those of source 1 after an
+    // upsampled source 0.  A batch of buffer loads is in flight before the
+    // LDS stores; pixels outside the image and padding channels get an
+    // out-of-range offset, which the hardware reads as zero.
     constexpr int kB = 6;
-    using V = typename std::conditional<E::kBytes == 2, uint4, uint2>::type;
+    constexpr int kOutside = (int)0x80000000u;  // beyond every source (< 2 GiB)
+    const int ng = groups - g0;
+    const int total = PR * PC * ng;
+    const __amdgpu_buffer_rsrc_t r0 = make_rsrc(a.src0, a.src0_bytes);
+    const __amdgpu_buffer_rsrc_t r1 = make_rsrc(a.src1 ? a.src1 : a.src0, a.src1 ? a.src1_bytes : 0u);
     for (int base = tid; base < total; base += 256 * kB) {
-      V v[kB];
+      typename C8::T v[kB];
       int dst[kB];
+      #pragma unroll
       for (int u = 0; u < kB; ++u) {
         const int e = base + u * 256;
         dst[u] = -1;
-        V z;
-        memset(&z, 0, sizeof z);
-        v[u] = z;
         if (e >= total) continue;
-        const int g = e % groups, pix = e / groups;
+        const int pix = a.gmagic ? (int)__umulhi((uint32_t)e, a.gmagic) : e;
+        const int g = g0 + e - pix * ng;
         const int r = pix / PC, c = pix - r * PC;
         const int y = y0 - 1 + r, x = x0 - 1 + c, ch = g * 8;
         dst[u] = pix * S + ch;
-        if (y < 0 || y >= a.h || x < 0 || x >= a.w) continue;
-        const uint8_t* src = ch < a.c0
-            ? a.src0 + ((((int64_t)b * a.h + y) * a.w + x) * a.c0 + ch) * E::kBytes
-            : (ch < a.c0 + a.c1
-                   ? a.src1 + ((((int64_t)b * a.h + y) * a.w + x) * a.c1 + (ch - a.c0)) * E::kBytes
-                   : nullptr);
-        if (src) v[u] = *(const V*)src;
+        const bool in = y >= 0 && y < a.h && x >= 0 && x < a.w;
+        const uint32_t p = ((uint32_t)b * (uint32_t)a.h + (uint32_t)y) * (uint32_t)a.w + (uint32_t)x;
+        if (ch < a.c0) {
+          v[u] = C8::load(r0, in ? (int)((p * (uint32_t)a.c0 + ch) * E::kBytes) : kOutside);
+        } else {
+          v[u] = C8::load(r1, in && ch < a.c0 + a.c1
+                                  ? (int)((p * (uint32_t)a.c1 + (ch - a.c0)) * E::kBytes)
+                                  : kOutside);
+        }
       }
+      #pragma unroll
       for (int u = 0; u < kB; ++u)
-        if (dst[u] >= 0) *(V*)(smem + (size_t)dst[u] * E::kBytes) = v[u];
+        if (dst[u] >= 0) *(typename C8::T*)(smem + (size_t)dst[u] * E::kBytes) = v[u];
     }
-  } else {
-    for (int e = tid; e < total; e += 256) {
-      const int g = e % groups, pix = e / groups;
+  }
+  if (a.up0) {
+    // bilinear x2 (half-pixel centres) from the staged patch.  Patch row r is
+    // output row y0 - 1 + r; its two source rows are staged rows r/2 and
+    // r/2 + 1 with weight 0.25 (r even) or 0.75 (r odd) on the second: the
+    // same taps and weights as the clamped formula, borders included.
+    __syncthreads();
+    constexpr int LC = LowPatch<R>::kCols;
+    const int tot = PR * PC * g0;
+    const int rs = LC * a.c0;
+    for (int e = tid; e < tot; e += 256) {
+      const int pix = (int)__umulhi((uint32_t)e, a.umagic), g = e - pix * g0;
       const int r = pix / PC, c = pix - r * PC;
-      fill_group<E, R>(a, low, b, y0, x0, y0 - 1 + r, x0 - 1 + c, g * 8,
-                       smem + ((size_t)pix * S + g * 8) * E::kBytes);
+      const int y = y0 - 1 + r, x = x0 - 1 + c;
+      uint8_t* dst = smem + ((size_t)pix * S + g * 8) * E::kBytes;
+      if (y < 0 || y >= a.h || x < 0 || x >= a.w) {
+        E::zero8(dst);
+        continue;
+      }
+      const float fy = (r & 1) ? 0.75f : 0.25f, fx = (c & 1) ? 0.75f : 0.25f;
+      const uint8_t* p = low + ((r >> 1) * rs + (c >> 1) * a.c0 + g * 8) * E::kBytes;
+      float v00[8], v01[8], v10[8], v11[8], o[8];
+      E::load8(p, v00);
+      E::load8(p + a.c0 * E::kBytes, v01);
+      E::load8(p + rs * E::kBytes, v10);
+      E::load8(p + (rs + a.c0) * E::kBytes, v11);
+      #pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float top = fmaf(fx, v01[i] - v00[i], v00[i]);
+        const float bot = fmaf(fx, v11[i] - v10[i], v10[i]);
+        o[i] = fmaf(fy, bot - top, top);
+      }
+      E::store8(dst, o);
     }
   }
   __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
   f32x4_t acc[R][NB];
+  #pragma unroll
   for (int rr = 0; rr < R; ++rr)
+    #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[rr][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
   const int col = lane & 15;
   const uint8_t* wl = a.wsw + (size_t)lane * 8 * E::kBytes;
@@ -282,16 +327,19 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a) {
   auto load_a = [&](int tp, int cc, typename E::Frag* af) {
     if (tp < 9) {
       const int ky = tp / 3, kx = tp - ky * 3;
+      #pragma unroll
       for (int rr = 0; rr < R; ++rr) {
         const int pix = (wave * R + rr + ky) * PC + col + kx;
         af[rr] = E::frag(smem + ((size_t)pix * S + cc) * E::kBytes);
       }
     } else {
+      #pragma unroll
       for (int rr = 0; rr < R; ++rr) af[rr] = E::zero();
     }
   };
   typename E::Frag acur[R], anext[R], bcur[NB], bnext[NB];
   load_a(tap, ci, acur);
+  #pragma unroll
   for (int nb = 0; nb < NB; ++nb) bcur[nb] = E::frag(wl + (size_t)nb * 512 * E::kBytes);
   for (int c = 0; c < a.kc; ++c) {
     const bool more = c + 1 < a.kc;
@@ -301,56 +349,79 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a) {
         ci -= a.cip;
         ++tap;
       }
+      #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
         bnext[nb] = E::frag(wl + ((size_t)(c + 1) * NB + nb) * 512 * E::kBytes);
       load_a(tap, ci, anext);
     }
+    // weights as the A operand (M = output channels), pixels as B (N): each
+    // lane ends with 4 consecutive channels of one pixel
+    #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
-      for (int rr = 0; rr < R; ++rr) acc[rr][nb] = E::mma(acur[rr], bcur[nb], acc[rr][nb]);
+      #pragma unroll
+      for (int rr = 0; rr < R; ++rr) acc[rr][nb] = E::mma(bcur[nb], acur[rr], acc[rr][nb]);
     if (more) {
+      #pragma unroll
       for (int nb = 0; nb < NB; ++nb) bcur[nb] = bnext[nb];
+      #pragma unroll
       for (int rr = 0; rr < R; ++rr) acur[rr] = anext[rr];
     }
   }
-  // epilogue: bias, ReLU, (calibration max), then store
+  // epilogue: bias, ReLU, (calibration max), one packed store per 4 channels;
+  // with pool_out also the 2x2 average of the stored values (rows rr, rr + 1
+  // of this lane, columns of this lane and its neighbour lane ^ 1), summed in
+  // the order (0,0), (0,1), (1,0), (1,1) like the stand-alone pooling kernel
   float mx = 0.f;
-  const int OS = a.co + E::kPad;  // LDS output pixel stride (elements)
-  if (!a.out_fp32) __syncthreads();  // the patch is dead; reuse LDS for the output tile
-  for (int rr = 0; rr < R; ++rr) {
-    const int ty = wave * R + rr;
-    const int y = y0 + ty;
-    for (int nb = 0; nb < NB; ++nb) {
-      const int n = nb * 16 + col;
-      if (n >= a.co) continue;
-      const float al = a.alpha ? a.alpha[n] : 1.0f;
-      const float bi = a.bias ? a.bias[n] : 0.0f;
+  const int x = x0 + col;
+  #pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    const int c4 = nb * 16 + 4 * (lane >> 4);
+    if (c4 >= a.co) continue;  // co is a multiple of 8, so c4 + 3 < co here
+    float al[4], bi[4];
+    #pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      al[i] = a.alpha ? a.alpha[c4 + i] : 1.0f;
+      bi[i] = a.bias ? a.bias[c4 + i] : 0.0f;
+    }
+    float st[R][4];
+    #pragma unroll
+    for (int rr = 0; rr < R; ++rr) {
+      const int y = y0 + wave * R + rr;
+      float v[4];
+      #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int tx = 4 * (lane >> 4) + i;
-        float v = fmaf(acc[rr][nb][i], al, bi);
-        if (a.relu) v = fmaxf(v, 0.0f);
-        if (y < a.h && x0 + tx < a.w) mx = fmaxf(mx, fabsf(v));
-        if (a.out_fp32) {
-          if (y < a.h && x0 + tx < a.w)
-            ((float*)a.out)[(((int64_t)b * a.h + y) * a.w + x0 + tx) * a.out_ch + n] = v;
-        } else {
-          E::store1(smem + ((size_t)(ty * 16 + tx) * OS + n) * E::kBytes, v);
+        v[i] = fmaf(acc[rr][nb][i], al[i], bi[i]);
+        if (a.relu) v[i] = fmaxf(v[i], 0.0f);
+        st[rr][i] = v[i];
+      }
+      if (y >= a.h || x >= a.w) continue;
+      #pragma unroll
+      for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(v[i]));
+      const int64_t o = (((int64_t)b * a.h + y) * a.w + x) * a.out_ch + c4;
+      if (a.out_fp32)
+        *(float4*)((float*)a.out + o) = make_float4(v[0], v[1], v[2], v[3]);
+      else
+        E::store4(a.out + o * E::kBytes, v);
+    }
+    if (R >= 2 && a.pool_out) {
+      #pragma unroll
+      for (int rr = 0; rr + 1 < R; rr += 2) {
+        const int y = y0 + wave * R + rr;
+        float pv[4];
+        #pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float t0 = E::rnd(st[rr][i]), t1 = E::rnd(st[rr + 1][i]);
+          const float n0 = __shfl_xor(t0, 1, 64), n1 = __shfl_xor(t1, 1, 64);
+          pv[i] = (((t0 + n0) + t1) + n1) * 0.25f;
         }
+        if ((col & 1) || y >= a.h || x >= a.w) continue;
+        const int64_t o =
+            (((int64_t)b * (a.h >> 1) + (y >> 1)) * (a.w >> 1) + (x >> 1)) * a.out_ch + c4;
+        E::store4(a.pool_out + o * E::kBytes, pv);
       }
     }
   }
   if (a.absmax) wave_absmax(a.absmax, mx);
-  if (a.out_fp32) return;
-  __syncthreads();
-  const int cg = a.co >> 3;  // 8-channel groups per pixel (co is a multiple of 8)
-  const int tot = 4 * R * 16 * cg;
-  for (int e = tid; e < tot; e += 256) {
-    const int g = e % cg, pix = e / cg;
-    const int ty = pix >> 4, tx = pix & 15;
-    const int y = y0 + ty, x = x0 + tx;
-    if (y >= a.h || x >= a.w) continue;
-    E::copy8(a.out + ((((int64_t)b * a.h + y) * a.w + x) * a.out_ch + g * 8) * E::kBytes,
-             smem + ((size_t)pix * OS + g * 8) * E::kBytes);
-  }
 }
 
 template <class E>

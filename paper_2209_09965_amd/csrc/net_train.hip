@@ -303,8 +303,9 @@ __global__ void __launch_bounds__(256) k_heads_bwd(const float* __restrict__ dou
   const float* whk = params + off_hk;
   for (int k = 0; k < 32; ++k) {
     float s = 0.f;
-    for (int c = 0; c < 3; ++c) s = fmaf(whd[c * 32 + k], d[c], s);
-    for (int qq = 0; qq < 25; ++qq) s = fmaf(whk[qq * 32 + k], d[3 + qq], s);
+    // the forward used the BF16-rounded head weights
+    for (int c = 0; c < 3; ++c) s = fmaf((float)(__bf16)whd[c * 32 + k], d[c], s);
+    for (int qq = 0; qq < 25; ++qq) s = fmaf((float)(__bf16)whk[qq * 32 + k], d[3 + qq], s);
     gh[p * 32 + k] = s;
   }
 }
