@@ -33,7 +33,10 @@ struct LayerDesc {
 extern const LayerDesc kLayers[kNumLayers];
 
 __host__ __device__ inline int cip_of(int ci) { return (ci + 7) / 8 * 8; }
+// K chunks of a 3x3 conv over ci input channels: 32 wide (BF16 MFMA) or
+// 128 wide (FP8 MFMA); K = 9 taps x cip, zero-padded to whole chunks.
 __host__ __device__ inline int kchunks_of(int ci) { return (9 * cip_of(ci) + 31) / 32; }
+__host__ __device__ inline int kchunks128_of(int ci) { return (9 * cip_of(ci) + 127) / 128; }
 __host__ __device__ inline int nblocks_of(int co) { return (co + 15) / 16; }
 
 // Offsets of each layer's weight / bias in the flat parameter vector.

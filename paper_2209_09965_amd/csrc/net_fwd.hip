@@ -334,14 +334,15 @@ __global__ void k_zero_f32(float* p, int n) {
 template <class E, int NB, int R>
 void conv_launch(const ConvArgs& a, hipStream_t s) {
   static bool attr_set = false;
-  const size_t lds = conv_lds_bytes<E, R>(a.cip, a.c0, a.up0, a.co);
+  const size_t lds = conv_lds_bytes<E, R>(a.cip, a.c0, a.up0, a.kc, NB, a.co, a.b_lds);
   if (!attr_set) {
     hipFuncSetAttribute((const void*)k_conv3x3<E, NB, R>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     attr_set = true;
   }
-  dim3 grid((a.w + 15) / 16, (a.h + 4 * R - 1) / (4 * R), a.n);
-  k_conv3x3<E, NB, R><<<grid, 256, lds, s>>>(a);
+  // one block per tile, tiles in (image, row, column) order
+  const int64_t tiles = (int64_t)((a.w + 15) / 16) * ((a.h + 4 * R - 1) / (4 * R)) * a.n;
+  k_conv3x3<E, NB, R><<<(unsigned)tiles, 256, lds, s>>>(a);
 }
 
 template <class E, int NB>
@@ -374,18 +375,23 @@ fv_status launch_conv(const ConvArgs& args, int nb, hipStream_t s) {
   const uint32_t g0 = a.up0 ? (uint32_t)(a.c0 >> 3) : 0u;
   a.gmagic = magic((uint32_t)(a.cip >> 3) - g0);
   a.umagic = magic(g0);
-  // rows per wave: the largest R whose LDS fits in 80 KB (two blocks per CU)
-  // and that still gives at least two blocks per CU (256 CUs)
+  // rows per wave: the largest R that still gives at least two blocks per CU
+  // (256 CUs) and whose patch fits in 48 KB of LDS; the weights are staged in
+  // LDS only while the block's LDS stays within 40 KB (four blocks per CU)
+  auto lds_of = [&](int r, int bl) {
+    return r == 4 ? conv_lds_bytes<E, 4>(a.cip, a.c0, a.up0, a.kc, nb, a.co, bl)
+                  : r == 2 ? conv_lds_bytes<E, 2>(a.cip, a.c0, a.up0, a.kc, nb, a.co, bl)
+                           : conv_lds_bytes<E, 1>(a.cip, a.c0, a.up0, a.kc, nb, a.co, bl);
+  };
   int R = 4;
   while (R > 1) {
     const int64_t blocks = (int64_t)((a.w + 15) / 16) * ((a.h + 4 * R - 1) / (4 * R)) * a.n;
-    const size_t lds = R == 4 ? conv_lds_bytes<E, 4>(a.cip, a.c0, a.up0, a.co)
-                              : conv_lds_bytes<E, 2>(a.cip, a.c0, a.up0, a.co);
-    if (lds <= 80 * 1024 && blocks >= 512) break;
+    if (lds_of(R, 0) <= 48 * 1024 && blocks >= 512) break;
     R >>= 1;
   }
-  if (nb >= 10 && R == 4) R = 2;  // 160 accumulators per lane would spill
-  if (a.co % 8) return fail(FV_ERR_UNSUPPORTED, "conv: %d output channels", a.co);
+  if (nb >= 7 && R == 4) R = 2;  // 112+ accumulators per lane would spill
+  a.b_lds = (size_t)a.kc * nb * 64 * E::kFragBytes <= kMaxLdsWeights && lds_of(R, 1) <= 40 * 1024;
+  if (a.co % 8 || a.co > 256) return fail(FV_ERR_UNSUPPORTED, "conv: %d output channels", a.co);
   // the fused 2x2 pooling needs both rows of a pair in one wave
   uint8_t* pool_out = a.pool_out;
   if (pool_out && (R == 1 || a.out_fp32 || a.out_ch != a.co || (a.h | a.w) & 1)) a.pool_out = nullptr;
@@ -464,7 +470,7 @@ fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const floa
     a.n = p.n;
     a.h = p.h >> L.level;
     a.w = p.w >> L.level;
-    a.kc = kchunks_of(L.c0 + L.c1);
+    a.kc = fp8 ? kchunks128_of(L.c0 + L.c1) : kchunks_of(L.c0 + L.c1);
     a.co = L.co;
     a.relu = 1;
     a.out = ws + p.t[io[2]];
@@ -530,13 +536,15 @@ fv_status build_fp8(fv_net* n, hipStream_t s) {
       alpha[co] = wscale[co] / s_out;
       bias[co] = B[co] / s_out;
     }
-    const int kc = kchunks_of(cin), nb = nblocks_of(L.co);
-    std::vector<float> sw((size_t)kc * nb * 512, 0.f);
+    // fragments [chunk][n block][64 lanes][32 bytes]: lane ln holds output
+    // channel 16 nb + ln % 16 at K positions 128 c + 32 (ln / 16) + j
+    const int kc = kchunks128_of(cin), nb = nblocks_of(L.co);
+    std::vector<float> sw((size_t)kc * nb * 2048, 0.f);
     for (size_t e = 0; e < sw.size(); ++e) {
-      const int j = (int)(e & 7), ln = (int)((e >> 3) & 63);
-      const int nbi = (int)((e >> 9) % nb);
-      const int c = (int)(e / (512 * (size_t)nb));
-      const int kk = c * 32 + 8 * (ln >> 4) + j;
+      const int j = (int)(e & 31), ln = (int)((e >> 5) & 63);
+      const int nbi = (int)((e >> 11) % nb);
+      const int c = (int)(e / (2048 * (size_t)nb));
+      const int kk = c * 128 + 32 * (ln >> 4) + j;
       const int tap = kk / cip, ci = kk - tap * cip;
       const int co = nbi * 16 + (ln & 15);
       if (tap < 9 && ci < L.ci && co < L.co)
@@ -604,7 +612,9 @@ fv_status fv_net_create(const float* host_params, size_t n_params, fv_net** out)
   for (int l = 0; ok && l < kNumConv; ++l) {
     const size_t e = swizzled_elems(kLayers[l].c0 + kLayers[l].c1, kLayers[l].co);
     const size_t et = swizzled_elems(kLayers[l].co, kLayers[l].c0 + kLayers[l].c1);
-    ok = hipMalloc(&n->w_bf16[l], e * 2) == hipSuccess && hipMalloc(&n->w_fp8[l], e) == hipSuccess &&
+    const size_t e8 = (size_t)kchunks128_of(kLayers[l].c0 + kLayers[l].c1) *
+                      nblocks_of(kLayers[l].co) * 2048;
+    ok = hipMalloc(&n->w_bf16[l], e * 2) == hipSuccess && hipMalloc(&n->w_fp8[l], e8) == hipSuccess &&
          hipMalloc(&n->w_bf16t[l], et * 2) == hipSuccess &&
          hipMalloc(&n->alpha_fp8[l], kLayers[l].co * sizeof(float)) == hipSuccess &&
          hipMalloc(&n->bias_fp8[l], kLayers[l].co * sizeof(float)) == hipSuccess;

@@ -17,9 +17,15 @@ __device__ __forceinline__ float bf16_bits_to_f(uint32_t b16) { return __uint_as
 
 struct BF16 {
   static constexpr int kBytes = 2;
-  static constexpr int kPad = 8;  // LDS pixel padding (elements): 16-byte skew
+  static constexpr int kK = 32;          // K per MFMA (16x16x32)
+  static constexpr int kFragBytes = 16;  // operand bytes per lane
+  static constexpr int kSub = 1;         // 8-channel pixel reads per lane and chunk
+  static constexpr bool kPrefetch = true;  // double-buffer the operands across chunks
   typedef bf16x8_t Frag;
   static __device__ __forceinline__ Frag frag(const uint8_t* p) { return *(const Frag*)p; }
+  static __device__ __forceinline__ Frag bfrag(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(Frag, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+  }
   static __device__ __forceinline__ Frag zero() {
     const uint4 z = make_uint4(0, 0, 0, 0);
     return __builtin_bit_cast(Frag, z);
@@ -65,14 +71,35 @@ struct BF16 {
   static __device__ __forceinline__ float rnd(float v) { return bf16_bits_to_f(enc_bits(v)); }
 };
 
+typedef int i32x8_t __attribute__((ext_vector_type(8)));
+
 struct FP8 {
   static constexpr int kBytes = 1;
-  static constexpr int kPad = 16;  // 16-byte skew
-  typedef long Frag;
-  static __device__ __forceinline__ Frag frag(const uint8_t* p) { return *(const long*)p; }
-  static __device__ __forceinline__ Frag zero() { return 0; }
+  static constexpr int kK = 128;         // K per MFMA (16x16x128, E4M3 operands)
+  static constexpr int kFragBytes = 32;
+  static constexpr int kSub = 4;
+  static constexpr bool kPrefetch = false;
+  // A lane's operand: 32 consecutive K positions (lane group g of a chunk
+  // holds K = 32 g .. 32 g + 31); any order consistent between the two
+  // operands gives the same dot product.
+  typedef i32x8_t Frag;
+  static __device__ __forceinline__ Frag frag(const uint8_t* p) { return *(const Frag*)p; }
+  static __device__ __forceinline__ Frag bfrag(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i4;
+    const i4 lo = __builtin_bit_cast(i4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+    const i4 hi =
+        __builtin_bit_cast(i4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff + 16, 0));
+    return Frag{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  }
+  // the 32 bytes of a pixel operand from four 8-byte reads
+  static __device__ __forceinline__ Frag frag4(const uint8_t* p, int4 o) {
+    const uint2 a = *(const uint2*)(p + o.x), b = *(const uint2*)(p + o.y);
+    const uint2 c = *(const uint2*)(p + o.z), d = *(const uint2*)(p + o.w);
+    return Frag{(int)a.x, (int)a.y, (int)b.x, (int)b.y, (int)c.x, (int)c.y, (int)d.x, (int)d.y};
+  }
   static __device__ __forceinline__ f32x4_t mma(Frag a, Frag b, f32x4_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+    // unit block scales (E8M0 127 = 2^0)
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
   }
   static __device__ __forceinline__ void copy8(uint8_t* dst, const uint8_t* src) {
     *(uint2*)dst = *(const uint2*)src;
@@ -129,7 +156,7 @@ struct ConvArgs {
   int c0, c1, cip;      // cip = c0 + c1 rounded up to 8
   int up0;
   int n, h, w;          // output size
-  const uint8_t* wsw;   // swizzled B fragments [kc][nb][64 lanes][8]
+  const uint8_t* wsw;   // swizzled weight fragments [kc][nb][64 lanes][kFragBytes]
   int kc;
   const float* alpha;   // per-output-channel multiplier, or null (= 1)
   const float* bias;    // per-output-channel bias, or null
@@ -144,6 +171,7 @@ struct ConvArgs {
   // copied from memory (0: ng == 1); umagic likewise for the c0 / 8
   // upsampled groups
   uint32_t gmagic, umagic;
+  int b_lds;  // set by launch_conv: the weight fragments are staged in LDS
 };
 
 template <class E>
@@ -180,107 +208,191 @@ struct LowPatch {
   static constexpr int kRows = 2 * R + 2, kCols = 10;
 };
 
-// Bytes of dynamic LDS k_conv3x3<E, NB, R> needs.
-template <class E, int R>
-__host__ __device__ inline size_t conv_lds_bytes(int cip, int c0, int up0, int co) {
-  size_t patch = (size_t)(4 * R + 2) * 18 * (cip + E::kPad) * E::kBytes;
-  size_t low = up0 ? (size_t)LowPatch<R>::kRows * LowPatch<R>::kCols * c0 * E::kBytes : 0;
-  (void)co;
-  return patch + low;
+// Patch pixel stride in elements (cip is a multiple of 8).  The 16 lanes of
+// a fragment read 16 consecutive pixels; a stride of 8 mod 16 elements (FP8:
+// 8 mod 16 bytes for 8-byte reads; BF16: 16 mod 32 bytes for 16-byte reads)
+// spreads them over all LDS banks.
+template <class E>
+__host__ __device__ inline int patch_stride(int cip) {
+  return cip + ((cip % 16) == 0 ? 8 : 0);
 }
 
-// Block = 4 waves; output tile = (4 R) rows x 16 columns of one image; wave w
-// owns rows [w R, w R + R), each row one 16-pixel N block.  The input patch
-// (tile + 1-pixel halo, all cip channels) is staged in LDS once; per 32-wide
-// K chunk each lane reads its pixel fragment (8 channels of one pixel at one
-// tap) from LDS; weight fragments (pre-swizzled) come from global memory one
-// chunk ahead of their use.  With the weights as the A operand each lane's
-// accumulator holds 4 consecutive channels of one pixel, so the epilogue
-// writes them straight to global memory as one packed store.
+// Weight fragments of a layer are staged in LDS when they take at most this
+// many bytes (the K loop then reads only LDS).
+constexpr size_t kMaxLdsWeights = 48 * 1024;
+
+// Bytes of dynamic LDS k_conv3x3<E, NB, R> needs: the input patch, the
+// low-resolution source patch (upsampled source 0), the table of K-chunk
+// patch offsets (4 kSub per chunk), the per-channel scale and bias and, when
+// b_lds, the weight fragments.  Every
+// region starts 16-byte aligned.
+template <class E, int R>
+__host__ __device__ inline size_t conv_lds_bytes(int cip, int c0, int up0, int kc, int nb,
+                                                 int co, int b_lds) {
+  size_t patch = (size_t)(4 * R + 2) * 18 * patch_stride<E>(cip) * E::kBytes;
+  size_t low = up0 ? (size_t)LowPatch<R>::kRows * LowPatch<R>::kCols * c0 * E::kBytes : 0;
+  size_t w = b_lds ? (size_t)kc * nb * 64 * E::kFragBytes : 0;
+  return patch + low + (size_t)16 * E::kSub * kc + (size_t)2 * 4 * ((co + 3) & ~3) + w;
+}
+
+// Block = 4 waves; tile = (4 R) rows x 16 columns of one image; wave w owns
+// rows [w R, w R + R), each row one 16-pixel N block.  Every global load a
+// block needs before its K loop (the input patch: tile + 1-pixel halo, all
+// cip channels; the weight fragments when they fit in LDS; the per-channel
+// scale and bias) is issued at once, so a block waits for one memory round
+// trip before its MFMAs.  Per 32- (BF16) or 128-wide (FP8) K chunk each lane
+// reads its pixel operand (8 channels at one tap, or four such groups) from
+// LDS.  With the weights as the A operand each lane's accumulator holds 4
+// consecutive channels of one pixel, so the epilogue writes them straight to
+// global memory as one packed store.
+// Occupancy target (waves per SIMD) for the register allocator, out of 512
+// registers: the accumulators (4 NB R) plus about 80 (FP8) or 96 (BF16,
+// double-buffered operands) for the rest; at 5 or more N blocks the weight
+// fragments alone need so many registers that two waves is the target.
 template <class E, int NB, int R>
-__global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a) {
+struct ConvWaves {
+  static constexpr int kRegs = 4 * NB * R + (E::kBytes == 2 ? 96 : 80);
+  static constexpr int v = NB >= 5 ? 2 : (512 / kRegs > 8 ? 8 : 512 / kRegs);
+};
+
+template <class E, int NB, int R>
+__global__ void __launch_bounds__(256)
+    __attribute__((amdgpu_waves_per_eu(ConvWaves<E, NB, R>::v))) k_conv3x3(ConvArgs a) {
   extern __shared__ __align__(16) uint8_t smem[];
   constexpr int PR = 4 * R + 2, PC = 18;
-  const int S = a.cip + E::kPad;  // patch pixel stride in elements
-  const int x0 = blockIdx.x * 16, y0 = blockIdx.y * (4 * R), b = blockIdx.z;
-  const int tid = threadIdx.x;
-  uint8_t* low = smem + (size_t)PR * PC * S * E::kBytes;
+  constexpr int LR = LowPatch<R>::kRows, LC = LowPatch<R>::kCols;
+  constexpr int kPF = 8;                      // fill items per thread in the first batch
+  constexpr int kPW = 6;                      // weight loads (16 B) per thread in flight
+  constexpr int kOutside = (int)0x80000000u;  // beyond every source (< 2 GiB)
   using C8 = Chunk8<E>;
-  const int groups = a.cip >> 3, g0 = a.up0 ? a.c0 >> 3 : 0;
-  if (a.up0) {
-    // the low-resolution source patch, rows/columns clamped to the image
-    // (which is what the clamped bilinear taps read at the borders)
-    constexpr int LR = LowPatch<R>::kRows, LC = LowPatch<R>::kCols;
-    const int hh = a.h >> 1, ww = a.w >> 1;
-    const int tot = LR * LC * g0;
-    constexpr int kB = 4;
-    const __amdgpu_buffer_rsrc_t rl = make_rsrc(a.src0, a.src0_bytes);
-    for (int base = tid; base < tot; base += 256 * kB) {
-      typename C8::T v[kB];
-      #pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        const int e = base + u * 256;
-        if (e >= tot) continue;
-        const int pix = (int)__umulhi((uint32_t)e, a.umagic), g = e - pix * g0;
-        const int r = pix / LC, c = pix - r * LC;
-        const int ly = min(max((y0 >> 1) - 1 + r, 0), hh - 1);
-        const int lx = min(max((x0 >> 1) - 1 + c, 0), ww - 1);
-        const uint32_t p = ((uint32_t)b * (uint32_t)hh + (uint32_t)ly) * (uint32_t)ww + (uint32_t)lx;
-        v[u] = C8::load(rl, (int)((p * (uint32_t)a.c0 + g * 8) * E::kBytes));
-      }
-      #pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        const int e = base + u * 256;
-        if (e < tot) *(typename C8::T*)(low + (size_t)e * 8 * E::kBytes) = v[u];
-      }
+  using Item = typename C8::T;
+  typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i4;
+  const int S = patch_stride<E>(a.cip);  // patch pixel stride in elements
+  const int tid = threadIdx.x;
+  const int tiles_x = (a.w + 15) / 16, tiles_y = (a.h + 4 * R - 1) / (4 * R);
+  const int x0 = (blockIdx.x % tiles_x) * 16;
+  const int y0 = ((blockIdx.x / tiles_x) % tiles_y) * 4 * R;
+  const int b = blockIdx.x / (tiles_x * tiles_y);
+  uint8_t* low = smem + (size_t)PR * PC * S * E::kBytes;
+  int* ktab = (int*)(low + (a.up0 ? (size_t)LR * LC * a.c0 * E::kBytes : 0));
+  float* s_ab = (float*)(ktab + 4 * E::kSub * a.kc);  // alpha[co], bias[co]
+  uint8_t* wsm = (uint8_t*)(s_ab + 2 * ((a.co + 3) & ~3));  // staged weights (b_lds)
+  // LDS fill items: the first nlow are the low-resolution patch of an
+  // upsampled source 0 (8 channels each, rows/columns clamped to the image,
+  // which is what the clamped bilinear taps read at the borders), the rest
+  // the channel groups copied from memory (all of them, or those of source 1
+  // after an upsampled source 0).  Pixels outside the image and padding
+  // channels load from an out-of-range offset, which the hardware reads as
+  // zero.
+  const int groups = a.cip >> 3, g0 = a.up0 ? a.c0 >> 3 : 0, ng = groups - g0;
+  const int nlow = a.up0 ? LR * LC * g0 : 0;
+  const int nitems = nlow + PR * PC * ng;
+  const int hh = a.h >> 1, ww = a.w >> 1;
+  const __amdgpu_buffer_rsrc_t r0 = make_rsrc(a.src0, a.src0_bytes);
+  const __amdgpu_buffer_rsrc_t r1 =
+      make_rsrc(a.src1 ? a.src1 : a.src0, a.src1 ? a.src1_bytes : 0u);
+  auto load_item = [&](int i) -> Item {
+    if (i < nlow) {
+      const int pix = (int)__umulhi((uint32_t)i, a.umagic), g = i - pix * g0;
+      const int r = pix / LC, c = pix - r * LC;
+      const int ly = min(max((y0 >> 1) - 1 + r, 0), hh - 1);
+      const int lx = min(max((x0 >> 1) - 1 + c, 0), ww - 1);
+      const uint32_t p = ((uint32_t)b * (uint32_t)hh + (uint32_t)ly) * (uint32_t)ww + (uint32_t)lx;
+      return C8::load(r0, (int)((p * (uint32_t)a.c0 + g * 8) * E::kBytes));
+    }
+    const int e = i - nlow;
+    const int pix = a.gmagic ? (int)__umulhi((uint32_t)e, a.gmagic) : e;
+    const int g = g0 + e - pix * ng;
+    const int r = pix / PC, c = pix - r * PC;
+    const int y = y0 - 1 + r, x = x0 - 1 + c, ch = g * 8;
+    const bool in = y >= 0 && y < a.h && x >= 0 && x < a.w;
+    const uint32_t p = ((uint32_t)b * (uint32_t)a.h + (uint32_t)y) * (uint32_t)a.w + (uint32_t)x;
+    if (ch < a.c0)  // (never with an upsampled source 0: then g >= g0)
+      return C8::load(r0, in ? (int)((p * (uint32_t)a.c0 + ch) * E::kBytes) : kOutside);
+    return C8::load(r1, in && ch < a.c0 + a.c1
+                            ? (int)((p * (uint32_t)a.c1 + (ch - a.c0)) * E::kBytes)
+                            : kOutside);
+  };
+  auto item_dst = [&](int i) -> uint8_t* {
+    if (i < nlow) return low + (size_t)i * 8 * E::kBytes;
+    const int e = i - nlow;
+    const int pix = a.gmagic ? (int)__umulhi((uint32_t)e, a.gmagic) : e;
+    const int g = g0 + e - pix * ng;
+    return smem + ((size_t)pix * S + g * 8) * E::kBytes;
+  };
+  // 1. every global load up front: patch items, weight fragments, scale/bias
+  Item pf[kPF];
+#pragma unroll
+  for (int u = 0; u < kPF; ++u)
+    if (tid + u * 256 < nitems) pf[u] = load_item(tid + u * 256);
+  const int n16 = a.b_lds ? a.kc * NB * 64 * E::kFragBytes / 16 : 0;
+  const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.wsw, (uint32_t)a.kc * NB * 64 * E::kFragBytes);
+  i4 wv[kPW];
+#pragma unroll
+  for (int u = 0; u < kPW; ++u)
+    if (tid + u * 256 < n16)
+      wv[u] = __builtin_bit_cast(i4, __builtin_amdgcn_raw_buffer_load_b128(rw, (tid + u * 256) * 16,
+                                                                           0, 0));
+  // scale (entries 0 .. co-1) and bias (co .. 2 co - 1), two per thread
+  // (co <= 256, checked by the launcher)
+  float ab[2] = {0.f, 0.f};
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + u * 256;
+    if (e < 2 * a.co) {
+      const float* src = e < a.co ? a.alpha : a.bias;
+      ab[u] = src ? src[e < a.co ? e : e - a.co] : (e < a.co ? 1.0f : 0.0f);
     }
   }
-  {
-    // channels copied from memory: all of them, or those of source 1 after an
-    // upsampled source 0.  A batch of buffer loads is in flight before the
-    // LDS stores; pixels outside the image and padding channels get an
-    // out-of-range offset, which the hardware reads as zero.
-    constexpr int kB = 6;
-    constexpr int kOutside = (int)0x80000000u;  // beyond every source (< 2 GiB)
-    const int ng = groups - g0;
-    const int total = PR * PC * ng;
-    const __amdgpu_buffer_rsrc_t r0 = make_rsrc(a.src0, a.src0_bytes);
-    const __amdgpu_buffer_rsrc_t r1 = make_rsrc(a.src1 ? a.src1 : a.src0, a.src1 ? a.src1_bytes : 0u);
-    for (int base = tid; base < total; base += 256 * kB) {
-      typename C8::T v[kB];
-      int dst[kB];
-      #pragma unroll
-      for (int u = 0; u < kB; ++u) {
-        const int e = base + u * 256;
-        dst[u] = -1;
-        if (e >= total) continue;
-        const int pix = a.gmagic ? (int)__umulhi((uint32_t)e, a.gmagic) : e;
-        const int g = g0 + e - pix * ng;
-        const int r = pix / PC, c = pix - r * PC;
-        const int y = y0 - 1 + r, x = x0 - 1 + c, ch = g * 8;
-        dst[u] = pix * S + ch;
-        const bool in = y >= 0 && y < a.h && x >= 0 && x < a.w;
-        const uint32_t p = ((uint32_t)b * (uint32_t)a.h + (uint32_t)y) * (uint32_t)a.w + (uint32_t)x;
-        if (ch < a.c0) {
-          v[u] = C8::load(r0, in ? (int)((p * (uint32_t)a.c0 + ch) * E::kBytes) : kOutside);
-        } else {
-          v[u] = C8::load(r1, in && ch < a.c0 + a.c1
-                                  ? (int)((p * (uint32_t)a.c1 + (ch - a.c0)) * E::kBytes)
-                                  : kOutside);
-        }
-      }
-      #pragma unroll
-      for (int u = 0; u < kB; ++u)
-        if (dst[u] >= 0) *(typename C8::T*)(smem + (size_t)dst[u] * E::kBytes) = v[u];
-    }
+  // 2. K-chunk table: entry e = (4 c + g) kSub + q = byte offset, from a
+  // pixel's top-left halo pixel, of the 8 K positions 8 e .. 8 e + 7 (lane
+  // group g's q-th read in chunk c; K is tap-major: tap = k / cip, channel =
+  // k % cip).  Positions past the 9 taps carry zero weights; they point at
+  // offset 0, a finite activation.
+  for (int e = tid; e < 4 * E::kSub * a.kc; e += 256) {
+    const int k = e * 8, tap = k / a.cip, ch = k - tap * a.cip;
+    const int ky = tap / 3, kx = tap - 3 * ky;
+    ktab[e] = tap < 9 ? ((ky * PC + kx) * S + ch) * E::kBytes : 0;
+  }
+  // 3. LDS stores (the rest of a large fill and of large weights in batches)
+#pragma unroll
+  for (int u = 0; u < kPF; ++u)
+    if (tid + u * 256 < nitems) *(Item*)item_dst(tid + u * 256) = pf[u];
+#pragma unroll
+  for (int u = 0; u < kPW; ++u)
+    if (tid + u * 256 < n16) *(i4*)(wsm + (size_t)(tid + u * 256) * 16) = wv[u];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int e = tid + u * 256;
+    if (e < 2 * a.co) s_ab[e < a.co ? e : ((a.co + 3) & ~3) + e - a.co] = ab[u];
+  }
+  for (int base = tid + kPF * 256; base < nitems; base += 256 * 4) {
+    Item v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (base + u * 256 < nitems) v[u] = load_item(base + u * 256);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (base + u * 256 < nitems) *(Item*)item_dst(base + u * 256) = v[u];
+  }
+  for (int base = tid + kPW * 256; base < n16; base += 256 * 4) {
+    i4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (base + u * 256 < n16)
+        v[u] = __builtin_bit_cast(i4, __builtin_amdgcn_raw_buffer_load_b128(rw, (base + u * 256) * 16,
+                                                                            0, 0));
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (base + u * 256 < n16) *(i4*)(wsm + (size_t)(base + u * 256) * 16) = v[u];
   }
   if (a.up0) {
-    // bilinear x2 (half-pixel centres) from the staged patch.  Patch row r is
-    // output row y0 - 1 + r; its two source rows are staged rows r/2 and
-    // r/2 + 1 with weight 0.25 (r even) or 0.75 (r odd) on the second: the
-    // same taps and weights as the clamped formula, borders included.
+    // 4. bilinear x2 (half-pixel centres) from the staged low patch.  Patch
+    // row r is output row y0 - 1 + r; its two source rows are staged rows
+    // r/2 and r/2 + 1 with weight 0.25 (r even) or 0.75 (r odd) on the
+    // second: the same taps and weights as the clamped formula, borders
+    // included.
     __syncthreads();
-    constexpr int LC = LowPatch<R>::kCols;
     const int tot = PR * PC * g0;
     const int rs = LC * a.c0;
     for (int e = tid; e < tot; e += 256) {
@@ -299,7 +411,7 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a) {
       E::load8(p + a.c0 * E::kBytes, v01);
       E::load8(p + rs * E::kBytes, v10);
       E::load8(p + (rs + a.c0) * E::kBytes, v11);
-      #pragma unroll
+#pragma unroll
       for (int i = 0; i < 8; ++i) {
         const float top = fmaf(fx, v01[i] - v00[i], v00[i]);
         const float bot = fmaf(fx, v11[i] - v10[i], v10[i]);
@@ -310,118 +422,135 @@ __global__ void __launch_bounds__(256) k_conv3x3(ConvArgs a) {
   }
   __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
-  f32x4_t acc[R][NB];
-  #pragma unroll
-  for (int rr = 0; rr < R; ++rr)
-    #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[rr][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
-  const int col = lane & 15;
-  const uint8_t* wl = a.wsw + (size_t)lane * 8 * E::kBytes;
-  // this lane's K position (c * 32 + 8 * (lane / 16)) as (tap, channel),
-  // advanced incrementally (no division in the loop)
-  int ci = 8 * (lane >> 4), tap = 0;
-  while (ci >= a.cip) {
-    ci -= a.cip;
-    ++tap;
-  }
-  auto load_a = [&](int tp, int cc, typename E::Frag* af) {
-    if (tp < 9) {
-      const int ky = tp / 3, kx = tp - ky * 3;
-      #pragma unroll
-      for (int rr = 0; rr < R; ++rr) {
-        const int pix = (wave * R + rr + ky) * PC + col + kx;
-        af[rr] = E::frag(smem + ((size_t)pix * S + cc) * E::kBytes);
-      }
+  const int col = lane & 15, grp = lane >> 4;
+  // weight fragments by buffer loads: per-lane offset in a VGPR, the chunk's
+  // offset uniform (SGPR)
+  const __amdgpu_buffer_rsrc_t wr =
+      make_rsrc(a.wsw, (uint32_t)a.kc * NB * 64 * E::kFragBytes);
+  const int wlane = lane * E::kFragBytes;
+  auto load_b = [&](int c, typename E::Frag* bf) {
+    if (a.b_lds) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        bf[nb] = E::frag(wsm + wlane + (c * NB + nb) * 64 * E::kFragBytes);
     } else {
-      #pragma unroll
-      for (int rr = 0; rr < R; ++rr) af[rr] = E::zero();
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        bf[nb] = E::bfrag(wr, wlane, (c * NB + nb) * 64 * E::kFragBytes);
     }
   };
-  typename E::Frag acur[R], anext[R], bcur[NB], bnext[NB];
-  load_a(tap, ci, acur);
-  #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) bcur[nb] = E::frag(wl + (size_t)nb * 512 * E::kBytes);
-  for (int c = 0; c < a.kc; ++c) {
-    const bool more = c + 1 < a.kc;
-    if (more) {
-      ci += 32;
-      while (ci >= a.cip) {
-        ci -= a.cip;
-        ++tap;
-      }
-      #pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        bnext[nb] = E::frag(wl + ((size_t)(c + 1) * NB + nb) * 512 * E::kBytes);
-      load_a(tap, ci, anext);
-    }
-    // weights as the A operand (M = output channels), pixels as B (N): each
-    // lane ends with 4 consecutive channels of one pixel
-    #pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-      #pragma unroll
-      for (int rr = 0; rr < R; ++rr) acc[rr][nb] = E::mma(bcur[nb], acur[rr], acc[rr][nb]);
-    if (more) {
-      #pragma unroll
-      for (int nb = 0; nb < NB; ++nb) bcur[nb] = bnext[nb];
-      #pragma unroll
-      for (int rr = 0; rr < R; ++rr) acur[rr] = anext[rr];
-    }
-  }
-  // epilogue: bias, ReLU, (calibration max), one packed store per 4 channels;
-  // with pool_out also the 2x2 average of the stored values (rows rr, rr + 1
-  // of this lane, columns of this lane and its neighbour lane ^ 1), summed in
-  // the order (0,0), (0,1), (1,0), (1,1) like the stand-alone pooling kernel
-  float mx = 0.f;
-  const int x = x0 + col;
-  #pragma unroll
-  for (int nb = 0; nb < NB; ++nb) {
-    const int c4 = nb * 16 + 4 * (lane >> 4);
-    if (c4 >= a.co) continue;  // co is a multiple of 8, so c4 + 3 < co here
-    float al[4], bi[4];
-    #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      al[i] = a.alpha ? a.alpha[c4 + i] : 1.0f;
-      bi[i] = a.bias ? a.bias[c4 + i] : 0.0f;
-    }
-    float st[R][4];
-    #pragma unroll
+  // this lane's pixel (row wave R + rr, column col) in the patch, in bytes
+  const uint8_t* prow = smem + (size_t)((wave * R) * PC + col) * S * E::kBytes;
+  const int rstep = PC * S * E::kBytes;
+  using Off = typename std::conditional<E::kSub == 1, int, int4>::type;
+  auto load_a = [&](Off off, typename E::Frag* af) {
+#pragma unroll
     for (int rr = 0; rr < R; ++rr) {
-      const int y = y0 + wave * R + rr;
-      float v[4];
+      if constexpr (E::kSub == 1)
+        af[rr] = E::frag(prow + rr * rstep + off);
+      else
+        af[rr] = E::frag4(prow + rr * rstep, off);
+    }
+  };
+  auto koff = [&](int c) -> Off { return ((const Off*)ktab)[4 * c + grp]; };
+  {
+    f32x4_t acc[R][NB];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) acc[rr][nb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+    if constexpr (!E::kPrefetch) {
+      // 32-byte fragments: no register double buffering (it would double the
+      // operand registers); the other waves on the SIMD cover the LDS latency
+      for (int c = 0; c < a.kc; ++c) {
+        typename E::Frag af[R], bf[NB];
+        load_b(c, bf);
+        load_a(koff(c), af);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr) acc[rr][nb] = E::mma(bf[nb], af[rr], acc[rr][nb]);
+      }
+    } else {
+      typename E::Frag acur[R], anext[R], bcur[NB], bnext[NB];
+      load_a(koff(0), acur);
+      load_b(0, bcur);
+      Off offn = koff(a.kc > 1 ? 1 : 0);
+      for (int c = 0; c < a.kc; ++c) {
+        const bool more = c + 1 < a.kc;
+        if (more) {
+          load_b(c + 1, bnext);
+          load_a(offn, anext);
+          offn = koff(c + 2 < a.kc ? c + 2 : 0);
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr) acc[rr][nb] = E::mma(bcur[nb], acur[rr], acc[rr][nb]);
+        if (more) {
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb) bcur[nb] = bnext[nb];
+#pragma unroll
+          for (int rr = 0; rr < R; ++rr) acur[rr] = anext[rr];
+        }
+      }
+    }
+    // epilogue: bias, ReLU, (calibration max), one packed store per 4 channels;
+    // with pool_out also the 2x2 average of the stored values (rows rr, rr + 1
+    // of this lane, columns of this lane and its neighbour lane ^ 1), summed in
+    // the order (0,0), (0,1), (1,0), (1,1) like the stand-alone pooling kernel
+    float mx = 0.f;
+    const int x = x0 + col;
+    #pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+      const int c4 = nb * 16 + 4 * (lane >> 4);
+      if (c4 >= a.co) continue;  // co is a multiple of 8, so c4 + 3 < co here
+      float al[4], bi[4];
       #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        v[i] = fmaf(acc[rr][nb][i], al[i], bi[i]);
-        if (a.relu) v[i] = fmaxf(v[i], 0.0f);
-        st[rr][i] = v[i];
+        al[i] = s_ab[c4 + i];
+        bi[i] = s_ab[((a.co + 3) & ~3) + c4 + i];
       }
-      if (y >= a.h || x >= a.w) continue;
+      float st[R][4];
       #pragma unroll
-      for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(v[i]));
-      const int64_t o = (((int64_t)b * a.h + y) * a.w + x) * a.out_ch + c4;
-      if (a.out_fp32)
-        *(float4*)((float*)a.out + o) = make_float4(v[0], v[1], v[2], v[3]);
-      else
-        E::store4(a.out + o * E::kBytes, v);
-    }
-    if (R >= 2 && a.pool_out) {
-      #pragma unroll
-      for (int rr = 0; rr + 1 < R; rr += 2) {
+      for (int rr = 0; rr < R; ++rr) {
         const int y = y0 + wave * R + rr;
-        float pv[4];
+        float v[4];
         #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const float t0 = E::rnd(st[rr][i]), t1 = E::rnd(st[rr + 1][i]);
-          const float n0 = __shfl_xor(t0, 1, 64), n1 = __shfl_xor(t1, 1, 64);
-          pv[i] = (((t0 + n0) + t1) + n1) * 0.25f;
+          v[i] = fmaf(acc[rr][nb][i], al[i], bi[i]);
+          if (a.relu) v[i] = fmaxf(v[i], 0.0f);
+          st[rr][i] = v[i];
         }
-        if ((col & 1) || y >= a.h || x >= a.w) continue;
-        const int64_t o =
-            (((int64_t)b * (a.h >> 1) + (y >> 1)) * (a.w >> 1) + (x >> 1)) * a.out_ch + c4;
-        E::store4(a.pool_out + o * E::kBytes, pv);
+        if (y >= a.h || x >= a.w) continue;
+        #pragma unroll
+        for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(v[i]));
+        const int64_t o = (((int64_t)b * a.h + y) * a.w + x) * a.out_ch + c4;
+        if (a.out_fp32)
+          *(float4*)((float*)a.out + o) = make_float4(v[0], v[1], v[2], v[3]);
+        else
+          E::store4(a.out + o * E::kBytes, v);
+      }
+      if (R >= 2 && a.pool_out) {
+        #pragma unroll
+        for (int rr = 0; rr + 1 < R; rr += 2) {
+          const int y = y0 + wave * R + rr;
+          float pv[4];
+          #pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float t0 = E::rnd(st[rr][i]), t1 = E::rnd(st[rr + 1][i]);
+            const float n0 = __shfl_xor(t0, 1, 64), n1 = __shfl_xor(t1, 1, 64);
+            pv[i] = (((t0 + n0) + t1) + n1) * 0.25f;
+          }
+          if ((col & 1) || y >= a.h || x >= a.w) continue;
+          const int64_t o =
+              (((int64_t)b * (a.h >> 1) + (y >> 1)) * (a.w >> 1) + (x >> 1)) * a.out_ch + c4;
+          E::store4(a.pool_out + o * E::kBytes, pv);
+        }
       }
     }
+    if (a.absmax) wave_absmax(a.absmax, mx);
   }
-  if (a.absmax) wave_absmax(a.absmax, mx);
 }
 
 template <class E>
