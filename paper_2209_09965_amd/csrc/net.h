@@ -101,7 +101,8 @@ struct fv_net {
   int64_t step;           // Adam steps taken
   void* w_bf16[fv::net::kNumConv];
   void* w_bf16t[fv::net::kNumConv];     // transposed (input-gradient) weights
-  void* w_heads;                        // the two 1x1 heads as BF16 MFMA B fragments
+  void* w_heads;                        // the two 1x1 heads as BF16 MFMA fragments
+  void* w_heads_fp8;                    // the same times the FP8 decoder-output scale
   void* w_fp8[fv::net::kNumConv];
   float* alpha_fp8[fv::net::kNumConv];  // per-output-channel dequant x requant factor
   float* bias_fp8[fv::net::kNumConv];   // bias / output scale

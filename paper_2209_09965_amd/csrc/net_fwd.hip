@@ -135,36 +135,41 @@ __global__ void __launch_bounds__(256) k_avgpool2(const uint8_t* __restrict__ sr
 // [400 halo pixels x 32] x [32 x 32] (BF16 operands, FP32 accumulation; FP8
 // activations are widened in registers) whose 28 used columns land in LDS;
 // softmax and the kernel application run in FP32.
-// 8 stored channels of one pixel (FP8 times its tensor scale) as BF16.
+// 8 stored channels of one pixel as BF16 (exact for E4M3 codes; the FP8
+// tensor scale is folded into the FP8-mode head weights).
 template <class E>
-__device__ __forceinline__ bf16x8_t heads_frag(const typename Chunk8<E>::T& raw, float in_scale) {
-  float v[8];
-  E::load8((const uint8_t*)&raw, v);
-  bf16x8_t f;
-  for (int j = 0; j < 8; ++j) f[j] = (__bf16)(v[j] * in_scale);
-  return f;
+__device__ __forceinline__ bf16x8_t heads_frag(const typename Chunk8<E>::T& raw);
+
+template <>
+__device__ __forceinline__ bf16x8_t heads_frag<FP8>(const uint2& raw) {
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  const bf16x2_t p0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8((int)raw.x, 1.0f, false);
+  const bf16x2_t p1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8((int)raw.x, 1.0f, true);
+  const bf16x2_t p2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8((int)raw.y, 1.0f, false);
+  const bf16x2_t p3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8((int)raw.y, 1.0f, true);
+  return bf16x8_t{p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
 }
 
 template <>
-__device__ __forceinline__ bf16x8_t heads_frag<BF16>(const uint4& raw, float) {
+__device__ __forceinline__ bf16x8_t heads_frag<BF16>(const uint4& raw) {
   return __builtin_bit_cast(bf16x8_t, raw);
 }
 
 // The two 1x1 heads and the kernel-prediction output (Sec. 3.2, "Direct
-// Prediction" and "Kernel Prediction"): per pixel
-// O_d = hd . h + b_d and logits = hk . h + b_k (h = the 32 decoder channels),
-// w = softmax(logits) over the 25 taps, O = sum_q w_q O_d(pixel + offset_q)
-// with edge-replicated O_d.  Block = 16 x 16 output pixels.  Both heads run
-// on MFMA with the head weights as the A operand, so a lane holds 4 output
-// channels of one pixel: O_d of the 20 x 20 halo goes to LDS, while the
-// logits of a tile pixel stay in the registers of the 4 lanes that own it
-// and the softmax and the 5 x 5 sum reduce across those lanes.  All global
-// loads of a wave are issued before the first MFMA.
+// Prediction" and "Kernel Prediction"): per pixel O_d = hd . h + b_d and
+// logits = hk . h + b_k (h = the 32 decoder channels), w = softmax(logits)
+// over the 25 taps, O = sum_q w_q O_d(pixel + offset_q) with edge-replicated
+// O_d.  Block = 16 x 16 output pixels.  Both heads run on MFMA with the head
+// weights as the A operand, so a lane holds 4 output channels of one pixel:
+// O_d of the 20 x 20 halo goes to LDS, while the logits of a tile pixel stay
+// in the registers of the 4 lanes that own it and the softmax and the 5 x 5
+// sum reduce across those lanes.  All global loads of a wave are issued
+// before the first MFMA.
 template <class E>
 __global__ void __launch_bounds__(256) k_heads(const uint8_t* __restrict__ hdec, int n, int h,
                                                int w, const float* __restrict__ params,
                                                const __bf16* __restrict__ whs,
-                                               int64_t off_hd, int64_t off_hk, float in_scale,
+                                               int64_t off_hd, int64_t off_hk,
                                                float* __restrict__ out_rgb,
                                                float* __restrict__ out_od,
                                                float* __restrict__ out_wk) {
@@ -177,14 +182,14 @@ __global__ void __launch_bounds__(256) k_heads(const uint8_t* __restrict__ hdec,
   const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 16, b = blockIdx.z;
   const uint8_t* img = hdec + (int64_t)b * h * w * 32 * E::kBytes + 8 * grp * E::kBytes;
   Raw rh[KH], rc[4];
+#pragma unroll
   for (int k = 0; k < KH; ++k) {
-    const int hb = wave + 4 * k;
-    if (hb < HB) {
-      const int hp = hb * 16 + col, r = hp / HW, c = hp - r * HW;
-      const int y = min(max(y0 - 2 + r, 0), h - 1), x = min(max(x0 - 2 + c, 0), w - 1);
-      rh[k] = *(const Raw*)(img + ((int64_t)y * w + x) * 32 * E::kBytes);
-    }
+    const int hb = min(wave + 4 * k, HB - 1);  // (a repeated block is not stored)
+    const int hp = hb * 16 + col, r = hp / HW, c = hp - r * HW;
+    const int y = min(max(y0 - 2 + r, 0), h - 1), x = min(max(x0 - 2 + c, 0), w - 1);
+    rh[k] = *(const Raw*)(img + ((int64_t)y * w + x) * 32 * E::kBytes);
   }
+#pragma unroll
   for (int m = 0; m < 4; ++m) {
     const int y = min(y0 + wave * 4 + m, h - 1), x = min(x0 + col, w - 1);
     rc[m] = *(const Raw*)(img + ((int64_t)y * w + x) * 32 * E::kBytes);
@@ -193,45 +198,51 @@ __global__ void __launch_bounds__(256) k_heads(const uint8_t* __restrict__ hdec,
   const bf16x8_t w0 = *(const bf16x8_t*)(whs + (size_t)lane * 8);
   const bf16x8_t w1 = *(const bf16x8_t*)(whs + (size_t)(64 + lane) * 8);
   // this lane's 8 output channels: 4 grp + i (block 0) and 16 + 4 grp + i
-  // (block 1); channel c < 3 is O_d, 3 <= c < 28 is the logit of tap c - 3
+  // (block 1); channel c < 3 is O_d, 3 <= c < 28 the logit of tap c - 3.
+  // Slots that are not taps get a -inf logit bias: their softmax weight is 0.
   float bias[8];
   int tap_off[8];
-  bool is_tap[8];
+#pragma unroll
   for (int j = 0; j < 8; ++j) {
     const int c = (j < 4 ? 0 : 16) + 4 * grp + (j & 3);
-    is_tap[j] = c >= 3 && c < 28;
-    bias[j] = c < 3 ? params[off_hd + 96 + c] : (c < 28 ? params[off_hk + 800 + c - 3] : 0.f);
-    const int q = is_tap[j] ? c - 3 : 0;
+    const bool tap = c >= 3 && c < 28;
+    bias[j] = tap ? params[off_hk + 800 + c - 3] : -INFINITY;
+    const int q = tap ? c - 3 : 0;
     tap_off[j] = (q / 5) * HW + q % 5;
   }
+  float bd[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) bd[i] = params[off_hd + 96 + i];
+#pragma unroll
   for (int k = 0; k < KH; ++k) {
     const int hb = wave + 4 * k;
-    if (hb < HB) {
-      const f32x4_t d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-          w0, heads_frag<E>(rh[k], in_scale), f32x4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-      if (grp == 0) s_od[hb * 16 + col] = make_float4(d[0] + bias[0], d[1] + bias[1],
-                                                      d[2] + bias[2], 0.f);
-    }
+    const f32x4_t d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+        w0, heads_frag<E>(rh[k]), f32x4_t{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    if (hb < HB && grp == 0)
+      s_od[hb * 16 + col] = make_float4(d[0] + bd[0], d[1] + bd[1], d[2] + bd[2], 0.f);
   }
   __syncthreads();
+#pragma unroll
   for (int m = 0; m < 4; ++m) {
     const int ty = wave * 4 + m, y = y0 + ty, x = x0 + col;
-    const bf16x8_t f = heads_frag<E>(rc[m], in_scale);
+    const bf16x8_t f = heads_frag<E>(rc[m]);
     const f32x4_t d0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w0, f, f32x4_t{0.f, 0.f, 0.f, 0.f},
                                                                0, 0, 0);
     const f32x4_t d1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w1, f, f32x4_t{0.f, 0.f, 0.f, 0.f},
                                                                0, 0, 0);
     float lg[8];
     float mx = -INFINITY;
+#pragma unroll
     for (int j = 0; j < 8; ++j) {
       lg[j] = (j < 4 ? d0[j] : d1[j - 4]) + bias[j];
-      if (is_tap[j]) mx = fmaxf(mx, lg[j]);
+      mx = fmaxf(mx, lg[j]);
     }
     mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
     mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
     float den = 0.f;
+#pragma unroll
     for (int j = 0; j < 8; ++j) {
-      lg[j] = is_tap[j] ? expf(lg[j] - mx) : 0.f;
+      lg[j] = __expf(lg[j] - mx);
       den += lg[j];
     }
     den += __shfl_xor(den, 16, 64);
@@ -239,8 +250,8 @@ __global__ void __launch_bounds__(256) k_heads(const uint8_t* __restrict__ hdec,
     const float inv = 1.0f / den;
     const float4* win = s_od + ty * HW + col;  // top-left of this pixel's 5 x 5 window
     float o0 = 0.f, o1 = 0.f, o2 = 0.f;
+#pragma unroll
     for (int j = 0; j < 8; ++j) {
-      if (!is_tap[j]) continue;
       lg[j] *= inv;
       const float4 od = win[tap_off[j]];
       o0 = fmaf(lg[j], od.x, o0);
@@ -260,23 +271,25 @@ __global__ void __launch_bounds__(256) k_heads(const uint8_t* __restrict__ hdec,
       out_rgb[p * 3 + 1] = o1;
       out_rgb[p * 3 + 2] = o2;
       if (out_od) {
-        out_od[p * 3 + 0] = d0[0] + bias[0];
-        out_od[p * 3 + 1] = d0[1] + bias[1];
-        out_od[p * 3 + 2] = d0[2] + bias[2];
+        out_od[p * 3 + 0] = d0[0] + bd[0];
+        out_od[p * 3 + 1] = d0[1] + bd[1];
+        out_od[p * 3 + 2] = d0[2] + bd[2];
       }
     }
-    if (out_wk)
+    if (out_wk) {
+#pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int c = (j < 4 ? 0 : 16) + 4 * grp + (j & 3);
-        if (is_tap[j]) out_wk[p * 25 + c - 3] = lg[j];
+        if (c >= 3 && c < 28) out_wk[p * 25 + c - 3] = lg[j];
       }
+    }
   }
 }
 
 // Head weights [hd (3 rows); hk (25 rows); 4 zero rows] x 32 inputs as the
 // two BF16 MFMA B fragments (n block 0: rows 0-15, n block 1: rows 16-31).
 __global__ void k_swizzle_heads(const float* __restrict__ hd, const float* __restrict__ hk,
-                                __bf16* __restrict__ out) {
+                                __bf16* __restrict__ out, float scale) {
   const int e = blockIdx.x * 256 + threadIdx.x;
   if (e >= 2 * 512) return;
   const int j = e & 7, l = (e >> 3) & 63, nb = e >> 9;
@@ -286,7 +299,7 @@ __global__ void k_swizzle_heads(const float* __restrict__ hd, const float* __res
     v = hd[nrow * 32 + k];
   else if (nrow < 28)
     v = hk[(nrow - 3) * 32 + k];
-  out[e] = (__bf16)v;
+  out[e] = (__bf16)(v * scale);
 }
 
 // Master FP32 weights of a 3x3 layer -> swizzled BF16 MFMA B fragments.
@@ -372,9 +385,13 @@ fv_status launch_conv(const ConvArgs& args, int nb, hipStream_t s) {
   if (a.up0 && (a.c0 % 8 || a.c0 < 16 || (a.h | a.w) & 1))
     return fail(FV_ERR_UNSUPPORTED, "conv: upsampled source with %d channels at %d x %d", a.c0,
                 a.w, a.h);
-  const uint32_t g0 = a.up0 ? (uint32_t)(a.c0 >> 3) : 0u;
-  a.gmagic = magic((uint32_t)(a.cip >> 3) - g0);
+  // FP8 fill items of 16 channels when no item straddles a source boundary
+  a.wide = E::kBytes == 1 && a.cip % 16 == 0 && a.c0 % 16 == 0 && a.c1 % 16 == 0;
+  const uint32_t iw = a.wide ? 16u : 8u;
+  const uint32_t g0 = a.up0 ? (uint32_t)a.c0 / iw : 0u;
+  a.gmagic = magic((uint32_t)a.cip / iw - g0);
   a.umagic = magic(g0);
+  a.umagic8 = magic((uint32_t)a.c0 >> 3);  // (exact for the 2 x 2 block items too)
   // rows per wave: the largest R that still gives at least two blocks per CU
   // (256 CUs) and whose patch fits in 48 KB of LDS; the weights are staged in
   // LDS only while the block's LDS stays within 40 KB (four blocks per CU)
@@ -432,7 +449,7 @@ size_t swizzled_elems(int in_ch, int out_ch) {
 
 fv_status refresh_bf16(fv_net* n, hipStream_t s) {
   k_swizzle_heads<<<4, 256, 0, s>>>(n->master + param_offset(14), n->master + param_offset(15),
-                                    (__bf16*)n->w_heads);
+                                    (__bf16*)n->w_heads, 1.0f);
   for (int l = 0; l < kNumConv; ++l) {
     fv_status st = swizzle_bf16(n->master + param_offset(l), kLayers[l].ci, kLayers[l].co, 0,
                                 n->w_bf16[l], s);
@@ -494,9 +511,8 @@ fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const floa
   }
   dim3 grid((p.w + 15) / 16, (p.h + 15) / 16, p.n);
   k_heads<E><<<grid, 256, 0, s>>>(ws + p.t[T_D0B], p.n, p.h, p.w, net->master,
-                                  (const __bf16*)net->w_heads, param_offset(14),
-                                  param_offset(15), fp8 ? net->act_scale[T_D0B] : 1.0f, out_rgb,
-                                  out_od, out_wk);
+                                  (const __bf16*)(fp8 ? net->w_heads_fp8 : net->w_heads),
+                                  param_offset(14), param_offset(15), out_rgb, out_od, out_wk);
   return launch_status("heads");
 }
 
@@ -570,6 +586,12 @@ fv_status build_fp8(fv_net* n, hipStream_t s) {
                                 hipMemcpyHostToDevice), "fp8: bias");
     if (st != FV_OK) return st;
   }
+  // heads on FP8 decoder outputs: the tensor scale folded into the weights
+  k_swizzle_heads<<<4, 256, 0, s>>>(n->master + param_offset(14), n->master + param_offset(15),
+                                    (__bf16*)n->w_heads_fp8, n->act_scale[T_D0B]);
+  st = launch_status("fp8: heads");
+  if (st == FV_OK) st = hip_status(hipStreamSynchronize(s), "fp8: sync");
+  if (st != FV_OK) return st;
   n->fp8_ready = 1;
   return FV_OK;
 }
@@ -608,6 +630,7 @@ fv_status fv_net_create(const float* host_params, size_t n_params, fv_net** out)
   const size_t pb = n_params * sizeof(float);
   bool ok = hipMalloc(&n->master, pb) == hipSuccess && hipMalloc(&n->adam_m, pb) == hipSuccess &&
             hipMalloc(&n->w_heads, 2 * 512 * 2) == hipSuccess &&
+            hipMalloc(&n->w_heads_fp8, 2 * 512 * 2) == hipSuccess &&
             hipMalloc(&n->adam_v, pb) == hipSuccess && hipMalloc(&n->grad, pb) == hipSuccess;
   for (int l = 0; ok && l < kNumConv; ++l) {
     const size_t e = swizzled_elems(kLayers[l].c0 + kLayers[l].c1, kLayers[l].co);
@@ -645,6 +668,7 @@ fv_status fv_net_destroy(fv_net* n) {
   (void)hipFree(n->adam_v);
   (void)hipFree(n->grad);
   (void)hipFree(n->w_heads);
+  (void)hipFree(n->w_heads_fp8);
   for (int l = 0; l < kNumConv; ++l) {
     (void)hipFree(n->w_bf16[l]);
     (void)hipFree(n->w_bf16t[l]);

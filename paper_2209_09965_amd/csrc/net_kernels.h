@@ -167,10 +167,12 @@ struct ConvArgs {
   uint8_t* pool_out;    // 2x2 average of the stored output (half resolution,
                         // out_ch stride), or null
   uint32_t src0_bytes, src1_bytes;  // sizes for the buffer-load range checks
-  // set by launch_conv: e / ng == umulhi(e, gmagic) for ng = cip / 8 groups
-  // copied from memory (0: ng == 1); umagic likewise for the c0 / 8
-  // upsampled groups
+  // set by launch_conv: e / ng == umulhi(e, gmagic) for the ng fill-item
+  // channel groups copied from memory (0: ng == 1); umagic likewise for the
+  // groups of the low-resolution patch of an upsampled source 0
   uint32_t gmagic, umagic;
+  uint32_t umagic8;  // same for the c0 / 8 groups of the upsampling pass
+  int wide;   // set by launch_conv: fill items of 16 channels (FP8) instead of 8
   int b_lds;  // set by launch_conv: the weight fragments are staged in LDS
 };
 
@@ -261,11 +263,11 @@ __global__ void __launch_bounds__(256)
   extern __shared__ __align__(16) uint8_t smem[];
   constexpr int PR = 4 * R + 2, PC = 18;
   constexpr int LR = LowPatch<R>::kRows, LC = LowPatch<R>::kCols;
-  constexpr int kPF = 8;                      // fill items per thread in the first batch
+  constexpr int kPF = E::kBytes == 1 ? 6 : 8;  // fill items per thread in the first batch
   constexpr int kPW = 6;                      // weight loads (16 B) per thread in flight
   constexpr int kOutside = (int)0x80000000u;  // beyond every source (< 2 GiB)
   using C8 = Chunk8<E>;
-  using Item = typename C8::T;
+  using Item = uint4;  // 16 bytes: 16 FP8 channels (wide), else 8 channels
   typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i4;
   const int S = patch_stride<E>(a.cip);  // patch pixel stride in elements
   const int tid = threadIdx.x;
@@ -284,13 +286,22 @@ __global__ void __launch_bounds__(256)
   // after an upsampled source 0).  Pixels outside the image and padding
   // channels load from an out-of-range offset, which the hardware reads as
   // zero.
-  const int groups = a.cip >> 3, g0 = a.up0 ? a.c0 >> 3 : 0, ng = groups - g0;
+  const int IW = E::kBytes == 1 && a.wide ? 16 : 8;  // channels per fill item
+  const int groups = a.cip / IW, g0 = a.up0 ? a.c0 / IW : 0, ng = groups - g0;
   const int nlow = a.up0 ? LR * LC * g0 : 0;
   const int nitems = nlow + PR * PC * ng;
   const int hh = a.h >> 1, ww = a.w >> 1;
   const __amdgpu_buffer_rsrc_t r0 = make_rsrc(a.src0, a.src0_bytes);
   const __amdgpu_buffer_rsrc_t r1 =
       make_rsrc(a.src1 ? a.src1 : a.src0, a.src1 ? a.src1_bytes : 0u);
+  // a fill item's load: 16 bytes, or 8 (narrow FP8 items; the upper half
+  // is unused)
+  auto load16 = [&](__amdgpu_buffer_rsrc_t r, int off) -> Item {
+    if (E::kBytes == 2 || IW == 16)
+      return __builtin_bit_cast(Item, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+    const uint2 v = Chunk8<FP8>::load(r, off);
+    return make_uint4(v.x, v.y, 0u, 0u);
+  };
   auto load_item = [&](int i) -> Item {
     if (i < nlow) {
       const int pix = (int)__umulhi((uint32_t)i, a.umagic), g = i - pix * g0;
@@ -298,27 +309,38 @@ __global__ void __launch_bounds__(256)
       const int ly = min(max((y0 >> 1) - 1 + r, 0), hh - 1);
       const int lx = min(max((x0 >> 1) - 1 + c, 0), ww - 1);
       const uint32_t p = ((uint32_t)b * (uint32_t)hh + (uint32_t)ly) * (uint32_t)ww + (uint32_t)lx;
-      return C8::load(r0, (int)((p * (uint32_t)a.c0 + g * 8) * E::kBytes));
+      return load16(r0, (int)((p * (uint32_t)a.c0 + g * IW) * E::kBytes));
     }
     const int e = i - nlow;
     const int pix = a.gmagic ? (int)__umulhi((uint32_t)e, a.gmagic) : e;
     const int g = g0 + e - pix * ng;
     const int r = pix / PC, c = pix - r * PC;
-    const int y = y0 - 1 + r, x = x0 - 1 + c, ch = g * 8;
+    const int y = y0 - 1 + r, x = x0 - 1 + c, ch = g * IW;
     const bool in = y >= 0 && y < a.h && x >= 0 && x < a.w;
     const uint32_t p = ((uint32_t)b * (uint32_t)a.h + (uint32_t)y) * (uint32_t)a.w + (uint32_t)x;
     if (ch < a.c0)  // (never with an upsampled source 0: then g >= g0)
-      return C8::load(r0, in ? (int)((p * (uint32_t)a.c0 + ch) * E::kBytes) : kOutside);
-    return C8::load(r1, in && ch < a.c0 + a.c1
-                            ? (int)((p * (uint32_t)a.c1 + (ch - a.c0)) * E::kBytes)
-                            : kOutside);
+      return load16(r0, in ? (int)((p * (uint32_t)a.c0 + ch) * E::kBytes) : kOutside);
+    return load16(r1, in && ch < a.c0 + a.c1
+                          ? (int)((p * (uint32_t)a.c1 + (ch - a.c0)) * E::kBytes)
+                          : kOutside);
   };
-  auto item_dst = [&](int i) -> uint8_t* {
-    if (i < nlow) return low + (size_t)i * 8 * E::kBytes;
-    const int e = i - nlow;
-    const int pix = a.gmagic ? (int)__umulhi((uint32_t)e, a.gmagic) : e;
-    const int g = g0 + e - pix * ng;
-    return smem + ((size_t)pix * S + g * 8) * E::kBytes;
+  auto store_item = [&](int i, const Item& v) {
+    uint8_t* dst;
+    if (i < nlow) {
+      dst = low + (size_t)i * IW * E::kBytes;
+    } else {
+      const int e = i - nlow;
+      const int pix = a.gmagic ? (int)__umulhi((uint32_t)e, a.gmagic) : e;
+      const int g = g0 + e - pix * ng;
+      dst = smem + ((size_t)pix * S + g * IW) * E::kBytes;
+    }
+    if (E::kBytes == 2) {
+      *(Item*)dst = v;  // 16-byte aligned: the BF16 patch stride is 16 mod 32 bytes
+    } else {
+      // the FP8 patch stride is 8 mod 16 bytes: 8-byte stores
+      *(uint2*)dst = make_uint2(v.x, v.y);
+      if (IW == 16) *(uint2*)(dst + 8) = make_uint2(v.z, v.w);
+    }
   };
   // 1. every global load up front: patch items, weight fragments, scale/bias
   Item pf[kPF];
@@ -357,7 +379,7 @@ __global__ void __launch_bounds__(256)
   // 3. LDS stores (the rest of a large fill and of large weights in batches)
 #pragma unroll
   for (int u = 0; u < kPF; ++u)
-    if (tid + u * 256 < nitems) *(Item*)item_dst(tid + u * 256) = pf[u];
+    if (tid + u * 256 < nitems) store_item(tid + u * 256, pf[u]);
 #pragma unroll
   for (int u = 0; u < kPW; ++u)
     if (tid + u * 256 < n16) *(i4*)(wsm + (size_t)(tid + u * 256) * 16) = wv[u];
@@ -373,7 +395,7 @@ __global__ void __launch_bounds__(256)
       if (base + u * 256 < nitems) v[u] = load_item(base + u * 256);
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-      if (base + u * 256 < nitems) *(Item*)item_dst(base + u * 256) = v[u];
+      if (base + u * 256 < nitems) store_item(base + u * 256, v[u]);
   }
   for (int base = tid + kPW * 256; base < n16; base += 256 * 4) {
     i4 v[4];
@@ -388,36 +410,50 @@ __global__ void __launch_bounds__(256)
   }
   if (a.up0) {
     // 4. bilinear x2 (half-pixel centres) from the staged low patch.  Patch
-    // row r is output row y0 - 1 + r; its two source rows are staged rows
-    // r/2 and r/2 + 1 with weight 0.25 (r even) or 0.75 (r odd) on the
-    // second: the same taps and weights as the clamped formula, borders
-    // included.
+    // rows 2i and 2i + 1 are output rows y0 - 1 + 2i (+1); both read staged
+    // rows i and i + 1, with weight 0.25 (even row) or 0.75 (odd row) on the
+    // second (columns alike): the same taps and weights as the clamped
+    // formula, borders included.  One item = a 2 x 2 block of patch pixels
+    // and 8 channels, computed from one 2 x 2 block of staged pixels.
     __syncthreads();
-    const int tot = PR * PC * g0;
+    constexpr int PB = PR / 2, CB = PC / 2;  // 2 x 2 blocks per patch column / row
+    const int u8 = a.c0 >> 3;                 // 8-channel groups of source 0
+    const int tot = PB * CB * u8;
     const int rs = LC * a.c0;
     for (int e = tid; e < tot; e += 256) {
-      const int pix = (int)__umulhi((uint32_t)e, a.umagic), g = e - pix * g0;
-      const int r = pix / PC, c = pix - r * PC;
-      const int y = y0 - 1 + r, x = x0 - 1 + c;
-      uint8_t* dst = smem + ((size_t)pix * S + g * 8) * E::kBytes;
-      if (y < 0 || y >= a.h || x < 0 || x >= a.w) {
-        E::zero8(dst);
-        continue;
-      }
-      const float fy = (r & 1) ? 0.75f : 0.25f, fx = (c & 1) ? 0.75f : 0.25f;
-      const uint8_t* p = low + ((r >> 1) * rs + (c >> 1) * a.c0 + g * 8) * E::kBytes;
-      float v00[8], v01[8], v10[8], v11[8], o[8];
+      const int blk = (int)__umulhi((uint32_t)e, a.umagic8), g = e - blk * u8;
+      const int i = blk / CB, j = blk - i * CB;
+      const uint8_t* p = low + (i * rs + j * a.c0 + g * 8) * E::kBytes;
+      float v00[8], v01[8], v10[8], v11[8];
       E::load8(p, v00);
       E::load8(p + a.c0 * E::kBytes, v01);
       E::load8(p + rs * E::kBytes, v10);
       E::load8(p + (rs + a.c0) * E::kBytes, v11);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const float top = fmaf(fx, v01[i] - v00[i], v00[i]);
-        const float bot = fmaf(fx, v11[i] - v10[i], v10[i]);
-        o[i] = fmaf(fy, bot - top, top);
+      for (int dx = 0; dx < 2; ++dx) {
+        const float fx = dx ? 0.75f : 0.25f;
+        float top[8], bot[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          top[k] = fmaf(fx, v01[k] - v00[k], v00[k]);
+          bot[k] = fmaf(fx, v11[k] - v10[k], v10[k]);
+        }
+        const int c = 2 * j + dx, x = x0 - 1 + c;
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy) {
+          const float fy = dy ? 0.75f : 0.25f;
+          const int r = 2 * i + dy, y = y0 - 1 + r;
+          uint8_t* dst = smem + ((size_t)(r * PC + c) * S + g * 8) * E::kBytes;
+          if (y < 0 || y >= a.h || x < 0 || x >= a.w) {
+            E::zero8(dst);
+            continue;
+          }
+          float o[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) o[k] = fmaf(fy, bot[k] - top[k], top[k]);
+          E::store8(dst, o);
+        }
       }
-      E::store8(dst, o);
     }
   }
   __syncthreads();
