@@ -11,8 +11,14 @@ the network weights come from paper_2209_09965_amd/weights/recon.npy (trained
 by python -m paper_2209_09965_amd.train) and are calibrated for FP8 on one
 frame of the workload before the timed region.
 
-Prints one JSON line (see the keys below); per-stage times come from HIP
-events recorded on the stream the kernels run on.
+Timing: `value` is ms per foveated frame with the frames run one after the
+other on one HIP stream; the per-stage times come from HIP events recorded on
+that stream.  The dense baseline is timed the same way.  Beside them,
+pipelined_*: frames issued alternately on two streams (default priority), so
+that one frame's reconstruction may overlap the next frame's march (every
+frame computed in full); the dense march is pipelined the same way.
+
+Prints one JSON line (see the keys below).
 """
 import argparse
 import json
@@ -104,101 +110,119 @@ def main():
         return [synthetic.orbit_camera(k % 60, eye_offset=-eye_off),
                 synthetic.orbit_camera(k % 60, eye_offset=eye_off)]
 
-    stream = torch.cuda.current_stream()
+    # two streams at the default priority, each with its own frame buffers:
+    # the pipelined runs put frame k on stream k % 2, so frame k's
+    # reconstruction can overlap frame k + 1's sample map and march
+    streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
     vol_t = torch.from_numpy(vol).to(dev)
     volh = b.Volume(vol_t)
     del vol_t
     tf_t = torch.from_numpy(tf).reshape(-1).to(dev)
     total = V * W * H
-    ray_idx = torch.empty(total, dtype=torch.int32, device=dev)
-    count = torch.zeros(1, dtype=torch.int32, device=dev)
-    mask = torch.empty(total, dtype=torch.uint8, device=dev)
-    mws = torch.empty(b.fovea_mask_workspace(W, H, V), dtype=torch.uint8, device=dev)
-    sws = torch.empty(b.raymarch_sparse_workspace(), dtype=torch.uint8, device=dev)
-    frame = torch.zeros(total * 4, dtype=torch.float32, device=dev)
-    fdepth = torch.zeros(total, dtype=torch.float32, device=dev)
-    dframe = torch.zeros(total * 4, dtype=torch.float32, device=dev)
-    ddepth = torch.zeros(total, dtype=torch.float32, device=dev)
+    net = b.Net(np.load(args.weights))
+
+    def buffers():
+        return dict(
+            ray_idx=torch.empty(total, dtype=torch.int32, device=dev),
+            count=torch.zeros(1, dtype=torch.int32, device=dev),
+            mask=torch.empty(total, dtype=torch.uint8, device=dev),
+            mws=torch.empty(b.fovea_mask_workspace(W, H, V), dtype=torch.uint8, device=dev),
+            sws=torch.empty(b.raymarch_sparse_workspace(), dtype=torch.uint8, device=dev),
+            frame=torch.zeros(total * 4, dtype=torch.float32, device=dev),
+            fdepth=torch.zeros(total, dtype=torch.float32, device=dev),
+            out_rgb=torch.empty(total * 3, dtype=torch.float32, device=dev),
+            rws=torch.empty(net.workspace_bytes(V, W, H, args.precision), dtype=torch.uint8,
+                            device=dev),
+            dframe=torch.zeros(total * 4, dtype=torch.float32, device=dev),
+            ddepth=torch.zeros(total, dtype=torch.float32, device=dev))
+
+    bufs = [buffers(), buffers()]
     scount = torch.zeros(1, dtype=torch.int64, device=dev)
     dcount = torch.zeros(1, dtype=torch.int64, device=dev)
-    net = b.Net(np.load(args.weights))
-    out_rgb = torch.empty(total * 3, dtype=torch.float32, device=dev)
-    rws = torch.empty(net.workspace_bytes(V, W, H, args.precision), dtype=torch.uint8,
-                      device=dev)
     cam_list = [cams_for(k) for k in range(args.warmup + args.steps)]
     fps = [synthetic.fovea_params(W, H, sigma_frac=sig_frac, frame=k)
            for k in range(args.warmup + args.steps)]
 
-    def foveated(k, ev=None):
+    def foveated(k, j=0, ev=None):
+        st, bf = streams[j], bufs[j]
         if ev:
-            ev[0].record(stream)
-        b.fovea_mask(fps[k], W, H, V, ray_idx, count, mask=mask, workspace=mws, stream=stream)
+            ev[0].record(st)
+        b.fovea_mask(fps[k], W, H, V, bf["ray_idx"], bf["count"], mask=bf["mask"],
+                     workspace=bf["mws"], stream=st)
         if ev:
-            ev[1].record(stream)
-        b.raymarch_sparse(volh, tf_t, cam_list[k], W, H, mp, ray_idx, count, frame_rgba=frame,
-                          frame_depth=fdepth, sample_count=scount, workspace=sws, stream=stream)
+            ev[1].record(st)
+        b.raymarch_sparse(volh, tf_t, cam_list[k], W, H, mp, bf["ray_idx"], bf["count"],
+                          frame_rgba=bf["frame"], frame_depth=bf["fdepth"], sample_count=scount,
+                          workspace=bf["sws"], stream=st)
         if ev:
-            ev[2].record(stream)
-        net.reconstruct(frame, mask, fdepth, V, W, H, out_rgb, precision=args.precision,
-                        workspace=rws, stream=stream)
+            ev[2].record(st)
+        net.reconstruct(bf["frame"], bf["mask"], bf["fdepth"], V, W, H, bf["out_rgb"],
+                        precision=args.precision, workspace=bf["rws"], stream=st)
         if ev:
-            ev[3].record(stream)
+            ev[3].record(st)
 
     # FP8 scales from one frame of the workload (untimed, before warm-up)
-    b.fovea_mask(fps[0], W, H, V, ray_idx, count, mask=mask, workspace=mws, stream=stream)
-    b.raymarch_sparse(volh, tf_t, cam_list[0], W, H, mp, ray_idx, count, frame_rgba=frame,
-                      frame_depth=fdepth, workspace=sws, stream=stream)
+    b0 = bufs[0]
+    b.fovea_mask(fps[0], W, H, V, b0["ray_idx"], b0["count"], mask=b0["mask"],
+                 workspace=b0["mws"], stream=streams[0])
+    b.raymarch_sparse(volh, tf_t, cam_list[0], W, H, mp, b0["ray_idx"], b0["count"],
+                      frame_rgba=b0["frame"], frame_depth=b0["fdepth"], workspace=b0["sws"],
+                      stream=streams[0])
     if args.precision == "fp8":
         cws = torch.empty(net.workspace_bytes(V, W, H, "bf16"), dtype=torch.uint8, device=dev)
-        net.calibrate(frame, mask, fdepth, V, W, H, workspace=cws, stream=stream)
+        net.calibrate(b0["frame"], b0["mask"], b0["fdepth"], V, W, H, workspace=cws,
+                      stream=streams[0])
         del cws
 
-    def dense(k, ev=None):
+    def dense(k, j=0, ev=None):
+        st, bf = streams[j], bufs[j]
         if ev:
-            ev[0].record(stream)
-        b.raymarch_dense(volh, tf_t, cam_list[k], W, H, mp, dframe, ddepth, sample_count=dcount,
-                         stream=stream)
+            ev[0].record(st)
+        b.raymarch_dense(volh, tf_t, cam_list[k], W, H, mp, bf["dframe"], bf["ddepth"],
+                         sample_count=dcount, stream=st)
         if ev:
-            ev[1].record(stream)
+            ev[1].record(st)
 
-    # warm-up (untimed)
+    def timed(fn, pipelined, evs=None):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            fn(args.warmup + i, i % 2 if pipelined else 0, evs[i] if evs else None)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / args.steps
+
+    # warm-up (untimed), both streams
     for k in range(args.warmup):
-        foveated(k)
-        dense(k)
+        foveated(k, k % 2)
+        dense(k, k % 2)
     torch.cuda.synchronize()
-    scount.zero_()
-    dcount.zero_()
-    counts = []
 
-    # ---- timed: foveated frames
+    # ---- timed: foveated frames, one stream (per-stage times, sample counts)
+    scount.zero_()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        foveated(args.warmup + i, evs[i])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    fov_ms = (t1 - t0) * 1e3 / args.steps
+    seq_ms = timed(foveated, False, evs)
     mask_ms = [e[0].elapsed_time(e[1]) for e in evs]
     sparse_ms = [e[1].elapsed_time(e[2]) for e in evs]
     recon_ms = [e[2].elapsed_time(e[3]) for e in evs]
     sparse_samples = int(scount.item())
     last_k = args.warmup + args.steps - 1
-    fov_out = out_rgb.view(-1, 3).clone()
-    fov_mask = mask.clone()
+    fov_out = bufs[0]["out_rgb"].view(-1, 3).clone()
+    n_rays = int(bufs[0]["count"].item())
+    # ---- timed: foveated frames pipelined over the two streams
+    fov_pipe_ms = timed(foveated, True)
+    fov_ms = seq_ms
 
-    # ---- timed: dense frames (the baseline the method is compared with)
+    # ---- timed: dense frames (the baseline the method is compared with),
+    # one stream (kernel times) and the same two-stream pipelining
+    dcount.zero_()
     devs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        dense(args.warmup + i, devs[i])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    dense_ms = (t1 - t0) * 1e3 / args.steps
+    dense_ms = timed(dense, False, devs)
     dense_kernel_ms = [e[0].elapsed_time(e[1]) for e in devs]
     dense_samples = int(dcount.item())
-    n_rays = int(count.item())
+    dense_pipe_ms = timed(dense, True)
+    dframe = bufs[0]["dframe"]
+    dense(last_k, 0)  # the dense frame of the last foveated frame's view, for PSNR
+    torch.cuda.synchronize()
     # quality: the foveated reconstruction of the last timed frame against the
     # dense march of the same frame (the dense GPU march is the judge; the FP64
     # oracle frame is compared in the CPU-baseline leg)
@@ -233,6 +257,9 @@ def main():
                    "reconstruction": "U-Net 32/48/64/96 + 5x5 KPN, %s" % args.precision},
         "dense_ms_per_frame": round(dense_ms, 4),
         "speedup_vs_dense": round(dense_ms / fov_ms, 3),
+        "pipelined_ms_per_frame": round(fov_pipe_ms, 4),
+        "pipelined_dense_ms_per_frame": round(dense_pipe_ms, 4),
+        "pipelined_speedup_vs_dense": round(dense_pipe_ms / fov_pipe_ms, 3),
         "ray_samples_per_s": round(sparse_samples / (sum(sparse_ms) * 1e-3), 1),
         "dense_ray_samples_per_s": round(dense_samples / (sum(dense_kernel_ms) * 1e-3), 1),
         "sampled_rays_per_frame": n_rays,

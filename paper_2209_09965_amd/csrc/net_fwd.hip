@@ -381,6 +381,13 @@ fv_status launch_conv(const ConvArgs& args, int nb, hipStream_t s) {
                 (long long)(b0 > b1 ? b0 : b1));
   a.src0_bytes = (uint32_t)b0;
   a.src1_bytes = (uint32_t)b1;
+  const int64_t bo = px * a.out_ch * (a.out_fp32 ? 4 : E::kBytes);
+  const int64_t bp = a.pool_out ? (int64_t)a.n * (a.h >> 1) * (a.w >> 1) * a.out_ch * E::kBytes : 0;
+  if (bo >= ((int64_t)1 << 31) - 64)
+    return fail(FV_ERR_UNSUPPORTED, "conv: an output tensor of %lld bytes (limit 2 GiB)",
+                (long long)bo);
+  a.out_bytes = (uint32_t)bo;
+  a.pool_bytes = (uint32_t)bp;
   auto magic = [](uint32_t d) { return d > 1 ? (uint32_t)(((uint64_t)1 << 32) / d + 1) : 0u; };
   if (a.up0 && (a.c0 % 8 || a.c0 < 16 || (a.h | a.w) & 1))
     return fail(FV_ERR_UNSUPPORTED, "conv: upsampled source with %d channels at %d x %d", a.c0,

@@ -69,6 +69,18 @@ struct BF16 {
   }
   // the value as stored and read back
   static __device__ __forceinline__ float rnd(float v) { return bf16_bits_to_f(enc_bits(v)); }
+  // ReLU (when relu) and the range of the stored type
+  static __device__ __forceinline__ float act(float v, int relu) {
+    return relu ? fmaxf(v, 0.0f) : v;
+  }
+  static __device__ __forceinline__ float rnd_act(float v) { return rnd(v); }
+  static __device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, int voff, int soff,
+                                                 const float v[4]) {
+    typedef __attribute__((__vector_size__(2 * sizeof(int)))) int i2;
+    const i2 w = {(int)(enc_bits(v[0]) | (enc_bits(v[1]) << 16)),
+                  (int)(enc_bits(v[2]) | (enc_bits(v[3]) << 16))};
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, voff, soff, 0);
+  }
 };
 
 typedef int i32x8_t __attribute__((ext_vector_type(8)));
@@ -141,6 +153,22 @@ struct FP8 {
   static __device__ __forceinline__ float rnd(float v) {
     return __builtin_amdgcn_cvt_f32_fp8(__builtin_amdgcn_cvt_pk_fp8_f32(sat(v), 0.0f, 0, false), 0);
   }
+  // ReLU (when relu) and saturation to the E4M3 range in one clamp; values
+  // from act() need no further clamp before conversion
+  static __device__ __forceinline__ float act(float v, int relu) {
+    return __builtin_amdgcn_fmed3f(v, relu ? 0.0f : -448.0f, 448.0f);
+  }
+  static __device__ __forceinline__ float rnd_act(float v) {
+    return __builtin_amdgcn_cvt_f32_fp8(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false), 0);
+  }
+  // 4 values from act() packed to E4M3 and stored
+  static __device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, int voff, int soff,
+                                                 const float v[4]) {
+    int w = 0;
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], w, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w, true);
+    __builtin_amdgcn_raw_buffer_store_b32(w, r, voff, soff, 0);
+  }
 };
 
 __device__ __forceinline__ void wave_absmax(float* dst, float m) {
@@ -166,6 +194,7 @@ struct ConvArgs {
   float* absmax;        // per-tensor running maximum (calibration), or null
   uint8_t* pool_out;    // 2x2 average of the stored output (half resolution,
                         // out_ch stride), or null
+  uint32_t out_bytes, pool_bytes;  // set by launch_conv (buffer-store range checks)
   uint32_t src0_bytes, src1_bytes;  // sizes for the buffer-load range checks
   // set by launch_conv: e / ng == umulhi(e, gmagic) for the ng fill-item
   // channel groups copied from memory (0: ng == 1); umagic likewise for the
@@ -531,57 +560,77 @@ __global__ void __launch_bounds__(256)
         }
       }
     }
-    // epilogue: bias, ReLU, (calibration max), one packed store per 4 channels;
-    // with pool_out also the 2x2 average of the stored values (rows rr, rr + 1
-    // of this lane, columns of this lane and its neighbour lane ^ 1), summed in
-    // the order (0,0), (0,1), (1,0), (1,1) like the stand-alone pooling kernel
+    // epilogue: scale, bias, ReLU, one packed store per 4 channels; with
+    // pool_out also the 2x2 average of the stored values (rows rr, rr + 1 of
+    // this lane, columns of this lane and its neighbour lane ^ 1), summed in
+    // the order (0,0), (0,1), (1,0), (1,1) like the stand-alone pooling
+    // kernel.  Stores are buffer stores at a 32-bit offset (outputs < 2 GiB,
+    // checked by the launcher): the lane's offset is computed once, the row
+    // step is uniform; rows below the image are skipped (uniform test) and
+    // columns past it or channels past co get an out-of-range offset, which
+    // drops the store.
+    const int x = x0 + col, yb = y0 + wave * R;
+    const int ob = a.out_fp32 ? 4 : E::kBytes;
+    const int cpad = (a.co + 3) & ~3;
+    const __amdgpu_buffer_rsrc_t ro = make_rsrc(a.out, a.out_bytes);
+    const int rowb = a.w * a.out_ch * ob;
+    const int vo = x < a.w ? (((b * a.h + yb) * a.w + x) * a.out_ch + 4 * grp) * ob : kOutside;
+    const bool pool = R >= 2 && a.pool_out;
+    const __amdgpu_buffer_rsrc_t rp = make_rsrc(a.pool_out ? a.pool_out : a.out, a.pool_bytes);
+    const int prow = (a.w >> 1) * a.out_ch * E::kBytes;
+    const int vp = x < a.w && !(col & 1)
+                       ? (((b * (a.h >> 1) + (yb >> 1)) * (a.w >> 1) + (x >> 1)) * a.out_ch +
+                          4 * grp) * E::kBytes
+                       : kOutside;
     float mx = 0.f;
-    const int x = x0 + col;
-    #pragma unroll
+#pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
-      const int c4 = nb * 16 + 4 * (lane >> 4);
-      if (c4 >= a.co) continue;  // co is a multiple of 8, so c4 + 3 < co here
+      const int c4 = nb * 16 + 4 * grp;
+      const bool cok = c4 < a.co;  // co is a multiple of 8: c4 < co means c4 + 3 < co
+      const int cl = cok ? c4 : 0;
       float al[4], bi[4];
-      #pragma unroll
+#pragma unroll
       for (int i = 0; i < 4; ++i) {
-        al[i] = s_ab[c4 + i];
-        bi[i] = s_ab[((a.co + 3) & ~3) + c4 + i];
+        al[i] = s_ab[cl + i];
+        bi[i] = s_ab[cpad + cl + i];
       }
+      const int vn = cok ? vo + nb * 16 * ob : kOutside;
       float st[R][4];
-      #pragma unroll
+#pragma unroll
       for (int rr = 0; rr < R; ++rr) {
-        const int y = y0 + wave * R + rr;
         float v[4];
-        #pragma unroll
+#pragma unroll
         for (int i = 0; i < 4; ++i) {
           v[i] = fmaf(acc[rr][nb][i], al[i], bi[i]);
-          if (a.relu) v[i] = fmaxf(v[i], 0.0f);
+          if (!a.out_fp32) v[i] = E::act(v[i], a.relu);
           st[rr][i] = v[i];
         }
-        if (y >= a.h || x >= a.w) continue;
-        #pragma unroll
-        for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(v[i]));
-        const int64_t o = (((int64_t)b * a.h + y) * a.w + x) * a.out_ch + c4;
-        if (a.out_fp32)
-          *(float4*)((float*)a.out + o) = make_float4(v[0], v[1], v[2], v[3]);
-        else
-          E::store4(a.out + o * E::kBytes, v);
+        if (yb + rr >= a.h) continue;  // uniform across the wave
+        if (a.absmax && cok && x < a.w)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) mx = fmaxf(mx, fabsf(v[i]));
+        if (a.out_fp32) {
+          typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f4;
+          __builtin_amdgcn_raw_buffer_store_b128(
+              __builtin_bit_cast(__attribute__((__vector_size__(4 * sizeof(int)))) int,
+                                 f4{v[0], v[1], v[2], v[3]}),
+              ro, vn, rr * rowb, 0);
+        } else {
+          E::bstore4(ro, vn, rr * rowb, v);
+        }
       }
-      if (R >= 2 && a.pool_out) {
-        #pragma unroll
+      if (pool) {
+#pragma unroll
         for (int rr = 0; rr + 1 < R; rr += 2) {
-          const int y = y0 + wave * R + rr;
           float pv[4];
-          #pragma unroll
+#pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const float t0 = E::rnd(st[rr][i]), t1 = E::rnd(st[rr + 1][i]);
+            const float t0 = E::rnd_act(st[rr][i]), t1 = E::rnd_act(st[rr + 1][i]);
             const float n0 = __shfl_xor(t0, 1, 64), n1 = __shfl_xor(t1, 1, 64);
             pv[i] = (((t0 + n0) + t1) + n1) * 0.25f;
           }
-          if ((col & 1) || y >= a.h || x >= a.w) continue;
-          const int64_t o =
-              (((int64_t)b * (a.h >> 1) + (y >> 1)) * (a.w >> 1) + (x >> 1)) * a.out_ch + c4;
-          E::store4(a.pool_out + o * E::kBytes, pv);
+          if (yb + rr >= a.h) continue;
+          E::bstore4(rp, cok ? vp + nb * 16 * E::kBytes : kOutside, (rr >> 1) * prow, pv);
         }
       }
     }
