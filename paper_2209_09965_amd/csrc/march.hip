@@ -36,7 +36,6 @@ struct MarchArgs {
   float alpha_stop;
   float light[3];  // normalised, towards the light
   float ka, kd, ks, shininess;
-  int ipow;        // shininess as a small integer, or -1
   float bg[3];
   CamD cam[kMaxViews];
 };
@@ -51,15 +50,11 @@ __device__ __forceinline__ float tri(float v000, float v100, float v010, float v
   return lerpf(lerpf(c00, c10, wy), lerpf(c01, c11, wy), wz);
 }
 
-__device__ __forceinline__ float pow_small(float x, int n, float p) {
-  if (n < 0) return powf(x, p);
-  float r = 1.0f;
-  while (n) {
-    if (n & 1) r *= x;
-    x *= x;
-    n >>= 1;
-  }
-  return r;
+// x^p for x in [0, 1], p >= 0: exp2(p log2 x) with the hardware log/exp
+// (relative error a few 1e-6 at p = 32); x = 0 gives 0 (p > 0) and p = 0
+// gives 1.
+__device__ __forceinline__ float pow01(float x, float p) {
+  return p > 0.0f ? __builtin_amdgcn_exp2f(p * __builtin_amdgcn_logf(x)) : 1.0f;
 }
 
 template <typename VT>
@@ -281,7 +276,7 @@ __device__ __forceinline__ bool composite(const MarchArgs& a, const float4* __re
     const float nx = -gx * inv, ny = -gy * inv, nz = -gz * inv;
     const float ndl = fabsf(nx * a.light[0] + ny * a.light[1] + nz * a.light[2]);
     const float ndh = fabsf(nx * s.hv[0] + ny * s.hv[1] + nz * s.hv[2]);
-    const float spec = a.ks * pow_small(ndh, a.ipow, a.shininess);
+    const float spec = a.ks * pow01(ndh, a.shininess);
     const float diff = a.ka + a.kd * ndl;
     r = r * diff + spec;
     g = g * diff + spec;
@@ -374,7 +369,7 @@ __global__ void k_clear_queue(uint32_t* q) {
 // ray has finished (or missed the box) take the next rays, so long and short
 // rays of the sparse periphery do not leave lanes idle.  Results go to the
 // compact buffers and/or back to their pixels (back-projection).
-constexpr int kStepsPerRefill = 8;
+constexpr int kStepsPerRefill = 6;
 
 template <int DT, bool SHADE>
 __global__ void __launch_bounds__(256) k_march_sparse(
@@ -393,7 +388,7 @@ __global__ void __launch_bounds__(256) k_march_sparse(
   // defined (zero) rather than uninitialised.
   RayState s{};
   s.N = 1;
-  Stencil<DT, SHADE> A{}, B{};
+  Stencil<DT, SHADE> A{}, B{}, C{};
   bool active = false, exhausted = false;
   uint32_t slot = 0, lin = 0;
   uint32_t ns = 0;
@@ -434,16 +429,19 @@ __global__ void __launch_bounds__(256) k_march_sparse(
     // first gathers of the new rays, outside the divergent claim code (so the
     // stencil registers are not copied around it)
     if (__ballot(fresh)) {
-      Stencil<DT, SHADE> F;
-      gather(a, s, 0, F, fresh);
-      select_stencil(fresh, F, A);
+      Stencil<DT, SHADE> F0, F1;
+      gather(a, s, 0, F0, fresh);
+      gather(a, s, min(1, s.N - 1), F1, fresh);
+      select_stencil(fresh, F0, A);
+      select_stencil(fresh, F1, B);
     }
     if (!__ballot(active)) {
       if (!__ballot(!exhausted)) break;
       continue;
     }
-    // pipelined as in march_ray; an even number of steps per round leaves the
-    // next sample's voxels in A, where a newly claimed ray also starts
+    // pipelined two samples ahead (three buffers: the next sample's voxels in
+    // A, the one after in B; a multiple of 3 steps per round restores that,
+    // and a newly claimed ray starts the same way)
     auto finish = [&]() {
       const RayOut o = ray_finish(a, s);
       if (rgba_c) rgba_c[slot] = o.rgba;
@@ -453,15 +451,17 @@ __global__ void __launch_bounds__(256) k_march_sparse(
       ns += o.samples;
       active = false;
     };
-    static_assert(kStepsPerRefill % 2 == 0, "steps per refill round must be even");
+    static_assert(kStepsPerRefill % 3 == 0, "steps per refill round: a multiple of 3");
     // Every lane runs the loop body (idle lanes gather nothing and their
     // state is discarded); only active lanes commit a finished ray.
 #pragma unroll 1
-    for (int it = 0; it < kStepsPerRefill; it += 2) {
-      gather(a, s, min(s.k + 1, s.N - 1), B, active);
+    for (int it = 0; it < kStepsPerRefill; it += 3) {
+      gather(a, s, min(s.k + 2, s.N - 1), C, active);
       if (composite(a, tfs, s, A) && active) finish();
-      gather(a, s, min(s.k + 1, s.N - 1), A, active);
+      gather(a, s, min(s.k + 2, s.N - 1), A, active);
       if (composite(a, tfs, s, B) && active) finish();
+      gather(a, s, min(s.k + 2, s.N - 1), B, active);
+      if (composite(a, tfs, s, C) && active) finish();
     }
   }
   if (nsamp) add_samples(nsamp, ns);
@@ -514,8 +514,8 @@ fv_status fill_args(const fv_volume* v, const float* tf, int tf_n, const fv_came
   a->kd = mp->kd;
   a->ks = mp->ks;
   a->shininess = mp->shininess;
-  const float sh = mp->shininess;
-  a->ipow = (sh >= 0.0f && sh <= 256.0f && sh == std::floor(sh)) ? (int)sh : -1;
+  if (mp->shading && !(mp->shininess >= 0.0f && mp->shininess <= 1024.0f))
+    return fail(FV_ERR_INVALID_ARG, "%s: shininess must be in [0, 1024]", fn);
   for (int i = 0; i < 3; ++i) a->bg[i] = mp->bg[i];
   for (int k = 0; k < views; ++k) {
     const fv_camera& cm = cams[k];

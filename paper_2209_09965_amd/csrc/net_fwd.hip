@@ -347,7 +347,8 @@ __global__ void k_zero_f32(float* p, int n) {
 template <class E, int NB, int R>
 void conv_launch(const ConvArgs& a, hipStream_t s) {
   static bool attr_set = false;
-  const size_t lds = conv_lds_bytes<E, R>(a.cip, a.c0, a.up0, a.kc, NB, a.co, a.b_lds);
+  const size_t lds = conv_lds_bytes<E, R>(a.cip, a.c0, a.up0, a.kc, NB, a.co, a.b_lds) +
+                     (a.fuse0 ? fuse0_lds_bytes<E, R>(a.f_kc) : 0);
   if (!attr_set) {
     hipFuncSetAttribute((const void*)k_conv3x3<E, NB, R>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -415,6 +416,12 @@ fv_status launch_conv(const ConvArgs& args, int nb, hipStream_t s) {
   }
   if (nb >= 7 && R == 4) R = 2;  // 112+ accumulators per lane would spill
   a.b_lds = (size_t)a.kc * nb * 64 * E::kFragBytes <= kMaxLdsWeights && lds_of(R, 1) <= 40 * 1024;
+  if (a.fuse0) {
+    // the fused first layer keeps both layers' weights in LDS
+    if (nb != 2 || a.up0 || a.co != 32 || a.cip != 32)
+      return fail(FV_ERR_UNSUPPORTED, "conv: fused first layer needs a 32 -> 32 conv");
+    a.b_lds = 1;
+  }
   if (a.co % 8 || a.co > 256) return fail(FV_ERR_UNSUPPORTED, "conv: %d output channels", a.co);
   // the fused 2x2 pooling needs both rows of a pair in one wave
   uint8_t* pool_out = a.pool_out;
@@ -473,15 +480,22 @@ fv_status refresh_bf16(fv_net* n, hipStream_t s) {
 template <class E>
 fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const float* frame,
                        const uint8_t* mask, const float* depth, float* out_rgb, float* out_od,
-                       float* out_wk, float* absmax, hipStream_t s) {
+                       float* out_wk, float* absmax, hipStream_t s, bool fuse_first) {
   const bool fp8 = E::kBytes == 1;
   const int64_t npx = (int64_t)p.n * p.h * p.w;
   const float in_inv = fp8 ? 1.0f / net->act_scale[T_IN] : 1.0f;
-  k_pack<E><<<(unsigned)((npx + 255) / 256), 256, 0, s>>>(
-      (const float4*)frame, mask, depth, ws + p.t[T_IN], npx, in_inv, absmax ? absmax + T_IN : nullptr);
-  fv_status st = launch_status("pack");
-  if (st != FV_OK) return st;
+  fv_status st = FV_OK;
+  if (!fuse_first) {
+    k_pack<E><<<(unsigned)((npx + 255) / 256), 256, 0, s>>>(
+        (const float4*)frame, mask, depth, ws + p.t[T_IN], npx, in_inv,
+        absmax ? absmax + T_IN : nullptr);
+    st = launch_status("pack");
+    if (st != FV_OK) return st;
+  }
   for (int l = 0; l < kNumConv; ++l) {
+    // the packed input and the first conv are computed inside the second
+    // conv's blocks (their tensors are not written)
+    if (fuse_first && l == 0) continue;
     const LayerDesc& L = kLayers[l];
     const int* io = kLayerIO[l];
     ConvArgs a{};
@@ -510,6 +524,18 @@ fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const floa
       a.alpha = nullptr;
       a.bias = net->master + param_offset(l) + (int64_t)L.co * L.ci * 9;
     }
+    if (fuse_first && l == 1) {
+      const LayerDesc& L0 = kLayers[0];
+      a.fuse0 = 1;
+      a.f_rgba = (const float4*)frame;
+      a.f_mask = mask;
+      a.f_depth = depth;
+      a.f_inv = in_inv;
+      a.f_wsw = (const uint8_t*)(fp8 ? net->w_fp8[0] : net->w_bf16[0]);
+      a.f_kc = fp8 ? kchunks128_of(L0.ci) : kchunks_of(L0.ci);
+      a.f_alpha = fp8 ? net->alpha_fp8[0] : nullptr;
+      a.f_bias = fp8 ? net->bias_fp8[0] : net->master + param_offset(0) + (int64_t)L0.co * L0.ci * 9;
+    }
     // the encoder's second conv of levels 0-2 also writes the pooled input
     // of the next level
     a.pool_out = l == 1 ? ws + p.t[T_P0] : l == 3 ? ws + p.t[T_P1] : l == 5 ? ws + p.t[T_P2] : nullptr;
@@ -525,10 +551,10 @@ fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const floa
 
 template fv_status forward_impl<BF16>(const fv_net*, const Plan&, uint8_t*, const float*,
                                       const uint8_t*, const float*, float*, float*, float*,
-                                      float*, hipStream_t);
+                                      float*, hipStream_t, bool);
 template fv_status forward_impl<FP8>(const fv_net*, const Plan&, uint8_t*, const float*,
                                      const uint8_t*, const float*, float*, float*, float*, float*,
-                                     hipStream_t);
+                                     hipStream_t, bool);
 
 // FP8 weights: fold the per-input-channel activation scales into the
 // weights, quantise per output channel (E4M3, |q| <= 448), and fold the
@@ -742,9 +768,9 @@ fv_status fv_reconstruct(const fv_net* n, int precision, const float* frame_rgba
   hipStream_t s = (hipStream_t)stream;
   if (precision == FV_PREC_FP8)
     return forward_impl<FP8>(n, p, (uint8_t*)workspace, frame_rgba, mask, frame_depth, out_rgb,
-                             out_direct, nullptr, nullptr, s);
+                             out_direct, nullptr, nullptr, s, true);
   return forward_impl<BF16>(n, p, (uint8_t*)workspace, frame_rgba, mask, frame_depth, out_rgb,
-                            out_direct, nullptr, nullptr, s);
+                            out_direct, nullptr, nullptr, s, true);
 }
 
 fv_status fv_net_calibrate(fv_net* n, const float* frame_rgba, const uint8_t* mask,
@@ -766,7 +792,7 @@ fv_status fv_net_calibrate(fv_net* n, const float* frame_rgba, const uint8_t* ma
   if ((st = launch_status("calibrate: clear")) != FV_OK) return st;
   float* tmp_rgb = (float*)(ws + p.od);  // the O_d slot is free in this pass
   st = forward_impl<BF16>(n, p, ws, frame_rgba, mask, frame_depth, tmp_rgb, nullptr, nullptr,
-                          amax, s);
+                          amax, s, false);
   if (st != FV_OK) return st;
   float host[64];
   st = hip_status(hipMemcpyAsync(host, amax, sizeof host, hipMemcpyDeviceToHost, s),

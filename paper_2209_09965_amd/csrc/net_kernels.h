@@ -74,6 +74,10 @@ struct BF16 {
     return relu ? fmaxf(v, 0.0f) : v;
   }
   static __device__ __forceinline__ float rnd_act(float v) { return rnd(v); }
+  static __device__ __forceinline__ void lstore4(uint8_t* p, const float v[4]) {
+    *(uint2*)p = make_uint2(enc_bits(v[0]) | (enc_bits(v[1]) << 16),
+                            enc_bits(v[2]) | (enc_bits(v[3]) << 16));
+  }
   static __device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, int voff, int soff,
                                                  const float v[4]) {
     typedef __attribute__((__vector_size__(2 * sizeof(int)))) int i2;
@@ -161,6 +165,12 @@ struct FP8 {
   static __device__ __forceinline__ float rnd_act(float v) {
     return __builtin_amdgcn_cvt_f32_fp8(__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false), 0);
   }
+  static __device__ __forceinline__ void lstore4(uint8_t* p, const float v[4]) {
+    int w = 0;
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], w, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w, true);
+    *(int*)p = w;
+  }
   // 4 values from act() packed to E4M3 and stored
   static __device__ __forceinline__ void bstore4(__amdgpu_buffer_rsrc_t r, int voff, int soff,
                                                  const float v[4]) {
@@ -203,6 +213,21 @@ struct ConvArgs {
   uint32_t umagic8;  // same for the c0 / 8 groups of the upsampling pass
   int wide;   // set by launch_conv: fill items of 16 channels (FP8) instead of 8
   int b_lds;  // set by launch_conv: the weight fragments are staged in LDS
+  // Fused first layer (inference, 2 output blocks, b_lds): the patch of this
+  // conv is computed in the block from the frame instead of read from src0:
+  // the packed input [M rgb, M, M depth / 2] (times f_inv, the input tensor's
+  // inverse scale; zero outside the image), then a 3x3 conv of its 8 (5 used)
+  // channels to co0 = 32 channels with scale/bias f_alpha/f_bias and ReLU,
+  // zero outside the image (the padding of this conv).
+  int fuse0;
+  const float4* f_rgba;
+  const uint8_t* f_mask;
+  const float* f_depth;
+  float f_inv;
+  const uint8_t* f_wsw;  // the first layer's weight fragments
+  int f_kc;
+  const float* f_alpha;  // or null (= 1)
+  const float* f_bias;
 };
 
 template <class E>
@@ -276,6 +301,154 @@ __host__ __device__ inline size_t conv_lds_bytes(int cip, int c0, int up0, int k
 // LDS.  With the weights as the A operand each lane's accumulator holds 4
 // consecutive channels of one pixel, so the epilogue writes them straight to
 // global memory as one packed store.
+// Extra LDS of a fused first layer (after the regular regions): the packed
+// input patch (4 R + 4) x 20 pixels x 8 channels, its K-chunk table, scale
+// and bias of 32 channels, and its weight fragments (2 output blocks).
+template <class E, int R>
+__host__ __device__ inline size_t fuse0_lds_bytes(int f_kc) {
+  return (size_t)(4 * R + 4) * 20 * 8 * E::kBytes + (size_t)16 * E::kSub * f_kc + 2 * 4 * 32 +
+         (size_t)f_kc * 2 * 64 * E::kFragBytes;
+}
+
+// Fused first layer (see ConvArgs::fuse0): fills the block's patch (output
+// tile + 1-pixel halo, 32 channels, stride S) by computing the first conv on
+// it.  Also stages this conv's K-chunk table, scale/bias and weights (the
+// regular fill does that otherwise) and ends with every LDS region written
+// (the caller synchronises before its K loop).
+template <class E, int R>
+__device__ __forceinline__ void fuse0_fill(const ConvArgs& a, uint8_t* smem, int S, int* ktab,
+                                        float* s_ab, uint8_t* wsm, int b, int y0, int x0) {
+  constexpr int PR = 4 * R + 2, PC = 18;       // this conv's patch
+  constexpr int IR = 4 * R + 4, IC = 20;       // the packed-input patch
+  constexpr int NBLK = (PR * PC + 15) / 16;    // 16-pixel blocks of the patch
+  constexpr int kOutside = (int)0x80000000u;
+  typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i4;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 15, grp = lane >> 4;
+  const int cpad = (a.co + 3) & ~3;
+  uint8_t* in = smem + conv_lds_bytes<E, R>(a.cip, a.c0, 0, a.kc, 2, a.co, 1);
+  int* ktab0 = (int*)(in + (size_t)IR * IC * 8 * E::kBytes);
+  float* s_ab0 = (float*)(ktab0 + 4 * E::kSub * a.f_kc);
+  uint8_t* wsm0 = (uint8_t*)(s_ab0 + 64);
+  // 1. loads: packed-input pixels (at most 2 per thread), both layers' weights
+  // and scale/bias
+  float4 px_c[2];
+  uint32_t px_m[2];
+  float px_d[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int i = tid + u * 256;
+    px_m[u] = 0;
+    if (i < IR * IC) {
+      const int r = i / IC, c = i - r * IC;
+      const int y = y0 - 2 + r, x = x0 - 2 + c;
+      if (y >= 0 && y < a.h && x >= 0 && x < a.w) {
+        const int64_t p = ((int64_t)b * a.h + y) * a.w + x;
+        px_m[u] = a.f_mask[p];
+        px_c[u] = a.f_rgba[p];
+        px_d[u] = a.f_depth ? a.f_depth[p] : 0.0f;
+      }
+    }
+  }
+  const int n16 = a.kc * 2 * 64 * E::kFragBytes / 16;
+  const int n16f = a.f_kc * 2 * 64 * E::kFragBytes / 16;
+  const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.wsw, (uint32_t)n16 * 16);
+  const __amdgpu_buffer_rsrc_t rw0 = make_rsrc(a.f_wsw, (uint32_t)n16f * 16);
+  for (int base = tid; base < n16 + n16f; base += 256 * 4) {
+    i4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = base + u * 256;
+      if (e < n16)
+        v[u] = __builtin_bit_cast(i4, __builtin_amdgcn_raw_buffer_load_b128(rw, e * 16, 0, 0));
+      else if (e < n16 + n16f)
+        v[u] = __builtin_bit_cast(
+            i4, __builtin_amdgcn_raw_buffer_load_b128(rw0, (e - n16) * 16, 0, 0));
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = base + u * 256;
+      if (e < n16)
+        *(i4*)(wsm + (size_t)e * 16) = v[u];
+      else if (e < n16 + n16f)
+        *(i4*)(wsm0 + (size_t)(e - n16) * 16) = v[u];
+    }
+  }
+  if (tid < 64) {
+    const int c = tid & 31;
+    const bool is_bias = tid >= 32;
+    const float* src = is_bias ? a.f_bias : a.f_alpha;
+    s_ab0[tid] = src ? src[c] : (is_bias ? 0.0f : 1.0f);
+  } else if (tid < 64 + 2 * a.co) {
+    const int e = tid - 64;
+    const float* src = e < a.co ? a.alpha : a.bias;
+    s_ab[e < a.co ? e : cpad + e - a.co] =
+        src ? src[e < a.co ? e : e - a.co] : (e < a.co ? 1.0f : 0.0f);
+  }
+  // K-chunk tables: this conv's (patch stride S, 18 wide) and the first
+  // layer's (packed-input stride 8, 20 wide)
+  for (int e = tid; e < 4 * E::kSub * a.kc; e += 256) {
+    const int k = e * 8, tap = k / a.cip, ch = k - tap * a.cip;
+    const int ky = tap / 3, kx = tap - 3 * ky;
+    ktab[e] = tap < 9 ? ((ky * PC + kx) * S + ch) * E::kBytes : 0;
+  }
+  for (int e = tid; e < 4 * E::kSub * a.f_kc; e += 256) {
+    const int tap = e;  // 8 input channels: one tap per 8 K positions
+    const int ky = tap / 3, kx = tap - 3 * ky;
+    ktab0[e] = tap < 9 ? (ky * IC + kx) * 8 * E::kBytes : 0;
+  }
+  // 2. packed input -> LDS (the k_pack arithmetic: values times f_inv)
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int i = tid + u * 256;
+    if (i >= IR * IC) continue;
+    float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (px_m[u]) {
+      v[0] = px_c[u].x;
+      v[1] = px_c[u].y;
+      v[2] = px_c[u].z;
+      v[3] = 1.0f;
+      v[4] = 0.5f * px_d[u];
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] *= a.f_inv;
+    E::store8(in + (size_t)i * 8 * E::kBytes, v);
+  }
+  __syncthreads();
+  // 3. the first conv on the patch pixels, 16 consecutive patch pixels per
+  // MFMA column block; ReLU'd, stored in the patch (zero outside the image)
+  for (int blk = wave; blk < NBLK; blk += 4) {
+    const int p = blk * 16 + col;
+    const int pc = p < PR * PC ? p : 0;
+    const int r = pc / PC, c = pc - r * PC;
+    const uint8_t* pin = in + (size_t)(r * IC + c) * 8 * E::kBytes;
+    f32x4_t acc[2] = {f32x4_t{0.f, 0.f, 0.f, 0.f}, f32x4_t{0.f, 0.f, 0.f, 0.f}};
+    for (int ch = 0; ch < a.f_kc; ++ch) {
+      typename E::Frag af, bf[2];
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb)
+        bf[nb] = E::frag(wsm0 + lane * E::kFragBytes + (ch * 2 + nb) * 64 * E::kFragBytes);
+      if constexpr (E::kSub == 1)
+        af = E::frag(pin + ktab0[4 * ch + grp]);
+      else
+        af = E::frag4(pin, ((const int4*)ktab0)[4 * ch + grp]);
+#pragma unroll
+      for (int nb = 0; nb < 2; ++nb) acc[nb] = E::mma(bf[nb], af, acc[nb]);
+    }
+    const int y = y0 - 1 + r, x = x0 - 1 + c;
+    const bool inside = p < PR * PC && y >= 0 && y < a.h && x >= 0 && x < a.w;
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+      const int c4 = nb * 16 + 4 * grp;
+      float v[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        v[i] = inside ? E::act(fmaf(acc[nb][i], s_ab0[c4 + i], s_ab0[32 + c4 + i]), 1) : 0.0f;
+      if (p < PR * PC) E::lstore4(smem + ((size_t)pc * S + c4) * E::kBytes, v);
+    }
+  }
+}
+
 // Occupancy target (waves per SIMD) for the register allocator, out of 512
 // registers: the accumulators (4 NB R) plus about 80 (FP8) or 96 (BF16,
 // double-buffered operands) for the rest; at 5 or more N blocks the weight
@@ -371,6 +544,11 @@ __global__ void __launch_bounds__(256)
       if (IW == 16) *(uint2*)(dst + 8) = make_uint2(v.z, v.w);
     }
   };
+  bool fused = false;
+  if constexpr (NB == 2) fused = a.fuse0;
+  if (fused) {
+    if constexpr (NB == 2) fuse0_fill<E, R>(a, smem, S, ktab, s_ab, wsm, b, y0, x0);
+  } else {
   // 1. every global load up front: patch items, weight fragments, scale/bias
   Item pf[kPF];
 #pragma unroll
@@ -484,6 +662,7 @@ __global__ void __launch_bounds__(256)
         }
       }
     }
+  }
   }
   __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;

@@ -18,7 +18,7 @@ namespace net {
 template <class E>
 fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const float* frame,
                        const uint8_t* mask, const float* depth, float* out_rgb, float* out_od,
-                       float* out_wk, float* absmax, hipStream_t s);
+                       float* out_wk, float* absmax, hipStream_t s, bool fuse_first);
 fv_status refresh_bf16(fv_net* n, hipStream_t s);
 fv_status check_frame(int views, int W, int H, const char* fn);
 
@@ -617,7 +617,7 @@ fv_status fv_net_forward_train(fv_net* n, const float* frame_rgba, const uint8_t
   uint8_t* ws = (uint8_t*)workspace;
   return forward_impl<BF16>(n, tp.f, ws, frame_rgba, mask, frame_depth, out_rgb,
                             (float*)(ws + tp.f.od), (float*)(ws + tp.f.wk), nullptr,
-                            (hipStream_t)stream);
+                            (hipStream_t)stream, false);
 }
 
 fv_status fv_net_loss(const fv_net* n, const float* out_rgb, const float* target_rgba, int batch,

@@ -145,6 +145,29 @@ def test_forward_tiling_invariant(prec, dev):
     net.close()
 
 
+@pytest.mark.parametrize("views,H,W", [(1, 256, 256), (1, 40, 56)])
+def test_fused_first_layer_bit_exact(views, H, W, dev):
+    """Inference computes the packed input and the first conv inside the
+    second conv's blocks; the training forward runs them as separate kernels
+    through HBM.  Same arithmetic per pixel: the outputs must be equal bit for
+    bit (BF16)."""
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(31)
+    theta = _theta(6)
+    rgba, mask, depth = _frame(rng, views, H, W)
+    net = b.Net(theta)
+    fused, _ = _gpu(net, rgba, mask, depth, views, H, W, "bf16", dev)
+    ws = torch.empty(net.train_workspace_bytes(views, W, H), dtype=torch.uint8, device=dev)
+    out = torch.full((views * H * W * 3,), float("nan"), device=dev)
+    net.forward_train(torch.from_numpy(rgba).reshape(-1).to(dev), torch.from_numpy(mask).to(dev),
+                      torch.from_numpy(depth).to(dev), views, W, H, out, ws)
+    torch.cuda.synchronize()
+    sep = out.cpu().numpy().reshape(views, H, W, 3).transpose(0, 3, 1, 2)
+    assert np.isfinite(fused).all()
+    assert np.array_equal(fused, sep), np.abs(fused - sep).max()
+    net.close()
+
+
 def test_fp8_forward_error_stated(dev):
     from paper_2209_09965_amd import binding as b
     rng = np.random.default_rng(11)
