@@ -369,7 +369,7 @@ __global__ void k_clear_queue(uint32_t* q) {
 // ray has finished (or missed the box) take the next rays, so long and short
 // rays of the sparse periphery do not leave lanes idle.  Results go to the
 // compact buffers and/or back to their pixels (back-projection).
-constexpr int kStepsPerRefill = 6;
+constexpr int kStepsPerRefill = 8;
 
 template <int DT, bool SHADE>
 __global__ void __launch_bounds__(256) k_march_sparse(
@@ -388,7 +388,7 @@ __global__ void __launch_bounds__(256) k_march_sparse(
   // defined (zero) rather than uninitialised.
   RayState s{};
   s.N = 1;
-  Stencil<DT, SHADE> A{}, B{}, C{};
+  Stencil<DT, SHADE> A{}, B{}, C{}, D{};
   bool active = false, exhausted = false;
   uint32_t slot = 0, lin = 0;
   uint32_t ns = 0;
@@ -429,11 +429,13 @@ __global__ void __launch_bounds__(256) k_march_sparse(
     // first gathers of the new rays, outside the divergent claim code (so the
     // stencil registers are not copied around it)
     if (__ballot(fresh)) {
-      Stencil<DT, SHADE> F0, F1;
+      Stencil<DT, SHADE> F0, F1, F2;
       gather(a, s, 0, F0, fresh);
       gather(a, s, min(1, s.N - 1), F1, fresh);
+      gather(a, s, min(2, s.N - 1), F2, fresh);
       select_stencil(fresh, F0, A);
       select_stencil(fresh, F1, B);
+      select_stencil(fresh, F2, C);
     }
     if (!__ballot(active)) {
       if (!__ballot(!exhausted)) break;
@@ -451,17 +453,19 @@ __global__ void __launch_bounds__(256) k_march_sparse(
       ns += o.samples;
       active = false;
     };
-    static_assert(kStepsPerRefill % 3 == 0, "steps per refill round: a multiple of 3");
+    static_assert(kStepsPerRefill % 4 == 0, "steps per refill round: a multiple of 4");
     // Every lane runs the loop body (idle lanes gather nothing and their
     // state is discarded); only active lanes commit a finished ray.
 #pragma unroll 1
-    for (int it = 0; it < kStepsPerRefill; it += 3) {
-      gather(a, s, min(s.k + 2, s.N - 1), C, active);
+    for (int it = 0; it < kStepsPerRefill; it += 4) {
+      gather(a, s, min(s.k + 3, s.N - 1), D, active);
       if (composite(a, tfs, s, A) && active) finish();
-      gather(a, s, min(s.k + 2, s.N - 1), A, active);
+      gather(a, s, min(s.k + 3, s.N - 1), A, active);
       if (composite(a, tfs, s, B) && active) finish();
-      gather(a, s, min(s.k + 2, s.N - 1), B, active);
+      gather(a, s, min(s.k + 3, s.N - 1), B, active);
       if (composite(a, tfs, s, C) && active) finish();
+      gather(a, s, min(s.k + 3, s.N - 1), C, active);
+      if (composite(a, tfs, s, D) && active) finish();
     }
   }
   if (nsamp) add_samples(nsamp, ns);
