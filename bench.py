@@ -51,6 +51,10 @@ def parse():
                     help="only run a plain device copy of this many bytes (counter reference)")
     ap.add_argument("--net-crop", type=int, default=256,
                     help="side of the crop the CPU oracle network runs on (scaled to the frame)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="compression-efficiency sweep instead of the frame benchmark: "
+                         "stream compaction vs naive rejection vs the ideal rate")
+    ap.add_argument("--sweep-frames", type=int, default=12)
     return ap.parse_args()
 
 
@@ -80,6 +84,109 @@ def copy_reference(nbytes):
     print(json.dumps({"copy_reference_bytes": nbytes, "launches": 5}), flush=True)
 
 
+SWEEP_RATES = (1.0, 0.7, 0.5, 0.3, 0.2, 0.1, 0.05, 0.03, 0.02, 0.01, 0.005)
+
+
+def compression_sweep(args):
+    """Effective compression rate (paper Sec. 4, stream compaction vs naive
+    rejection): for sample maps of decreasing density, the dense march time
+    divided by the time of (a) sample map + compaction + sparse march and
+    (b) sample map + the full-frame launch that skips unsampled pixels, beside
+    the ideal rate 1/C for the sampled fraction C.  The density is swept with
+    a uniform floor p (fovea fall-off of half a pixel, so tau = p almost
+    everywhere), plus the foveated map of the frame benchmark.  Times are HIP
+    events on one stream, averaged over frames of the camera orbit."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_2209_09965_amd import binding as b
+
+    dev = torch.device("cuda:0")
+    wl = synthetic.WORKLOADS[args.workload]
+    W, H, V = wl["width"], wl["height"], wl["views"]
+    if V != 1:
+        sys.exit("the sweep runs single-view workloads")
+    vol, tf = make_inputs(wl)
+    mp = synthetic.march_params(shading=wl["shading"])
+    vol_t = torch.from_numpy(vol).to(dev)
+    volh = b.Volume(vol_t)
+    del vol_t
+    tf_t = torch.from_numpy(tf).reshape(-1).to(dev)
+    total = W * H
+    ray_idx = torch.empty(total, dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    mask = torch.empty(total, dtype=torch.uint8, device=dev)
+    mws = torch.empty(b.fovea_mask_workspace(W, H, V), dtype=torch.uint8, device=dev)
+    sws = torch.empty(b.raymarch_sparse_workspace(total), dtype=torch.uint8, device=dev)
+    frame = torch.zeros(total * 4, dtype=torch.float32, device=dev)
+    fdepth = torch.zeros(total, dtype=torch.float32, device=dev)
+    nf = args.sweep_frames
+    cams = [[synthetic.orbit_camera(k * 60 // nf)] for k in range(nf)]
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def run(fn, reps=2):
+        """fn(k) for every frame (one untimed pass first); mean ms per frame."""
+        for k in range(nf):
+            fn(k)
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            for k in range(nf):
+                e0, e1 = ev(), ev()
+                e0.record()
+                fn(k)
+                e1.record()
+                t.append((e0, e1))
+        torch.cuda.synchronize()
+        return sum(a.elapsed_time(c) for a, c in t) / len(t)
+
+    t_dense = run(lambda k: b.raymarch_dense(volh, tf_t, cams[k], W, H, mp, frame, fdepth))
+    rows = []
+    points = [("uniform", dict(sigma_px=0.5, p_floor=p)) for p in SWEEP_RATES]
+    points.append(("fovea", dict(sigma_px=wl.get("sigma_frac", 0.15) * H, p_floor=0.05)))
+    for kind, fpar in points:
+        fps = []
+        for k in range(nf):
+            fp = synthetic.fovea_params(W, H, frame=k)
+            fp.update(fpar)
+            fps.append(fp)
+
+        def do_mask(k):
+            b.fovea_mask(fps[k], W, H, V, ray_idx, count, mask=mask, workspace=mws)
+
+        def do_sparse(k):
+            b.raymarch_sparse(volh, tf_t, cams[k], W, H, mp, ray_idx, count, frame_rgba=frame,
+                              frame_depth=fdepth, workspace=sws)
+
+        def do_naive(k):
+            b.raymarch_masked(volh, tf_t, cams[k], W, H, mp, mask, frame, fdepth)
+
+        t_mask = run(do_mask)
+        t_sparse = run(lambda k: (do_mask(k), do_sparse(k))) - t_mask
+        t_naive = run(lambda k: (do_mask(k), do_naive(k))) - t_mask
+        frac = []
+        for k in range(nf):
+            do_mask(k)
+            torch.cuda.synchronize()
+            frac.append(int(count.item()) / total)
+        c = sum(frac) / len(frac)
+        rows.append(dict(
+            map=kind, p_floor=fpar["p_floor"], sigma_px=round(fpar["sigma_px"], 3),
+            sampled_fraction=round(c, 5), ideal_rate=round(1.0 / c, 2),
+            mask_ms=round(t_mask, 4), compaction_march_ms=round(t_sparse, 4),
+            naive_march_ms=round(t_naive, 4),
+            rate_compaction=round(t_dense / (t_mask + t_sparse), 3),
+            rate_naive=round(t_dense / (t_mask + t_naive), 3),
+            rate_compaction_march_only=round(t_dense / t_sparse, 3),
+            rate_naive_march_only=round(t_dense / t_naive, 3)))
+        print(json.dumps(rows[-1]), flush=True)
+    print(json.dumps({"sweep": "compression efficiency", "workload": args.workload,
+                      "dense_ms": round(t_dense, 4), "frames": nf, "rows": rows}), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_ref:
@@ -90,6 +197,9 @@ def main():
               "(the sharding design is described in DESIGN.md); run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
+    if args.sweep:
+        compression_sweep(args)
+        return
     import numpy as np
     import torch
 
@@ -127,7 +237,7 @@ def main():
             count=torch.zeros(1, dtype=torch.int32, device=dev),
             mask=torch.empty(total, dtype=torch.uint8, device=dev),
             mws=torch.empty(b.fovea_mask_workspace(W, H, V), dtype=torch.uint8, device=dev),
-            sws=torch.empty(b.raymarch_sparse_workspace(), dtype=torch.uint8, device=dev),
+            sws=torch.empty(b.raymarch_sparse_workspace(total), dtype=torch.uint8, device=dev),
             frame=torch.zeros(total * 4, dtype=torch.float32, device=dev),
             fdepth=torch.zeros(total, dtype=torch.float32, device=dev),
             out_rgb=torch.empty(total * 3, dtype=torch.float32, device=dev),

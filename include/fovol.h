@@ -227,8 +227,29 @@ fv_status fv_raymarch_dense(const fv_volume* v, const float* tf_rgba, int tf_n,
                             float* frame_rgba, float* frame_depth,
                             uint64_t* sample_count, void* stream);
 
-/* Bytes of device workspace fv_raymarch_sparse needs. */
-fv_status fv_raymarch_sparse_workspace(size_t* bytes);
+/* Naive rejection (paper Sec. 3.1.5, the alternative to stream compaction):
+ * the full-frame launch of fv_raymarch_dense, in which the thread of a pixel
+ * whose sample-map entry is 0 returns at once and the others march their ray
+ * exactly as fv_raymarch_dense does (the same results, bit for bit).  It is
+ * the baseline that stream compaction is measured against: a wave runs as
+ * long as its slowest sampled pixel however few of its pixels are sampled.
+ *   mask         dev uint8 [views*H*W], nonzero = march this pixel (the
+ *                layout fv_fovea_mask writes)
+ *   frame_rgba, frame_depth, sample_count  as fv_raymarch_dense; pixels with
+ *                mask 0 are left untouched
+ * Errors: as fv_raymarch_dense, plus a null mask. */
+fv_status fv_raymarch_masked(const fv_volume* v, const float* tf_rgba,
+                             int tf_n, const fv_camera* cams, int views,
+                             int width, int height, const fv_march_params* mp,
+                             const uint8_t* mask, float* frame_rgba,
+                             float* frame_depth, uint64_t* sample_count,
+                             void* stream);
+
+/* Bytes of device workspace fv_raymarch_sparse needs for a list of up to
+ * `capacity` rays: a claim counter and the per-ray set-up (the camera ray's
+ * box entry, sample step and segment count, 88 bytes a ray), which a first
+ * kernel computes once per listed ray.  Errors: null bytes, capacity 0. */
+fv_status fv_raymarch_sparse_workspace(uint32_t capacity, size_t* bytes);
 
 /* Sparse march over the compacted list written by fv_fovea_mask.  `count`
  * is read on the device (no host synchronisation).  For i < *count the ray
@@ -238,7 +259,8 @@ fv_status fv_raymarch_sparse_workspace(size_t* bytes);
  * (back-projection).  Frame pixels not in the list are left untouched: clear
  * the frame first to get the sparse image.  Entries of ray_idx must be
  * < views*W*H (they are checked on the device; a bad entry is skipped).
- *   workspace  dev, >= fv_raymarch_sparse_workspace() bytes, 256-byte aligned
+ *   workspace  dev, >= fv_raymarch_sparse_workspace(capacity) bytes,
+ *              256-byte aligned
  * Errors: as fv_raymarch_dense, plus null ray_idx/count/workspace, capacity
  * == 0 or > views*W*H, and all four outputs NULL. */
 fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba,

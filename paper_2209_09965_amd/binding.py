@@ -70,7 +70,9 @@ _SIGS = {
     "fv_volume_destroy": (_i, [_vp]),
     "fv_raymarch_dense": (_i, [_vp, _vp, _i, ctypes.POINTER(Camera), _i, _i, _i,
                                ctypes.POINTER(MarchParams), _vp, _vp, _vp, _vp]),
-    "fv_raymarch_sparse_workspace": (_i, [ctypes.POINTER(_sz)]),
+    "fv_raymarch_masked": (_i, [_vp, _vp, _i, ctypes.POINTER(Camera), _i, _i, _i,
+                                ctypes.POINTER(MarchParams), _vp, _vp, _vp, _vp, _vp]),
+    "fv_raymarch_sparse_workspace": (_i, [_u32, ctypes.POINTER(_sz)]),
     "fv_raymarch_sparse": (_i, [_vp, _vp, _i, ctypes.POINTER(Camera), _i, _i, _i,
                                 ctypes.POINTER(MarchParams), _vp, _vp, _u32, _vp, _vp, _vp, _vp,
                                 _vp, _vp, _sz, _vp]),
@@ -223,9 +225,20 @@ def raymarch_dense(vol, tf, cams, width, height, mp, frame_rgba, frame_depth=Non
                                  _ptr(frame_depth), _ptr(sample_count), _stream(stream)))
 
 
-def raymarch_sparse_workspace():
+def raymarch_masked(vol, tf, cams, width, height, mp, mask, frame_rgba, frame_depth=None,
+                    sample_count=None, stream=None):
+    """Naive rejection: the full-frame march where pixels with mask 0 return at once."""
+    arr = _cams(cams)
+    check(_lib.fv_raymarch_masked(vol.handle, _ptr(tf), tf.numel() // 4, arr, len(cams), width,
+                                  height, ctypes.byref(march_params(mp)), _ptr(mask),
+                                  _ptr(frame_rgba), _ptr(frame_depth), _ptr(sample_count),
+                                  _stream(stream)))
+
+
+def raymarch_sparse_workspace(capacity):
+    """Workspace bytes of fv_raymarch_sparse for a list of up to `capacity` rays."""
     b = _sz()
-    check(_lib.fv_raymarch_sparse_workspace(ctypes.byref(b)))
+    check(_lib.fv_raymarch_sparse_workspace(capacity, ctypes.byref(b)))
     return b.value
 
 
@@ -233,11 +246,11 @@ def raymarch_sparse(vol, tf, cams, width, height, mp, ray_idx, count, rgba_compa
                     depth_compact=None, frame_rgba=None, frame_depth=None, sample_count=None,
                     workspace=None, stream=None, capacity=None):
     """March the compacted list (ray_idx, count) and back-project to the frame."""
+    cap = ray_idx.numel() if capacity is None else capacity
     if workspace is None:
-        workspace = torch.empty(raymarch_sparse_workspace(), dtype=torch.uint8,
+        workspace = torch.empty(raymarch_sparse_workspace(cap), dtype=torch.uint8,
                                 device=ray_idx.device)
     arr = _cams(cams)
-    cap = ray_idx.numel() if capacity is None else capacity
     check(_lib.fv_raymarch_sparse(vol.handle, _ptr(tf), tf.numel() // 4, arr, len(cams), width,
                                   height, ctypes.byref(march_params(mp)), _ptr(ray_idx),
                                   _ptr(count), cap, _ptr(rgba_compact), _ptr(depth_compact),

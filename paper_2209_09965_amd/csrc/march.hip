@@ -338,8 +338,11 @@ __device__ __forceinline__ void add_samples(unsigned long long* nsamp, uint32_t 
 }
 
 // Dense: a 256-thread block covers a 16x16 pixel block as four 8x8 wave tiles.
+// With a sample map (naive rejection), a thread whose pixel is not sampled
+// returns at once; the others march as in the dense frame.
 template <int DT, bool SHADE>
-__global__ void __launch_bounds__(256) k_march_dense(MarchArgs a, float4* __restrict__ rgba,
+__global__ void __launch_bounds__(256) k_march_dense(MarchArgs a, const uint8_t* __restrict__ mask,
+                                                     float4* __restrict__ rgba,
                                                      float* __restrict__ depth,
                                                      unsigned long long* __restrict__ nsamp) {
   __shared__ float4 tfs[FV_TF_ENTRIES];
@@ -349,10 +352,10 @@ __global__ void __launch_bounds__(256) k_march_dense(MarchArgs a, float4* __rest
   const int x = blockIdx.x * 16 + (wave & 1) * 8 + (lane & 7);
   const int y = blockIdx.y * 16 + (wave >> 1) * 8 + (lane >> 3);
   const int view = blockIdx.z;
+  const uint32_t lin = (uint32_t)view * (uint32_t)a.W * (uint32_t)a.H + (uint32_t)y * a.W + x;
   uint32_t ns = 0;
-  if (x < a.W && y < a.H) {
+  if (x < a.W && y < a.H && (!mask || mask[lin])) {
     const RayOut r = march_ray<DT, SHADE>(a, tfs, view, x, y);
-    const uint32_t lin = (uint32_t)view * (uint32_t)a.W * (uint32_t)a.H + (uint32_t)y * a.W + x;
     rgba[lin] = r.rgba;
     if (depth) depth[lin] = r.depth;
     ns = r.samples;
@@ -360,43 +363,120 @@ __global__ void __launch_bounds__(256) k_march_dense(MarchArgs a, float4* __rest
   if (nsamp) add_samples(nsamp, ns);
 }
 
-__global__ void k_clear_queue(uint32_t* q) {
-  if (threadIdx.x == 0) q[0] = 0u;
+// Ray set-up of the compacted list, done once per listed ray by a kernel of
+// its own, so the march kernel's claim step only loads the state (the FP64
+// set-up and its temporaries stay out of the march loop's registers).  One
+// record per list slot, structure of arrays in the sparse workspace.
+struct SetupList {
+  double* q[7];  // q0 x y z, qs x y z, klast
+  float* f[7];   // t0, tstep, tlast, last_len, half vector x y z
+  int* n;        // segments N >= 1, 0 for a miss, -1 for an invalid list entry
+};
+
+constexpr int kSetupDoubles = 7, kSetupFloats = 7;
+
+__host__ __device__ inline size_t setup_stride(uint32_t capacity, size_t elem) {
+  return ((size_t)capacity * elem + 255) & ~(size_t)255;
+}
+
+inline size_t sparse_workspace_bytes(uint32_t capacity) {
+  return 256 + kSetupDoubles * setup_stride(capacity, 8) +
+         (kSetupFloats + 1) * setup_stride(capacity, 4);
+}
+
+inline SetupList setup_list(void* ws, uint32_t capacity) {
+  SetupList l;
+  char* p = (char*)ws + 256;
+  for (int i = 0; i < kSetupDoubles; ++i, p += setup_stride(capacity, 8)) l.q[i] = (double*)p;
+  for (int i = 0; i < kSetupFloats; ++i, p += setup_stride(capacity, 4)) l.f[i] = (float*)p;
+  l.n = (int*)p;
+  return l;
+}
+
+template <bool SHADE>
+__global__ void __launch_bounds__(256) k_setup_list(MarchArgs a,
+                                                    const uint32_t* __restrict__ ray_idx,
+                                                    const uint32_t* __restrict__ count,
+                                                    uint32_t capacity, SetupList l,
+                                                    uint32_t* __restrict__ queue) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i == 0) queue[0] = 0u;  // the march kernel's claim counter
+  if (i >= min(*count, capacity)) return;
+  const uint32_t lin = ray_idx[i];
+  if (lin >= a.total) {
+    l.n[i] = -1;
+    return;
+  }
+  const uint32_t wh = (uint32_t)a.W * (uint32_t)a.H;
+  const int view = (int)(lin / wh);
+  const uint32_t rem = lin - (uint32_t)view * wh;
+  const int y = (int)(rem / (uint32_t)a.W), x = (int)(rem - (uint32_t)y * a.W);
+  RayState s;
+  // a zero-length ray inside the box finishes with the same output as a miss
+  if (!ray_setup<SHADE>(a, view, x, y, s) || s.N <= 0) {
+    l.n[i] = 0;
+    return;
+  }
+  for (int j = 0; j < 3; ++j) {
+    l.q[j][i] = s.q0[j];
+    l.q[3 + j][i] = s.qs[j];
+  }
+  l.q[6][i] = s.klast;
+  l.f[0][i] = s.t0;
+  l.f[1][i] = s.tstep;
+  l.f[2][i] = s.tlast;
+  l.f[3][i] = s.last_len;
+  for (int j = 0; j < 3; ++j) l.f[4 + j][i] = SHADE ? s.hv[j] : 0.0f;
+  l.n[i] = s.N;
 }
 
 // Sparse, persistent: every wave claims rays from a global queue (one atomic
-// per refill round) in list order; every kStepsPerRefill segments, lanes whose
-// ray has finished (or missed the box) take the next rays, so long and short
-// rays of the sparse periphery do not leave lanes idle.  Results go to the
-// compact buffers and/or back to their pixels (back-projection).
-constexpr int kStepsPerRefill = 8;
+// per claim) in list order.  Every kStepsPerRefill segments, once at least
+// kRefillMin lanes are idle (their ray finished or missed the box), those
+// lanes take the next rays of the list: long and short rays of the sparse
+// periphery do not leave lanes idle for long, and a wave's lanes stay on
+// neighbouring pixels (one claim takes consecutive list entries).  Results
+// go to the compact buffers and/or back to their pixels (back-projection).
+// The loop is software-pipelined kSparseAhead samples ahead: each lane keeps
+// the voxels of its next kSparseAhead samples in flight.
+constexpr int kStepsPerRefill = 9;
+constexpr int kRefillMin = 32;
+constexpr int kSparseAhead = 2;
 
 template <int DT, bool SHADE>
 __global__ void __launch_bounds__(256) k_march_sparse(
     MarchArgs a, const uint32_t* __restrict__ ray_idx, const uint32_t* __restrict__ count,
-    uint32_t capacity, float4* __restrict__ rgba_c, float* __restrict__ depth_c,
+    uint32_t capacity, SetupList l, float4* __restrict__ rgba_c, float* __restrict__ depth_c,
     float4* __restrict__ rgba_f, float* __restrict__ depth_f,
     unsigned long long* __restrict__ nsamp, uint32_t* __restrict__ queue) {
+  constexpr int NB = kSparseAhead + 1;
+  static_assert(kStepsPerRefill % NB == 0, "steps per refill round: a multiple of the buffers");
   __shared__ float4 tfs[FV_TF_ENTRIES];
   tfs[threadIdx.x] = a.tf[threadIdx.x];
   __syncthreads();
   const uint32_t n = min(*count, capacity);
-  const uint32_t wh = (uint32_t)a.W * (uint32_t)a.H;
   const int lane = threadIdx.x & 63;
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   // Idle lanes run the loop body too, so their state and buffers start
   // defined (zero) rather than uninitialised.
   RayState s{};
   s.N = 1;
-  Stencil<DT, SHADE> A{}, B{}, C{}, D{};
-  bool active = false, exhausted = false;
+  Stencil<DT, SHADE> S[NB]{};
+  bool active = false, exhausted = false, done = false;
   uint32_t slot = 0, lin = 0;
   uint32_t ns = 0;
+  RayOut fin{};  // a ray finished in this round, stored at the round's end
+  auto store = [&](const RayOut& o) {
+    if (rgba_c) rgba_c[slot] = o.rgba;
+    if (depth_c) depth_c[slot] = o.depth;
+    if (rgba_f) rgba_f[lin] = o.rgba;
+    if (depth_f) depth_f[lin] = o.depth;
+  };
   while (true) {
     const bool want = !active && !exhausted;
     const uint64_t m = __ballot(want);
     bool fresh = false;  // claimed a ray this round that needs marching
-    if (m) {
+    if (m && (__popcll(m) >= kRefillMin || !__ballot(active))) {
       const int leader = __ffsll((long long)m) - 1;
       uint32_t base = 0;
       if (lane == leader) base = atomicAdd(queue, (uint32_t)__popcll(m));
@@ -406,22 +486,27 @@ __global__ void __launch_bounds__(256) k_march_sparse(
         if (slot >= n) {
           exhausted = true;
         } else {
-          lin = ray_idx[slot];
-          if (lin < a.total) {
-            const int view = (int)(lin / wh);
-            const uint32_t rem = lin - (uint32_t)view * wh;
-            const int y = (int)(rem / (uint32_t)a.W), x = (int)(rem - (uint32_t)y * a.W);
-            const bool hit = ray_setup<SHADE>(a, view, x, y, s);
-            active = hit && s.N > 0;
-            fresh = active;
-            if (!active) {
-              // a miss, or a zero-length ray inside the box
-              const RayOut o = hit ? ray_finish(a, s) : ray_miss(a);
-              if (rgba_c) rgba_c[slot] = o.rgba;
-              if (depth_c) depth_c[slot] = o.depth;
-              if (rgba_f) rgba_f[lin] = o.rgba;
-              if (depth_f) depth_f[lin] = o.depth;
+          const int N = l.n[slot];
+          if (N >= 0) lin = ray_idx[slot];
+          if (N > 0) {
+            for (int j = 0; j < 3; ++j) {
+              s.q0[j] = l.q[j][slot];
+              s.qs[j] = l.q[3 + j][slot];
             }
+            s.klast = l.q[6][slot];
+            s.t0 = l.f[0][slot];
+            s.tstep = l.f[1][slot];
+            s.tlast = l.f[2][slot];
+            s.last_len = l.f[3][slot];
+            for (int j = 0; j < 3; ++j) s.hv[j] = l.f[4 + j][slot];
+            s.N = N;
+            s.k = 0;
+            s.C0 = s.C1 = s.C2 = 0.f;
+            s.T = 1.0f;
+            s.D = 0.0f;
+            active = fresh = true;
+          } else if (N == 0) {
+            store(ray_miss(a));
           }
         }
       }
@@ -429,43 +514,37 @@ __global__ void __launch_bounds__(256) k_march_sparse(
     // first gathers of the new rays, outside the divergent claim code (so the
     // stencil registers are not copied around it)
     if (__ballot(fresh)) {
-      Stencil<DT, SHADE> F0, F1, F2;
-      gather(a, s, 0, F0, fresh);
-      gather(a, s, min(1, s.N - 1), F1, fresh);
-      gather(a, s, min(2, s.N - 1), F2, fresh);
-      select_stencil(fresh, F0, A);
-      select_stencil(fresh, F1, B);
-      select_stencil(fresh, F2, C);
+      Stencil<DT, SHADE> F[NB - 1];
+#pragma unroll
+      for (int j = 0; j < NB - 1; ++j) gather(a, s, min(j, s.N - 1), F[j], fresh);
+#pragma unroll
+      for (int j = 0; j < NB - 1; ++j) select_stencil(fresh, F[j], S[j]);
     }
     if (!__ballot(active)) {
       if (!__ballot(!exhausted)) break;
       continue;
     }
-    // pipelined two samples ahead (three buffers: the next sample's voxels in
-    // A, the one after in B; a multiple of 3 steps per round restores that,
-    // and a newly claimed ray starts the same way)
-    auto finish = [&]() {
-      const RayOut o = ray_finish(a, s);
-      if (rgba_c) rgba_c[slot] = o.rgba;
-      if (depth_c) depth_c[slot] = o.depth;
-      if (rgba_f) rgba_f[lin] = o.rgba;
-      if (depth_f) depth_f[lin] = o.depth;
-      ns += o.samples;
-      active = false;
-    };
-    static_assert(kStepsPerRefill % 4 == 0, "steps per refill round: a multiple of 4");
     // Every lane runs the loop body (idle lanes gather nothing and their
-    // state is discarded); only active lanes commit a finished ray.
+    // state is discarded); only active lanes take a finished ray's result,
+    // which is written once the round is over (stores inside the loop would
+    // hold their addresses in registers across it).  At the top of each
+    // group of NB steps, S[j] holds the voxels of sample k + j.
 #pragma unroll 1
-    for (int it = 0; it < kStepsPerRefill; it += 4) {
-      gather(a, s, min(s.k + 3, s.N - 1), D, active);
-      if (composite(a, tfs, s, A) && active) finish();
-      gather(a, s, min(s.k + 3, s.N - 1), A, active);
-      if (composite(a, tfs, s, B) && active) finish();
-      gather(a, s, min(s.k + 3, s.N - 1), B, active);
-      if (composite(a, tfs, s, C) && active) finish();
-      gather(a, s, min(s.k + 3, s.N - 1), C, active);
-      if (composite(a, tfs, s, D) && active) finish();
+    for (int it = 0; it < kStepsPerRefill; it += NB) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        gather(a, s, min(s.k + NB - 1, s.N - 1), S[(j + NB - 1) % NB], active);
+        if (composite(a, tfs, s, S[j]) && active) {
+          fin = ray_finish(a, s);
+          done = true;
+          active = false;
+        }
+      }
+    }
+    if (done) {
+      store(fin);
+      ns += fin.samples;
+      done = false;
     }
   }
   if (nsamp) add_samples(nsamp, ns);
@@ -560,16 +639,48 @@ fv_status fill_args(const fv_volume* v, const float* tf, int tf_n, const fv_came
 }
 
 template <int DT, bool SHADE>
-void launch_dense(const MarchArgs& a, float* rgba, float* depth, uint64_t* ns, hipStream_t s) {
+void launch_dense(const MarchArgs& a, const uint8_t* mask, float* rgba, float* depth,
+                  uint64_t* ns, hipStream_t s) {
   dim3 grid((a.W + 15) / 16, (a.H + 15) / 16, a.views);
-  k_march_dense<DT, SHADE><<<grid, 256, 0, s>>>(a, (float4*)rgba, depth,
+  k_march_dense<DT, SHADE><<<grid, 256, 0, s>>>(a, mask, (float4*)rgba, depth,
                                                 (unsigned long long*)ns);
+}
+
+fv_status dense_entry(const char* who, const fv_volume* v, const float* tf_rgba, int tf_n,
+                      const fv_camera* cams, int views, int width, int height,
+                      const fv_march_params* mp, const uint8_t* mask, bool need_mask,
+                      float* frame_rgba, float* frame_depth, uint64_t* sample_count,
+                      void* stream) {
+  clear_error();
+  MarchArgs a;
+  fv_status st = fill_args(v, tf_rgba, tf_n, cams, views, width, height, mp, &a, who);
+  if (st != FV_OK) return st;
+  if (!frame_rgba) return fail(FV_ERR_INVALID_ARG, "%s: null frame_rgba", who);
+  if (need_mask && !mask) return fail(FV_ERR_INVALID_ARG, "%s: null mask", who);
+  hipStream_t s = (hipStream_t)stream;
+  const bool sh = mp->shading != 0;
+  switch (v->dt) {
+    case FV_U8:
+      sh ? launch_dense<FV_U8, true>(a, mask, frame_rgba, frame_depth, sample_count, s)
+         : launch_dense<FV_U8, false>(a, mask, frame_rgba, frame_depth, sample_count, s);
+      break;
+    case FV_F16:
+      sh ? launch_dense<FV_F16, true>(a, mask, frame_rgba, frame_depth, sample_count, s)
+         : launch_dense<FV_F16, false>(a, mask, frame_rgba, frame_depth, sample_count, s);
+      break;
+    default:
+      sh ? launch_dense<FV_F32, true>(a, mask, frame_rgba, frame_depth, sample_count, s)
+         : launch_dense<FV_F32, false>(a, mask, frame_rgba, frame_depth, sample_count, s);
+  }
+  return launch_status(who);
 }
 
 template <int DT, bool SHADE>
 void launch_sparse(const MarchArgs& a, const uint32_t* idx, const uint32_t* count,
                    uint32_t capacity, float* rc, float* dc, float* rf, float* df, uint64_t* ns,
-                   uint32_t* queue, hipStream_t s) {
+                   void* ws, hipStream_t s) {
+  uint32_t* queue = (uint32_t*)ws;
+  const SetupList l = setup_list(ws, capacity);
   // persistent grid: as many blocks as can be resident at once
   static int per_cu = 0, cus = 0;
   if (!per_cu) {
@@ -584,9 +695,9 @@ void launch_sparse(const MarchArgs& a, const uint32_t* idx, const uint32_t* coun
   const uint64_t need = ((uint64_t)capacity + 255) / 256;
   uint64_t grid = (uint64_t)per_cu * cus;
   if (grid > need) grid = need;
-  k_clear_queue<<<1, 64, 0, s>>>(queue);
-  k_march_sparse<DT, SHADE><<<(unsigned)grid, 256, 0, s>>>(a, idx, count, capacity, (float4*)rc,
-                                                           dc, (float4*)rf, df,
+  k_setup_list<SHADE><<<(unsigned)need, 256, 0, s>>>(a, idx, count, capacity, l, queue);
+  k_march_sparse<DT, SHADE><<<(unsigned)grid, 256, 0, s>>>(a, idx, count, capacity, l,
+                                                           (float4*)rc, dc, (float4*)rf, df,
                                                            (unsigned long long*)ns, queue);
 }
 
@@ -599,34 +710,24 @@ fv_status fv_raymarch_dense(const fv_volume* v, const float* tf_rgba, int tf_n,
                             const fv_camera* cams, int views, int width, int height,
                             const fv_march_params* mp, float* frame_rgba, float* frame_depth,
                             uint64_t* sample_count, void* stream) {
-  fv::clear_error();
-  fv::MarchArgs a;
-  fv_status st =
-      fv::fill_args(v, tf_rgba, tf_n, cams, views, width, height, mp, &a, "fv_raymarch_dense");
-  if (st != FV_OK) return st;
-  if (!frame_rgba) return fv::fail(FV_ERR_INVALID_ARG, "fv_raymarch_dense: null frame_rgba");
-  hipStream_t s = (hipStream_t)stream;
-  const bool sh = mp->shading != 0;
-  switch (v->dt) {
-    case FV_U8:
-      sh ? fv::launch_dense<FV_U8, true>(a, frame_rgba, frame_depth, sample_count, s)
-         : fv::launch_dense<FV_U8, false>(a, frame_rgba, frame_depth, sample_count, s);
-      break;
-    case FV_F16:
-      sh ? fv::launch_dense<FV_F16, true>(a, frame_rgba, frame_depth, sample_count, s)
-         : fv::launch_dense<FV_F16, false>(a, frame_rgba, frame_depth, sample_count, s);
-      break;
-    default:
-      sh ? fv::launch_dense<FV_F32, true>(a, frame_rgba, frame_depth, sample_count, s)
-         : fv::launch_dense<FV_F32, false>(a, frame_rgba, frame_depth, sample_count, s);
-  }
-  return fv::launch_status("fv_raymarch_dense");
+  return fv::dense_entry("fv_raymarch_dense", v, tf_rgba, tf_n, cams, views, width, height, mp,
+                         nullptr, false, frame_rgba, frame_depth, sample_count, stream);
 }
 
-fv_status fv_raymarch_sparse_workspace(size_t* bytes) {
+fv_status fv_raymarch_masked(const fv_volume* v, const float* tf_rgba, int tf_n,
+                             const fv_camera* cams, int views, int width, int height,
+                             const fv_march_params* mp, const uint8_t* mask, float* frame_rgba,
+                             float* frame_depth, uint64_t* sample_count, void* stream) {
+  return fv::dense_entry("fv_raymarch_masked", v, tf_rgba, tf_n, cams, views, width, height, mp,
+                         mask, true, frame_rgba, frame_depth, sample_count, stream);
+}
+
+fv_status fv_raymarch_sparse_workspace(uint32_t capacity, size_t* bytes) {
   fv::clear_error();
   if (!bytes) return fv::fail(FV_ERR_INVALID_ARG, "fv_raymarch_sparse_workspace: null bytes");
-  *bytes = 256;
+  if (capacity == 0)
+    return fv::fail(FV_ERR_INVALID_ARG, "fv_raymarch_sparse_workspace: capacity 0");
+  *bytes = fv::sparse_workspace_bytes(capacity);
   return FV_OK;
 }
 
@@ -644,22 +745,24 @@ fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba, int tf_n,
   if (st != FV_OK) return st;
   if (!ray_idx || !count || !workspace)
     return fv::fail(FV_ERR_INVALID_ARG, "fv_raymarch_sparse: null ray_idx, count or workspace");
-  if (ws_bytes < 256)
-    return fv::fail(FV_ERR_CAPACITY, "fv_raymarch_sparse: workspace %zu < 256 bytes", ws_bytes);
   if (capacity == 0 || capacity > a.total)
     return fv::fail(FV_ERR_INVALID_ARG, "fv_raymarch_sparse: capacity %u not in [1, %u]", capacity,
                     a.total);
+  if (ws_bytes < fv::sparse_workspace_bytes(capacity))
+    return fv::fail(FV_ERR_CAPACITY, "fv_raymarch_sparse: workspace %zu < %zu bytes", ws_bytes,
+                    fv::sparse_workspace_bytes(capacity));
+  if (((uintptr_t)workspace & 255) != 0)
+    return fv::fail(FV_ERR_INVALID_ARG, "fv_raymarch_sparse: workspace not 256-byte aligned");
   if (!rgba_compact && !depth_compact && !frame_rgba && !frame_depth)
     return fv::fail(FV_ERR_INVALID_ARG, "fv_raymarch_sparse: no output given");
   hipStream_t s = (hipStream_t)stream;
   const bool sh = mp->shading != 0;
-  uint32_t* queue = (uint32_t*)workspace;
 #define FV_SPARSE(DT)                                                                          \
   (sh ? fv::launch_sparse<DT, true>(a, ray_idx, count, capacity, rgba_compact, depth_compact, \
-                                    frame_rgba, frame_depth, sample_count, queue, s)          \
+                                    frame_rgba, frame_depth, sample_count, workspace, s)      \
       : fv::launch_sparse<DT, false>(a, ray_idx, count, capacity, rgba_compact,               \
                                      depth_compact, frame_rgba, frame_depth, sample_count,    \
-                                     queue, s))
+                                     workspace, s))
   switch (v->dt) {
     case FV_U8:
       FV_SPARSE(FV_U8);

@@ -85,6 +85,8 @@ def test_march_host_errors():
     assert L.fv_raymarch_dense(None, fake, 256, cams, 1, 8, 8, mp, fake, None, None, None) == -1
     assert L.fv_raymarch_sparse(None, fake, 256, cams, 1, 8, 8, mp, fake, fake, 64, None, None,
                                 fake, None, None, fake, 256, None) == -1
+    assert L.fv_raymarch_masked(None, fake, 256, cams, 1, 8, 8, mp, fake, fake, None, None,
+                                None) == -1
     assert L.fv_volume_create(None, 8, 8, 8, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
     assert L.fv_volume_create(fake, 0, 8, 8, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
     assert L.fv_volume_create(fake, 8, 8, 8, 9, None, ctypes.byref(ctypes.c_void_p())) == -3

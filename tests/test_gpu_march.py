@@ -11,7 +11,7 @@ import torch
 
 import oracle
 import synthetic
-from tests.gpuhelp import f32, gpu_dense, hull_ok, report
+from tests.gpuhelp import f32, gpu_dense, hull_ok, oracle_mask, report
 
 pytestmark = pytest.mark.gpu
 
@@ -201,3 +201,91 @@ def test_dense_vs_oracle_1080p_sampled(noise256, dev):
     pick = rng.choice(W * H, size=20000, replace=False).astype(np.uint32)
     ora = oracle.march(vol, tf, cams, W, H, mp, idx=pick, alts=True)
     _check(rgba[pick], depth[pick], ora, "noise256 1080p dense")
+
+
+# ------------------------------------------------ naive rejection (masked march)
+
+def _masked_run(b, vol_t, tf_t, cams, W, H, mp, mask_np, dev, sentinel=-7.0):
+    total = len(cams) * W * H
+    mask = torch.from_numpy(np.ascontiguousarray(mask_np, np.uint8).reshape(-1)).to(dev)
+    frame = torch.full((total * 4,), sentinel, dtype=torch.float32, device=dev)
+    fdepth = torch.full((total,), sentinel, dtype=torch.float32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    vol = b.Volume(vol_t)
+    b.raymarch_masked(vol, tf_t, cams, W, H, mp, mask, frame, fdepth, sample_count=cnt)
+    torch.cuda.synchronize()
+    vol.close()
+    return frame.cpu().numpy().reshape(-1, 4), fdepth.cpu().numpy(), int(cnt.item())
+
+
+def test_masked_vs_oracle_stereo_ragged(dev):
+    """Naive rejection on a ragged stereo frame (45x31, two views, f16 noise,
+    Phong): the oracle's own sample map selects the pixels; each selected pixel
+    matches the oracle's ray, every other pixel is left untouched."""
+    from paper_2209_09965_amd import binding as b
+    vol = synthetic.value_noise_volume(5100, n=40, octaves=4, base_period=16).astype(np.float16)
+    tf = synthetic.tf_noise(5100)
+    cams = [synthetic.orbit_camera(9, eye_offset=-0.032), synthetic.orbit_camera(9, eye_offset=0.032)]
+    mp = synthetic.march_params(shading=True)
+    W, H = 45, 31
+    fp = synthetic.fovea_params(W, H, p_floor=0.2, seed=77, frame=3)
+    mask, idx = oracle_mask(oracle, fp, W, H, 2)
+    assert 0 < idx.size < 2 * W * H
+    rgba, depth, cnt = _masked_run(b, torch.from_numpy(vol).to(dev), _tf_t(tf, dev), cams, W, H,
+                                   mp, mask, dev)
+    ora = oracle.march(vol, tf, cams, W, H, mp, idx=idx, alts=True)
+    _check(rgba[idx], depth[idx], ora, "masked stereo")
+    rest = np.ones(2 * W * H, bool)
+    rest[idx] = False
+    assert np.all(rgba[rest] == -7.0) and np.all(depth[rest] == -7.0)
+    if not ora["flags"].any():
+        assert cnt == int(ora["samples"].sum())
+
+
+def test_masked_equals_sparse_bitwise_1080p(noise256, dev):
+    """The benchmarked frame (256^3 f32 noise, 1920x1080, Phong, fovea mask):
+    naive rejection and stream compaction march the same rays, so every sampled
+    pixel, the sample count and the untouched rest agree bit for bit."""
+    from paper_2209_09965_amd import binding as b
+    vol, tf = noise256
+    W, H = 1920, 1080
+    cams = [synthetic.orbit_camera(23)]
+    mp = synthetic.march_params(shading=True)
+    fp = synthetic.fovea_params(W, H, frame=23)
+    vol_t, tf_t = torch.from_numpy(vol).to(dev), _tf_t(tf, dev)
+    sp = _sparse_run(b, vol_t, tf_t, cams, W, H, mp, fp, dev)
+    rgba, depth, cnt = _masked_run(b, vol_t, tf_t, cams, W, H, mp, sp["mask"], dev)
+    assert np.array_equal(rgba, sp["frame"])
+    assert np.array_equal(depth, sp["fdepth"])
+    assert cnt == sp["samples"]
+
+
+@pytest.mark.parametrize("fill", [0, 1])
+def test_masked_degenerate_masks(fill, dev):
+    """An all-zero map touches nothing and composites no sample; an all-one map
+    is the dense frame, bit for bit."""
+    from paper_2209_09965_amd import binding as b
+    vol = synthetic.blob_volume(1002, 64)
+    tf = synthetic.tf_blob(1002)
+    cams = [synthetic.orbit_camera(5)]
+    mp = synthetic.march_params()
+    W, H = 70, 37
+    vol_t, tf_t = torch.from_numpy(vol).to(dev), _tf_t(tf, dev)
+    mask = np.full(W * H, fill, np.uint8)
+    rgba, depth, cnt = _masked_run(b, vol_t, tf_t, cams, W, H, mp, mask, dev)
+    if fill == 0:
+        assert np.all(rgba == -7.0) and np.all(depth == -7.0) and cnt == 0
+    else:
+        d_rgba, d_depth, d_cnt = gpu_dense(b, vol_t, tf_t, cams, W, H, mp, dev)
+        assert np.array_equal(rgba, d_rgba) and np.array_equal(depth, d_depth) and cnt == d_cnt
+
+
+def test_masked_null_mask_rejected(dev):
+    from paper_2209_09965_amd import binding as b
+    vol = b.Volume(torch.zeros((8, 8, 8), dtype=torch.uint8, device=dev))
+    frame = torch.zeros(8 * 8 * 4, dtype=torch.float32, device=dev)
+    tf_t = _tf_t(synthetic.tf_blob(1), dev)
+    with pytest.raises(b.FvError, match="null mask"):
+        b.raymarch_masked(vol, tf_t, [synthetic.orbit_camera(0)], 8, 8, synthetic.march_params(),
+                          None, frame)
+    vol.close()
