@@ -220,21 +220,26 @@ __device__ __forceinline__ void select_stencil(bool c, const Stencil<DT, SHADE>&
   for (int i = 0; i < 3; ++i) dst.w[i] = c ? src.w[i] : dst.w[i];
 }
 
-// One segment from its gathered voxels: trilinear sample (plus the
-// central-difference gradient and Blinn-Phong when shading), TF lookup,
-// front-to-back compositing.  Advances k; returns true when the ray is
-// finished (last segment or early termination).
+// The shaded result of one segment: colour, transmittance exp(-sigma l) and
+// the world-space distance of its sample point.
+struct Segment {
+  float r, g, b, tr, t;
+};
+
+// One segment k from its gathered voxels: trilinear sample (plus the
+// central-difference gradient and Blinn-Phong when shading) and TF lookup.
 template <int DT, bool SHADE>
-__device__ __forceinline__ bool composite(const MarchArgs& a, const float4* __restrict__ tfs,
-                                          RayState& s, const Stencil<DT, SHADE>& st) {
-  const bool last = s.k == s.N - 1;
+__device__ __forceinline__ Segment shade(const MarchArgs& a, const float4* __restrict__ tfs,
+                                         const RayState& s, int k,
+                                         const Stencil<DT, SHADE>& st) {
+  const bool last = k == s.N - 1;
   float len, t;
   if (last) {
     len = s.last_len;
     t = s.tlast;
   } else {
     len = (float)a.step;
-    t = fmaf((float)s.k, s.tstep, s.t0);
+    t = fmaf((float)k, s.tstep, s.t0);
   }
   const float wx = st.w[0], wy = st.w[1], wz = st.w[2];
 #define FV_C(x, y, z) Voxel<DT>::f(st.c[(x) + 2 * (y) + 4 * (z)])
@@ -251,9 +256,8 @@ __device__ __forceinline__ bool composite(const MarchArgs& a, const float4* __re
   const float4 e0 = tfs[j], e1 = tfs[j + 1];
   float r = lerpf(e0.x, e1.x, fr), g = lerpf(e0.y, e1.y, fr), bl = lerpf(e0.z, e1.z, fr);
   const float sig = lerpf(e0.w, e1.w, fr);
-  // segment transmittance exp(-sigma l) (hardware exp), opacity 1 - that
+  // segment transmittance exp(-sigma l) (hardware exp)
   const float tr = __expf(-sig * len);
-  const float alpha = 1.0f - tr;
   if (SHADE) {
     // one-voxel central differences of the interpolated field; arm entry j
     // holds the voxel at (u, v) = (j & 1, j >> 1) across the arm's axis
@@ -282,14 +286,29 @@ __device__ __forceinline__ bool composite(const MarchArgs& a, const float4* __re
     g = g * diff + spec;
     bl = bl * diff + spec;
   }
+  return Segment{r, g, bl, tr, t};
+}
+
+// Front-to-back compositing of the ray's next segment (opacity 1 - tr).
+// Advances k; returns true when the ray is finished (last segment or early
+// termination).
+__device__ __forceinline__ bool accumulate(const MarchArgs& a, RayState& s, const Segment& o) {
+  const bool last = s.k == s.N - 1;
+  const float alpha = 1.0f - o.tr;
   const float wgt = s.T * alpha;
-  s.C0 = fmaf(wgt, r, s.C0);
-  s.C1 = fmaf(wgt, g, s.C1);
-  s.C2 = fmaf(wgt, bl, s.C2);
-  s.D = fmaf(wgt, t, s.D);
-  s.T *= tr;
+  s.C0 = fmaf(wgt, o.r, s.C0);
+  s.C1 = fmaf(wgt, o.g, s.C1);
+  s.C2 = fmaf(wgt, o.b, s.C2);
+  s.D = fmaf(wgt, o.t, s.D);
+  s.T *= o.tr;
   ++s.k;
   return last || 1.0f - s.T >= a.alpha_stop;
+}
+
+template <int DT, bool SHADE>
+__device__ __forceinline__ bool composite(const MarchArgs& a, const float4* __restrict__ tfs,
+                                          RayState& s, const Stencil<DT, SHADE>& st) {
+  return accumulate(a, s, shade(a, tfs, s, s.k, st));
 }
 
 __device__ __forceinline__ RayOut ray_finish(const MarchArgs& a, const RayState& s) {
@@ -379,14 +398,20 @@ __host__ __device__ inline size_t setup_stride(uint32_t capacity, size_t elem) {
   return ((size_t)capacity * elem + 255) & ~(size_t)255;
 }
 
+// Workspace header: the claim counter (word 0) and kHitCounters counters of
+// the rays that reach the volume, one per 128-byte line (word 32 j), so the
+// set-up pass's atomics spread over many lines.
+constexpr int kHitCounters = 31;
+constexpr size_t kWsHeader = 4096;
+
 inline size_t sparse_workspace_bytes(uint32_t capacity) {
-  return 256 + kSetupDoubles * setup_stride(capacity, 8) +
+  return kWsHeader + kSetupDoubles * setup_stride(capacity, 8) +
          (kSetupFloats + 1) * setup_stride(capacity, 4);
 }
 
 inline SetupList setup_list(void* ws, uint32_t capacity) {
   SetupList l;
-  char* p = (char*)ws + 256;
+  char* p = (char*)ws + kWsHeader;
   for (int i = 0; i < kSetupDoubles; ++i, p += setup_stride(capacity, 8)) l.q[i] = (double*)p;
   for (int i = 0; i < kSetupFloats; ++i, p += setup_stride(capacity, 4)) l.f[i] = (float*)p;
   l.n = (int*)p;
@@ -400,21 +425,28 @@ __global__ void __launch_bounds__(256) k_setup_list(MarchArgs a,
                                                     uint32_t capacity, SetupList l,
                                                     uint32_t* __restrict__ queue) {
   const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-  if (i == 0) queue[0] = 0u;  // the march kernel's claim counter
-  if (i >= min(*count, capacity)) return;
-  const uint32_t lin = ray_idx[i];
-  if (lin >= a.total) {
-    l.n[i] = -1;
-    return;
-  }
-  const uint32_t wh = (uint32_t)a.W * (uint32_t)a.H;
-  const int view = (int)(lin / wh);
-  const uint32_t rem = lin - (uint32_t)view * wh;
-  const int y = (int)(rem / (uint32_t)a.W), x = (int)(rem - (uint32_t)y * a.W);
+  const bool listed = i < min(*count, capacity);
+  const uint32_t lin = listed ? ray_idx[i] : 0u;
+  bool hit = false;
   RayState s;
-  // a zero-length ray inside the box finishes with the same output as a miss
-  if (!ray_setup<SHADE>(a, view, x, y, s) || s.N <= 0) {
-    l.n[i] = 0;
+  if (listed && lin < a.total) {
+    const uint32_t wh = (uint32_t)a.W * (uint32_t)a.H;
+    const int view = (int)(lin / wh);
+    const uint32_t rem = lin - (uint32_t)view * wh;
+    const int y = (int)(rem / (uint32_t)a.W), x = (int)(rem - (uint32_t)y * a.W);
+    // a zero-length ray inside the box finishes with the same output as a miss
+    hit = ray_setup<SHADE>(a, view, x, y, s) && s.N > 0;
+  }
+  // rays that reach the volume: one atomic per wave, on one of the header's
+  // counters (cleared before this kernel)
+  const uint64_t hm = __ballot(hit);
+  if (hm && (threadIdx.x & 63) == __ffsll((long long)hm) - 1) {
+    const uint32_t wv = (blockIdx.x * 256u + threadIdx.x) >> 6;
+    atomicAdd(queue + 32 * (1 + wv % kHitCounters), (uint32_t)__popcll(hm));
+  }
+  if (!listed) return;
+  if (!hit) {
+    l.n[i] = lin < a.total ? 0 : -1;
     return;
   }
   for (int j = 0; j < 3; ++j) {
@@ -437,34 +469,76 @@ __global__ void __launch_bounds__(256) k_setup_list(MarchArgs a,
 // periphery do not leave lanes idle for long, and a wave's lanes stay on
 // neighbouring pixels (one claim takes consecutive list entries).  Results
 // go to the compact buffers and/or back to their pixels (back-projection).
-// The loop is software-pipelined kSparseAhead samples ahead: each lane keeps
+// The loop is software-pipelined kSparseAhead steps ahead: each lane keeps
 // the voxels of its next kSparseAhead samples in flight.
+//
+// When the list holds few rays for the lanes resident on the device, one ray
+// would otherwise take one lane for its whole length, and the frame would
+// last as long as its longest ray.  Then G = 2, 4 or 8 consecutive lanes
+// march one ray together: lane r of the group shades segments k + r, and
+// every lane of the group composites the group's G segments in ray order,
+// with the same operations as the single-lane march, so the pixel is the
+// same bit for bit and the group's lanes keep identical ray state.
 constexpr int kStepsPerRefill = 9;
 constexpr int kRefillMin = 32;
 constexpr int kSparseAhead = 2;
+// G is the largest of 1, 2, 4, 8 with h G^2 <= kGroupRule, h = (rays that
+// reach the volume) / (resident lanes).  Measured on the 1080p noise volume:
+// the best G was 1 at h = 11 (2 within 3 %), 2 at h = 2.2 to 2.5, 4 at
+// h = 0.55 and 8 at h = 0.11 (a larger G shortens each ray's critical path
+// and costs the exchange and the repeated compositing).
+constexpr int kGroupRule = 16;
 
-template <int DT, bool SHADE>
-__global__ void __launch_bounds__(256) k_march_sparse(
-    MarchArgs a, const uint32_t* __restrict__ ray_idx, const uint32_t* __restrict__ count,
-    uint32_t capacity, SetupList l, float4* __restrict__ rgba_c, float* __restrict__ depth_c,
-    float4* __restrict__ rgba_f, float* __restrict__ depth_f,
-    unsigned long long* __restrict__ nsamp, uint32_t* __restrict__ queue) {
+// Value of v held by lane Q of this lane's group of G (G a power of two).
+template <int G, int Q>
+__device__ __forceinline__ float group_get(float v) {
+  if constexpr (G == 1) {
+    return v;
+  } else if constexpr (G == 2 || G == 4) {
+    // quad permutation: lane i of each quad reads lane p_i of the quad
+    constexpr int p0 = G == 2 ? Q : Q, p2 = G == 2 ? 2 + Q : Q;
+    constexpr int ctrl = p0 | (p0 << 2) | (p2 << 4) | (p2 << 6);
+    return __builtin_bit_cast(
+        float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), ctrl, 0xF, 0xF, true));
+  } else {
+    const int lane = threadIdx.x & 63;
+    return __shfl(v, (lane & ~(G - 1)) | Q, 64);
+  }
+}
+
+template <int G, int Q = 0>
+__device__ __forceinline__ bool group_accumulate(const MarchArgs& a, RayState& s,
+                                                 const Segment& o, bool fin) {
+  if constexpr (Q == G) {
+    return fin;
+  } else {
+    const Segment q{group_get<G, Q>(o.r), group_get<G, Q>(o.g), group_get<G, Q>(o.b),
+                    group_get<G, Q>(o.tr), group_get<G, Q>(o.t)};
+    if (!fin) fin = accumulate(a, s, q);
+    return group_accumulate<G, Q + 1>(a, s, o, fin);
+  }
+}
+
+template <int DT, bool SHADE, int G>
+__device__ __forceinline__ void march_list(const MarchArgs& a, const float4* __restrict__ tfs,
+                                           const uint32_t* __restrict__ ray_idx, uint32_t n,
+                                           const SetupList& l, float4* __restrict__ rgba_c,
+                                           float* __restrict__ depth_c,
+                                           float4* __restrict__ rgba_f,
+                                           float* __restrict__ depth_f, uint32_t& ns,
+                                           uint32_t* __restrict__ queue) {
   constexpr int NB = kSparseAhead + 1;
   static_assert(kStepsPerRefill % NB == 0, "steps per refill round: a multiple of the buffers");
-  __shared__ float4 tfs[FV_TF_ENTRIES];
-  tfs[threadIdx.x] = a.tf[threadIdx.x];
-  __syncthreads();
-  const uint32_t n = min(*count, capacity);
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, r = lane & (G - 1);
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   // Idle lanes run the loop body too, so their state and buffers start
-  // defined (zero) rather than uninitialised.
+  // defined (zero) rather than uninitialised.  Every lane of a group holds
+  // the same ray state.
   RayState s{};
   s.N = 1;
   Stencil<DT, SHADE> S[NB]{};
   bool active = false, exhausted = false, done = false;
   uint32_t slot = 0, lin = 0;
-  uint32_t ns = 0;
   RayOut fin{};  // a ray finished in this round, stored at the round's end
   auto store = [&](const RayOut& o) {
     if (rgba_c) rgba_c[slot] = o.rgba;
@@ -474,15 +548,15 @@ __global__ void __launch_bounds__(256) k_march_sparse(
   };
   while (true) {
     const bool want = !active && !exhausted;
-    const uint64_t m = __ballot(want);
+    const uint64_t m = __ballot(want);  // G bits per idle group
     bool fresh = false;  // claimed a ray this round that needs marching
     if (m && (__popcll(m) >= kRefillMin || !__ballot(active))) {
       const int leader = __ffsll((long long)m) - 1;
       uint32_t base = 0;
-      if (lane == leader) base = atomicAdd(queue, (uint32_t)__popcll(m));
+      if (lane == leader) base = atomicAdd(queue, (uint32_t)__popcll(m) / G);
       base = __shfl(base, leader, 64);
       if (want) {
-        slot = base + (uint32_t)__popcll(m & lt);
+        slot = base + (uint32_t)__popcll(m & lt) / G;
         if (slot >= n) {
           exhausted = true;
         } else {
@@ -505,7 +579,7 @@ __global__ void __launch_bounds__(256) k_march_sparse(
             s.T = 1.0f;
             s.D = 0.0f;
             active = fresh = true;
-          } else if (N == 0) {
+          } else if (N == 0 && r == 0) {
             store(ray_miss(a));
           }
         }
@@ -516,7 +590,7 @@ __global__ void __launch_bounds__(256) k_march_sparse(
     if (__ballot(fresh)) {
       Stencil<DT, SHADE> F[NB - 1];
 #pragma unroll
-      for (int j = 0; j < NB - 1; ++j) gather(a, s, min(j, s.N - 1), F[j], fresh);
+      for (int j = 0; j < NB - 1; ++j) gather(a, s, min(r + G * j, s.N - 1), F[j], fresh);
 #pragma unroll
       for (int j = 0; j < NB - 1; ++j) select_stencil(fresh, F[j], S[j]);
     }
@@ -528,13 +602,16 @@ __global__ void __launch_bounds__(256) k_march_sparse(
     // state is discarded); only active lanes take a finished ray's result,
     // which is written once the round is over (stores inside the loop would
     // hold their addresses in registers across it).  At the top of each
-    // group of NB steps, S[j] holds the voxels of sample k + j.
+    // group of NB steps, S[j] holds the voxels of segment k + r + G j.
+    // Segments past the last one are clamped to it: they are shaded but
+    // never composited.
 #pragma unroll 1
     for (int it = 0; it < kStepsPerRefill; it += NB) {
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
-        gather(a, s, min(s.k + NB - 1, s.N - 1), S[(j + NB - 1) % NB], active);
-        if (composite(a, tfs, s, S[j]) && active) {
+        gather(a, s, min(s.k + r + G * (NB - 1), s.N - 1), S[(j + NB - 1) % NB], active);
+        const Segment o = shade(a, tfs, s, G == 1 ? s.k : min(s.k + r, s.N - 1), S[j]);
+        if (group_accumulate<G>(a, s, o, false) && active) {
           fin = ray_finish(a, s);
           done = true;
           active = false;
@@ -542,12 +619,53 @@ __global__ void __launch_bounds__(256) k_march_sparse(
       }
     }
     if (done) {
-      store(fin);
-      ns += fin.samples;
+      if (r == 0) {
+        store(fin);
+        ns += fin.samples;
+      }
       done = false;
     }
   }
+}
+
+template <int DT, bool SHADE>
+__global__ void __launch_bounds__(256) k_march_sparse(
+    MarchArgs a, const uint32_t* __restrict__ ray_idx, const uint32_t* __restrict__ count,
+    uint32_t capacity, SetupList l, float4* __restrict__ rgba_c, float* __restrict__ depth_c,
+    float4* __restrict__ rgba_f, float* __restrict__ depth_f,
+    unsigned long long* __restrict__ nsamp, uint32_t* __restrict__ queue) {
+  __shared__ float4 tfs[FV_TF_ENTRIES];
+  tfs[threadIdx.x] = a.tf[threadIdx.x];
+  __syncthreads();
+  const uint32_t n = min(*count, capacity);
+  // lanes per ray, from the rays that reach the volume (counted by the set-up
+  // pass) and the lanes of the persistent grid (the same for every wave)
+  const int lane = threadIdx.x & 63;
+  uint32_t hc = lane < kHitCounters ? queue[32 * (1 + lane)] : 0u;
+  for (int off = 32; off; off >>= 1) hc += __shfl_xor(hc, off, 64);
+  const uint64_t hits = hc, lanes = (uint64_t)gridDim.x * 256u;
+  int g = 1;
+  while (g < 8 && hits * (uint64_t)(4 * g * g) <= lanes * kGroupRule) g *= 2;
+  uint32_t ns = 0;
+  switch (g) {
+    case 8:
+      march_list<DT, SHADE, 8>(a, tfs, ray_idx, n, l, rgba_c, depth_c, rgba_f, depth_f, ns, queue);
+      break;
+    case 4:
+      march_list<DT, SHADE, 4>(a, tfs, ray_idx, n, l, rgba_c, depth_c, rgba_f, depth_f, ns, queue);
+      break;
+    case 2:
+      march_list<DT, SHADE, 2>(a, tfs, ray_idx, n, l, rgba_c, depth_c, rgba_f, depth_f, ns, queue);
+      break;
+    default:
+      march_list<DT, SHADE, 1>(a, tfs, ray_idx, n, l, rgba_c, depth_c, rgba_f, depth_f, ns, queue);
+  }
   if (nsamp) add_samples(nsamp, ns);
+}
+
+// Clears the workspace header's counters.
+__global__ void k_clear_queue(uint32_t* q) {
+  if (threadIdx.x <= kHitCounters) q[32 * threadIdx.x] = 0u;
 }
 
 // ---------------------------------------------------------------- host side
@@ -695,6 +813,7 @@ void launch_sparse(const MarchArgs& a, const uint32_t* idx, const uint32_t* coun
   const uint64_t need = ((uint64_t)capacity + 255) / 256;
   uint64_t grid = (uint64_t)per_cu * cus;
   if (grid > need) grid = need;
+  k_clear_queue<<<1, 64, 0, s>>>(queue);
   k_setup_list<SHADE><<<(unsigned)need, 256, 0, s>>>(a, idx, count, capacity, l, queue);
   k_march_sparse<DT, SHADE><<<(unsigned)grid, 256, 0, s>>>(a, idx, count, capacity, l,
                                                            (float4*)rc, dc, (float4*)rf, df,

@@ -32,8 +32,9 @@ def _check(gpu_rgba, gpu_depth, ora, label):
     d_err = np.abs(gpu_depth - ora["depth"])[~flagged]
     assert d_err.size == 0 or d_err.max() <= DEPTH_TOL * 4, d_err.max()
     # ambiguous early-termination decisions are rare (the opacity jump per step near
-    # alpha_stop is ~1e-4..1e-3, so a 2e-6 window catches well under 1% of rays)
-    assert flagged.mean() < 1e-2
+    # alpha_stop is ~1e-4..1e-3, so a 2e-6 window catches well under 1% of rays;
+    # a sample of a hundred rays may still hold one or two)
+    assert flagged.sum() <= max(2, 0.01 * flagged.size)
 
 
 def test_empty_volume_background_exact(dev):
@@ -171,6 +172,56 @@ def test_sparse_equals_dense_bitwise_1080p(noise256, dev):
     untouched[idx] = False
     assert np.all(sp["frame"][untouched] == -7.0) and np.all(sp["fdepth"][untouched] == -7.0)
     assert sp["samples"] < cnt_dense
+
+
+@pytest.mark.parametrize("nrays", [1, 100, 12000, 24000, 60000, 1920 * 1080])
+def test_sparse_short_lists_equal_dense(nrays, noise256, dev):
+    """Lists with few rays for the resident lanes make several lanes march
+    one ray together (8, 4 or 2 lanes a ray, chosen from the rays that reach
+    the volume; one lane a ray for the full frame).  Every listed pixel
+    equals the dense march bit for bit, for lists of 1 .. 60 000 rays in
+    random order, mostly inside the volume's footprint at 1920x1080, and for
+    the whole frame."""
+    from paper_2209_09965_amd import binding as b
+    vol, tf = noise256
+    W, H = 1920, 1080
+    cams = [synthetic.orbit_camera(29)]
+    mp = synthetic.march_params(shading=True)
+    vol_t, tf_t = torch.from_numpy(vol).to(dev), _tf_t(tf, dev)
+    rng = np.random.default_rng(nrays)
+    ys, xs = np.mgrid[240:840, 660:1260]
+    pool = (ys * W + xs).reshape(-1)
+    total = W * H
+    if nrays == total:
+        idx = np.arange(total, dtype=np.int64)
+    else:
+        idx = np.sort(rng.choice(pool, size=nrays, replace=False)).astype(np.int64)
+        rng.shuffle(idx)
+    ray_idx = torch.zeros(total, dtype=torch.int32, device=dev)
+    ray_idx[:nrays] = torch.from_numpy(idx.astype(np.int32)).to(dev)
+    count = torch.tensor([nrays], dtype=torch.int32, device=dev)
+    frame = torch.full((total * 4,), -7.0, dtype=torch.float32, device=dev)
+    fdepth = torch.full((total,), -7.0, dtype=torch.float32, device=dev)
+    rc = torch.full((total * 4,), -7.0, dtype=torch.float32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    vol_h = b.Volume(vol_t)
+    b.raymarch_sparse(vol_h, tf_t, cams, W, H, mp, ray_idx, count, rgba_compact=rc,
+                      frame_rgba=frame, frame_depth=fdepth, sample_count=cnt)
+    torch.cuda.synchronize()
+    vol_h.close()
+    rgba, depth, _ = gpu_dense(b, vol_t, tf_t, cams, W, H, mp, dev)
+    fr = frame.cpu().numpy().reshape(-1, 4)
+    assert np.array_equal(fr[idx], rgba[idx])
+    assert np.array_equal(rc.cpu().numpy().reshape(-1, 4)[:nrays], rgba[idx])
+    assert np.array_equal(fdepth.cpu().numpy()[idx], depth[idx])
+    rest = np.ones(total, bool)
+    rest[idx] = False
+    assert np.all(fr[rest] == -7.0)
+    if nrays <= 100:
+        ora = oracle.march(vol, tf, cams, W, H, mp, idx=idx.astype(np.uint32), alts=True)
+        _check(fr[idx], fdepth.cpu().numpy()[idx], ora, "short list %d" % nrays)
+        if not ora["flags"].any():
+            assert int(cnt.item()) == int(ora["samples"].sum())
 
 
 def test_sparse_vs_oracle_1080p_sampled(noise256, dev):
