@@ -348,7 +348,11 @@ def main():
                 "traffic": measured_traffic(args.workload),
                 "model": "%d B/sample = %d unique stencil voxels x %d B; %.4g samples/launch" %
                          (bytes_per_sample, bytes_per_sample // vol.itemsize, vol.itemsize,
-                          sparse_samples / args.steps)}
+                          sparse_samples / args.steps),
+                "duration": "HIP events around the fv_raymarch_sparse call (counter clear, "
+                            "ray set-up pass and k_march_sparse), %.4f ms" % sp_avg,
+                "note": "frac > 1: the stencil voxels are mostly served by L1/L2/MALL; the "
+                        "HBM bytes actually moved are `traffic`"}
     dn_avg = sum(dense_kernel_ms) / len(dense_kernel_ms)
     dense_ach = dense_samples / args.steps * bytes_per_sample / (dn_avg * 1e-3) / 1e9
 
