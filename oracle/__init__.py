@@ -70,6 +70,9 @@ def lib():
         L.or_sample.restype = ctypes.c_double
         L.or_sample.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                 ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.or_shadow_at.restype = ctypes.c_double
+        L.or_shadow_at.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_int, dp] + [ctypes.c_double] * 7
         L.or_pack_input.restype = None
         L.or_pack_input.argtypes = [dp, u8p, dp, ctypes.c_int64, dp]
         _lib = L
@@ -143,6 +146,7 @@ def _mp_array(mp):
     v += list(mp.get("light_dir", (1.0, 1.0, 1.0)))
     v += [mp.get("ka", 0.2), mp.get("kd", 0.7), mp.get("ks", 0.3), mp.get("shininess", 32.0)]
     v += list(mp.get("bg", (0.0, 0.0, 0.0)))
+    v += [mp.get("shadow_step", 0.0)]
     a = np.asarray(v, dtype=np.float32).astype(np.float64)
     a[2] = float(mp.get("shading", 0))
     return a
@@ -199,6 +203,17 @@ def sample(volume, q):
     nz, ny, nx = vol.shape
     return lib().or_sample(vol.ctypes.data, nx, ny, nz, DTYPES[vol.dtype],
                            float(q[0]), float(q[1]), float(q[2]))
+
+
+def shadow_at(volume, tf, q, light, ds):
+    """Shadow transmittance at voxel-index position q towards the light
+    direction `light`, shadow segments of ds voxel lengths."""
+    vol = np.ascontiguousarray(volume)
+    nz, ny, nx = vol.shape
+    tfa = np.ascontiguousarray(np.asarray(tf, dtype=np.float32).astype(np.float64).reshape(-1))
+    return lib().or_shadow_at(vol.ctypes.data, nx, ny, nz, DTYPES[vol.dtype],
+                              _ptr(tfa, ctypes.c_double), float(q[0]), float(q[1]), float(q[2]),
+                              float(light[0]), float(light[1]), float(light[2]), float(ds))
 
 
 def pack_input(frame_rgba, mask, frame_depth):

@@ -295,7 +295,49 @@ typedef struct {
   double step, alpha_stop;
   int shading;
   double light[3], ka, kd, ks, shininess, bg[3];
+  double shadow_step; /* shadow-ray segment length in voxels, 0 = no shadows */
 } or_mp;
+
+/* TF opacity channel (sigma) at value v: linear interpolation between the
+ * 256 entries at clamp(v, 0, 1) * 255. */
+static double or_tf_sigma(const double* tf, double v) {
+  double xv = v < 0.0 ? 0.0 : (v > 1.0 ? 1.0 : v);
+  xv *= 255.0;
+  int j = (int)floor(xv);
+  if (j > 254) j = 254;
+  double f = xv - j;
+  return (1.0 - f) * tf[j * 4 + 3] + f * tf[(j + 1) * 4 + 3];
+}
+
+/* Global ray-marched shadow (paper Sec. 3.1 "Foveated Rendering": one shadow
+ * ray per sample, towards the light, at a lower sample rate).  Reading: a
+ * directional light; the shadow ray leaves the sample point p (voxel index
+ * space, where the box is [-1/2, n_a - 1/2] on axis a) along the unit light
+ * direction lhat and ends where it leaves the box, after L voxel lengths.
+ * It is cut into ceil(L / ds) segments of length ds (the last one shorter),
+ * each sampled at its midpoint like the primary ray, and the light reaching
+ * p is attenuated by the transmittance exp(-sum sigma_j len_j). */
+static double or_shadow(const or_vol* V, const double* tf, const double q[3],
+                        const double lhat[3], double ds) {
+  double L = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    if (lhat[a] == 0.0) continue;
+    double face = lhat[a] > 0.0 ? V->n[a] - 0.5 : -0.5;
+    double t = (face - q[a]) / lhat[a];
+    if (t < L) L = t;
+  }
+  if (!(L > 0.0)) return 1.0;
+  int64_t N = (int64_t)ceil(L / ds);
+  double tau = 0.0;
+  for (int64_t j = 0; j < N; ++j) {
+    double a0 = j * ds, b0 = (j + 1) * ds;
+    if (b0 > L) b0 = L;
+    double m = 0.5 * (a0 + b0), qs[3];
+    for (int a = 0; a < 3; ++a) qs[a] = q[a] + m * lhat[a];
+    tau += or_tf_sigma(tf, or_trilinear(V, qs)) * (b0 - a0);
+  }
+  return exp(-tau);
+}
 
 typedef struct {
   double rgba[4];
@@ -374,8 +416,11 @@ static void or_march_ray(const or_vol* V, const double* tf, const or_mp* mp,
       double ndl = fabs(or_dot(nrm, Lhat));
       double ndh = fabs(or_dot(nrm, Hv));
       double spec = mp->ks * pow(ndh, mp->shininess);
+      /* with shadows, the light reaching the sample (diffuse and specular
+       * terms) is attenuated; the ambient term is not */
+      double ts = mp->shadow_step > 0.0 ? or_shadow(V, tf, q, Lhat, mp->shadow_step) : 1.0;
       for (int ch = 0; ch < 3; ++ch)
-        col[ch] = c4[ch] * (mp->ka + mp->kd * ndl) + spec;
+        col[ch] = c4[ch] * (mp->ka + ts * (mp->kd * ndl)) + ts * spec;
     }
     double w = T * alpha;
     for (int ch = 0; ch < 3; ++ch) C[ch] += w * col[ch];
@@ -394,6 +439,7 @@ static void or_march_ray(const or_vol* V, const double* tf, const or_mp* mp,
  *   tf     256*4 doubles (r, g, b, sigma)
  *   cams   views*11 doubles: eye[3] target[3] up[3] fovy_deg eye_offset
  *   mpv    14 doubles: step alpha_stop shading light[3] ka kd ks shininess bg[3]
+ *          shadow_step (0 = no shadows)
  *   idx    pixel indices (v*W*H + y*W + x), or NULL for all pixels in order
  *   rgba   n*4, depth n, samples n (any of these may be NULL)
  *   flags, rgba_lo, rgba_hi: if non-NULL, the ray is also marched with the
@@ -424,6 +470,7 @@ int or_march(const void* vol, int nx, int ny, int nz, int dtype,
   mp.ks = mpv[8];
   mp.shininess = mpv[9];
   for (int a = 0; a < 3; ++a) mp.bg[a] = mpv[10 + a];
+  mp.shadow_step = mpv[13];
   int64_t total = (int64_t)views * W * H;
   if (!idx) n = total;
 #pragma omp parallel for schedule(dynamic, 64)
@@ -462,6 +509,25 @@ int or_march(const void* vol, int nx, int ny, int nz, int dtype,
     }
   }
   return 0;
+}
+
+/* Shadow transmittance at voxel-index position q towards the light
+ * direction (normalised here), exposed for pin tests. */
+double or_shadow_at(const void* vol, int nx, int ny, int nz, int dtype, const double* tf,
+                    double qx, double qy, double qz, double lx, double ly, double lz,
+                    double ds) {
+  or_vol V;
+  V.data = vol;
+  V.n[0] = nx;
+  V.n[1] = ny;
+  V.n[2] = nz;
+  V.dtype = dtype;
+  int nmax = nx > ny ? nx : ny;
+  if (nz > nmax) nmax = nz;
+  V.h = 1.0 / nmax;
+  double l[3] = {lx, ly, lz}, q[3] = {qx, qy, qz};
+  or_normalize(l);
+  return or_shadow(&V, tf, q, l, ds);
 }
 
 /* Single trilinear sample, exposed for pin tests. */

@@ -161,10 +161,13 @@ def random_camera(rng, radius=2.0, fovy_deg=45.0):
 # --------------------------------------------------------------- parameters
 
 def march_params(shading=False, step_vox=0.5, alpha_stop=0.99, light_dir=(1.0, 1.0, 1.0),
-                 ka=0.2, kd=0.7, ks=0.3, shininess=32.0, bg=(0.0, 0.0, 0.0)):
+                 ka=0.2, kd=0.7, ks=0.3, shininess=32.0, bg=(0.0, 0.0, 0.0), shadow_step=0.0):
+    """shadow_step: shadow-ray segment length in voxels (0 = no shadows); the
+    paper's renderer marches its shadow rays at a quarter of the primary
+    sample rate, i.e. shadow_step = 4 step_vox."""
     return dict(step_vox=step_vox, alpha_stop=alpha_stop, shading=int(bool(shading)),
                 light_dir=tuple(light_dir), ka=ka, kd=kd, ks=ks, shininess=shininess,
-                bg=tuple(bg))
+                bg=tuple(bg), shadow_step=shadow_step)
 
 
 def fovea_params(width, height, sigma_frac=0.15, p_floor=0.05, mode=0, seed=42, frame=0,

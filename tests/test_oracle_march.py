@@ -221,3 +221,109 @@ def test_ambiguity_flags_mark_threshold_rays():
     assert f.any()
     assert np.all(out["rgba_lo"][f, 3] <= out["rgba_hi"][f, 3])
     assert np.array_equal(out["rgba_lo"][~f], out["rgba_hi"][~f])
+
+
+# ------------------------------------------------------------------ shadows
+# Global ray-marched shadows (Methods, "Foveated Rendering": one shadow ray
+# per sample towards the light, at a quarter of the primary sample rate).
+# Reading: directional light; the shadow ray runs from the sample to where it
+# leaves the box, midpoint segments of shadow_step voxel lengths (the last
+# shorter), transmittance exp(-sum sigma_j len_j) scaling the diffuse and
+# specular terms.
+
+@pytest.mark.parametrize("ds", [0.5, 2.0, 3.7])
+def test_shadow_constant_extinction_closed_form(ds):
+    """With the same extinction c everywhere, the transmittance is exp(-c L)
+    for the exit distance L of the box [-1/2, n - 1/2]^3, whatever the
+    segment length."""
+    vol = np.full((12, 10, 8), 0.3, np.float32)  # nz, ny, nx
+    c = 0.07
+    tf = const_tf((1, 1, 1), c)
+    c = f32(c)
+    # along +x from x = 3: the face x = 7.5 is 4.5 away
+    t = oracle.shadow_at(vol, tf, (3.0, 2.0, 5.0), (1, 0, 0), ds)
+    assert t == pytest.approx(math.exp(-c * 4.5), rel=1e-13)
+    # along -y from y = 2.25: the face y = -0.5 is 2.75 away
+    t = oracle.shadow_at(vol, tf, (3.0, 2.25, 5.0), (0, -1, 0), ds)
+    assert t == pytest.approx(math.exp(-c * 2.75), rel=1e-13)
+    # diagonal from (1, 2, 3): faces 7.5, 9.5, 11.5 -> min(6.5, 7.5, 8.5) sqrt(3)
+    t = oracle.shadow_at(vol, tf, (1.0, 2.0, 3.0), (1, 1, 1), ds)
+    assert t == pytest.approx(math.exp(-c * 6.5 * math.sqrt(3)), rel=1e-12)
+
+
+@pytest.mark.parametrize("direction", [1, -1])
+def test_shadow_slab_integral_exact(direction):
+    """A one-voxel-thick wall (value 1 on the planes x = 4 and 5, 0 elsewhere)
+    seen through a linear TF sigma = c v: the trilinear field along x is a
+    trapezoid with integral 2, and half-voxel midpoint segments that start on
+    a voxel plane integrate it exactly, so T = exp(-2 c) from either side."""
+    vol = np.zeros((4, 4, 10), np.float32)
+    vol[:, :, 4:6] = 1.0
+    c = 0.3
+    tf = np.zeros((256, 4), np.float32)
+    tf[:, 3] = c * np.arange(256) / 255.0
+    x0 = 1.0 if direction > 0 else 8.0
+    t = oracle.shadow_at(vol, tf, (x0, 1.5, 2.0), (direction, 0, 0), 0.5)
+    sig = tf[:, 3].astype(np.float64)
+    # the TF's float32 entries are linear in the index up to rounding
+    assert t == pytest.approx(math.exp(-2 * c), rel=1e-6)
+    # beyond the wall, looking away from it: nothing in the way
+    xb = 7.0 if direction > 0 else 2.0
+    assert oracle.shadow_at(vol, tf, (xb, 1.5, 2.0), (direction, 0, 0), 0.5) == 1.0
+    assert sig[0] == 0.0
+
+
+def test_shadow_marching_closed_form():
+    """The linear ramp v = a x + b (constant colour and extinction c) seen along -z with
+    the light along (1, 1, 1): every sample has the same normal -x^, and its shadow ray
+    leaves the box through the face it meets first, so each sample's light is scaled by
+    exp(-c L_k) with L_k from the geometry alone."""
+    n = 16
+    x = np.arange(n, dtype=np.float64)
+    vol = np.broadcast_to((0.02 * x + 0.1).astype(np.float32), (n, n, n)).copy()
+    rgb, sigma = np.array([0.8, 0.4, 0.2]), 0.04
+    tf = const_tf(rgb, sigma)
+    mp = synthetic.march_params(shading=True, alpha_stop=1.0, shadow_step=2.0)
+    W = H = 3
+    out = oracle.march(vol, tf, [AXIAL], W, H, mp, idx=np.array([4], np.uint32))
+    c = f32(sigma)
+    Lh = np.ones(3) / math.sqrt(3)
+    Hv = Lh + np.array([0, 0, 1.0])
+    Hv /= np.linalg.norm(Hv)
+    nrm = np.array([-1.0, 0, 0])
+    # the centre pixel's ray: x = y = 7.5 (index space), z from n - 1/2 down to -1/2;
+    # sample k sits at z = n - 1/2 - (k + 1/2) * 0.5 (16 voxels / 0.5 = 32 segments)
+    total = np.zeros(3)
+    T = 1.0
+    a = 1 - math.exp(-c * 0.5)
+    for k in range(32):
+        z = n - 0.5 - (k + 0.5) * 0.5
+        L = min(n - 0.5 - 7.5, n - 0.5 - 7.5, n - 0.5 - z) * math.sqrt(3)
+        ts = math.exp(-c * L)
+        col = rgb.astype(np.float32) * (f32(0.2) + ts * f32(0.7) * abs(nrm @ Lh)) + \
+            ts * f32(0.3) * abs(nrm @ Hv) ** 32
+        total += T * a * col
+        T *= 1 - a
+    np.testing.assert_allclose(out["rgba"][0, :3], total, atol=1e-12)
+
+
+def test_shadows_only_darken():
+    """Shadows scale the diffuse and specular light by a transmittance in [0, 1]: on a
+    black background every colour channel can only drop, and opacity, depth and the
+    sample count do not change.  shadow_step = 0 is the unshadowed march, bit for bit."""
+    vol = synthetic.value_noise_volume(17, n=24, octaves=3, base_period=8)
+    tf = synthetic.tf_noise(17)
+    tf[:, 3] *= 4
+    cam = synthetic.orbit_camera(11)
+    W, H = 20, 14
+    plain = oracle.march(vol, tf, [cam], W, H, synthetic.march_params(shading=True))
+    zero = oracle.march(vol, tf, [cam], W, H,
+                        synthetic.march_params(shading=True, shadow_step=0.0))
+    shad = oracle.march(vol, tf, [cam], W, H,
+                        synthetic.march_params(shading=True, shadow_step=2.0))
+    assert np.array_equal(plain["rgba"], zero["rgba"])
+    assert np.all(shad["rgba"][:, :3] <= plain["rgba"][:, :3] + 1e-15)
+    assert (shad["rgba"][:, :3] < plain["rgba"][:, :3] - 1e-6).any()
+    np.testing.assert_array_equal(shad["rgba"][:, 3], plain["rgba"][:, 3])
+    np.testing.assert_array_equal(shad["depth"], plain["depth"])
+    np.testing.assert_array_equal(shad["samples"], plain["samples"])
