@@ -55,6 +55,10 @@ def parse():
                     help="compression-efficiency sweep instead of the frame benchmark: "
                          "stream compaction vs naive rejection vs the ideal rate")
     ap.add_argument("--sweep-frames", type=int, default=12)
+    ap.add_argument("--shadow-step", type=float, default=0.0,
+                    help="global shadows: shadow-ray segment length in voxels (0 = off; the "
+                         "paper's renderer uses 4 x step = 2.0); the CPU-oracle leg is skipped "
+                         "with shadows (its dense reference frame would take hours)")
     return ap.parse_args()
 
 
@@ -108,7 +112,7 @@ def compression_sweep(args):
     if V != 1:
         sys.exit("the sweep runs single-view workloads")
     vol, tf = make_inputs(wl)
-    mp = synthetic.march_params(shading=wl["shading"])
+    mp = synthetic.march_params(shading=wl["shading"], shadow_step=args.shadow_step)
     vol_t = torch.from_numpy(vol).to(dev)
     volh = b.Volume(vol_t)
     del vol_t
@@ -184,6 +188,7 @@ def compression_sweep(args):
             rate_naive_march_only=round(t_dense / t_naive, 3)))
         print(json.dumps(rows[-1]), flush=True)
     print(json.dumps({"sweep": "compression efficiency", "workload": args.workload,
+                      "shadow_step": mp["shadow_step"],
                       "dense_ms": round(t_dense, 4), "frames": nf, "rows": rows}), flush=True)
 
 
@@ -210,7 +215,7 @@ def main():
     wl = synthetic.WORKLOADS[args.workload]
     W, H, V = wl["width"], wl["height"], wl["views"]
     vol, tf = make_inputs(wl)
-    mp = synthetic.march_params(shading=wl["shading"])
+    mp = synthetic.march_params(shading=wl["shading"], shadow_step=args.shadow_step)
     sig_frac = wl.get("sigma_frac", 0.15)
     eye_off = wl.get("eye_offset", 0.0)
 
@@ -368,6 +373,8 @@ def main():
                    "step_vox": mp["step_vox"], "alpha_stop": mp["alpha_stop"],
                    "fovea": {"sigma_px": fps[0]["sigma_px"], "p_floor": fps[0]["p_floor"],
                              "mode": "clamp"},
+                   "shadows": ({"shadow_step": mp["shadow_step"]} if mp["shadow_step"] > 0
+                               else "none"),
                    "reconstruction": "U-Net 32/48/64/96 + 5x5 KPN, %s" % args.precision},
         "dense_ms_per_frame": round(dense_ms, 4),
         "speedup_vs_dense": round(dense_ms / fov_ms, 3),
@@ -390,7 +397,7 @@ def main():
         "roofline": roofline,
     }
 
-    if not args.no_cpu:
+    if not args.no_cpu and mp["shadow_step"] == 0:
         out["cpu_baseline"] = cpu_baseline(vol, tf, cam_list[last_k], fps[last_k], W, H, V, mp,
                                            args.cpu_rays, np.load(args.weights), args.net_crop,
                                            fov_out.cpu().numpy(), dframe.view(-1, 4).cpu().numpy())

@@ -178,6 +178,13 @@ fv_status fv_volume_destroy(fv_volume* v);
  * c = rgb (ka + kd |n.L|) + ks |n.Hv|^shininess, the power computed as
  * exp2(shininess log2 x) with the hardware exp2/log2 (relative error a few
  * 1e-6 at shininess 32).
+ * Global shadows (shading != 0 and shadow_step > 0; paper "Foveated
+ * Rendering": one shadow ray per sample towards the light at a lower sample
+ * rate): from the sample's position q (voxel index space, where the box is
+ * [-1/2, n-1/2] per axis) a ray along L runs to the box exit, L_s voxel
+ * lengths away, in ceil(L_s/shadow_step) midpoint-sampled segments (the last
+ * shorter); with tau = sum sigma_j len_j over them,
+ * c = rgb (ka + e^-tau kd |n.L|) + e^-tau ks |n.Hv|^shininess.
  * Compositing front to back in FP32 with early termination:
  *   w = T alpha_k; C += w c; D += w t_k; T *= (1 - alpha_k);
  *   stop once 1 - T >= alpha_stop.
@@ -203,6 +210,9 @@ typedef struct {
   float ka, kd, ks;
   float shininess;   /* specular exponent, in [0, 1024] when shading      */
   float bg[3];       /* background colour                                 */
+  float shadow_step; /* global shadows (shading only): 0 = none, else the
+                        shadow-ray segment length in voxels, in [1/64, 64];
+                        the paper's renderer uses 4 x step_vox           */
 } fv_march_params;
 
 #define FV_TF_ENTRIES 256
@@ -218,7 +228,8 @@ typedef struct {
  * Errors: null v/tf/cams/params/frame_rgba, width/height/views <= 0,
  * views > 8, views*W*H >= 2^32, W or H > 65535, tf_n != 256, step_vox
  * outside [1/64, 64], alpha_stop outside (0,1], a zero light_dir or a
- * shininess outside [0, 1024] with shading, shading not 0/1
+ * shininess outside [0, 1024] with shading, shadow_step not 0 and outside
+ * [1/64, 64], shading not 0/1
  * (FV_ERR_UNSUPPORTED), non-finite camera, fovy outside (0,180), eye ==
  * target or up parallel to the view direction. */
 fv_status fv_raymarch_dense(const fv_volume* v, const float* tf_rgba, int tf_n,

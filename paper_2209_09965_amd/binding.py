@@ -45,7 +45,8 @@ class MarchParams(ctypes.Structure):
     _fields_ = [("step_vox", ctypes.c_float), ("alpha_stop", ctypes.c_float),
                 ("shading", ctypes.c_int32), ("light_dir", ctypes.c_float * 3),
                 ("ka", ctypes.c_float), ("kd", ctypes.c_float), ("ks", ctypes.c_float),
-                ("shininess", ctypes.c_float), ("bg", ctypes.c_float * 3)]
+                ("shininess", ctypes.c_float), ("bg", ctypes.c_float * 3),
+                ("shadow_step", ctypes.c_float)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -145,6 +146,7 @@ def march_params(m):
     mp.light_dir[:] = [float(v) for v in m.get("light_dir", (1.0, 1.0, 1.0))]
     mp.ka, mp.kd, mp.ks = float(m.get("ka", 0.2)), float(m.get("kd", 0.7)), float(m.get("ks", 0.3))
     mp.shininess = float(m.get("shininess", 32.0))
+    mp.shadow_step = float(m.get("shadow_step", 0.0))
     mp.bg[:] = [float(v) for v in m.get("bg", (0.0, 0.0, 0.0))]
     return mp
 

@@ -35,6 +35,8 @@ struct MarchArgs {
   double step;
   float alpha_stop;
   float light[3];  // normalised, towards the light
+  double lightd[3];  // the same in FP64 (shadow-ray positions)
+  double shadow_step;  // shadow-ray segment length in voxels (0: no shadows)
   float ka, kd, ks, shininess;
   float bg[3];
   CamD cam[kMaxViews];
@@ -220,6 +222,97 @@ __device__ __forceinline__ void select_stencil(bool c, const Stencil<DT, SHADE>&
   for (int i = 0; i < 3; ++i) dst.w[i] = c ? src.w[i] : dst.w[i];
 }
 
+// Voxel index space position of segment k (the last one may be shorter).
+__device__ __forceinline__ double seg_pos(const RayState& s, int k, int i) {
+  const double kk = k == s.N - 1 ? s.klast : (double)k;
+  return fma(kk, s.qs[i], s.q0[i]);
+}
+
+constexpr int kMaxShadowSegs = 1 << 20;  // a bound on every shadow loop
+constexpr int kShadowBufs = 2;           // shadow segments in flight per lane
+
+// Global ray-marched shadow: transmittance from the sample at voxel-index
+// position q towards the (directional) light.  The shadow ray runs to where
+// it leaves the box [-1/2, n - 1/2]^3, in segments of shadow_step voxel
+// lengths sampled at their midpoints (the last one shorter), and the light is
+// attenuated by exp(-sum sigma_j len_j).  Positions are FP64 and split into a
+// cell and FP32 weights like the primary samples; the two-buffer loop issues
+// the loads of segment j + 1 before segment j is blended.
+template <int DT>
+__device__ __forceinline__ float shadow_transmittance(const MarchArgs& a,
+                                                      const float4* __restrict__ tfs,
+                                                      const double q[3]) {
+  using VT = typename Voxel<DT>::T;
+  double L = INFINITY;
+  for (int i = 0; i < 3; ++i) {
+    const double l = a.lightd[i];
+    if (l == 0.0) continue;
+    const double face = l > 0.0 ? (double)a.n[i] - 0.5 : -0.5;
+    L = fmin(L, (face - q[i]) / l);
+  }
+  if (!(L > 0.0)) return 1.0f;
+  const double ds = a.shadow_step;
+  const int ns = (int)fmin(ceil(L / ds), (double)kMaxShadowSegs);
+  constexpr int EB = (int)sizeof(VT);
+  const __amdgpu_buffer_rsrc_t rs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)a.vol, (short)0, (int)a.vol_bytes, 0x00020000);
+  const int sy = (int)a.px * EB, sz = (int)(a.px * a.py) * EB;
+  struct Cell {
+    VT c[8];
+    float w[3];
+    float len;
+  };
+  auto load = [&](int j, Cell& cl) {
+    const double a0 = (double)j * ds, b0 = fmin((double)(j + 1) * ds, L);
+    const double m = 0.5 * (a0 + b0);
+    cl.len = (float)(b0 - a0);
+    int ii[3];
+    for (int i = 0; i < 3; ++i) {
+      const double p = fma(m, a.lightd[i], q[i]);
+      const double fp = floor(p);
+      cl.w[i] = (float)(p - fp);
+      ii[i] = min(max((int)fp, -1), a.n[i] - 1);
+    }
+    const int o = (int)(((uint32_t)(ii[2] + 1) * (uint32_t)(a.px * a.py) +
+                         (uint32_t)(ii[1] + 1) * (uint32_t)a.px + (uint32_t)(ii[0] + 1)) * EB);
+    for (int z = 0; z < 2; ++z)
+      for (int y = 0; y < 2; ++y)
+        for (int x = 0; x < 2; ++x)
+          cl.c[x + 2 * y + 4 * z] =
+              buffer_voxel<VT>(rs, o + (1 + x) * EB, (1 + y) * sy + (1 + z) * sz);
+  };
+  auto sigma = [&](const Cell& cl) {
+#define FV_C(x, y, z) Voxel<DT>::f(cl.c[(x) + 2 * (y) + 4 * (z)])
+    const float v = tri(FV_C(0, 0, 0), FV_C(1, 0, 0), FV_C(0, 1, 0), FV_C(1, 1, 0),
+                        FV_C(0, 0, 1), FV_C(1, 0, 1), FV_C(0, 1, 1), FV_C(1, 1, 1), cl.w[0],
+                        cl.w[1], cl.w[2]);
+#undef FV_C
+    const float xv = fminf(fmaxf(v, 0.0f), 1.0f) * 255.0f;
+    const int j = min((int)xv, 254);
+    return lerpf(tfs[j].w, tfs[j + 1].w, xv - (float)j);
+  };
+  // kShadowBufs cells in flight: at the top of each pass C[u] holds segment
+  // j + u (indices past the last segment are clamped to it, loaded and never
+  // blended)
+  constexpr int NS = kShadowBufs;
+  float tau = 0.0f;
+  Cell C[NS];
+#pragma unroll
+  for (int u = 0; u < NS - 1; ++u) load(min(u, ns - 1), C[u]);
+  int j = 0;
+  bool more = true;
+  while (more) {
+#pragma unroll
+    for (int u = 0; u < NS; ++u) {
+      if (!more) break;
+      load(min(j + NS - 1, ns - 1), C[(u + NS - 1) % NS]);
+      tau = fmaf(sigma(C[u]), C[u].len, tau);
+      more = ++j < ns;
+    }
+  }
+  return __expf(-tau);
+}
+
 // The shaded result of one segment: colour, transmittance exp(-sigma l) and
 // the world-space distance of its sample point.
 struct Segment {
@@ -227,8 +320,9 @@ struct Segment {
 };
 
 // One segment k from its gathered voxels: trilinear sample (plus the
-// central-difference gradient and Blinn-Phong when shading) and TF lookup.
-template <int DT, bool SHADE>
+// central-difference gradient and Blinn-Phong when shading, with the light
+// attenuated by the shadow ray's transmittance when SHADOW) and TF lookup.
+template <int DT, bool SHADE, bool SHADOW = false>
 __device__ __forceinline__ Segment shade(const MarchArgs& a, const float4* __restrict__ tfs,
                                          const RayState& s, int k,
                                          const Stencil<DT, SHADE>& st) {
@@ -280,8 +374,17 @@ __device__ __forceinline__ Segment shade(const MarchArgs& a, const float4* __res
     const float nx = -gx * inv, ny = -gy * inv, nz = -gz * inv;
     const float ndl = fabsf(nx * a.light[0] + ny * a.light[1] + nz * a.light[2]);
     const float ndh = fabsf(nx * s.hv[0] + ny * s.hv[1] + nz * s.hv[2]);
-    const float spec = a.ks * pow01(ndh, a.shininess);
-    const float diff = a.ka + a.kd * ndl;
+    float spec = a.ks * pow01(ndh, a.shininess);
+    float diff;
+    if constexpr (SHADOW) {
+      // the light reaching the sample (diffuse and specular) is attenuated
+      const double q[3] = {seg_pos(s, k, 0), seg_pos(s, k, 1), seg_pos(s, k, 2)};
+      const float ts = shadow_transmittance<DT>(a, tfs, q);
+      diff = a.ka + ts * (a.kd * ndl);
+      spec = ts * spec;
+    } else {
+      diff = a.ka + a.kd * ndl;
+    }
     r = r * diff + spec;
     g = g * diff + spec;
     bl = bl * diff + spec;
@@ -305,10 +408,10 @@ __device__ __forceinline__ bool accumulate(const MarchArgs& a, RayState& s, cons
   return last || 1.0f - s.T >= a.alpha_stop;
 }
 
-template <int DT, bool SHADE>
+template <int DT, bool SHADE, bool SHADOW>
 __device__ __forceinline__ bool composite(const MarchArgs& a, const float4* __restrict__ tfs,
                                           RayState& s, const Stencil<DT, SHADE>& st) {
-  return accumulate(a, s, shade(a, tfs, s, s.k, st));
+  return accumulate(a, s, shade<DT, SHADE, SHADOW>(a, tfs, s, s.k, st));
 }
 
 __device__ __forceinline__ RayOut ray_finish(const MarchArgs& a, const RayState& s) {
@@ -332,7 +435,7 @@ __device__ __forceinline__ RayOut ray_miss(const MarchArgs& a) {
 // issued before sample k is composited (two stencil buffers, A and B), so the
 // memory latency of one sample overlaps the arithmetic of the previous one.
 // The sample after the last is never read: its index is clamped to N - 1.
-template <int DT, bool SHADE>
+template <int DT, bool SHADE, bool SHADOW>
 __device__ __forceinline__ RayOut march_ray(const MarchArgs& a, const float4* __restrict__ tfs,
                                             int view, int x, int y) {
   RayState s;
@@ -342,9 +445,9 @@ __device__ __forceinline__ RayOut march_ray(const MarchArgs& a, const float4* __
     gather(a, s, 0, A);
     while (true) {
       gather(a, s, min(s.k + 1, s.N - 1), B);
-      if (composite(a, tfs, s, A)) break;
+      if (composite<DT, SHADE, SHADOW>(a, tfs, s, A)) break;
       gather(a, s, min(s.k + 1, s.N - 1), A);
-      if (composite(a, tfs, s, B)) break;
+      if (composite<DT, SHADE, SHADOW>(a, tfs, s, B)) break;
     }
   }
   return ray_finish(a, s);
@@ -359,7 +462,7 @@ __device__ __forceinline__ void add_samples(unsigned long long* nsamp, uint32_t 
 // Dense: a 256-thread block covers a 16x16 pixel block as four 8x8 wave tiles.
 // With a sample map (naive rejection), a thread whose pixel is not sampled
 // returns at once; the others march as in the dense frame.
-template <int DT, bool SHADE>
+template <int DT, bool SHADE, bool SHADOW>
 __global__ void __launch_bounds__(256) k_march_dense(MarchArgs a, const uint8_t* __restrict__ mask,
                                                      float4* __restrict__ rgba,
                                                      float* __restrict__ depth,
@@ -374,7 +477,7 @@ __global__ void __launch_bounds__(256) k_march_dense(MarchArgs a, const uint8_t*
   const uint32_t lin = (uint32_t)view * (uint32_t)a.W * (uint32_t)a.H + (uint32_t)y * a.W + x;
   uint32_t ns = 0;
   if (x < a.W && y < a.H && (!mask || mask[lin])) {
-    const RayOut r = march_ray<DT, SHADE>(a, tfs, view, x, y);
+    const RayOut r = march_ray<DT, SHADE, SHADOW>(a, tfs, view, x, y);
     rgba[lin] = r.rgba;
     if (depth) depth[lin] = r.depth;
     ns = r.samples;
@@ -480,6 +583,16 @@ __global__ void __launch_bounds__(256) k_setup_list(MarchArgs a,
 // with the same operations as the single-lane march, so the pixel is the
 // same bit for bit and the group's lanes keep identical ray state.
 constexpr int kStepsPerRefill = 9;
+// With shadows each segment runs its own shadow loop, whose length depends
+// on where the sample is: one primary sample ahead and a register budget for
+// two waves per SIMD (the shadowed full list took 30.7 ms with one wave and
+// two samples ahead, 21.5 ms with this), and claims only by whole idle waves
+// every 4 segments, so a wave's lanes step through neighbouring rays in lock
+// step and their shadow loops stay about equally long (21.5 -> 10.5 ms, the
+// dense march's time for the same rays).
+constexpr int kSparseAheadShadow = 1;
+constexpr int kStepsPerRefillShadow = 4;
+constexpr int kRefillMinShadow = 64;
 constexpr int kRefillMin = 32;
 constexpr int kSparseAhead = 2;
 // G is the largest of 1, 2, 4, 8 with h G^2 <= kGroupRule, h = (rays that
@@ -519,7 +632,7 @@ __device__ __forceinline__ bool group_accumulate(const MarchArgs& a, RayState& s
   }
 }
 
-template <int DT, bool SHADE, int G>
+template <int DT, bool SHADE, bool SHADOW, int G>
 __device__ __forceinline__ void march_list(const MarchArgs& a, const float4* __restrict__ tfs,
                                            const uint32_t* __restrict__ ray_idx, uint32_t n,
                                            const SetupList& l, float4* __restrict__ rgba_c,
@@ -527,8 +640,9 @@ __device__ __forceinline__ void march_list(const MarchArgs& a, const float4* __r
                                            float4* __restrict__ rgba_f,
                                            float* __restrict__ depth_f, uint32_t& ns,
                                            uint32_t* __restrict__ queue) {
-  constexpr int NB = kSparseAhead + 1;
-  static_assert(kStepsPerRefill % NB == 0, "steps per refill round: a multiple of the buffers");
+  constexpr int NB = (SHADOW ? kSparseAheadShadow : kSparseAhead) + 1;
+  constexpr int kSteps = SHADOW ? kStepsPerRefillShadow : kStepsPerRefill;
+  static_assert(kSteps % NB == 0, "steps per refill round: a multiple of the buffers");
   const int lane = threadIdx.x & 63, r = lane & (G - 1);
   const uint64_t lt = lane ? (~0ull >> (64 - lane)) : 0ull;
   // Idle lanes run the loop body too, so their state and buffers start
@@ -550,7 +664,7 @@ __device__ __forceinline__ void march_list(const MarchArgs& a, const float4* __r
     const bool want = !active && !exhausted;
     const uint64_t m = __ballot(want);  // G bits per idle group
     bool fresh = false;  // claimed a ray this round that needs marching
-    if (m && (__popcll(m) >= kRefillMin || !__ballot(active))) {
+    if (m && (__popcll(m) >= (SHADOW ? kRefillMinShadow : kRefillMin) || !__ballot(active))) {
       const int leader = __ffsll((long long)m) - 1;
       uint32_t base = 0;
       if (lane == leader) base = atomicAdd(queue, (uint32_t)__popcll(m) / G);
@@ -606,11 +720,12 @@ __device__ __forceinline__ void march_list(const MarchArgs& a, const float4* __r
     // Segments past the last one are clamped to it: they are shaded but
     // never composited.
 #pragma unroll 1
-    for (int it = 0; it < kStepsPerRefill; it += NB) {
+    for (int it = 0; it < kSteps; it += NB) {
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         gather(a, s, min(s.k + r + G * (NB - 1), s.N - 1), S[(j + NB - 1) % NB], active);
-        const Segment o = shade(a, tfs, s, G == 1 ? s.k : min(s.k + r, s.N - 1), S[j]);
+        const Segment o =
+            shade<DT, SHADE, SHADOW>(a, tfs, s, G == 1 ? s.k : min(s.k + r, s.N - 1), S[j]);
         if (group_accumulate<G>(a, s, o, false) && active) {
           fin = ray_finish(a, s);
           done = true;
@@ -628,8 +743,9 @@ __device__ __forceinline__ void march_list(const MarchArgs& a, const float4* __r
   }
 }
 
-template <int DT, bool SHADE>
-__global__ void __launch_bounds__(256) k_march_sparse(
+template <int DT, bool SHADE, bool SHADOW>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(SHADOW ? 2 : 1)))
+k_march_sparse(
     MarchArgs a, const uint32_t* __restrict__ ray_idx, const uint32_t* __restrict__ count,
     uint32_t capacity, SetupList l, float4* __restrict__ rgba_c, float* __restrict__ depth_c,
     float4* __restrict__ rgba_f, float* __restrict__ depth_f,
@@ -649,16 +765,16 @@ __global__ void __launch_bounds__(256) k_march_sparse(
   uint32_t ns = 0;
   switch (g) {
     case 8:
-      march_list<DT, SHADE, 8>(a, tfs, ray_idx, n, l, rgba_c, depth_c, rgba_f, depth_f, ns, queue);
+      march_list<DT, SHADE, SHADOW, 8>(a, tfs, ray_idx, n, l, rgba_c, depth_c, rgba_f, depth_f, ns, queue);
       break;
     case 4:
-      march_list<DT, SHADE, 4>(a, tfs, ray_idx, n, l, rgba_c, depth_c, rgba_f, depth_f, ns, queue);
+      march_list<DT, SHADE, SHADOW, 4>(a, tfs, ray_idx, n, l, rgba_c, depth_c, rgba_f, depth_f, ns, queue);
       break;
     case 2:
-      march_list<DT, SHADE, 2>(a, tfs, ray_idx, n, l, rgba_c, depth_c, rgba_f, depth_f, ns, queue);
+      march_list<DT, SHADE, SHADOW, 2>(a, tfs, ray_idx, n, l, rgba_c, depth_c, rgba_f, depth_f, ns, queue);
       break;
     default:
-      march_list<DT, SHADE, 1>(a, tfs, ray_idx, n, l, rgba_c, depth_c, rgba_f, depth_f, ns, queue);
+      march_list<DT, SHADE, SHADOW, 1>(a, tfs, ray_idx, n, l, rgba_c, depth_c, rgba_f, depth_f, ns, queue);
   }
   if (nsamp) add_samples(nsamp, ns);
 }
@@ -711,6 +827,10 @@ fv_status fill_args(const fv_volume* v, const float* tf, int tf_n, const fv_came
   if (mp->shading && !(ll > 0.0 && std::isfinite(ll)))
     return fail(FV_ERR_INVALID_ARG, "%s: light_dir must be non-zero", fn);
   for (int i = 0; i < 3; ++i) a->light[i] = ll > 0.0 ? (float)(L[i] / ll) : 0.0f;
+  for (int i = 0; i < 3; ++i) a->lightd[i] = ll > 0.0 ? L[i] / ll : 0.0;
+  if (!(mp->shadow_step == 0.0f || (mp->shadow_step >= 1.0f / 64.0f && mp->shadow_step <= 64.0f)))
+    return fail(FV_ERR_INVALID_ARG, "%s: shadow_step must be 0 or in [1/64, 64]", fn);
+  a->shadow_step = mp->shading ? (double)mp->shadow_step : 0.0;
   a->ka = mp->ka;
   a->kd = mp->kd;
   a->ks = mp->ks;
@@ -756,11 +876,11 @@ fv_status fill_args(const fv_volume* v, const float* tf, int tf_n, const fv_came
   return FV_OK;
 }
 
-template <int DT, bool SHADE>
+template <int DT, bool SHADE, bool SHADOW>
 void launch_dense(const MarchArgs& a, const uint8_t* mask, float* rgba, float* depth,
                   uint64_t* ns, hipStream_t s) {
   dim3 grid((a.W + 15) / 16, (a.H + 15) / 16, a.views);
-  k_march_dense<DT, SHADE><<<grid, 256, 0, s>>>(a, mask, (float4*)rgba, depth,
+  k_march_dense<DT, SHADE, SHADOW><<<grid, 256, 0, s>>>(a, mask, (float4*)rgba, depth,
                                                 (unsigned long long*)ns);
 }
 
@@ -776,24 +896,27 @@ fv_status dense_entry(const char* who, const fv_volume* v, const float* tf_rgba,
   if (!frame_rgba) return fail(FV_ERR_INVALID_ARG, "%s: null frame_rgba", who);
   if (need_mask && !mask) return fail(FV_ERR_INVALID_ARG, "%s: null mask", who);
   hipStream_t s = (hipStream_t)stream;
-  const bool sh = mp->shading != 0;
+  // 0: emission-absorption, 1: Blinn-Phong, 2: Blinn-Phong with shadows
+  const int mode = mp->shading == 0 ? 0 : (a.shadow_step > 0.0 ? 2 : 1);
+#define FV_DENSE(DT)                                                                         \
+  (mode == 0   ? launch_dense<DT, false, false>(a, mask, frame_rgba, frame_depth, sample_count, s) \
+   : mode == 1 ? launch_dense<DT, true, false>(a, mask, frame_rgba, frame_depth, sample_count, s)  \
+               : launch_dense<DT, true, true>(a, mask, frame_rgba, frame_depth, sample_count, s))
   switch (v->dt) {
     case FV_U8:
-      sh ? launch_dense<FV_U8, true>(a, mask, frame_rgba, frame_depth, sample_count, s)
-         : launch_dense<FV_U8, false>(a, mask, frame_rgba, frame_depth, sample_count, s);
+      FV_DENSE(FV_U8);
       break;
     case FV_F16:
-      sh ? launch_dense<FV_F16, true>(a, mask, frame_rgba, frame_depth, sample_count, s)
-         : launch_dense<FV_F16, false>(a, mask, frame_rgba, frame_depth, sample_count, s);
+      FV_DENSE(FV_F16);
       break;
     default:
-      sh ? launch_dense<FV_F32, true>(a, mask, frame_rgba, frame_depth, sample_count, s)
-         : launch_dense<FV_F32, false>(a, mask, frame_rgba, frame_depth, sample_count, s);
+      FV_DENSE(FV_F32);
   }
+#undef FV_DENSE
   return launch_status(who);
 }
 
-template <int DT, bool SHADE>
+template <int DT, bool SHADE, bool SHADOW>
 void launch_sparse(const MarchArgs& a, const uint32_t* idx, const uint32_t* count,
                    uint32_t capacity, float* rc, float* dc, float* rf, float* df, uint64_t* ns,
                    void* ws, hipStream_t s) {
@@ -805,7 +928,7 @@ void launch_sparse(const MarchArgs& a, const uint32_t* idx, const uint32_t* coun
     int dev = 0;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march_sparse<DT, SHADE>, 256,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_march_sparse<DT, SHADE, SHADOW>, 256,
                                                      0) != hipSuccess || per_cu < 1)
       per_cu = 4;
     if (cus < 1) cus = 256;
@@ -815,7 +938,7 @@ void launch_sparse(const MarchArgs& a, const uint32_t* idx, const uint32_t* coun
   if (grid > need) grid = need;
   k_clear_queue<<<1, 64, 0, s>>>(queue);
   k_setup_list<SHADE><<<(unsigned)need, 256, 0, s>>>(a, idx, count, capacity, l, queue);
-  k_march_sparse<DT, SHADE><<<(unsigned)grid, 256, 0, s>>>(a, idx, count, capacity, l,
+  k_march_sparse<DT, SHADE, SHADOW><<<(unsigned)grid, 256, 0, s>>>(a, idx, count, capacity, l,
                                                            (float4*)rc, dc, (float4*)rf, df,
                                                            (unsigned long long*)ns, queue);
 }
@@ -875,13 +998,14 @@ fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba, int tf_n,
   if (!rgba_compact && !depth_compact && !frame_rgba && !frame_depth)
     return fv::fail(FV_ERR_INVALID_ARG, "fv_raymarch_sparse: no output given");
   hipStream_t s = (hipStream_t)stream;
-  const bool sh = mp->shading != 0;
-#define FV_SPARSE(DT)                                                                          \
-  (sh ? fv::launch_sparse<DT, true>(a, ray_idx, count, capacity, rgba_compact, depth_compact, \
-                                    frame_rgba, frame_depth, sample_count, workspace, s)      \
-      : fv::launch_sparse<DT, false>(a, ray_idx, count, capacity, rgba_compact,               \
-                                     depth_compact, frame_rgba, frame_depth, sample_count,    \
-                                     workspace, s))
+  // 0: emission-absorption, 1: Blinn-Phong, 2: Blinn-Phong with shadows
+  const int mode = mp->shading == 0 ? 0 : (a.shadow_step > 0.0 ? 2 : 1);
+#define FV_SPARSE_M(DT, SH, SW)                                                         \
+  fv::launch_sparse<DT, SH, SW>(a, ray_idx, count, capacity, rgba_compact, depth_compact, \
+                                frame_rgba, frame_depth, sample_count, workspace, s)
+#define FV_SPARSE(DT)                                                                     \
+  (mode == 0 ? FV_SPARSE_M(DT, false, false)                                            \
+             : mode == 1 ? FV_SPARSE_M(DT, true, false) : FV_SPARSE_M(DT, true, true))
   switch (v->dt) {
     case FV_U8:
       FV_SPARSE(FV_U8);
@@ -893,6 +1017,7 @@ fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba, int tf_n,
       FV_SPARSE(FV_F32);
   }
 #undef FV_SPARSE
+#undef FV_SPARSE_M
   return fv::launch_status("fv_raymarch_sparse");
 }
 

@@ -237,17 +237,15 @@ __global__ void __launch_bounds__(256) k_heads(const uint8_t* __restrict__ hdec,
       lg[j] = (j < 4 ? d0[j] : d1[j - 4]) + bias[j];
       mx = fmaxf(mx, lg[j]);
     }
-    mx = fmaxf(mx, __shfl_xor(mx, 16, 64));
-    mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+    mx = pair_max32(pair_max16(mx));
     float den = 0.f;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       lg[j] = __expf(lg[j] - mx);
       den += lg[j];
     }
-    den += __shfl_xor(den, 16, 64);
-    den += __shfl_xor(den, 32, 64);
-    const float inv = 1.0f / den;
+    den = pair_sum32(pair_sum16(den));
+    const float inv = __builtin_amdgcn_rcpf(den);  // hardware reciprocal (1 ulp)
     const float4* win = s_od + ty * HW + col;  // top-left of this pixel's 5 x 5 window
     float o0 = 0.f, o1 = 0.f, o2 = 0.f;
 #pragma unroll
@@ -258,12 +256,9 @@ __global__ void __launch_bounds__(256) k_heads(const uint8_t* __restrict__ hdec,
       o1 = fmaf(lg[j], od.y, o1);
       o2 = fmaf(lg[j], od.z, o2);
     }
-    o0 += __shfl_xor(o0, 16, 64);
-    o1 += __shfl_xor(o1, 16, 64);
-    o2 += __shfl_xor(o2, 16, 64);
-    o0 += __shfl_xor(o0, 32, 64);
-    o1 += __shfl_xor(o1, 32, 64);
-    o2 += __shfl_xor(o2, 32, 64);
+    o0 = pair_sum32(pair_sum16(o0));
+    o1 = pair_sum32(pair_sum16(o1));
+    o2 = pair_sum32(pair_sum16(o2));
     if (y >= h || x >= w) continue;
     const int64_t p = ((int64_t)b * h + y) * w + x;
     if (grp == 0) {

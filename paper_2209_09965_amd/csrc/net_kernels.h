@@ -181,6 +181,36 @@ struct FP8 {
   }
 };
 
+// Cross-lane partners without an LDS round trip.  The gfx950 lane-swap
+// instructions (rows of 16 lanes, halves of 32) leave v[l] and v[l ^ 16]
+// (resp. v[l ^ 32]) in their two results at every lane l, in an order that
+// depends on the lane; the sum or maximum of the two is therefore what
+// v + v[l ^ m] (resp. max) gives, since both operations are commutative.
+__device__ __forceinline__ float pair_sum16(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float pair_sum32(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float pair_max16(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                  false);
+  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+__device__ __forceinline__ float pair_max32(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false,
+                                                  false);
+  return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+// v of lane l ^ 1 (a quad permutation [1, 0, 3, 2])
+__device__ __forceinline__ float lane_xor1(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+
 __device__ __forceinline__ void wave_absmax(float* dst, float m) {
   for (int off = 32; off; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
   if ((threadIdx.x & 63) == 0 && m > 0.f) atomicMax((unsigned int*)dst, __float_as_uint(m));
@@ -805,7 +835,7 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const float t0 = E::rnd_act(st[rr][i]), t1 = E::rnd_act(st[rr + 1][i]);
-            const float n0 = __shfl_xor(t0, 1, 64), n1 = __shfl_xor(t1, 1, 64);
+            const float n0 = lane_xor1(t0), n1 = lane_xor1(t1);
             pv[i] = (((t0 + n0) + t1) + n1) * 0.25f;
           }
           if (yb + rr >= a.h) continue;

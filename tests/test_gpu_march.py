@@ -340,3 +340,81 @@ def test_masked_null_mask_rejected(dev):
         b.raymarch_masked(vol, tf_t, [synthetic.orbit_camera(0)], 8, 8, synthetic.march_params(),
                           None, frame)
     vol.close()
+
+
+# ------------------------------------------------------------------ shadows
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3, 4, 5])
+def test_shadows_dense_vs_oracle(seed, dev):
+    """Global shadows (one shadow ray per sample towards the light, segments of
+    shadow_step voxels): small volumes of the three voxel types, oblique lights,
+    a camera inside the box for one seed, against the FP64 oracle at 1e-5."""
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(900 + seed)
+    n = [int(rng.choice([9, 16, 24, 33])) for _ in range(3)]
+    dt = [np.uint8, np.float16, np.float32][seed % 3]
+    if dt == np.uint8:
+        vol = synthetic.blob_volume(seed, 32)[: n[2], : n[1], : n[0]].copy()
+        tf = synthetic.tf_blob(seed)
+        tf[:, 3] *= 3
+    else:
+        vol = synthetic.value_noise_volume(seed, n=max(n), octaves=3, base_period=8)
+        vol = vol[: n[2], : n[1], : n[0]].astype(dt)
+        tf = synthetic.tf_noise(seed)
+        tf[:, 3] *= float(rng.uniform(2, 10))
+    if seed == 5:  # inside the box
+        cam = dict(eye=(0.05, -0.1, 0.08), target=(0.3, -0.2, 0.1), up=(0.0, 1.0, 0.0),
+                   fovy_deg=70.0, eye_offset=0.0)
+    else:
+        cam = synthetic.orbit_camera(int(rng.integers(60)), phi_deg=float(rng.uniform(-40, 40)))
+    light = tuple(float(v) for v in rng.normal(size=3))
+    if seed == 0:
+        light = (0.0, 1.0, 0.0)  # along an axis: two components zero
+    mp = synthetic.march_params(shading=True, light_dir=light,
+                                shadow_step=float(rng.choice([0.5, 2.0, 3.3])),
+                                bg=(0.05, 0.1, 0.0))
+    W, H = 37, 29
+    rgba, depth, cnt = gpu_dense(b, torch.from_numpy(vol).to(dev), _tf_t(tf, dev), [cam], W, H,
+                                 mp, dev)
+    ora = oracle.march(vol, tf, [cam], W, H, mp, alts=True)
+    _check(rgba, depth, ora, "shadows seed %d" % seed)
+    # shadows only darken: the same frame without them is never darker
+    mp0 = dict(mp, shadow_step=0.0)
+    rgba0, _, _ = gpu_dense(b, torch.from_numpy(vol).to(dev), _tf_t(tf, dev), [cam], W, H, mp0,
+                            dev)
+    assert np.all(rgba[:, :3] <= rgba0[:, :3] + 1e-6)
+
+
+def test_shadows_sparse_equals_dense(noise256, dev):
+    """The sparse march with shadows (fovea map at 480x270, few rays: several lanes
+    per ray) equals the dense march bit for bit, and a sample of its rays matches
+    the oracle."""
+    from paper_2209_09965_amd import binding as b
+    vol, tf = noise256
+    W, H = 480, 270
+    cams = [synthetic.orbit_camera(37)]
+    mp = synthetic.march_params(shading=True, shadow_step=2.0)
+    fp = synthetic.fovea_params(W, H, frame=37)
+    vol_t, tf_t = torch.from_numpy(vol).to(dev), _tf_t(tf, dev)
+    sp = _sparse_run(b, vol_t, tf_t, cams, W, H, mp, fp, dev)
+    rgba, depth, cnt = gpu_dense(b, vol_t, tf_t, cams, W, H, mp, dev)
+    idx = sp["idx"]
+    assert sp["n"] > 1000
+    assert np.array_equal(sp["frame"][idx], rgba[idx])
+    assert np.array_equal(sp["fdepth"][idx], depth[idx])
+    rng = np.random.default_rng(5)
+    pick = rng.choice(sp["n"], size=200, replace=False)
+    ora = oracle.march(vol, tf, cams, W, H, mp, idx=sp["idx"][pick], alts=True)
+    _check(sp["rc"][pick], sp["dc"][pick], ora, "noise256 sparse shadows")
+
+
+def test_shadow_step_out_of_range_rejected(dev):
+    from paper_2209_09965_amd import binding as b
+    vol = b.Volume(torch.zeros((8, 8, 8), dtype=torch.uint8, device=dev))
+    frame = torch.zeros(8 * 8 * 4, dtype=torch.float32, device=dev)
+    tf_t = _tf_t(synthetic.tf_blob(1), dev)
+    for bad in (1e-3, 65.0, -1.0, float("nan")):
+        mp = synthetic.march_params(shading=True, shadow_step=bad)
+        with pytest.raises(b.FvError, match="shadow_step"):
+            b.raymarch_dense(vol, tf_t, [synthetic.orbit_camera(0)], 8, 8, mp, frame)
+    vol.close()
