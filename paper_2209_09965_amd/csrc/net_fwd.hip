@@ -350,8 +350,8 @@ void conv_launch(const ConvArgs& a, hipStream_t s) {
     attr_set = true;
   }
   // one block per tile, tiles in (image, row, column) order
-  const int64_t tiles = (int64_t)((a.w + 15) / 16) * ((a.h + 4 * R - 1) / (4 * R)) * a.n;
-  k_conv3x3<E, NB, R><<<(unsigned)tiles, 256, lds, s>>>(a);
+  const dim3 grid((a.w + 15) / 16, (a.h + 4 * R - 1) / (4 * R), a.n);
+  k_conv3x3<E, NB, R><<<grid, 256, lds, s>>>(a);
 }
 
 template <class E, int NB>

@@ -503,10 +503,8 @@ __global__ void __launch_bounds__(256)
   typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i4;
   const int S = patch_stride<E>(a.cip);  // patch pixel stride in elements
   const int tid = threadIdx.x;
-  const int tiles_x = (a.w + 15) / 16, tiles_y = (a.h + 4 * R - 1) / (4 * R);
-  const int x0 = (blockIdx.x % tiles_x) * 16;
-  const int y0 = ((blockIdx.x / tiles_x) % tiles_y) * 4 * R;
-  const int b = blockIdx.x / (tiles_x * tiles_y);
+  // one block per tile: grid (tile columns, tile rows, images)
+  const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4 * R, b = blockIdx.z;
   uint8_t* low = smem + (size_t)PR * PC * S * E::kBytes;
   int* ktab = (int*)(low + (a.up0 ? (size_t)LR * LC * a.c0 * E::kBytes : 0));
   float* s_ab = (float*)(ktab + 4 * E::kSub * a.kc);  // alpha[co], bias[co]
