@@ -59,6 +59,12 @@ def lib():
         L.or_fovea_mask.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_int,
                                     ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_int, u8p, u32p]
+        L.or_fovea_mask_src.restype = ctypes.c_int64
+        L.or_fovea_mask_src.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        ctypes.c_int, u32p, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_int, u8p, u32p]
         L.or_cmax.restype = ctypes.c_double
         L.or_cmax.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                               ctypes.c_double, ctypes.c_double, ctypes.c_int]
@@ -119,6 +125,23 @@ def fovea_mask(seed, frame, width, height, views, focus_x, focus_y, sigma_px, p_
     cnt = lib().or_fovea_mask(seed, frame, width, height, views, float(focus_x), float(focus_y),
                               float(sigma_px), float(p_floor), int(mode),
                               _ptr(mask, ctypes.c_uint8), _ptr(idx, ctypes.c_uint32))
+    if cnt < 0:
+        raise ValueError("mask failed")
+    return mask.reshape(views, height, width), idx[:cnt].copy()
+
+
+def fovea_mask_tiles(tiles, frame, width, height, views, focus_x, focus_y, sigma_px, p_floor,
+                     mode):
+    """Sample map and ordered compaction with the uniform numbers taken from a
+    noise tile stack tiles[count, th, tw] (24-bit values) instead of the hash."""
+    t = np.ascontiguousarray(tiles, dtype=np.uint32)
+    tc, th, tw = t.shape
+    mask = np.zeros(views * height * width, dtype=np.uint8)
+    idx = np.zeros(views * height * width, dtype=np.uint32)
+    cnt = lib().or_fovea_mask_src(0, frame, width, height, views, float(focus_x), float(focus_y),
+                                  float(sigma_px), float(p_floor), int(mode),
+                                  _ptr(t, ctypes.c_uint32), tw, th, tc,
+                                  _ptr(mask, ctypes.c_uint8), _ptr(idx, ctypes.c_uint32))
     if cnt < 0:
         raise ValueError("mask failed")
     return mask.reshape(views, height, width), idx[:cnt].copy()

@@ -122,9 +122,14 @@ int or_fovea_lut(int W, int H, double focus_x, double focus_y, double sigma,
  * ("Stream Compaction"): the selected pixels are listed in the order view,
  * 8x8 tile (row-major over tiles), row-major inside the tile.  mask may be
  * NULL; idx must hold views*W*H entries.  Returns the count, or -1. */
-int64_t or_fovea_mask(uint64_t seed, uint32_t frame, int W, int H, int views,
-                      double focus_x, double focus_y, double sigma,
-                      double p_floor, int mode, uint8_t* mask, uint32_t* idx) {
+/* Sample map + compaction.  The uniform number of each pixel is the seeded
+ * hash, or, when `tiles` is given, the entry of the noise tile stack that
+ * the paper's tileable textures stand for (Sec. 3.1.1): tile
+ * (frame + view) mod tile_count, repeated over the frame. */
+int64_t or_fovea_mask_src(uint64_t seed, uint32_t frame, int W, int H, int views,
+                          double focus_x, double focus_y, double sigma,
+                          double p_floor, int mode, const uint32_t* tiles, int tw,
+                          int th, int tcount, uint8_t* mask, uint32_t* idx) {
   uint32_t* lut = (uint32_t*)malloc(sizeof(uint32_t) * OR_LUT_MAX);
   int n, sh;
   uint32_t tinf;
@@ -147,8 +152,13 @@ int64_t or_fovea_mask(uint64_t seed, uint32_t frame, int W, int H, int views,
             int64_t R = dx * dx + dy * dy;
             int64_t k = R >> sh;
             uint32_t T = k < n ? lut[k] : tinf;
-            uint32_t u = or_noise24(seed, frame, (uint32_t)v, (uint32_t)y,
-                                    (uint32_t)x);
+            uint32_t u;
+            if (tiles) {
+              uint32_t ti = (frame + (uint32_t)v) % (uint32_t)tcount;
+              u = tiles[((size_t)ti * th + (size_t)(y % th)) * tw + (size_t)(x % tw)];
+            } else {
+              u = or_noise24(seed, frame, (uint32_t)v, (uint32_t)y, (uint32_t)x);
+            }
             int m = u < T;
             uint64_t lin = (uint64_t)v * W * H + (uint64_t)y * W + x;
             if (mask) mask[lin] = (uint8_t)m;
@@ -156,6 +166,13 @@ int64_t or_fovea_mask(uint64_t seed, uint32_t frame, int W, int H, int views,
           }
   free(lut);
   return count;
+}
+
+int64_t or_fovea_mask(uint64_t seed, uint32_t frame, int W, int H, int views,
+                      double focus_x, double focus_y, double sigma,
+                      double p_floor, int mode, uint8_t* mask, uint32_t* idx) {
+  return or_fovea_mask_src(seed, frame, W, H, views, focus_x, focus_y, sigma, p_floor,
+                           mode, NULL, 0, 0, 0, mask, idx);
 }
 
 /* Mean of tau over the frame: C_max of Eq. (3), the expected sampled

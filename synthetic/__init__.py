@@ -177,6 +177,67 @@ def fovea_params(width, height, sigma_frac=0.15, p_floor=0.05, mode=0, seed=42, 
                 sigma_px=sigma_frac * height, p_floor=p_floor)
 
 
+# ------------------------------------------------------------- noise tiles
+
+def blue_noise_tile(seed, size=64, sigma=1.9, start=0.1):
+    """A size x size dither array by void-and-cluster (Ulichney, 1993): every
+    rank 0 .. size^2 - 1 once, ranks spread so that every threshold picks an
+    evenly spaced set of pixels.  Energy is the pattern filtered by a wrapped
+    Gaussian of width sigma.  Returns uint32 24-bit values
+    floor((rank + 1/2) 2^24 / size^2)."""
+    n = size * size
+    rng = _rng(seed, 77)
+    d = np.arange(size)
+    d = np.minimum(d, size - d).astype(np.float64)
+    g = np.exp(-(d[:, None] ** 2 + d[None, :] ** 2) / (2 * sigma * sigma))
+
+    def add(e, p, s):
+        y, x = divmod(p, size)
+        e += s * np.roll(np.roll(g, y, 0), x, 1)
+
+    # initial pattern: random minority pixels, relaxed until the tightest
+    # cluster is also the largest void
+    pat = np.zeros((size, size), bool)
+    pat.flat[rng.choice(n, size=max(1, int(start * n)), replace=False)] = True
+    e = np.zeros((size, size))
+    for p in np.flatnonzero(pat):
+        add(e, p, 1.0)
+    for _ in range(10 * n):
+        c = int(np.argmax(np.where(pat, e, -np.inf)))
+        pat.flat[c] = False
+        add(e, c, -1.0)
+        v = int(np.argmin(np.where(pat, np.inf, e)))
+        pat.flat[v] = True
+        add(e, v, 1.0)
+        if v == c:
+            break
+    rank = np.zeros(n, np.int64)
+    ones = int(pat.sum())
+    # phase 1: remove tightest clusters, ranks ones-1 .. 0
+    p1, e1 = pat.copy(), e.copy()
+    for r in range(ones - 1, -1, -1):
+        c = int(np.argmax(np.where(p1, e1, -np.inf)))
+        p1.flat[c] = False
+        add(e1, c, -1.0)
+        rank[c] = r
+    # phases 2 and 3: fill the largest voids, ranks ones .. n-1
+    for r in range(ones, n):
+        v = int(np.argmin(np.where(pat, np.inf, e)))
+        pat.flat[v] = True
+        add(e, v, 1.0)
+        rank[v] = r
+    return ((rank * 2 + 1) * (1 << 24) // (2 * n)).astype(np.uint32).reshape(size, size)
+
+
+def noise_tiles(seed, size=64, count=64, kind="blue"):
+    """A stack of `count` noise tiles [count, size, size] of 24-bit values:
+    independent void-and-cluster arrays ("blue"), or uniform integers
+    ("white")."""
+    if kind == "white":
+        return _rng(seed, 78).integers(0, 1 << 24, (count, size, size), dtype=np.uint32)
+    return np.stack([blue_noise_tile(seed * 1000 + i, size) for i in range(count)])
+
+
 # ---------------------------------------------------------------- workloads
 
 WORKLOADS = {

@@ -135,3 +135,52 @@ def test_compaction_order_and_uniqueness():
     y, x = rem // W, rem % W
     key = (((v * ((H + 7) // 8) + y // 8) * ((W + 7) // 8) + x // 8) * 64 + (y % 8) * 8 + (x % 8))
     assert np.all(np.diff(key) > 0)
+
+
+# ------------------------------------------------------------- noise tiles
+# Sec. 3.1.1: the sample map thresholds tileable noise textures, a different
+# tile each frame, looping over the stack.
+
+def _flat_params(p):
+    # a Gaussian far narrower than a pixel, focused on a pixel corner: tau = p
+    # at every pixel centre
+    return dict(focus_x=10.0, focus_y=10.0, sigma_px=1e-3, p_floor=p, mode=1)
+
+
+def test_stratified_tile_samples_exactly_its_share():
+    """A tile holding every rank 0 .. N-1 once, as (rank + 1/2) 2^24 / N, under
+    tau = 1/4 (T = 2^22) samples exactly N/4 of its pixels: over a frame of
+    3 x 2 tiles exactly a quarter of the pixels."""
+    import synthetic
+    tile = synthetic.blue_noise_tile(4, 16)
+    ranks = np.sort(((tile.astype(np.int64) * 256) >> 24).reshape(-1))
+    assert np.array_equal(ranks, np.arange(256))
+    q = _flat_params(0.25)
+    m, idx = oracle.fovea_mask_tiles(tile[None], 0, 48, 32, 1, q["focus_x"], q["focus_y"],
+                                     q["sigma_px"], q["p_floor"], q["mode"])
+    assert idx.size == 48 * 32 // 4
+    # every 16 x 16 period holds exactly 64 samples
+    per = m[0].reshape(2, 16, 3, 16).sum(axis=(1, 3))
+    assert np.all(per == 64)
+
+
+def test_zero_tiles_sample_everything_with_a_floor():
+    q = _flat_params(0.05)
+    tiles = np.zeros((2, 8, 8), np.uint32)
+    m, idx = oracle.fovea_mask_tiles(tiles, 3, 21, 13, 2, q["focus_x"], q["focus_y"],
+                                     q["sigma_px"], q["p_floor"], q["mode"])
+    assert m.all() and idx.size == 2 * 21 * 13
+
+
+def test_tile_stack_loops_and_views_advance():
+    """Frame f and frame f + count draw the same tile; view v of frame f draws
+    the tile of view 0 in frame f + v."""
+    import synthetic
+    tiles = synthetic.noise_tiles(3, size=8, count=5, kind="white")
+    args = (40, 24)
+    a, _ = oracle.fovea_mask_tiles(tiles, 2, *args, 2, 20.0, 12.0, 6.0, 0.1, 1)
+    b, _ = oracle.fovea_mask_tiles(tiles, 7, *args, 2, 20.0, 12.0, 6.0, 0.1, 1)
+    c, _ = oracle.fovea_mask_tiles(tiles, 3, *args, 1, 20.0, 12.0, 6.0, 0.1, 1)
+    assert np.array_equal(a, b)
+    assert np.array_equal(a[1], c[0])
+    assert not np.array_equal(a[0], a[1])
