@@ -134,6 +134,24 @@ fv_status fv_fovea_mask(const fv_fovea_params* p, int width, int height,
                         uint32_t capacity, uint32_t* count, void* workspace,
                         size_t ws_bytes, void* stream);
 
+/* Sample map from a stack of noise tiles (paper Sec. 3.1.1: tileable noise
+ * textures, a different tile each frame, looping over the stack) in place of
+ * the seeded hash: pixel (x, y) of view v in frame f draws
+ *   u = tiles[((f + v) mod tile_count) * tile_h + y mod tile_h][x mod tile_w]
+ * and is sampled when u < T (the same quantised density as fv_fovea_mask;
+ * the seed is not used).  Everything else, outputs and workspace included,
+ * is as fv_fovea_mask.
+ *   tiles  dev uint32 [tile_count][tile_h][tile_w], values in [0, 2^24)
+ *          (a value v of an 8-bit noise texture maps to v * 2^16 + 2^15)
+ * Errors: as fv_fovea_mask, plus a null tile stack, non-positive tile sizes
+ * or a stack of 2^31 values or more. */
+fv_status fv_fovea_mask_tiles(const fv_fovea_params* p, const uint32_t* tiles,
+                              int tile_w, int tile_h, int tile_count,
+                              int width, int height, int views, uint8_t* mask,
+                              uint32_t* ray_idx, uint32_t capacity,
+                              uint32_t* count, void* workspace,
+                              size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * 2. Volume
  * ------------------------------------------------------------------------

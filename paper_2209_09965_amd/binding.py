@@ -67,6 +67,8 @@ _SIGS = {
     "fv_fovea_mask_workspace": (_i, [_i, _i, _i, ctypes.POINTER(_sz)]),
     "fv_fovea_mask": (_i, [ctypes.POINTER(FoveaParams), _i, _i, _i, _vp, _vp, _u32, _vp, _vp, _sz,
                            _vp]),
+    "fv_fovea_mask_tiles": (_i, [ctypes.POINTER(FoveaParams), _vp, _i, _i, _i, _i, _i, _i, _vp,
+                                 _vp, _u32, _vp, _vp, _sz, _vp]),
     "fv_volume_create": (_i, [_vp, _i, _i, _i, _i, _vp, ctypes.POINTER(_vp)]),
     "fv_volume_destroy": (_i, [_vp]),
     "fv_raymarch_dense": (_i, [_vp, _vp, _i, ctypes.POINTER(Camera), _i, _i, _i,
@@ -180,6 +182,20 @@ def fovea_mask(params, width, height, views, ray_idx, count, mask=None, workspac
     check(_lib.fv_fovea_mask(ctypes.byref(fovea_params(params)), width, height, views,
                              _ptr(mask), _ptr(ray_idx), ray_idx.numel(), _ptr(count),
                              _ptr(workspace), workspace.numel(), _stream(stream)))
+
+
+def fovea_mask_tiles(params, tiles, width, height, views, ray_idx, count, mask=None,
+                     workspace=None, stream=None):
+    """As fovea_mask, with the noise drawn from a device stack of tiles
+    (int32/uint32 [count, tile_h, tile_w], 24-bit values) instead of the hash."""
+    if workspace is None:
+        workspace = torch.empty(fovea_mask_workspace(width, height, views), dtype=torch.uint8,
+                                device=ray_idx.device)
+    tc, th, tw = tiles.shape
+    check(_lib.fv_fovea_mask_tiles(ctypes.byref(fovea_params(params)), _ptr(tiles), tw, th, tc,
+                                   width, height, views, _ptr(mask), _ptr(ray_idx),
+                                   ray_idx.numel(), _ptr(count), _ptr(workspace),
+                                   workspace.numel(), _stream(stream)))
 
 
 # ---------------------------------------------------------------------- volume

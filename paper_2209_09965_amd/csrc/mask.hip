@@ -150,6 +150,10 @@ struct MaskArgs {
   int W, H, tiles_x, tiles_per_view;
   int64_t total_tiles;
   int64_t f2x, f2y;
+  // noise tiles instead of the hash (NULL: hash): tcount tiles of tw x th
+  // 24-bit values, tile (frame + view) mod tcount, repeated over the frame
+  const uint32_t* noise;
+  int tw, th, tcount;
 };
 
 __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
@@ -169,14 +173,21 @@ __device__ __forceinline__ bool mask_bit(const MaskArgs& a, int64_t t, int lane,
   const int ty = r / a.tiles_x, tx = r - ty * a.tiles_x;
   const int x = tx * 8 + (lane & 7), y = ty * 8 + (lane >> 3);
   if (x >= a.W || y >= a.H) return false;
-  uint32_t h = 0x6A09E667u;
-  h = fmix32(h ^ a.seed_lo);
-  h = fmix32(h ^ a.seed_hi);
-  h = fmix32(h ^ a.frame);
-  h = fmix32(h ^ (uint32_t)view);
-  h = fmix32(h ^ (uint32_t)y);
-  h = fmix32(h ^ (uint32_t)x);
-  const uint32_t u = h >> 8;
+  uint32_t u;
+  if (a.noise) {
+    const uint32_t ti = (a.frame + (uint32_t)view) % (uint32_t)a.tcount;
+    const uint32_t ty2 = (uint32_t)y % (uint32_t)a.th, tx2 = (uint32_t)x % (uint32_t)a.tw;
+    u = a.noise[((size_t)ti * (uint32_t)a.th + ty2) * (uint32_t)a.tw + tx2];
+  } else {
+    uint32_t h = 0x6A09E667u;
+    h = fmix32(h ^ a.seed_lo);
+    h = fmix32(h ^ a.seed_hi);
+    h = fmix32(h ^ a.frame);
+    h = fmix32(h ^ (uint32_t)view);
+    h = fmix32(h ^ (uint32_t)y);
+    h = fmix32(h ^ (uint32_t)x);
+    u = h >> 8;
+  }
   const int64_t dx = 2 * (int64_t)x + 1 - a.f2x, dy = 2 * (int64_t)y + 1 - a.f2y;
   const int64_t k = (dx * dx + dy * dy) >> a.shift;
   const uint32_t T = k < a.n ? a.lut[k] : a.t_inf;
@@ -296,27 +307,28 @@ fv_status fv_fovea_mask_workspace(int width, int height, int views, size_t* byte
   return FV_OK;
 }
 
-fv_status fv_fovea_mask(const fv_fovea_params* p, int width, int height, int views,
-                        uint8_t* mask, uint32_t* ray_idx, uint32_t capacity, uint32_t* count,
-                        void* workspace, size_t ws_bytes, void* stream) {
+static fv_status mask_entry(const char* fn, const fv_fovea_params* p, const uint32_t* tiles,
+                            int tile_w, int tile_h, int tile_count, int width, int height,
+                            int views, uint8_t* mask, uint32_t* ray_idx, uint32_t capacity,
+                            uint32_t* count, void* workspace, size_t ws_bytes, void* stream) {
   fv::clear_error();
-  fv_status st = fv::check_params(p, width, height, "fv_fovea_mask");
+  fv_status st = fv::check_params(p, width, height, fn);
   if (st != FV_OK) return st;
-  if (views <= 0) return fv::fail(FV_ERR_INVALID_ARG, "fv_fovea_mask: views must be > 0");
+  if (views <= 0) return fv::fail(FV_ERR_INVALID_ARG, "%s: views must be > 0", fn);
   const uint64_t total = (uint64_t)views * (uint64_t)width * (uint64_t)height;
   if (total >= (1ull << 32))
-    return fv::fail(FV_ERR_INVALID_ARG, "fv_fovea_mask: views*W*H must be < 2^32");
+    return fv::fail(FV_ERR_INVALID_ARG, "%s: views*W*H must be < 2^32", fn);
   if (!ray_idx || !count || !workspace)
-    return fv::fail(FV_ERR_INVALID_ARG, "fv_fovea_mask: null ray_idx, count or workspace");
+    return fv::fail(FV_ERR_INVALID_ARG, "%s: null ray_idx, count or workspace", fn);
   if ((uint64_t)capacity < total)
-    return fv::fail(FV_ERR_CAPACITY, "fv_fovea_mask: capacity %u < views*W*H = %llu", capacity,
+    return fv::fail(FV_ERR_CAPACITY, "%s: capacity %u < views*W*H = %llu", fn, capacity,
                     (unsigned long long)total);
   size_t need = 0;
   fv_fovea_mask_workspace(width, height, views, &need);
   if (ws_bytes < need)
-    return fv::fail(FV_ERR_CAPACITY, "fv_fovea_mask: workspace %zu < %zu bytes", ws_bytes, need);
+    return fv::fail(FV_ERR_CAPACITY, "%s: workspace %zu < %zu bytes", fn, ws_bytes, need);
   if ((uintptr_t)workspace % 256)
-    return fv::fail(FV_ERR_INVALID_ARG, "fv_fovea_mask: workspace not 256-byte aligned");
+    return fv::fail(FV_ERR_INVALID_ARG, "%s: workspace not 256-byte aligned", fn);
   fv::CachedTable tab;
   st = fv::get_device_table(*p, width, height, &tab);
   if (st != FV_OK) return st;
@@ -336,17 +348,41 @@ fv_status fv_fovea_mask(const fv_fovea_params* p, int width, int height, int vie
   a.total_tiles = (int64_t)a.tiles_per_view * views;
   a.f2x = (int64_t)llround(2.0 * (double)p->focus_x);
   a.f2y = (int64_t)llround(2.0 * (double)p->focus_y);
+  a.noise = tiles;
+  a.tw = tile_w;
+  a.th = tile_h;
+  a.tcount = tile_count;
 
   const int64_t nb = fv::num_blocks(width, height, views);
   uint32_t* counts = (uint32_t*)workspace;
   uint32_t* offsets = counts + nb;
   hipStream_t s = (hipStream_t)stream;
   fv::k_mask_count<<<(unsigned)nb, 256, 0, s>>>(a, counts);
-  if ((st = fv::launch_status("fv_fovea_mask: count kernel")) != FV_OK) return st;
+  if ((st = fv::launch_status("count kernel")) != FV_OK) return st;
   fv::k_block_scan<<<1, 1024, 0, s>>>(counts, offsets, nb, count);
-  if ((st = fv::launch_status("fv_fovea_mask: scan kernel")) != FV_OK) return st;
+  if ((st = fv::launch_status("scan kernel")) != FV_OK) return st;
   fv::k_mask_scatter<<<(unsigned)nb, 256, 0, s>>>(a, offsets, mask, ray_idx);
-  return fv::launch_status("fv_fovea_mask: scatter kernel");
+  return fv::launch_status("scatter kernel");
+}
+
+fv_status fv_fovea_mask(const fv_fovea_params* p, int width, int height, int views,
+                        uint8_t* mask, uint32_t* ray_idx, uint32_t capacity, uint32_t* count,
+                        void* workspace, size_t ws_bytes, void* stream) {
+  return mask_entry("fv_fovea_mask", p, nullptr, 0, 0, 0, width, height, views, mask, ray_idx,
+                    capacity, count, workspace, ws_bytes, stream);
+}
+
+fv_status fv_fovea_mask_tiles(const fv_fovea_params* p, const uint32_t* tiles, int tile_w,
+                              int tile_h, int tile_count, int width, int height, int views,
+                              uint8_t* mask, uint32_t* ray_idx, uint32_t capacity,
+                              uint32_t* count, void* workspace, size_t ws_bytes, void* stream) {
+  if (!tiles || tile_w <= 0 || tile_h <= 0 || tile_count <= 0 ||
+      (uint64_t)tile_w * tile_h * tile_count >= (1ull << 31)) {
+    fv::clear_error();
+    return fv::fail(FV_ERR_INVALID_ARG, "fv_fovea_mask_tiles: bad tile stack");
+  }
+  return mask_entry("fv_fovea_mask_tiles", p, tiles, tile_w, tile_h, tile_count, width, height,
+                    views, mask, ray_idx, capacity, count, workspace, ws_bytes, stream);
 }
 
 }  // extern "C"

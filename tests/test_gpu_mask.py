@@ -51,3 +51,52 @@ def test_mask_repeatable_and_seed_sensitive(dev):
     p["frame"] = 1
     m3, _ = gpu_mask(b, p, 640, 360, 1, dev)
     assert not np.array_equal(m1, m3)
+
+
+TILE_CASES = [
+    # (W, H, views, sigma_px, p_floor, mode, tile size (w, h), tiles, kind, frame)
+    (1920, 1080, 1, 162.0, 0.05, 0, (64, 64), 8, "blue", 9),   # 1080p, frame 9 -> tile 1
+    (45, 31, 2, 6.0, 0.2, 1, (13, 7), 3, "white", 5),          # ragged, odd tile sizes, stereo
+    (256, 256, 1, 38.4, 0.05, 0, (16, 16), 64, "blue", 63),    # a 64-tile loop
+]
+
+
+@pytest.mark.parametrize("case", TILE_CASES, ids=[f"{c[0]}x{c[1]}_t{c[6][0]}" for c in TILE_CASES])
+def test_mask_tiles_bit_exact(case, dev):
+    """The sample map drawn from a noise tile stack (Sec. 3.1.1) equals the
+    oracle's bit for bit, mask and ordered list."""
+    import torch
+
+    import synthetic
+    from paper_2209_09965_amd import binding as b
+    W, H, V, s, pf, mode, (tw, th), count, kind, frame = case
+    print("tile mask case", case, flush=True)
+    tiles = synthetic.noise_tiles(11, size=max(tw, th), count=count, kind=kind)[:, :th, :tw]
+    tiles = np.ascontiguousarray(tiles)
+    p = dict(seed=0, frame=frame, mode=mode, focus_x=W / 2, focus_y=H / 2, sigma_px=s,
+             p_floor=pf)
+    total = V * W * H
+    ray_idx = torch.empty(total, dtype=torch.int32, device=dev)
+    count_t = torch.zeros(1, dtype=torch.int32, device=dev)
+    mask = torch.full((total,), 7, dtype=torch.uint8, device=dev)
+    tiles_t = torch.from_numpy(tiles.view(np.int32)).to(dev)
+    b.fovea_mask_tiles(p, tiles_t, W, H, V, ray_idx, count_t, mask=mask)
+    torch.cuda.synchronize()
+    n = int(count_t.item())
+    q = widen_fovea(p)
+    mo, io = oracle.fovea_mask_tiles(tiles, frame, W, H, V, q["focus_x"], q["focus_y"],
+                                     q["sigma_px"], q["p_floor"], mode)
+    assert np.array_equal(mask.cpu().numpy().reshape(V, H, W), mo)
+    assert np.array_equal(ray_idx[:n].cpu().numpy().view(np.uint32), io)
+
+
+def test_mask_tiles_bad_stack_rejected(dev):
+    import torch
+
+    from paper_2209_09965_amd import binding as b
+    p = dict(seed=0, frame=0, mode=0, focus_x=8.0, focus_y=8.0, sigma_px=4.0, p_floor=0.1)
+    ray_idx = torch.empty(256, dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    empty = torch.zeros((0, 4, 4), dtype=torch.int32, device=dev)
+    with pytest.raises(b.FvError, match="tile"):
+        b.fovea_mask_tiles(p, empty, 16, 16, 1, ray_idx, count)
