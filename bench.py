@@ -55,6 +55,11 @@ def parse():
                     help="compression-efficiency sweep instead of the frame benchmark: "
                          "stream compaction vs naive rejection vs the ideal rate")
     ap.add_argument("--sweep-frames", type=int, default=12)
+    ap.add_argument("--noise", default="hash", choices=["hash", "blue"],
+                    help="sample-map noise: the seeded hash, or a stack of 64 blue-noise "
+                         "tiles of 64 x 64 (void-and-cluster), one tile per frame")
+    ap.add_argument("--tpsnr-frames", type=int, default=12,
+                    help="consecutive frames of the orbit for the temporal PSNR")
     ap.add_argument("--shadow-step", type=float, default=0.0,
                     help="global shadows: shadow-ray segment length in voxels (0 = off; the "
                          "paper's renderer uses 4 x step = 2.0); the CPU-oracle leg is skipped "
@@ -258,12 +263,24 @@ def main():
     fps = [synthetic.fovea_params(W, H, sigma_frac=sig_frac, frame=k)
            for k in range(args.warmup + args.steps)]
 
+    tiles_t = None
+    if args.noise == "blue":
+        tiles_t = torch.from_numpy(
+            synthetic.noise_tiles(wl["seeds"][0], size=64, count=64).view(np.int32)).to(dev)
+
+    def sample_map(k, bf, st):
+        if tiles_t is None:
+            b.fovea_mask(fps[k], W, H, V, bf["ray_idx"], bf["count"], mask=bf["mask"],
+                         workspace=bf["mws"], stream=st)
+        else:
+            b.fovea_mask_tiles(fps[k], tiles_t, W, H, V, bf["ray_idx"], bf["count"],
+                               mask=bf["mask"], workspace=bf["mws"], stream=st)
+
     def foveated(k, j=0, ev=None):
         st, bf = streams[j], bufs[j]
         if ev:
             ev[0].record(st)
-        b.fovea_mask(fps[k], W, H, V, bf["ray_idx"], bf["count"], mask=bf["mask"],
-                     workspace=bf["mws"], stream=st)
+        sample_map(k, bf, st)
         if ev:
             ev[1].record(st)
         b.raymarch_sparse(volh, tf_t, cam_list[k], W, H, mp, bf["ray_idx"], bf["count"],
@@ -278,8 +295,7 @@ def main():
 
     # FP8 scales from one frame of the workload (untimed, before warm-up)
     b0 = bufs[0]
-    b.fovea_mask(fps[0], W, H, V, b0["ray_idx"], b0["count"], mask=b0["mask"],
-                 workspace=b0["mws"], stream=streams[0])
+    sample_map(0, b0, streams[0])
     b.raymarch_sparse(volh, tf_t, cam_list[0], W, H, mp, b0["ray_idx"], b0["count"],
                       frame_rgba=b0["frame"], frame_depth=b0["fdepth"], workspace=b0["sws"],
                       stream=streams[0])
@@ -344,6 +360,23 @@ def main():
     dref = dframe.view(-1, 4)[:, :3]
     mse = torch.mean((fov_out.clamp(0, 1) - dref.clamp(0, 1)) ** 2).item()
     psnr_dense = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
+    # temporal stability (Sec. 4, "Temporal Stability"): tPSNR, the PSNR of
+    # the differences between consecutive frames, over the last frames of the
+    # run, foveated output against the dense march (untimed)
+    nt = min(args.tpsnr_frames, args.warmup + args.steps)
+    seq_f, seq_d = [], []
+    for k in range(args.warmup + args.steps - nt, args.warmup + args.steps):
+        foveated(k, 0)
+        dense(k, 0)
+        seq_f.append(bufs[0]["out_rgb"].view(-1, 3).clamp(0, 1).clone())
+        seq_d.append(bufs[0]["dframe"].view(-1, 4)[:, :3].clamp(0, 1).clone())
+    torch.cuda.synchronize()
+    dif = [(seq_f[t] - seq_f[t - 1]) - (seq_d[t] - seq_d[t - 1]) for t in range(1, nt)]
+    tmse = float(sum(torch.mean(d * d).item() for d in dif) / max(1, len(dif)))
+    tpsnr = 10 * math.log10(1.0 / tmse) if tmse > 0 else float("inf")
+    seq_psnr = float(np.mean([10 * math.log10(1.0 / max(torch.mean((f - d) ** 2).item(), 1e-30))
+                              for f, d in zip(seq_f, seq_d)]))
+    del seq_f, seq_d, dif
 
     bytes_per_sample = (32 if mp["shading"] else 8) * vol.itemsize
     sp_avg = sum(sparse_ms) / len(sparse_ms)
@@ -375,6 +408,8 @@ def main():
                              "mode": "clamp"},
                    "shadows": ({"shadow_step": mp["shadow_step"]} if mp["shadow_step"] > 0
                                else "none"),
+                   "sample_noise": ("seeded hash" if args.noise == "hash"
+                                    else "64 blue-noise tiles of 64x64, one per frame"),
                    "reconstruction": "U-Net 32/48/64/96 + 5x5 KPN, %s" % args.precision},
         "dense_ms_per_frame": round(dense_ms, 4),
         "speedup_vs_dense": round(dense_ms / fov_ms, 3),
@@ -389,6 +424,8 @@ def main():
                       "reconstruct": round(sum(recon_ms) / len(recon_ms), 4),
                       "raymarch_dense": round(dn_avg, 4)},
         "psnr_vs_gpu_dense_db": round(psnr_dense, 2),
+        "quality_sequence": {"frames": nt, "mean_psnr_db": round(seq_psnr, 2),
+                             "tpsnr_db": round(tpsnr, 2)},
         "net_mfma": {"precision": args.precision, "flop_per_px": 167968,
                      "achieved_tflops": round(167968.0 * total / (sum(recon_ms) / len(recon_ms)
                                                                    * 1e-3) / 1e12, 1),

@@ -327,6 +327,17 @@ def psnr(x, ref):
     return float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
 
 
+def tpsnr(seq, ref_seq):
+    """Temporal PSNR (Sec. 4, "Temporal Stability"): the PSNR of the
+    finite differences between consecutive frames, frame t - frame t-1 of the
+    output against the same of the reference, over all consecutive pairs;
+    frames are clamped to [0, 1] first and the peak is 1."""
+    a = np.clip(np.asarray(seq, np.float64), 0, 1)
+    b = np.clip(np.asarray(ref_seq, np.float64), 0, 1)
+    mse = np.mean(((a[1:] - a[:-1]) - (b[1:] - b[:-1])) ** 2)
+    return float("inf") if mse == 0 else 10 * np.log10(1.0 / mse)
+
+
 def ssim_metric(x, ref):
     return ssim(np.clip(x, 0, 1), np.clip(ref, 0, 1))
 

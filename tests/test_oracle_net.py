@@ -154,3 +154,21 @@ def test_param_count_and_macs():
     """480 060 parameters and 83 984 multiply-adds per output pixel."""
     assert N.N_PARAMS == 480060 == synthetic.net_init(0).size
     assert N.MACS_PER_PX == 83984
+
+
+def test_tpsnr_closed_forms():
+    """tPSNR looks only at changes between frames: a fixed error in every frame
+    does not count, a flicker does.  A frame-to-frame error alternating between
+    +d and -d on every pixel gives differences off by 2d, i.e. 10 log10(1/(4 d^2))."""
+    rng = np.random.default_rng(0)
+    ref = rng.uniform(0.2, 0.8, (6, 8, 8, 3))
+    assert N.tpsnr(ref, ref) == float("inf")
+    assert N.tpsnr(ref + 0.05, ref) > 250  # only rounding of the offset remains
+    d = 0.01
+    flick = ref + d * np.array([1, -1, 1, -1, 1, -1])[:, None, None, None]
+    assert N.tpsnr(flick, ref) == pytest.approx(10 * np.log10(1 / (4 * d * d)), rel=1e-9)
+    # a single changed frame in the middle changes two differences
+    one = ref.copy()
+    one[3] += d
+    want = 10 * np.log10(1 / (2 * d * d / 5))
+    assert N.tpsnr(one, ref) == pytest.approx(want, rel=1e-9)
