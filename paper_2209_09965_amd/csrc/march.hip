@@ -566,12 +566,13 @@ __global__ void __launch_bounds__(256) k_setup_list(MarchArgs a,
 }
 
 // Sparse, persistent: every wave claims rays from a global queue (one atomic
-// per claim) in list order.  Every kStepsPerRefill segments, once at least
-// kRefillMin lanes are idle (their ray finished or missed the box), those
-// lanes take the next rays of the list: long and short rays of the sparse
-// periphery do not leave lanes idle for long, and a wave's lanes stay on
-// neighbouring pixels (one claim takes consecutive list entries).  Results
-// go to the compact buffers and/or back to their pixels (back-projection).
+// per claim) in list order.  A wave claims once all its lanes are idle
+// (their rays finished or missed the box), checked every kStepsPerRefill
+// segments: one claim takes consecutive list entries, so a wave's lanes step
+// through neighbouring pixels in lock step and fetch neighbouring voxels.
+// (Refilling lanes as soon as half a wave was idle, or one by one, was
+// slower: lanes at different depths share no cache lines.)  Results go to
+// the compact buffers and/or back to their pixels (back-projection).
 // The loop is software-pipelined kSparseAhead steps ahead: each lane keeps
 // the voxels of its next kSparseAhead samples in flight.
 //
@@ -583,18 +584,15 @@ __global__ void __launch_bounds__(256) k_setup_list(MarchArgs a,
 // with the same operations as the single-lane march, so the pixel is the
 // same bit for bit and the group's lanes keep identical ray state.
 constexpr int kStepsPerRefill = 9;
+constexpr int kSparseAhead = 2;
 // With shadows each segment runs its own shadow loop, whose length depends
 // on where the sample is: one primary sample ahead and a register budget for
 // two waves per SIMD (the shadowed full list took 30.7 ms with one wave and
-// two samples ahead, 21.5 ms with this), and claims only by whole idle waves
-// every 4 segments, so a wave's lanes step through neighbouring rays in lock
-// step and their shadow loops stay about equally long (21.5 -> 10.5 ms, the
-// dense march's time for the same rays).
+// two samples ahead, 21.5 ms with this), and the idle check every 4
+// segments (with whole-wave claims the lanes' shadow loops stay about
+// equally long: 21.5 -> 10.5 ms, the dense march's time for the same rays).
 constexpr int kSparseAheadShadow = 1;
 constexpr int kStepsPerRefillShadow = 4;
-constexpr int kRefillMinShadow = 64;
-constexpr int kRefillMin = 32;
-constexpr int kSparseAhead = 2;
 // G is the largest of 1, 2, 4, 8 with h G^2 <= kGroupRule, h = (rays that
 // reach the volume) / (resident lanes).  Measured on the 1080p noise volume:
 // the best G was 1 at h = 11 (2 within 3 %), 2 at h = 2.2 to 2.5, 4 at
@@ -664,7 +662,7 @@ __device__ __forceinline__ void march_list(const MarchArgs& a, const float4* __r
     const bool want = !active && !exhausted;
     const uint64_t m = __ballot(want);  // G bits per idle group
     bool fresh = false;  // claimed a ray this round that needs marching
-    if (m && (__popcll(m) >= (SHADOW ? kRefillMinShadow : kRefillMin) || !__ballot(active))) {
+    if (m && !__ballot(active)) {
       const int leader = __ffsll((long long)m) - 1;
       uint32_t base = 0;
       if (lane == leader) base = atomicAdd(queue, (uint32_t)__popcll(m) / G);
