@@ -76,6 +76,41 @@ def test_fovea_mask_host_errors():
                            None) == -1  # views*W*H >= 2^32
 
 
+def test_fovea_mask_tiles_host_errors():
+    """The tile-stack sample map rejects a missing or empty stack and otherwise
+    checks its arguments like fv_fovea_mask, before any device work."""
+    from paper_2209_09965_amd import binding as b
+    L = b.lib()
+    p = ctypes.byref(b.fovea_params(_fp()))
+    fake = ctypes.c_void_p(0x1000)
+    # null tiles, non-positive tile sizes, a stack of 2^31 values
+    assert L.fv_fovea_mask_tiles(p, None, 8, 8, 1, 16, 16, 1, None, fake, 256, fake, fake,
+                                 4096, None) == -1
+    assert "tile" in b.last_error()
+    for tw, th, tc in ((0, 8, 1), (8, -1, 1), (8, 8, 0), (1 << 16, 1 << 15, 1)):
+        assert L.fv_fovea_mask_tiles(p, fake, tw, th, tc, 16, 16, 1, None, fake, 256, fake,
+                                     fake, 4096, None) == -1
+    # the fv_fovea_mask checks: capacity, workspace
+    assert L.fv_fovea_mask_tiles(p, fake, 8, 8, 1, 16, 16, 1, None, fake, 255, fake, fake,
+                                 4096, None) == -2
+    need = b.fovea_mask_workspace(16, 16, 1)
+    assert L.fv_fovea_mask_tiles(p, fake, 8, 8, 1, 16, 16, 1, None, fake, 256, fake, fake,
+                                 need - 1, None) == -2
+
+
+def test_sparse_workspace_size():
+    """A 4 KB header of counters plus 88 bytes of set-up per listed ray (each
+    array 256-byte aligned); capacity 0 is an error."""
+    from paper_2209_09965_amd import binding as b
+    L = b.lib()
+    n = ctypes.c_size_t()
+    assert L.fv_raymarch_sparse_workspace(0, ctypes.byref(n)) == -1
+    for cap in (1, 1000, 1920 * 1080):
+        got = b.raymarch_sparse_workspace(cap)
+        assert got >= 4096 + 88 * cap
+        assert got <= 4096 + 88 * cap + 15 * 256
+
+
 def test_march_host_errors():
     from paper_2209_09965_amd import binding as b
     L = b.lib()
