@@ -321,6 +321,23 @@ def loss(out, target, grad=False):
     return 0.9 * (1 - s) + 0.1 * l1, -0.9 * ds + 0.1 * dl1
 
 
+def temporal_loss(out, target, grad=False):
+    """First component of the temporal loss (Sec. 3.3.2): the output's change
+    between consecutive frames should match the target's.  Batch entries
+    (2i, 2i + 1) are frames t - 1 and t of one sequence (NCHW, N even):
+    L_t = mean |(out[2i+1] - out[2i]) - (target[2i+1] - target[2i])| over
+    pairs, channels and pixels (and d L_t / d out)."""
+    d = (out[1::2] - out[0::2]) - (target[1::2] - target[0::2])
+    lt = np.abs(d).mean()
+    if not grad:
+        return lt
+    g = np.zeros_like(out)
+    sg = np.sign(d) / d.size
+    g[1::2] = sg
+    g[0::2] = -sg
+    return lt, g
+
+
 def psnr(x, ref):
     """10 log10(1 / MSE) over values clamped to [0, 1]."""
     mse = np.mean((np.clip(x, 0, 1) - np.clip(ref, 0, 1)) ** 2)

@@ -172,3 +172,30 @@ def test_tpsnr_closed_forms():
     one[3] += d
     want = 10 * np.log10(1 / (2 * d * d / 5))
     assert N.tpsnr(one, ref) == pytest.approx(want, rel=1e-9)
+
+
+def test_temporal_loss_closed_forms_and_gradient():
+    """Pairs (2i, 2i+1) are consecutive frames.  A constant error per pair, or
+    an output that follows the target's change exactly, costs nothing; an
+    output change of d over a static target costs |d|; the gradient matches
+    finite differences away from the kinks."""
+    t = rng.uniform(0.2, 0.8, size=(4, 3, 6, 7))
+    assert N.temporal_loss(t, t) == 0.0
+    off = t.copy()
+    off[0:2] += 0.07
+    off[2:4] -= 0.02
+    assert N.temporal_loss(off, t) == pytest.approx(0.0, abs=1e-15)
+    static = np.repeat(t[0:1], 4, axis=0)
+    o = static.copy()
+    o[1::2] += 0.03
+    assert N.temporal_loss(o, static) == pytest.approx(0.03, rel=1e-12)
+    x = t + rng.normal(size=t.shape) * 0.05
+    val, g = N.temporal_loss(x, t, grad=True)
+    h = 1e-7
+    for _ in range(20):
+        idx = tuple(rng.integers(0, s) for s in x.shape)
+        xp, xm = x.copy(), x.copy()
+        xp[idx] += h
+        xm[idx] -= h
+        fd = (N.temporal_loss(xp, t) - N.temporal_loss(xm, t)) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-6 * abs(g[idx]) + 1e-9, (idx, fd, g[idx])
