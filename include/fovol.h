@@ -411,6 +411,20 @@ fv_status fv_net_forward_train(fv_net* n, const float* frame_rgba, const uint8_t
 fv_status fv_net_loss(const fv_net* n, const float* out_rgb, const float* target_rgba,
                       int batch, int width, int height, float* loss3, float* dloss_dout,
                       void* workspace, size_t ws_bytes, void* stream);
+/* Temporal loss, the finite-difference term of the paper's temporal loss
+ * (Sec. 3.3.2; the optical-flow term is not included): batch entries
+ * (2i, 2i+1) are consecutive frames t-1 and t of one sequence, and
+ *   L_t = mean |(out_2i+1 - out_2i) - (target_2i+1 - target_2i)|
+ * over pairs, pixels and RGB channels.  Writes L_t to loss[0] (dev float
+ * [1]) and ADDS weight * d L_t / d out to dloss_dout, so it is called after
+ * fv_net_loss (which writes dloss_dout), on the same stream and workspace.
+ * Errors: as fv_net_loss, plus an odd batch and a negative or non-finite
+ * weight. */
+fv_status fv_net_loss_temporal(const fv_net* n, const float* out_rgb,
+                               const float* target_rgba, int batch, int width,
+                               int height, float weight, float* loss,
+                               float* dloss_dout, void* workspace,
+                               size_t ws_bytes, void* stream);
 fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int width,
                           int height, float* grad_out, void* workspace, size_t ws_bytes,
                           void* stream);

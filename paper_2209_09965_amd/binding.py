@@ -90,6 +90,8 @@ _SIGS = {
     "fv_train_workspace": (_i, [_vp, _i, _i, _i, ctypes.POINTER(_sz)]),
     "fv_net_forward_train": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _sz, _vp]),
     "fv_net_loss": (_i, [_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _sz, _vp]),
+    "fv_net_loss_temporal": (_i, [_vp, _vp, _vp, _i, _i, _i, ctypes.c_float, _vp, _vp, _vp, _sz,
+                                  _vp]),
     "fv_net_backward": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp, _sz, _vp]),
     "fv_net_adam": (_i, [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                          _vp]),
@@ -354,6 +356,14 @@ class Net:
         check(_lib.fv_net_loss(self.handle, _ptr(out_rgb), _ptr(target_rgba), batch, width,
                                height, _ptr(loss3), _ptr(dloss), _ptr(workspace),
                                workspace.numel(), _stream(stream)))
+
+    def loss_temporal(self, out_rgb, target_rgba, batch, width, height, weight, loss, dloss,
+                      workspace, stream=None):
+        """Temporal finite-difference loss over batch pairs (2i, 2i+1); adds
+        weight * d L_t / d out to dloss (call after loss())."""
+        check(_lib.fv_net_loss_temporal(self.handle, _ptr(out_rgb), _ptr(target_rgba), batch,
+                                        width, height, float(weight), _ptr(loss), _ptr(dloss),
+                                        _ptr(workspace), workspace.numel(), _stream(stream)))
 
     def backward(self, dloss, batch, width, height, workspace, grad_out=None, stream=None):
         check(_lib.fv_net_backward(self.handle, _ptr(dloss), batch, width, height,

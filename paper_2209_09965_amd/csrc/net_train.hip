@@ -233,6 +233,56 @@ __global__ void k_loss_final(const double* __restrict__ rs, int ns, const double
   }
 }
 
+// Temporal loss, finite-difference term, over batch pairs (2i, 2i + 1):
+// d = (out_2i+1 - out_2i) - (target_2i+1 - target_2i) per channel; |d| is
+// summed per block in FP64 and d L / d out (+-gscale by the sign of d) is
+// added to dloss.
+__global__ void __launch_bounds__(256) k_tloss(const float* __restrict__ out,
+                                               const float4* __restrict__ tgt, int64_t pairs,
+                                               int64_t hw, float gscale,
+                                               float* __restrict__ dloss,
+                                               double* __restrict__ red) {
+  __shared__ double sh[256];
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double ad = 0.0;
+  if (e < pairs * hw * 3) {
+    const int64_t pr = e / (hw * 3), rem = e - pr * hw * 3;
+    const int64_t px = rem / 3;
+    const int c = (int)(rem - px * 3);
+    const int64_t i0 = 2 * pr * hw * 3 + rem, i1 = i0 + hw * 3;
+    const float4 a = tgt[2 * pr * hw + px], b = tgt[(2 * pr + 1) * hw + px];
+    const float t0 = c == 0 ? a.x : c == 1 ? a.y : a.z;
+    const float t1 = c == 0 ? b.x : c == 1 ? b.y : b.z;
+    const float d = (out[i1] - out[i0]) - (t1 - t0);
+    ad = fabs((double)d);
+    const float g = d > 0.0f ? gscale : (d < 0.0f ? -gscale : 0.0f);
+    dloss[i1] += g;
+    dloss[i0] -= g;
+  }
+  sh[threadIdx.x] = ad;
+  __syncthreads();
+  for (int st = 128; st; st >>= 1) {
+    if (threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) red[blockIdx.x] = sh[0];
+}
+
+// fixed-order sum of the block partials -> L_t
+__global__ void k_tloss_final(const double* __restrict__ red, int nb, double scale,
+                              float* __restrict__ out) {
+  __shared__ double a[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nb; i += 256) s += red[i];
+  a[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st; st >>= 1) {
+    if (threadIdx.x < st) a[threadIdx.x] += a[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = (float)(a[0] * scale);
+}
+
 __global__ void __launch_bounds__(256) k_rgb_of_rgba(const float4* __restrict__ src,
                                                      float* __restrict__ dst, int64_t npx) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -650,6 +700,35 @@ fv_status fv_net_loss(const fv_net* n, const float* out_rgb, const float* target
                                 (float)l1_scale, dloss_dout, red + nbv);
   k_loss_final<<<1, 256, 0, s>>>(red, (int)nbv, red + nbv, (int)nbl, ssim_scale, l1_scale, loss3);
   return launch_status("fv_net_loss");
+}
+
+fv_status fv_net_loss_temporal(const fv_net* n, const float* out_rgb, const float* target_rgba,
+                               int batch, int width, int height, float weight, float* loss,
+                               float* dloss_dout, void* workspace, size_t ws_bytes,
+                               void* stream) {
+  clear_error();
+  TrainPlan tp;
+  fv_status st = train_check(n, batch, width, height, workspace, ws_bytes, &tp,
+                             "fv_net_loss_temporal");
+  if (st != FV_OK) return st;
+  if (!out_rgb || !target_rgba || !loss || !dloss_dout)
+    return fail(FV_ERR_INVALID_ARG, "fv_net_loss_temporal: null pointer");
+  if (batch % 2)
+    return fail(FV_ERR_INVALID_ARG, "fv_net_loss_temporal: batch %d is not a set of pairs",
+                batch);
+  if (!(weight >= 0.0f && std::isfinite(weight)))
+    return fail(FV_ERR_INVALID_ARG, "fv_net_loss_temporal: weight must be finite and >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* ws = (uint8_t*)workspace;
+  const int64_t hw = (int64_t)height * width, pairs = batch / 2;
+  const int64_t cnt = pairs * hw * 3;
+  // the block partials fit in the loss partial-sum region (half the L1 blocks)
+  double* red = (double*)(ws + tp.red);
+  const unsigned nb = nblk(cnt);
+  k_tloss<<<nb, 256, 0, s>>>(out_rgb, (const float4*)target_rgba, pairs, hw,
+                             (float)((double)weight / (double)cnt), dloss_dout, red);
+  k_tloss_final<<<1, 256, 0, s>>>(red, (int)nb, 1.0 / (double)cnt, loss);
+  return launch_status("fv_net_loss_temporal");
 }
 
 fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int width, int height,

@@ -108,3 +108,40 @@ def test_adam_steps_reduce_loss(dev):
     assert losses[-1] < 0.8 * losses[0]
     # Adam's first step moves each weight by about lr (closed form of the first step)
     net.close()
+
+
+def test_temporal_loss_matches_oracle(dev):
+    """The temporal finite-difference term over batch pairs: L_t against the
+    oracle, and d L_t / d out added to the spatial gradient already in dloss,
+    element by element (sign ties where |d| is at the FP32 rounding level
+    are skipped); an odd batch and a negative weight are rejected."""
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(3)
+    n, H, W = 4, 24, 32
+    tgt = rng.uniform(0.05, 0.95, (n, H, W, 3)).astype(np.float32)
+    out = np.clip(tgt + rng.normal(0, 0.05, tgt.shape), 0, 1).astype(np.float32)
+    tgt4 = np.concatenate([tgt, np.ones((n, H, W, 1), np.float32)], axis=3)
+    base = rng.normal(0, 1e-3, (n, H, W, 3)).astype(np.float32)
+    net = b.Net(synthetic.net_init(0))
+    ws = torch.empty(net.train_workspace_bytes(n, W, H), dtype=torch.uint8, device=dev)
+    lt = torch.zeros(1, device=dev)
+    dl = _t(base, dev)
+    w = 0.25
+    net.loss_temporal(_t(out, dev), _t(tgt4, dev), n, W, H, w, lt, dl, ws)
+    torch.cuda.synchronize()
+    o = out.astype(np.float64).transpose(0, 3, 1, 2)
+    t = tgt.astype(np.float64).transpose(0, 3, 1, 2)
+    val, g = N.temporal_loss(o, t, grad=True)
+    print("temporal loss gpu %.8f oracle %.8f" % (float(lt.item()), val))
+    assert abs(float(lt.item()) - val) <= 1e-6 * val
+    gg = dl.cpu().numpy().reshape(n, H, W, 3).transpose(0, 3, 1, 2) - \
+        base.transpose(0, 3, 1, 2)
+    d = (o[1::2] - o[0::2]) - (t[1::2] - t[0::2])
+    clear = np.repeat(np.abs(d) > 1e-6, 2, axis=0)  # pairs -> both frames
+    assert clear.mean() > 0.99
+    np.testing.assert_allclose(gg[clear], w * g[clear], rtol=1e-5, atol=1e-12)
+    with pytest.raises(b.FvError, match="pairs"):
+        net.loss_temporal(_t(out, dev), _t(tgt4, dev), 3, W, H, w, lt, dl, ws)
+    with pytest.raises(b.FvError, match="weight"):
+        net.loss_temporal(_t(out, dev), _t(tgt4, dev), n, W, H, -1.0, lt, dl, ws)
+    net.close()
