@@ -7,9 +7,11 @@ sparse march with back-projection (fv_raymarch_sparse) -> full-frame
 reconstruction by the trained network in FP8 (fv_reconstruct).  The plain
 dense march of the same frames (fv_raymarch_dense) is timed beside it.
 Inputs are synthetic, seeded and resident in HBM before the timed region;
-the network weights come from paper_2209_09965_amd/weights/recon.npy (trained
-by python -m paper_2209_09965_amd.train) and are calibrated for FP8 on one
-frame of the workload before the timed region.
+the network weights come from paper_2209_09965_amd/weights/recon_temporal.npy
+(trained by python -m paper_2209_09965_amd.train, then fine-tuned on
+consecutive-frame pairs with the temporal loss, --temporal 1.0 --init
+recon.npy) and are calibrated for FP8 on one frame of the workload before the
+timed region.
 
 Timing: `value` is ms per foveated frame with the frames run one after the
 other on one HIP stream; the per-stage times come from HIP events recorded on
@@ -46,7 +48,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--precision", default="fp8", choices=["fp8", "bf16"])
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2209_09965_amd", "weights",
-                                                      "recon.npy"))
+                                                      "recon_temporal.npy"))
     ap.add_argument("--copy-ref", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter reference)")
     ap.add_argument("--net-crop", type=int, default=256,

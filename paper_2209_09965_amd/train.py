@@ -12,6 +12,12 @@ Training: fv_train_step (BF16 forward/backward on MFMA, FP32 Adam), batch
 16, lr 1e-3.  Every kernel of a step is the library's; torch only holds the
 frames in device memory and gathers batches.
 
+With --temporal W the pairs come as consecutive frames (the camera turned by
+3 degrees about the volume, the sample map of the next frame), batches hold
+8 such pairs, and each step adds W times the temporal finite-difference loss
+(fv_net_loss_temporal, Sec. 3.3.2) to the spatial loss; validation then also
+reports the temporal PSNR of the pairs.  --init starts from saved weights.
+
 Usage: python -m paper_2209_09965_amd.train --epochs 30 --out weights.npy
 """
 import argparse
@@ -34,12 +40,15 @@ from paper_2209_09965_amd import binding as b  # noqa: E402
 W = H = 512
 
 
-def render_pairs(dev, vol_specs, views, seed, log=print):
+def render_pairs(dev, vol_specs, views, seed, log=print, consecutive=False):
     """vol_specs: list of (kind, seed, n).  Returns dict of device tensors:
     rgba [N, H*W*4] f32, depth [N, H*W] f32, mask [N, H*W] u8, plus the volume
-    index of each pair."""
+    index of each pair.  consecutive: every view is two frames, entries 2j and
+    2j + 1, the second seen after a 3 degree turn of the camera about the
+    volume, with the sample map of the next frame."""
     rng = np.random.default_rng(seed)
-    n_pairs = len(vol_specs) * views
+    per_view = 2 if consecutive else 1
+    n_pairs = len(vol_specs) * views * per_view
     rgba = torch.empty((n_pairs, H * W * 4), dtype=torch.float32, device=dev)
     depth = torch.empty((n_pairs, H * W), dtype=torch.float32, device=dev)
     mask = torch.empty((n_pairs, H * W), dtype=torch.uint8, device=dev)
@@ -64,14 +73,16 @@ def render_pairs(dev, vol_specs, views, seed, log=print):
                 synthetic.tf_noise(tf_seed_base + v)
             tf_t = torch.from_numpy(tf).reshape(-1).to(dev)
             cam = synthetic.random_camera(rng)
-            b.raymarch_dense(volh, tf_t, [cam], W, H, mp, rgba[k], depth[k])
             fx = float(rng.uniform(W * 0.25, W * 0.75))
             fy = float(rng.uniform(H * 0.25, H * 0.75))
-            fp = synthetic.fovea_params(W, H, focus=(fx, fy), seed=int(rng.integers(1 << 31)),
-                                        frame=k)
-            b.fovea_mask(fp, W, H, 1, ray_idx, count, mask=mask[k])
-            vol_of[k] = vi
-            k += 1
+            mseed = int(rng.integers(1 << 31))
+            for f in range(per_view):
+                c = cam if f == 0 else turn_camera(cam, 3.0)
+                b.raymarch_dense(volh, tf_t, [c], W, H, mp, rgba[k], depth[k])
+                fp = synthetic.fovea_params(W, H, focus=(fx, fy), seed=mseed, frame=k)
+                b.fovea_mask(fp, W, H, 1, ray_idx, count, mask=mask[k])
+                vol_of[k] = vi
+                k += 1
         volh.close()
         if (vi + 1) % 10 == 0:
             torch.cuda.synchronize()
@@ -81,27 +92,46 @@ def render_pairs(dev, vol_specs, views, seed, log=print):
     return dict(rgba=rgba, depth=depth, mask=mask, vol=vol_of)
 
 
+def turn_camera(cam, deg):
+    """The camera rotated by deg about the vertical axis through the target."""
+    a = math.radians(deg)
+    ex, ey, ez = (cam["eye"][i] - cam["target"][i] for i in range(3))
+    eye = (cam["target"][0] + ex * math.cos(a) + ez * math.sin(a), cam["eye"][1],
+           cam["target"][2] - ex * math.sin(a) + ez * math.cos(a))
+    return dict(cam, eye=eye)
+
+
 def psnr_t(x, ref):
     mse = torch.mean((x.clamp(0, 1) - ref.clamp(0, 1)) ** 2).item()
     return float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
 
 
-def evaluate(net, data, idx, dev, precision="bf16"):
+def evaluate(net, data, idx, dev, precision="bf16", temporal=False):
     """PSNR of the hybrid output, the direct head and the raw sparse frame vs the
-    dense frame, averaged over the pairs idx."""
+    dense frame, averaged over the pairs idx; with temporal (idx = first frames
+    of consecutive pairs) also the temporal PSNR of each pair, averaged."""
     out = torch.empty(H * W * 3, device=dev)
     od = torch.empty(H * W * 3, device=dev)
     ws = torch.empty(net.workspace_bytes(1, W, H, precision), dtype=torch.uint8, device=dev)
     res = {"hybrid": [], "direct": [], "sparse": []}
+    if temporal:
+        res["tpsnr"] = []
     for i in idx:
-        fr = data["rgba"][i]
-        net.reconstruct(fr, data["mask"][i], data["depth"][i], 1, W, H, out, od,
-                        precision=precision, workspace=ws)
-        ref = fr.view(-1, 4)[:, :3]
-        sparse = ref * data["mask"][i].view(-1, 1).float()
-        res["hybrid"].append(psnr_t(out.view(-1, 3), ref))
-        res["direct"].append(psnr_t(od.view(-1, 3), ref))
-        res["sparse"].append(psnr_t(sparse, ref))
+        outs = []
+        for j in ((i, i + 1) if temporal else (i,)):
+            fr = data["rgba"][j]
+            net.reconstruct(fr, data["mask"][j], data["depth"][j], 1, W, H, out, od,
+                            precision=precision, workspace=ws)
+            ref = fr.view(-1, 4)[:, :3]
+            sparse = ref * data["mask"][j].view(-1, 1).float()
+            res["hybrid"].append(psnr_t(out.view(-1, 3), ref))
+            res["direct"].append(psnr_t(od.view(-1, 3), ref))
+            res["sparse"].append(psnr_t(sparse, ref))
+            outs.append((out.view(-1, 3).clamp(0, 1).clone(), ref.clamp(0, 1)))
+        if temporal:
+            (oa, ra), (ob, rb) = outs
+            mse = torch.mean(((ob - oa) - (rb - ra)) ** 2).item()
+            res["tpsnr"].append(float("inf") if mse == 0 else 10 * math.log10(1.0 / mse))
     return {k: float(np.mean(v)) for k, v in res.items()}
 
 
@@ -119,6 +149,10 @@ def main():
     ap.add_argument("--log", default=None)
     ap.add_argument("--time-limit", type=float, default=900.0,
                     help="stop training after this many seconds")
+    ap.add_argument("--temporal", type=float, default=-1.0,
+                    help="train on consecutive-frame pairs with this weight on the temporal "
+                         "loss (0 = pairs without the term; < 0 = single frames)")
+    ap.add_argument("--init", default=None, help="start from these saved parameters")
     args = ap.parse_args()
     logf = open(args.log, "a") if args.log else None
 
@@ -132,7 +166,8 @@ def main():
     t_start = time.time()
     specs = [("blob", 2000 + i, 64) for i in range(args.blob_volumes)]
     specs += [("noise", 4000 + i, 128) for i in range(args.noise_volumes)]
-    data = render_pairs(dev, specs, args.views, args.seed, log)
+    temporal = args.temporal >= 0
+    data = render_pairs(dev, specs, args.views, args.seed, log, consecutive=temporal)
     nv = len(specs)
     # split by volume 10:1:1 (every 12-volume group: 10 train, 1 val, 1 test)
     role = np.array(["train" if (i % 12) < 10 else ("val" if i % 12 == 10 else "test")
@@ -143,8 +178,16 @@ def main():
     te = np.flatnonzero(pair_role == "test")
     log("pairs: %d train / %d val / %d test" % (tr.size, va.size, te.size))
 
-    net = b.Net(synthetic.net_init(args.seed))
+    net = b.Net(np.load(args.init) if args.init else synthetic.net_init(args.seed))
     B = args.batch
+    if temporal:
+        assert B % 2 == 0
+        tr = tr[tr % 2 == 0]  # pairs as units: their first frames
+        va = va[va % 2 == 0]
+        te = te[te % 2 == 0]
+    lt = torch.zeros(1, device=dev)
+    dl = torch.empty(B * H * W * 3, device=dev)
+    out = torch.empty(B * H * W * 3, device=dev)
     ws = torch.empty(net.train_workspace_bytes(B, W, H), dtype=torch.uint8, device=dev)
     loss3 = torch.zeros(3, device=dev)
     rng = np.random.default_rng(args.seed + 1)
@@ -155,30 +198,41 @@ def main():
         t0 = time.time()
         tot = 0.0
         nb = 0
-        for s in range(0, perm.size - B + 1, B):
-            sel = torch.from_numpy(perm[s:s + B]).to(dev)
+        per = B // 2 if temporal else B
+        for s in range(0, perm.size - per + 1, per):
+            first = perm[s:s + per]
+            rows = np.stack([first, first + 1], 1).reshape(-1) if temporal else first
+            sel = torch.from_numpy(rows).to(dev)
             fr = data["rgba"].index_select(0, sel)
             m = data["mask"].index_select(0, sel)
             d = data["depth"].index_select(0, sel)
-            net.train_step(fr, m, d, fr, B, W, H, args.lr, loss3, ws)
+            if not temporal:
+                net.train_step(fr, m, d, fr, B, W, H, args.lr, loss3, ws)
+            else:
+                net.forward_train(fr, m, d, B, W, H, out, ws)
+                net.loss(out, fr, B, W, H, loss3, dl, ws)
+                net.loss_temporal(out, fr, B, W, H, args.temporal, lt, dl, ws)
+                net.backward(dl, B, W, H, ws)
+                net.adam(args.lr)
             step += 1
             nb += 1
             if nb % 25 == 0:
                 tot += float(loss3[0].item())
         torch.cuda.synchronize()
-        ev = evaluate(net, data, va[:40], dev)
+        ev = evaluate(net, data, va[:40], dev, temporal=temporal)
         hist.append(dict(epoch=ep, loss=float(loss3[0].item()), val=ev,
                          s_per_epoch=time.time() - t0))
-        log("epoch %d loss %.4f val PSNR hybrid %.2f direct %.2f sparse %.2f (%.1f s)" %
-            (ep, float(loss3[0].item()), ev["hybrid"], ev["direct"], ev["sparse"],
-             time.time() - t0))
+        log("epoch %d loss %.4f temporal %.4f val PSNR hybrid %.2f direct %.2f sparse %.2f "
+            "tPSNR %.2f (%.1f s)" %
+            (ep, float(loss3[0].item()), float(lt.item()), ev["hybrid"], ev["direct"],
+             ev["sparse"], ev.get("tpsnr", float("nan")), time.time() - t0))
         if time.time() - t_start > args.time_limit:
             log("time limit reached")
             break
     params = net.get_params()
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, params)
-    test_bf16 = evaluate(net, data, te, dev)
+    test_bf16 = evaluate(net, data, te, dev, temporal=temporal)
     res = dict(test_bf16=test_bf16, steps=step, epochs=len(hist), history=hist,
                pairs=dict(train=int(tr.size), val=int(va.size), test=int(te.size)))
     try:
@@ -187,7 +241,7 @@ def main():
         cw = torch.empty(net.workspace_bytes(1, W, H, "bf16"), dtype=torch.uint8, device=dev)
         net.calibrate(data["rgba"][tr[0]], data["mask"][tr[0]], data["depth"][tr[0]], 1, W, H,
                       workspace=cw)
-        res["test_fp8"] = evaluate(net, data, te, dev, precision="fp8")
+        res["test_fp8"] = evaluate(net, data, te, dev, precision="fp8", temporal=temporal)
     except Exception as e:  # noqa: BLE001
         res["test_fp8_error"] = str(e)
     log("RESULT " + json.dumps({k: v for k, v in res.items() if k != "history"}))
