@@ -205,8 +205,8 @@ def main():
         copy_reference(args.copy_ref)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1",
+        print("bench.py measures one GPU only: the library has no multi-GPU path; "
+              "run with --gpus 1",
               file=sys.stderr)
         sys.exit(2)
     if args.sweep:
@@ -357,7 +357,7 @@ def main():
     dense(last_k, 0)  # the dense frame of the last foveated frame's view, for PSNR
     torch.cuda.synchronize()
     # quality: the foveated reconstruction of the last timed frame against the
-    # dense march of the same frame (the dense GPU march is the judge; the FP64
+    # dense march of the same frame (the dense GPU march is the reference; the FP64
     # oracle frame is compared in the CPU-baseline leg)
     dref = dframe.view(-1, 4)[:, :3]
     mse = torch.mean((fov_out.clamp(0, 1) - dref.clamp(0, 1)) ** 2).item()
