@@ -25,8 +25,16 @@ weights are not available).  SSIM: Wang et al. 2004, 11x11 Gaussian window
 sigma 1.5, K1 = 0.01, K2 = 0.03, L = 1, valid region, mean over the map and
 channels.  Optimiser: Adam (beta 0.9 / 0.999, eps 1e-8).
 
+Recurrent form (Sec. 3.2.4, the feedback of D's output): the direct
+prediction O_d of the previous frame of a sequence is concatenated to the
+next frame's input along the channel axis, so the first conv sees 8
+channels [M*r, M*g, M*b, M, M*depth/2, O_d,prev r, g, b] (LAYERS_RECURRENT);
+the first frame of a sequence gets O_d,prev = 0.  The recurrent decoder
+hidden states are not part of this form.
+
 Arrays are NCHW float64.  Parameters are one flat vector in the canonical
-order of LAYERS, each layer's weight [Co, Ci, k, k] followed by its bias [Co].
+order of LAYERS (or LAYERS_RECURRENT, told apart by the vector's length),
+each layer's weight [Co, Ci, k, k] followed by its bias [Co].
 """
 import numpy as np
 
@@ -42,13 +50,25 @@ LAYERS = [
     ("hd", 32, 3, 1), ("hk", 32, 25, 1),
 ]
 N_PARAMS = sum(co * ci * k * k + co for _, ci, co, k in LAYERS)
+# the recurrent form: the first conv also reads the previous frame's O_d
+LAYERS_RECURRENT = [("e0a", 8, 32, 3)] + LAYERS[1:]
+N_PARAMS_RECURRENT = sum(co * ci * k * k + co for _, ci, co, k in LAYERS_RECURRENT)
 MACS_PER_PX = sum(co * ci * k * k / (4 ** lvl) for (name, ci, co, k), lvl in
                   zip(LAYERS, [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0, 0]))
 
 
-def unflatten(theta, n_layers=None):
+def layers_of(n_params):
+    """The layer list of a parameter vector of this length."""
+    if n_params == N_PARAMS:
+        return LAYERS
+    if n_params == N_PARAMS_RECURRENT:
+        return LAYERS_RECURRENT
+    raise ValueError("%d parameters: neither network form" % n_params)
+
+
+def unflatten(theta):
     out, off = {}, 0
-    for name, ci, co, k in LAYERS:
+    for name, ci, co, k in layers_of(len(theta)):
         nw = co * ci * k * k
         out[name] = (theta[off:off + nw].reshape(co, ci, k, k), theta[off + nw:off + nw + co])
         off += nw + co
@@ -57,7 +77,8 @@ def unflatten(theta, n_layers=None):
 
 def flatten(d):
     parts = []
-    for name, ci, co, k in LAYERS:
+    layers = LAYERS_RECURRENT if np.shape(d["e0a"][0])[1] == 8 else LAYERS
+    for name, ci, co, k in layers:
         w, b = d[name]
         parts += [np.asarray(w, np.float64).reshape(-1), np.asarray(b, np.float64).reshape(-1)]
     return np.concatenate(parts)
@@ -189,6 +210,9 @@ def forward(theta, x, keep=False, act_round=None):
     test can reproduce an implementation that stores activations at reduced
     precision; the arithmetic itself stays FP64."""
     P = unflatten(np.asarray(theta, np.float64))
+    if x.shape[1] != P["e0a"][0].shape[1]:
+        raise ValueError("input has %d channels, the network reads %d"
+                         % (x.shape[1], P["e0a"][0].shape[1]))
     rnd = act_round if act_round is not None else (lambda t: t)
     x = rnd(x)
     c = {"x": x}
@@ -214,6 +238,27 @@ def forward(theta, x, keep=False, act_round=None):
     if keep:
         return out, od, c
     return out, od
+
+
+def recurrent_input(x, od_prev=None):
+    """The recurrent network's input: the 5 sparse-frame channels x (NCHW)
+    followed by the previous frame's O_d (3 channels, zero at the start of a
+    sequence)."""
+    if od_prev is None:
+        od_prev = np.zeros((x.shape[0], 3) + x.shape[2:])
+    return np.concatenate([x, od_prev], axis=1)
+
+
+def forward_sequence(theta, xs, act_round=None):
+    """Runs the recurrent network over the frames xs (each NCHW, 5 channels)
+    in order, feeding each frame's O_d into the next; returns the lists of
+    outputs and of O_d."""
+    outs, ods, od = [], [], None
+    for x in xs:
+        out, od = forward(theta, recurrent_input(x, od), act_round=act_round)
+        outs.append(out)
+        ods.append(od)
+    return outs, ods
 
 
 def backward(theta, c, dout):

@@ -16,7 +16,8 @@ import numpy as np
 
 __all__ = [
     "blob_volume", "value_noise_volume", "tf_blob", "tf_noise", "orbit_camera",
-    "random_camera", "march_params", "fovea_params", "WORKLOADS", "NET_SHAPES", "net_init",
+    "random_camera", "march_params", "fovea_params", "WORKLOADS", "NET_SHAPES",
+    "NET_SHAPES_RECURRENT", "net_init",
 ]
 
 
@@ -267,13 +268,19 @@ NET_SHAPES = [
 ]
 
 
-def net_init(seed):
+# the recurrent form: the first conv also reads the previous frame's 3-channel
+# direct prediction
+NET_SHAPES_RECURRENT = [(8, 32, 3)] + NET_SHAPES[1:]
+
+
+def net_init(seed, recurrent=False):
     """Initial parameters (flat float32, each layer's [Co, Ci, k, k] weight then its
     bias): He-normal 3x3 convs with zero bias; direct head N(0, 1/fan_in); kernel
     head N(0, 0.01^2) with a +2 bias on the centre tap."""
     r = _rng(seed, 5)
     parts = []
-    for i, (ci, co, k) in enumerate(NET_SHAPES):
+    shapes = NET_SHAPES_RECURRENT if recurrent else NET_SHAPES
+    for i, (ci, co, k) in enumerate(shapes):
         fan = ci * k * k
         std = math.sqrt(2.0 / fan) if k == 3 else (math.sqrt(1.0 / fan) if co == 3 else 0.01)
         parts.append(r.normal(0.0, std, size=co * ci * k * k))

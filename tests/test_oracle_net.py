@@ -199,3 +199,84 @@ def test_temporal_loss_closed_forms_and_gradient():
         xm[idx] -= h
         fd = (N.temporal_loss(xp, t) - N.temporal_loss(xm, t)) / (2 * h)
         assert abs(fd - g[idx]) <= 1e-6 * abs(g[idx]) + 1e-9, (idx, fd, g[idx])
+
+
+def _embed_recurrent(theta):
+    """A recurrent parameter vector with the plain network's weights and zero
+    weights on the three fed-back channels."""
+    P = N.unflatten(np.asarray(theta, np.float64))
+    w, bias = P["e0a"]
+    P["e0a"] = (np.concatenate([w, np.zeros((w.shape[0], 3, 3, 3))], axis=1), bias)
+    th = N.flatten(P)
+    assert th.size == N.N_PARAMS_RECURRENT == N.N_PARAMS + 32 * 3 * 9
+    return th
+
+
+def test_recurrent_with_zero_feedback_weights_is_the_plain_network():
+    theta, x = _tiny_inputs()
+    th_r = _embed_recurrent(theta)
+    prev = rng.uniform(0, 1, size=(1, 3) + x.shape[2:])
+    want, want_od = N.forward(theta, x)
+    for p in (None, prev):
+        out, od = N.forward(th_r, N.recurrent_input(x, p))
+        np.testing.assert_allclose(out, want, atol=1e-12)
+        np.testing.assert_allclose(od, want_od, atol=1e-12)
+    with pytest.raises(ValueError):
+        N.forward(th_r, x)  # 5 channels into the 8-channel network
+
+
+def test_recurrent_gradient_finite_differences():
+    """The fed-back channels' weights get gradients too (central differences)."""
+    theta, x = _tiny_inputs()
+    th_r = _embed_recurrent(theta) + rng.normal(size=N.N_PARAMS_RECURRENT) * 1e-2
+    xr = N.recurrent_input(x, rng.uniform(0, 1, size=(1, 3) + x.shape[2:]))
+    out, od, cache = N.forward(th_r, xr, keep=True)
+    g = rng.normal(size=out.shape)
+    grad = N.backward(th_r, cache, g)
+    assert grad.size == N.N_PARAMS_RECURRENT
+    # e0a weight [co, ci, ky, kx]: the fed-back channels 5-7, and later layers
+    picks = [(co * 8 + ci) * 9 + t for co, ci, t in [(0, 5, 4), (7, 6, 0), (31, 7, 8), (3, 2, 5)]]
+    picks += [32 * 8 * 9 + 5, N.N_PARAMS_RECURRENT - 1, N.N_PARAMS_RECURRENT // 2]
+    h = 1e-6
+    for i in picks:
+        tp, tm = th_r.copy(), th_r.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = ((N.forward(tp, xr)[0] * g).sum() - (N.forward(tm, xr)[0] * g).sum()) / (2 * h)
+        assert abs(fd - grad[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-8, (i, fd, grad[i])
+
+
+def _accumulator_net(bias):
+    """A recurrent network that routes (sparse RGB + fed-back O_d) through the
+    full-resolution path only: e0a, e0b, the skip into d0a, d0b, the direct
+    head (plus a bias per channel); every other weight is zero, so the kernel
+    head's softmax is uniform (a 5x5 box filter of O_d)."""
+    P = {name: (np.zeros((co, ci, k, k)), np.zeros(co)) for name, ci, co, k in N.LAYERS_RECURRENT}
+    for j in range(3):
+        P["e0a"][0][j, j, 1, 1] = 1.0       # M * colour
+        P["e0a"][0][j, 5 + j, 1, 1] = 1.0   # previous O_d of the same colour
+        P["e0b"][0][j, j, 1, 1] = 1.0
+        P["d0a"][0][j, 48 + j, 1, 1] = 1.0  # the skip channels follow the 48 upsampled ones
+        P["d0b"][0][j, j, 1, 1] = 1.0
+        P["hd"][0][j, j, 0, 0] = 1.0
+        P["hd"][1][j] = bias[j]
+    return N.flatten(P)
+
+
+def test_recurrence_accumulates_direct_prediction_closed_form():
+    """With the accumulator network, O_d(t) = x(t) + O_d(t-1) + bias, i.e. the
+    running sum of the sparse colours plus (t+1) bias per channel: the
+    feedback is O_d (not the filtered output), of the previous frame, in
+    colour order.  The output is the 5x5 box filter of O_d with edge
+    replication."""
+    bias = np.array([0.1, 0.2, 0.3])
+    th = _accumulator_net(bias)
+    frames = [rng.uniform(0, 1, size=(2, 5, 16, 8)) for _ in range(4)]
+    outs, ods = N.forward_sequence(th, frames)
+    run = np.zeros((2, 3, 16, 8))
+    for t, x in enumerate(frames):
+        run = run + x[:, :3] + bias[None, :, None, None]
+        np.testing.assert_allclose(ods[t], run, atol=1e-12)
+        pad = np.pad(run, ((0, 0), (0, 0), (2, 2), (2, 2)), mode="edge")
+        box = sum(pad[:, :, dy:dy + 16, dx:dx + 8] for dy in range(5) for dx in range(5)) / 25
+        np.testing.assert_allclose(outs[t], box, atol=1e-12)
