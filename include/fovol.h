@@ -331,20 +331,35 @@ fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba,
  */
 #define FV_NET_PARAMS 480060
 
+/* Recurrent form (paper Sec. 3.2.4, the feedback of the direct prediction):
+ * the first conv (e0a) reads 8 channels, the 5 above followed by the
+ * previous frame's direct prediction O_d (r, g, b, FP32, unmasked), so its
+ * weight is [32][8][3][3] and the vector has 32 * 3 * 9 = 864 more entries.
+ * The first frame of a sequence is run with a zero O_d.  The recurrent
+ * decoder hidden states of the paper's network are not part of this form.
+ * fv_net_create tells the two forms apart by n_params. */
+#define FV_NET_PARAMS_RECURRENT 480924
+
 typedef enum { FV_PREC_BF16 = 1, FV_PREC_FP8 = 2 } fv_precision;
 
 typedef struct fv_net fv_net;
 
+/* FV_NET_PARAMS (the plain form). */
 size_t fv_net_param_count(void);
+/* Input channels of the handle's network: 5 (plain) or 8 (recurrent); -1
+ * for a null handle. */
+int fv_net_input_channels(const fv_net* n);
 
-/* Uploads host FP32 parameters (n_params == FV_NET_PARAMS), zeroes the Adam
+/* Uploads host FP32 parameters (n_params == FV_NET_PARAMS for the plain
+ * form, FV_NET_PARAMS_RECURRENT for the recurrent one), zeroes the Adam
  * state and builds the BF16 copy; synchronises the device.  FP8 is not
  * usable until fv_net_calibrate.  Errors: null pointers, wrong n_params,
  * allocation failure (FV_ERR_NOMEM). */
 fv_status fv_net_create(const float* host_params, size_t n_params, fv_net** out);
 fv_status fv_net_destroy(fv_net* n);
-/* Copies the FP32 master parameters to / from host memory (synchronous).
- * fv_net_set_params invalidates the FP8 copy. */
+/* Copies the FP32 master parameters to / from host memory (synchronous);
+ * n_params must be the handle's form's count.  fv_net_set_params
+ * invalidates the FP8 copy. */
 fv_status fv_net_get_params(const fv_net* n, float* host_params, size_t n_params);
 fv_status fv_net_set_params(fv_net* n, const float* host_params, size_t n_params);
 
@@ -368,6 +383,20 @@ fv_status fv_reconstruct(const fv_net* n, int precision, const float* frame_rgba
                          int width, int height, float* out_rgb, float* out_direct,
                          void* workspace, size_t ws_bytes, void* stream);
 
+/* fv_reconstruct for the recurrent form (Sec. 3.2.4): frame t of a sequence
+ * reads the direct prediction of frame t-1 of the same view.
+ *   prev_direct dev float [views*H*W*3] or NULL (zero: the first frame), the
+ *               out_direct of the previous call; it may be the same buffer
+ *               as this call's out_direct (it is read before O_d is written)
+ * fv_reconstruct on a recurrent network is this call with a NULL
+ * prev_direct.  Errors: those of fv_reconstruct, and a non-NULL prev_direct
+ * for a plain network (FV_ERR_INVALID_ARG). */
+fv_status fv_reconstruct_recurrent(const fv_net* n, int precision, const float* frame_rgba,
+                                   const uint8_t* mask, const float* frame_depth,
+                                   const float* prev_direct, int views, int width, int height,
+                                   float* out_rgb, float* out_direct, void* workspace,
+                                   size_t ws_bytes, void* stream);
+
 /* Post-training quantisation to FP8: runs one BF16 forward pass over the
  * given frames, records the largest magnitude of every activation tensor
  * (scale = max / 448), folds the scales into per-output-channel E4M3
@@ -377,6 +406,13 @@ fv_status fv_reconstruct(const fv_net* n, int precision, const float* frame_rgba
 fv_status fv_net_calibrate(fv_net* n, const float* frame_rgba, const uint8_t* mask,
                            const float* frame_depth, int views, int width, int height,
                            void* workspace, size_t ws_bytes, void* stream);
+/* The same with the fed-back O_d of the recurrent form in the calibration
+ * pass (prev_direct as in fv_reconstruct_recurrent), so the input tensor's
+ * scale covers it. */
+fv_status fv_net_calibrate_recurrent(fv_net* n, const float* frame_rgba, const uint8_t* mask,
+                                     const float* frame_depth, const float* prev_direct,
+                                     int views, int width, int height, void* workspace,
+                                     size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
  * 5. Training of the reconstruction network (paper: "Loss", "Training")
@@ -399,7 +435,8 @@ fv_status fv_net_calibrate(fv_net* n, const float* frame_rgba, const uint8_t* ma
  *   out_rgb / dloss_dout   dev float [batch*H*W*3]
  *   target_rgba            dev float [batch*H*W*4] (dense frames; RGB used)
  *   loss3                  dev float [3] = {loss, SSIM, L1}
- *   grad_out               dev float [FV_NET_PARAMS] or NULL
+ *   grad_out               dev float [FV_NET_PARAMS or FV_NET_PARAMS_RECURRENT,
+ *                          the handle's form] or NULL
  * Errors: null pointers, bad sizes, workspace too small (FV_ERR_CAPACITY),
  * hyper-parameters out of range (Adam: lr >= 0, betas in [0,1), eps > 0). */
 fv_status fv_train_workspace(const fv_net* n, int batch, int width, int height,
@@ -408,6 +445,17 @@ fv_status fv_net_forward_train(fv_net* n, const float* frame_rgba, const uint8_t
                                const float* frame_depth, int batch, int width, int height,
                                float* out_rgb, void* workspace, size_t ws_bytes,
                                void* stream);
+/* fv_net_forward_train for the recurrent form: entry b of the batch reads
+ * prev_direct[b] (dev float [batch*H*W*3], or NULL for zeros) as its
+ * previous frame's O_d.  The feedback is an input: fv_net_backward gives
+ * no gradient through it (the state is carried over one step, detached).
+ * Errors: those of fv_net_forward_train, and a non-NULL prev_direct for a
+ * plain network. */
+fv_status fv_net_forward_train_recurrent(fv_net* n, const float* frame_rgba,
+                                         const uint8_t* mask, const float* frame_depth,
+                                         const float* prev_direct, int batch, int width,
+                                         int height, float* out_rgb, void* workspace,
+                                         size_t ws_bytes, void* stream);
 fv_status fv_net_loss(const fv_net* n, const float* out_rgb, const float* target_rgba,
                       int batch, int width, int height, float* loss3, float* dloss_dout,
                       void* workspace, size_t ws_bytes, void* stream);

@@ -80,15 +80,21 @@ _SIGS = {
                                 ctypes.POINTER(MarchParams), _vp, _vp, _u32, _vp, _vp, _vp, _vp,
                                 _vp, _vp, _sz, _vp]),
     "fv_net_param_count": (_sz, []),
+    "fv_net_input_channels": (_i, [_vp]),
     "fv_net_create": (_i, [_vp, _sz, ctypes.POINTER(_vp)]),
     "fv_net_destroy": (_i, [_vp]),
     "fv_net_get_params": (_i, [_vp, _vp, _sz]),
     "fv_net_set_params": (_i, [_vp, _vp, _sz]),
     "fv_reconstruct_workspace": (_i, [_vp, _i, _i, _i, _i, ctypes.POINTER(_sz)]),
     "fv_reconstruct": (_i, [_vp, _i, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _sz, _vp]),
+    "fv_reconstruct_recurrent": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp,
+                                      _sz, _vp]),
     "fv_net_calibrate": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _sz, _vp]),
+    "fv_net_calibrate_recurrent": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _sz, _vp]),
     "fv_train_workspace": (_i, [_vp, _i, _i, _i, ctypes.POINTER(_sz)]),
     "fv_net_forward_train": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _sz, _vp]),
+    "fv_net_forward_train_recurrent": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _sz,
+                                            _vp]),
     "fv_net_loss": (_i, [_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _sz, _vp]),
     "fv_net_loss_temporal": (_i, [_vp, _vp, _vp, _i, _i, _i, ctypes.c_float, _vp, _vp, _vp, _sz,
                                   _vp]),
@@ -299,13 +305,22 @@ class Net:
         check(_lib.fv_net_create(ctypes.c_void_p(arr.ctypes.data), arr.size, ctypes.byref(h)))
         self.handle = h
 
+    # parameter counts of the plain form and of the recurrent form (the first
+    # conv also reads the previous frame's direct prediction, 3 channels)
+    PARAMS = 480060
+    PARAMS_RECURRENT = 480924
+
     @staticmethod
     def param_count():
         return int(_lib.fv_net_param_count())
 
+    @property
+    def recurrent(self):
+        return int(_lib.fv_net_input_channels(self.handle)) == 8
+
     def get_params(self):
         import numpy as np
-        out = np.zeros(self.param_count(), dtype=np.float32)
+        out = np.zeros(self.PARAMS_RECURRENT if self.recurrent else self.PARAMS, dtype=np.float32)
         check(_lib.fv_net_get_params(self.handle, ctypes.c_void_p(out.ctypes.data), out.size))
         return out
 
@@ -330,6 +345,30 @@ class Net:
                                   _ptr(out_direct), _ptr(workspace), workspace.numel(),
                                   _stream(stream)))
 
+    def reconstruct_recurrent(self, frame_rgba, mask, frame_depth, prev_direct, views, width,
+                              height, out_rgb, out_direct=None, precision="bf16",
+                              workspace=None, stream=None):
+        """Recurrent form: prev_direct is the previous frame's out_direct (None
+        for the first frame of a sequence); it may be out_direct itself."""
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes(views, width, height, precision),
+                                    dtype=torch.uint8, device=frame_rgba.device)
+        check(_lib.fv_reconstruct_recurrent(self.handle, _prec(precision), _ptr(frame_rgba),
+                                            _ptr(mask), _ptr(frame_depth), _ptr(prev_direct),
+                                            views, width, height, _ptr(out_rgb),
+                                            _ptr(out_direct), _ptr(workspace), workspace.numel(),
+                                            _stream(stream)))
+
+    def calibrate_recurrent(self, frame_rgba, mask, frame_depth, prev_direct, views, width,
+                            height, workspace=None, stream=None):
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes(views, width, height, "bf16"),
+                                    dtype=torch.uint8, device=frame_rgba.device)
+        check(_lib.fv_net_calibrate_recurrent(self.handle, _ptr(frame_rgba), _ptr(mask),
+                                              _ptr(frame_depth), _ptr(prev_direct), views, width,
+                                              height, _ptr(workspace), workspace.numel(),
+                                              _stream(stream)))
+
     def calibrate(self, frame_rgba, mask, frame_depth, views, width, height, workspace=None,
                   stream=None):
         if workspace is None:
@@ -350,6 +389,13 @@ class Net:
         check(_lib.fv_net_forward_train(self.handle, _ptr(frame_rgba), _ptr(mask),
                                         _ptr(frame_depth), batch, width, height, _ptr(out_rgb),
                                         _ptr(workspace), workspace.numel(), _stream(stream)))
+
+    def forward_train_recurrent(self, frame_rgba, mask, frame_depth, prev_direct, batch, width,
+                                height, out_rgb, workspace, stream=None):
+        check(_lib.fv_net_forward_train_recurrent(self.handle, _ptr(frame_rgba), _ptr(mask),
+                                                  _ptr(frame_depth), _ptr(prev_direct), batch,
+                                                  width, height, _ptr(out_rgb), _ptr(workspace),
+                                                  workspace.numel(), _stream(stream)))
 
     def loss(self, out_rgb, target_rgba, batch, width, height, loss3, dloss, workspace,
              stream=None):

@@ -29,8 +29,13 @@ struct LayerDesc {
 };
 
 // Canonical layer order (also the order of the flat parameter vector:
-// each layer's weight [Co][Ci][k][k] then its bias [Co]).
+// each layer's weight [Co][Ci][k][k] then its bias [Co]).  Inside the
+// library the first conv always reads 8 input channels: the 5 of the sparse
+// frame and 3 for the previous frame's direct prediction O_d (the recurrent
+// form, paper Sec. 3.2.4).  The plain network keeps zero weights on those
+// channels and its parameter vector leaves them out (external layout).
 extern const LayerDesc kLayers[kNumLayers];
+constexpr int kFedBack = 3;  // fed-back channels of the recurrent form
 
 __host__ __device__ inline int cip_of(int ci) { return (ci + 7) / 8 * 8; }
 // K chunks of a 3x3 conv over ci input channels: 32 wide (BF16 MFMA) or
@@ -39,9 +44,15 @@ __host__ __device__ inline int kchunks_of(int ci) { return (9 * cip_of(ci) + 31)
 __host__ __device__ inline int kchunks128_of(int ci) { return (9 * cip_of(ci) + 127) / 128; }
 __host__ __device__ inline int nblocks_of(int co) { return (co + 15) / 16; }
 
-// Offsets of each layer's weight / bias in the flat parameter vector.
+// Offsets of each layer's weight / bias in the internal parameter vector.
 int64_t param_offset(int layer);
 int64_t param_count();
+// Length of the external parameter vector of either form.
+int64_t external_param_count(int recurrent);
+// External <-> internal layout (they differ in the first conv's weights of
+// the plain form only).
+void params_to_internal(const float* ext, int recurrent, float* internal);
+void params_to_external(const float* internal, int recurrent, float* ext);
 
 // Activation tensors of one forward pass (indices into Plan::t).
 enum Tensor {
@@ -108,4 +119,5 @@ struct fv_net {
   float* bias_fp8[fv::net::kNumConv];   // bias / output scale
   float act_scale[fv::net::kNumTensors];  // FP8 per-tensor activation scales
   int fp8_ready;
+  int recurrent;  // 1: the first conv reads the previous frame's O_d
 };

@@ -13,7 +13,7 @@ namespace net {
 
 const LayerDesc kLayers[kNumLayers] = {
     // name   ci  co  k lvl  c0  c1 up0
-    {"e0a", 5, 32, 3, 0, 8, 0, 0},     {"e0b", 32, 32, 3, 0, 32, 0, 0},
+    {"e0a", 8, 32, 3, 0, 8, 0, 0},     {"e0b", 32, 32, 3, 0, 32, 0, 0},
     {"e1a", 32, 48, 3, 1, 32, 0, 0},   {"e1b", 48, 48, 3, 1, 48, 0, 0},
     {"e2a", 48, 64, 3, 2, 48, 0, 0},   {"e2b", 64, 64, 3, 2, 64, 0, 0},
     {"e3a", 64, 96, 3, 3, 64, 0, 0},   {"e3b", 96, 96, 3, 3, 96, 0, 0},
@@ -47,6 +47,40 @@ int64_t param_offset(int layer) {
 
 int64_t param_count() { return param_offset(kNumLayers); }
 
+int64_t external_param_count(int recurrent) {
+  return param_count() - (recurrent ? 0 : (int64_t)kLayers[0].co * kFedBack * 9);
+}
+
+// The first conv's weights are [32][8][3][3] inside and [32][5][3][3] in the
+// plain form's external vector; everything after them is shifted alike.
+void params_to_internal(const float* ext, int recurrent, float* in) {
+  const int64_t n = param_count();
+  if (recurrent) {
+    std::memcpy(in, ext, n * sizeof(float));
+    return;
+  }
+  const int co = kLayers[0].co, ci = kLayers[0].ci, ce = ci - kFedBack;
+  for (int o = 0; o < co; ++o)
+    for (int c = 0; c < ci; ++c)
+      for (int t = 0; t < 9; ++t)
+        in[((int64_t)o * ci + c) * 9 + t] = c < ce ? ext[((int64_t)o * ce + c) * 9 + t] : 0.0f;
+  const int64_t wi = (int64_t)co * ci * 9, we = (int64_t)co * ce * 9;
+  std::memcpy(in + wi, ext + we, (n - wi) * sizeof(float));
+}
+
+void params_to_external(const float* in, int recurrent, float* ext) {
+  const int64_t n = param_count();
+  if (recurrent) {
+    std::memcpy(ext, in, n * sizeof(float));
+    return;
+  }
+  const int co = kLayers[0].co, ci = kLayers[0].ci, ce = ci - kFedBack;
+  for (int o = 0; o < co; ++o)
+    std::memcpy(ext + (int64_t)o * ce * 9, in + (int64_t)o * ci * 9, ce * 9 * sizeof(float));
+  const int64_t wi = (int64_t)co * ci * 9, we = (int64_t)co * ce * 9;
+  std::memcpy(ext + we, in + wi, (n - wi) * sizeof(float));
+}
+
 static size_t align256(size_t v) { return (v + 255) / 256 * 256; }
 
 Plan make_plan(int n, int h, int w, size_t elem) {
@@ -73,13 +107,17 @@ Plan make_plan(int n, int h, int w, size_t elem) {
 
 // ------------------------------------------------------------------ kernels
 
-// Sparse frame -> 8-channel network input [M r, M g, M b, M, M depth/2, 0, 0, 0]
-// (the back-projected sparse image with its mask and depth; paper: the network
-// reconstructs from the sparse RGB input).  Pixels with M = 0 are not read.
+// Sparse frame -> 8-channel network input
+// [M r, M g, M b, M, M depth/2, O_d,prev r, g, b] (the back-projected sparse
+// image with its mask and depth; paper: the network reconstructs from the
+// sparse RGB input; the last three are the previous frame's direct
+// prediction in the recurrent form, Sec. 3.2.4, else 0).  The frame is not
+// read where M = 0; the previous O_d is read everywhere.
 template <class E>
 __global__ void __launch_bounds__(256) k_pack(const float4* __restrict__ rgba,
                                               const uint8_t* __restrict__ mask,
-                                              const float* __restrict__ depth, uint8_t* out,
+                                              const float* __restrict__ depth,
+                                              const float* __restrict__ prev, uint8_t* out,
                                               int64_t npx, float inv_scale,
                                               float* __restrict__ absmax) {
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -92,9 +130,14 @@ __global__ void __launch_bounds__(256) k_pack(const float4* __restrict__ rgba,
     v[3] = 1.0f;
     v[4] = depth ? 0.5f * depth[p] : 0.0f;
   }
+  if (p < npx && prev) {
+    v[5] = prev[p * 3 + 0];
+    v[6] = prev[p * 3 + 1];
+    v[7] = prev[p * 3 + 2];
+  }
   if (absmax) {
     float m = 0.f;
-    for (int i = 0; i < 5; ++i) m = fmaxf(m, fabsf(v[i]));
+    for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(v[i]));
     wave_absmax(absmax, m);
   }
   if (p >= npx) return;
@@ -474,15 +517,16 @@ fv_status refresh_bf16(fv_net* n, hipStream_t s) {
 // BF16 pass records per-tensor maxima (calibration).
 template <class E>
 fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const float* frame,
-                       const uint8_t* mask, const float* depth, float* out_rgb, float* out_od,
-                       float* out_wk, float* absmax, hipStream_t s, bool fuse_first) {
+                       const uint8_t* mask, const float* depth, const float* prev,
+                       float* out_rgb, float* out_od, float* out_wk, float* absmax,
+                       hipStream_t s, bool fuse_first) {
   const bool fp8 = E::kBytes == 1;
   const int64_t npx = (int64_t)p.n * p.h * p.w;
   const float in_inv = fp8 ? 1.0f / net->act_scale[T_IN] : 1.0f;
   fv_status st = FV_OK;
   if (!fuse_first) {
     k_pack<E><<<(unsigned)((npx + 255) / 256), 256, 0, s>>>(
-        (const float4*)frame, mask, depth, ws + p.t[T_IN], npx, in_inv,
+        (const float4*)frame, mask, depth, prev, ws + p.t[T_IN], npx, in_inv,
         absmax ? absmax + T_IN : nullptr);
     st = launch_status("pack");
     if (st != FV_OK) return st;
@@ -525,6 +569,7 @@ fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const floa
       a.f_rgba = (const float4*)frame;
       a.f_mask = mask;
       a.f_depth = depth;
+      a.f_prev = prev;
       a.f_inv = in_inv;
       a.f_wsw = (const uint8_t*)(fp8 ? net->w_fp8[0] : net->w_bf16[0]);
       a.f_kc = fp8 ? kchunks128_of(L0.ci) : kchunks_of(L0.ci);
@@ -545,11 +590,11 @@ fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const floa
 }
 
 template fv_status forward_impl<BF16>(const fv_net*, const Plan&, uint8_t*, const float*,
-                                      const uint8_t*, const float*, float*, float*, float*,
-                                      float*, hipStream_t, bool);
+                                      const uint8_t*, const float*, const float*, float*, float*,
+                                      float*, float*, hipStream_t, bool);
 template fv_status forward_impl<FP8>(const fv_net*, const Plan&, uint8_t*, const float*,
-                                     const uint8_t*, const float*, float*, float*, float*, float*,
-                                     hipStream_t, bool);
+                                     const uint8_t*, const float*, const float*, float*, float*,
+                                     float*, float*, hipStream_t, bool);
 
 // FP8 weights: fold the per-input-channel activation scales into the
 // weights, quantise per output channel (E4M3, |q| <= 448), and fold the
@@ -640,17 +685,27 @@ using namespace fv::net;
 
 extern "C" {
 
-size_t fv_net_param_count(void) { return (size_t)param_count(); }
+size_t fv_net_param_count(void) { return (size_t)external_param_count(0); }
+
+int fv_net_input_channels(const fv_net* n) {
+  if (!n) return -1;
+  return n->recurrent ? kLayers[0].ci : kLayers[0].ci - kFedBack;
+}
 
 fv_status fv_net_create(const float* host_params, size_t n_params, fv_net** out) {
   clear_error();
   if (!host_params || !out) return fail(FV_ERR_INVALID_ARG, "fv_net_create: null pointer");
   *out = nullptr;
-  if (n_params != (size_t)param_count())
-    return fail(FV_ERR_INVALID_ARG, "fv_net_create: %zu parameters, expected %lld", n_params,
-                (long long)param_count());
+  if (n_params != (size_t)external_param_count(0) && n_params != (size_t)external_param_count(1))
+    return fail(FV_ERR_INVALID_ARG,
+                "fv_net_create: %zu parameters, expected %lld (plain) or %lld (recurrent)",
+                n_params, (long long)external_param_count(0), (long long)external_param_count(1));
   fv_net* n = new fv_net();
   memset(n, 0, sizeof(*n));
+  n->recurrent = n_params == (size_t)external_param_count(1);
+  std::vector<float> internal((size_t)param_count());
+  params_to_internal(host_params, n->recurrent, internal.data());
+  n_params = internal.size();
   if (hipGetDevice(&n->device) != hipSuccess) {
     delete n;
     return fail(FV_ERR_DEVICE, "fv_net_create: hipGetDevice");
@@ -674,7 +729,7 @@ fv_status fv_net_create(const float* host_params, size_t n_params, fv_net** out)
     fv_net_destroy(n);
     return fail(FV_ERR_NOMEM, "fv_net_create: allocation failed");
   }
-  fv_status st = hip_status(hipMemcpy(n->master, host_params, pb, hipMemcpyHostToDevice),
+  fv_status st = hip_status(hipMemcpy(n->master, internal.data(), pb, hipMemcpyHostToDevice),
                             "fv_net_create: upload");
   if (st == FV_OK) st = hip_status(hipMemset(n->adam_m, 0, pb), "fv_net_create: adam");
   if (st == FV_OK) st = hip_status(hipMemset(n->adam_v, 0, pb), "fv_net_create: adam");
@@ -711,19 +766,27 @@ fv_status fv_net_destroy(fv_net* n) {
 fv_status fv_net_get_params(const fv_net* n, float* host_params, size_t n_params) {
   clear_error();
   if (!n || !host_params) return fail(FV_ERR_INVALID_ARG, "fv_net_get_params: null pointer");
-  if (n_params != (size_t)param_count())
-    return fail(FV_ERR_INVALID_ARG, "fv_net_get_params: size %zu", n_params);
-  return hip_status(hipMemcpy(host_params, n->master, n_params * sizeof(float),
-                              hipMemcpyDeviceToHost), "fv_net_get_params");
+  if (n_params != (size_t)external_param_count(n->recurrent))
+    return fail(FV_ERR_INVALID_ARG, "fv_net_get_params: size %zu, the network has %lld",
+                n_params, (long long)external_param_count(n->recurrent));
+  std::vector<float> internal((size_t)param_count());
+  fv_status st = hip_status(hipMemcpy(internal.data(), n->master, internal.size() * sizeof(float),
+                                      hipMemcpyDeviceToHost), "fv_net_get_params");
+  if (st == FV_OK) params_to_external(internal.data(), n->recurrent, host_params);
+  return st;
 }
 
 fv_status fv_net_set_params(fv_net* n, const float* host_params, size_t n_params) {
   clear_error();
   if (!n || !host_params) return fail(FV_ERR_INVALID_ARG, "fv_net_set_params: null pointer");
-  if (n_params != (size_t)param_count())
-    return fail(FV_ERR_INVALID_ARG, "fv_net_set_params: size %zu", n_params);
-  fv_status st = hip_status(hipMemcpy(n->master, host_params, n_params * sizeof(float),
-                                      hipMemcpyHostToDevice), "fv_net_set_params");
+  if (n_params != (size_t)external_param_count(n->recurrent))
+    return fail(FV_ERR_INVALID_ARG, "fv_net_set_params: size %zu, the network has %lld",
+                n_params, (long long)external_param_count(n->recurrent));
+  std::vector<float> internal((size_t)param_count());
+  params_to_internal(host_params, n->recurrent, internal.data());
+  fv_status st = hip_status(hipMemcpy(n->master, internal.data(),
+                                      internal.size() * sizeof(float), hipMemcpyHostToDevice),
+                            "fv_net_set_params");
   if (st == FV_OK) st = refresh_bf16(n, nullptr);
   if (st == FV_OK) st = hip_status(hipDeviceSynchronize(), "fv_net_set_params: sync");
   n->fp8_ready = 0;
@@ -742,52 +805,76 @@ fv_status fv_reconstruct_workspace(const fv_net* n, int precision, int views, in
   return FV_OK;
 }
 
+static fv_status reconstruct(const fv_net* n, int precision, const float* frame_rgba,
+                             const uint8_t* mask, const float* frame_depth, const float* prev,
+                             int views, int width, int height, float* out_rgb,
+                             float* out_direct, void* workspace, size_t ws_bytes, void* stream,
+                             const char* fn) {
+  clear_error();
+  if (!n || !frame_rgba || !mask || !out_rgb || !workspace)
+    return fail(FV_ERR_INVALID_ARG, "%s: null pointer", fn);
+  if (prev && !n->recurrent)
+    return fail(FV_ERR_INVALID_ARG, "%s: the network has no recurrent input", fn);
+  if (precision != FV_PREC_BF16 && precision != FV_PREC_FP8)
+    return fail(FV_ERR_UNSUPPORTED, "%s: precision %d", fn, precision);
+  fv_status st = check_frame(views, width, height, fn);
+  if (st != FV_OK) return st;
+  if (precision == FV_PREC_FP8 && !n->fp8_ready)
+    return fail(FV_ERR_INVALID_ARG, "%s: FP8 requested before fv_net_calibrate", fn);
+  const Plan p = make_plan(views, height, width, precision == FV_PREC_FP8 ? 1 : 2);
+  if (ws_bytes < p.bytes)
+    return fail(FV_ERR_CAPACITY, "%s: workspace %zu < %zu bytes", fn, ws_bytes, p.bytes);
+  if ((uintptr_t)workspace % 256)
+    return fail(FV_ERR_INVALID_ARG, "%s: workspace not 256-byte aligned", fn);
+  hipStream_t s = (hipStream_t)stream;
+  if (precision == FV_PREC_FP8)
+    return forward_impl<FP8>(n, p, (uint8_t*)workspace, frame_rgba, mask, frame_depth, prev,
+                             out_rgb, out_direct, nullptr, nullptr, s, true);
+  return forward_impl<BF16>(n, p, (uint8_t*)workspace, frame_rgba, mask, frame_depth, prev,
+                            out_rgb, out_direct, nullptr, nullptr, s, true);
+}
+
 fv_status fv_reconstruct(const fv_net* n, int precision, const float* frame_rgba,
                          const uint8_t* mask, const float* frame_depth, int views, int width,
                          int height, float* out_rgb, float* out_direct, void* workspace,
                          size_t ws_bytes, void* stream) {
-  clear_error();
-  if (!n || !frame_rgba || !mask || !out_rgb || !workspace)
-    return fail(FV_ERR_INVALID_ARG, "fv_reconstruct: null pointer");
-  if (precision != FV_PREC_BF16 && precision != FV_PREC_FP8)
-    return fail(FV_ERR_UNSUPPORTED, "fv_reconstruct: precision %d", precision);
-  fv_status st = check_frame(views, width, height, "fv_reconstruct");
-  if (st != FV_OK) return st;
-  if (precision == FV_PREC_FP8 && !n->fp8_ready)
-    return fail(FV_ERR_INVALID_ARG, "fv_reconstruct: FP8 requested before fv_net_calibrate");
-  const Plan p = make_plan(views, height, width, precision == FV_PREC_FP8 ? 1 : 2);
-  if (ws_bytes < p.bytes)
-    return fail(FV_ERR_CAPACITY, "fv_reconstruct: workspace %zu < %zu bytes", ws_bytes, p.bytes);
-  if ((uintptr_t)workspace % 256)
-    return fail(FV_ERR_INVALID_ARG, "fv_reconstruct: workspace not 256-byte aligned");
-  hipStream_t s = (hipStream_t)stream;
-  if (precision == FV_PREC_FP8)
-    return forward_impl<FP8>(n, p, (uint8_t*)workspace, frame_rgba, mask, frame_depth, out_rgb,
-                             out_direct, nullptr, nullptr, s, true);
-  return forward_impl<BF16>(n, p, (uint8_t*)workspace, frame_rgba, mask, frame_depth, out_rgb,
-                            out_direct, nullptr, nullptr, s, true);
+  return reconstruct(n, precision, frame_rgba, mask, frame_depth, nullptr, views, width, height,
+                     out_rgb, out_direct, workspace, ws_bytes, stream, "fv_reconstruct");
 }
 
-fv_status fv_net_calibrate(fv_net* n, const float* frame_rgba, const uint8_t* mask,
-                           const float* frame_depth, int views, int width, int height,
-                           void* workspace, size_t ws_bytes, void* stream) {
+fv_status fv_reconstruct_recurrent(const fv_net* n, int precision, const float* frame_rgba,
+                                   const uint8_t* mask, const float* frame_depth,
+                                   const float* prev_direct, int views, int width, int height,
+                                   float* out_rgb, float* out_direct, void* workspace,
+                                   size_t ws_bytes, void* stream) {
+  return reconstruct(n, precision, frame_rgba, mask, frame_depth, prev_direct, views, width,
+                     height, out_rgb, out_direct, workspace, ws_bytes, stream,
+                     "fv_reconstruct_recurrent");
+}
+
+static fv_status calibrate(fv_net* n, const float* frame_rgba, const uint8_t* mask,
+                           const float* frame_depth, const float* prev, int views, int width,
+                           int height, void* workspace, size_t ws_bytes, void* stream,
+                           const char* fn) {
   clear_error();
   if (!n || !frame_rgba || !mask || !workspace)
-    return fail(FV_ERR_INVALID_ARG, "fv_net_calibrate: null pointer");
-  fv_status st = check_frame(views, width, height, "fv_net_calibrate");
+    return fail(FV_ERR_INVALID_ARG, "%s: null pointer", fn);
+  if (prev && !n->recurrent)
+    return fail(FV_ERR_INVALID_ARG, "%s: the network has no recurrent input", fn);
+  fv_status st = check_frame(views, width, height, fn);
   if (st != FV_OK) return st;
   const Plan p = make_plan(views, height, width, 2);
   if (ws_bytes < p.bytes)
-    return fail(FV_ERR_CAPACITY, "fv_net_calibrate: workspace %zu < %zu bytes (BF16 plan)",
-                ws_bytes, p.bytes);
+    return fail(FV_ERR_CAPACITY, "%s: workspace %zu < %zu bytes (BF16 plan)", fn, ws_bytes,
+                p.bytes);
   hipStream_t s = (hipStream_t)stream;
   uint8_t* ws = (uint8_t*)workspace;
   float* amax = (float*)(ws + p.absmax);
   k_zero_f32<<<1, 64, 0, s>>>(amax, 64);
   if ((st = launch_status("calibrate: clear")) != FV_OK) return st;
   float* tmp_rgb = (float*)(ws + p.od);  // the O_d slot is free in this pass
-  st = forward_impl<BF16>(n, p, ws, frame_rgba, mask, frame_depth, tmp_rgb, nullptr, nullptr,
-                          amax, s, false);
+  st = forward_impl<BF16>(n, p, ws, frame_rgba, mask, frame_depth, prev, tmp_rgb, nullptr,
+                          nullptr, amax, s, false);
   if (st != FV_OK) return st;
   float host[64];
   st = hip_status(hipMemcpyAsync(host, amax, sizeof host, hipMemcpyDeviceToHost, s),
@@ -799,6 +886,21 @@ fv_status fv_net_calibrate(fv_net* n, const float* frame_rgba, const uint8_t* ma
   n->act_scale[T_P1] = n->act_scale[T_E1B];
   n->act_scale[T_P2] = n->act_scale[T_E2B];
   return build_fp8(n, s);
+}
+
+fv_status fv_net_calibrate(fv_net* n, const float* frame_rgba, const uint8_t* mask,
+                           const float* frame_depth, int views, int width, int height,
+                           void* workspace, size_t ws_bytes, void* stream) {
+  return calibrate(n, frame_rgba, mask, frame_depth, nullptr, views, width, height, workspace,
+                   ws_bytes, stream, "fv_net_calibrate");
+}
+
+fv_status fv_net_calibrate_recurrent(fv_net* n, const float* frame_rgba, const uint8_t* mask,
+                                     const float* frame_depth, const float* prev_direct,
+                                     int views, int width, int height, void* workspace,
+                                     size_t ws_bytes, void* stream) {
+  return calibrate(n, frame_rgba, mask, frame_depth, prev_direct, views, width, height,
+                   workspace, ws_bytes, stream, "fv_net_calibrate_recurrent");
 }
 
 }  // extern "C"

@@ -245,14 +245,16 @@ struct ConvArgs {
   int b_lds;  // set by launch_conv: the weight fragments are staged in LDS
   // Fused first layer (inference, 2 output blocks, b_lds): the patch of this
   // conv is computed in the block from the frame instead of read from src0:
-  // the packed input [M rgb, M, M depth / 2] (times f_inv, the input tensor's
-  // inverse scale; zero outside the image), then a 3x3 conv of its 8 (5 used)
-  // channels to co0 = 32 channels with scale/bias f_alpha/f_bias and ReLU,
-  // zero outside the image (the padding of this conv).
+  // the packed input [M rgb, M, M depth / 2, O_d,prev rgb] (times f_inv, the
+  // input tensor's inverse scale; zero outside the image; O_d,prev = 0 when
+  // f_prev is null), then a 3x3 conv of its 8 channels to co0 = 32 channels
+  // with scale/bias f_alpha/f_bias and ReLU, zero outside the image (the
+  // padding of this conv).
   int fuse0;
   const float4* f_rgba;
   const uint8_t* f_mask;
   const float* f_depth;
+  const float* f_prev;  // [n h w 3] or null
   float f_inv;
   const uint8_t* f_wsw;  // the first layer's weight fragments
   int f_kc;
@@ -365,10 +367,12 @@ __device__ __forceinline__ void fuse0_fill(const ConvArgs& a, uint8_t* smem, int
   float4 px_c[2];
   uint32_t px_m[2];
   float px_d[2];
+  float px_p[2][3];
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
     const int i = tid + u * 256;
     px_m[u] = 0;
+    px_p[u][0] = px_p[u][1] = px_p[u][2] = 0.0f;
     if (i < IR * IC) {
       const int r = i / IC, c = i - r * IC;
       const int y = y0 - 2 + r, x = x0 - 2 + c;
@@ -377,6 +381,11 @@ __device__ __forceinline__ void fuse0_fill(const ConvArgs& a, uint8_t* smem, int
         px_m[u] = a.f_mask[p];
         px_c[u] = a.f_rgba[p];
         px_d[u] = a.f_depth ? a.f_depth[p] : 0.0f;
+        if (a.f_prev) {
+          px_p[u][0] = a.f_prev[p * 3 + 0];
+          px_p[u][1] = a.f_prev[p * 3 + 1];
+          px_p[u][2] = a.f_prev[p * 3 + 2];
+        }
       }
     }
   }
@@ -440,6 +449,9 @@ __device__ __forceinline__ void fuse0_fill(const ConvArgs& a, uint8_t* smem, int
       v[3] = 1.0f;
       v[4] = 0.5f * px_d[u];
     }
+    v[5] = px_p[u][0];
+    v[6] = px_p[u][1];
+    v[7] = px_p[u][2];
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] *= a.f_inv;
     E::store8(in + (size_t)i * 8 * E::kBytes, v);

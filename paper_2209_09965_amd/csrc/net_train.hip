@@ -17,8 +17,9 @@ namespace net {
 
 template <class E>
 fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const float* frame,
-                       const uint8_t* mask, const float* depth, float* out_rgb, float* out_od,
-                       float* out_wk, float* absmax, hipStream_t s, bool fuse_first);
+                       const uint8_t* mask, const float* depth, const float* prev,
+                       float* out_rgb, float* out_od, float* out_wk, float* absmax,
+                       hipStream_t s, bool fuse_first);
 fv_status refresh_bf16(fv_net* n, hipStream_t s);
 fv_status check_frame(int views, int W, int H, const char* fn);
 
@@ -654,20 +655,37 @@ static fv_status train_check(const fv_net* n, int batch, int width, int height, 
   return FV_OK;
 }
 
+static fv_status forward_train(fv_net* n, const float* frame_rgba, const uint8_t* mask,
+                               const float* frame_depth, const float* prev, int batch,
+                               int width, int height, float* out_rgb, void* workspace,
+                               size_t ws_bytes, void* stream, const char* fn) {
+  clear_error();
+  TrainPlan tp;
+  fv_status st = train_check(n, batch, width, height, workspace, ws_bytes, &tp, fn);
+  if (st != FV_OK) return st;
+  if (!frame_rgba || !mask || !out_rgb) return fail(FV_ERR_INVALID_ARG, "%s: null pointer", fn);
+  if (prev && !n->recurrent)
+    return fail(FV_ERR_INVALID_ARG, "%s: the network has no recurrent input", fn);
+  uint8_t* ws = (uint8_t*)workspace;
+  return forward_impl<BF16>(n, tp.f, ws, frame_rgba, mask, frame_depth, prev, out_rgb,
+                            (float*)(ws + tp.f.od), (float*)(ws + tp.f.wk), nullptr,
+                            (hipStream_t)stream, false);
+}
+
 fv_status fv_net_forward_train(fv_net* n, const float* frame_rgba, const uint8_t* mask,
                                const float* frame_depth, int batch, int width, int height,
                                float* out_rgb, void* workspace, size_t ws_bytes, void* stream) {
-  clear_error();
-  TrainPlan tp;
-  fv_status st = train_check(n, batch, width, height, workspace, ws_bytes, &tp,
-                             "fv_net_forward_train");
-  if (st != FV_OK) return st;
-  if (!frame_rgba || !mask || !out_rgb)
-    return fail(FV_ERR_INVALID_ARG, "fv_net_forward_train: null pointer");
-  uint8_t* ws = (uint8_t*)workspace;
-  return forward_impl<BF16>(n, tp.f, ws, frame_rgba, mask, frame_depth, out_rgb,
-                            (float*)(ws + tp.f.od), (float*)(ws + tp.f.wk), nullptr,
-                            (hipStream_t)stream, false);
+  return forward_train(n, frame_rgba, mask, frame_depth, nullptr, batch, width, height, out_rgb,
+                       workspace, ws_bytes, stream, "fv_net_forward_train");
+}
+
+fv_status fv_net_forward_train_recurrent(fv_net* n, const float* frame_rgba,
+                                         const uint8_t* mask, const float* frame_depth,
+                                         const float* prev_direct, int batch, int width,
+                                         int height, float* out_rgb, void* workspace,
+                                         size_t ws_bytes, void* stream) {
+  return forward_train(n, frame_rgba, mask, frame_depth, prev_direct, batch, width, height,
+                       out_rgb, workspace, ws_bytes, stream, "fv_net_forward_train_recurrent");
 }
 
 fv_status fv_net_loss(const fv_net* n, const float* out_rgb, const float* target_rgba, int batch,
@@ -820,9 +838,26 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
                                                           G(src));
     if ((st = launch_status("dgrad")) != FV_OK) return st;
   }
-  if (grad_out)
-    st = hip_status(hipMemcpyAsync(grad_out, grad, param_count() * sizeof(float),
-                                   hipMemcpyDeviceToDevice, s), "fv_net_backward: copy grads");
+  if (grad_out) {
+    // in the external layout of the network's form
+    const int64_t P = param_count();
+    if (n->recurrent) {
+      st = hip_status(hipMemcpyAsync(grad_out, grad, P * sizeof(float), hipMemcpyDeviceToDevice,
+                                     s), "fv_net_backward: copy grads");
+    } else {
+      const LayerDesc& L0 = kLayers[0];
+      const int ce = L0.ci - kFedBack;
+      const int64_t wi = (int64_t)L0.co * L0.ci * 9, we = (int64_t)L0.co * ce * 9;
+      st = hip_status(hipMemcpy2DAsync(grad_out, ce * 9 * sizeof(float), grad,
+                                       L0.ci * 9 * sizeof(float), ce * 9 * sizeof(float), L0.co,
+                                       hipMemcpyDeviceToDevice, s),
+                      "fv_net_backward: copy grads");
+      if (st == FV_OK)
+        st = hip_status(hipMemcpyAsync(grad_out + we, grad + wi, (P - wi) * sizeof(float),
+                                       hipMemcpyDeviceToDevice, s),
+                        "fv_net_backward: copy grads");
+    }
+  }
   return st;
 }
 

@@ -125,3 +125,27 @@ def test_march_host_errors():
     assert L.fv_volume_create(None, 8, 8, 8, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
     assert L.fv_volume_create(fake, 0, 8, 8, 0, None, ctypes.byref(ctypes.c_void_p())) == -1
     assert L.fv_volume_create(fake, 8, 8, 8, 9, None, ctypes.byref(ctypes.c_void_p())) == -3
+
+
+def test_net_forms_host_checks():
+    """Both parameter counts are declared; a wrong count and null handles
+    are rejected on the host."""
+    from paper_2209_09965_amd import binding as b
+    from oracle import net as N
+    L = b.lib()
+    hdr = open(os.path.join(ROOT, "include", "fovol.h")).read()
+    assert "#define FV_NET_PARAMS %d" % N.N_PARAMS in hdr
+    assert "#define FV_NET_PARAMS_RECURRENT %d" % N.N_PARAMS_RECURRENT in hdr
+    assert b.Net.PARAMS == N.N_PARAMS and b.Net.PARAMS_RECURRENT == N.N_PARAMS_RECURRENT
+    assert L.fv_net_param_count() == N.N_PARAMS
+    assert L.fv_net_input_channels(None) == -1
+    theta = np.zeros(N.N_PARAMS + 1, np.float32)
+    h = ctypes.c_void_p()
+    assert L.fv_net_create(ctypes.c_void_p(theta.ctypes.data), theta.size, ctypes.byref(h)) == -1
+    assert b"parameters" in L.fv_last_error()
+    assert L.fv_reconstruct_recurrent(None, 1, None, None, None, None, 1, 8, 8, None, None, None,
+                                      0, None) == -1
+    assert L.fv_net_forward_train_recurrent(None, None, None, None, None, 1, 16, 16, None, None,
+                                            0, None) == -1
+    assert L.fv_net_calibrate_recurrent(None, None, None, None, None, 1, 8, 8, None, 0,
+                                        None) == -1

@@ -25,12 +25,17 @@ def bf16_round(a):
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
-def _theta(seed):
+def _shapes(theta):
+    return synthetic.NET_SHAPES_RECURRENT if theta.size == N.N_PARAMS_RECURRENT else \
+        synthetic.NET_SHAPES
+
+
+def _theta(seed, recurrent=False):
     rng = np.random.default_rng(seed)
-    th = synthetic.net_init(seed)
+    th = synthetic.net_init(seed, recurrent=recurrent)
     # non-zero biases everywhere so the bias path is exercised
     off = 0
-    for ci, co, k in synthetic.NET_SHAPES:
+    for ci, co, k in _shapes(th):
         nw = co * ci * k * k
         th[off + nw: off + nw + co] += rng.normal(0, 0.05, co).astype(np.float32)
         off += nw + co
@@ -42,7 +47,7 @@ def _bf16_weights(theta):
     1x1 heads) rounded to BF16, biases FP32."""
     th = theta.astype(np.float64).copy()
     off = 0
-    for ci, co, k in synthetic.NET_SHAPES:
+    for ci, co, k in _shapes(theta):
         nw = co * ci * k * k
         th[off:off + nw] = bf16_round(th[off:off + nw])
         off += nw + co
@@ -192,4 +197,147 @@ def test_fp8_forward_error_stated(dev):
     # zero-mean random-weight sum keeps that relative error (~5% per layer),
     # and 14 layers compound it to ~sqrt(14) * 5% ~ 19% on random weights
     assert e8 < 0.25
+    net.close()
+
+
+# ------------------------------------------------------------ recurrent form
+
+def _gpu_seq(net, frames, views, H, W, prec, dev, in_place=False):
+    """Runs the frames (rgba, mask, depth) in order through
+    reconstruct_recurrent, each reading the previous call's O_d; returns
+    the per-frame (out, O_d) in NCHW and the O_d each frame read."""
+    res, prevs = [], []
+    od_prev = None
+    for rgba, mask, depth in frames:
+        out = torch.full((views * H * W * 3,), float("nan"), device=dev)
+        od = od_prev if (in_place and od_prev is not None) else \
+            torch.full((views * H * W * 3,), float("nan"), device=dev)
+        prevs.append(None if od_prev is None else od_prev.cpu().numpy().copy())
+        net.reconstruct_recurrent(torch.from_numpy(rgba).reshape(-1).to(dev),
+                                  torch.from_numpy(mask).to(dev), torch.from_numpy(depth).to(dev),
+                                  od_prev, views, W, H, out, od, precision=prec)
+        torch.cuda.synchronize()
+        to = lambda t: t.cpu().numpy().reshape(views, H, W, 3).transpose(0, 3, 1, 2)
+        res.append((to(out), to(od)))
+        od_prev = od
+    return res, prevs
+
+
+def _nchw3(flat, views, H, W):
+    return None if flat is None else flat.reshape(views, H, W, 3).transpose(0, 3, 1, 2)
+
+
+@pytest.mark.parametrize("views,H,W", [(1, 64, 96), (2, 40, 56), (1, 256, 256)])
+def test_recurrent_sequence_matches_oracle(views, H, W, dev):
+    """Three frames through the recurrent form: every frame against the
+    BF16-emulated oracle given the same fed-back O_d, at the tolerance of the
+    single-frame test; the sequence run in place (O_d written over the
+    buffer it read) gives the same bits; frame 0 reads a zero O_d."""
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(views * 1000 + H)
+    theta = _theta(17, recurrent=True)
+    frames = [_frame(rng, views, H, W) for _ in range(3)]
+    net = b.Net(theta)
+    assert net.recurrent and net.get_params().size == N.N_PARAMS_RECURRENT
+    res, prevs = _gpu_seq(net, frames, views, H, W, "bf16", dev)
+    res2, _ = _gpu_seq(net, frames, views, H, W, "bf16", dev, in_place=True)
+    th16 = _bf16_weights(theta)
+    for t, ((out, od), prev) in enumerate(zip(res, prevs)):
+        assert np.array_equal(out, res2[t][0]) and np.array_equal(od, res2[t][1])
+        x = N.recurrent_input(_oracle_input(*frames[t], views, H, W),
+                              _nchw3(prev, views, H, W))
+        want, want_od = N.forward(th16, x, act_round=bf16_round)
+        err, err_od = np.abs(out - want), np.abs(od - want_od)
+        print("frame %d: out max %.3g mean %.3g | O_d max %.3g mean %.3g"
+              % (t, err.max(), err.mean(), err_od.max(), err_od.mean()), flush=True)
+        assert np.isfinite(out).all()
+        # BF16 rounding is relative: the bounds of the single-frame test at its
+        # output scale (|out| ~ 0.2), scaled with this frame's |out|, which
+        # grows along the sequence of a random-weight recurrent network
+        sc = max(1.0, np.abs(want).mean() / 0.2)
+        assert err.max() < 2e-2 * sc and err.mean() < 5e-4 * sc
+        assert err_od.max() < 3e-2 * sc and \
+            err_od.mean() < 2e-3 * max(1.0, np.abs(want_od).mean() / 0.2)
+    # the first frame equals the plain call (no fed-back O_d)
+    out0, od0 = _gpu(net, *frames[0], views, H, W, "bf16", dev)
+    assert np.array_equal(out0, res[0][0]) and np.array_equal(od0, res[0][1])
+    net.close()
+
+
+def test_recurrent_fused_first_layer_bit_exact(dev):
+    """The fused first layer reads the fed-back O_d as the separate pack
+    kernel of the training forward does: equal bit for bit."""
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(41)
+    views, H, W = 1, 256, 256
+    theta = _theta(18, recurrent=True)
+    rgba, mask, depth = _frame(rng, views, H, W)
+    prev = torch.from_numpy(rng.uniform(0, 1, views * H * W * 3).astype(np.float32)).to(dev)
+    net = b.Net(theta)
+    out = torch.full((views * H * W * 3,), float("nan"), device=dev)
+    fr, m, d = (torch.from_numpy(a).reshape(-1).to(dev) for a in (rgba, mask, depth))
+    net.reconstruct_recurrent(fr, m, d, prev, views, W, H, out)
+    ws = torch.empty(net.train_workspace_bytes(views, W, H), dtype=torch.uint8, device=dev)
+    out2 = torch.full((views * H * W * 3,), float("nan"), device=dev)
+    net.forward_train_recurrent(fr, m, d, prev, views, W, H, out2, ws)
+    torch.cuda.synchronize()
+    a, b2 = out.cpu().numpy(), out2.cpu().numpy()
+    assert np.isfinite(a).all()
+    assert np.array_equal(a, b2), np.abs(a - b2).max()
+    net.close()
+
+
+def test_zero_feedback_weights_equal_plain_network(dev):
+    """A recurrent network whose fed-back channels have zero weights is the
+    plain network bit for bit, whatever O_d it reads; the parameters of both
+    forms come back unchanged."""
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(43)
+    views, H, W = 1, 64, 64
+    theta = _theta(19)
+    P = N.unflatten(theta.astype(np.float64))
+    w, bias = P["e0a"]
+    P["e0a"] = (np.concatenate([w, np.zeros((32, 3, 3, 3))], axis=1), bias)
+    th_r = N.flatten(P).astype(np.float32)
+    plain, rec = b.Net(theta), b.Net(th_r)
+    assert not plain.recurrent and rec.recurrent
+    assert np.array_equal(plain.get_params(), theta)
+    assert np.array_equal(rec.get_params(), th_r)
+    rgba, mask, depth = _frame(rng, views, H, W)
+    want, want_od = _gpu(plain, rgba, mask, depth, views, H, W, "bf16", dev)
+    fr, m, d = (torch.from_numpy(a).reshape(-1).to(dev) for a in (rgba, mask, depth))
+    prev = torch.from_numpy(rng.uniform(0, 1, views * H * W * 3).astype(np.float32)).to(dev)
+    out = torch.empty(views * H * W * 3, device=dev)
+    od = torch.empty(views * H * W * 3, device=dev)
+    rec.reconstruct_recurrent(fr, m, d, prev, views, W, H, out, od)
+    torch.cuda.synchronize()
+    to = lambda t: t.cpu().numpy().reshape(views, H, W, 3).transpose(0, 3, 1, 2)
+    assert np.array_equal(to(out), want) and np.array_equal(to(od), want_od)
+    with pytest.raises(RuntimeError):
+        plain.reconstruct_recurrent(fr, m, d, prev, views, W, H, out, od)
+    plain.close()
+    rec.close()
+
+
+def test_recurrent_fp8_error_stated(dev):
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(47)
+    views, H, W = 1, 64, 64
+    theta = _theta(20, recurrent=True)
+    rgba, mask, depth = _frame(rng, views, H, W)
+    prev_np = rng.uniform(0, 1, views * H * W * 3).astype(np.float32)
+    prev = torch.from_numpy(prev_np).to(dev)
+    fr, m, d = (torch.from_numpy(a).reshape(-1).to(dev) for a in (rgba, mask, depth))
+    net = b.Net(theta)
+    net.calibrate_recurrent(fr, m, d, prev, views, W, H)
+    out = torch.empty(views * H * W * 3, device=dev)
+    net.reconstruct_recurrent(fr, m, d, prev, views, W, H, out, precision="fp8")
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(views, H, W, 3).transpose(0, 3, 1, 2)
+    x = N.recurrent_input(_oracle_input(rgba, mask, depth, views, H, W),
+                          _nchw3(prev_np, views, H, W))
+    exact, _ = N.forward(theta.astype(np.float64), x)
+    e8 = np.abs(got - exact).mean() / np.abs(exact).mean()
+    print("recurrent fp8 relative mean error vs FP64 net: %.4f" % e8, flush=True)
+    assert np.isfinite(got).all() and e8 < 0.25
     net.close()

@@ -145,3 +145,48 @@ def test_temporal_loss_matches_oracle(dev):
     with pytest.raises(b.FvError, match="weight"):
         net.loss_temporal(_t(out, dev), _t(tgt4, dev), n, W, H, -1.0, lt, dl, ws)
     net.close()
+
+
+def test_recurrent_backward_matches_oracle(dev):
+    """Recurrent form: the training forward reads a fed-back O_d per batch
+    entry, and the gradient of every layer, the first conv's fed-back
+    channels included, matches the oracle's backward of the BF16-emulated
+    forward (the 16 x 16 bound of the plain test)."""
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(8)
+    n, H, W = 2, 16, 16
+    theta = _theta(21, recurrent=True)
+    rgba, mask, depth = _frame(rng, n, H, W, density=0.3)
+    prev = rng.uniform(0, 1, (n, H, W, 3)).astype(np.float32)
+    dloss = rng.normal(0, 1.0, (n, H, W, 3)).astype(np.float32)
+    net = b.Net(theta)
+    ws = torch.empty(net.train_workspace_bytes(n, W, H), dtype=torch.uint8, device=dev)
+    out = torch.empty(n * H * W * 3, device=dev)
+    net.forward_train_recurrent(_t(rgba, dev), _t(mask, dev), _t(depth, dev), _t(prev, dev), n,
+                                W, H, out, ws)
+    g = torch.zeros(N.N_PARAMS_RECURRENT, device=dev)
+    net.backward(_t(dloss, dev), n, W, H, ws, grad_out=g)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    x = N.recurrent_input(_oracle_input(rgba, mask, depth, n, H, W),
+                          prev.astype(np.float64).transpose(0, 3, 1, 2))
+    th16 = _bf16_weights(theta)
+    want, _, cache = N.forward(th16, x, keep=True, act_round=bf16_round)
+    gw = N.backward(th16, cache, dloss.astype(np.float64).transpose(0, 3, 1, 2))
+    got = out.cpu().numpy().reshape(n, H, W, 3).transpose(0, 3, 1, 2)
+    assert np.abs(got - want).max() < 2e-2
+    off, worst = 0, 0.0
+    for name, ci, co, k in N.LAYERS_RECURRENT:
+        nw = co * ci * k * k + co
+        a, r = g[off:off + nw], gw[off:off + nw]
+        rel = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
+        print("%-4s grad rel L2 err %.4f" % (name, rel))
+        worst = max(worst, rel)
+        if name == "e0a":
+            fb = lambda v: v[:co * ci * 9].reshape(co, ci, 9)[:, 5:]
+            rel_fb = np.linalg.norm(fb(a) - fb(r)) / np.linalg.norm(fb(r))
+            print("e0a fed-back channels rel L2 err %.4f" % rel_fb)
+            assert rel_fb < 0.01
+        off += nw
+    assert worst < 0.01
+    net.close()
