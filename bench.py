@@ -11,7 +11,9 @@ the network weights come from paper_2209_09965_amd/weights/recon_temporal.npy
 (trained by python -m paper_2209_09965_amd.train, then fine-tuned on
 consecutive-frame pairs with the temporal loss, --temporal 1.0 --init
 recon.npy) and are calibrated for FP8 on one frame of the workload before the
-timed region.
+timed region.  With weights of the recurrent form (--weights
+.../recon_recurrent.npy) every frame's reconstruction reads the previous
+frame's direct prediction (fv_reconstruct_recurrent).
 
 Timing: `value` is ms per foveated frame with the frames run one after the
 other on one HIP stream; the per-stage times come from HIP events recorded on
@@ -34,6 +36,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ms/frame foveated+recon vs dense march @1080p at PSNR>=30dB; ray-samples/s"
 HBM_PEAK_GBS = 8000.0
+REC_LEAD = 4  # frames a recurrent network runs before the measured sequence
 
 
 def parse():
@@ -256,9 +259,32 @@ def main():
             rws=torch.empty(net.workspace_bytes(V, W, H, args.precision), dtype=torch.uint8,
                             device=dev),
             dframe=torch.zeros(total * 4, dtype=torch.float32, device=dev),
-            ddepth=torch.zeros(total, dtype=torch.float32, device=dev))
+            ddepth=torch.zeros(total, dtype=torch.float32, device=dev),
+            od=torch.zeros(total * 3, dtype=torch.float32, device=dev))
 
     bufs = [buffers(), buffers()]
+    # recurrent network (Sec. 3.2.4): each frame reads the previous frame's
+    # O_d.  state["prev"] is the buffer set holding it (None: a sequence
+    # starts); a frame on the other stream first waits for that
+    # reconstruction, so the next frame's sample map and march still overlap it
+    state = {"prev": None}
+    recon_done = [torch.cuda.Event(), torch.cuda.Event()]
+
+    def reconstruct(j, st):
+        bf = bufs[j]
+        if not net.recurrent:
+            net.reconstruct(bf["frame"], bf["mask"], bf["fdepth"], V, W, H, bf["out_rgb"],
+                            precision=args.precision, workspace=bf["rws"], stream=st)
+            return
+        p = state["prev"]
+        if p is not None and p != j:
+            st.wait_event(recon_done[p])
+        net.reconstruct_recurrent(bf["frame"], bf["mask"], bf["fdepth"],
+                                  None if p is None else bufs[p]["od"], V, W, H, bf["out_rgb"],
+                                  bf["od"], precision=args.precision, workspace=bf["rws"],
+                                  stream=st)
+        recon_done[j].record(st)
+        state["prev"] = j
     scount = torch.zeros(1, dtype=torch.int64, device=dev)
     dcount = torch.zeros(1, dtype=torch.int64, device=dev)
     cam_list = [cams_for(k) for k in range(args.warmup + args.steps)]
@@ -290,8 +316,7 @@ def main():
                           workspace=bf["sws"], stream=st)
         if ev:
             ev[2].record(st)
-        net.reconstruct(bf["frame"], bf["mask"], bf["fdepth"], V, W, H, bf["out_rgb"],
-                        precision=args.precision, workspace=bf["rws"], stream=st)
+        reconstruct(j, st)
         if ev:
             ev[3].record(st)
 
@@ -303,8 +328,15 @@ def main():
                       stream=streams[0])
     if args.precision == "fp8":
         cws = torch.empty(net.workspace_bytes(V, W, H, "bf16"), dtype=torch.uint8, device=dev)
-        net.calibrate(b0["frame"], b0["mask"], b0["fdepth"], V, W, H, workspace=cws,
-                      stream=streams[0])
+        if net.recurrent:
+            # a fed-back O_d of the workload's magnitude: the frame's own BF16 O_d
+            net.reconstruct_recurrent(b0["frame"], b0["mask"], b0["fdepth"], None, V, W, H,
+                                      b0["out_rgb"], b0["od"], workspace=cws, stream=streams[0])
+            net.calibrate_recurrent(b0["frame"], b0["mask"], b0["fdepth"], b0["od"], V, W, H,
+                                    workspace=cws, stream=streams[0])
+        else:
+            net.calibrate(b0["frame"], b0["mask"], b0["fdepth"], V, W, H, workspace=cws,
+                          stream=streams[0])
         del cws
 
     def dense(k, j=0, ev=None):
@@ -367,8 +399,15 @@ def main():
     # run, foveated output against the dense march (untimed)
     nt = min(args.tpsnr_frames, args.warmup + args.steps)
     seq_f, seq_d = [], []
-    for k in range(args.warmup + args.steps - nt, args.warmup + args.steps):
+    # a recurrent network's state starts over REC_LEAD frames before the
+    # measured frames (the paper likewise discounts a sequence's first frames)
+    lead = REC_LEAD if net.recurrent else 0
+    k0 = max(0, args.warmup + args.steps - nt - lead)
+    state["prev"] = None
+    for k in range(k0, args.warmup + args.steps):
         foveated(k, 0)
+        if k < args.warmup + args.steps - nt:
+            continue
         dense(k, 0)
         seq_f.append(bufs[0]["out_rgb"].view(-1, 3).clamp(0, 1).clone())
         seq_d.append(bufs[0]["dframe"].view(-1, 4)[:, :3].clamp(0, 1).clone())
@@ -412,7 +451,9 @@ def main():
                                else "none"),
                    "sample_noise": ("seeded hash" if args.noise == "hash"
                                     else "64 blue-noise tiles of 64x64, one per frame"),
-                   "reconstruction": "U-Net 32/48/64/96 + 5x5 KPN, %s" % args.precision},
+                   "reconstruction": "U-Net 32/48/64/96 + 5x5 KPN%s, %s" %
+                                     (", recurrent O_d feedback" if net.recurrent else "",
+                                      args.precision)},
         "dense_ms_per_frame": round(dense_ms, 4),
         "speedup_vs_dense": round(dense_ms / fov_ms, 3),
         "pipelined_ms_per_frame": round(fov_pipe_ms, 4),
@@ -500,6 +541,8 @@ def cpu_baseline(vol, tf, cams, fp, W, H, V, mp, n_rays, theta, crop, fov_out, g
     sparse_rgba[idx] = dense["rgba"][idx]
     x = oracle.pack_input(sparse_rgba, m.reshape(-1), dense["depth"] * m.reshape(-1))
     x = x.reshape(V, H, W, 5).transpose(0, 3, 1, 2)
+    if theta.size == N.N_PARAMS_RECURRENT:
+        x = N.recurrent_input(x)  # the fed-back O_d: same arithmetic whatever its value
     y0, x0 = (H - crop) // 2 // 8 * 8, (W - crop) // 2 // 8 * 8
     t0 = time.perf_counter()
     N.forward(theta.astype(np.float64), np.ascontiguousarray(x[:1, :, y0:y0 + crop, x0:x0 + crop]))

@@ -335,8 +335,11 @@ fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba,
  * the first conv (e0a) reads 8 channels, the 5 above followed by the
  * previous frame's direct prediction O_d (r, g, b, FP32, unmasked), so its
  * weight is [32][8][3][3] and the vector has 32 * 3 * 9 = 864 more entries.
- * The first frame of a sequence is run with a zero O_d.  The recurrent
- * decoder hidden states of the paper's network are not part of this form.
+ * The first frame of a sequence is run with a zero O_d.  Under FP8 this
+ * form computes its first conv in BF16 (the fed-back O_d is a dense image;
+ * E4M3 would round it by up to 6 %); its output and every later layer are
+ * FP8 as in the plain form.  The recurrent decoder hidden states of the
+ * paper's network are not part of this form.
  * fv_net_create tells the two forms apart by n_params. */
 #define FV_NET_PARAMS_RECURRENT 480924
 
@@ -407,8 +410,8 @@ fv_status fv_net_calibrate(fv_net* n, const float* frame_rgba, const uint8_t* ma
                            const float* frame_depth, int views, int width, int height,
                            void* workspace, size_t ws_bytes, void* stream);
 /* The same with the fed-back O_d of the recurrent form in the calibration
- * pass (prev_direct as in fv_reconstruct_recurrent), so the input tensor's
- * scale covers it. */
+ * pass (prev_direct as in fv_reconstruct_recurrent, NULL for zeros), so the
+ * activation scales reflect the fed-back input. */
 fv_status fv_net_calibrate_recurrent(fv_net* n, const float* frame_rgba, const uint8_t* mask,
                                      const float* frame_depth, const float* prev_direct,
                                      int views, int width, int height, void* workspace,

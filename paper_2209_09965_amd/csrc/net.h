@@ -120,4 +120,5 @@ struct fv_net {
   float act_scale[fv::net::kNumTensors];  // FP8 per-tensor activation scales
   int fp8_ready;
   int recurrent;  // 1: the first conv reads the previous frame's O_d
+  float* mix0_ab;  // [2 x 32] scale / bias of the BF16 first layer under FP8
 };

@@ -386,7 +386,9 @@ template <class E, int NB, int R>
 void conv_launch(const ConvArgs& a, hipStream_t s) {
   static bool attr_set = false;
   const size_t lds = conv_lds_bytes<E, R>(a.cip, a.c0, a.up0, a.kc, NB, a.co, a.b_lds) +
-                     (a.fuse0 ? fuse0_lds_bytes<E, R>(a.f_kc) : 0);
+                     (!a.fuse0 ? 0
+                      : a.f_mixed ? fuse0_lds_bytes<BF16, R>(a.f_kc)
+                                  : fuse0_lds_bytes<E, R>(a.f_kc));
   if (!attr_set) {
     hipFuncSetAttribute((const void*)k_conv3x3<E, NB, R>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -570,11 +572,18 @@ fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const floa
       a.f_mask = mask;
       a.f_depth = depth;
       a.f_prev = prev;
-      a.f_inv = in_inv;
-      a.f_wsw = (const uint8_t*)(fp8 ? net->w_fp8[0] : net->w_bf16[0]);
-      a.f_kc = fp8 ? kchunks128_of(L0.ci) : kchunks_of(L0.ci);
-      a.f_alpha = fp8 ? net->alpha_fp8[0] : nullptr;
-      a.f_bias = fp8 ? net->bias_fp8[0] : net->master + param_offset(0) + (int64_t)L0.co * L0.ci * 9;
+      // the recurrent form runs its first layer in BF16 under FP8: its
+      // fed-back O_d is a dense image, which E4M3 would round by up to 6 %
+      const bool mixed = fp8 && net->recurrent;
+      const bool f8 = fp8 && !mixed;
+      a.f_mixed = mixed;
+      a.f_inv = f8 ? in_inv : 1.0f;
+      a.f_wsw = (const uint8_t*)(f8 ? net->w_fp8[0] : net->w_bf16[0]);
+      a.f_kc = f8 ? kchunks128_of(L0.ci) : kchunks_of(L0.ci);
+      a.f_alpha = f8 ? net->alpha_fp8[0] : mixed ? net->mix0_ab : nullptr;
+      a.f_bias = f8 ? net->bias_fp8[0]
+                 : mixed ? net->mix0_ab + L0.co
+                         : net->master + param_offset(0) + (int64_t)L0.co * L0.ci * 9;
     }
     // the encoder's second conv of levels 0-2 also writes the pooled input
     // of the next level
@@ -659,6 +668,20 @@ fv_status build_fp8(fv_net* n, hipStream_t s) {
                                 hipMemcpyHostToDevice), "fp8: bias");
     if (st != FV_OK) return st;
   }
+  {
+    // BF16 first layer of the recurrent form under FP8: FP32 accumulators
+    // times 1 / (output scale), bias / (output scale)
+    const LayerDesc& L0 = kLayers[0];
+    const float s_out = n->act_scale[T_E0A];
+    std::vector<float> ab(2 * L0.co);
+    for (int co = 0; co < L0.co; ++co) {
+      ab[co] = 1.0f / s_out;
+      ab[L0.co + co] = host[param_offset(0) + (int64_t)L0.co * L0.ci * 9 + co] / s_out;
+    }
+    st = hip_status(hipMemcpy(n->mix0_ab, ab.data(), ab.size() * sizeof(float),
+                              hipMemcpyHostToDevice), "fp8: first-layer scales");
+    if (st != FV_OK) return st;
+  }
   // heads on FP8 decoder outputs: the tensor scale folded into the weights
   k_swizzle_heads<<<4, 256, 0, s>>>(n->master + param_offset(14), n->master + param_offset(15),
                                     (__bf16*)n->w_heads_fp8, n->act_scale[T_D0B]);
@@ -714,7 +737,8 @@ fv_status fv_net_create(const float* host_params, size_t n_params, fv_net** out)
   bool ok = hipMalloc(&n->master, pb) == hipSuccess && hipMalloc(&n->adam_m, pb) == hipSuccess &&
             hipMalloc(&n->w_heads, 2 * 512 * 2) == hipSuccess &&
             hipMalloc(&n->w_heads_fp8, 2 * 512 * 2) == hipSuccess &&
-            hipMalloc(&n->adam_v, pb) == hipSuccess && hipMalloc(&n->grad, pb) == hipSuccess;
+            hipMalloc(&n->adam_v, pb) == hipSuccess && hipMalloc(&n->grad, pb) == hipSuccess &&
+            hipMalloc(&n->mix0_ab, 2 * kLayers[0].co * sizeof(float)) == hipSuccess;
   for (int l = 0; ok && l < kNumConv; ++l) {
     const size_t e = swizzled_elems(kLayers[l].c0 + kLayers[l].c1, kLayers[l].co);
     const size_t et = swizzled_elems(kLayers[l].co, kLayers[l].c0 + kLayers[l].c1);
@@ -752,6 +776,7 @@ fv_status fv_net_destroy(fv_net* n) {
   (void)hipFree(n->grad);
   (void)hipFree(n->w_heads);
   (void)hipFree(n->w_heads_fp8);
+  (void)hipFree(n->mix0_ab);
   for (int l = 0; l < kNumConv; ++l) {
     (void)hipFree(n->w_bf16[l]);
     (void)hipFree(n->w_bf16t[l]);

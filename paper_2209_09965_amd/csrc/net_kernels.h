@@ -260,6 +260,11 @@ struct ConvArgs {
   int f_kc;
   const float* f_alpha;  // or null (= 1)
   const float* f_bias;
+  // FP8 conv with a BF16 first layer (the recurrent form, whose fed-back O_d
+  // is a dense image): the packed input, the first layer's weight fragments
+  // (f_wsw, f_kc) and its MFMA are BF16; its output is stored in the patch in
+  // FP8 with f_alpha / f_bias folding the output scale
+  int f_mixed;
 };
 
 template <class E>
@@ -347,7 +352,7 @@ __host__ __device__ inline size_t fuse0_lds_bytes(int f_kc) {
 // it.  Also stages this conv's K-chunk table, scale/bias and weights (the
 // regular fill does that otherwise) and ends with every LDS region written
 // (the caller synchronises before its K loop).
-template <class E, int R>
+template <class E, class F0, int R>
 __device__ __forceinline__ void fuse0_fill(const ConvArgs& a, uint8_t* smem, int S, int* ktab,
                                         float* s_ab, uint8_t* wsm, int b, int y0, int x0) {
   constexpr int PR = 4 * R + 2, PC = 18;       // this conv's patch
@@ -359,8 +364,8 @@ __device__ __forceinline__ void fuse0_fill(const ConvArgs& a, uint8_t* smem, int
   const int col = lane & 15, grp = lane >> 4;
   const int cpad = (a.co + 3) & ~3;
   uint8_t* in = smem + conv_lds_bytes<E, R>(a.cip, a.c0, 0, a.kc, 2, a.co, 1);
-  int* ktab0 = (int*)(in + (size_t)IR * IC * 8 * E::kBytes);
-  float* s_ab0 = (float*)(ktab0 + 4 * E::kSub * a.f_kc);
+  int* ktab0 = (int*)(in + (size_t)IR * IC * 8 * F0::kBytes);
+  float* s_ab0 = (float*)(ktab0 + 4 * F0::kSub * a.f_kc);
   uint8_t* wsm0 = (uint8_t*)(s_ab0 + 64);
   // 1. loads: packed-input pixels (at most 2 per thread), both layers' weights
   // and scale/bias
@@ -390,7 +395,7 @@ __device__ __forceinline__ void fuse0_fill(const ConvArgs& a, uint8_t* smem, int
     }
   }
   const int n16 = a.kc * 2 * 64 * E::kFragBytes / 16;
-  const int n16f = a.f_kc * 2 * 64 * E::kFragBytes / 16;
+  const int n16f = a.f_kc * 2 * 64 * F0::kFragBytes / 16;
   const __amdgpu_buffer_rsrc_t rw = make_rsrc(a.wsw, (uint32_t)n16 * 16);
   const __amdgpu_buffer_rsrc_t rw0 = make_rsrc(a.f_wsw, (uint32_t)n16f * 16);
   for (int base = tid; base < n16 + n16f; base += 256 * 4) {
@@ -431,10 +436,10 @@ __device__ __forceinline__ void fuse0_fill(const ConvArgs& a, uint8_t* smem, int
     const int ky = tap / 3, kx = tap - 3 * ky;
     ktab[e] = tap < 9 ? ((ky * PC + kx) * S + ch) * E::kBytes : 0;
   }
-  for (int e = tid; e < 4 * E::kSub * a.f_kc; e += 256) {
+  for (int e = tid; e < 4 * F0::kSub * a.f_kc; e += 256) {
     const int tap = e;  // 8 input channels: one tap per 8 K positions
     const int ky = tap / 3, kx = tap - 3 * ky;
-    ktab0[e] = tap < 9 ? (ky * IC + kx) * 8 * E::kBytes : 0;
+    ktab0[e] = tap < 9 ? (ky * IC + kx) * 8 * F0::kBytes : 0;
   }
   // 2. packed input -> LDS (the k_pack arithmetic: values times f_inv)
 #pragma unroll
@@ -454,7 +459,7 @@ __device__ __forceinline__ void fuse0_fill(const ConvArgs& a, uint8_t* smem, int
     v[7] = px_p[u][2];
 #pragma unroll
     for (int k = 0; k < 8; ++k) v[k] *= a.f_inv;
-    E::store8(in + (size_t)i * 8 * E::kBytes, v);
+    F0::store8(in + (size_t)i * 8 * F0::kBytes, v);
   }
   __syncthreads();
   // 3. the first conv on the patch pixels, 16 consecutive patch pixels per
@@ -463,19 +468,19 @@ __device__ __forceinline__ void fuse0_fill(const ConvArgs& a, uint8_t* smem, int
     const int p = blk * 16 + col;
     const int pc = p < PR * PC ? p : 0;
     const int r = pc / PC, c = pc - r * PC;
-    const uint8_t* pin = in + (size_t)(r * IC + c) * 8 * E::kBytes;
+    const uint8_t* pin = in + (size_t)(r * IC + c) * 8 * F0::kBytes;
     f32x4_t acc[2] = {f32x4_t{0.f, 0.f, 0.f, 0.f}, f32x4_t{0.f, 0.f, 0.f, 0.f}};
     for (int ch = 0; ch < a.f_kc; ++ch) {
-      typename E::Frag af, bf[2];
+      typename F0::Frag af, bf[2];
 #pragma unroll
       for (int nb = 0; nb < 2; ++nb)
-        bf[nb] = E::frag(wsm0 + lane * E::kFragBytes + (ch * 2 + nb) * 64 * E::kFragBytes);
-      if constexpr (E::kSub == 1)
-        af = E::frag(pin + ktab0[4 * ch + grp]);
+        bf[nb] = F0::frag(wsm0 + lane * F0::kFragBytes + (ch * 2 + nb) * 64 * F0::kFragBytes);
+      if constexpr (F0::kSub == 1)
+        af = F0::frag(pin + ktab0[4 * ch + grp]);
       else
-        af = E::frag4(pin, ((const int4*)ktab0)[4 * ch + grp]);
+        af = F0::frag4(pin, ((const int4*)ktab0)[4 * ch + grp]);
 #pragma unroll
-      for (int nb = 0; nb < 2; ++nb) acc[nb] = E::mma(bf[nb], af, acc[nb]);
+      for (int nb = 0; nb < 2; ++nb) acc[nb] = F0::mma(bf[nb], af, acc[nb]);
     }
     const int y = y0 - 1 + r, x = x0 - 1 + c;
     const bool inside = p < PR * PC && y >= 0 && y < a.h && x >= 0 && x < a.w;
@@ -587,7 +592,16 @@ __global__ void __launch_bounds__(256)
   bool fused = false;
   if constexpr (NB == 2) fused = a.fuse0;
   if (fused) {
-    if constexpr (NB == 2) fuse0_fill<E, R>(a, smem, S, ktab, s_ab, wsm, b, y0, x0);
+    if constexpr (NB == 2) {
+      if constexpr (E::kBytes == 1) {
+        if (a.f_mixed)
+          fuse0_fill<E, BF16, R>(a, smem, S, ktab, s_ab, wsm, b, y0, x0);
+        else
+          fuse0_fill<E, E, R>(a, smem, S, ktab, s_ab, wsm, b, y0, x0);
+      } else {
+        fuse0_fill<E, E, R>(a, smem, S, ktab, s_ab, wsm, b, y0, x0);
+      }
+    }
   } else {
   // 1. every global load up front: patch items, weight fragments, scale/bias
   Item pf[kPF];

@@ -18,6 +18,14 @@ With --temporal W the pairs come as consecutive frames (the camera turned by
 (fv_net_loss_temporal, Sec. 3.3.2) to the spatial loss; validation then also
 reports the temporal PSNR of the pairs.  --init starts from saved weights.
 
+--seq-len L renders L consecutive frames per view (the camera turned by 3
+degrees per frame) and draws each batch pair from a random position in its
+sequence.  --recurrent trains the recurrent form (Sec. 3.2.4): every frame
+reads the previous frame's direct prediction O_d, computed by BF16 inference
+passes along the sequence with the current weights (zero before the first
+frame); the feedback is an input, so gradients do not flow through it.  A
+plain --init vector is widened with zero weights on the fed-back channels.
+
 Usage: python -m paper_2209_09965_amd.train --epochs 30 --out weights.npy
 """
 import argparse
@@ -40,14 +48,13 @@ from paper_2209_09965_amd import binding as b  # noqa: E402
 W = H = 512
 
 
-def render_pairs(dev, vol_specs, views, seed, log=print, consecutive=False):
+def render_pairs(dev, vol_specs, views, seed, log=print, per_view=1):
     """vol_specs: list of (kind, seed, n).  Returns dict of device tensors:
     rgba [N, H*W*4] f32, depth [N, H*W] f32, mask [N, H*W] u8, plus the volume
-    index of each pair.  consecutive: every view is two frames, entries 2j and
-    2j + 1, the second seen after a 3 degree turn of the camera about the
+    index of each pair.  per_view > 1: every view is that many consecutive
+    frames, each seen after a further 3 degree turn of the camera about the
     volume, with the sample map of the next frame."""
     rng = np.random.default_rng(seed)
-    per_view = 2 if consecutive else 1
     n_pairs = len(vol_specs) * views * per_view
     rgba = torch.empty((n_pairs, H * W * 4), dtype=torch.float32, device=dev)
     depth = torch.empty((n_pairs, H * W), dtype=torch.float32, device=dev)
@@ -77,7 +84,7 @@ def render_pairs(dev, vol_specs, views, seed, log=print, consecutive=False):
             fy = float(rng.uniform(H * 0.25, H * 0.75))
             mseed = int(rng.integers(1 << 31))
             for f in range(per_view):
-                c = cam if f == 0 else turn_camera(cam, 3.0)
+                c = cam if f == 0 else turn_camera(cam, 3.0 * f)
                 b.raymarch_dense(volh, tf_t, [c], W, H, mp, rgba[k], depth[k])
                 fp = synthetic.fovea_params(W, H, focus=(fx, fy), seed=mseed, frame=k)
                 b.fovea_mask(fp, W, H, 1, ray_idx, count, mask=mask[k])
@@ -101,15 +108,25 @@ def turn_camera(cam, deg):
     return dict(cam, eye=eye)
 
 
+def widen_recurrent(theta):
+    """Plain parameters -> the recurrent form with zero weights on the three
+    fed-back channels of the first conv ([32, 5, 3, 3] -> [32, 8, 3, 3])."""
+    w = theta[:32 * 5 * 9].reshape(32, 5, 9)
+    w8 = np.concatenate([w, np.zeros((32, 3, 9), theta.dtype)], axis=1).reshape(-1)
+    return np.concatenate([w8, theta[32 * 5 * 9:]]).astype(np.float32)
+
+
 def psnr_t(x, ref):
     mse = torch.mean((x.clamp(0, 1) - ref.clamp(0, 1)) ** 2).item()
     return float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
 
 
-def evaluate(net, data, idx, dev, precision="bf16", temporal=False):
+def evaluate(net, data, idx, dev, precision="bf16", temporal=False, seq_len=2):
     """PSNR of the hybrid output, the direct head and the raw sparse frame vs the
-    dense frame, averaged over the pairs idx; with temporal (idx = first frames
-    of consecutive pairs) also the temporal PSNR of each pair, averaged."""
+    dense frame, averaged over the frames of idx; with temporal (idx = first
+    frames of sequences of seq_len consecutive frames) also the temporal PSNR
+    of each consecutive pair, averaged.  A recurrent network runs each
+    sequence in order, every frame reading the previous frame's O_d."""
     out = torch.empty(H * W * 3, device=dev)
     od = torch.empty(H * W * 3, device=dev)
     ws = torch.empty(net.workspace_bytes(1, W, H, precision), dtype=torch.uint8, device=dev)
@@ -118,10 +135,16 @@ def evaluate(net, data, idx, dev, precision="bf16", temporal=False):
         res["tpsnr"] = []
     for i in idx:
         outs = []
-        for j in ((i, i + 1) if temporal else (i,)):
+        for t, j in enumerate(range(i, i + seq_len) if temporal else (i,)):
             fr = data["rgba"][j]
-            net.reconstruct(fr, data["mask"][j], data["depth"][j], 1, W, H, out, od,
-                            precision=precision, workspace=ws)
+            if net.recurrent:
+                # O_d is written over the previous frame's, which it reads first
+                net.reconstruct_recurrent(fr, data["mask"][j], data["depth"][j],
+                                          od if t > 0 else None, 1, W, H, out, od,
+                                          precision=precision, workspace=ws)
+            else:
+                net.reconstruct(fr, data["mask"][j], data["depth"][j], 1, W, H, out, od,
+                                precision=precision, workspace=ws)
             ref = fr.view(-1, 4)[:, :3]
             sparse = ref * data["mask"][j].view(-1, 1).float()
             res["hybrid"].append(psnr_t(out.view(-1, 3), ref))
@@ -129,9 +152,9 @@ def evaluate(net, data, idx, dev, precision="bf16", temporal=False):
             res["sparse"].append(psnr_t(sparse, ref))
             outs.append((out.view(-1, 3).clamp(0, 1).clone(), ref.clamp(0, 1)))
         if temporal:
-            (oa, ra), (ob, rb) = outs
-            mse = torch.mean(((ob - oa) - (rb - ra)) ** 2).item()
-            res["tpsnr"].append(float("inf") if mse == 0 else 10 * math.log10(1.0 / mse))
+            for (oa, ra), (ob, rb) in zip(outs[:-1], outs[1:]):
+                mse = torch.mean(((ob - oa) - (rb - ra)) ** 2).item()
+                res["tpsnr"].append(float("inf") if mse == 0 else 10 * math.log10(1.0 / mse))
     return {k: float(np.mean(v)) for k, v in res.items()}
 
 
@@ -153,6 +176,10 @@ def main():
                     help="train on consecutive-frame pairs with this weight on the temporal "
                          "loss (0 = pairs without the term; < 0 = single frames)")
     ap.add_argument("--init", default=None, help="start from these saved parameters")
+    ap.add_argument("--seq-len", type=int, default=2,
+                    help="consecutive frames per view with --temporal (>= 2)")
+    ap.add_argument("--recurrent", action="store_true",
+                    help="train the recurrent form (previous frame's O_d fed back)")
     args = ap.parse_args()
     logf = open(args.log, "a") if args.log else None
 
@@ -167,7 +194,10 @@ def main():
     specs = [("blob", 2000 + i, 64) for i in range(args.blob_volumes)]
     specs += [("noise", 4000 + i, 128) for i in range(args.noise_volumes)]
     temporal = args.temporal >= 0
-    data = render_pairs(dev, specs, args.views, args.seed, log, consecutive=temporal)
+    L = args.seq_len if temporal else 1
+    assert L >= 2 or not temporal
+    assert temporal or not args.recurrent, "--recurrent trains on sequences: give --temporal"
+    data = render_pairs(dev, specs, args.views, args.seed, log, per_view=L)
     nv = len(specs)
     # split by volume 10:1:1 (every 12-volume group: 10 train, 1 val, 1 test)
     role = np.array(["train" if (i % 12) < 10 else ("val" if i % 12 == 10 else "test")
@@ -178,13 +208,26 @@ def main():
     te = np.flatnonzero(pair_role == "test")
     log("pairs: %d train / %d val / %d test" % (tr.size, va.size, te.size))
 
-    net = b.Net(np.load(args.init) if args.init else synthetic.net_init(args.seed))
+    if args.init:
+        theta = np.load(args.init)
+        if args.recurrent and theta.size == b.Net.PARAMS:
+            theta = widen_recurrent(theta)
+    else:
+        theta = synthetic.net_init(args.seed, recurrent=args.recurrent)
+    net = b.Net(theta)
+    assert net.recurrent == args.recurrent
     B = args.batch
     if temporal:
         assert B % 2 == 0
-        tr = tr[tr % 2 == 0]  # pairs as units: their first frames
-        va = va[va % 2 == 0]
-        te = te[te % 2 == 0]
+        tr = tr[tr % L == 0]  # sequences as units: their first frames
+        va = va[va % L == 0]
+        te = te[te % L == 0]
+        per = B // 2
+        # O_d of the first L - 1 frames of the batch's sequences (recurrent)
+        ods = [torch.zeros(per * H * W * 3, device=dev) for _ in range(L - 1)]
+        iws = torch.empty(net.workspace_bytes(per, W, H, "bf16"), dtype=torch.uint8, device=dev)
+        iout = torch.empty(per * H * W * 3, device=dev)
+        prev = torch.zeros(B, H * W * 3, device=dev)
     lt = torch.zeros(1, device=dev)
     dl = torch.empty(B * H * W * 3, device=dev)
     out = torch.empty(B * H * W * 3, device=dev)
@@ -201,13 +244,41 @@ def main():
         per = B // 2 if temporal else B
         for s in range(0, perm.size - per + 1, per):
             first = perm[s:s + per]
-            rows = np.stack([first, first + 1], 1).reshape(-1) if temporal else first
+            if temporal:
+                # a consecutive pair from a random position of each sequence
+                j = rng.integers(0, L - 1, size=per)
+                rows = np.stack([first + j, first + j + 1], 1).reshape(-1)
+            else:
+                rows = first
             sel = torch.from_numpy(rows).to(dev)
             fr = data["rgba"].index_select(0, sel)
             m = data["mask"].index_select(0, sel)
             d = data["depth"].index_select(0, sel)
             if not temporal:
                 net.train_step(fr, m, d, fr, B, W, H, args.lr, loss3, ws)
+            elif args.recurrent:
+                # the fed-back O_d of every frame of the pairs, by inference
+                # along the sequences with the current weights
+                for t in range(L - 1):
+                    st = torch.from_numpy(first + t).to(dev)
+                    net.reconstruct_recurrent(
+                        data["rgba"].index_select(0, st).reshape(-1),
+                        data["mask"].index_select(0, st).reshape(-1),
+                        data["depth"].index_select(0, st).reshape(-1),
+                        ods[t - 1] if t > 0 else None, per, W, H, iout, ods[t],
+                        workspace=iws)
+                for q in range(per):
+                    jq = int(j[q])
+                    if jq == 0:
+                        prev[2 * q].zero_()
+                    else:
+                        prev[2 * q].copy_(ods[jq - 1].view(per, -1)[q])
+                    prev[2 * q + 1].copy_(ods[jq].view(per, -1)[q])
+                net.forward_train_recurrent(fr, m, d, prev, B, W, H, out, ws)
+                net.loss(out, fr, B, W, H, loss3, dl, ws)
+                net.loss_temporal(out, fr, B, W, H, args.temporal, lt, dl, ws)
+                net.backward(dl, B, W, H, ws)
+                net.adam(args.lr)
             else:
                 net.forward_train(fr, m, d, B, W, H, out, ws)
                 net.loss(out, fr, B, W, H, loss3, dl, ws)
@@ -219,7 +290,7 @@ def main():
             if nb % 25 == 0:
                 tot += float(loss3[0].item())
         torch.cuda.synchronize()
-        ev = evaluate(net, data, va[:40], dev, temporal=temporal)
+        ev = evaluate(net, data, va[:40], dev, temporal=temporal, seq_len=L)
         hist.append(dict(epoch=ep, loss=float(loss3[0].item()), val=ev,
                          s_per_epoch=time.time() - t0))
         log("epoch %d loss %.4f temporal %.4f val PSNR hybrid %.2f direct %.2f sparse %.2f "
@@ -232,16 +303,27 @@ def main():
     params = net.get_params()
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, params)
-    test_bf16 = evaluate(net, data, te, dev, temporal=temporal)
+    test_bf16 = evaluate(net, data, te, dev, temporal=temporal, seq_len=L)
     res = dict(test_bf16=test_bf16, steps=step, epochs=len(hist), history=hist,
                pairs=dict(train=int(tr.size), val=int(va.size), test=int(te.size)))
     try:
         # FP8 after calibration on training frames
         cal = torch.from_numpy(tr[:1]).to(dev)
         cw = torch.empty(net.workspace_bytes(1, W, H, "bf16"), dtype=torch.uint8, device=dev)
-        net.calibrate(data["rgba"][tr[0]], data["mask"][tr[0]], data["depth"][tr[0]], 1, W, H,
-                      workspace=cw)
-        res["test_fp8"] = evaluate(net, data, te, dev, precision="fp8", temporal=temporal)
+        if net.recurrent:
+            # the second frame of a training sequence with its fed-back O_d
+            k = int(tr[0])
+            pod = torch.empty(H * W * 3, device=dev)
+            pout = torch.empty(H * W * 3, device=dev)
+            net.reconstruct_recurrent(data["rgba"][k], data["mask"][k], data["depth"][k], None,
+                                      1, W, H, pout, pod, workspace=cw)
+            net.calibrate_recurrent(data["rgba"][k + 1], data["mask"][k + 1],
+                                    data["depth"][k + 1], pod, 1, W, H, workspace=cw)
+        else:
+            net.calibrate(data["rgba"][tr[0]], data["mask"][tr[0]], data["depth"][tr[0]], 1, W,
+                          H, workspace=cw)
+        res["test_fp8"] = evaluate(net, data, te, dev, precision="fp8", temporal=temporal,
+                                   seq_len=L)
     except Exception as e:  # noqa: BLE001
         res["test_fp8_error"] = str(e)
     log("RESULT " + json.dumps({k: v for k, v in res.items() if k != "history"}))

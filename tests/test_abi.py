@@ -149,3 +149,21 @@ def test_net_forms_host_checks():
                                             0, None) == -1
     assert L.fv_net_calibrate_recurrent(None, None, None, None, None, 1, 8, 8, None, 0,
                                         None) == -1
+
+
+def test_widen_recurrent_layout():
+    """The training driver's plain -> recurrent widening puts zero weights on
+    the first conv's fed-back channels and leaves every other parameter in
+    place (against the oracle's layout)."""
+    import synthetic
+    from oracle import net as N
+    from paper_2209_09965_amd.train import widen_recurrent
+    th = synthetic.net_init(3)
+    w = widen_recurrent(th)
+    assert w.size == N.N_PARAMS_RECURRENT
+    P, Q = N.unflatten(th.astype(np.float64)), N.unflatten(w.astype(np.float64))
+    assert np.array_equal(Q["e0a"][0][:, :5], P["e0a"][0]) and not Q["e0a"][0][:, 5:].any()
+    for name in P:
+        assert np.array_equal(P[name][1], Q[name][1])
+        if name != "e0a":
+            assert np.array_equal(P[name][0], Q[name][0])

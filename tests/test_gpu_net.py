@@ -319,6 +319,65 @@ def test_zero_feedback_weights_equal_plain_network(dev):
     rec.close()
 
 
+def test_recurrent_fp8_tiling_invariant(dev):
+    """FP8 recurrent form (its first layer in BF16 inside the fused FP8
+    conv): two views of 256 x 256 equal each view run alone, bit for bit."""
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(53)
+    H = W = 256
+    theta = _theta(22, recurrent=True)
+    rgba, mask, depth = _frame(rng, 2, H, W)
+    prev = rng.uniform(0, 1, 2 * H * W * 3).astype(np.float32)
+    net = b.Net(theta)
+    n1 = H * W
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).reshape(-1).to(dev)
+    net.calibrate_recurrent(T(rgba[:n1]), T(mask[:n1]), T(depth[:n1]), T(prev[:3 * n1]), 1, W, H)
+
+    def run(sl, views):
+        out = torch.full((views * n1 * 3,), float("nan"), device=dev)
+        od = torch.full((views * n1 * 3,), float("nan"), device=dev)
+        net.reconstruct_recurrent(T(rgba[sl]), T(mask[sl]), T(depth[sl]),
+                                  T(prev[sl.start * 3:sl.stop * 3]), views, W, H, out, od,
+                                  precision="fp8")
+        torch.cuda.synchronize()
+        return out.cpu().numpy(), od.cpu().numpy()
+
+    both, both_od = run(slice(0, 2 * n1), 2)
+    assert np.isfinite(both).all()
+    for v in range(2):
+        one, one_od = run(slice(v * n1, (v + 1) * n1), 1)
+        assert np.array_equal(both[v * n1 * 3:(v + 1) * n1 * 3], one)
+        assert np.array_equal(both_od[v * n1 * 3:(v + 1) * n1 * 3], one_od)
+    net.close()
+
+
+def test_recurrent_fp8_first_layer_is_bf16(dev):
+    """Under FP8 the recurrent form computes its first conv in BF16.  With zero
+    weights on the fed-back channels it is the plain network with a more
+    precise first layer: its error against the FP64 network may not exceed
+    the plain FP8 network's (the layers after it are the same FP8 code)."""
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(59)
+    views, H, W = 1, 64, 64
+    theta = _theta(23)
+    P = N.unflatten(theta.astype(np.float64))
+    w, bias = P["e0a"]
+    P["e0a"] = (np.concatenate([w, np.zeros((32, 3, 3, 3))], axis=1), bias)
+    th_r = N.flatten(P).astype(np.float32)
+    rgba, mask, depth = _frame(rng, views, H, W)
+    fr, m, d = (torch.from_numpy(a).reshape(-1).to(dev) for a in (rgba, mask, depth))
+    exact, _ = N.forward(theta.astype(np.float64), _oracle_input(rgba, mask, depth, views, H, W))
+    errs = []
+    for th in (theta, th_r):
+        net = b.Net(th)
+        net.calibrate(fr, m, d, views, W, H)
+        out, _ = _gpu(net, rgba, mask, depth, views, H, W, "fp8", dev)
+        errs.append(np.abs(out - exact).mean() / np.abs(exact).mean())
+        net.close()
+    print("fp8 relative mean error: plain %.4f, BF16 first layer %.4f" % tuple(errs), flush=True)
+    assert errs[1] <= 1.02 * errs[0]
+
+
 def test_recurrent_fp8_error_stated(dev):
     from paper_2209_09965_amd import binding as b
     rng = np.random.default_rng(47)
