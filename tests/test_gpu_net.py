@@ -400,3 +400,56 @@ def test_recurrent_fp8_error_stated(dev):
     print("recurrent fp8 relative mean error vs FP64 net: %.4f" % e8, flush=True)
     assert np.isfinite(got).all() and e8 < 0.25
     net.close()
+
+
+# The output at a pixel depends on the input within its receptive field:
+# +-2 px per level-0 conv, the 5x5 kernel, and the coarser levels' convs,
+# poolings and bilinear upsamplings scaled by 2, 4, 8, about +-67 px in all.
+# On a crop whose origin is a multiple of 8 (so the poolings align), the
+# outputs at least RF_MARGIN px inside every crop side that is not an image
+# edge equal those of the whole frame.
+RF_MARGIN = 80
+
+
+@pytest.mark.timeout(300)  # the FP64 oracle takes ~25 s per crop on the host
+@pytest.mark.parametrize("recurrent", [False, True])
+def test_full_hd_bf16_matches_oracle_on_crops(recurrent, dev):
+    """1920 x 1080 (the benchmark's frame, its tiling and ragged coarse
+    levels) in BF16: two 224 x 224 crops (the centre and the bottom-right
+    corner, where the ragged tiles are) against the BF16-emulated oracle, at
+    the single-frame tolerance."""
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(61 + recurrent)
+    H, W, C = 1080, 1920, 224
+    theta = _theta(24, recurrent=recurrent)
+    rgba, mask, depth = _frame(rng, 1, H, W, density=0.12)
+    prev = rng.uniform(0, 1, H * W * 3).astype(np.float32) if recurrent else None
+    net = b.Net(theta)
+    fr, m, d = (torch.from_numpy(a).reshape(-1).to(dev) for a in (rgba, mask, depth))
+    out = torch.full((H * W * 3,), float("nan"), device=dev)
+    if recurrent:
+        net.reconstruct_recurrent(fr, m, d, torch.from_numpy(prev).to(dev), 1, W, H, out)
+    else:
+        net.reconstruct(fr, m, d, 1, W, H, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(H, W, 3)
+    assert np.isfinite(got).all()
+    th16 = _bf16_weights(theta)
+    img = lambda a, ch: a.reshape(H, W, ch)
+    for y0, x0 in [(H // 2 // 8 * 8 - C // 2, W // 2 - C // 2), (H - C, W - C)]:
+        sl = (slice(y0, y0 + C), slice(x0, x0 + C))
+        x = _oracle_input(img(rgba, 4)[sl].reshape(-1, 4), img(mask, 1)[sl].reshape(-1),
+                          img(depth, 1)[sl].reshape(-1), 1, C, C)
+        if recurrent:
+            x = N.recurrent_input(x, img(prev, 3)[sl].transpose(2, 0, 1)[None].astype(np.float64))
+        want, _ = N.forward(th16, x, act_round=bf16_round)
+        ya = 0 if y0 == 0 else RF_MARGIN
+        yb = C if y0 + C == H else C - RF_MARGIN
+        xa = 0 if x0 == 0 else RF_MARGIN
+        xb = C if x0 + C == W else C - RF_MARGIN
+        g = got[y0 + ya:y0 + yb, x0 + xa:x0 + xb].transpose(2, 0, 1)
+        err = np.abs(g - want[0][:, ya:yb, xa:xb])
+        print("crop (%d, %d): %d px, max %.3g mean %.3g" % (y0, x0, g[0].size, err.max(),
+                                                           err.mean()), flush=True)
+        assert err.max() < 2e-2 and err.mean() < 5e-4
+    net.close()
