@@ -481,7 +481,8 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
                           void* stream);
 fv_status fv_net_adam(fv_net* n, float lr, float beta1, float beta2, float eps,
                       void* stream);
-/* forward_train + loss + backward + Adam (beta 0.9 / 0.999, eps 1e-8). */
+/* forward_train + loss + backward + Adam (beta 0.9 / 0.999, eps 1e-8).  A
+ * recurrent network is trained here with a zero fed-back O_d. */
 fv_status fv_train_step(fv_net* n, const float* frame_rgba, const uint8_t* mask,
                         const float* frame_depth, const float* target_rgba, int batch,
                         int width, int height, float lr, float* loss3, void* workspace,
