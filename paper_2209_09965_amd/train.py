@@ -48,13 +48,18 @@ from paper_2209_09965_amd import binding as b  # noqa: E402
 W = H = 512
 
 
-def render_pairs(dev, vol_specs, views, seed, log=print, per_view=1):
+def render_pairs(dev, vol_specs, views, seed, log=print, per_view=1, noise="hash"):
     """vol_specs: list of (kind, seed, n).  Returns dict of device tensors:
     rgba [N, H*W*4] f32, depth [N, H*W] f32, mask [N, H*W] u8, plus the volume
     index of each pair.  per_view > 1: every view is that many consecutive
     frames, each seen after a further 3 degree turn of the camera about the
-    volume, with the sample map of the next frame."""
+    volume, with the sample map of the next frame.  noise "blue": the sample
+    maps threshold a stack of 64 blue-noise tiles of 64 x 64 (frame k uses
+    tile k mod 64) instead of the seeded hash."""
     rng = np.random.default_rng(seed)
+    tiles_t = None
+    if noise == "blue":
+        tiles_t = torch.from_numpy(synthetic.noise_tiles(seed, size=64, count=64).view(np.int32)).to(dev)
     n_pairs = len(vol_specs) * views * per_view
     rgba = torch.empty((n_pairs, H * W * 4), dtype=torch.float32, device=dev)
     depth = torch.empty((n_pairs, H * W), dtype=torch.float32, device=dev)
@@ -87,7 +92,10 @@ def render_pairs(dev, vol_specs, views, seed, log=print, per_view=1):
                 c = cam if f == 0 else turn_camera(cam, 3.0 * f)
                 b.raymarch_dense(volh, tf_t, [c], W, H, mp, rgba[k], depth[k])
                 fp = synthetic.fovea_params(W, H, focus=(fx, fy), seed=mseed, frame=k)
-                b.fovea_mask(fp, W, H, 1, ray_idx, count, mask=mask[k])
+                if tiles_t is None:
+                    b.fovea_mask(fp, W, H, 1, ray_idx, count, mask=mask[k])
+                else:
+                    b.fovea_mask_tiles(fp, tiles_t, W, H, 1, ray_idx, count, mask=mask[k])
                 vol_of[k] = vi
                 k += 1
         volh.close()
@@ -180,6 +188,8 @@ def main():
                     help="consecutive frames per view with --temporal (>= 2)")
     ap.add_argument("--recurrent", action="store_true",
                     help="train the recurrent form (previous frame's O_d fed back)")
+    ap.add_argument("--noise", choices=["hash", "blue"], default="hash",
+                    help="sample-map noise: seeded hash or a 64-tile blue-noise stack")
     args = ap.parse_args()
     logf = open(args.log, "a") if args.log else None
 
@@ -197,7 +207,7 @@ def main():
     L = args.seq_len if temporal else 1
     assert L >= 2 or not temporal
     assert temporal or not args.recurrent, "--recurrent trains on sequences: give --temporal"
-    data = render_pairs(dev, specs, args.views, args.seed, log, per_view=L)
+    data = render_pairs(dev, specs, args.views, args.seed, log, per_view=L, noise=args.noise)
     nv = len(specs)
     # split by volume 10:1:1 (every 12-volume group: 10 train, 1 val, 1 test)
     role = np.array(["train" if (i % 12) < 10 else ("val" if i % 12 == 10 else "test")
