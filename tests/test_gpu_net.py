@@ -453,3 +453,52 @@ def test_full_hd_bf16_matches_oracle_on_crops(recurrent, dev):
                                                            err.mean()), flush=True)
         assert err.max() < 2e-2 and err.mean() < 5e-4
     net.close()
+
+
+@pytest.mark.timeout(300)  # the FP64 oracle takes ~25 s per crop on the host
+@pytest.mark.parametrize("weights", ["recon_temporal.npy", "recon_recurrent.npy"])
+def test_full_hd_fp8_trained_error_on_crops(weights, dev):
+    """The configuration the benchmark times: 1920 x 1080, FP8, the trained
+    weights (the benchmark's, and the recurrent form's with a fed-back O_d),
+    calibrated on the frame.  On two 224 x 224 crops (interiors as in the
+    BF16 test) the error against the FP64 network is stated and held to the
+    E4M3 bound of the random-weight FP8 test."""
+    import os
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(71)
+    H, W, C = 1080, 1920, 224
+    theta = np.load(os.path.join(os.path.dirname(b.__file__), "weights", weights))
+    rgba, mask, depth = _frame(rng, 1, H, W, density=0.12)
+    net = b.Net(theta)
+    rec = net.recurrent
+    prev = rng.uniform(0, 1, H * W * 3).astype(np.float32) if rec else None
+    fr, m, d = (torch.from_numpy(a).reshape(-1).to(dev) for a in (rgba, mask, depth))
+    out = torch.full((H * W * 3,), float("nan"), device=dev)
+    if rec:
+        pv = torch.from_numpy(prev).to(dev)
+        net.calibrate_recurrent(fr, m, d, pv, 1, W, H)
+        net.reconstruct_recurrent(fr, m, d, pv, 1, W, H, out, precision="fp8")
+    else:
+        net.calibrate(fr, m, d, 1, W, H)
+        net.reconstruct(fr, m, d, 1, W, H, out, precision="fp8")
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(H, W, 3)
+    assert np.isfinite(got).all()
+    img = lambda a, ch: a.reshape(H, W, ch)
+    errs = []
+    for y0, x0 in [(H // 2 // 8 * 8 - C // 2, W // 2 - C // 2), (H - C, W - C)]:
+        sl = (slice(y0, y0 + C), slice(x0, x0 + C))
+        x = _oracle_input(img(rgba, 4)[sl].reshape(-1, 4), img(mask, 1)[sl].reshape(-1),
+                          img(depth, 1)[sl].reshape(-1), 1, C, C)
+        if rec:
+            x = N.recurrent_input(x, img(prev, 3)[sl].transpose(2, 0, 1)[None].astype(np.float64))
+        exact, _ = N.forward(theta.astype(np.float64), x)
+        ya, yb = RF_MARGIN, C if y0 + C == H else C - RF_MARGIN
+        xa, xb = RF_MARGIN, C if x0 + C == W else C - RF_MARGIN
+        g = got[y0 + ya:y0 + yb, x0 + xa:x0 + xb].transpose(2, 0, 1)
+        e = exact[0][:, ya:yb, xa:xb]
+        errs.append(np.abs(g - e).mean() / np.abs(e).mean())
+        print("%s crop (%d, %d): FP8 relative mean error vs FP64 %.4f" % (weights, y0, x0,
+                                                                          errs[-1]), flush=True)
+    assert max(errs) < 0.25
+    net.close()
