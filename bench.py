@@ -394,6 +394,15 @@ def main():
     dref = dframe.view(-1, 4)[:, :3]
     mse = torch.mean((fov_out.clamp(0, 1) - dref.clamp(0, 1)) ** 2).item()
     psnr_dense = 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
+    # SSIM of the same pair (11x11 Gaussian window, sigma 1.5; the library's
+    # loss computes it on the GPU, loss3[1]), untimed
+    tws = torch.empty(net.train_workspace_bytes(V, W, H), dtype=torch.uint8, device=dev)
+    loss3 = torch.zeros(3, device=dev)
+    dls = torch.empty(V * W * H * 3, device=dev)
+    tgt = torch.cat([dref.clamp(0, 1), torch.ones_like(dref[:, :1])], 1).contiguous()
+    net.loss(fov_out.clamp(0, 1).contiguous(), tgt, V, W, H, loss3, dls, tws)
+    ssim_dense = float(loss3[1].item())
+    del tws, dls, tgt
     # temporal stability (Sec. 4, "Temporal Stability"): tPSNR, the PSNR of
     # the differences between consecutive frames, over the last frames of the
     # run, foveated output against the dense march (untimed)
@@ -467,6 +476,7 @@ def main():
                       "reconstruct": round(sum(recon_ms) / len(recon_ms), 4),
                       "raymarch_dense": round(dn_avg, 4)},
         "psnr_vs_gpu_dense_db": round(psnr_dense, 2),
+        "ssim_vs_gpu_dense": round(ssim_dense, 4),
         "quality_sequence": {"frames": nt, "mean_psnr_db": round(seq_psnr, 2),
                              "tpsnr_db": round(tpsnr, 2)},
         "net_mfma": {"precision": args.precision, "flop_per_px": 167968,
@@ -550,6 +560,8 @@ def cpu_baseline(vol, tf, cams, fp, W, H, V, mp, n_rays, theta, crop, fov_out, g
     per_frame_s = t_mask + t_march * idx.size / pick.size + t_net
     ref = dense["rgba"][:, :3]
     psnr = N.psnr(fov_out.reshape(-1, 3), ref)
+    to_nchw = lambda a: np.clip(a, 0, 1).reshape(V, H, W, 3).transpose(0, 3, 1, 2)
+    ssim = N.ssim(to_nchw(np.asarray(fov_out, np.float64)), to_nchw(ref))
     psnr_gpu_dense = N.psnr(gpu_dense[:, :3], ref)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
     return {"value": round(per_frame_s * 1e3, 1), "unit": "ms/frame", "cores": cores,
@@ -557,6 +569,7 @@ def cpu_baseline(vol, tf, cams, fp, W, H, V, mp, n_rays, theta, crop, fov_out, g
             "ray_samples_per_s": round(float(r["samples"].sum()) / t_march, 1),
             "dense_ms_per_frame": round(t_dense * 1e3, 1),
             "psnr_foveated_vs_oracle_dense_db": round(float(psnr), 2),
+            "ssim_foveated_vs_oracle_dense": round(float(ssim), 4),
             "psnr_gpu_dense_vs_oracle_dense_db": round(float(psnr_gpu_dense), 2),
             "sample": "one foveated frame: full sample map + compaction, the FP64 march of %d "
                       "of its %d sampled rays%s, and the FP64 network on a %dx%d crop scaled "
