@@ -167,3 +167,41 @@ def test_widen_recurrent_layout():
         assert np.array_equal(P[name][1], Q[name][1])
         if name != "e0a":
             assert np.array_equal(P[name][0], Q[name][0])
+
+
+def _prototypes():
+    txt = open(os.path.join(ROOT, "include", "fovol.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    out = {}
+    for m in re.finditer(r"\b(fv_status|int|size_t|const char\s*\*)\s+(fv_[a-z0-9_]+)\s*\(([^)]*)\)\s*;",
+                         txt):
+        args = [a.strip() for a in m.group(3).split(",") if a.strip() and a.strip() != "void"]
+        out[m.group(2)] = (m.group(1), args)
+    return out
+
+
+def test_binding_signatures_match_the_header():
+    """Every ctypes signature of the binding has the header prototype's arity
+    and, argument by argument, a matching type (pointer, int, unsigned,
+    size_t, float), so the marshalling cannot drift from the C ABI."""
+    from paper_2209_09965_amd import binding as b
+    protos = _prototypes()
+    assert set(protos) == set(b._SIGS), set(protos) ^ set(b._SIGS)
+
+    def ok(c, t):
+        if "*" in c:
+            return t in (ctypes.c_void_p, ctypes.c_char_p) or issubclass(t, ctypes._Pointer)
+        base = c.replace("const", "").split()[0]
+        want = {"float": ctypes.c_float, "uint32_t": ctypes.c_uint32, "size_t": ctypes.c_size_t,
+                "int": ctypes.c_int, "int32_t": ctypes.c_int32, "uint64_t": ctypes.c_uint64}
+        if base.startswith("fv_"):  # an enum of the header
+            return t is ctypes.c_int
+        return want.get(base) is t or (base == "int32_t" and t is ctypes.c_int)
+
+    for name, (res, args) in b._SIGS.items():
+        cres, cargs = protos[name]
+        assert len(args) == len(cargs), (name, len(args), len(cargs))
+        for i, (c, t) in enumerate(zip(cargs, args)):
+            assert ok(c, t), (name, i, c, t)
+        want_res = {"fv_status": ctypes.c_int, "int": ctypes.c_int, "size_t": ctypes.c_size_t}
+        assert (res is ctypes.c_char_p) if "char" in cres else (res is want_res[cres]), name
