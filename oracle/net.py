@@ -202,24 +202,32 @@ def kpn_apply_bwd(wk, od, dout):
 
 # ------------------------------------------------------------------ network
 
-def forward(theta, x, keep=False, act_round=None):
+def forward(theta, x, keep=False, act_round=None, observe=None):
     """Returns (out, O_d) and, with keep=True, the cache for backward().
 
     act_round, if given, is applied to every stored activation tensor (the
     input, each conv output, each pooled and each upsampled tensor), so a
     test can reproduce an implementation that stores activations at reduced
-    precision; the arithmetic itself stays FP64."""
+    precision; the arithmetic itself stays FP64.  observe(name, tensor), if
+    given, sees the input ("x") and every conv output (the layer's name)
+    before it is rounded."""
     P = unflatten(np.asarray(theta, np.float64))
     if x.shape[1] != P["e0a"][0].shape[1]:
         raise ValueError("input has %d channels, the network reads %d"
                          % (x.shape[1], P["e0a"][0].shape[1]))
-    rnd = act_round if act_round is not None else (lambda t: t)
-    x = rnd(x)
+    rnd0 = act_round if act_round is not None else (lambda t: t)
+
+    def rnd(t, name=None):
+        if observe is not None and name is not None:
+            observe(name, t)
+        return rnd0(t)
+
+    x = rnd(x, "x")
     c = {"x": x}
 
     def block(name_a, name_b, inp):
-        a = rnd(relu(conv2d(inp, *P[name_a])))
-        bb = rnd(relu(conv2d(a, *P[name_b])))
+        a = rnd(relu(conv2d(inp, *P[name_a])), name_a)
+        bb = rnd(relu(conv2d(a, *P[name_b])), name_b)
         c[name_a + "_in"], c[name_a], c[name_b] = inp, a, bb
         return bb
 
@@ -412,3 +420,157 @@ def adam(theta, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     vh = v / (1 - b2 ** step)
     return theta - lr * mh / (np.sqrt(vh) + eps), m, v
 
+
+
+# ------------------------------------------------ reduced-precision storage
+# The library stores activations in BF16 (training, BF16 inference) or FP8
+# E4M3 (inference), Sec. 3.4 "Model Precision & Optimization" (the paper
+# uses FP16 through TensorRT; the formats here are the library's).  These
+# functions emulate the storage formats from their definitions so that a
+# test can hold the GPU to the network it actually computes.
+
+def bf16_round(a):
+    """Rounds to bfloat16 (the upper 16 bits of an IEEE binary32, round to
+    nearest, ties to even), through binary32; returns float64."""
+    u = np.asarray(a, np.float32).view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+E4M3_MAX = 448.0
+
+
+def e4m3_round(a):
+    """Rounds to the OCP 8-bit E4M3 format (1 sign, 4 exponent bits with bias
+    7, 3 mantissa bits; no infinities; largest finite 448 = 1.75 * 2^8,
+    smallest normal 2^-6, subnormals in steps of 2^-9), round to nearest,
+    ties to even, saturating at +-448.  Returns float64 values on the grid."""
+    a = np.clip(np.asarray(a, np.float64), -E4M3_MAX, E4M3_MAX)
+    _, e = np.frexp(a)                     # |a| = m 2^e, 1/2 <= m < 1
+    q = np.exp2(np.maximum(e - 4, -9))     # the grid step: 3 mantissa bits, floor 2^-9
+    r = np.rint(a / q) * q                 # rint: ties to even
+    return np.clip(r, -E4M3_MAX, E4M3_MAX)
+
+
+def round_weights(theta, rnd):
+    """Every conv weight (3x3 layers and the two 1x1 heads) through rnd;
+    biases unchanged (the library keeps them in FP32)."""
+    th = np.asarray(theta, np.float64).copy()
+    off = 0
+    for _, ci, co, k in layers_of(th.size):
+        nw = co * ci * k * k
+        th[off:off + nw] = rnd(th[off:off + nw])
+        off += nw + co
+    return th
+
+
+# FP8 tensors that carry their own scale: the input and every conv output.
+# A pooled tensor keeps the scale of the tensor it pools and an upsampled
+# tensor the scale of its source.
+FP8_TENSORS = ["x"] + [name for name, _, _, k in LAYERS if k == 3]
+
+
+def calibrate_fp8(theta, x, storage_round=bf16_round):
+    """Per-tensor FP8 activation scales from one pass over the calibration
+    input x (the library's post-training quantisation): the pass runs with
+    conv weights and stored activations through storage_round (BF16, the
+    library's calibration pass), records the largest magnitude m_t of every
+    tensor as computed (before rounding) and returns
+    s_t = max(m_t, 1e-6) / 448."""
+    m = {}
+
+    def observe(name, t):
+        m[name] = max(m.get(name, 0.0), float(np.abs(t).max()))
+
+    forward(round_weights(theta, storage_round), x, act_round=storage_round, observe=observe)
+    return {k: max(v, 1e-6) / E4M3_MAX for k, v in m.items()}
+
+
+def fp8_weights(w, in_scale, rnd=e4m3_round):
+    """Quantised weights of a conv layer whose input channel c is stored with
+    scale in_scale[c]: the input scales are folded into the weights,
+    W'[o,c,t] = W[o,c,t] in_scale[c]; each output channel o gets the scale
+    omega_o = max_{c,t} |W'[o,c,t]| / 448 (1 for an all-zero channel); the
+    stored codes are Wq = E4M3(W' / omega_o).  Returns (Wq, omega)."""
+    w1 = w * np.asarray(in_scale, np.float64)[None, :, None, None]
+    mx = np.abs(w1).reshape(w1.shape[0], -1).max(axis=1)
+    om = np.where(mx > 0, mx / E4M3_MAX, 1.0)
+    return rnd(w1 / om[:, None, None, None]), om
+
+
+def forward_fp8(theta, x, scales, e4m3=e4m3_round, head_round=bf16_round,
+                first_bf16=None, bf16=bf16_round):
+    """The network as the library's FP8 inference computes it (Sec. 3.4):
+    every stored tensor t is an E4M3 code q with value q s_t (s_t from
+    calibrate_fp8).  Per 3x3 conv (weights from fp8_weights over the scales
+    of its input channels, output scale s_out):
+        acc_o = sum_{c,t} Wq[o,c,t] q_c(p + t)          (FP32 accumulation)
+        q_out = E4M3(min(max(acc_o omega_o / s_out + B_o / s_out, 0), 448))
+    i.e. ReLU and saturation at the largest E4M3 value.  A pooled tensor is
+    E4M3 of the mean of the four codes, an upsampled one E4M3 of the bilinear
+    blend of the codes (both keep their source's scale).  The heads read the
+    codes of the last decoder tensor with weights BF16(W s_d0b) and FP32 bias;
+    softmax and the 5x5 kernel application are exact.
+
+    The recurrent form (8 input channels) computes its first conv in BF16
+    (first_bf16 defaults to True for it): input and weights rounded to BF16,
+    q_out = E4M3(min(max(acc / s_out + B / s_out, 0), 448)).
+
+    With e4m3, head_round and bf16 all the identity this is the FP64 network
+    (forward()) exactly, whatever the scales.  Returns (out, O_d)."""
+    P = unflatten(np.asarray(theta, np.float64))
+    if x.shape[1] != P["e0a"][0].shape[1]:
+        raise ValueError("input has %d channels, the network reads %d"
+                         % (x.shape[1], P["e0a"][0].shape[1]))
+    if first_bf16 is None:
+        first_bf16 = x.shape[1] == 8
+
+    def store(v, s):
+        return e4m3(np.clip(v / s, -E4M3_MAX, E4M3_MAX))
+
+    def conv(name, srcs, relu_out=True):
+        """srcs: list of (codes, scale) concatenated along channels."""
+        w, b = P[name]
+        codes = np.concatenate([q for q, _ in srcs], axis=1)
+        in_scale = np.concatenate([np.full(q.shape[1], s) for q, s in srcs])
+        wq, om = fp8_weights(w, in_scale, e4m3)
+        s_out = scales[name]
+        acc = conv2d(codes, wq, np.zeros(w.shape[0]))
+        y = acc * (om / s_out)[None, :, None, None] + (b / s_out)[None, :, None, None]
+        return e4m3(np.clip(y, 0.0, E4M3_MAX))
+
+    if first_bf16:
+        w, b = P["e0a"]
+        acc = conv2d(bf16(x), bf16(w), np.zeros(w.shape[0]))
+        s_out = scales["e0a"]
+        q = e4m3(np.clip(acc / s_out + (b / s_out)[None, :, None, None], 0.0, E4M3_MAX))
+        e0a = (q, s_out)
+    else:
+        qx = (store(x, scales["x"]), scales["x"])
+        e0a = (conv("e0a", [qx]), scales["e0a"])
+
+    def sc(name, q):
+        return (q, scales[name])
+
+    e0b = sc("e0b", conv("e0b", [e0a]))
+    p0 = (e4m3(avgpool2(e0b[0])), e0b[1])
+    e1a = sc("e1a", conv("e1a", [p0]))
+    e1b = sc("e1b", conv("e1b", [e1a]))
+    p1 = (e4m3(avgpool2(e1b[0])), e1b[1])
+    e2a = sc("e2a", conv("e2a", [p1]))
+    e2b = sc("e2b", conv("e2b", [e2a]))
+    p2 = (e4m3(avgpool2(e2b[0])), e2b[1])
+    e3a = sc("e3a", conv("e3a", [p2]))
+    e3b = sc("e3b", conv("e3b", [e3a]))
+    d2a = sc("d2a", conv("d2a", [(e4m3(upsample2(e3b[0])), e3b[1]), e2b]))
+    d2b = sc("d2b", conv("d2b", [d2a]))
+    d1a = sc("d1a", conv("d1a", [(e4m3(upsample2(d2b[0])), d2b[1]), e1b]))
+    d1b = sc("d1b", conv("d1b", [d1a]))
+    d0a = sc("d0a", conv("d0a", [(e4m3(upsample2(d1b[0])), d1b[1]), e0b]))
+    d0b = sc("d0b", conv("d0b", [d0a]))
+    q, s = d0b
+    wd, bd = P["hd"]
+    wk, bk = P["hk"]
+    od = conv2d(q, head_round(wd * s), bd)
+    logits = conv2d(q, head_round(wk * s), bk)
+    return kpn_apply(softmax_c(logits), od), od

@@ -16,7 +16,10 @@ from tests.gpuhelp import f32, gpu_dense, hull_ok, oracle_mask, report
 pytestmark = pytest.mark.gpu
 
 TOL = 1e-5
-DEPTH_TOL = 1e-5  # depth is premultiplied by opacity, world units (<= ~3)
+# depth is premultiplied by opacity and measured in world units from the ray
+# origin: the colour bound of 1e-5 scaled by the largest distance a sample can
+# have here (eye at radius <= 2 plus the box's half diagonal, < 4)
+DEPTH_TOL = 4e-5
 
 
 def _tf_t(tf, dev):
@@ -30,7 +33,7 @@ def _check(gpu_rgba, gpu_depth, ora, label):
     assert ok.all(), (label, rep, np.argwhere(~ok)[:5])
     flagged = ora["flags"].astype(bool)
     d_err = np.abs(gpu_depth - ora["depth"])[~flagged]
-    assert d_err.size == 0 or d_err.max() <= DEPTH_TOL * 4, d_err.max()
+    assert d_err.size == 0 or d_err.max() <= DEPTH_TOL, d_err.max()
     # ambiguous early-termination decisions are rare (the opacity jump per step near
     # alpha_stop is ~1e-4..1e-3, so a 2e-6 window catches well under 1% of rays;
     # a sample of a hundred rays may still hold one or two)

@@ -327,3 +327,102 @@ def test_shadows_only_darken():
     np.testing.assert_array_equal(shad["rgba"][:, 3], plain["rgba"][:, 3])
     np.testing.assert_array_equal(shad["depth"], plain["depth"])
     np.testing.assert_array_equal(shad["samples"], plain["samples"])
+
+
+# ------------------------------------------------------------------ depth
+# The premultiplied depth D = sum_k T_k alpha_k t_k, with t_k the distance of
+# sample k from the ray's origin (world units), is pinned on the centre pixel
+# of the axial camera: the ray runs along -z from z = 2, enters the unit box
+# at t0 = 1.5 and every sample sits at t_k = t0 + h m_k (h = 1/n, m_k the
+# segment's midpoint in voxel lengths).  With a constant extinction sigma the
+# sums are geometric series, evaluated here in closed form.
+
+def _axial_depth_closed_form(n, sigma, step, K=None):
+    """D for the constant medium: full segments k < N - 1 of length `step`, the
+    last one of length L - (N - 1) step, the ray stopped after K samples."""
+    L = float(n)
+    N = math.ceil(L / step - 1e-12)
+    K = N if K is None else K
+    h, t0 = 1.0 / n, 1.5
+    r = math.exp(-sigma * step)
+    a = 1.0 - r
+    kf = min(K, N - 1)  # full segments composited
+    s0 = (1 - r ** kf) / (1 - r)
+    s1 = r * (1 - kf * r ** (kf - 1) + (kf - 1) * r ** kf) / (1 - r) ** 2
+    D = a * ((t0 + h * step / 2) * s0 + h * step * s1)
+    if K == N:  # the partial last segment
+        ll = L - (N - 1) * step
+        D += r ** (N - 1) * (1 - math.exp(-sigma * ll)) * (t0 + h * ((N - 1) * step + ll / 2))
+    return D
+
+
+@pytest.mark.parametrize("step", [0.5, 0.37])
+def test_depth_homogeneous_axial_closed_form(step):
+    """No early termination: every segment composited, the partial last one
+    (step 0.37: 43 full segments and one of 0.09 voxels) included."""
+    n = 16
+    vol = np.full((n, n, n), 0.5, np.float32)
+    tf = const_tf((0.3, 0.6, 0.9), 0.05)
+    mp = synthetic.march_params(alpha_stop=1.0, step_vox=step)
+    out = oracle.march(vol, tf, [AXIAL], 3, 3, mp, idx=np.array([4], np.uint32))
+    want = _axial_depth_closed_form(n, f32(0.05), f32(step))
+    assert out["samples"][0] == math.ceil(n / f32(step))
+    assert abs(out["depth"][0] - want) < 1e-12
+    # the depth is a weighted mean distance times the opacity: between the
+    # box entry and exit distances
+    A = out["rgba"][0, 3]
+    assert 1.5 * A < out["depth"][0] < 2.5 * A
+
+
+def test_depth_early_termination_closed_form():
+    """sigma l = 0.25: the ray stops after 19 samples (see the opacity pin);
+    D sums only those."""
+    n = 16
+    vol = np.full((n, n, n), 1.0, np.float32)
+    tf = const_tf((1.0, 0.5, 0.25), 0.5)
+    mp = synthetic.march_params(alpha_stop=0.99)
+    out = oracle.march(vol, tf, [AXIAL], 3, 3, mp, idx=np.array([4], np.uint32))
+    assert out["samples"][0] == 19
+    want = _axial_depth_closed_form(n, 0.5, 0.5, K=19)
+    assert abs(out["depth"][0] - want) < 1e-12
+    # a slip that measured t from the box entry would give D - t0 A
+    assert abs(out["depth"][0] - (want - 1.5 * out["rgba"][0, 3])) > 1.0
+
+
+def test_depth_single_opaque_voxel_plane():
+    """One plane of ones (z index 5) in an empty 16^3 volume, a TF with extinction
+    2 above v ~ 0.7 and 0 below.  Along the axis the field is the triangle
+    1 - |z - 5|, and the samples sit at quarter-voxel offsets from the voxel
+    planes, so exactly two of them see v = 0.75: z = 5.25 and then 4.75 (index
+    space; the ray runs from z = n - 1/2 down).  Each is at the world distance
+    t = 2 - (z - 7.5) h from the eye."""
+    n = 16
+    vol = np.zeros((n, n, n), np.float32)
+    vol[5] = 1.0
+    tf = np.zeros((256, 4), np.float32)
+    tf[:, :3] = 1.0
+    tf[int(0.7 * 255) + 1:, 3] = 2.0  # entries above v ~ 0.7
+    mp = synthetic.march_params(alpha_stop=1.0)
+    out = oracle.march(vol, tf, [AXIAL], 3, 3, mp, idx=np.array([4], np.uint32))
+    h = 1.0 / n
+    # the ray meets z index 5.25 first (it runs from z = n - 1/2 downwards)
+    a = 1 - math.exp(-f32(2.0) * 0.5)
+    t1 = 2.0 - (5.25 - 7.5) * h
+    t2 = 2.0 - (4.75 - 7.5) * h
+    want = a * t1 + (1 - a) * a * t2
+    assert abs(out["depth"][0] - want) < 1e-12
+    assert abs(out["rgba"][0, 3] - (1 - (1 - a) ** 2)) < 1e-12
+
+
+def test_pack_input_literal():
+    """Network input per pixel [M r, M g, M b, M, M depth / 2]: two pixels, the
+    first sampled, the second not (its colour and depth must not leak)."""
+    rgba = np.array([[0.1, 0.2, 0.3, 0.4], [0.5, 0.6, 0.7, 0.8]])
+    mask = np.array([1, 0], np.uint8)
+    depth = np.array([3.0, 5.0])
+    got = oracle.pack_input(rgba, mask, depth)
+    want = np.array([[0.1, 0.2, 0.3, 1.0, 1.5], [0.0, 0.0, 0.0, 0.0, 0.0]])
+    assert np.array_equal(got, want)
+    # any non-zero mask byte counts as sampled
+    got = oracle.pack_input(rgba[::-1], np.array([0, 7], np.uint8), depth[::-1])
+    assert np.array_equal(got, np.array([[0.0] * 5, [0.1, 0.2, 0.3, 1.0, 1.5]]))
