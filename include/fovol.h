@@ -322,9 +322,28 @@ fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba,
  *
  * Precision:
  *  FV_PREC_BF16  activations and weights BF16, MFMA with FP32 accumulation.
- *  FV_PREC_FP8   activations and weights FP8 E4M3 (OCP), FP32 accumulation;
- *                per-tensor activation scales from fv_net_calibrate are
- *                folded into per-output-channel weight scales.
+ *  FV_PREC_FP8   activations and weights FP8 E4M3 (OCP: 4 exponent bits,
+ *                bias 7, 3 mantissa bits, largest finite 448), FP32
+ *                accumulation, post-training quantisation:
+ *    Activation scales: fv_net_calibrate runs the BF16 network over its
+ *      frames and takes, for every tensor t with a scale (the packed input
+ *      and the output of each 3x3 conv, after its ReLU), the largest
+ *      magnitude m_t as computed before the tensor is rounded for storage:
+ *      s_t = max(m_t, 1e-6) / 448.  A value a of t is stored as the code
+ *      q = E4M3(a / s_t), saturated at +-448, rounded to nearest even.  A
+ *      pooled tensor stores E4M3 of the mean of four codes and an upsampled
+ *      one E4M3 of the bilinear blend of the codes; both keep their source's
+ *      scale.
+ *    Weight scales: for a 3x3 layer whose input channel c comes from a
+ *      tensor of scale s_in(c), W'[o][c][t] = W[o][c][t] s_in(c),
+ *      omega_o = max over c, t of |W'[o][c][t]| / 448 (1 for an all-zero
+ *      channel), weight codes Wq = E4M3(W' / omega_o).
+ *    Epilogue: acc_o = sum of Wq q over the 3x3 taps and channels (FP32
+ *      accumulation), stored q_out = E4M3(min(max(acc_o (omega_o / s_out) +
+ *      B_o / s_out, 0), 448)), the two factors in FP32 (ReLU and
+ *      saturation in one clamp).
+ *    Heads: the codes of the last decoder tensor with the head weights
+ *      BF16(W s_d0b), FP32 bias and accumulation.
  *  The two 1x1 heads run on MFMA with BF16 operands (FP8 activations are
  *  widened) and FP32 accumulation; softmax and the kernel application run
  *  in FP32.
@@ -417,6 +436,14 @@ fv_status fv_net_calibrate_recurrent(fv_net* n, const float* frame_rgba, const u
                                      int views, int width, int height, void* workspace,
                                      size_t ws_bytes, void* stream);
 
+/* The FP8 scales of a calibrated network (a test hook and a diagnostic):
+ * host_scales[0] = s_in of the packed input, host_scales[1 + l] = the scale
+ * of the output of 3x3 conv l in canonical order (e0a, e0b, ..., d0b); 15
+ * values.  Errors: null pointers, count != FV_NET_FP8_TENSORS, a network
+ * that has not been calibrated (FV_ERR_INVALID_ARG). */
+#define FV_NET_FP8_TENSORS 15
+fv_status fv_net_fp8_scales(const fv_net* n, float* host_scales, int count);
+
 /* ------------------------------------------------------------------------
  * 5. Training of the reconstruction network (paper: "Loss", "Training")
  * ------------------------------------------------------------------------
@@ -481,6 +508,35 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
                           void* stream);
 fv_status fv_net_adam(fv_net* n, float lr, float beta1, float beta2, float eps,
                       void* stream);
+/* Replaces the handle's parameter gradient with a caller-supplied one:
+ *   grad  dev float [n_params], the external layout of the handle's form
+ *         (the layout of fv_net_backward's grad_out)
+ * enqueued on `stream`; the next fv_net_adam applies it.  This is where a
+ * gradient that was reduced outside the library (for instance over
+ * data-parallel replicas) re-enters the handle.  Errors: null pointers,
+ * n_params not the form's count. */
+fv_status fv_net_set_grad(fv_net* n, const float* grad, size_t n_params, void* stream);
+
+/* Checkpoints of the training state (the paper exports its trained network
+ * for deployment, Sec. 3.4; here the blob also carries what training needs
+ * to resume).  Blob layout, little-endian:
+ *   64-byte header: the 8 characters "FOVOLNET", u32 version (1), u32 form
+ *     (0 plain, 1 recurrent), u64 n_params, i64 Adam step, 32 zero bytes;
+ *   then FP32 master weights, Adam first moments m and second moments v,
+ *     n_params each, in the external parameter layout of the form.
+ * fv_net_save with host_blob NULL stores the blob size in *bytes; otherwise
+ * *bytes is the buffer size on entry (FV_ERR_CAPACITY if too small) and the
+ * blob size on return.  It reads the device state synchronously, so the
+ * caller first synchronises the streams that updated the handle.
+ * fv_net_load creates a handle from a blob, as fv_net_create does, with the
+ * Adam moments and step restored: training resumes exactly where the saved
+ * handle stood (the FP8 copy needs fv_net_calibrate again).  Errors: null
+ * pointers, a short blob, a bad magic, form or parameter count, a negative
+ * step (FV_ERR_INVALID_ARG), an unknown version (FV_ERR_UNSUPPORTED),
+ * allocation failure (FV_ERR_NOMEM). */
+fv_status fv_net_save(const fv_net* n, void* host_blob, size_t* bytes);
+fv_status fv_net_load(const void* host_blob, size_t bytes, fv_net** out);
+
 /* forward_train + loss + backward + Adam (beta 0.9 / 0.999, eps 1e-8).  A
  * recurrent network is trained here with a zero fed-back O_d. */
 fv_status fv_train_step(fv_net* n, const float* frame_rgba, const uint8_t* mask,

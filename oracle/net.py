@@ -92,11 +92,12 @@ def conv2d(x, w, b):
     co, _, k, _ = w.shape
     p = k // 2
     xp = np.pad(x, ((0, 0), (0, 0), (p, p), (p, p)))
-    y = np.zeros((n, co, h, wd))
+    y = np.zeros((co, n, h, wd))
     for ky in range(k):
         for kx in range(k):
-            y += np.einsum("oc,nchw->nohw", w[:, :, ky, kx], xp[:, :, ky:ky + h, kx:kx + wd])
-    return y + b[None, :, None, None]
+            # sum over input channels c of w[o, c] x[n, c, y + ky, x + kx] (a matmul)
+            y += np.tensordot(w[:, :, ky, kx], xp[:, :, ky:ky + h, kx:kx + wd], axes=([1], [1]))
+    return y.transpose(1, 0, 2, 3) + b[None, :, None, None]
 
 
 def conv2d_bwd(x, w, dy):
@@ -108,8 +109,12 @@ def conv2d_bwd(x, w, dy):
     dw = np.zeros_like(w)
     for ky in range(k):
         for kx in range(k):
-            dw[:, :, ky, kx] = np.einsum("nohw,nchw->oc", dy, xp[:, :, ky:ky + h, kx:kx + wd])
-            dxp[:, :, ky:ky + h, kx:kx + wd] += np.einsum("oc,nohw->nchw", w[:, :, ky, kx], dy)
+            # dw[o, c] = sum over n, y, x of dy[n, o] x[n, c] at the tap's offset
+            dw[:, :, ky, kx] = np.tensordot(dy, xp[:, :, ky:ky + h, kx:kx + wd],
+                                            axes=([0, 2, 3], [0, 2, 3]))
+            # dx[n, c] at the tap's offset += sum over o of w[o, c] dy[n, o]
+            dxp[:, :, ky:ky + h, kx:kx + wd] += np.tensordot(
+                w[:, :, ky, kx], dy, axes=([0], [1])).transpose(1, 0, 2, 3)
     db = dy.sum(axis=(0, 2, 3))
     return dxp[:, :, p:p + h, p:p + wd], dw, db
 

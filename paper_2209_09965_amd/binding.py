@@ -103,6 +103,10 @@ _SIGS = {
                          _vp]),
     "fv_train_step": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, ctypes.c_float, _vp, _vp, _sz,
                            _vp]),
+    "fv_net_fp8_scales": (_i, [_vp, _vp, _i]),
+    "fv_net_set_grad": (_i, [_vp, _vp, _sz, _vp]),
+    "fv_net_save": (_i, [_vp, _vp, ctypes.POINTER(_sz)]),
+    "fv_net_load": (_i, [_vp, _sz, ctypes.POINTER(_vp)]),
 }
 for _name, (_res, _args) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -123,8 +127,40 @@ def check(status):
         raise FvError(status, last_error())
 
 
-def _ptr(t):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
+F32 = (torch.float32,)
+U8 = (torch.uint8,)
+U32 = (torch.int32, torch.uint32)   # 32-bit index / count buffers (bits as uint32)
+U64 = (torch.int64, torch.uint64)
+
+
+def _dev(t, name, dtypes, numel, required=True):
+    """The device pointer of tensor argument `name`, after checking on the host
+    that it is a contiguous CUDA tensor of one of `dtypes` holding at least
+    `numel` elements (a buffer the library would overrun raises here instead
+    of faulting on the device).  None passes through when not required."""
+    if t is None:
+        if required:
+            raise ValueError("%s is required" % name)
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise ValueError("%s must be a torch tensor" % name)
+    if t.dtype not in dtypes:
+        raise ValueError("%s has dtype %s, expected %s" % (name, t.dtype,
+                                                            " or ".join(map(str, dtypes))))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.numel() < numel:
+        raise ValueError("%s holds %d elements, needs %d" % (name, t.numel(), numel))
+    if not t.is_cuda:
+        raise ValueError("%s must be a CUDA tensor" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ws(t):
+    """(pointer, size in bytes) of a workspace tensor (any dtype, contiguous, CUDA)."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("workspace must be a contiguous CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr()), t.numel() * t.element_size()
 
 
 def _stream(stream):
@@ -184,26 +220,33 @@ def fovea_mask(params, width, height, views, ray_idx, count, mask=None, workspac
                stream=None):
     """Sample map + ordered compaction into ray_idx (uint32, capacity = its numel) and
     count (uint32 [1]); optional mask (uint8 [views*H*W])."""
+    npx = views * width * height
+    pr = _dev(ray_idx, "ray_idx", U32, 1)
     if workspace is None:
         workspace = torch.empty(fovea_mask_workspace(width, height, views), dtype=torch.uint8,
                                 device=ray_idx.device)
+    wp, wb = _ws(workspace)
     check(_lib.fv_fovea_mask(ctypes.byref(fovea_params(params)), width, height, views,
-                             _ptr(mask), _ptr(ray_idx), ray_idx.numel(), _ptr(count),
-                             _ptr(workspace), workspace.numel(), _stream(stream)))
+                             _dev(mask, "mask", U8, npx, False), pr, ray_idx.numel(),
+                             _dev(count, "count", U32, 1), wp, wb, _stream(stream)))
 
 
 def fovea_mask_tiles(params, tiles, width, height, views, ray_idx, count, mask=None,
                      workspace=None, stream=None):
     """As fovea_mask, with the noise drawn from a device stack of tiles
     (int32/uint32 [count, tile_h, tile_w], 24-bit values) instead of the hash."""
+    npx = views * width * height
+    tc, th, tw = tiles.shape
+    pt = _dev(tiles, "tiles", U32, tc * th * tw)
+    pr = _dev(ray_idx, "ray_idx", U32, 1)
     if workspace is None:
         workspace = torch.empty(fovea_mask_workspace(width, height, views), dtype=torch.uint8,
                                 device=ray_idx.device)
-    tc, th, tw = tiles.shape
-    check(_lib.fv_fovea_mask_tiles(ctypes.byref(fovea_params(params)), _ptr(tiles), tw, th, tc,
-                                   width, height, views, _ptr(mask), _ptr(ray_idx),
-                                   ray_idx.numel(), _ptr(count), _ptr(workspace),
-                                   workspace.numel(), _stream(stream)))
+    wp, wb = _ws(workspace)
+    check(_lib.fv_fovea_mask_tiles(ctypes.byref(fovea_params(params)), pt, tw, th, tc,
+                                   width, height, views, _dev(mask, "mask", U8, npx, False), pr,
+                                   ray_idx.numel(), _dev(count, "count", U32, 1), wp, wb,
+                                   _stream(stream)))
 
 
 # ---------------------------------------------------------------------- volume
@@ -217,8 +260,8 @@ class Volume:
         data = data.contiguous()
         nz, ny, nx = data.shape
         h = ctypes.c_void_p()
-        check(_lib.fv_volume_create(_ptr(data), nx, ny, nz, DTYPE_CODES[data.dtype],
-                                    _stream(stream), ctypes.byref(h)))
+        check(_lib.fv_volume_create(ctypes.c_void_p(data.data_ptr()), nx, ny, nz,
+                                    DTYPE_CODES[data.dtype], _stream(stream), ctypes.byref(h)))
         self.handle = h
         self.shape = (nz, ny, nx)
         self.dtype = data.dtype
@@ -242,22 +285,35 @@ def _cams(cams):
     return arr
 
 
+def _tf(tf):
+    return _dev(tf, "tf", F32, 1), tf.numel() // 4
+
+
 def raymarch_dense(vol, tf, cams, width, height, mp, frame_rgba, frame_depth=None,
                    sample_count=None, stream=None):
     """Full-frame march of len(cams) views into frame_rgba [views*H*W*4] f32."""
     arr = _cams(cams)
-    check(_lib.fv_raymarch_dense(vol.handle, _ptr(tf), tf.numel() // 4, arr, len(cams), width,
-                                 height, ctypes.byref(march_params(mp)), _ptr(frame_rgba),
-                                 _ptr(frame_depth), _ptr(sample_count), _stream(stream)))
+    npx = len(cams) * width * height
+    tp, tn = _tf(tf)
+    check(_lib.fv_raymarch_dense(vol.handle, tp, tn, arr, len(cams), width, height,
+                                 ctypes.byref(march_params(mp)),
+                                 _dev(frame_rgba, "frame_rgba", F32, npx * 4),
+                                 _dev(frame_depth, "frame_depth", F32, npx, False),
+                                 _dev(sample_count, "sample_count", U64, 1, False),
+                                 _stream(stream)))
 
 
 def raymarch_masked(vol, tf, cams, width, height, mp, mask, frame_rgba, frame_depth=None,
                     sample_count=None, stream=None):
     """Naive rejection: the full-frame march where pixels with mask 0 return at once."""
     arr = _cams(cams)
-    check(_lib.fv_raymarch_masked(vol.handle, _ptr(tf), tf.numel() // 4, arr, len(cams), width,
-                                  height, ctypes.byref(march_params(mp)), _ptr(mask),
-                                  _ptr(frame_rgba), _ptr(frame_depth), _ptr(sample_count),
+    npx = len(cams) * width * height
+    tp, tn = _tf(tf)
+    check(_lib.fv_raymarch_masked(vol.handle, tp, tn, arr, len(cams), width, height,
+                                  ctypes.byref(march_params(mp)), _dev(mask, "mask", U8, npx),
+                                  _dev(frame_rgba, "frame_rgba", F32, npx * 4),
+                                  _dev(frame_depth, "frame_depth", F32, npx, False),
+                                  _dev(sample_count, "sample_count", U64, 1, False),
                                   _stream(stream)))
 
 
@@ -273,15 +329,23 @@ def raymarch_sparse(vol, tf, cams, width, height, mp, ray_idx, count, rgba_compa
                     workspace=None, stream=None, capacity=None):
     """March the compacted list (ray_idx, count) and back-project to the frame."""
     cap = ray_idx.numel() if capacity is None else capacity
+    npx = len(cams) * width * height
+    pr = _dev(ray_idx, "ray_idx", U32, cap)
     if workspace is None:
         workspace = torch.empty(raymarch_sparse_workspace(cap), dtype=torch.uint8,
                                 device=ray_idx.device)
+    wp, wb = _ws(workspace)
     arr = _cams(cams)
-    check(_lib.fv_raymarch_sparse(vol.handle, _ptr(tf), tf.numel() // 4, arr, len(cams), width,
-                                  height, ctypes.byref(march_params(mp)), _ptr(ray_idx),
-                                  _ptr(count), cap, _ptr(rgba_compact), _ptr(depth_compact),
-                                  _ptr(frame_rgba), _ptr(frame_depth), _ptr(sample_count),
-                                  _ptr(workspace), workspace.numel(), _stream(stream)))
+    tp, tn = _tf(tf)
+    check(_lib.fv_raymarch_sparse(vol.handle, tp, tn, arr, len(cams), width, height,
+                                  ctypes.byref(march_params(mp)), pr,
+                                  _dev(count, "count", U32, 1), cap,
+                                  _dev(rgba_compact, "rgba_compact", F32, cap * 4, False),
+                                  _dev(depth_compact, "depth_compact", F32, cap, False),
+                                  _dev(frame_rgba, "frame_rgba", F32, npx * 4, False),
+                                  _dev(frame_depth, "frame_depth", F32, npx, False),
+                                  _dev(sample_count, "sample_count", U64, 1, False),
+                                  wp, wb, _stream(stream)))
 
 
 # ----------------------------------------------------------------- network
@@ -289,6 +353,7 @@ def raymarch_sparse(vol, tf, cams, width, height, mp, ray_idx, count, rgba_compa
 FV_PREC_BF16 = 1
 FV_PREC_FP8 = 2
 PRECISIONS = {"bf16": FV_PREC_BF16, "fp8": FV_PREC_FP8}
+FP8_TENSORS = 15  # FV_NET_FP8_TENSORS: the input and the 14 conv outputs
 
 
 def _prec(p):
@@ -298,7 +363,10 @@ def _prec(p):
 class Net:
     """Library-owned reconstruction network (FP32 master + BF16/FP8 copies)."""
 
-    def __init__(self, params):
+    def __init__(self, params=None, _handle=None):
+        if _handle is not None:
+            self.handle = _handle
+            return
         import numpy as np
         arr = np.ascontiguousarray(params, dtype=np.float32)
         h = ctypes.c_void_p()
@@ -318,9 +386,13 @@ class Net:
     def recurrent(self):
         return int(_lib.fv_net_input_channels(self.handle)) == 8
 
+    @property
+    def n_params(self):
+        return self.PARAMS_RECURRENT if self.recurrent else self.PARAMS
+
     def get_params(self):
         import numpy as np
-        out = np.zeros(self.PARAMS_RECURRENT if self.recurrent else self.PARAMS, dtype=np.float32)
+        out = np.zeros(self.n_params, dtype=np.float32)
         check(_lib.fv_net_get_params(self.handle, ctypes.c_void_p(out.ctypes.data), out.size))
         return out
 
@@ -329,20 +401,58 @@ class Net:
         arr = np.ascontiguousarray(params, dtype=np.float32)
         check(_lib.fv_net_set_params(self.handle, ctypes.c_void_p(arr.ctypes.data), arr.size))
 
+    def fp8_scales(self):
+        """The calibrated FP8 scales: [input, e0a, e0b, ..., d0b] (numpy float32)."""
+        import numpy as np
+        out = np.zeros(FP8_TENSORS, dtype=np.float32)
+        check(_lib.fv_net_fp8_scales(self.handle, ctypes.c_void_p(out.ctypes.data), out.size))
+        return out
+
+    def set_grad(self, grad, stream=None):
+        """Replace the handle's gradient with a device float32 vector (external layout)."""
+        check(_lib.fv_net_set_grad(self.handle, _dev(grad, "grad", F32, self.n_params),
+                                   self.n_params, _stream(stream)))
+
+    def save(self):
+        """The checkpoint blob (bytes): header, FP32 weights, Adam m and v."""
+        import numpy as np
+        n = _sz()
+        check(_lib.fv_net_save(self.handle, None, ctypes.byref(n)))
+        buf = np.zeros(n.value, dtype=np.uint8)
+        check(_lib.fv_net_save(self.handle, ctypes.c_void_p(buf.ctypes.data), ctypes.byref(n)))
+        return buf.tobytes()
+
+    @classmethod
+    def load(cls, blob):
+        """A new handle from a checkpoint blob written by save()."""
+        import numpy as np
+        buf = np.frombuffer(blob, dtype=np.uint8)
+        h = ctypes.c_void_p()
+        check(_lib.fv_net_load(ctypes.c_void_p(buf.ctypes.data), buf.size, ctypes.byref(h)))
+        return cls(_handle=h)
+
     def workspace_bytes(self, views, width, height, precision="bf16"):
         b = _sz()
         check(_lib.fv_reconstruct_workspace(self.handle, _prec(precision), views, width, height,
                                             ctypes.byref(b)))
         return b.value
 
+    def _frame_args(self, frame_rgba, mask, frame_depth, n, width, height):
+        npx = n * width * height
+        return (_dev(frame_rgba, "frame_rgba", F32, npx * 4), _dev(mask, "mask", U8, npx),
+                _dev(frame_depth, "frame_depth", F32, npx, False))
+
     def reconstruct(self, frame_rgba, mask, frame_depth, views, width, height, out_rgb,
                     out_direct=None, precision="bf16", workspace=None, stream=None):
+        npx = views * width * height
+        fa = self._frame_args(frame_rgba, mask, frame_depth, views, width, height)
         if workspace is None:
             workspace = torch.empty(self.workspace_bytes(views, width, height, precision),
                                     dtype=torch.uint8, device=frame_rgba.device)
-        check(_lib.fv_reconstruct(self.handle, _prec(precision), _ptr(frame_rgba), _ptr(mask),
-                                  _ptr(frame_depth), views, width, height, _ptr(out_rgb),
-                                  _ptr(out_direct), _ptr(workspace), workspace.numel(),
+        wp, wb = _ws(workspace)
+        check(_lib.fv_reconstruct(self.handle, _prec(precision), *fa, views, width, height,
+                                  _dev(out_rgb, "out_rgb", F32, npx * 3),
+                                  _dev(out_direct, "out_direct", F32, npx * 3, False), wp, wb,
                                   _stream(stream)))
 
     def reconstruct_recurrent(self, frame_rgba, mask, frame_depth, prev_direct, views, width,
@@ -350,32 +460,40 @@ class Net:
                               workspace=None, stream=None):
         """Recurrent form: prev_direct is the previous frame's out_direct (None
         for the first frame of a sequence); it may be out_direct itself."""
+        npx = views * width * height
+        fa = self._frame_args(frame_rgba, mask, frame_depth, views, width, height)
         if workspace is None:
             workspace = torch.empty(self.workspace_bytes(views, width, height, precision),
                                     dtype=torch.uint8, device=frame_rgba.device)
-        check(_lib.fv_reconstruct_recurrent(self.handle, _prec(precision), _ptr(frame_rgba),
-                                            _ptr(mask), _ptr(frame_depth), _ptr(prev_direct),
-                                            views, width, height, _ptr(out_rgb),
-                                            _ptr(out_direct), _ptr(workspace), workspace.numel(),
-                                            _stream(stream)))
+        wp, wb = _ws(workspace)
+        check(_lib.fv_reconstruct_recurrent(self.handle, _prec(precision), *fa,
+                                            _dev(prev_direct, "prev_direct", F32, npx * 3, False),
+                                            views, width, height,
+                                            _dev(out_rgb, "out_rgb", F32, npx * 3),
+                                            _dev(out_direct, "out_direct", F32, npx * 3, False),
+                                            wp, wb, _stream(stream)))
 
     def calibrate_recurrent(self, frame_rgba, mask, frame_depth, prev_direct, views, width,
                             height, workspace=None, stream=None):
+        npx = views * width * height
+        fa = self._frame_args(frame_rgba, mask, frame_depth, views, width, height)
         if workspace is None:
             workspace = torch.empty(self.workspace_bytes(views, width, height, "bf16"),
                                     dtype=torch.uint8, device=frame_rgba.device)
-        check(_lib.fv_net_calibrate_recurrent(self.handle, _ptr(frame_rgba), _ptr(mask),
-                                              _ptr(frame_depth), _ptr(prev_direct), views, width,
-                                              height, _ptr(workspace), workspace.numel(),
-                                              _stream(stream)))
+        wp, wb = _ws(workspace)
+        check(_lib.fv_net_calibrate_recurrent(self.handle, *fa,
+                                              _dev(prev_direct, "prev_direct", F32, npx * 3,
+                                                   False),
+                                              views, width, height, wp, wb, _stream(stream)))
 
     def calibrate(self, frame_rgba, mask, frame_depth, views, width, height, workspace=None,
                   stream=None):
+        fa = self._frame_args(frame_rgba, mask, frame_depth, views, width, height)
         if workspace is None:
             workspace = torch.empty(self.workspace_bytes(views, width, height, "bf16"),
                                     dtype=torch.uint8, device=frame_rgba.device)
-        check(_lib.fv_net_calibrate(self.handle, _ptr(frame_rgba), _ptr(mask), _ptr(frame_depth),
-                                    views, width, height, _ptr(workspace), workspace.numel(),
+        wp, wb = _ws(workspace)
+        check(_lib.fv_net_calibrate(self.handle, *fa, views, width, height, wp, wb,
                                     _stream(stream)))
 
     # -- training (one workspace shared by the calls of an iteration)
@@ -386,34 +504,48 @@ class Net:
 
     def forward_train(self, frame_rgba, mask, frame_depth, batch, width, height, out_rgb,
                       workspace, stream=None):
-        check(_lib.fv_net_forward_train(self.handle, _ptr(frame_rgba), _ptr(mask),
-                                        _ptr(frame_depth), batch, width, height, _ptr(out_rgb),
-                                        _ptr(workspace), workspace.numel(), _stream(stream)))
+        fa = self._frame_args(frame_rgba, mask, frame_depth, batch, width, height)
+        wp, wb = _ws(workspace)
+        check(_lib.fv_net_forward_train(self.handle, *fa, batch, width, height,
+                                        _dev(out_rgb, "out_rgb", F32, batch * width * height * 3),
+                                        wp, wb, _stream(stream)))
 
     def forward_train_recurrent(self, frame_rgba, mask, frame_depth, prev_direct, batch, width,
                                 height, out_rgb, workspace, stream=None):
-        check(_lib.fv_net_forward_train_recurrent(self.handle, _ptr(frame_rgba), _ptr(mask),
-                                                  _ptr(frame_depth), _ptr(prev_direct), batch,
-                                                  width, height, _ptr(out_rgb), _ptr(workspace),
-                                                  workspace.numel(), _stream(stream)))
+        npx = batch * width * height
+        fa = self._frame_args(frame_rgba, mask, frame_depth, batch, width, height)
+        wp, wb = _ws(workspace)
+        check(_lib.fv_net_forward_train_recurrent(
+            self.handle, *fa, _dev(prev_direct, "prev_direct", F32, npx * 3, False), batch,
+            width, height, _dev(out_rgb, "out_rgb", F32, npx * 3), wp, wb, _stream(stream)))
 
     def loss(self, out_rgb, target_rgba, batch, width, height, loss3, dloss, workspace,
              stream=None):
-        check(_lib.fv_net_loss(self.handle, _ptr(out_rgb), _ptr(target_rgba), batch, width,
-                               height, _ptr(loss3), _ptr(dloss), _ptr(workspace),
-                               workspace.numel(), _stream(stream)))
+        npx = batch * width * height
+        wp, wb = _ws(workspace)
+        check(_lib.fv_net_loss(self.handle, _dev(out_rgb, "out_rgb", F32, npx * 3),
+                               _dev(target_rgba, "target_rgba", F32, npx * 4), batch, width,
+                               height, _dev(loss3, "loss3", F32, 3),
+                               _dev(dloss, "dloss", F32, npx * 3), wp, wb, _stream(stream)))
 
     def loss_temporal(self, out_rgb, target_rgba, batch, width, height, weight, loss, dloss,
                       workspace, stream=None):
         """Temporal finite-difference loss over batch pairs (2i, 2i+1); adds
         weight * d L_t / d out to dloss (call after loss())."""
-        check(_lib.fv_net_loss_temporal(self.handle, _ptr(out_rgb), _ptr(target_rgba), batch,
-                                        width, height, float(weight), _ptr(loss), _ptr(dloss),
-                                        _ptr(workspace), workspace.numel(), _stream(stream)))
+        npx = batch * width * height
+        wp, wb = _ws(workspace)
+        check(_lib.fv_net_loss_temporal(self.handle, _dev(out_rgb, "out_rgb", F32, npx * 3),
+                                        _dev(target_rgba, "target_rgba", F32, npx * 4), batch,
+                                        width, height, float(weight), _dev(loss, "loss", F32, 1),
+                                        _dev(dloss, "dloss", F32, npx * 3), wp, wb,
+                                        _stream(stream)))
 
     def backward(self, dloss, batch, width, height, workspace, grad_out=None, stream=None):
-        check(_lib.fv_net_backward(self.handle, _ptr(dloss), batch, width, height,
-                                   _ptr(grad_out), _ptr(workspace), workspace.numel(),
+        wp, wb = _ws(workspace)
+        check(_lib.fv_net_backward(self.handle,
+                                   _dev(dloss, "dloss", F32, batch * width * height * 3), batch,
+                                   width, height,
+                                   _dev(grad_out, "grad_out", F32, self.n_params, False), wp, wb,
                                    _stream(stream)))
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
@@ -421,9 +553,12 @@ class Net:
 
     def train_step(self, frame_rgba, mask, frame_depth, target_rgba, batch, width, height, lr,
                    loss3, workspace, stream=None):
-        check(_lib.fv_train_step(self.handle, _ptr(frame_rgba), _ptr(mask), _ptr(frame_depth),
-                                 _ptr(target_rgba), batch, width, height, lr, _ptr(loss3),
-                                 _ptr(workspace), workspace.numel(), _stream(stream)))
+        npx = batch * width * height
+        fa = self._frame_args(frame_rgba, mask, frame_depth, batch, width, height)
+        wp, wb = _ws(workspace)
+        check(_lib.fv_train_step(self.handle, *fa, _dev(target_rgba, "target_rgba", F32, npx * 4),
+                                 batch, width, height, lr, _dev(loss3, "loss3", F32, 3), wp, wb,
+                                 _stream(stream)))
 
     def close(self):
         if self.handle:

@@ -205,3 +205,68 @@ def test_binding_signatures_match_the_header():
             assert ok(c, t), (name, i, c, t)
         want_res = {"fv_status": ctypes.c_int, "int": ctypes.c_int, "size_t": ctypes.c_size_t}
         assert (res is ctypes.c_char_p) if "char" in cres else (res is want_res[cres]), name
+
+
+def test_binding_checks_tensors_before_the_call():
+    """Every tensor argument is checked on the host (dtype, contiguity, size,
+    device) before its pointer crosses the ABI, so an undersized or mistyped
+    buffer raises instead of being overrun on the device."""
+    import torch
+    from paper_2209_09965_amd import binding as b
+    f = torch.zeros(64, dtype=torch.float32)
+    with pytest.raises(ValueError, match="dtype"):
+        b._dev(f, "frame_rgba", b.U8, 1)
+    with pytest.raises(ValueError, match="contiguous"):
+        b._dev(torch.zeros(8, 8)[:, ::2], "frame_rgba", b.F32, 1)
+    with pytest.raises(ValueError, match="needs 65"):
+        b._dev(f, "frame_rgba", b.F32, 65)
+    with pytest.raises(ValueError, match="CUDA"):
+        b._dev(f, "frame_rgba", b.F32, 64)
+    with pytest.raises(ValueError, match="required"):
+        b._dev(None, "mask", b.U8, 1)
+    assert b._dev(None, "frame_depth", b.F32, 1, required=False) is None
+    with pytest.raises(ValueError, match="workspace"):
+        b._ws(f)
+    # through a wrapper: the transfer function is checked first
+    mp = dict(step_vox=0.5, alpha_stop=0.99)
+    cam = dict(eye=(0, 0, 2), target=(0, 0, 0), up=(0, 1, 0), fovy_deg=45.0)
+    with pytest.raises(ValueError, match="tf"):
+        b.raymarch_dense(None, torch.zeros(1024, dtype=torch.float64), [cam], 8, 8, mp, f)
+    with pytest.raises(ValueError, match="tf must be a CUDA"):
+        b.raymarch_dense(None, torch.zeros(1024), [cam], 8, 8, mp, f)
+
+
+def _blob(recurrent=0, n=None, step=3, version=1, magic=b"FOVOLNET", payload=True):
+    import struct
+    from oracle import net as N
+    n = (N.N_PARAMS_RECURRENT if recurrent else N.N_PARAMS) if n is None else n
+    hdr = magic + struct.pack("<IIQq", version, recurrent, n, step) + bytes(32)
+    return hdr + (bytes(12 * n) if payload else b"")
+
+
+def test_checkpoint_and_state_host_errors():
+    """fv_net_load validates the blob on the host before it creates a handle;
+    null handles are rejected by save, set_grad and the FP8 scale query."""
+    from paper_2209_09965_amd import binding as b
+    L = b.lib()
+    h = ctypes.c_void_p()
+    n = ctypes.c_size_t(0)
+    assert L.fv_net_save(None, None, ctypes.byref(n)) == -1
+    assert L.fv_net_set_grad(None, ctypes.c_void_p(0x1000), 480060, None) == -1
+    assert L.fv_net_fp8_scales(None, ctypes.c_void_p(0x1000), 15) == -1
+    assert L.fv_net_load(None, 0, ctypes.byref(h)) == -1
+
+    def load(blob):
+        buf = np.frombuffer(blob, np.uint8)
+        return L.fv_net_load(ctypes.c_void_p(buf.ctypes.data), buf.size, ctypes.byref(h))
+
+    assert load(_blob()[:40]) == -1                     # no header
+    assert load(_blob(magic=b"NOTANET!")) == -1
+    assert b"checkpoint" in L.fv_last_error()
+    assert load(_blob(version=2)) == -3
+    assert load(_blob(n=12345)) == -1                   # count of neither form
+    assert load(_blob(recurrent=1, n=480060)) == -1     # count of the other form
+    assert load(_blob(step=-1)) == -1
+    assert load(_blob(payload=False)) == -1             # header only
+    hdr = open(os.path.join(ROOT, "include", "fovol.h")).read()
+    assert "#define FV_NET_FP8_TENSORS 15" in hdr and b.FP8_TENSORS == 15

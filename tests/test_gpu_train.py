@@ -106,8 +106,104 @@ def test_adam_steps_reduce_loss(dev):
     print("losses", ["%.4f" % v for v in losses[::5]], "%.4f" % losses[-1])
     assert all(np.isfinite(losses))
     assert losses[-1] < 0.8 * losses[0]
-    # Adam's first step moves each weight by about lr (closed form of the first step)
     net.close()
+
+
+def _parse_blob(blob):
+    import struct
+    magic, ver, form, n, step = struct.unpack("<8sIIQq", blob[:32])
+    assert magic == b"FOVOLNET" and ver == 1 and blob[32:64] == bytes(32)
+    a = np.frombuffer(blob[64:], dtype="<f4")
+    assert a.size == 3 * n
+    return form, step, a[:n], a[n:2 * n], a[2 * n:]
+
+
+def test_adam_matches_oracle(dev):
+    """Three Adam steps (Sec. 3.5: Adam; bias-corrected moments, the step
+    counted from 1) on seeded gradients handed to the handle with
+    fv_net_set_grad, with different hyper-parameters per step: the FP32
+    weights and both moments, read back through fv_net_save, against
+    oracle.net.adam in FP64 on the same gradients, element by element.
+    FP32 rounding of the three steps bounds the difference at a few 1e-7 of
+    each quantity's scale."""
+    from paper_2209_09965_amd import binding as b
+    theta = _theta(12)
+    net = b.Net(theta)
+    rng = np.random.default_rng(40)
+    th = theta.astype(np.float64)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    mabs = np.zeros_like(th)  # the first moment of |g|: m's scale without cancellation
+    f32 = lambda x: float(np.float32(x))
+    hps = [(1e-3, 0.9, 0.999, 1e-8), (5e-4, 0.8, 0.99, 1e-6), (2e-3, 0.9, 0.999, 1e-8)]
+    for step, (lr, b1, b2, eps) in enumerate(hps, 1):
+        g = rng.normal(0, 1e-2, th.size).astype(np.float32)
+        g[::7] *= 1e-3  # gradients spread over magnitudes
+        g[::11] = 0.0
+        net.set_grad(torch.from_numpy(g).to(dev))
+        net.adam(lr, b1, b2, eps)
+        th, m, v = N.adam(th, g.astype(np.float64), m, v, step, lr=f32(lr), b1=f32(b1),
+                          b2=f32(b2), eps=f32(eps))
+        mabs = f32(b1) * mabs + (1 - f32(b1)) * np.abs(g)
+    torch.cuda.synchronize()
+    form, step, gth, gm, gv = _parse_blob(net.save())
+    net.close()
+    assert form == 0 and step == 3
+    dth, dm, dv = np.abs(gth - th), np.abs(gm - m), np.abs(gv - v)
+    print("adam: |d theta| max %.3g (rel %.3g) | |d m| max %.3g | |d v| rel max %.3g"
+          % (dth.max(), (dth / np.maximum(np.abs(th), 1e-30)).max(), dm.max(),
+             (dv / np.maximum(v, 1e-300)).max()), flush=True)
+    # theta: FP32 rounding of the weight (and 1e-6 of the ~lr-sized updates)
+    assert np.all(dth <= 1e-6 * np.abs(th) + 1e-9)
+    assert np.all(dm <= 1e-6 * mabs)
+    assert np.all(dv <= 1e-6 * v)
+
+
+def _batch(seed, n, H, W):
+    rng = np.random.default_rng(seed)
+    rgba, mask, depth = _frame(rng, n, H, W, density=0.3)
+    tgt = rgba.copy()
+    tgt[:, :3] = np.clip(tgt[:, :3] + rng.normal(0, 0.05, (tgt.shape[0], 3)), 0, 1)
+    return rgba, mask, depth, tgt
+
+
+@pytest.mark.parametrize("recurrent", [False, True])
+def test_checkpoint_resume_is_bitwise(recurrent, dev):
+    """Training k steps, saving, loading into a new handle and training on
+    gives the same weights and Adam state, bit for bit, as training straight
+    through (the training step is deterministic: fixed-order reductions);
+    a loaded handle saves the blob it was loaded from."""
+    from paper_2209_09965_amd import binding as b
+    n, H, W = 2, 32, 48
+    theta = _theta(13, recurrent=recurrent)
+    batches = [[_t(a, dev) for a in _batch(50 + k, n, H, W)] for k in range(4)]
+
+    def train(net, ks):
+        ws = torch.empty(net.train_workspace_bytes(n, W, H), dtype=torch.uint8, device=dev)
+        loss3 = torch.zeros(3, device=dev)
+        for k in ks:
+            fr, m, d, t = batches[k]
+            net.train_step(fr, m, d, t, n, W, H, 1e-3, loss3, ws)
+        torch.cuda.synchronize()
+
+    a = b.Net(theta)
+    train(a, range(4))
+    blob_a = a.save()
+    a.close()
+    c = b.Net(theta)
+    train(c, range(2))
+    mid = c.save()
+    c.close()
+    d = b.Net.load(mid)
+    assert d.recurrent == recurrent
+    assert d.save() == mid
+    train(d, range(2, 4))
+    blob_d = d.save()
+    form, step, th, _, _ = _parse_blob(blob_d)
+    assert form == int(recurrent) and step == 4
+    assert np.array_equal(th, d.get_params())
+    d.close()
+    assert blob_d == blob_a
 
 
 def test_temporal_loss_matches_oracle(dev):
