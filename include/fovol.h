@@ -362,7 +362,10 @@ fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba,
  * fv_net_create tells the two forms apart by n_params. */
 #define FV_NET_PARAMS_RECURRENT 480924
 
-typedef enum { FV_PREC_BF16 = 1, FV_PREC_FP8 = 2 } fv_precision;
+/* FV_RECON_PULLPUSH selects the reconstruction without a network (section
+ * 4b below) in fv_reconstruct and fv_reconstruct_workspace; the network
+ * handle may then be NULL and frame_depth is ignored. */
+typedef enum { FV_PREC_BF16 = 1, FV_PREC_FP8 = 2, FV_RECON_PULLPUSH = 3 } fv_precision;
 
 typedef struct fv_net fv_net;
 
@@ -443,6 +446,96 @@ fv_status fv_net_calibrate_recurrent(fv_net* n, const float* frame_rgba, const u
  * that has not been calibrated (FV_ERR_INVALID_ARG). */
 #define FV_NET_FP8_TENSORS 15
 fv_status fv_net_fp8_scales(const fv_net* n, float* host_scales, int count);
+
+/* ------------------------------------------------------------------------
+ * 4b. Reconstruction without a network: pull-push
+ * ------------------------------------------------------------------------
+ * The baseline against which the learned reconstruction (paper Sec. 3.2) is
+ * measured, and a full-frame fill that needs no weights: the pull-push
+ * scattered-data interpolation of Gortler et al. ("The Lumigraph", 1996,
+ * Sec. 3.3) on an image pyramid, per view.  Level l+1 has ceil(H_l/2) x
+ * ceil(W_l/2) pixels, down to 1 x 1; level 0 holds c_0 = the sampled RGB and
+ * w_0 = M (the sample map).
+ *   Pull: with t = min(w, 1) for each of the (up to) four children q of a
+ *     coarse pixel, w' = sum t(q), c' = sum t(q) c(q) / w' (0 if w' = 0).
+ *   Push: f_top = c_top; f_l(q) = t_l(q) c_l(q) + (1 - t_l(q)) u(q), where
+ *     u is f_{l+1} interpolated bilinearly at (q + 1/2)/2 - 1/2 per axis,
+ *     clamped to the coarser level's pixel range.
+ * out = f_0: sampled pixels keep their colour exactly; a frame without any
+ * sample gives 0.  FP32 arithmetic.
+ *   frame_rgba  dev float [views*H*W*4]; only pixels with mask != 0 are read
+ *   mask        dev uint8 [views*H*W]
+ *   out_rgb     dev float [views*H*W*3]
+ *   workspace   dev, >= fv_pullpush_workspace() bytes (the pulled pyramid
+ *               levels 1.., a float4 per pixel), 256-byte aligned
+ * Any frame size with views*W*H < 2^32 and W, H <= 65535.  Errors: null
+ * pointers, bad sizes (FV_ERR_INVALID_ARG), workspace too small
+ * (FV_ERR_CAPACITY). */
+fv_status fv_pullpush_workspace(int views, int width, int height, size_t* bytes);
+fv_status fv_reconstruct_pullpush(const float* frame_rgba, const uint8_t* mask, int views,
+                                  int width, int height, float* out_rgb, void* workspace,
+                                  size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * 4c. The foveated frame in one call, with the dense march as judge and
+ *     fallback
+ * ------------------------------------------------------------------------
+ * The paper's pipeline (Sec. 3, Fig. 2): sample map and compaction
+ * (fv_fovea_mask), sparse march with back-projection (fv_raymarch_sparse),
+ * full-frame reconstruction (fv_reconstruct with the policy's precision).
+ * The conventional renderer it replaces, the dense march, stays available
+ * as the judge of the reconstruction and as its fallback:
+ *   - frame f is a check frame when check_every > 0 and f mod check_every
+ *     == 0 (f counts the renderer's frames from 0); a check frame renders
+ *     the foveated frame and the dense frame and scores the reconstruction
+ *     by PSNR = 10 log10(1 / MSE), MSE over all pixels and RGB channels of
+ *     values clamped to [0, 1] (FP64 sums in a fixed order), then
+ *     synchronises the stream once to read it;
+ *   - a check frame scoring below min_psnr_db (or NaN) puts the renderer in
+ *     fallback and its output is the dense frame's RGB; one scoring at or
+ *     above the threshold takes it out of fallback;
+ *   - in fallback, frames between checks are dense frames (no sample map,
+ *     no reconstruction).
+ * The renderer owns every intermediate buffer (about 37 bytes a pixel plus
+ * the march and network workspaces); it is single-stream like the other
+ * handles.  Calls on one renderer must not overlap. */
+typedef struct {
+  int32_t precision;    /* FV_PREC_FP8, FV_PREC_BF16 or FV_RECON_PULLPUSH     */
+  int32_t check_every;  /* >= 0; 0 = never check (never falls back)           */
+  float min_psnr_db;    /* fallback threshold, finite                         */
+} fv_render_policy;
+
+typedef struct {
+  uint64_t frame;       /* this frame's index in the renderer's sequence      */
+  int32_t checked;      /* 1: the dense frame was marched and compared        */
+  int32_t dense;        /* 1: out_rgb is the dense frame (fallback)           */
+  int32_t fallback;     /* the renderer's state after this frame              */
+  float psnr_db;        /* the reconstruction's PSNR on a check frame, else NaN */
+} fv_frame_info;
+
+typedef struct fv_renderer fv_renderer;
+
+/* Errors: null pointers, views outside [1, 8], W or H not a multiple of 8 in
+ * [8, 16384], views*W*H >= 2^32, check_every < 0 or a non-finite threshold
+ * (FV_ERR_INVALID_ARG), an unknown precision (FV_ERR_UNSUPPORTED),
+ * allocation failure (FV_ERR_NOMEM). */
+fv_status fv_renderer_create(int views, int width, int height, const fv_render_policy* policy,
+                             fv_renderer** out);
+fv_status fv_renderer_destroy(fv_renderer* r);
+
+/* One frame of the renderer's views: cams[views], the fovea parameters of
+ * fv_fovea_mask, and the march parameters and transfer function of the
+ * march calls.
+ *   net      the reconstruction network (FP8 needs fv_net_calibrate first);
+ *            may be NULL for FV_RECON_PULLPUSH
+ *   out_rgb  dev float [views*H*W*3]
+ *   info     host, filled on return
+ * Errors: those of the calls it makes, and a NULL network for a network
+ * precision (FV_ERR_INVALID_ARG). */
+fv_status fv_render_frame(fv_renderer* r, const fv_volume* vol, const float* tf_rgba, int tf_n,
+                          const fv_camera* cams, const fv_march_params* mp,
+                          const fv_fovea_params* fp, const fv_net* net, float* out_rgb,
+                          fv_frame_info* info, void* stream);
 
 /* ------------------------------------------------------------------------
  * 5. Training of the reconstruction network (paper: "Loss", "Training")

@@ -49,6 +49,17 @@ class MarchParams(ctypes.Structure):
                 ("shadow_step", ctypes.c_float)]
 
 
+class RenderPolicy(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("check_every", ctypes.c_int32),
+                ("min_psnr_db", ctypes.c_float)]
+
+
+class FrameInfo(ctypes.Structure):
+    _fields_ = [("frame", ctypes.c_uint64), ("checked", ctypes.c_int32),
+                ("dense", ctypes.c_int32), ("fallback", ctypes.c_int32),
+                ("psnr_db", ctypes.c_float)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError("libfovol.so is not built (run python -m paper_2209_09965_amd._build); "
                       "there is no fallback implementation")
@@ -105,6 +116,13 @@ _SIGS = {
                            _vp]),
     "fv_net_fp8_scales": (_i, [_vp, _vp, _i]),
     "fv_net_set_grad": (_i, [_vp, _vp, _sz, _vp]),
+    "fv_pullpush_workspace": (_i, [_i, _i, _i, ctypes.POINTER(_sz)]),
+    "fv_reconstruct_pullpush": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp, _sz, _vp]),
+    "fv_renderer_create": (_i, [_i, _i, _i, ctypes.POINTER(RenderPolicy), ctypes.POINTER(_vp)]),
+    "fv_renderer_destroy": (_i, [_vp]),
+    "fv_render_frame": (_i, [_vp, _vp, _vp, _i, ctypes.POINTER(Camera),
+                             ctypes.POINTER(MarchParams), ctypes.POINTER(FoveaParams), _vp, _vp,
+                             ctypes.POINTER(FrameInfo), _vp]),
     "fv_net_save": (_i, [_vp, _vp, ctypes.POINTER(_sz)]),
     "fv_net_load": (_i, [_vp, _sz, ctypes.POINTER(_vp)]),
 }
@@ -348,11 +366,34 @@ def raymarch_sparse(vol, tf, cams, width, height, mp, ray_idx, count, rgba_compa
                                   wp, wb, _stream(stream)))
 
 
+# ------------------------------------------------- reconstruction without a net
+
+def pullpush_workspace(views, width, height):
+    b = _sz()
+    check(_lib.fv_pullpush_workspace(views, width, height, ctypes.byref(b)))
+    return b.value
+
+
+def reconstruct_pullpush(frame_rgba, mask, views, width, height, out_rgb, workspace=None,
+                         stream=None):
+    """Pull-push fill of the sparse frames (no network) into out_rgb [views*H*W*3]."""
+    npx = views * width * height
+    pf = _dev(frame_rgba, "frame_rgba", F32, npx * 4)
+    if workspace is None:
+        workspace = torch.empty(pullpush_workspace(views, width, height), dtype=torch.uint8,
+                                device=frame_rgba.device)
+    wp, wb = _ws(workspace)
+    check(_lib.fv_reconstruct_pullpush(pf, _dev(mask, "mask", U8, npx), views, width, height,
+                                       _dev(out_rgb, "out_rgb", F32, npx * 3), wp, wb,
+                                       _stream(stream)))
+
+
 # ----------------------------------------------------------------- network
 
 FV_PREC_BF16 = 1
 FV_PREC_FP8 = 2
-PRECISIONS = {"bf16": FV_PREC_BF16, "fp8": FV_PREC_FP8}
+FV_RECON_PULLPUSH = 3
+PRECISIONS = {"bf16": FV_PREC_BF16, "fp8": FV_PREC_FP8, "pullpush": FV_RECON_PULLPUSH}
 FP8_TENSORS = 15  # FV_NET_FP8_TENSORS: the input and the 14 conv outputs
 
 
@@ -563,6 +604,50 @@ class Net:
     def close(self):
         if self.handle:
             _lib.fv_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --------------------------------------------------------- foveated renderer
+
+class Renderer:
+    """The foveated frame in one call with the dense march as judge and
+    fallback (fv_render_frame): every check_every-th frame is scored against
+    the dense frame, and below min_psnr_db the dense frame replaces it until
+    a later check passes."""
+
+    def __init__(self, views, width, height, precision="fp8", check_every=0, min_psnr_db=30.0):
+        pol = RenderPolicy(_prec(precision), int(check_every), float(min_psnr_db))
+        h = ctypes.c_void_p()
+        check(_lib.fv_renderer_create(views, width, height, ctypes.byref(pol), ctypes.byref(h)))
+        self.handle = h
+        self.views, self.width, self.height = views, width, height
+
+    def render(self, vol, tf, cams, mp, fovea, net, out_rgb, stream=None):
+        """Renders one frame into out_rgb [views*H*W*3]; returns a dict of the
+        frame's FrameInfo (frame, checked, dense, fallback, psnr_db)."""
+        if len(cams) != self.views:
+            raise ValueError("%d cameras for a %d-view renderer" % (len(cams), self.views))
+        info = FrameInfo()
+        tp, tn = _tf(tf)
+        npx = self.views * self.width * self.height
+        check(_lib.fv_render_frame(self.handle, vol.handle, tp, tn, _cams(cams),
+                                   ctypes.byref(march_params(mp)),
+                                   ctypes.byref(fovea_params(fovea)),
+                                   net.handle if net is not None else None,
+                                   _dev(out_rgb, "out_rgb", F32, npx * 3), ctypes.byref(info),
+                                   _stream(stream)))
+        return dict(frame=info.frame, checked=info.checked, dense=info.dense,
+                    fallback=info.fallback, psnr_db=info.psnr_db)
+
+    def close(self):
+        if self.handle:
+            _lib.fv_renderer_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

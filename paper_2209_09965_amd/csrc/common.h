@@ -39,6 +39,13 @@ template <> struct Voxel<FV_F32> {
 
 inline size_t dtype_bytes(fv_dtype d) { return d == FV_U8 ? 1 : d == FV_F16 ? 2 : 4; }
 
+// Pull-push reconstruction (pullpush.hip), also reached through
+// fv_reconstruct with FV_RECON_PULLPUSH.
+size_t pullpush_workspace_bytes(int views, int W, int H);
+fv_status pullpush_run(const float* frame_rgba, const uint8_t* mask, int views, int W, int H,
+                       float* out_rgb, void* workspace, size_t ws_bytes, hipStream_t s,
+                       const char* fn);
+
 }  // namespace fv
 
 // Library-owned volume copy.  Storage: the scalar grid with a 2-voxel apron

@@ -821,7 +821,10 @@ fv_status fv_net_set_params(fv_net* n, const float* host_params, size_t n_params
 fv_status fv_reconstruct_workspace(const fv_net* n, int precision, int views, int width,
                                    int height, size_t* bytes) {
   clear_error();
-  if (!n || !bytes) return fail(FV_ERR_INVALID_ARG, "fv_reconstruct_workspace: null pointer");
+  if (!bytes) return fail(FV_ERR_INVALID_ARG, "fv_reconstruct_workspace: null pointer");
+  if (precision == FV_RECON_PULLPUSH)
+    return fv_pullpush_workspace(views, width, height, bytes);
+  if (!n) return fail(FV_ERR_INVALID_ARG, "fv_reconstruct_workspace: null network");
   if (precision != FV_PREC_BF16 && precision != FV_PREC_FP8)
     return fail(FV_ERR_UNSUPPORTED, "fv_reconstruct_workspace: precision %d", precision);
   fv_status st = check_frame(views, width, height, "fv_reconstruct_workspace");
@@ -836,6 +839,12 @@ static fv_status reconstruct(const fv_net* n, int precision, const float* frame_
                              float* out_direct, void* workspace, size_t ws_bytes, void* stream,
                              const char* fn) {
   clear_error();
+  if (precision == FV_RECON_PULLPUSH) {
+    if (prev || out_direct)
+      return fail(FV_ERR_INVALID_ARG, "%s: pull-push has no direct prediction or feedback", fn);
+    return pullpush_run(frame_rgba, mask, views, width, height, out_rgb, workspace, ws_bytes,
+                        (hipStream_t)stream, fn);
+  }
   if (!n || !frame_rgba || !mask || !out_rgb || !workspace)
     return fail(FV_ERR_INVALID_ARG, "%s: null pointer", fn);
   if (prev && !n->recurrent)

@@ -270,3 +270,55 @@ def test_checkpoint_and_state_host_errors():
     assert load(_blob(payload=False)) == -1             # header only
     hdr = open(os.path.join(ROOT, "include", "fovol.h")).read()
     assert "#define FV_NET_FP8_TENSORS 15" in hdr and b.FP8_TENSORS == 15
+
+
+def test_pullpush_host_errors():
+    """Pull-push rejects bad sizes, null pointers and a short workspace on the
+    host; fv_reconstruct's pull-push route needs no network handle but takes
+    no direct-prediction output."""
+    from paper_2209_09965_amd import binding as b
+    L = b.lib()
+    fake = ctypes.c_void_p(0x1000)
+    need = b.pullpush_workspace(1, 16, 16)
+    assert need > 0 and need % 256 == 0
+    assert b.pullpush_workspace(1, 1, 1) >= 256
+    assert L.fv_reconstruct_pullpush(fake, fake, 1, 0, 16, fake, fake, need, None) == -1
+    assert L.fv_reconstruct_pullpush(None, fake, 1, 16, 16, fake, fake, need, None) == -1
+    assert L.fv_reconstruct_pullpush(fake, fake, 1, 16, 16, fake, fake, need - 1, None) == -2
+    assert "workspace" in b.last_error()
+    assert L.fv_reconstruct_pullpush(fake, fake, 1, 16, 16, fake, ctypes.c_void_p(0x1001), need,
+                                     None) == -1
+    assert L.fv_reconstruct_pullpush(fake, fake, 2, 65535, 65535, fake, fake, 1 << 40,
+                                     None) == -1
+    n = ctypes.c_size_t()
+    assert L.fv_reconstruct_workspace(None, b.FV_RECON_PULLPUSH, 1, 16, 16, ctypes.byref(n)) == 0
+    assert n.value == need
+    assert L.fv_reconstruct_workspace(None, b.FV_PREC_BF16, 1, 16, 16, ctypes.byref(n)) == -1
+    assert L.fv_reconstruct(None, b.FV_RECON_PULLPUSH, fake, fake, None, 1, 16, 16, fake, fake,
+                            fake, need, None) == -1
+    assert "direct" in b.last_error()
+
+
+def test_renderer_host_errors():
+    """Renderer creation and frame calls reject bad sizes, policies and null
+    pointers on the host."""
+    from paper_2209_09965_amd import binding as b
+    L = b.lib()
+    h = ctypes.c_void_p()
+    pol = b.RenderPolicy(b.FV_PREC_FP8, 4, 30.0)
+    assert L.fv_renderer_create(1, 100, 64, ctypes.byref(pol), ctypes.byref(h)) == -1
+    assert L.fv_renderer_create(0, 64, 64, ctypes.byref(pol), ctypes.byref(h)) == -1
+    assert L.fv_renderer_create(9, 64, 64, ctypes.byref(pol), ctypes.byref(h)) == -1
+    assert L.fv_renderer_create(1, 64, 64, None, ctypes.byref(h)) == -1
+    bad = b.RenderPolicy(7, 4, 30.0)
+    assert L.fv_renderer_create(1, 64, 64, ctypes.byref(bad), ctypes.byref(h)) == -3
+    bad = b.RenderPolicy(b.FV_PREC_FP8, -1, 30.0)
+    assert L.fv_renderer_create(1, 64, 64, ctypes.byref(bad), ctypes.byref(h)) == -1
+    bad = b.RenderPolicy(b.FV_PREC_FP8, 1, float("nan"))
+    assert L.fv_renderer_create(1, 64, 64, ctypes.byref(bad), ctypes.byref(h)) == -1
+    info = b.FrameInfo()
+    assert L.fv_render_frame(None, None, None, 256, None, None, None, None, None,
+                             ctypes.byref(info), None) == -1
+    assert ctypes.sizeof(b.FrameInfo) == 24 and ctypes.sizeof(b.RenderPolicy) == 12
+    assert L.fv_renderer_destroy(None) == 0
+

@@ -1,0 +1,132 @@
+"""The foveated renderer with the dense march as judge and fallback
+(fv_render_frame), through the C ABI: with trained weights its output is the
+foveated pipeline's, bit for bit, and its PSNR the one the host computes from
+the same frames; with corrupted weights (or a threshold above what the
+reconstruction reaches) the check frame falls back to the dense frame, the
+frames until the next check stay dense, and a passing check ends the
+fallback."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import synthetic
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+W = H = 256
+
+
+def _scene(dev, k=7):
+    from paper_2209_09965_amd import binding as b
+    vol = b.Volume(torch.from_numpy(synthetic.blob_volume(1003, 64)).to(dev))
+    tf = torch.from_numpy(synthetic.tf_blob(1003)).reshape(-1).to(dev)
+    cams = [synthetic.orbit_camera(k)]
+    mp = synthetic.march_params(shading=False)
+    fp = synthetic.fovea_params(W, H, frame=k)
+    return vol, tf, cams, mp, fp
+
+
+def _theta():
+    return np.load(os.path.join(ROOT, "paper_2209_09965_amd", "weights", "recon.npy"))
+
+
+def _manual(b, dev, vol, tf, cams, mp, fp, net, prec):
+    """The same frame through the individual entry points."""
+    npx = W * H
+    ray_idx = torch.empty(npx, dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    mask = torch.empty(npx, dtype=torch.uint8, device=dev)
+    b.fovea_mask(fp, W, H, 1, ray_idx, count, mask=mask)
+    frame = torch.zeros(npx * 4, dtype=torch.float32, device=dev)
+    depth = torch.zeros(npx, dtype=torch.float32, device=dev)
+    b.raymarch_sparse(vol, tf, cams, W, H, mp, ray_idx, count, frame_rgba=frame,
+                      frame_depth=depth)
+    out = torch.empty(npx * 3, dtype=torch.float32, device=dev)
+    if prec == "pullpush":
+        b.reconstruct_pullpush(frame, mask, 1, W, H, out)
+    else:
+        net.reconstruct(frame, mask, depth, 1, W, H, out, precision=prec)
+    dense = torch.empty(npx * 4, dtype=torch.float32, device=dev)
+    b.raymarch_dense(vol, tf, cams, W, H, mp, dense)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), dense.cpu().numpy().reshape(-1, 4)[:, :3].reshape(-1)
+
+
+def _psnr(a, ref):
+    mse = np.mean((np.clip(a.astype(np.float64), 0, 1) - np.clip(ref.astype(np.float64), 0, 1)) ** 2)
+    return 10 * np.log10(1.0 / mse)
+
+
+def test_trained_network_passes_and_matches_pipeline(dev):
+    from paper_2209_09965_amd import binding as b
+    vol, tf, cams, mp, fp = _scene(dev)
+    net = b.Net(_theta())
+    r = b.Renderer(1, W, H, precision="bf16", check_every=2, min_psnr_db=30.0)
+    out = torch.full((W * H * 3,), float("nan"), dtype=torch.float32, device=dev)
+    info = r.render(vol, tf, cams, mp, fp, net, out)
+    torch.cuda.synchronize()
+    want, dense = _manual(b, dev, vol, tf, cams, mp, fp, net, "bf16")
+    got = out.cpu().numpy()
+    assert info["checked"] == 1 and info["dense"] == 0 and info["fallback"] == 0
+    assert np.array_equal(got, want)
+    assert abs(info["psnr_db"] - _psnr(want, dense)) < 1e-3
+    assert info["psnr_db"] >= 30.0
+    # the next frame is not a check frame: foveated, no score
+    info = r.render(vol, tf, cams, mp, fp, net, out)
+    assert info["frame"] == 1 and info["checked"] == 0 and info["dense"] == 0
+    assert np.isnan(info["psnr_db"])
+    r.close()
+    net.close()
+    vol.close()
+
+
+def test_corrupted_weights_fall_back_to_dense(dev):
+    from paper_2209_09965_amd import binding as b
+    vol, tf, cams, mp, fp = _scene(dev)
+    theta = _theta()
+    rng = np.random.default_rng(99)
+    bad = (theta + rng.normal(0.0, 0.5, theta.shape)).astype(np.float32)
+    net = b.Net(bad)
+    r = b.Renderer(1, W, H, precision="bf16", check_every=3, min_psnr_db=30.0)
+    out = torch.empty(W * H * 3, dtype=torch.float32, device=dev)
+    _, dense = _manual(b, dev, vol, tf, cams, mp, fp, net, "bf16")
+    info = r.render(vol, tf, cams, mp, fp, net, out)  # frame 0: a check, fails
+    torch.cuda.synchronize()
+    assert info["checked"] == 1 and info["psnr_db"] < 30.0
+    assert info["dense"] == 1 and info["fallback"] == 1
+    assert np.array_equal(out.cpu().numpy(), dense)
+    for f in (1, 2):  # between checks: dense frames, no score
+        out.fill_(float("nan"))
+        info = r.render(vol, tf, cams, mp, fp, net, out)
+        torch.cuda.synchronize()
+        assert info["frame"] == f and info["checked"] == 0 and info["dense"] == 1
+        assert np.array_equal(out.cpu().numpy(), dense)
+    net.set_params(theta)  # repaired: the next check passes and ends the fallback
+    info = r.render(vol, tf, cams, mp, fp, net, out)
+    torch.cuda.synchronize()
+    assert info["frame"] == 3 and info["checked"] == 1 and info["psnr_db"] >= 30.0
+    assert info["dense"] == 0 and info["fallback"] == 0
+    want, _ = _manual(b, dev, vol, tf, cams, mp, fp, net, "bf16")
+    assert np.array_equal(out.cpu().numpy(), want)
+    r.close()
+    net.close()
+    vol.close()
+
+
+@pytest.mark.parametrize("threshold,falls", [(99.0, True), (-1.0, False)])
+def test_pullpush_threshold(dev, threshold, falls):
+    from paper_2209_09965_amd import binding as b
+    vol, tf, cams, mp, fp = _scene(dev, k=21)
+    r = b.Renderer(1, W, H, precision="pullpush", check_every=1, min_psnr_db=threshold)
+    out = torch.empty(W * H * 3, dtype=torch.float32, device=dev)
+    info = r.render(vol, tf, cams, mp, fp, None, out)
+    torch.cuda.synchronize()
+    want, dense = _manual(b, dev, vol, tf, cams, mp, fp, None, "pullpush")
+    assert info["checked"] == 1 and info["dense"] == int(falls)
+    assert abs(info["psnr_db"] - _psnr(want, dense)) < 1e-3
+    assert np.array_equal(out.cpu().numpy(), dense if falls else want)
+    r.close()
+    vol.close()
