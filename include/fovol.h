@@ -447,6 +447,58 @@ fv_status fv_net_calibrate_recurrent(fv_net* n, const float* frame_rgba, const u
 #define FV_NET_FP8_TENSORS 15
 fv_status fv_net_fp8_scales(const fv_net* n, float* host_scales, int count);
 
+/* FP8 from scales calibrated elsewhere (offline, over many frames, or by a
+ * reference): host_scales in the order fv_net_fp8_scales returns them; the
+ * handle then quantises its weights exactly as fv_net_calibrate does after
+ * measuring them.  Synchronises `stream`.  Errors: null pointers, count !=
+ * FV_NET_FP8_TENSORS, a scale that is not finite and positive. */
+fv_status fv_net_set_fp8_scales(fv_net* n, const float* host_scales, int count, void* stream);
+
+/* Test hooks: the forward pass one step at a time (paper Sec. 3.2, the
+ * network's layers; Sec. 3.4, its reduced-precision storage), so that a test
+ * can hold each layer's kernel to a reference on inputs of the test's
+ * choosing.
+ *
+ * Activation tensors of a forward pass, in this order (index: name,
+ * channels, resolution level; level l is (H >> l) x (W >> l)):
+ *   0 packed input 8, 0    1 e0a 32, 0    2 e0b 32, 0    3 pool(e0b) 32, 1
+ *   4 e1a 48, 1            5 e1b 48, 1    6 pool(e1b) 48, 2
+ *   7 e2a 64, 2            8 e2b 64, 2    9 pool(e2b) 64, 3
+ *  10 e3a 96, 3           11 e3b 96, 3
+ *  12 d2a 64, 2  13 d2b 64, 2  14 d1a 48, 1  15 d1b 48, 1  16 d0a 32, 0
+ *  17 d0b 32, 0
+ * Each lives in the workspace of fv_reconstruct at a fixed byte offset as
+ * views x h x w x channels (channel fastest), one element per value in the
+ * precision's storage format: FP8 the E4M3 code q of the scheme above (the
+ * value is q times the tensor's scale; a pooled tensor has the scale of its
+ * source), BF16 the bfloat16 value.  An upsampled source is not stored: a
+ * decoder conv computes it from the lower level on the fly.
+ *
+ * fv_reconstruct_tensor: offset (bytes from the workspace start), channels
+ * and level of tensor `tensor` at this frame size and precision.  Errors:
+ * null pointers, tensor outside 0 .. 17, precision not BF16 / FP8, a frame
+ * size fv_reconstruct rejects. */
+#define FV_NET_TENSORS 18
+fv_status fv_reconstruct_tensor(int precision, int views, int width, int height, int tensor,
+                                size_t* offset, int* channels, int* level);
+
+/* fv_reconstruct (or fv_reconstruct_recurrent: prev_direct) restricted to
+ * steps first .. last of its forward pass: step l in 0 .. 13 is 3x3 conv l
+ * in canonical order (writing its output tensor, and for l = 1, 3, 5 also
+ * the pooled tensor after it), step 14 the heads (out_rgb, out_direct).
+ * Steps 0 and 1 run as one fused kernel that computes the packed input and
+ * e0a from the frame without storing them (tensors 0 and 1 are not
+ * written); a range that starts at 0 or 1 runs both.  A step reads its
+ * input tensors from the workspace as an earlier step (or the caller)
+ * left them.  frame_rgba and mask may be NULL when first >= 2, out_rgb when
+ * last < 14.  Errors: those of fv_reconstruct, first < 0, last > 14,
+ * first > last. */
+fv_status fv_reconstruct_steps(const fv_net* n, int precision, int first, int last,
+                               const float* frame_rgba, const uint8_t* mask,
+                               const float* frame_depth, const float* prev_direct, int views,
+                               int width, int height, float* out_rgb, float* out_direct,
+                               void* workspace, size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------------
  * 4b. Reconstruction without a network: pull-push
  * ------------------------------------------------------------------------

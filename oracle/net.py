@@ -503,79 +503,120 @@ def fp8_weights(w, in_scale, rnd=e4m3_round):
     return rnd(w1 / om[:, None, None, None]), om
 
 
+def fp8_conv(srcs, w, b, s_out, e4m3=e4m3_round):
+    """One 3x3 conv of the FP8 scheme (Sec. 3.4) on stored tensors.
+    srcs: list of (codes, scale) concatenated along channels; the weights are
+    quantised by fp8_weights over the scales of the input channels;
+        acc_o = sum_{c,t} Wq[o,c,t] q_c(p + t)
+        y_o   = acc_o omega_o / s_out + B_o / s_out
+        q_out = E4M3(min(max(y_o, 0), 448))      (ReLU and saturation)
+    Returns (q_out, y, S) with S = sum_{c,t} |Wq q| omega_o / s_out +
+    |B_o / s_out|, the magnitude a finite-precision evaluation of y rounds
+    against."""
+    codes = np.concatenate([q for q, _ in srcs], axis=1)
+    in_scale = np.concatenate([np.full(q.shape[1], sc) for q, sc in srcs])
+    wq, om = fp8_weights(w, in_scale, e4m3)
+    z = np.zeros(w.shape[0])
+    al = (om / s_out)[None, :, None, None]
+    bi = (b / s_out)[None, :, None, None]
+    y = conv2d(codes, wq, z) * al + bi
+    S = conv2d(np.abs(codes), np.abs(wq), z) * al + np.abs(bi)
+    return e4m3(np.clip(y, 0.0, E4M3_MAX)), y, S
+
+
 def forward_fp8(theta, x, scales, e4m3=e4m3_round, head_round=bf16_round,
-                first_bf16=None, bf16=bf16_round):
+                first_bf16=None, bf16=bf16_round, record=None):
     """The network as the library's FP8 inference computes it (Sec. 3.4):
     every stored tensor t is an E4M3 code q with value q s_t (s_t from
-    calibrate_fp8).  Per 3x3 conv (weights from fp8_weights over the scales
-    of its input channels, output scale s_out):
-        acc_o = sum_{c,t} Wq[o,c,t] q_c(p + t)          (FP32 accumulation)
-        q_out = E4M3(min(max(acc_o omega_o / s_out + B_o / s_out, 0), 448))
-    i.e. ReLU and saturation at the largest E4M3 value.  A pooled tensor is
-    E4M3 of the mean of the four codes, an upsampled one E4M3 of the bilinear
-    blend of the codes (both keep their source's scale).  The heads read the
-    codes of the last decoder tensor with weights BF16(W s_d0b) and FP32 bias;
-    softmax and the 5x5 kernel application are exact.
+    calibrate_fp8).  Each 3x3 conv is fp8_conv over its input tensors (the
+    upsampled one first).  A pooled tensor is E4M3 of the mean of the four
+    codes, an upsampled one E4M3 of the bilinear blend of the codes (both
+    keep their source's scale).  The heads read the codes of the last decoder
+    tensor with weights BF16(W s_d0b) and FP32 bias; softmax and the 5x5
+    kernel application are exact.
 
     The recurrent form (8 input channels) computes its first conv in BF16
     (first_bf16 defaults to True for it): input and weights rounded to BF16,
     q_out = E4M3(min(max(acc / s_out + B / s_out, 0), 448)).
 
     With e4m3, head_round and bf16 all the identity this is the FP64 network
-    (forward()) exactly, whatever the scales.  Returns (out, O_d)."""
+    (forward()) exactly, whatever the scales.  Returns (out, O_d).
+
+    record, if a dict, receives every stored tensor's codes: "x" (the input),
+    each conv's name -> (q, y, S) as fp8_conv returns them, "p0" .. "p2"
+    (pooled), "u3", "u2", "u1" (upsampled sources of d2a, d1a, d0a), and for
+    the heads "od" -> (O_d, S_od), "logits" -> (logits, S_logits) with S the
+    sums of the terms' magnitudes."""
     P = unflatten(np.asarray(theta, np.float64))
     if x.shape[1] != P["e0a"][0].shape[1]:
         raise ValueError("input has %d channels, the network reads %d"
                          % (x.shape[1], P["e0a"][0].shape[1]))
     if first_bf16 is None:
         first_bf16 = x.shape[1] == 8
+    rec = record if record is not None else {}
 
-    def store(v, s):
-        return e4m3(np.clip(v / s, -E4M3_MAX, E4M3_MAX))
-
-    def conv(name, srcs, relu_out=True):
-        """srcs: list of (codes, scale) concatenated along channels."""
+    def conv(name, srcs):
         w, b = P[name]
-        codes = np.concatenate([q for q, _ in srcs], axis=1)
-        in_scale = np.concatenate([np.full(q.shape[1], s) for q, s in srcs])
-        wq, om = fp8_weights(w, in_scale, e4m3)
-        s_out = scales[name]
-        acc = conv2d(codes, wq, np.zeros(w.shape[0]))
-        y = acc * (om / s_out)[None, :, None, None] + (b / s_out)[None, :, None, None]
-        return e4m3(np.clip(y, 0.0, E4M3_MAX))
+        q, y, S = fp8_conv(srcs, w, b, scales[name], e4m3)
+        rec[name] = (q, y, S)
+        return q, scales[name]
 
     if first_bf16:
         w, b = P["e0a"]
-        acc = conv2d(bf16(x), bf16(w), np.zeros(w.shape[0]))
+        xb, wb = bf16(x), bf16(w)
+        z = np.zeros(w.shape[0])
         s_out = scales["e0a"]
-        q = e4m3(np.clip(acc / s_out + (b / s_out)[None, :, None, None], 0.0, E4M3_MAX))
+        y = conv2d(xb, wb, z) / s_out + (b / s_out)[None, :, None, None]
+        S = conv2d(np.abs(xb), np.abs(wb), z) / s_out + np.abs(b / s_out)[None, :, None, None]
+        q = e4m3(np.clip(y, 0.0, E4M3_MAX))
+        rec["x"] = xb
+        rec["e0a"] = (q, y, S)
         e0a = (q, s_out)
     else:
-        qx = (store(x, scales["x"]), scales["x"])
-        e0a = (conv("e0a", [qx]), scales["e0a"])
+        qx = e4m3(np.clip(x / scales["x"], -E4M3_MAX, E4M3_MAX))
+        rec["x"] = qx
+        e0a = conv("e0a", [(qx, scales["x"])])
 
-    def sc(name, q):
-        return (q, scales[name])
+    def pool(name, t):
+        q = e4m3(avgpool2(t[0]))
+        rec[name] = q
+        return q, t[1]
 
-    e0b = sc("e0b", conv("e0b", [e0a]))
-    p0 = (e4m3(avgpool2(e0b[0])), e0b[1])
-    e1a = sc("e1a", conv("e1a", [p0]))
-    e1b = sc("e1b", conv("e1b", [e1a]))
-    p1 = (e4m3(avgpool2(e1b[0])), e1b[1])
-    e2a = sc("e2a", conv("e2a", [p1]))
-    e2b = sc("e2b", conv("e2b", [e2a]))
-    p2 = (e4m3(avgpool2(e2b[0])), e2b[1])
-    e3a = sc("e3a", conv("e3a", [p2]))
-    e3b = sc("e3b", conv("e3b", [e3a]))
-    d2a = sc("d2a", conv("d2a", [(e4m3(upsample2(e3b[0])), e3b[1]), e2b]))
-    d2b = sc("d2b", conv("d2b", [d2a]))
-    d1a = sc("d1a", conv("d1a", [(e4m3(upsample2(d2b[0])), d2b[1]), e1b]))
-    d1b = sc("d1b", conv("d1b", [d1a]))
-    d0a = sc("d0a", conv("d0a", [(e4m3(upsample2(d1b[0])), d1b[1]), e0b]))
-    d0b = sc("d0b", conv("d0b", [d0a]))
-    q, s = d0b
-    wd, bd = P["hd"]
-    wk, bk = P["hk"]
-    od = conv2d(q, head_round(wd * s), bd)
-    logits = conv2d(q, head_round(wk * s), bk)
+    def up(name, t):
+        q = e4m3(upsample2(t[0]))
+        rec[name] = q
+        return q, t[1]
+
+    e0b = conv("e0b", [e0a])
+    e1a = conv("e1a", [pool("p0", e0b)])
+    e1b = conv("e1b", [e1a])
+    e2a = conv("e2a", [pool("p1", e1b)])
+    e2b = conv("e2b", [e2a])
+    e3a = conv("e3a", [pool("p2", e2b)])
+    e3b = conv("e3b", [e3a])
+    d2a = conv("d2a", [up("u3", e3b), e2b])
+    d2b = conv("d2b", [d2a])
+    d1a = conv("d1a", [up("u2", d2b), e1b])
+    d1b = conv("d1b", [d1a])
+    d0a = conv("d0a", [up("u1", d1b), e0b])
+    q, s = conv("d0b", [d0a])
+    od, logits = fp8_heads(theta, q, s, head_round, rec)
     return kpn_apply(softmax_c(logits), od), od
+
+
+def fp8_heads(theta, q, s, head_round=bf16_round, record=None):
+    """The heads of the FP8 network on the codes q (scale s) of the last
+    decoder tensor: O_d and the kernel logits, 1x1 convs with weights
+    head_round(W s) and the FP32 biases.  Returns (O_d, logits); record, if a
+    dict, receives "od" -> (O_d, S_od) and "logits" -> (logits, S_logits), S
+    the sums of the terms' magnitudes."""
+    P = unflatten(np.asarray(theta, np.float64))
+    out = []
+    for name, key in (("hd", "od"), ("hk", "logits")):
+        w, b = P[name]
+        wr = head_round(w * s)
+        v = conv2d(q, wr, b)
+        if record is not None:
+            record[key] = (v, conv2d(np.abs(q), np.abs(wr), np.abs(b)))
+        out.append(v)
+    return out[0], out[1]

@@ -115,6 +115,11 @@ _SIGS = {
     "fv_train_step": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, ctypes.c_float, _vp, _vp, _sz,
                            _vp]),
     "fv_net_fp8_scales": (_i, [_vp, _vp, _i]),
+    "fv_net_set_fp8_scales": (_i, [_vp, _vp, _i, _vp]),
+    "fv_reconstruct_tensor": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(_sz),
+                                   ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "fv_reconstruct_steps": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp,
+                                  _vp, _sz, _vp]),
     "fv_net_set_grad": (_i, [_vp, _vp, _sz, _vp]),
     "fv_pullpush_workspace": (_i, [_i, _i, _i, ctypes.POINTER(_sz)]),
     "fv_reconstruct_pullpush": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp, _sz, _vp]),
@@ -395,6 +400,17 @@ FV_PREC_FP8 = 2
 FV_RECON_PULLPUSH = 3
 PRECISIONS = {"bf16": FV_PREC_BF16, "fp8": FV_PREC_FP8, "pullpush": FV_RECON_PULLPUSH}
 FP8_TENSORS = 15  # FV_NET_FP8_TENSORS: the input and the 14 conv outputs
+NET_TENSORS = 18  # FV_NET_TENSORS: activation tensors of a forward pass
+NET_STEPS = 15    # steps of a forward pass: the 14 convs and the heads
+
+
+def reconstruct_tensor(precision, views, width, height, tensor):
+    """(byte offset, channels, level) of activation tensor `tensor` in the
+    workspace of a forward pass at this size and precision."""
+    off, ch, lv = _sz(), ctypes.c_int(), ctypes.c_int()
+    check(_lib.fv_reconstruct_tensor(_prec(precision), views, width, height, tensor,
+                                     ctypes.byref(off), ctypes.byref(ch), ctypes.byref(lv)))
+    return off.value, ch.value, lv.value
 
 
 def _prec(p):
@@ -448,6 +464,16 @@ class Net:
         out = np.zeros(FP8_TENSORS, dtype=np.float32)
         check(_lib.fv_net_fp8_scales(self.handle, ctypes.c_void_p(out.ctypes.data), out.size))
         return out
+
+    def set_fp8_scales(self, scales, stream=None):
+        """FP8 from given activation scales (FP8_TENSORS values, the order of
+        fp8_scales()) instead of a calibration pass."""
+        import numpy as np
+        arr = np.ascontiguousarray(scales, dtype=np.float32)
+        if arr.shape != (FP8_TENSORS,):
+            raise ValueError("scales: %d values expected" % FP8_TENSORS)
+        check(_lib.fv_net_set_fp8_scales(self.handle, ctypes.c_void_p(arr.ctypes.data), arr.size,
+                                         _stream(stream)))
 
     def set_grad(self, grad, stream=None):
         """Replace the handle's gradient with a device float32 vector (external layout)."""
@@ -513,6 +539,23 @@ class Net:
                                             _dev(out_rgb, "out_rgb", F32, npx * 3),
                                             _dev(out_direct, "out_direct", F32, npx * 3, False),
                                             wp, wb, _stream(stream)))
+
+    def reconstruct_steps(self, first, last, views, width, height, workspace, frame_rgba=None,
+                          mask=None, frame_depth=None, prev_direct=None, out_rgb=None,
+                          out_direct=None, precision="fp8", stream=None):
+        """Steps first .. last of the forward pass (0-13 the convs, 14 the
+        heads) on the tensors in `workspace` (see reconstruct_tensor)."""
+        npx = views * width * height
+        wp, wb = _ws(workspace)
+        need_frame = first <= 1
+        check(_lib.fv_reconstruct_steps(
+            self.handle, _prec(precision), first, last,
+            _dev(frame_rgba, "frame_rgba", F32, npx * 4, need_frame),
+            _dev(mask, "mask", U8, npx, need_frame),
+            _dev(frame_depth, "frame_depth", F32, npx, False),
+            _dev(prev_direct, "prev_direct", F32, npx * 3, False), views, width, height,
+            _dev(out_rgb, "out_rgb", F32, npx * 3, last >= NET_STEPS - 1),
+            _dev(out_direct, "out_direct", F32, npx * 3, False), wp, wb, _stream(stream)))
 
     def calibrate_recurrent(self, frame_rgba, mask, frame_depth, prev_direct, views, width,
                             height, workspace=None, stream=None):

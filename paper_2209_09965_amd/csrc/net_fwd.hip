@@ -2,6 +2,7 @@
 // fv_reconstruct (paper: "Reconstruction Network", "Model Precision &
 // Optimization").
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -516,24 +517,26 @@ fv_status refresh_bf16(fv_net* n, hipStream_t s) {
 }
 
 // Runs the forward pass; prec 1 = BF16, 2 = FP8.  With absmax != nullptr the
-// BF16 pass records per-tensor maxima (calibration).
+// BF16 pass records per-tensor maxima (calibration).  Steps first .. last
+// only (0 .. 13 the 3x3 convs, 14 the heads; the packed input is part of
+// step 0): a later step reads the tensors an earlier one left in ws.
 template <class E>
 fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const float* frame,
                        const uint8_t* mask, const float* depth, const float* prev,
                        float* out_rgb, float* out_od, float* out_wk, float* absmax,
-                       hipStream_t s, bool fuse_first) {
+                       hipStream_t s, bool fuse_first, int first, int last) {
   const bool fp8 = E::kBytes == 1;
   const int64_t npx = (int64_t)p.n * p.h * p.w;
   const float in_inv = fp8 ? 1.0f / net->act_scale[T_IN] : 1.0f;
   fv_status st = FV_OK;
-  if (!fuse_first) {
+  if (!fuse_first && first == 0) {
     k_pack<E><<<(unsigned)((npx + 255) / 256), 256, 0, s>>>(
         (const float4*)frame, mask, depth, prev, ws + p.t[T_IN], npx, in_inv,
         absmax ? absmax + T_IN : nullptr);
     st = launch_status("pack");
     if (st != FV_OK) return st;
   }
-  for (int l = 0; l < kNumConv; ++l) {
+  for (int l = first; l < kNumConv && l <= last; ++l) {
     // the packed input and the first conv are computed inside the second
     // conv's blocks (their tensors are not written)
     if (fuse_first && l == 0) continue;
@@ -591,6 +594,7 @@ fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const floa
     st = launch_conv<E>(a, nblocks_of(L.co), s);
     if (st != FV_OK) return st;
   }
+  if (last < kNumConv) return FV_OK;
   dim3 grid((p.w + 15) / 16, (p.h + 15) / 16, p.n);
   k_heads<E><<<grid, 256, 0, s>>>(ws + p.t[T_D0B], p.n, p.h, p.w, net->master,
                                   (const __bf16*)(fp8 ? net->w_heads_fp8 : net->w_heads),
@@ -600,14 +604,30 @@ fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const floa
 
 template fv_status forward_impl<BF16>(const fv_net*, const Plan&, uint8_t*, const float*,
                                       const uint8_t*, const float*, const float*, float*, float*,
-                                      float*, float*, hipStream_t, bool);
+                                      float*, float*, hipStream_t, bool, int, int);
 template fv_status forward_impl<FP8>(const fv_net*, const Plan&, uint8_t*, const float*,
                                      const uint8_t*, const float*, const float*, float*, float*,
-                                     float*, float*, hipStream_t, bool);
+                                     float*, float*, hipStream_t, bool, int, int);
+
+// Nearest E4M3 value of v (ties to even, saturated at +-448), in double:
+// 3 mantissa bits, so the spacing in [2^(e-1), 2^e) is 2^(e-4), and 2^-9
+// below 2^-6 (subnormals).
+static double e4m3_nearest(double v) {
+  const double a = std::fabs(v);
+  if (a >= 448.0) return std::copysign(448.0, v);
+  int e = 0;
+  (void)std::frexp(a, &e);
+  const int se = std::max(e - 4, -9);
+  const double q = std::ldexp(std::nearbyint(std::ldexp(a, -se)), se);
+  return std::copysign(std::min(q, 448.0), v);
+}
 
 // FP8 weights: fold the per-input-channel activation scales into the
 // weights, quantise per output channel (E4M3, |q| <= 448), and fold the
-// output scale into alpha and bias.
+// output scale into alpha and bias.  The quantisation runs in double on the
+// host (W s_in is exact there, one rounding for the division), so every
+// code is the nearest E4M3 value of W' / omega; the device conversion of
+// these exact values is exact.
 fv_status build_fp8(fv_net* n, hipStream_t s) {
   const int64_t P = param_count();
   std::vector<float> host((size_t)P);
@@ -624,15 +644,17 @@ fv_status build_fp8(fv_net* n, hipStream_t s) {
     auto in_scale = [&](int ci) {
       return n->act_scale[ci < L.c0 ? io[0] : io[1]];
     };
-    std::vector<float> wscale(L.co), alpha(L.co), bias(L.co);
+    std::vector<double> wscale(L.co);
+    std::vector<float> alpha(L.co), bias(L.co);
     for (int co = 0; co < L.co; ++co) {
-      float m = 0.f;
+      double m = 0.0;
       for (int ci = 0; ci < L.ci; ++ci)
         for (int t = 0; t < 9; ++t)
-          m = std::max(m, std::fabs(W[((int64_t)co * L.ci + ci) * 9 + t] * in_scale(ci)));
-      wscale[co] = m > 0.f ? m / 448.0f : 1.0f;
-      alpha[co] = wscale[co] / s_out;
-      bias[co] = B[co] / s_out;
+          m = std::max(m, std::fabs((double)W[((int64_t)co * L.ci + ci) * 9 + t] *
+                                    (double)in_scale(ci)));
+      wscale[co] = m > 0.0 ? m / 448.0 : 1.0;
+      alpha[co] = (float)(wscale[co] / (double)s_out);
+      bias[co] = (float)((double)B[co] / (double)s_out);
     }
     // fragments [chunk][n block][64 lanes][32 bytes]: lane ln holds output
     // channel 16 nb + ln % 16 at K positions 128 c + 32 (ln / 16) + j
@@ -646,7 +668,8 @@ fv_status build_fp8(fv_net* n, hipStream_t s) {
       const int tap = kk / cip, ci = kk - tap * cip;
       const int co = nbi * 16 + (ln & 15);
       if (tap < 9 && ci < L.ci && co < L.co)
-        sw[e] = W[((int64_t)co * L.ci + ci) * 9 + tap] * in_scale(ci) / wscale[co];
+        sw[e] = (float)e4m3_nearest((double)W[((int64_t)co * L.ci + ci) * 9 + tap] *
+                                    (double)in_scale(ci) / wscale[co]);
     }
     float* tmp = nullptr;
     if (hipMalloc(&tmp, sw.size() * sizeof(float)) != hipSuccess)
@@ -837,7 +860,7 @@ static fv_status reconstruct(const fv_net* n, int precision, const float* frame_
                              const uint8_t* mask, const float* frame_depth, const float* prev,
                              int views, int width, int height, float* out_rgb,
                              float* out_direct, void* workspace, size_t ws_bytes, void* stream,
-                             const char* fn) {
+                             const char* fn, int first = 0, int last = kNumConv) {
   clear_error();
   if (precision == FV_RECON_PULLPUSH) {
     if (prev || out_direct)
@@ -845,7 +868,12 @@ static fv_status reconstruct(const fv_net* n, int precision, const float* frame_
     return pullpush_run(frame_rgba, mask, views, width, height, out_rgb, workspace, ws_bytes,
                         (hipStream_t)stream, fn);
   }
-  if (!n || !frame_rgba || !mask || !out_rgb || !workspace)
+  if (first < 0 || last > kNumConv || first > last)
+    return fail(FV_ERR_INVALID_ARG, "%s: steps %d .. %d (0 .. %d)", fn, first, last, kNumConv);
+  // the frame is read by the first two steps (the fused first layer), the
+  // output is written by the last one (the heads)
+  const bool need_frame = first <= 1, need_out = last == kNumConv;
+  if (!n || !workspace || (need_frame && (!frame_rgba || !mask)) || (need_out && !out_rgb))
     return fail(FV_ERR_INVALID_ARG, "%s: null pointer", fn);
   if (prev && !n->recurrent)
     return fail(FV_ERR_INVALID_ARG, "%s: the network has no recurrent input", fn);
@@ -863,9 +891,9 @@ static fv_status reconstruct(const fv_net* n, int precision, const float* frame_
   hipStream_t s = (hipStream_t)stream;
   if (precision == FV_PREC_FP8)
     return forward_impl<FP8>(n, p, (uint8_t*)workspace, frame_rgba, mask, frame_depth, prev,
-                             out_rgb, out_direct, nullptr, nullptr, s, true);
+                             out_rgb, out_direct, nullptr, nullptr, s, true, first, last);
   return forward_impl<BF16>(n, p, (uint8_t*)workspace, frame_rgba, mask, frame_depth, prev,
-                            out_rgb, out_direct, nullptr, nullptr, s, true);
+                            out_rgb, out_direct, nullptr, nullptr, s, true, first, last);
 }
 
 fv_status fv_reconstruct(const fv_net* n, int precision, const float* frame_rgba,
@@ -874,6 +902,35 @@ fv_status fv_reconstruct(const fv_net* n, int precision, const float* frame_rgba
                          size_t ws_bytes, void* stream) {
   return reconstruct(n, precision, frame_rgba, mask, frame_depth, nullptr, views, width, height,
                      out_rgb, out_direct, workspace, ws_bytes, stream, "fv_reconstruct");
+}
+
+fv_status fv_reconstruct_steps(const fv_net* n, int precision, int first, int last,
+                               const float* frame_rgba, const uint8_t* mask,
+                               const float* frame_depth, const float* prev_direct, int views,
+                               int width, int height, float* out_rgb, float* out_direct,
+                               void* workspace, size_t ws_bytes, void* stream) {
+  return reconstruct(n, precision, frame_rgba, mask, frame_depth, prev_direct, views, width,
+                     height, out_rgb, out_direct, workspace, ws_bytes, stream,
+                     "fv_reconstruct_steps", first, last);
+}
+
+fv_status fv_reconstruct_tensor(int precision, int views, int width, int height, int tensor,
+                                size_t* offset, int* channels, int* level) {
+  clear_error();
+  if (!offset || !channels || !level)
+    return fail(FV_ERR_INVALID_ARG, "fv_reconstruct_tensor: null pointer");
+  if (precision != FV_PREC_BF16 && precision != FV_PREC_FP8)
+    return fail(FV_ERR_UNSUPPORTED, "fv_reconstruct_tensor: precision %d", precision);
+  if (tensor < 0 || tensor >= kNumTensors)
+    return fail(FV_ERR_INVALID_ARG, "fv_reconstruct_tensor: tensor %d (0 .. %d)", tensor,
+                kNumTensors - 1);
+  fv_status st = check_frame(views, width, height, "fv_reconstruct_tensor");
+  if (st != FV_OK) return st;
+  const Plan p = make_plan(views, height, width, precision == FV_PREC_FP8 ? 1 : 2);
+  *offset = p.t[tensor];
+  *channels = kTensors[tensor].channels;
+  *level = kTensors[tensor].level;
+  return FV_OK;
 }
 
 fv_status fv_reconstruct_recurrent(const fv_net* n, int precision, const float* frame_rgba,
@@ -908,7 +965,7 @@ static fv_status calibrate(fv_net* n, const float* frame_rgba, const uint8_t* ma
   if ((st = launch_status("calibrate: clear")) != FV_OK) return st;
   float* tmp_rgb = (float*)(ws + p.od);  // the O_d slot is free in this pass
   st = forward_impl<BF16>(n, p, ws, frame_rgba, mask, frame_depth, prev, tmp_rgb, nullptr,
-                          nullptr, amax, s, false);
+                          nullptr, amax, s, false, 0, kNumConv);
   if (st != FV_OK) return st;
   float host[64];
   st = hip_status(hipMemcpyAsync(host, amax, sizeof host, hipMemcpyDeviceToHost, s),
@@ -920,6 +977,25 @@ static fv_status calibrate(fv_net* n, const float* frame_rgba, const uint8_t* ma
   n->act_scale[T_P1] = n->act_scale[T_E1B];
   n->act_scale[T_P2] = n->act_scale[T_E2B];
   return build_fp8(n, s);
+}
+
+fv_status fv_net_set_fp8_scales(fv_net* n, const float* host_scales, int count,
+                                void* stream) {
+  clear_error();
+  if (!n || !host_scales) return fail(FV_ERR_INVALID_ARG, "fv_net_set_fp8_scales: null pointer");
+  if (count != FV_NET_FP8_TENSORS)
+    return fail(FV_ERR_INVALID_ARG, "fv_net_set_fp8_scales: count %d, expected %d", count,
+                FV_NET_FP8_TENSORS);
+  for (int i = 0; i < count; ++i)
+    if (!(host_scales[i] > 0.f) || !std::isfinite(host_scales[i]))
+      return fail(FV_ERR_INVALID_ARG, "fv_net_set_fp8_scales: scale %d is %g", i,
+                  (double)host_scales[i]);
+  n->act_scale[T_IN] = host_scales[0];
+  for (int l = 0; l < kNumConv; ++l) n->act_scale[kLayerIO[l][2]] = host_scales[1 + l];
+  n->act_scale[T_P0] = n->act_scale[T_E0B];
+  n->act_scale[T_P1] = n->act_scale[T_E1B];
+  n->act_scale[T_P2] = n->act_scale[T_E2B];
+  return build_fp8(n, (hipStream_t)stream);
 }
 
 fv_status fv_net_calibrate(fv_net* n, const float* frame_rgba, const uint8_t* mask,

@@ -19,7 +19,7 @@ template <class E>
 fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const float* frame,
                        const uint8_t* mask, const float* depth, const float* prev,
                        float* out_rgb, float* out_od, float* out_wk, float* absmax,
-                       hipStream_t s, bool fuse_first);
+                       hipStream_t s, bool fuse_first, int first, int last);
 fv_status refresh_bf16(fv_net* n, hipStream_t s);
 fv_status check_frame(int views, int W, int H, const char* fn);
 
@@ -669,7 +669,7 @@ static fv_status forward_train(fv_net* n, const float* frame_rgba, const uint8_t
   uint8_t* ws = (uint8_t*)workspace;
   return forward_impl<BF16>(n, tp.f, ws, frame_rgba, mask, frame_depth, prev, out_rgb,
                             (float*)(ws + tp.f.od), (float*)(ws + tp.f.wk), nullptr,
-                            (hipStream_t)stream, false);
+                            (hipStream_t)stream, false, 0, kNumConv);
 }
 
 fv_status fv_net_forward_train(fv_net* n, const float* frame_rgba, const uint8_t* mask,
@@ -869,8 +869,10 @@ fv_status fv_net_adam(fv_net* n, float lr, float beta1, float beta2, float eps, 
     return fail(FV_ERR_INVALID_ARG, "fv_net_adam: bad hyper-parameters");
   hipStream_t s = (hipStream_t)stream;
   n->step += 1;
-  const float c1 = 1.0f - (float)std::pow((double)beta1, (double)n->step);
-  const float c2 = 1.0f - (float)std::pow((double)beta2, (double)n->step);
+  // bias corrections 1 - beta^t, formed in double: in FP32 the subtraction
+  // of a rounded beta^t close to 1 would lose most of the difference's bits
+  const float c1 = (float)(1.0 - std::pow((double)beta1, (double)n->step));
+  const float c2 = (float)(1.0 - std::pow((double)beta2, (double)n->step));
   const int64_t P = param_count();
   k_adam<<<nblk(P), 256, 0, s>>>(n->master, n->adam_m, n->adam_v, n->grad, P, lr, beta1, beta2,
                                  eps, c1, c2);

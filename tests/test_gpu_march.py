@@ -335,13 +335,22 @@ def test_masked_degenerate_masks(fill, dev):
 
 
 def test_masked_null_mask_rejected(dev):
+    """A null mask is refused twice over: by the binding's host-side argument
+    check, and (called through the C ABI directly) by the library itself,
+    before anything is enqueued."""
+    import ctypes
     from paper_2209_09965_amd import binding as b
     vol = b.Volume(torch.zeros((8, 8, 8), dtype=torch.uint8, device=dev))
     frame = torch.zeros(8 * 8 * 4, dtype=torch.float32, device=dev)
     tf_t = _tf_t(synthetic.tf_blob(1), dev)
-    with pytest.raises(b.FvError, match="null mask"):
-        b.raymarch_masked(vol, tf_t, [synthetic.orbit_camera(0)], 8, 8, synthetic.march_params(),
-                          None, frame)
+    cams = [synthetic.orbit_camera(0)]
+    with pytest.raises(ValueError, match="mask is required"):
+        b.raymarch_masked(vol, tf_t, cams, 8, 8, synthetic.march_params(), None, frame)
+    mp = b.march_params(synthetic.march_params())
+    st = b._lib.fv_raymarch_masked(vol.handle, ctypes.c_void_p(tf_t.data_ptr()), 256,
+                                   b._cams(cams), 1, 8, 8, ctypes.byref(mp), None,
+                                   ctypes.c_void_p(frame.data_ptr()), None, None, None)
+    assert st == -1 and "null mask" in b.last_error()
     vol.close()
 
 
