@@ -134,6 +134,24 @@ fv_status fv_fovea_mask(const fv_fovea_params* p, int width, int height,
                         uint32_t capacity, uint32_t* count, void* workspace,
                         size_t ws_bytes, void* stream);
 
+/* fv_fovea_mask without a workspace and without any device allocation, for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Outputs, arguments and errors are
+ * those of fv_fovea_mask minus the workspace.  The scan's block counts and
+ * the threshold table live in one library array per device, held until the
+ * process ends: FV_LUT_MAX + 2 * FV_MASK_NOALLOC_MAX_BLOCKS 32-bit words
+ * (320 KiB).  A frame stack of more than FV_MASK_NOALLOC_MAX_BLOCKS blocks
+ * (a block = 16 tiles of 8 x 8 pixels of one view, so about 33.5 million
+ * pixels) is refused with FV_ERR_CAPACITY.  The table is uploaded into the
+ * array, on `stream`, when its parameters (sigma_px, p_floor, mode, W, H)
+ * differ from the previous call's on the device.  Every call on a device
+ * shares that array: calls that overlap on one device (other streams, other
+ * host threads) race and must be ordered by the caller. */
+#define FV_MASK_NOALLOC_MAX_BLOCKS 32768
+fv_status fv_fovea_mask_noalloc(const fv_fovea_params* p, int width, int height,
+                                int views, uint8_t* mask, uint32_t* ray_idx,
+                                uint32_t capacity, uint32_t* count, void* stream);
+
 /* Sample map from a stack of noise tiles (paper Sec. 3.1.1: tileable noise
  * textures, a different tile each frame, looping over the stack) in place of
  * the seeded hash: pixel (x, y) of view v in frame f draws

@@ -78,6 +78,8 @@ _SIGS = {
     "fv_fovea_mask_workspace": (_i, [_i, _i, _i, ctypes.POINTER(_sz)]),
     "fv_fovea_mask": (_i, [ctypes.POINTER(FoveaParams), _i, _i, _i, _vp, _vp, _u32, _vp, _vp, _sz,
                            _vp]),
+    "fv_fovea_mask_noalloc": (_i, [ctypes.POINTER(FoveaParams), _i, _i, _i, _vp, _vp, _u32, _vp,
+                                   _vp]),
     "fv_fovea_mask_tiles": (_i, [ctypes.POINTER(FoveaParams), _vp, _i, _i, _i, _i, _i, _i, _vp,
                                  _vp, _u32, _vp, _vp, _sz, _vp]),
     "fv_volume_create": (_i, [_vp, _i, _i, _i, _i, _vp, ctypes.POINTER(_vp)]),
@@ -252,6 +254,16 @@ def fovea_mask(params, width, height, views, ray_idx, count, mask=None, workspac
     check(_lib.fv_fovea_mask(ctypes.byref(fovea_params(params)), width, height, views,
                              _dev(mask, "mask", U8, npx, False), pr, ray_idx.numel(),
                              _dev(count, "count", U32, 1), wp, wb, _stream(stream)))
+
+
+def fovea_mask_noalloc(params, width, height, views, ray_idx, count, mask=None, stream=None):
+    """fovea_mask without a workspace or any device allocation (the library's
+    per-device array; at most FV_MASK_NOALLOC_MAX_BLOCKS blocks)."""
+    npx = views * width * height
+    pr = _dev(ray_idx, "ray_idx", U32, 1)
+    check(_lib.fv_fovea_mask_noalloc(ctypes.byref(fovea_params(params)), width, height, views,
+                                     _dev(mask, "mask", U8, npx, False), pr, ray_idx.numel(),
+                                     _dev(count, "count", U32, 1), _stream(stream)))
 
 
 def fovea_mask_tiles(params, tiles, width, height, views, ray_idx, count, mask=None,

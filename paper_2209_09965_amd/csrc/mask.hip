@@ -275,6 +275,28 @@ int64_t num_blocks(int W, int H, int views) {
   return (tiles + kTilesPerBlock - 1) / kTilesPerBlock;
 }
 
+// ------------------------------------------- allocation-free variant's memory
+// fv_fovea_mask_noalloc keeps the threshold table and the per-block counts
+// and offsets of the scan in this array instead of library allocations and a
+// workspace: [table: FV_LUT_MAX words][counts: kNoAllocBlocks][offsets:
+// kNoAllocBlocks].  Each device holds its own copy for the life of the
+// process; host code reaches it only through the address hipGetSymbolAddress
+// returns on that device (the array's name is not a device address there).
+constexpr int64_t kNoAllocBlocks = FV_MASK_NOALLOC_MAX_BLOCKS;
+constexpr size_t kScratchWords = (size_t)FV_LUT_MAX + 2 * (size_t)kNoAllocBlocks;
+static __device__ __align__(256) uint32_t scratch[kScratchWords];
+
+struct NoAllocDevice {
+  uint32_t* ptr = nullptr;  // this device's scratch
+  bool has_table = false;   // which table the scratch holds
+  int mode = 0, W = 0, H = 0;
+  uint32_t sigma_bits = 0, pf_bits = 0;
+  Table table;              // its host copy (the source of the last upload)
+};
+std::mutex g_noalloc_mu;
+constexpr int kMaxDevices = 64;
+NoAllocDevice g_noalloc[kMaxDevices];
+
 }  // namespace
 }  // namespace fv
 
@@ -307,22 +329,37 @@ fv_status fv_fovea_mask_workspace(int width, int height, int views, size_t* byte
   return FV_OK;
 }
 
-static fv_status mask_entry(const char* fn, const fv_fovea_params* p, const uint32_t* tiles,
-                            int tile_w, int tile_h, int tile_count, int width, int height,
-                            int views, uint8_t* mask, uint32_t* ray_idx, uint32_t capacity,
-                            uint32_t* count, void* workspace, size_t ws_bytes, void* stream) {
-  fv::clear_error();
+static fv_status launch_mask(const fv_fovea_params* p, const uint32_t* tiles, int tile_w,
+                             int tile_h, int tile_count, int width, int height, int views,
+                             uint8_t* mask, uint32_t* ray_idx, uint32_t* count,
+                             const uint32_t* lut, int n, int shift, uint32_t t_inf,
+                             uint32_t* counts, uint32_t* offsets, hipStream_t s);
+
+// Host-side checks shared by the entry points (everything but the workspace).
+static fv_status check_mask_args(const char* fn, const fv_fovea_params* p, int width,
+                                 int height, int views, const uint32_t* ray_idx,
+                                 uint32_t capacity, const uint32_t* count) {
   fv_status st = fv::check_params(p, width, height, fn);
   if (st != FV_OK) return st;
   if (views <= 0) return fv::fail(FV_ERR_INVALID_ARG, "%s: views must be > 0", fn);
   const uint64_t total = (uint64_t)views * (uint64_t)width * (uint64_t)height;
   if (total >= (1ull << 32))
     return fv::fail(FV_ERR_INVALID_ARG, "%s: views*W*H must be < 2^32", fn);
-  if (!ray_idx || !count || !workspace)
-    return fv::fail(FV_ERR_INVALID_ARG, "%s: null ray_idx, count or workspace", fn);
+  if (!ray_idx || !count) return fv::fail(FV_ERR_INVALID_ARG, "%s: null ray_idx or count", fn);
   if ((uint64_t)capacity < total)
     return fv::fail(FV_ERR_CAPACITY, "%s: capacity %u < views*W*H = %llu", fn, capacity,
                     (unsigned long long)total);
+  return FV_OK;
+}
+
+static fv_status mask_entry(const char* fn, const fv_fovea_params* p, const uint32_t* tiles,
+                            int tile_w, int tile_h, int tile_count, int width, int height,
+                            int views, uint8_t* mask, uint32_t* ray_idx, uint32_t capacity,
+                            uint32_t* count, void* workspace, size_t ws_bytes, void* stream) {
+  fv::clear_error();
+  fv_status st = check_mask_args(fn, p, width, height, views, ray_idx, capacity, count);
+  if (st != FV_OK) return st;
+  if (!workspace) return fv::fail(FV_ERR_INVALID_ARG, "%s: null workspace", fn);
   size_t need = 0;
   fv_fovea_mask_workspace(width, height, views, &need);
   if (ws_bytes < need)
@@ -332,12 +369,26 @@ static fv_status mask_entry(const char* fn, const fv_fovea_params* p, const uint
   fv::CachedTable tab;
   st = fv::get_device_table(*p, width, height, &tab);
   if (st != FV_OK) return st;
+  const int64_t nb = fv::num_blocks(width, height, views);
+  uint32_t* counts = (uint32_t*)workspace;
+  return launch_mask(p, tiles, tile_w, tile_h, tile_count, width, height, views, mask, ray_idx,
+                     count, tab.dev_lut, tab.n, tab.shift, tab.t_inf, counts, counts + nb,
+                     (hipStream_t)stream);
+}
 
+// The three launches over a device table (lut, n, shift, t_inf) and the
+// scan's block counts / offsets (num_blocks words each).
+static fv_status launch_mask(const fv_fovea_params* p, const uint32_t* tiles, int tile_w,
+                             int tile_h, int tile_count, int width, int height, int views,
+                             uint8_t* mask, uint32_t* ray_idx, uint32_t* count,
+                             const uint32_t* lut, int n, int shift, uint32_t t_inf,
+                             uint32_t* counts, uint32_t* offsets, hipStream_t s) {
+  fv_status st;
   fv::MaskArgs a;
-  a.lut = tab.dev_lut;
-  a.n = tab.n;
-  a.shift = tab.shift;
-  a.t_inf = tab.t_inf;
+  a.lut = lut;
+  a.n = n;
+  a.shift = shift;
+  a.t_inf = t_inf;
   a.seed_lo = (uint32_t)(p->seed & 0xffffffffu);
   a.seed_hi = (uint32_t)(p->seed >> 32);
   a.frame = p->frame;
@@ -354,9 +405,6 @@ static fv_status mask_entry(const char* fn, const fv_fovea_params* p, const uint
   a.tcount = tile_count;
 
   const int64_t nb = fv::num_blocks(width, height, views);
-  uint32_t* counts = (uint32_t*)workspace;
-  uint32_t* offsets = counts + nb;
-  hipStream_t s = (hipStream_t)stream;
   fv::k_mask_count<<<(unsigned)nb, 256, 0, s>>>(a, counts);
   if ((st = fv::launch_status("count kernel")) != FV_OK) return st;
   fv::k_block_scan<<<1, 1024, 0, s>>>(counts, offsets, nb, count);
@@ -370,6 +418,62 @@ fv_status fv_fovea_mask(const fv_fovea_params* p, int width, int height, int vie
                         void* workspace, size_t ws_bytes, void* stream) {
   return mask_entry("fv_fovea_mask", p, nullptr, 0, 0, 0, width, height, views, mask, ray_idx,
                     capacity, count, workspace, ws_bytes, stream);
+}
+
+fv_status fv_fovea_mask_noalloc(const fv_fovea_params* p, int width, int height, int views,
+                                uint8_t* mask, uint32_t* ray_idx, uint32_t capacity,
+                                uint32_t* count, void* stream) {
+  const char* fn = "fv_fovea_mask_noalloc";
+  fv::clear_error();
+  fv_status st = check_mask_args(fn, p, width, height, views, ray_idx, capacity, count);
+  if (st != FV_OK) return st;
+  const int64_t nb = fv::num_blocks(width, height, views);
+  if (nb > fv::kNoAllocBlocks)
+    return fv::fail(FV_ERR_CAPACITY,
+                    "%s: %lld blocks of 16 8x8 tiles, at most %d without a workspace", fn,
+                    (long long)nb, (int)fv::kNoAllocBlocks);
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fv::fail(FV_ERR_DEVICE, "%s: hipGetDevice", fn);
+  if (dev < 0 || dev >= fv::kMaxDevices)
+    return fv::fail(FV_ERR_UNSUPPORTED, "%s: device %d", fn, dev);
+  std::lock_guard<std::mutex> lock(fv::g_noalloc_mu);
+  fv::NoAllocDevice& d = fv::g_noalloc[dev];
+  if (!d.ptr) {
+    // once per device, with that device current: the address of its copy
+    void* addr = nullptr;
+    st = fv::hip_status(hipGetSymbolAddress(&addr, HIP_SYMBOL(fv::scratch)),
+                        "fv_fovea_mask_noalloc: scratch address");
+    if (st != FV_OK) return st;
+    d.ptr = (uint32_t*)addr;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  // the table: uploaded into the scratch when the parameters it depends on
+  // change (ordered on the stream after earlier calls' kernels)
+  if (!d.has_table || d.mode != p->mode || d.W != width || d.H != height ||
+      d.sigma_bits != fv::bits_of(p->sigma_px) || d.pf_bits != fv::bits_of(p->p_floor)) {
+    fv::Table t;
+    if (!fv::build_table(*p, width, height, &t))
+      return fv::fail(FV_ERR_INVALID_ARG, "%s: no table fits", fn);
+    d.has_table = false;
+    d.table = std::move(t);
+    if (!d.table.lut.empty()) {
+      st = fv::hip_status(hipMemcpyAsync(d.ptr, d.table.lut.data(),
+                                         d.table.lut.size() * sizeof(uint32_t),
+                                         hipMemcpyHostToDevice, s),
+                          "fv_fovea_mask_noalloc: table upload");
+      if (st != FV_OK) return st;
+    }
+    d.has_table = true;
+    d.mode = p->mode;
+    d.W = width;
+    d.H = height;
+    d.sigma_bits = fv::bits_of(p->sigma_px);
+    d.pf_bits = fv::bits_of(p->p_floor);
+  }
+  uint32_t* counts = d.ptr + FV_LUT_MAX;
+  return launch_mask(p, nullptr, 0, 0, 0, width, height, views, mask, ray_idx, count, d.ptr,
+                     (int)d.table.lut.size(), d.table.shift, d.table.t_inf, counts,
+                     counts + fv::kNoAllocBlocks, s);
 }
 
 fv_status fv_fovea_mask_tiles(const fv_fovea_params* p, const uint32_t* tiles, int tile_w,
