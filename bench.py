@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 METRIC = "ms/frame foveated+recon vs dense march @1080p at PSNR>=30dB; ray-samples/s"
 HBM_PEAK_GBS = 8000.0
 REC_LEAD = 4  # frames a recurrent network runs before the measured sequence
+BIG_FRAME_PX = 4 << 20  # frame stacks beyond this: the CPU leg works on 1/16 subsets
 
 
 def parse():
@@ -72,19 +73,27 @@ def parse():
     return ap.parse_args()
 
 
-def make_inputs(wl):
+def make_inputs(wl, dev=None):
+    """(host volume, transfer function, device volume or None).  Volumes of
+    1024^3 are generated on the device (the same recipe, float32 blend) and
+    copied back for the oracle."""
     import numpy as np
     import synthetic
     kind, n = wl["volume"]
     seed = wl["seeds"][0]
+    vol_t = None
     if kind == "noise":
-        dt = np.float16 if n >= 1024 else np.float32
-        vol = synthetic.value_noise_volume(seed, n=n, base_period=64 * n // 256, dtype=dt)
+        if n >= 1024 and dev is not None:
+            vol_t = synthetic.value_noise_volume_device(seed, n, dev, base_period=64 * n // 256)
+            vol = vol_t.cpu().numpy()
+        else:
+            dt = np.float16 if n >= 1024 else np.float32
+            vol = synthetic.value_noise_volume(seed, n=n, base_period=64 * n // 256, dtype=dt)
         tf = synthetic.tf_noise(seed)
     else:
         vol = synthetic.blob_volume(seed, n)
         tf = synthetic.tf_blob(seed)
-    return vol, tf
+    return vol, tf, vol_t
 
 
 def copy_reference(nbytes):
@@ -121,7 +130,7 @@ def compression_sweep(args):
     W, H, V = wl["width"], wl["height"], wl["views"]
     if V != 1:
         sys.exit("the sweep runs single-view workloads")
-    vol, tf = make_inputs(wl)
+    vol, tf, _ = make_inputs(wl)
     mp = synthetic.march_params(shading=wl["shading"], shadow_step=args.shadow_step)
     vol_t = torch.from_numpy(vol).to(dev)
     volh = b.Volume(vol_t)
@@ -223,8 +232,11 @@ def main():
 
     dev = torch.device("cuda:0")
     wl = synthetic.WORKLOADS[args.workload]
+    if wl.get("training"):
+        training_step_bench(args, wl)
+        return
     W, H, V = wl["width"], wl["height"], wl["views"]
-    vol, tf = make_inputs(wl)
+    vol, tf, vol_dev = make_inputs(wl, dev)
     mp = synthetic.march_params(shading=wl["shading"], shadow_step=args.shadow_step)
     sig_frac = wl.get("sigma_frac", 0.15)
     eye_off = wl.get("eye_offset", 0.0)
@@ -239,9 +251,12 @@ def main():
     # the pipelined runs put frame k on stream k % 2, so frame k's
     # reconstruction can overlap frame k + 1's sample map and march
     streams = [torch.cuda.current_stream(), torch.cuda.Stream()]
-    vol_t = torch.from_numpy(vol).to(dev)
+    vol_t = vol_dev if vol_dev is not None else torch.from_numpy(vol).to(dev)
     volh = b.Volume(vol_t)
-    del vol_t
+    del vol_t, vol_dev
+    if wl.get("dense_only"):
+        dense_only_bench(args, wl, b, volh, tf, vol, mp, cams_for)
+        return
     tf_t = torch.from_numpy(tf).reshape(-1).to(dev)
     total = V * W * H
     net = b.Net(np.load(args.weights))
@@ -370,6 +385,7 @@ def main():
     sparse_ms = [e[1].elapsed_time(e[2]) for e in evs]
     recon_ms = [e[2].elapsed_time(e[3]) for e in evs]
     sparse_samples = int(scount.item())
+    fov_frame_ms = [e[0].elapsed_time(e[3]) for e in evs]
     last_k = args.warmup + args.steps - 1
     fov_out = bufs[0]["out_rgb"].view(-1, 3).clone()
     n_rays = int(bufs[0]["count"].item())
@@ -463,6 +479,10 @@ def main():
                    "reconstruction": "U-Net 32/48/64/96 + 5x5 KPN%s, %s" %
                                      (", recurrent O_d feedback" if net.recurrent else "",
                                       args.precision)},
+        "frame_ms_p50_p99": [round(nearest_rank(fov_frame_ms, 50), 4),
+                             round(nearest_rank(fov_frame_ms, 99), 4)],
+        "dense_frame_ms_p50_p99": [round(nearest_rank(dense_kernel_ms, 50), 4),
+                                   round(nearest_rank(dense_kernel_ms, 99), 4)],
         "dense_ms_per_frame": round(dense_ms, 4),
         "speedup_vs_dense": round(dense_ms / fov_ms, 3),
         "pipelined_ms_per_frame": round(fov_pipe_ms, 4),
@@ -492,6 +512,149 @@ def main():
                                            args.cpu_rays, np.load(args.weights), args.net_crop,
                                            fov_out.cpu().numpy(), dframe.view(-1, 4).cpu().numpy())
     volh.close()
+    net.close()
+    print(json.dumps(out), flush=True)
+
+
+def nearest_rank(values, pct):
+    """The pct-th percentile by nearest rank."""
+    v = sorted(values)
+    return v[max(0, min(len(v) - 1, int(math.ceil(pct / 100.0 * len(v))) - 1))]
+
+
+def dense_only_bench(args, wl, b, volh, tf, vol, mp, cams_for):
+    """The dense-march-only workload (64^3 u8 blobs at 256 x 256, no
+    shading): K timed frames of the orbit, HIP events per frame; the FP64
+    oracle marches the same frame on the host for the CPU baseline."""
+    import numpy as np
+    import torch
+
+    import oracle
+    dev = torch.device("cuda:0")
+    W, H, V = wl["width"], wl["height"], wl["views"]
+    tf_t = torch.from_numpy(tf).reshape(-1).to(dev)
+    total = V * W * H
+    frame = torch.zeros(total * 4, dtype=torch.float32, device=dev)
+    depth = torch.zeros(total, dtype=torch.float32, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int64, device=dev)
+    cams = [cams_for(k) for k in range(args.warmup + args.steps)]
+    for k in range(args.warmup):
+        b.raymarch_dense(volh, tf_t, cams[k], W, H, mp, frame, depth)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        evs[i][0].record()
+        b.raymarch_dense(volh, tf_t, cams[args.warmup + i], W, H, mp, frame, depth,
+                         sample_count=cnt)
+        evs[i][1].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms = [e[0].elapsed_time(e[1]) for e in evs]
+    avg = sum(ms) / len(ms)
+    samples = int(cnt.item())
+    bps = (32 if mp["shading"] else 8) * vol.itemsize
+    ach = samples / args.steps * bps / (avg * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(wall, 4), "unit": "ms/frame", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall, 4),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 march", "data": "synthetic",
+        "config": {"workload": args.workload, "volume": "%d^3 %s %s" % (vol.shape[0], vol.dtype,
+                                                                         wl["volume"][0]),
+                   "width": W, "height": H, "views": V, "shading": "none",
+                   "step_vox": mp["step_vox"], "alpha_stop": mp["alpha_stop"],
+                   "march": "dense only"},
+        "frame_ms_p50_p99": [round(nearest_rank(ms, 50), 4), round(nearest_rank(ms, 99), 4)],
+        "ray_samples_per_s": round(samples / (sum(ms) * 1e-3), 1),
+        "roofline": {"bound": "hbm", "kernel": "k_march_dense", "achieved": round(ach, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": None,
+                     "model": "%d B/sample = 8 trilinear voxels x %d B; %.4g samples/launch" %
+                              (bps, vol.itemsize, samples / args.steps),
+                     "duration": "HIP events around fv_raymarch_dense, %.4f ms" % avg,
+                     "note": "the 256 KiB volume lives in L2: frac is against HBM only for "
+                             "comparison; the launch is latency-bound at %d rays" % total},
+    }
+    if not args.no_cpu:
+        t0 = time.perf_counter()
+        r = oracle.march(vol, tf, cams[-1], W, H, mp)
+        t = time.perf_counter() - t0
+        ref = r["rgba"]
+        got = frame.view(-1, 4).cpu().numpy()
+        out["cpu_baseline"] = {
+            "value": round(t * 1e3, 1), "unit": "ms/frame",
+            "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count())), "kind": "oracle",
+            "ray_samples_per_s": round(float(r["samples"].sum()) / t, 1),
+            "max_abs_gpu_vs_oracle": float(np.abs(got - ref).max()),
+            "sample": "the last timed frame, every pixel, FP64"}
+    volh.close()
+    print(json.dumps(out), flush=True)
+
+
+def training_step_bench(args, wl):
+    """One training step of the reconstruction network (fv_train_step: BF16
+    forward and backward on the GPU, loss, Adam) at batch B of 512 x 512
+    frames; synthetic pairs (a value-noise volume, the dense march as target,
+    a foveated sample map).  HIP events around each step."""
+    import numpy as np
+    import torch
+
+    import synthetic
+    from paper_2209_09965_amd import binding as b
+    dev = torch.device("cuda:0")
+    B, W, H = wl["batch"], wl["width"], wl["height"]
+    vol = synthetic.value_noise_volume(wl["seeds"][0], n=128, base_period=32)
+    tf = synthetic.tf_noise(wl["seeds"][0])
+    volh = b.Volume(torch.from_numpy(vol).to(dev))
+    tf_t = torch.from_numpy(tf).reshape(-1).to(dev)
+    mp = synthetic.march_params(shading=True)
+    fr = torch.zeros(B, W * H * 4, device=dev)
+    dp = torch.zeros(B, W * H, device=dev)
+    mk = torch.zeros(B, W * H, dtype=torch.uint8, device=dev)
+    ray_idx = torch.empty(W * H, dtype=torch.int32, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    rng = np.random.default_rng(1)
+    for i in range(B):
+        cam = synthetic.random_camera(rng)
+        b.raymarch_dense(volh, tf_t, [cam], W, H, mp, fr[i], dp[i])
+        b.fovea_mask(synthetic.fovea_params(W, H, seed=i, frame=i), W, H, 1, ray_idx, count,
+                     mask=mk[i])
+    volh.close()
+    net = b.Net(synthetic.net_init(0))
+    ws = torch.empty(net.train_workspace_bytes(B, W, H), dtype=torch.uint8, device=dev)
+    loss3 = torch.zeros(3, device=dev)
+    for _ in range(args.warmup):
+        net.train_step(fr, mk, dp, fr, B, W, H, 1e-4, loss3, ws)
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        evs[i][0].record()
+        net.train_step(fr, mk, dp, fr, B, W, H, 1e-4, loss3, ws)
+        evs[i][1].record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / args.steps
+    ms = [e[0].elapsed_time(e[1]) for e in evs]
+    avg = sum(ms) / len(ms)
+    # forward 167968 FLOP per pixel; backward (input and weight gradients) twice that
+    flop = 3 * 167968.0 * B * W * H
+    out = {
+        "metric": "ms/training step (BF16 forward + backward + Adam)", "value": round(wall, 3),
+        "unit": "ms/step", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(wall, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16 (fp32 master, adam)", "data": "synthetic",
+        "config": {"workload": args.workload, "batch": B, "width": W, "height": H,
+                   "network": "U-Net 32/48/64/96 + 5x5 KPN", "loss": "0.9 (1 - SSIM) + 0.1 L1"},
+        "step_ms_p50_p99": [round(nearest_rank(ms, 50), 3), round(nearest_rank(ms, 99), 3)],
+        "roofline": {"bound": "mfma", "kernel": "fv_train_step (all kernels of a step)",
+                     "achieved": round(flop / (avg * 1e-3) / 1e12, 1), "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": round(flop / (avg * 1e-3) / 1e12 / 2500.0, 4),
+                     "traffic": None,
+                     "model": "3 x 167968 FLOP/px (forward, input and weight gradients) x %d px"
+                              % (B * W * H),
+                     "duration": "HIP events around fv_train_step, %.3f ms" % avg},
+    }
     net.close()
     print(json.dumps(out), flush=True)
 
@@ -536,47 +699,78 @@ def cpu_baseline(vol, tf, cams, fp, W, H, V, mp, n_rays, theta, crop, fov_out, g
                                q["sigma_px"], q["p_floor"], fp["mode"])
     t_mask = time.perf_counter() - t0
     rng = np.random.default_rng(0)
-    if n_rays <= 0 or n_rays >= idx.size:
+    big = V * W * H > BIG_FRAME_PX
+    if big:
+        # a deterministic 1/16 of the sampled rays (every 16th of the list)
+        pick = np.arange(0, idx.size, 16)
+    elif n_rays <= 0 or n_rays >= idx.size:
         pick = np.arange(idx.size)
     else:
         pick = np.sort(rng.choice(idx.size, size=n_rays, replace=False))
     t0 = time.perf_counter()
     r = oracle.march(vol, tf, cams, W, H, mp, idx=idx[pick])
     t_march = time.perf_counter() - t0
+    # the dense oracle frame (on large frames every 16th pixel): the PSNR reference
+    sub = np.arange(0, V * W * H, 16, dtype=np.uint32) if big else None
+    t0 = time.perf_counter()
+    dense = oracle.march(vol, tf, cams, W, H, mp, idx=sub)
+    t_dense = (time.perf_counter() - t0) * (16 if big else 1)
     # network on a crop of the packed input (same arithmetic per pixel everywhere)
-    t0 = time.perf_counter()
-    dense = oracle.march(vol, tf, cams, W, H, mp)
-    t_dense = time.perf_counter() - t0
-    sparse_rgba = np.zeros((V * W * H, 4))
-    sparse_rgba[idx] = dense["rgba"][idx]
-    x = oracle.pack_input(sparse_rgba, m.reshape(-1), dense["depth"] * m.reshape(-1))
-    x = x.reshape(V, H, W, 5).transpose(0, 3, 1, 2)
-    if theta.size == N.N_PARAMS_RECURRENT:
-        x = N.recurrent_input(x)  # the fed-back O_d: same arithmetic whatever its value
     y0, x0 = (H - crop) // 2 // 8 * 8, (W - crop) // 2 // 8 * 8
+    if big:
+        # the oracle's samples inside the crop of view 0
+        yy, xx = np.divmod(idx.astype(np.int64), W)
+        inc = (idx < W * H) & (yy >= y0) & (yy < y0 + crop) & (xx >= x0) & (xx < x0 + crop)
+        rc = oracle.march(vol, tf, cams, W, H, mp, idx=idx[inc])
+        sparse_rgba = np.zeros((crop * crop, 4))
+        sdepth = np.zeros(crop * crop)
+        mc = np.zeros(crop * crop, np.uint8)
+        loc = (yy[inc] - y0) * crop + (xx[inc] - x0)
+        sparse_rgba[loc], sdepth[loc], mc[loc] = rc["rgba"], rc["depth"], 1
+        xc = oracle.pack_input(sparse_rgba, mc, sdepth).reshape(1, crop, crop, 5)
+        xc = xc.transpose(0, 3, 1, 2)
+    else:
+        sparse_rgba = np.zeros((V * W * H, 4))
+        sparse_rgba[idx] = dense["rgba"][idx]
+        x = oracle.pack_input(sparse_rgba, m.reshape(-1), dense["depth"] * m.reshape(-1))
+        x = x.reshape(V, H, W, 5).transpose(0, 3, 1, 2)
+        xc = x[:1, :, y0:y0 + crop, x0:x0 + crop]
+    if theta.size == N.N_PARAMS_RECURRENT:
+        xc = N.recurrent_input(xc)  # the fed-back O_d: same arithmetic whatever its value
     t0 = time.perf_counter()
-    N.forward(theta.astype(np.float64), np.ascontiguousarray(x[:1, :, y0:y0 + crop, x0:x0 + crop]))
+    N.forward(theta.astype(np.float64), np.ascontiguousarray(xc))
     t_net = (time.perf_counter() - t0) * (W * H * V) / (crop * crop)
     per_frame_s = t_mask + t_march * idx.size / pick.size + t_net
     ref = dense["rgba"][:, :3]
-    psnr = N.psnr(fov_out.reshape(-1, 3), ref)
-    to_nchw = lambda a: np.clip(a, 0, 1).reshape(V, H, W, 3).transpose(0, 3, 1, 2)
-    ssim = N.ssim(to_nchw(np.asarray(fov_out, np.float64)), to_nchw(ref))
-    psnr_gpu_dense = N.psnr(gpu_dense[:, :3], ref)
+    fov = fov_out.reshape(-1, 3)[sub] if big else fov_out
+    psnr = N.psnr(fov.reshape(-1, 3), ref)
+    psnr_gpu_dense = N.psnr((gpu_dense[sub] if big else gpu_dense)[:, :3], ref)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count()))
-    return {"value": round(per_frame_s * 1e3, 1), "unit": "ms/frame", "cores": cores,
-            "kind": "oracle",
-            "ray_samples_per_s": round(float(r["samples"].sum()) / t_march, 1),
-            "dense_ms_per_frame": round(t_dense * 1e3, 1),
-            "psnr_foveated_vs_oracle_dense_db": round(float(psnr), 2),
-            "ssim_foveated_vs_oracle_dense": round(float(ssim), 4),
-            "psnr_gpu_dense_vs_oracle_dense_db": round(float(psnr_gpu_dense), 2),
-            "sample": "one foveated frame: full sample map + compaction, the FP64 march of %d "
-                      "of its %d sampled rays%s, and the FP64 network on a %dx%d crop scaled "
-                      "to the %dx%d frame; the dense oracle frame of the same view is the "
-                      "PSNR reference" %
-                      (pick.size, idx.size, "" if pick.size == idx.size else
-                       " (random subset, scaled)", crop, crop, W, H)}
+    res = {"value": round(per_frame_s * 1e3, 1), "unit": "ms/frame", "cores": cores,
+           "kind": "oracle",
+           "ray_samples_per_s": round(float(r["samples"].sum()) / t_march, 1),
+           "dense_ms_per_frame": round(t_dense * 1e3, 1),
+           "psnr_foveated_vs_oracle_dense_db": round(float(psnr), 2),
+           "psnr_gpu_dense_vs_oracle_dense_db": round(float(psnr_gpu_dense), 2)}
+    if not big:
+        to_nchw = lambda a: np.clip(a, 0, 1).reshape(V, H, W, 3).transpose(0, 3, 1, 2)
+        res["ssim_foveated_vs_oracle_dense"] = round(
+            float(N.ssim(to_nchw(np.asarray(fov_out, np.float64)), to_nchw(ref))), 4)
+    if big:
+        res["sample"] = (
+            "one foveated frame of %d views: full sample map + compaction, the FP64 march of "
+            "every 16th of its %d sampled rays (time scaled by 16), and the FP64 network on a "
+            "%dx%d crop of view 0 scaled to the %d x %dx%d frames; PSNR against the dense "
+            "oracle frames on every 16th pixel (dense time scaled by 16)" %
+            (V, idx.size, crop, crop, V, W, H))
+    else:
+        res["sample"] = (
+            "one foveated frame: full sample map + compaction, the FP64 march of %d of its %d "
+            "sampled rays%s, and the FP64 network on a %dx%d crop scaled to the %dx%d frame; "
+            "the dense oracle frame of the same view is the PSNR reference" %
+            (pick.size, idx.size, "" if pick.size == idx.size else " (random subset, scaled)",
+             crop, crop, W, H))
+    return res
 
 
 if __name__ == "__main__":

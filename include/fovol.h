@@ -347,8 +347,10 @@ fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba,
  *      frames and takes, for every tensor t with a scale (the packed input
  *      and the output of each 3x3 conv, after its ReLU), the largest
  *      magnitude m_t as computed before the tensor is rounded for storage:
- *      s_t = max(m_t, 1e-6) / 448.  A value a of t is stored as the code
- *      q = E4M3(a / s_t), saturated at +-448, rounded to nearest even.  A
+ *      s_t = FV_FP8_HEADROOM max(m_t, 1e-6) / 448 (the headroom keeps
+ *      frames brighter than the calibration frames from saturating).  A
+ *      value a of t is stored as the code q = E4M3(a / s_t), saturated at
+ *      +-448, rounded to nearest even.  A
  *      pooled tensor stores E4M3 of the mean of four codes and an upsampled
  *      one E4M3 of the bilinear blend of the codes; both keep their source's
  *      scale.
@@ -360,22 +362,27 @@ fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba,
  *      accumulation), stored q_out = E4M3(min(max(acc_o (omega_o / s_out) +
  *      B_o / s_out, 0), 448)), the two factors in FP32 (ReLU and
  *      saturation in one clamp).
+ *    First layer: the packed input (the sampled colours, and the fed-back
+ *      O_d of the recurrent form) is not quantised to E4M3, whose 6 % steps
+ *      the output would inherit: e0a reads it in BF16 with BF16 weights
+ *      (FP32 accumulation) and stores q = E4M3(min(max(acc / s_e0a +
+ *      B / s_e0a, 0), 448)); the input's scale s_in is measured but unused.
  *    Heads: the codes of the last decoder tensor with the head weights
  *      BF16(W s_d0b), FP32 bias and accumulation.
  *  The two 1x1 heads run on MFMA with BF16 operands (FP8 activations are
  *  widened) and FP32 accumulation; softmax and the kernel application run
  *  in FP32.
  */
+#define FV_FP8_HEADROOM 2.0f
 #define FV_NET_PARAMS 480060
 
 /* Recurrent form (paper Sec. 3.2.4, the feedback of the direct prediction):
  * the first conv (e0a) reads 8 channels, the 5 above followed by the
  * previous frame's direct prediction O_d (r, g, b, FP32, unmasked), so its
  * weight is [32][8][3][3] and the vector has 32 * 3 * 9 = 864 more entries.
- * The first frame of a sequence is run with a zero O_d.  Under FP8 this
- * form computes its first conv in BF16 (the fed-back O_d is a dense image;
- * E4M3 would round it by up to 6 %); its output and every later layer are
- * FP8 as in the plain form.  The recurrent decoder hidden states of the
+ * The first frame of a sequence is run with a zero O_d.  Under FP8 the
+ * first conv reads the input in BF16 as in the plain form.  The recurrent
+ * decoder hidden states of the
  * paper's network are not part of this form.
  * fv_net_create tells the two forms apart by n_params. */
 #define FV_NET_PARAMS_RECURRENT 480924

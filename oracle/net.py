@@ -475,20 +475,24 @@ def round_weights(theta, rnd):
 FP8_TENSORS = ["x"] + [name for name, _, _, k in LAYERS if k == 3]
 
 
+FP8_HEADROOM = 2.0
+
+
 def calibrate_fp8(theta, x, storage_round=bf16_round):
     """Per-tensor FP8 activation scales from one pass over the calibration
     input x (the library's post-training quantisation): the pass runs with
     conv weights and stored activations through storage_round (BF16, the
     library's calibration pass), records the largest magnitude m_t of every
     tensor as computed (before rounding) and returns
-    s_t = max(m_t, 1e-6) / 448."""
+    s_t = 2 max(m_t, 1e-6) / 448, a headroom of 2 so that frames brighter
+    than the calibration frames do not saturate."""
     m = {}
 
     def observe(name, t):
         m[name] = max(m.get(name, 0.0), float(np.abs(t).max()))
 
     forward(round_weights(theta, storage_round), x, act_round=storage_round, observe=observe)
-    return {k: max(v, 1e-6) / E4M3_MAX for k, v in m.items()}
+    return {k: FP8_HEADROOM * max(v, 1e-6) / E4M3_MAX for k, v in m.items()}
 
 
 def fp8_weights(w, in_scale, rnd=e4m3_round):
@@ -535,9 +539,11 @@ def forward_fp8(theta, x, scales, e4m3=e4m3_round, head_round=bf16_round,
     tensor with weights BF16(W s_d0b) and FP32 bias; softmax and the 5x5
     kernel application are exact.
 
-    The recurrent form (8 input channels) computes its first conv in BF16
-    (first_bf16 defaults to True for it): input and weights rounded to BF16,
-    q_out = E4M3(min(max(acc / s_out + B / s_out, 0), 448)).
+    The first conv reads the input in BF16 (first_bf16, the default):
+    input and weights rounded to BF16, q_out = E4M3(min(max(acc / s_out +
+    B / s_out, 0), 448)); the sampled colours would otherwise carry E4M3's
+    6 % steps into the output.  first_bf16=False quantises the input to
+    E4M3 with its own scale instead.
 
     With e4m3, head_round and bf16 all the identity this is the FP64 network
     (forward()) exactly, whatever the scales.  Returns (out, O_d).
@@ -552,7 +558,7 @@ def forward_fp8(theta, x, scales, e4m3=e4m3_round, head_round=bf16_round,
         raise ValueError("input has %d channels, the network reads %d"
                          % (x.shape[1], P["e0a"][0].shape[1]))
     if first_bf16 is None:
-        first_bf16 = x.shape[1] == 8
+        first_bf16 = True
     rec = record if record is not None else {}
 
     def conv(name, srcs):

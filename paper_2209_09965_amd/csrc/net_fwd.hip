@@ -575,9 +575,10 @@ fv_status forward_impl(const fv_net* net, const Plan& p, uint8_t* ws, const floa
       a.f_mask = mask;
       a.f_depth = depth;
       a.f_prev = prev;
-      // the recurrent form runs its first layer in BF16 under FP8: its
-      // fed-back O_d is a dense image, which E4M3 would round by up to 6 %
-      const bool mixed = fp8 && net->recurrent;
+      // under FP8 the first layer runs in BF16: its input is the sampled
+      // colours (and, recurrent, the fed-back O_d), which the output has to
+      // carry to well below E4M3's 6 % steps
+      const bool mixed = fp8;
       const bool f8 = fp8 && !mixed;
       a.f_mixed = mixed;
       a.f_inv = f8 ? in_inv : 1.0f;
@@ -692,7 +693,7 @@ fv_status build_fp8(fv_net* n, hipStream_t s) {
     if (st != FV_OK) return st;
   }
   {
-    // BF16 first layer of the recurrent form under FP8: FP32 accumulators
+    // BF16 first layer under FP8: FP32 accumulators
     // times 1 / (output scale), bias / (output scale)
     const LayerDesc& L0 = kLayers[0];
     const float s_out = n->act_scale[T_E0A];
@@ -972,7 +973,8 @@ static fv_status calibrate(fv_net* n, const float* frame_rgba, const uint8_t* ma
                   "calibrate: read");
   if (st == FV_OK) st = hip_status(hipStreamSynchronize(s), "calibrate: sync");
   if (st != FV_OK) return st;
-  for (int t = 0; t < kNumTensors; ++t) n->act_scale[t] = std::max(host[t], 1e-6f) / 448.0f;
+  for (int t = 0; t < kNumTensors; ++t)
+    n->act_scale[t] = FV_FP8_HEADROOM * std::max(host[t], 1e-6f) / 448.0f;
   n->act_scale[T_P0] = n->act_scale[T_E0B];
   n->act_scale[T_P1] = n->act_scale[T_E1B];
   n->act_scale[T_P2] = n->act_scale[T_E2B];

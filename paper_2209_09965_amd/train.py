@@ -9,8 +9,15 @@ dense frame at the sampled pixels (a sparse pixel equals the dense pixel).
 Volumes: 64^3 uint8 Gaussian blobs (unshaded) and 128^3 float32 value noise
 (Blinn-Phong shaded); split by volume 10:1:1.
 Training: fv_train_step (BF16 forward/backward on MFMA, FP32 Adam), batch
-16, lr 1e-3.  Every kernel of a step is the library's; torch only holds the
-frames in device memory and gathers batches.
+16, lr 1e-3 annealed to 1e-5 on a cosine schedule (by steps or by the time
+budget, whichever is further along), the weights of the best validation
+epoch kept.  Every kernel of a step is the library's; torch only holds the
+frames in device memory, gathers batches and augments them: each frame (each
+pair of consecutive frames) gets one random permutation of its RGB channels
+and per-channel gains in [0.6, 1.25] (clipped to 1), applied to the sparse
+input and the target alike, so that the network learns to carry the colours
+of the samples instead of the colour statistics of the training transfer
+functions (--no-augment turns it off; recurrent training is not augmented).
 
 With --temporal W the pairs come as consecutive frames (the camera turned by
 3 degrees about the volume, the sample map of the next frame), batches hold
@@ -107,6 +114,26 @@ def render_pairs(dev, vol_specs, views, seed, log=print, per_view=1, noise="hash
     return dict(rgba=rgba, depth=depth, mask=mask, vol=vol_of)
 
 
+def augment_colours(fr, rng, group=1):
+    """Random RGB permutation and per-channel gains in [0.6, 1.25] (clipped to
+    [0, 1]) per frame of the batch fr [n, H*W*4]; `group` consecutive frames
+    share one transform.  Alpha is unchanged."""
+    n = fr.shape[0]
+    g = n // group
+    perm = np.stack([rng.permutation(3) for _ in range(g)]).repeat(group, axis=0)
+    gain = rng.uniform(0.6, 1.25, size=(g, 3)).repeat(group, axis=0)
+    v = fr.view(n, -1, 4)
+    idx = torch.from_numpy(perm).to(fr.device).view(n, 1, 3).expand(n, v.shape[1], 3)
+    rgb = torch.gather(v[:, :, :3], 2, idx) * torch.from_numpy(gain).float().to(fr.device)[:, None]
+    return torch.cat([rgb.clamp_(0.0, 1.0), v[:, :, 3:]], dim=2).reshape(n, -1).contiguous()
+
+
+def cosine_lr(lr0, lr_min, progress):
+    """Cosine annealing from lr0 (progress 0) to lr_min (progress 1)."""
+    p = min(max(progress, 0.0), 1.0)
+    return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + math.cos(math.pi * p))
+
+
 def turn_camera(cam, deg):
     """The camera rotated by deg about the vertical axis through the target."""
     a = math.radians(deg)
@@ -171,6 +198,10 @@ def main():
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-min", type=float, default=1e-5)
+    ap.add_argument("--schedule", choices=["cosine", "constant"], default="cosine")
+    ap.add_argument("--no-augment", action="store_true",
+                    help="train on the rendered colours only (no channel permutation / gains)")
     ap.add_argument("--blob-volumes", type=int, default=100)
     ap.add_argument("--noise-volumes", type=int, default=40)
     ap.add_argument("--views", type=int, default=20)
@@ -244,8 +275,15 @@ def main():
     ws = torch.empty(net.train_workspace_bytes(B, W, H), dtype=torch.uint8, device=dev)
     loss3 = torch.zeros(3, device=dev)
     rng = np.random.default_rng(args.seed + 1)
+    arng = np.random.default_rng(args.seed + 2)
+    augment = not args.no_augment and not args.recurrent
+    per0 = B // 2 if temporal else B
+    total_steps = max(1, args.epochs * (tr.size // per0))
+    t_train = time.time()
+    budget = max(args.time_limit - (t_train - t_start), 1.0)
     step = 0
     hist = []
+    best = (-float("inf"), None, -1)
     for ep in range(args.epochs):
         perm = rng.permutation(tr)
         t0 = time.time()
@@ -264,8 +302,12 @@ def main():
             fr = data["rgba"].index_select(0, sel)
             m = data["mask"].index_select(0, sel)
             d = data["depth"].index_select(0, sel)
+            if augment:
+                fr = augment_colours(fr, arng, group=2 if temporal else 1)
+            lr = args.lr if args.schedule == "constant" else cosine_lr(
+                args.lr, args.lr_min, max(step / total_steps, (time.time() - t_train) / budget))
             if not temporal:
-                net.train_step(fr, m, d, fr, B, W, H, args.lr, loss3, ws)
+                net.train_step(fr, m, d, fr, B, W, H, lr, loss3, ws)
             elif args.recurrent:
                 # the fed-back O_d of every frame of the pairs, by inference
                 # along the sequences with the current weights
@@ -288,13 +330,13 @@ def main():
                 net.loss(out, fr, B, W, H, loss3, dl, ws)
                 net.loss_temporal(out, fr, B, W, H, args.temporal, lt, dl, ws)
                 net.backward(dl, B, W, H, ws)
-                net.adam(args.lr)
+                net.adam(lr)
             else:
                 net.forward_train(fr, m, d, B, W, H, out, ws)
                 net.loss(out, fr, B, W, H, loss3, dl, ws)
                 net.loss_temporal(out, fr, B, W, H, args.temporal, lt, dl, ws)
                 net.backward(dl, B, W, H, ws)
-                net.adam(args.lr)
+                net.adam(lr)
             step += 1
             nb += 1
             if nb % 25 == 0:
@@ -303,18 +345,25 @@ def main():
         ev = evaluate(net, data, va[:40], dev, temporal=temporal, seq_len=L)
         hist.append(dict(epoch=ep, loss=float(loss3[0].item()), val=ev,
                          s_per_epoch=time.time() - t0))
-        log("epoch %d loss %.4f temporal %.4f val PSNR hybrid %.2f direct %.2f sparse %.2f "
-            "tPSNR %.2f (%.1f s)" %
-            (ep, float(loss3[0].item()), float(lt.item()), ev["hybrid"], ev["direct"],
+        log("epoch %d lr %.2e loss %.4f temporal %.4f val PSNR hybrid %.2f direct %.2f sparse "
+            "%.2f tPSNR %.2f (%.1f s)" %
+            (ep, lr, float(loss3[0].item()), float(lt.item()), ev["hybrid"], ev["direct"],
              ev["sparse"], ev.get("tpsnr", float("nan")), time.time() - t0))
+        if ev["hybrid"] > best[0]:
+            best = (ev["hybrid"], net.get_params(), ep)
         if time.time() - t_start > args.time_limit:
             log("time limit reached")
             break
+    if best[1] is not None:
+        # the weights of the best validation epoch
+        net.set_params(best[1])
+        log("kept epoch %d (val PSNR hybrid %.2f)" % (best[2], best[0]))
     params = net.get_params()
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, params)
     test_bf16 = evaluate(net, data, te, dev, temporal=temporal, seq_len=L)
-    res = dict(test_bf16=test_bf16, steps=step, epochs=len(hist), history=hist,
+    res = dict(test_bf16=test_bf16, steps=step, epochs=len(hist), best_epoch=best[2],
+               history=hist,
                pairs=dict(train=int(tr.size), val=int(va.size), test=int(te.size)))
     try:
         # FP8 after calibration on training frames

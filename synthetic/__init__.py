@@ -100,6 +100,52 @@ def value_noise_volume(seed, n=256, octaves=5, base_period=64, dtype=np.float32,
     return out
 
 
+def value_noise_volume_device(seed, n, device, octaves=5, base_period=64, dtype=None,
+                              chunk=64):
+    """value_noise_volume's recipe computed on a torch device (the lattices
+    are the same seeded draws; the blend runs in float32 there, so values
+    differ from the float64 host version by float32 rounding).  For volumes
+    too large to generate on the host in reasonable time (1024^3).  Returns a
+    [n, n, n] device tensor ([z, y, x]) of dtype (default float16)."""
+    import torch
+    dtype = torch.float16 if dtype is None else dtype
+    out = torch.empty((n, n, n), dtype=dtype, device=device)
+    amps = [0.5 ** o for o in range(octaves)]
+    norm = sum(amps)
+    lats = []
+    for o in range(octaves):
+        period = base_period / (2 ** o)
+        m = int(math.ceil(n / period)) + 2
+        lat = _rng(seed, 2, o).uniform(0.0, 1.0, size=(m, m, m))
+        lats.append((period, torch.from_numpy(lat.astype(np.float32)).to(device)))
+
+    def axis(period, lo, hi):
+        c = (torch.arange(lo, hi, device=device, dtype=torch.float64) + 0.5) / period
+        i0 = torch.floor(c)
+        t = c - i0
+        return i0.long(), (t * t * (3.0 - 2.0 * t)).float()
+
+    for z0 in range(0, n, chunk):
+        z1 = min(n, z0 + chunk)
+        acc = torch.zeros((z1 - z0, n, n), device=device)
+        for (period, lat), amp in zip(lats, amps):
+            iz, fz = axis(period, z0, z1)
+            iy, fy = axis(period, 0, n)
+            ix, fx = axis(period, 0, n)
+            for cz in (0, 1):
+                wz = fz if cz else 1.0 - fz
+                for cy in (0, 1):
+                    wy = fy if cy else 1.0 - fy
+                    for cx in (0, 1):
+                        wx = fx if cx else 1.0 - fx
+                        g = lat[(iz + cz)[:, None, None], (iy + cy)[None, :, None],
+                                (ix + cx)[None, None, :]]
+                        acc += (amp * g) * (wz[:, None, None] * wy[None, :, None] *
+                                            wx[None, None, :])
+        out[z0:z1] = (acc / norm).to(dtype)
+    return out
+
+
 # ------------------------------------------------------- transfer functions
 
 def _tf_from_points(pos, sigma, rgb):
@@ -244,13 +290,16 @@ def noise_tiles(seed, size=64, count=64, kind="blue"):
 WORKLOADS = {
     # dense FP32 march only; 64^3 u8 blobs at 256x256, no shading
     "blob64_256": dict(volume=("blob", 64), width=256, height=256, views=1,
-                       tf="blob", shading=False, seeds=(1000, 1001, 1002, 1003, 1004)),
+                       tf="blob", shading=False, seeds=(1000, 1001, 1002, 1003, 1004),
+                       dense_only=True),
     # foveated sparse + dense march; 256^3 f32 value noise at 1920x1080, Phong
     "noise256_1080p": dict(volume=("noise", 256), width=1920, height=1080, views=1,
                            tf="noise", shading=True, seeds=(3000, 3001, 3002, 3003, 3004)),
     # blob volume at 1080p (end-to-end inference workload)
     "blob64_1080p": dict(volume=("blob", 64), width=1920, height=1080, views=1,
                          tf="blob", shading=False, seeds=(1000,)),
+    # training step: batch 16 of 512x512 frames (BF16 forward/backward, Adam)
+    "train512_b16": dict(training=True, batch=16, width=512, height=512, seeds=(4000,)),
     # stereo: 1024^3 f16 value noise, two 2160x2160 views
     "noise1024_stereo2160": dict(volume=("noise", 1024), width=2160, height=2160, views=2,
                                  tf="noise", shading=True, seeds=(5000,), sigma_frac=0.12,
