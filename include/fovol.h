@@ -615,6 +615,49 @@ fv_status fv_render_frame(fv_renderer* r, const fv_volume* vol, const float* tf_
                           fv_frame_info* info, void* stream);
 
 /* ------------------------------------------------------------------------
+ * 4d. The two-stage W-Net (paper Sec. 3.2.1-3.2.3, Sec. 3.5.1), inference in
+ *     BF16
+ * ------------------------------------------------------------------------
+ * Network D: a U-Net of 3x3 convs + ReLU with the paper's depth progression
+ * e64-e64-e80-d96-d80-d64-d64 read as encoder 64/64/80/96 (two convs per
+ * level, 2x2 average pooling between levels) and decoder 80/64/64 (bilinear
+ * x2 upsampling with half-pixel centres, [upsampled, encoder skip]
+ * concatenated); its last decoder state gives the direct prediction O_d by a
+ * 1x1 conv (linear).  Network K: 1x1 convs on D's hidden states H_0..H_3 (the
+ * decoder states at 1, 1/2, 1/4 resolution and the 1/8 bottleneck).  Its
+ * encoder filters J_0 = O_d at level 0 with the softmax of 25 predicted
+ * logits as a 5x5 kernel (replicated border, tap k = 5 (dy+2) + (dx+2)), pools
+ * the result 2x2 into J_1, and so on to level 3; its decoder at level l
+ * (2, 1, 0) predicts 25 logits and a blend logit z, forms
+ * B = (1 - sigmoid(z)) Je_l + sigmoid(z) up(J_(l+1)) from the encoder's
+ * filtered image Je_l and the upsampled coarser result, and filters B with
+ * its kernel; the output is J_0.  The input is the 5-channel packed sparse
+ * frame of section 4.
+ * D runs on MFMA with BF16 operands and stored activations, FP32
+ * accumulation; O_d and K in FP32.
+ *
+ * Parameters: FV_WNET_PARAMS floats, per layer the weight [Co][Ci][k][k]
+ * then the bias [Co], in the order e0a e0b e1a e1b e2a e2b e3a e3b d2a d2b
+ * d1a d1b d0a d0b (3x3), hd (64 -> 3), ke0 ke1 ke2 ke3 (64/64/80/96 -> 25),
+ * kd2 kd1 kd0 (80/64/64 -> 26, the 26th the blend logit). */
+#define FV_WNET_PARAMS 798341
+typedef struct fv_wnet fv_wnet;
+size_t fv_wnet_param_count(void);
+/* Uploads host FP32 parameters and builds D's BF16 weights; synchronises the
+ * device.  Errors: null pointers, n_params != FV_WNET_PARAMS, allocation
+ * failure (FV_ERR_NOMEM). */
+fv_status fv_wnet_create(const float* host_params, size_t n_params, fv_wnet** out);
+fv_status fv_wnet_destroy(fv_wnet* n);
+/* Device workspace of fv_wnet_reconstruct at this size. */
+fv_status fv_wnet_workspace(int views, int width, int height, size_t* bytes);
+/* Full-frame reconstruction by the W-Net; arguments, layouts and errors as
+ * fv_reconstruct (out_direct: O_d or NULL). */
+fv_status fv_wnet_reconstruct(const fv_wnet* n, const float* frame_rgba, const uint8_t* mask,
+                              const float* frame_depth, int views, int width, int height,
+                              float* out_rgb, float* out_direct, void* workspace,
+                              size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * 5. Training of the reconstruction network (paper: "Loss", "Training")
  * ------------------------------------------------------------------------
  * One workspace (fv_train_workspace) serves the four steps of a training

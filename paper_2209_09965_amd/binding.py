@@ -118,6 +118,11 @@ _SIGS = {
                            _vp]),
     "fv_net_fp8_scales": (_i, [_vp, _vp, _i]),
     "fv_net_set_fp8_scales": (_i, [_vp, _vp, _i, _vp]),
+    "fv_wnet_param_count": (_sz, []),
+    "fv_wnet_create": (_i, [_vp, _sz, ctypes.POINTER(_vp)]),
+    "fv_wnet_destroy": (_i, [_vp]),
+    "fv_wnet_workspace": (_i, [_i, _i, _i, ctypes.POINTER(_sz)]),
+    "fv_wnet_reconstruct": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _sz, _vp]),
     "fv_reconstruct_tensor": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(_sz),
                                    ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "fv_reconstruct_steps": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp,
@@ -427,6 +432,45 @@ def reconstruct_tensor(precision, views, width, height, tensor):
 
 def _prec(p):
     return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+class WNet:
+    """Library-owned two-stage W-Net (FP32 parameters, BF16 copy of D's convs)."""
+
+    def __init__(self, params):
+        import numpy as np
+        arr = np.ascontiguousarray(params, dtype=np.float32)
+        h = ctypes.c_void_p()
+        check(_lib.fv_wnet_create(ctypes.c_void_p(arr.ctypes.data), arr.size, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if self.handle:
+            check(_lib.fv_wnet_destroy(self.handle))
+            self.handle = None
+
+    @staticmethod
+    def workspace_bytes(views, width, height):
+        b = _sz()
+        check(_lib.fv_wnet_workspace(views, width, height, ctypes.byref(b)))
+        return b.value
+
+    def reconstruct(self, frame_rgba, mask, frame_depth, views, width, height, out_rgb,
+                    out_direct=None, workspace=None, stream=None):
+        npx = views * width * height
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes(views, width, height), dtype=torch.uint8,
+                                    device=frame_rgba.device)
+        wp, wb = _ws(workspace)
+        check(_lib.fv_wnet_reconstruct(
+            self.handle, _dev(frame_rgba, "frame_rgba", F32, npx * 4), _dev(mask, "mask", U8, npx),
+            _dev(frame_depth, "frame_depth", F32, npx, False), views, width, height,
+            _dev(out_rgb, "out_rgb", F32, npx * 3),
+            _dev(out_direct, "out_direct", F32, npx * 3, False), wp, wb, _stream(stream)))
+
+
+def wnet_param_count():
+    return int(_lib.fv_wnet_param_count())
 
 
 class Net:

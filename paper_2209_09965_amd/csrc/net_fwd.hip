@@ -716,6 +716,13 @@ fv_status build_fp8(fv_net* n, hipStream_t s) {
   return FV_OK;
 }
 
+fv_status pack_input_bf16(const float* frame, const uint8_t* mask, const float* depth,
+                          uint8_t* out, int64_t npx, hipStream_t s) {
+  k_pack<BF16><<<(unsigned)((npx + 255) / 256), 256, 0, s>>>((const float4*)frame, mask, depth,
+                                                           nullptr, out, npx, 1.0f, nullptr);
+  return launch_status("pack");
+}
+
 fv_status check_frame(int views, int W, int H, const char* fn) {
   if (views <= 0 || W < 8 || H < 8 || W % 8 || H % 8 || W > 16384 || H > 16384)
     return fail(FV_ERR_INVALID_ARG,

@@ -1,0 +1,419 @@
+// The paper's two-stage reconstruction network (the W-Net; paper Sec. 3.2.1-
+// 3.2.3 and Sec. 3.5.1), inference in BF16:
+//
+//   D  a U-Net of 3x3 convs with the paper's depths, encoder 64/64/80/96 and
+//      decoder 80/64/64 (two convs + ReLU per block, 2x2 average pooling,
+//      bilinear x2 upsampling, [upsampled, skip] concatenation), whose last
+//      decoder state gives the direct prediction O_d through a 1x1 conv.
+//      Every conv runs on the library's MFMA conv kernel (BF16 operands,
+//      FP32 accumulation), activations stored in BF16.
+//   K  1x1 kernel predictors on D's hidden states H_0..H_3 (the decoder
+//      states at full, 1/2 and 1/4 resolution and the bottleneck at 1/8):
+//      encoder level l filters the image J_l with its predicted 5x5 kernel
+//      (softmax of 25 logits, replicated border) and pools the result into
+//      J_(l+1); decoder level l predicts 25 logits and a blend logit, blends
+//      the encoder's filtered image with the upsampled coarser one by the
+//      sigmoid of the blend logit and filters the blend.  K runs in FP32.
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "net.h"
+#include "net_kernels.h"
+
+namespace fv {
+namespace wnet {
+
+using net::BF16;
+using net::ConvArgs;
+
+constexpr int kTaps = 25;
+constexpr int kConv = 14;  // D's 3x3 convs; then the O_d head and K's seven 1x1 layers
+constexpr int kLayersAll = kConv + 1 + 7;
+
+struct Layer {
+  int ci, co, k, level;
+  int c0, c1, up0;  // conv inputs (3x3 layers): channels of source 0 / 1, upsampled source 0
+};
+
+// Parameter order (each weight [Co][Ci][k][k], then the bias [Co]): D's convs
+// e0a e0b e1a e1b e2a e2b e3a e3b d2a d2b d1a d1b d0a d0b, the O_d head hd,
+// then K: ke0 ke1 ke2 ke3 (encoder, 25 logits) and kd2 kd1 kd0 (decoder, 25
+// logits and one blend logit).
+const Layer kL[kLayersAll] = {
+    {5, 64, 3, 0, 8, 0, 0},      {64, 64, 3, 0, 64, 0, 0},   {64, 64, 3, 1, 64, 0, 0},
+    {64, 64, 3, 1, 64, 0, 0},    {64, 80, 3, 2, 64, 0, 0},   {80, 80, 3, 2, 80, 0, 0},
+    {80, 96, 3, 3, 80, 0, 0},    {96, 96, 3, 3, 96, 0, 0},   {176, 80, 3, 2, 96, 80, 1},
+    {80, 80, 3, 2, 80, 0, 0},    {144, 64, 3, 1, 80, 64, 1}, {64, 64, 3, 1, 64, 0, 0},
+    {128, 64, 3, 0, 64, 64, 1},  {64, 64, 3, 0, 64, 0, 0},   {64, 3, 1, 0, 0, 0, 0},
+    {64, kTaps, 1, 0, 0, 0, 0},  {64, kTaps, 1, 1, 0, 0, 0}, {80, kTaps, 1, 2, 0, 0, 0},
+    {96, kTaps, 1, 3, 0, 0, 0},  {80, kTaps + 1, 1, 2, 0, 0, 0},
+    {64, kTaps + 1, 1, 1, 0, 0, 0}, {64, kTaps + 1, 1, 0, 0, 0, 0},
+};
+constexpr int kHead = 14, kKe0 = 15, kKd2 = 19;
+
+// BF16 activation tensors of D
+enum T {
+  T_IN = 0, T_E0A, T_E0B, T_P0, T_E1A, T_E1B, T_P1, T_E2A, T_E2B, T_P2, T_E3A, T_E3B,
+  T_D2A, T_D2B, T_D1A, T_D1B, T_D0A, T_D0B, kTensors
+};
+const int kTC[kTensors][2] = {  // channels, level
+    {8, 0},  {64, 0}, {64, 0}, {64, 1}, {64, 1}, {64, 1}, {64, 2}, {80, 2}, {80, 2},
+    {80, 3}, {96, 3}, {96, 3}, {80, 2}, {80, 2}, {64, 1}, {64, 1}, {64, 0}, {64, 0}};
+// per conv: source 0, source 1 or -1, output, pooled output or -1
+const int kIO[kConv][4] = {
+    {T_IN, -1, T_E0A, -1},    {T_E0A, -1, T_E0B, T_P0}, {T_P0, -1, T_E1A, -1},
+    {T_E1A, -1, T_E1B, T_P1}, {T_P1, -1, T_E2A, -1},    {T_E2A, -1, T_E2B, T_P2},
+    {T_P2, -1, T_E3A, -1},    {T_E3A, -1, T_E3B, -1},   {T_E3B, T_E2B, T_D2A, -1},
+    {T_D2A, -1, T_D2B, -1},   {T_D2B, T_E1B, T_D1A, -1}, {T_D1A, -1, T_D1B, -1},
+    {T_D1B, T_E0B, T_D0A, -1}, {T_D0A, -1, T_D0B, -1}};
+// K's hidden states H_0..H_3
+const int kHidden[4] = {T_D0B, T_D1B, T_D2B, T_E3B};
+
+int64_t param_offset(int layer) {
+  int64_t off = 0;
+  for (int l = 0; l < layer; ++l)
+    off += (int64_t)kL[l].co * kL[l].ci * kL[l].k * kL[l].k + kL[l].co;
+  return off;
+}
+
+static size_t al(size_t v) { return (v + 255) / 256 * 256; }
+
+// Workspace: D's BF16 tensors, then FP32 images: O_d, the kernel weights and
+// blend weights of the current K level (full-resolution sized), the pooled
+// encoder inputs J_1..J_3, the encoder outputs Je_0..Je_3, the blend B and
+// the decoder outputs J_2, J_1 (J_0 is the caller's output).
+struct Plan {
+  int n, h, w;
+  size_t t[kTensors];
+  size_t od, wk, av, jin[4], je[4], blend, jd[3];
+  size_t bytes;
+};
+
+Plan make_plan(int n, int h, int w) {
+  Plan p;
+  p.n = n;
+  p.h = h;
+  p.w = w;
+  size_t off = 0;
+  auto px = [&](int lv) { return (size_t)n * (h >> lv) * (w >> lv); };
+  for (int t = 0; t < kTensors; ++t) {
+    p.t[t] = off;
+    off += al(px(kTC[t][1]) * kTC[t][0] * 2);
+  }
+  p.od = off;
+  off += al(px(0) * 3 * 4);
+  p.wk = off;
+  off += al(px(0) * kTaps * 4);
+  p.av = off;
+  off += al(px(0) * 4);
+  for (int l = 0; l < 4; ++l) {
+    p.jin[l] = off;
+    off += l ? al(px(l) * 3 * 4) : 0;
+    p.je[l] = off;
+    off += al(px(l) * 3 * 4);
+  }
+  p.blend = off;
+  off += al(px(0) * 3 * 4);
+  for (int l = 0; l < 3; ++l) {
+    p.jd[l] = off;
+    off += l ? al(px(l) * 3 * 4) : 0;
+  }
+  p.bytes = off;
+  return p;
+}
+
+// 1x1 layer on a BF16 tensor of C channels (C a multiple of 8), T outputs.
+// MODE 0: the T outputs as they are (O_d); 1: softmax over T = 25 (encoder
+// kernels); 2: softmax over the first 25 and the sigmoid of the 26th (the
+// decoder's kernels and blend weight).
+template <int T, int MODE>
+__global__ void __launch_bounds__(256) k_predict(const __bf16* __restrict__ h, int C,
+                                                 const float* __restrict__ w,
+                                                 const float* __restrict__ b, int64_t npx,
+                                                 float* __restrict__ out,
+                                                 float* __restrict__ aout) {
+  extern __shared__ float sw[];  // w [T][C], then b [T]
+  for (int i = threadIdx.x; i < T * C + T; i += 256) sw[i] = i < T * C ? w[i] : b[i - T * C];
+  __syncthreads();
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= npx) return;
+  float z[T];
+  for (int t = 0; t < T; ++t) z[t] = sw[T * C + t];
+  const uint4* src = (const uint4*)(h + p * C);
+  for (int c8 = 0; c8 < C / 8; ++c8) {
+    const uint4 u = src[c8];
+    const uint32_t q[4] = {u.x, u.y, u.z, u.w};
+    for (int j = 0; j < 8; ++j) {
+      const float v = net::bf16_bits_to_f((q[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+      const int c = 8 * c8 + j;
+      for (int t = 0; t < T; ++t) z[t] = fmaf(sw[t * C + c], v, z[t]);
+    }
+  }
+  if constexpr (MODE == 0) {
+    for (int t = 0; t < T; ++t) out[p * T + t] = z[t];
+    return;
+  }
+  float m = z[0];
+  for (int t = 1; t < kTaps; ++t) m = fmaxf(m, z[t]);
+  float s = 0.f;
+  for (int t = 0; t < kTaps; ++t) {
+    z[t] = __expf(z[t] - m);
+    s += z[t];
+  }
+  const float inv = 1.0f / s;
+  for (int t = 0; t < kTaps; ++t) out[p * kTaps + t] = z[t] * inv;
+  if constexpr (MODE == 2) {
+    const float zb = z[kTaps];
+    const float e = __expf(-fabsf(zb));
+    aout[p] = zb >= 0.f ? 1.0f / (1.0f + e) : e / (1.0f + e);
+  }
+}
+
+// out(p) = sum over the 5x5 taps k of wk[p][k] img(clamp(p + delta_k)), RGB,
+// n images of h x w.
+__global__ void __launch_bounds__(256) k_apply(const float* __restrict__ wk,
+                                               const float* __restrict__ img, int n, int h,
+                                               int w, float* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t npx = (int64_t)n * h * w;
+  if (p >= npx) return;
+  const int x = (int)(p % w);
+  const int64_t r = p / w;
+  const int y = (int)(r % h);
+  const int64_t base = (r / h) * h * w;
+  float acc[3] = {0.f, 0.f, 0.f};
+  for (int dy = -2; dy <= 2; ++dy) {
+    const int yy = min(max(y + dy, 0), h - 1);
+    for (int dx = -2; dx <= 2; ++dx) {
+      const int xx = min(max(x + dx, 0), w - 1);
+      const float k = wk[p * kTaps + 5 * (dy + 2) + (dx + 2)];
+      const float* s = img + (base + (int64_t)yy * w + xx) * 3;
+      for (int c = 0; c < 3; ++c) acc[c] = fmaf(k, s[c], acc[c]);
+    }
+  }
+  for (int c = 0; c < 3; ++c) out[p * 3 + c] = acc[c];
+}
+
+// 2x2 average of an RGB image of h x w (h, w even) into (h/2) x (w/2).
+__global__ void __launch_bounds__(256) k_pool3(const float* __restrict__ src, int n, int h,
+                                               int w, float* __restrict__ dst) {
+  const int ho = h / 2, wo = w / 2;
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= (int64_t)n * ho * wo) return;
+  const int x = (int)(p % wo);
+  const int64_t r = p / wo;
+  const int y = (int)(r % ho);
+  const int64_t b = r / ho;
+  for (int c = 0; c < 3; ++c) {
+    float s = 0.f;
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx)
+        s += src[((b * h + 2 * y + dy) * w + 2 * x + dx) * 3 + c];
+    dst[p * 3 + c] = 0.25f * s;
+  }
+}
+
+// Source index and weight of bilinear x2 upsampling along one axis (half-pixel
+// centres, edge clamp): output i samples the input at (i + 1/2) / 2 - 1/2.
+__device__ __forceinline__ void up_axis(int i, int n, int* i0, int* i1, float* f) {
+  float s = fminf(fmaxf((i + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(n - 1));
+  const int a = (int)floorf(s);
+  *i0 = a;
+  *i1 = min(a + 1, n - 1);
+  *f = s - (float)a;
+}
+
+// B = (1 - a) je + a up(jc): the decoder's blend of the encoder's filtered
+// image je (h x w) with the upsampled coarser image jc ((h/2) x (w/2)).
+__global__ void __launch_bounds__(256) k_blend(const float* __restrict__ je,
+                                               const float* __restrict__ jc,
+                                               const float* __restrict__ a, int n, int h, int w,
+                                               float* __restrict__ out) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= (int64_t)n * h * w) return;
+  const int x = (int)(p % w);
+  const int64_t r = p / w;
+  const int y = (int)(r % h);
+  const int64_t b = r / h;
+  const int hc = h / 2, wc = w / 2;
+  int y0, y1, x0, x1;
+  float fy, fx;
+  up_axis(y, hc, &y0, &y1, &fy);
+  up_axis(x, wc, &x0, &x1, &fx);
+  const float* c00 = jc + ((b * hc + y0) * wc + x0) * 3;
+  const float* c01 = jc + ((b * hc + y0) * wc + x1) * 3;
+  const float* c10 = jc + ((b * hc + y1) * wc + x0) * 3;
+  const float* c11 = jc + ((b * hc + y1) * wc + x1) * 3;
+  const float av = a[p];
+  for (int c = 0; c < 3; ++c) {
+    const float top = c00[c] * (1.0f - fx) + c01[c] * fx;
+    const float bot = c10[c] * (1.0f - fx) + c11[c] * fx;
+    const float u = top * (1.0f - fy) + bot * fy;
+    out[p * 3 + c] = (1.0f - av) * je[p * 3 + c] + av * u;
+  }
+}
+
+static unsigned blocks_of(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace wnet
+}  // namespace fv
+
+struct fv_wnet {
+  int device;
+  float* master;                       // FP32 parameters, the order of fv::wnet::kL
+  void* w_bf16[fv::wnet::kConv];       // D's convs as swizzled BF16 MFMA fragments
+};
+
+using namespace fv;
+using namespace fv::wnet;
+
+extern "C" {
+
+size_t fv_wnet_param_count(void) { return (size_t)param_offset(kLayersAll); }
+
+fv_status fv_wnet_create(const float* host_params, size_t n_params, fv_wnet** out) {
+  clear_error();
+  if (!host_params || !out) return fail(FV_ERR_INVALID_ARG, "fv_wnet_create: null pointer");
+  const int64_t P = param_offset(kLayersAll);
+  if ((int64_t)n_params != P)
+    return fail(FV_ERR_INVALID_ARG, "fv_wnet_create: %zu parameters, expected %lld", n_params,
+                (long long)P);
+  fv_wnet* n = new fv_wnet();
+  std::memset(n->w_bf16, 0, sizeof n->w_bf16);
+  if (hipGetDevice(&n->device) != hipSuccess) {
+    delete n;
+    return fail(FV_ERR_DEVICE, "fv_wnet_create: hipGetDevice");
+  }
+  bool ok = hipMalloc(&n->master, P * sizeof(float)) == hipSuccess;
+  for (int l = 0; ok && l < kConv; ++l)
+    ok = hipMalloc(&n->w_bf16[l], net::swizzled_elems(kL[l].ci, kL[l].co) * 2) == hipSuccess;
+  if (!ok) {
+    fv_wnet_destroy(n);
+    return fail(FV_ERR_NOMEM, "fv_wnet_create: allocation");
+  }
+  fv_status st = hip_status(hipMemcpy(n->master, host_params, P * sizeof(float),
+                                      hipMemcpyHostToDevice), "fv_wnet_create: upload");
+  for (int l = 0; st == FV_OK && l < kConv; ++l)
+    st = net::swizzle_bf16(n->master + param_offset(l), kL[l].ci, kL[l].co, 0, n->w_bf16[l],
+                           nullptr);
+  if (st == FV_OK) st = hip_status(hipDeviceSynchronize(), "fv_wnet_create: sync");
+  if (st != FV_OK) {
+    fv_wnet_destroy(n);
+    return st;
+  }
+  *out = n;
+  return FV_OK;
+}
+
+fv_status fv_wnet_destroy(fv_wnet* n) {
+  clear_error();
+  if (!n) return FV_OK;
+  (void)hipFree(n->master);
+  for (int l = 0; l < kConv; ++l) (void)hipFree(n->w_bf16[l]);
+  delete n;
+  return FV_OK;
+}
+
+fv_status fv_wnet_workspace(int views, int width, int height, size_t* bytes) {
+  clear_error();
+  if (!bytes) return fail(FV_ERR_INVALID_ARG, "fv_wnet_workspace: null bytes");
+  fv_status st = net::check_frame(views, width, height, "fv_wnet_workspace");
+  if (st != FV_OK) return st;
+  *bytes = make_plan(views, height, width).bytes;
+  return FV_OK;
+}
+
+fv_status fv_wnet_reconstruct(const fv_wnet* n, const float* frame_rgba, const uint8_t* mask,
+                              const float* frame_depth, int views, int width, int height,
+                              float* out_rgb, float* out_direct, void* workspace,
+                              size_t ws_bytes, void* stream) {
+  clear_error();
+  const char* fn = "fv_wnet_reconstruct";
+  if (!n || !frame_rgba || !mask || !out_rgb || !workspace)
+    return fail(FV_ERR_INVALID_ARG, "%s: null pointer", fn);
+  fv_status st = net::check_frame(views, width, height, fn);
+  if (st != FV_OK) return st;
+  const Plan p = make_plan(views, height, width);
+  if (ws_bytes < p.bytes)
+    return fail(FV_ERR_CAPACITY, "%s: workspace %zu < %zu bytes", fn, ws_bytes, p.bytes);
+  if ((uintptr_t)workspace % 256)
+    return fail(FV_ERR_INVALID_ARG, "%s: workspace not 256-byte aligned", fn);
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* ws = (uint8_t*)workspace;
+  const int64_t npx = (int64_t)views * height * width;
+  // D: the packed input, the 14 convs (pooling fused into e0b, e1b, e2b), O_d
+  st = net::pack_input_bf16(frame_rgba, mask, frame_depth, ws + p.t[T_IN], npx, s);
+  if (st != FV_OK) return st;
+  for (int l = 0; l < kConv; ++l) {
+    const Layer& L = kL[l];
+    ConvArgs a{};
+    a.src0 = ws + p.t[kIO[l][0]];
+    a.src1 = kIO[l][1] >= 0 ? ws + p.t[kIO[l][1]] : nullptr;
+    a.c0 = L.c0;
+    a.c1 = L.c1;
+    a.cip = net::cip_of(L.c0 + L.c1);
+    a.up0 = L.up0;
+    a.n = views;
+    a.h = height >> L.level;
+    a.w = width >> L.level;
+    a.kc = net::kchunks_of(L.c0 + L.c1);
+    a.wsw = (const uint8_t*)n->w_bf16[l];
+    a.bias = n->master + param_offset(l) + (int64_t)L.co * L.ci * 9;
+    a.co = L.co;
+    a.relu = 1;
+    a.out = ws + p.t[kIO[l][2]];
+    a.out_ch = L.co;
+    a.pool_out = kIO[l][3] >= 0 ? ws + p.t[kIO[l][3]] : nullptr;
+    st = net::launch_conv<BF16>(a, net::nblocks_of(L.co), s);
+    if (st != FV_OK) return st;
+  }
+  float* od = out_direct ? out_direct : (float*)(ws + p.od);
+  {
+    const Layer& L = kL[kHead];
+    const float* w = n->master + param_offset(kHead);
+    k_predict<3, 0><<<blocks_of(npx), 256, (3 * L.ci + 3) * 4, s>>>(
+        (const __bf16*)(ws + p.t[T_D0B]), L.ci, w, w + 3 * L.ci, npx, od, nullptr);
+    if ((st = launch_status("wnet: O_d")) != FV_OK) return st;
+  }
+  // K, encoder: J_0 = O_d; filter J_l with ke_l; pool into J_(l+1)
+  float* wk = (float*)(ws + p.wk);
+  float* av = (float*)(ws + p.av);
+  const float* jin = od;
+  for (int l = 0; l < 4; ++l) {
+    const Layer& L = kL[kKe0 + l];
+    const int h = height >> l, w = width >> l;
+    const int64_t m = (int64_t)views * h * w;
+    const float* wl = n->master + param_offset(kKe0 + l);
+    k_predict<kTaps, 1><<<blocks_of(m), 256, (kTaps * L.ci + kTaps) * 4, s>>>(
+        (const __bf16*)(ws + p.t[kHidden[l]]), L.ci, wl, wl + kTaps * L.ci, m, wk, nullptr);
+    float* je = (float*)(ws + p.je[l]);
+    k_apply<<<blocks_of(m), 256, 0, s>>>(wk, jin, views, h, w, je);
+    if (l < 3) {
+      float* nxt = (float*)(ws + p.jin[l + 1]);
+      k_pool3<<<blocks_of(m / 4), 256, 0, s>>>(je, views, h, w, nxt);
+      jin = nxt;
+    }
+    if ((st = launch_status("wnet: K encoder")) != FV_OK) return st;
+  }
+  // K, decoder: from J_3 = Je_3 up to J_0 = the output
+  const float* jc = (const float*)(ws + p.je[3]);
+  for (int l = 2; l >= 0; --l) {
+    const int li = kKd2 + (2 - l);
+    const Layer& L = kL[li];
+    const int h = height >> l, w = width >> l;
+    const int64_t m = (int64_t)views * h * w;
+    const float* wl = n->master + param_offset(li);
+    k_predict<kTaps + 1, 2><<<blocks_of(m), 256, ((kTaps + 1) * L.ci + kTaps + 1) * 4, s>>>(
+        (const __bf16*)(ws + p.t[kHidden[l]]), L.ci, wl, wl + (kTaps + 1) * L.ci, m, wk, av);
+    float* bl = (float*)(ws + p.blend);
+    k_blend<<<blocks_of(m), 256, 0, s>>>((const float*)(ws + p.je[l]), jc, av, views, h, w, bl);
+    float* dst = l ? (float*)(ws + p.jd[l]) : out_rgb;
+    k_apply<<<blocks_of(m), 256, 0, s>>>(wk, bl, views, h, w, dst);
+    if ((st = launch_status("wnet: K decoder")) != FV_OK) return st;
+    jc = dst;
+  }
+  return FV_OK;
+}
+
+}  // extern "C"

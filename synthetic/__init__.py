@@ -309,6 +309,32 @@ WORKLOADS = {
 
 # ------------------------------------------------------- network parameters
 
+# (Ci, Co, k) of the two-stage W-Net's layers (D at the paper's depths, its
+# O_d head, then K's encoder and decoder kernel predictors)
+WNET_SHAPES = [
+    (5, 64, 3), (64, 64, 3), (64, 64, 3), (64, 64, 3), (64, 80, 3), (80, 80, 3),
+    (80, 96, 3), (96, 96, 3), (176, 80, 3), (80, 80, 3), (144, 64, 3), (64, 64, 3),
+    (128, 64, 3), (64, 64, 3), (64, 3, 1),
+    (64, 25, 1), (64, 25, 1), (80, 25, 1), (96, 25, 1), (80, 26, 1), (64, 26, 1), (64, 26, 1),
+]
+
+
+def wnet_init(seed):
+    """Initial W-Net parameters (flat float32): He-normal 3x3 convs, the O_d
+    head N(0, 1/fan_in), kernel predictors N(0, 0.01^2) with a +2 bias on the
+    centre tap (and a zero blend bias); biases otherwise zero."""
+    r = _rng(seed, 6)
+    parts = []
+    for ci, co, k in WNET_SHAPES:
+        fan = ci * k * k
+        std = math.sqrt(2.0 / fan) if k == 3 else (math.sqrt(1.0 / fan) if co == 3 else 0.01)
+        parts.append(r.normal(0.0, std, size=co * ci * k * k))
+        b = np.zeros(co)
+        if co >= 25:
+            b[12] = 2.0
+        parts.append(b)
+    return np.concatenate(parts).astype(np.float32)
+
 # (Ci, Co, k) of the reconstruction network's layers in canonical order
 NET_SHAPES = [
     (5, 32, 3), (32, 32, 3), (32, 48, 3), (48, 48, 3), (48, 64, 3), (64, 64, 3),
