@@ -36,8 +36,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ms/frame foveated+recon vs dense march @1080p at PSNR>=30dB; ray-samples/s"
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+# FP32 vector FLOP of one march sample (an FMA counts 2, a lerp 3): position
+# split 12, trilinear 21, transfer function 16, opacity 3, compositing and the
+# stop test 13, segment distance 2; shading adds the 24 arm differences, three
+# blends and the halving (90) and normalisation + Blinn-Phong (32)
+MARCH_FLOP_PLAIN = 67
+MARCH_FLOP_SHADED = 189
 REC_LEAD = 4  # frames a recurrent network runs before the measured sequence
 BIG_FRAME_PX = 4 << 20  # frame stacks beyond this: the CPU leg works on 1/16 subsets
+WNET_MACS_PER_PX = 223660.5  # the two-stage W-Net at the paper's depths (D and K)
 
 
 def parse():
@@ -50,6 +58,7 @@ def parse():
                     help="sampled rays of one frame marched by the CPU oracle for the "
                          "baseline (0 = all of them)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-wnet", action="store_true", help="skip timing the two-stage W-Net")
     ap.add_argument("--precision", default="fp8", choices=["fp8", "bf16"])
     ap.add_argument("--weights", default=os.path.join(ROOT, "paper_2209_09965_amd", "weights",
                                                       "recon_temporal.npy"))
@@ -445,18 +454,27 @@ def main():
     del seq_f, seq_d, dif
 
     bytes_per_sample = (32 if mp["shading"] else 8) * vol.itemsize
+    flop_per_sample = MARCH_FLOP_SHADED if mp["shading"] else MARCH_FLOP_PLAIN
     sp_avg = sum(sparse_ms) / len(sparse_ms)
-    ach = sparse_samples / args.steps * bytes_per_sample / (sp_avg * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "k_march_sparse", "achieved": round(ach, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+    samples_per_launch = sparse_samples / args.steps
+    ach_gbs = samples_per_launch * bytes_per_sample / (sp_avg * 1e-3) / 1e9
+    ach = samples_per_launch * flop_per_sample / (sp_avg * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "k_march_sparse", "achieved": round(ach, 2),
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / FP32_PEAK_TFLOPS, 4),
                 "traffic": measured_traffic(args.workload),
-                "model": "%d B/sample = %d unique stencil voxels x %d B; %.4g samples/launch" %
-                         (bytes_per_sample, bytes_per_sample // vol.itemsize, vol.itemsize,
-                          sparse_samples / args.steps),
+                "model": "%d FLOP/sample (FP32 vector arithmetic of one %s sample); %.4g "
+                         "samples/launch" % (flop_per_sample,
+                                             "shaded" if mp["shading"] else "unshaded",
+                                             samples_per_launch),
                 "duration": "HIP events around the fv_raymarch_sparse call (counter clear, "
                             "ray set-up pass and k_march_sparse), %.4f ms" % sp_avg,
-                "note": "frac > 1: the stencil voxels are mostly served by L1/L2/MALL; the "
-                        "HBM bytes actually moved are `traffic`"}
+                "bytes_model": {"bytes_per_sample": bytes_per_sample,
+                                "achieved_gbs": round(ach_gbs, 1),
+                                "frac_of_hbm_peak": round(ach_gbs / HBM_PEAK_GBS, 4)},
+                "note": "the stencil voxels are served by L2/MALL (L2 hit rate 0.94); the HBM "
+                        "bytes actually moved (`traffic`) are a few % of the HBM peak, so "
+                        "the bound is the vector ALU issue, not DRAM"}
     dn_avg = sum(dense_kernel_ms) / len(dense_kernel_ms)
     dense_ach = dense_samples / args.steps * bytes_per_sample / (dn_avg * 1e-3) / 1e9
 
@@ -507,6 +525,31 @@ def main():
         "roofline": roofline,
     }
 
+    # the two-stage W-Net (BF16, untrained weights: the time does not depend on
+    # them) on the same frames, timed like the reconstruction stage
+    if not args.no_wnet:
+        wn = b.WNet(synthetic.wnet_init(0))
+        wws = torch.empty(b.WNet.workspace_bytes(V, W, H), dtype=torch.uint8, device=dev)
+        wout = torch.empty(total * 3, dtype=torch.float32, device=dev)
+        b0 = bufs[0]
+        for _ in range(3):
+            wn.reconstruct(b0["frame"], b0["mask"], b0["fdepth"], V, W, H, wout, workspace=wws)
+        wev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(10)]
+        for e in wev:
+            e[0].record()
+            wn.reconstruct(b0["frame"], b0["mask"], b0["fdepth"], V, W, H, wout, workspace=wws)
+            e[1].record()
+        torch.cuda.synchronize()
+        wms = sum(e[0].elapsed_time(e[1]) for e in wev) / len(wev)
+        wn.close()
+        del wws, wout
+        wflop = 2 * WNET_MACS_PER_PX * total
+        out["wnet_bf16"] = {"ms_per_frame": round(wms, 4), "flop_per_px": 2 * WNET_MACS_PER_PX,
+                            "achieved_tflops": round(wflop / (wms * 1e-3) / 1e12, 1),
+                            "peak_tflops": 2500.0,
+                            "note": "two-stage W-Net (D 64/64/80/96 | 80/64/64 + K), BF16, "
+                                    "untrained weights, timed alone"}
+
     if not args.no_cpu and mp["shadow_step"] == 0:
         out["cpu_baseline"] = cpu_baseline(vol, tf, cam_list[last_k], fps[last_k], W, H, V, mp,
                                            args.cpu_rays, np.load(args.weights), args.net_crop,
@@ -555,6 +598,7 @@ def dense_only_bench(args, wl, b, volh, tf, vol, mp, cams_for):
     samples = int(cnt.item())
     bps = (32 if mp["shading"] else 8) * vol.itemsize
     ach = samples / args.steps * bps / (avg * 1e-3) / 1e9
+    fl = samples / args.steps * MARCH_FLOP_PLAIN / (avg * 1e-3) / 1e12
     out = {
         "metric": METRIC, "value": round(wall, 4), "unit": "ms/frame", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall, 4),
@@ -567,14 +611,16 @@ def dense_only_bench(args, wl, b, volh, tf, vol, mp, cams_for):
                    "march": "dense only"},
         "frame_ms_p50_p99": [round(nearest_rank(ms, 50), 4), round(nearest_rank(ms, 99), 4)],
         "ray_samples_per_s": round(samples / (sum(ms) * 1e-3), 1),
-        "roofline": {"bound": "hbm", "kernel": "k_march_dense", "achieved": round(ach, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": None,
-                     "model": "%d B/sample = 8 trilinear voxels x %d B; %.4g samples/launch" %
-                              (bps, vol.itemsize, samples / args.steps),
+        "roofline": {"bound": "alu", "kernel": "k_march_dense", "achieved": round(fl, 3),
+                     "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(fl / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                     "model": "%d FLOP/sample (FP32 vector arithmetic of one unshaded "
+                              "sample); %.4g samples/launch" % (MARCH_FLOP_PLAIN,
+                                                                samples / args.steps),
                      "duration": "HIP events around fv_raymarch_dense, %.4f ms" % avg,
-                     "note": "the 256 KiB volume lives in L2: frac is against HBM only for "
-                             "comparison; the launch is latency-bound at %d rays" % total},
+                     "bytes_model": {"bytes_per_sample": bps, "achieved_gbs": round(ach, 1)},
+                     "note": "the 256 KiB volume lives in L2 and %d rays are about one "
+                             "wave per SIMD: the launch is latency-bound" % total},
     }
     if not args.no_cpu:
         t0 = time.perf_counter()
