@@ -39,6 +39,13 @@ the last).  Readings (the paper leaves these open):
       at level l, the skip connection; up = bilinear x2), giving J_l.  The
       output is J_0 after decoder block 0.
   R5  Every K convolution is 1x1 with a bias, no activation (the logits).
+  R6  The recurrent form (Sec. 3.2.4): each decoder block of D also reads its
+      own output of the previous frame, concatenated last, after
+      [upsampled, skip] (same resolution, so no resampling), and D's input
+      carries the previous frame's O_d as three more channels after the five
+      of the sparse frame (as in net.py's recurrent form).  At a sequence
+      start the fed-back state is zero.  Training carries the state over one
+      step, detached: backward() takes it as a constant input.
 
 Parameters: one flat vector, layers in the order of layers(), each layer's
 weight [Co, Ci, k, k] then its bias [Co].
@@ -51,37 +58,39 @@ PAPER_DEPTHS = (64, 64, 80, 96, 80, 64, 64)
 TAPS = 25
 
 
-def layers(depths=PAPER_DEPTHS, cin=5):
+def layers(depths=PAPER_DEPTHS, cin=5, recurrent=False):
     """(name, Ci, Co, k) of D and K for the depth progression
-    (e0, e1, e2, e3, d2, d1, d0)."""
+    (e0, e1, e2, e3, d2, d1, d0); the recurrent form (R6) reads 3 more input
+    channels and each decoder block's first conv its own previous output."""
     e0, e1, e2, e3, d2, d1, d0 = depths
-    D = [("e0a", cin, e0, 3), ("e0b", e0, e0, 3),
+    r = 1 if recurrent else 0
+    D = [("e0a", cin + 3 * r, e0, 3), ("e0b", e0, e0, 3),
          ("e1a", e0, e1, 3), ("e1b", e1, e1, 3),
          ("e2a", e1, e2, 3), ("e2b", e2, e2, 3),
          ("e3a", e2, e3, 3), ("e3b", e3, e3, 3),
-         ("d2a", e3 + e2, d2, 3), ("d2b", d2, d2, 3),
-         ("d1a", d2 + e1, d1, 3), ("d1b", d1, d1, 3),
-         ("d0a", d1 + e0, d0, 3), ("d0b", d0, d0, 3),
+         ("d2a", e3 + e2 + r * d2, d2, 3), ("d2b", d2, d2, 3),
+         ("d1a", d2 + e1 + r * d1, d1, 3), ("d1b", d1, d1, 3),
+         ("d0a", d1 + e0 + r * d0, d0, 3), ("d0b", d0, d0, 3),
          ("hd", d0, 3, 1)]
     K = [("ke0", d0, TAPS, 1), ("ke1", d1, TAPS, 1), ("ke2", d2, TAPS, 1), ("ke3", e3, TAPS, 1),
          ("kd2", d2, TAPS + 1, 1), ("kd1", d1, TAPS + 1, 1), ("kd0", d0, TAPS + 1, 1)]
     return D + K
 
 
-def n_params(depths=PAPER_DEPTHS, cin=5):
-    return sum(co * ci * k * k + co for _, ci, co, k in layers(depths, cin))
+def n_params(depths=PAPER_DEPTHS, cin=5, recurrent=False):
+    return sum(co * ci * k * k + co for _, ci, co, k in layers(depths, cin, recurrent))
 
 
-def macs_per_px(depths=PAPER_DEPTHS, cin=5):
+def macs_per_px(depths=PAPER_DEPTHS, cin=5, recurrent=False):
     lv = {"e0": 0, "e1": 1, "e2": 2, "e3": 3, "d2": 2, "d1": 1, "d0": 0, "hd": 0,
           "ke0": 0, "ke1": 1, "ke2": 2, "ke3": 3, "kd2": 2, "kd1": 1, "kd0": 0}
     return sum(co * ci * k * k / 4 ** lv[name[:2] if name[0] in "ed" else name]
-               for name, ci, co, k in layers(depths, cin))
+               for name, ci, co, k in layers(depths, cin, recurrent))
 
 
-def unflatten(theta, depths=PAPER_DEPTHS, cin=5):
+def unflatten(theta, depths=PAPER_DEPTHS, cin=5, recurrent=False):
     out, off = {}, 0
-    for name, ci, co, k in layers(depths, cin):
+    for name, ci, co, k in layers(depths, cin, recurrent):
         nw = co * ci * k * k
         out[name] = (theta[off:off + nw].reshape(co, ci, k, k), theta[off + nw:off + nw + co])
         off += nw + co
@@ -90,9 +99,9 @@ def unflatten(theta, depths=PAPER_DEPTHS, cin=5):
     return out
 
 
-def flatten(d, depths=PAPER_DEPTHS, cin=5):
+def flatten(d, depths=PAPER_DEPTHS, cin=5, recurrent=False):
     parts = []
-    for name, _, _, _ in layers(depths, cin):
+    for name, _, _, _ in layers(depths, cin, recurrent):
         w, b = d[name]
         parts += [np.asarray(w, np.float64).reshape(-1), np.asarray(b, np.float64).reshape(-1)]
     return np.concatenate(parts)
@@ -104,10 +113,19 @@ def sigmoid(z):
     return np.where(z >= 0, 1.0 / (1.0 + e), e / (1.0 + e))
 
 
-def forward_d(P, x, c, act_round=lambda t: t):
-    """Network D (R2): returns O_d and records every state in the cache c."""
+def forward_d(P, x, c, act_round=lambda t: t, state=None):
+    """Network D (R2): returns O_d and records every state in the cache c.
+    With a state (the recurrent form, R6) x already carries the fed-back O_d
+    and each decoder block's first conv also reads state[<block output>]."""
     x = act_round(x)
     c["x"] = x
+    c["recurrent"] = state is not None
+
+    def dec_in(low, skip, name):
+        parts = [act_round(N.upsample2(low)), skip]
+        if state is not None:
+            parts.append(state[name])
+        return np.concatenate(parts, axis=1)
 
     def block(na, nb, inp):
         a = act_round(N.relu(N.conv2d(inp, *P[na])))
@@ -119,9 +137,9 @@ def forward_d(P, x, c, act_round=lambda t: t):
     e1 = block("e1a", "e1b", act_round(N.avgpool2(e0)))
     e2 = block("e2a", "e2b", act_round(N.avgpool2(e1)))
     e3 = block("e3a", "e3b", act_round(N.avgpool2(e2)))
-    d2 = block("d2a", "d2b", np.concatenate([act_round(N.upsample2(e3)), e2], axis=1))
-    d1 = block("d1a", "d1b", np.concatenate([act_round(N.upsample2(d2)), e1], axis=1))
-    d0 = block("d0a", "d0b", np.concatenate([act_round(N.upsample2(d1)), e0], axis=1))
+    d2 = block("d2a", "d2b", dec_in(e3, e2, "d2b"))
+    d1 = block("d1a", "d1b", dec_in(d2, e1, "d1b"))
+    d0 = block("d0a", "d0b", dec_in(d1, e0, "d0b"))
     od = N.conv2d(d0, *P["hd"])
     c["od"] = od
     return od
@@ -168,6 +186,42 @@ def forward(theta, x, depths=PAPER_DEPTHS, keep=False, act_round=None):
     return out, od
 
 
+def zero_state(n, h, w, depths=PAPER_DEPTHS):
+    """The recurrent form's state at a sequence start (R6): O_d and the three
+    decoder blocks' outputs, all zero."""
+    _, _, _, _, d2, d1, d0 = depths
+    return {"od": np.zeros((n, 3, h, w)), "d2b": np.zeros((n, d2, h // 4, w // 4)),
+            "d1b": np.zeros((n, d1, h // 2, w // 2)), "d0b": np.zeros((n, d0, h, w))}
+
+
+def forward_recurrent(theta, x, state, depths=PAPER_DEPTHS, keep=False, act_round=None):
+    """One frame of the recurrent form (R6).  x: NCHW, the 5 packed channels;
+    state: the previous frame's (zero_state() at a start).  Returns (out,
+    O_d, the next state) and, with keep, the cache for backward()."""
+    P = unflatten(np.asarray(theta, np.float64), depths, 5, recurrent=True)
+    c = {}
+    xin = np.concatenate([x, state["od"]], axis=1)
+    od = forward_d(P, xin, c, act_round if act_round is not None else (lambda t: t), state)
+    out = forward_k(P, od, hidden_states(c), c)
+    nxt = {"od": od, "d2b": c["d2b"], "d1b": c["d1b"], "d0b": c["d0b"]}
+    if keep:
+        return out, od, nxt, c
+    return out, od, nxt
+
+
+def forward_sequence(theta, xs, depths=PAPER_DEPTHS, act_round=None):
+    """The recurrent form over the frames xs (each NCHW, 5 channels), the
+    state starting at zero.  Returns the lists of outputs and O_d."""
+    n, _, h, w = xs[0].shape
+    state = zero_state(n, h, w, depths)
+    outs, ods = [], []
+    for x in xs:
+        out, od, state = forward_recurrent(theta, x, state, depths, act_round=act_round)
+        outs.append(out)
+        ods.append(od)
+    return outs, ods
+
+
 def _kpn_bwd(wk, img, dout):
     """Adjoint of out = kpn_apply(wk, img) for any channel count of img."""
     n, ch, h, w = img.shape
@@ -191,9 +245,11 @@ def _softmax_bwd(wk, dwk):
 
 
 def backward(theta, c, dout, depths=PAPER_DEPTHS):
-    """Gradient of sum(dout * out) w.r.t. theta (flat, the order of layers())."""
-    cin = c["x"].shape[1]
-    P = unflatten(np.asarray(theta, np.float64), depths, cin)
+    """Gradient of sum(dout * out) w.r.t. theta (flat, the order of layers());
+    in the recurrent form the fed-back state is a constant (R6)."""
+    rec = c.get("recurrent", False)
+    cin = c["x"].shape[1] - (3 if rec else 0)
+    P = unflatten(np.asarray(theta, np.float64), depths, cin, rec)
     H = hidden_states(c)
     g = {}
     dH = [np.zeros_like(h) for h in H]
@@ -240,15 +296,18 @@ def backward(theta, c, dout, depths=PAPER_DEPTHS):
         g[na] = tuple(ga)
         return dinp
 
-    def split_up(dinp, c_up, low):
-        return N.upsample2_bwd(dinp[:, :c_up], low.shape[2], low.shape[3]), dinp[:, c_up:]
+    def split_up(dinp, low, skip):
+        # [upsampled low, skip(, fed-back state: no gradient)]
+        cu, cs = low.shape[1], skip.shape[1]
+        return (N.upsample2_bwd(dinp[:, :cu], low.shape[2], low.shape[3]),
+                dinp[:, cu:cu + cs])
 
     din = block_bwd("d0a", "d0b", extra["d0b"])
-    dd1, de0 = split_up(din, c["d1b"].shape[1], c["d1b"])
+    dd1, de0 = split_up(din, c["d1b"], c["e0b"])
     din = block_bwd("d1a", "d1b", dd1 + extra["d1b"])
-    dd2, de1 = split_up(din, c["d2b"].shape[1], c["d2b"])
+    dd2, de1 = split_up(din, c["d2b"], c["e1b"])
     din = block_bwd("d2a", "d2b", dd2 + extra["d2b"])
-    de3, de2 = split_up(din, c["e3b"].shape[1], c["e3b"])
+    de3, de2 = split_up(din, c["e3b"], c["e2b"])
     dp = block_bwd("e3a", "e3b", de3 + extra["e3b"])
     de2 = de2 + N.avgpool2_bwd(dp)
     dp = block_bwd("e2a", "e2b", de2)
@@ -256,4 +315,4 @@ def backward(theta, c, dout, depths=PAPER_DEPTHS):
     dp = block_bwd("e1a", "e1b", de1)
     de0 = de0 + N.avgpool2_bwd(dp)
     block_bwd("e0a", "e0b", de0)
-    return flatten(g, depths, cin)
+    return flatten(g, depths, cin, rec)

@@ -137,3 +137,156 @@ def test_backward_matches_finite_differences():
         fm = np.sum(WN.forward(tm, x, TINY)[0] * dout)
         fd = (fp - fm) / (2 * eps)
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
+
+
+# ---------------------------------------------------------------- recurrent form (R6)
+
+def _theta_rec(depths, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, ci, co, k in WN.layers(depths, recurrent=True):
+        parts.append(rng.normal(0, scale * np.sqrt(2.0 / (ci * k * k)), co * ci * k * k))
+        parts.append(rng.normal(0, 0.05, co))
+    return np.concatenate(parts)
+
+
+def _state(depths, seed, n=1, h=16, w=16):
+    """A non-negative state, as ReLU outputs are, and an O_d of either sign."""
+    rng = np.random.default_rng(seed)
+    s = WN.zero_state(n, h, w, depths)
+    return {k: (rng.normal(size=v.shape) if k == "od" else rng.random(v.shape))
+            for k, v in s.items()}
+
+
+def test_recurrent_parameter_count():
+    # the plain form plus e0a's 3 fed-back channels (3 x 64 x 9) and each
+    # decoder block's own output (80 x 80 x 9, 64 x 64 x 9, 64 x 64 x 9)
+    assert WN.n_params(recurrent=True) == 798341 + 1728 + 57600 + 36864 + 36864 == 931397
+
+
+def _embed_plain(theta_plain, depths):
+    """The recurrent parameters that give the plain network: the plain
+    weights, zeros on the fed-back input channels (after the 5 frame channels
+    of e0a, after [upsampled, skip] of each decoder block's first conv)."""
+    Pp = WN.unflatten(theta_plain, depths)
+    Pr = {}
+    for name, ci, co, k in WN.layers(depths, recurrent=True):
+        w, b = Pp[name]
+        if w.shape[1] != ci:
+            w = np.concatenate([w, np.zeros((co, ci - w.shape[1], k, k))], axis=1)
+        Pr[name] = (w, b)
+    return WN.flatten(Pr, depths, recurrent=True)
+
+
+def test_recurrent_with_silent_feedback_is_the_plain_wnet():
+    """Zero weights on every fed-back channel: any state leaves out and O_d
+    equal to the plain W-Net's (pins where the fed-back channels sit), and
+    the next state holds this frame's O_d and decoder outputs."""
+    depths = TINY
+    th = _theta(depths, 21, scale=1.5)
+    thr = _embed_plain(th, depths)
+    x = _x(22)
+    out_p, od_p, c = WN.forward(th, x, depths, keep=True)
+    out_r, od_r, nxt = WN.forward_recurrent(thr, x, _state(depths, 23), depths)
+    assert np.allclose(out_r, out_p, rtol=1e-12, atol=1e-13)
+    assert np.allclose(od_r, od_p, rtol=1e-12, atol=1e-13)
+    assert np.array_equal(nxt["od"], od_r)
+    for name in ("d2b", "d1b", "d0b"):
+        assert np.allclose(nxt[name], c[name], rtol=1e-12, atol=1e-13)
+
+
+def test_recurrent_od_feedback_is_net_py_recurrent_form():
+    """With the hidden-state weights zero and the C3 depths, D's O_d equals
+    oracle.net's recurrent form (pinned there) given the same fed-back O_d."""
+    rng = np.random.default_rng(31)
+    theta_u = rng.normal(0, 0.1, N.N_PARAMS_RECURRENT)
+    Pu = N.unflatten(theta_u)
+    Pw = WN.unflatten(_theta_rec(C3, 32), C3, recurrent=True)
+    for name in Pu:
+        if name in Pw:
+            w, b = Pu[name]
+            if Pw[name][0].shape != w.shape:  # decoder first convs: zero hidden weights
+                cw = Pw[name][0].shape[1]
+                w = np.concatenate([w, np.zeros((w.shape[0], cw - w.shape[1], 3, 3))], axis=1)
+            Pw[name] = (w, b)
+    x = _x(33, 1, 16, 24)
+    st = _state(C3, 34, 1, 16, 24)
+    _, od_u = N.forward(theta_u, N.recurrent_input(x, st["od"]))
+    _, od_w, _ = WN.forward_recurrent(WN.flatten(Pw, C3, recurrent=True), x, st, C3)
+    assert np.allclose(od_w, od_u, rtol=1e-12, atol=1e-13)
+
+
+def test_state_carried_through_permuting_blocks():
+    """Each decoder block maps its fed-back output through a channel
+    permutation (first conv: centre tap 1 on hidden channel perm[o], all its
+    other weights and biases 0; second conv: the identity): the block's
+    output is the previous frame's, permuted, whatever the frame.  Over three
+    frames the state is perm^k of the initial one, and O_d = hd(d0b) of it."""
+    depths = TINY
+    P = WN.unflatten(_theta_rec(depths, 41), depths, recurrent=True)
+    rng = np.random.default_rng(42)
+    perms = {}
+    for blk in ("d2", "d1", "d0"):
+        wa, _ = P[blk + "a"]
+        co, ci = wa.shape[:2]
+        perm = rng.permutation(co)
+        wa = np.zeros_like(wa)
+        wa[np.arange(co), ci - co + perm, 1, 1] = 1.0
+        wb = np.zeros((co, co, 3, 3))
+        wb[np.arange(co), np.arange(co), 1, 1] = 1.0
+        P[blk + "a"] = (wa, np.zeros(co))
+        P[blk + "b"] = (wb, np.zeros(co))
+        perms[blk + "b"] = perm
+    th = WN.flatten(P, depths, recurrent=True)
+    st = _state(depths, 43)
+    want = {k: st[k] for k in perms}
+    whd, bhd = P["hd"]
+    for f in range(3):
+        _, od, st = WN.forward_recurrent(th, _x(44 + f), st, depths)
+        want = {k: v[:, perms[k]] for k, v in want.items()}
+        for k in perms:
+            assert np.array_equal(st[k], want[k]), (f, k)
+        od_want = np.einsum("oc,nchw->nohw", whd[:, :, 0, 0], want["d0b"]) + bhd[None, :, None, None]
+        assert np.allclose(od, od_want, rtol=1e-13, atol=1e-14)
+
+
+def test_recurrent_sequence_starts_from_zero_state():
+    depths = TINY
+    th = _theta_rec(depths, 51)
+    xs = [_x(52 + i) for i in range(3)]
+    outs, ods = WN.forward_sequence(th, xs, depths)
+    out0, od0, _ = WN.forward_recurrent(th, xs[0], WN.zero_state(1, 16, 16, depths), depths)
+    assert np.array_equal(outs[0], out0) and np.array_equal(ods[0], od0)
+    # the state matters: the same frame later in the sequence differs
+    outs2, _ = WN.forward_sequence(th, [xs[1], xs[1]], depths)
+    assert np.abs(outs2[1] - outs2[0]).max() > 1e-6
+
+
+def test_recurrent_backward_matches_finite_differences():
+    """The recurrent form's gradient with the fed-back state held constant."""
+    depths = TINY
+    th = _theta_rec(depths, 61, scale=1.5)
+    x = _x(62)
+    st = _state(depths, 63)
+    rng = np.random.default_rng(64)
+    out, _, _, c = WN.forward_recurrent(th, x, st, depths, keep=True)
+    dout = rng.normal(size=out.shape)
+    g = WN.backward(th, c, dout, depths)
+    assert g.shape == th.shape
+    idx, off = [], 0
+    for name, ci, co, k in WN.layers(depths, recurrent=True):
+        nw = co * ci * k * k
+        idx += [off + int(rng.integers(nw)), off + nw + int(rng.integers(co))]
+        if name in ("d2a", "d1a", "d0a", "e0a"):  # weights on the fed-back channels
+            w_idx = np.arange(nw).reshape(co, ci, k, k)[:, ci - (3 if name == "e0a" else co):]
+            idx += list(off + rng.choice(w_idx.reshape(-1), 3, replace=False))
+        off += nw + co
+    eps = 1e-6
+    for i in idx:
+        tp, tm = th.copy(), th.copy()
+        tp[i] += eps
+        tm[i] -= eps
+        fp = np.sum(WN.forward_recurrent(tp, x, st, depths)[0] * dout)
+        fm = np.sum(WN.forward_recurrent(tm, x, st, depths)[0] * dout)
+        fd = (fp - fm) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (i, fd, g[i])
