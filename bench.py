@@ -46,6 +46,7 @@ MARCH_FLOP_SHADED = 189
 REC_LEAD = 4  # frames a recurrent network runs before the measured sequence
 BIG_FRAME_PX = 4 << 20  # frame stacks beyond this: the CPU leg works on 1/16 subsets
 WNET_MACS_PER_PX = 223660.5  # the two-stage W-Net at the paper's depths (D and K)
+WNET_REC_MACS_PER_PX = 275068.5  # its recurrent form
 
 
 def parse():
@@ -542,13 +543,32 @@ def main():
         torch.cuda.synchronize()
         wms = sum(e[0].elapsed_time(e[1]) for e in wev) / len(wev)
         wn.close()
-        del wws, wout
+        # the recurrent form over a sequence of the same frames (state carried)
+        wn = b.WNet(synthetic.wnet_init(0, recurrent=True))
+        wst = torch.empty(b.WNet.state_bytes(V, W, H), dtype=torch.uint8, device=dev)
+        for k in range(3):
+            wn.reconstruct_recurrent(b0["frame"], b0["mask"], b0["fdepth"], wst, k == 0, V, W, H,
+                                     wout, workspace=wws)
+        for e in wev:
+            e[0].record()
+            wn.reconstruct_recurrent(b0["frame"], b0["mask"], b0["fdepth"], wst, False, V, W, H,
+                                     wout, workspace=wws)
+            e[1].record()
+        torch.cuda.synchronize()
+        wrms = sum(e[0].elapsed_time(e[1]) for e in wev) / len(wev)
+        wn.close()
+        del wws, wout, wst
         wflop = 2 * WNET_MACS_PER_PX * total
+        wrflop = 2 * WNET_REC_MACS_PER_PX * total
         out["wnet_bf16"] = {"ms_per_frame": round(wms, 4), "flop_per_px": 2 * WNET_MACS_PER_PX,
                             "achieved_tflops": round(wflop / (wms * 1e-3) / 1e12, 1),
+                            "recurrent_ms_per_frame": round(wrms, 4),
+                            "recurrent_flop_per_px": 2 * WNET_REC_MACS_PER_PX,
+                            "recurrent_achieved_tflops": round(wrflop / (wrms * 1e-3) / 1e12, 1),
                             "peak_tflops": 2500.0,
                             "note": "two-stage W-Net (D 64/64/80/96 | 80/64/64 + K), BF16, "
-                                    "untrained weights, timed alone"}
+                                    "untrained weights, timed alone; recurrent: decoder "
+                                    "hidden states and O_d fed back"}
 
     if not args.no_cpu and mp["shadow_step"] == 0:
         out["cpu_baseline"] = cpu_baseline(vol, tf, cam_list[last_k], fps[last_k], W, H, V, mp,

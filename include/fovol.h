@@ -644,18 +644,55 @@ fv_status fv_render_frame(fv_renderer* r, const fv_volume* vol, const float* tf_
 typedef struct fv_wnet fv_wnet;
 size_t fv_wnet_param_count(void);
 /* Uploads host FP32 parameters and builds D's BF16 weights; synchronises the
- * device.  Errors: null pointers, n_params != FV_WNET_PARAMS, allocation
- * failure (FV_ERR_NOMEM). */
+ * device.  Errors: null pointers, n_params neither FV_WNET_PARAMS nor
+ * FV_WNET_PARAMS_RECURRENT (the recurrent form, below), allocation failure
+ * (FV_ERR_NOMEM). */
 fv_status fv_wnet_create(const float* host_params, size_t n_params, fv_wnet** out);
 fv_status fv_wnet_destroy(fv_wnet* n);
 /* Device workspace of fv_wnet_reconstruct at this size. */
 fv_status fv_wnet_workspace(int views, int width, int height, size_t* bytes);
 /* Full-frame reconstruction by the W-Net; arguments, layouts and errors as
- * fv_reconstruct (out_direct: O_d or NULL). */
+ * fv_reconstruct (out_direct: O_d or NULL).  Error for a recurrent handle. */
 fv_status fv_wnet_reconstruct(const fv_wnet* n, const float* frame_rgba, const uint8_t* mask,
                               const float* frame_depth, int views, int width, int height,
                               float* out_rgb, float* out_direct, void* workspace,
                               size_t ws_bytes, void* stream);
+
+/* The recurrent W-Net (paper Sec. 3.2.4): a state carried from frame to
+ * frame.  D's first conv also reads the previous frame's O_d (packed input
+ * channels 5-7, as fv_reconstruct_recurrent), and the first conv of each
+ * decoder block (d2, d1, d0) also reads that block's own output of the
+ * previous frame, concatenated after [upsampled, skip]; the state is zero at
+ * a sequence start.
+ * Parameters: FV_WNET_PARAMS_RECURRENT floats, the order of the plain form
+ * with e0a's Ci = 8 (the 5 frame channels, then O_d,prev RGB) and the
+ * decoders' first convs reading [upsampled, skip, fed-back]: d2a 96+80+80,
+ * d1a 80+64+64, d0a 64+64+64 input channels.  fv_wnet_create takes either
+ * count and builds the form it names; fv_wnet_is_recurrent tells which.
+ *
+ * State: caller-owned device memory of fv_wnet_state_bytes, 256-byte
+ * aligned, one per sequence (views x W x H).  Layout (fv_wnet_state_layout
+ * gives the byte offsets): O_d float [views*H*W*3]; then d2b, d1b, d0b as
+ * BF16 NHWC at 1/4, 1/2 and full resolution with 80, 64 and 64 channels.
+ * fv_wnet_reconstruct_recurrent reads the state, runs the frame and leaves
+ * this frame's O_d and decoder outputs in it; reset != 0 zeroes it first (a
+ * sequence start).  Calls on one state must be issued in frame order on one
+ * stream.  Other arguments as fv_wnet_reconstruct (out_direct: a copy of
+ * O_d, or NULL).
+ * Errors: as fv_wnet_reconstruct; a null or unaligned state; state_bytes too
+ * small (FV_ERR_CAPACITY); a plain handle. */
+#define FV_WNET_PARAMS_RECURRENT 931397
+size_t fv_wnet_param_count_recurrent(void);
+int fv_wnet_is_recurrent(const fv_wnet* n);
+fv_status fv_wnet_state_bytes(int views, int width, int height, size_t* bytes);
+fv_status fv_wnet_state_layout(int views, int width, int height, size_t* od_offset,
+                               size_t* d2_offset, size_t* d1_offset, size_t* d0_offset);
+fv_status fv_wnet_reconstruct_recurrent(const fv_wnet* n, const float* frame_rgba,
+                                        const uint8_t* mask, const float* frame_depth,
+                                        void* state, size_t state_bytes, int reset, int views,
+                                        int width, int height, float* out_rgb,
+                                        float* out_direct, void* workspace, size_t ws_bytes,
+                                        void* stream);
 
 /* ------------------------------------------------------------------------
  * 5. Training of the reconstruction network (paper: "Loss", "Training")

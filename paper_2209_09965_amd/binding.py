@@ -123,6 +123,12 @@ _SIGS = {
     "fv_wnet_destroy": (_i, [_vp]),
     "fv_wnet_workspace": (_i, [_i, _i, _i, ctypes.POINTER(_sz)]),
     "fv_wnet_reconstruct": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _sz, _vp]),
+    "fv_wnet_param_count_recurrent": (_sz, []),
+    "fv_wnet_is_recurrent": (_i, [_vp]),
+    "fv_wnet_state_bytes": (_i, [_i, _i, _i, ctypes.POINTER(_sz)]),
+    "fv_wnet_state_layout": (_i, [_i, _i, _i] + [ctypes.POINTER(_sz)] * 4),
+    "fv_wnet_reconstruct_recurrent": (_i, [_vp, _vp, _vp, _vp, _vp, _sz, _i, _i, _i, _i, _vp,
+                                           _vp, _vp, _sz, _vp]),
     "fv_reconstruct_tensor": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(_sz),
                                    ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "fv_reconstruct_steps": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp,
@@ -435,7 +441,11 @@ def _prec(p):
 
 
 class WNet:
-    """Library-owned two-stage W-Net (FP32 parameters, BF16 copy of D's convs)."""
+    """Library-owned two-stage W-Net (FP32 parameters, BF16 copy of D's
+    convs), plain or recurrent by the parameter count."""
+
+    PARAMS = 798341
+    PARAMS_RECURRENT = 931397
 
     def __init__(self, params):
         import numpy as np
@@ -443,6 +453,34 @@ class WNet:
         h = ctypes.c_void_p()
         check(_lib.fv_wnet_create(ctypes.c_void_p(arr.ctypes.data), arr.size, ctypes.byref(h)))
         self.handle = h
+        self.recurrent = bool(_lib.fv_wnet_is_recurrent(h))
+
+    @staticmethod
+    def state_bytes(views, width, height):
+        b = _sz()
+        check(_lib.fv_wnet_state_bytes(views, width, height, ctypes.byref(b)))
+        return b.value
+
+    @staticmethod
+    def state_layout(views, width, height):
+        """Byte offsets (O_d, d2b, d1b, d0b) in the recurrent state."""
+        o = [_sz() for _ in range(4)]
+        check(_lib.fv_wnet_state_layout(views, width, height, *[ctypes.byref(x) for x in o]))
+        return tuple(x.value for x in o)
+
+    def reconstruct_recurrent(self, frame_rgba, mask, frame_depth, state, reset, views, width,
+                              height, out_rgb, out_direct=None, workspace=None, stream=None):
+        npx = views * width * height
+        if workspace is None:
+            workspace = torch.empty(self.workspace_bytes(views, width, height), dtype=torch.uint8,
+                                    device=frame_rgba.device)
+        wp, wb = _ws(workspace)
+        sp, sbytes = _ws(state)
+        check(_lib.fv_wnet_reconstruct_recurrent(
+            self.handle, _dev(frame_rgba, "frame_rgba", F32, npx * 4), _dev(mask, "mask", U8, npx),
+            _dev(frame_depth, "frame_depth", F32, npx, False), sp, sbytes, 1 if reset else 0,
+            views, width, height, _dev(out_rgb, "out_rgb", F32, npx * 3),
+            _dev(out_direct, "out_direct", F32, npx * 3, False), wp, wb, _stream(stream)))
 
     def close(self):
         if self.handle:
@@ -469,8 +507,8 @@ class WNet:
             _dev(out_direct, "out_direct", F32, npx * 3, False), wp, wb, _stream(stream)))
 
 
-def wnet_param_count():
-    return int(_lib.fv_wnet_param_count())
+def wnet_param_count(recurrent=False):
+    return int(_lib.fv_wnet_param_count_recurrent() if recurrent else _lib.fv_wnet_param_count())
 
 
 class Net:

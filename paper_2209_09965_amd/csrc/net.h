@@ -98,12 +98,13 @@ struct TrainPlan {
 TrainPlan make_train_plan(int n, int h, int w);
 
 // Shared with the W-Net (wnet.hip): BF16 weight fragments of a 3x3 layer,
-// their element count, the 8-channel BF16 input packing and the frame checks
-// of the reconstruction entry points.
+// their element count, the 8-channel BF16 input packing (the last three the
+// previous O_d, [n h w 3] FP32, or zero when prev is null) and the frame
+// checks of the reconstruction entry points.
 fv_status swizzle_bf16(const float* w, int ci, int co, int transposed, void* out, hipStream_t s);
 size_t swizzled_elems(int in_ch, int out_ch);
 fv_status pack_input_bf16(const float* frame, const uint8_t* mask, const float* depth,
-                          uint8_t* out, int64_t npx, hipStream_t s);
+                          const float* prev, uint8_t* out, int64_t npx, hipStream_t s);
 fv_status check_frame(int views, int W, int H, const char* fn);
 
 }  // namespace net

@@ -418,11 +418,17 @@ fv_status launch_conv(const ConvArgs& args, int nb, hipStream_t s) {
   const int64_t px = (int64_t)a.n * a.h * a.w;
   const int64_t b0 = (a.up0 ? (int64_t)a.n * (a.h >> 1) * (a.w >> 1) : px) * a.c0 * E::kBytes;
   const int64_t b1 = a.src1 ? px * a.c1 * E::kBytes : 0;
-  if (b0 >= ((int64_t)1 << 31) - 64 || b1 >= ((int64_t)1 << 31) - 64)
+  const int64_t b2 = a.src2 ? px * a.c2 * E::kBytes : 0;
+  const int64_t bmax = std::max(b0, std::max(b1, b2));
+  if (bmax >= ((int64_t)1 << 31) - 64)
     return fail(FV_ERR_UNSUPPORTED, "conv: an input tensor of %lld bytes (limit 2 GiB)",
-                (long long)(b0 > b1 ? b0 : b1));
+                (long long)bmax);
+  if (a.src2 && (!a.src1 || (a.c0 + a.c1) % 8 || a.c2 <= 0))
+    return fail(FV_ERR_UNSUPPORTED, "conv: a third source needs the second and 8-aligned groups");
+  if (!a.src2) a.c2 = 0;
   a.src0_bytes = (uint32_t)b0;
   a.src1_bytes = (uint32_t)b1;
+  a.src2_bytes = (uint32_t)b2;
   const int64_t bo = px * a.out_ch * (a.out_fp32 ? 4 : E::kBytes);
   const int64_t bp = a.pool_out ? (int64_t)a.n * (a.h >> 1) * (a.w >> 1) * a.out_ch * E::kBytes : 0;
   if (bo >= ((int64_t)1 << 31) - 64)
@@ -435,7 +441,8 @@ fv_status launch_conv(const ConvArgs& args, int nb, hipStream_t s) {
     return fail(FV_ERR_UNSUPPORTED, "conv: upsampled source with %d channels at %d x %d", a.c0,
                 a.w, a.h);
   // FP8 fill items of 16 channels when no item straddles a source boundary
-  a.wide = E::kBytes == 1 && a.cip % 16 == 0 && a.c0 % 16 == 0 && a.c1 % 16 == 0;
+  a.wide = E::kBytes == 1 && a.cip % 16 == 0 && a.c0 % 16 == 0 && a.c1 % 16 == 0 &&
+           a.c2 % 16 == 0;
   const uint32_t iw = a.wide ? 16u : 8u;
   const uint32_t g0 = a.up0 ? (uint32_t)a.c0 / iw : 0u;
   a.gmagic = magic((uint32_t)a.cip / iw - g0);
@@ -717,9 +724,9 @@ fv_status build_fp8(fv_net* n, hipStream_t s) {
 }
 
 fv_status pack_input_bf16(const float* frame, const uint8_t* mask, const float* depth,
-                          uint8_t* out, int64_t npx, hipStream_t s) {
+                          const float* prev, uint8_t* out, int64_t npx, hipStream_t s) {
   k_pack<BF16><<<(unsigned)((npx + 255) / 256), 256, 0, s>>>((const float4*)frame, mask, depth,
-                                                           nullptr, out, npx, 1.0f, nullptr);
+                                                           prev, out, npx, 1.0f, nullptr);
   return launch_status("pack");
 }
 

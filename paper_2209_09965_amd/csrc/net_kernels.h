@@ -221,7 +221,8 @@ __device__ __forceinline__ void wave_absmax(float* dst, float m) {
 struct ConvArgs {
   const uint8_t* src0;  // NHWC, c0 channels; half resolution if up0
   const uint8_t* src1;  // NHWC, c1 channels (concatenated after src0), or null
-  int c0, c1, cip;      // cip = c0 + c1 rounded up to 8
+  const uint8_t* src2;  // NHWC, c2 channels (concatenated after src1), or null
+  int c0, c1, c2, cip;  // cip = c0 + c1 + c2 rounded up to 8
   int up0;
   int n, h, w;          // output size
   const uint8_t* wsw;   // swizzled weight fragments [kc][nb][64 lanes][kFragBytes]
@@ -235,7 +236,7 @@ struct ConvArgs {
   uint8_t* pool_out;    // 2x2 average of the stored output (half resolution,
                         // out_ch stride), or null
   uint32_t out_bytes, pool_bytes;  // set by launch_conv (buffer-store range checks)
-  uint32_t src0_bytes, src1_bytes;  // sizes for the buffer-load range checks
+  uint32_t src0_bytes, src1_bytes, src2_bytes;  // sizes for the buffer-load range checks
   // set by launch_conv: e / ng == umulhi(e, gmagic) for the ng fill-item
   // channel groups copied from memory (0: ng == 1); umagic likewise for the
   // groups of the low-resolution patch of an upsampled source 0
@@ -541,6 +542,8 @@ __global__ void __launch_bounds__(256)
   const __amdgpu_buffer_rsrc_t r0 = make_rsrc(a.src0, a.src0_bytes);
   const __amdgpu_buffer_rsrc_t r1 =
       make_rsrc(a.src1 ? a.src1 : a.src0, a.src1 ? a.src1_bytes : 0u);
+  const __amdgpu_buffer_rsrc_t r2 =
+      make_rsrc(a.src2 ? a.src2 : a.src0, a.src2 ? a.src2_bytes : 0u);
   // a fill item's load: 16 bytes, or 8 (narrow FP8 items; the upper half
   // is unused)
   auto load16 = [&](__amdgpu_buffer_rsrc_t r, int off) -> Item {
@@ -567,8 +570,12 @@ __global__ void __launch_bounds__(256)
     const uint32_t p = ((uint32_t)b * (uint32_t)a.h + (uint32_t)y) * (uint32_t)a.w + (uint32_t)x;
     if (ch < a.c0)  // (never with an upsampled source 0: then g >= g0)
       return load16(r0, in ? (int)((p * (uint32_t)a.c0 + ch) * E::kBytes) : kOutside);
-    return load16(r1, in && ch < a.c0 + a.c1
-                          ? (int)((p * (uint32_t)a.c1 + (ch - a.c0)) * E::kBytes)
+    const int c01 = a.c0 + a.c1;
+    if (ch < c01 || !a.src2)
+      return load16(r1, in && ch < c01 ? (int)((p * (uint32_t)a.c1 + (ch - a.c0)) * E::kBytes)
+                                       : kOutside);
+    return load16(r2, in && ch < c01 + a.c2
+                          ? (int)((p * (uint32_t)a.c2 + (ch - c01)) * E::kBytes)
                           : kOutside);
   };
   auto store_item = [&](int i, const Item& v) {

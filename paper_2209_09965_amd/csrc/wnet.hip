@@ -14,6 +14,13 @@
 //      J_(l+1); decoder level l predicts 25 logits and a blend logit, blends
 //      the encoder's filtered image with the upsampled coarser one by the
 //      sigmoid of the blend logit and filters the blend.  K runs in FP32.
+//
+// The recurrent form (paper Sec. 3.2.4) keeps a state across frames: the
+// previous frame's O_d, read by D's first conv as three more input channels,
+// and each decoder block's previous output, read by the block's first conv
+// as a third concatenated source after [upsampled, skip].  The decoder
+// blocks write their outputs straight into the state (after the first conv
+// has read the old one), so it costs no copies.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -34,6 +41,7 @@ constexpr int kLayersAll = kConv + 1 + 7;
 struct Layer {
   int ci, co, k, level;
   int c0, c1, up0;  // conv inputs (3x3 layers): channels of source 0 / 1, upsampled source 0
+  int c2;           // channels of the fed-back state (recurrent decoder blocks)
 };
 
 // Parameter order (each weight [Co][Ci][k][k], then the bias [Co]): D's convs
@@ -46,6 +54,18 @@ const Layer kL[kLayersAll] = {
     {80, 96, 3, 3, 80, 0, 0},    {96, 96, 3, 3, 96, 0, 0},   {176, 80, 3, 2, 96, 80, 1},
     {80, 80, 3, 2, 80, 0, 0},    {144, 64, 3, 1, 80, 64, 1}, {64, 64, 3, 1, 64, 0, 0},
     {128, 64, 3, 0, 64, 64, 1},  {64, 64, 3, 0, 64, 0, 0},   {64, 3, 1, 0, 0, 0, 0},
+    {64, kTaps, 1, 0, 0, 0, 0},  {64, kTaps, 1, 1, 0, 0, 0}, {80, kTaps, 1, 2, 0, 0, 0},
+    {96, kTaps, 1, 3, 0, 0, 0},  {80, kTaps + 1, 1, 2, 0, 0, 0},
+    {64, kTaps + 1, 1, 1, 0, 0, 0}, {64, kTaps + 1, 1, 0, 0, 0, 0},
+};
+// The recurrent form: e0a reads the 8 packed channels (the previous O_d
+// last), each decoder block's first conv its own previous output last.
+const Layer kLR[kLayersAll] = {
+    {8, 64, 3, 0, 8, 0, 0},      {64, 64, 3, 0, 64, 0, 0},   {64, 64, 3, 1, 64, 0, 0},
+    {64, 64, 3, 1, 64, 0, 0},    {64, 80, 3, 2, 64, 0, 0},   {80, 80, 3, 2, 80, 0, 0},
+    {80, 96, 3, 3, 80, 0, 0},    {96, 96, 3, 3, 96, 0, 0},   {256, 80, 3, 2, 96, 80, 1, 80},
+    {80, 80, 3, 2, 80, 0, 0},    {208, 64, 3, 1, 80, 64, 1, 64}, {64, 64, 3, 1, 64, 0, 0},
+    {192, 64, 3, 0, 64, 64, 1, 64}, {64, 64, 3, 0, 64, 0, 0}, {64, 3, 1, 0, 0, 0, 0},
     {64, kTaps, 1, 0, 0, 0, 0},  {64, kTaps, 1, 1, 0, 0, 0}, {80, kTaps, 1, 2, 0, 0, 0},
     {96, kTaps, 1, 3, 0, 0, 0},  {80, kTaps + 1, 1, 2, 0, 0, 0},
     {64, kTaps + 1, 1, 1, 0, 0, 0}, {64, kTaps + 1, 1, 0, 0, 0, 0},
@@ -69,13 +89,23 @@ const int kIO[kConv][4] = {
     {T_D1B, T_E0B, T_D0A, -1}, {T_D0A, -1, T_D0B, -1}};
 // K's hidden states H_0..H_3
 const int kHidden[4] = {T_D0B, T_D1B, T_D2B, T_E3B};
+// per conv: the fed-back tensor its first conv reads (recurrent form), or -1
+const int kFeed[kConv] = {-1, -1, -1, -1, -1, -1, -1, -1, T_D2B, -1, T_D1B, -1, T_D0B, -1};
 
-int64_t param_offset(int layer) {
+int64_t param_offset(const Layer* L, int layer) {
   int64_t off = 0;
-  for (int l = 0; l < layer; ++l)
-    off += (int64_t)kL[l].co * kL[l].ci * kL[l].k * kL[l].k + kL[l].co;
+  for (int l = 0; l < layer; ++l) off += (int64_t)L[l].co * L[l].ci * L[l].k * L[l].k + L[l].co;
   return off;
 }
+int64_t param_offset(int layer) { return param_offset(kL, layer); }
+
+// The recurrent state, caller-owned device memory: O_d (FP32 [n h w 3]),
+// then D's decoder outputs d2b, d1b, d0b (BF16 NHWC at 1/4, 1/2 and full
+// resolution), each 256-byte aligned.
+struct StatePlan {
+  size_t od, t[kTensors];  // t[] set for T_D2B, T_D1B, T_D0B
+  size_t bytes;
+};
 
 static size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
@@ -89,6 +119,25 @@ struct Plan {
   size_t od, wk, av, jin[4], je[4], blend, jd[3];
   size_t bytes;
 };
+
+StatePlan make_state_plan(int n, int h, int w) {
+  StatePlan p{};
+  auto px = [&](int lv) { return (size_t)n * (h >> lv) * (w >> lv); };
+  size_t off = 0;
+  p.od = off;
+  off += al(px(0) * 3 * 4);
+  for (int t : {T_D2B, T_D1B, T_D0B}) {
+    p.t[t] = off;
+    off += al(px(kTC[t][1]) * kTC[t][0] * 2);
+  }
+  p.bytes = off;
+  return p;
+}
+
+__global__ void __launch_bounds__(256) k_zero(uint4* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
 
 Plan make_plan(int n, int h, int w) {
   Plan p;
@@ -261,33 +310,167 @@ static unsigned blocks_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 struct fv_wnet {
   int device;
-  float* master;                       // FP32 parameters, the order of fv::wnet::kL
+  int recurrent;                       // 1: the recurrent form (table kLR)
+  const fv::wnet::Layer* L;            // its layer table
+  float* master;                       // FP32 parameters, the order of the layer table
   void* w_bf16[fv::wnet::kConv];       // D's convs as swizzled BF16 MFMA fragments
 };
 
 using namespace fv;
 using namespace fv::wnet;
 
+namespace {
+
+fv_status reconstruct(const fv_wnet* n, const float* frame_rgba, const uint8_t* mask,
+                      const float* frame_depth, void* state, size_t state_bytes, int reset,
+                      int views, int width, int height, float* out_rgb, float* out_direct,
+                      void* workspace, size_t ws_bytes, void* stream, const char* fn) {
+  if (!n || !frame_rgba || !mask || !out_rgb || !workspace)
+    return fail(FV_ERR_INVALID_ARG, "%s: null pointer", fn);
+  const bool rec = state != nullptr;
+  if (rec != (n->recurrent != 0))
+    return fail(FV_ERR_INVALID_ARG,
+                n->recurrent ? "%s: a recurrent network needs fv_wnet_reconstruct_recurrent"
+                             : "%s: the plain network has no state (fv_wnet_reconstruct)",
+                fn);
+  fv_status st = net::check_frame(views, width, height, fn);
+  if (st != FV_OK) return st;
+  const Plan p = make_plan(views, height, width);
+  if (ws_bytes < p.bytes)
+    return fail(FV_ERR_CAPACITY, "%s: workspace %zu < %zu bytes", fn, ws_bytes, p.bytes);
+  if ((uintptr_t)workspace % 256)
+    return fail(FV_ERR_INVALID_ARG, "%s: workspace not 256-byte aligned", fn);
+  const StatePlan sp = make_state_plan(views, height, width);
+  if (rec && state_bytes < sp.bytes)
+    return fail(FV_ERR_CAPACITY, "%s: state %zu < %zu bytes", fn, state_bytes, sp.bytes);
+  if (rec && (uintptr_t)state % 256)
+    return fail(FV_ERR_INVALID_ARG, "%s: state not 256-byte aligned", fn);
+  hipStream_t s = (hipStream_t)stream;
+  uint8_t* ws = (uint8_t*)workspace;
+  uint8_t* sb = (uint8_t*)state;
+  const int64_t npx = (int64_t)views * height * width;
+  // D's tensors: the decoder outputs of the recurrent form live in the state
+  auto tensor = [&](int t) -> uint8_t* {
+    if (rec && (t == T_D2B || t == T_D1B || t == T_D0B)) return sb + sp.t[t];
+    return ws + p.t[t];
+  };
+  if (rec && reset) {
+    const int64_t n16 = (int64_t)(sp.bytes / 16);
+    k_zero<<<blocks_of(n16), 256, 0, s>>>((uint4*)sb, n16);
+    if ((st = launch_status("wnet: state reset")) != FV_OK) return st;
+  }
+  float* od_state = rec ? (float*)(sb + sp.od) : nullptr;
+  // D: the packed input (with the previous O_d in the recurrent form), the
+  // 14 convs (pooling fused into e0b, e1b, e2b), O_d
+  st = net::pack_input_bf16(frame_rgba, mask, frame_depth, od_state, ws + p.t[T_IN], npx, s);
+  if (st != FV_OK) return st;
+  const Layer* LT = n->L;
+  for (int l = 0; l < kConv; ++l) {
+    const Layer& L = LT[l];
+    ConvArgs a{};
+    a.src0 = tensor(kIO[l][0]);
+    a.src1 = kIO[l][1] >= 0 ? tensor(kIO[l][1]) : nullptr;
+    a.src2 = rec && kFeed[l] >= 0 ? tensor(kFeed[l]) : nullptr;
+    a.c0 = L.c0;
+    a.c1 = L.c1;
+    a.c2 = a.src2 ? L.c2 : 0;
+    a.cip = net::cip_of(L.c0 + L.c1 + a.c2);
+    a.up0 = L.up0;
+    a.n = views;
+    a.h = height >> L.level;
+    a.w = width >> L.level;
+    a.kc = net::kchunks_of(L.c0 + L.c1 + a.c2);
+    a.wsw = (const uint8_t*)n->w_bf16[l];
+    a.bias = n->master + param_offset(LT, l) + (int64_t)L.co * L.ci * 9;
+    a.co = L.co;
+    a.relu = 1;
+    a.out = tensor(kIO[l][2]);
+    a.out_ch = L.co;
+    a.pool_out = kIO[l][3] >= 0 ? tensor(kIO[l][3]) : nullptr;
+    st = net::launch_conv<BF16>(a, net::nblocks_of(L.co), s);
+    if (st != FV_OK) return st;
+  }
+  float* od = rec ? od_state : out_direct ? out_direct : (float*)(ws + p.od);
+  {
+    const Layer& L = LT[kHead];
+    const float* w = n->master + param_offset(LT, kHead);
+    k_predict<3, 0><<<blocks_of(npx), 256, (3 * L.ci + 3) * 4, s>>>(
+        (const __bf16*)tensor(T_D0B), L.ci, w, w + 3 * L.ci, npx, od, nullptr);
+    if ((st = launch_status("wnet: O_d")) != FV_OK) return st;
+  }
+  if (rec && out_direct &&
+      (st = hip_status(hipMemcpyAsync(out_direct, od, npx * 3 * sizeof(float),
+                                      hipMemcpyDeviceToDevice, s), "wnet: O_d copy")) != FV_OK)
+    return st;
+  // K, encoder: J_0 = O_d; filter J_l with ke_l; pool into J_(l+1)
+  float* wk = (float*)(ws + p.wk);
+  float* av = (float*)(ws + p.av);
+  const float* jin = od;
+  for (int l = 0; l < 4; ++l) {
+    const Layer& L = LT[kKe0 + l];
+    const int h = height >> l, w = width >> l;
+    const int64_t m = (int64_t)views * h * w;
+    const float* wl = n->master + param_offset(LT, kKe0 + l);
+    k_predict<kTaps, 1><<<blocks_of(m), 256, (kTaps * L.ci + kTaps) * 4, s>>>(
+        (const __bf16*)tensor(kHidden[l]), L.ci, wl, wl + kTaps * L.ci, m, wk, nullptr);
+    float* je = (float*)(ws + p.je[l]);
+    k_apply<<<blocks_of(m), 256, 0, s>>>(wk, jin, views, h, w, je);
+    if (l < 3) {
+      float* nxt = (float*)(ws + p.jin[l + 1]);
+      k_pool3<<<blocks_of(m / 4), 256, 0, s>>>(je, views, h, w, nxt);
+      jin = nxt;
+    }
+    if ((st = launch_status("wnet: K encoder")) != FV_OK) return st;
+  }
+  // K, decoder: from J_3 = Je_3 up to J_0 = the output
+  const float* jc = (const float*)(ws + p.je[3]);
+  for (int l = 2; l >= 0; --l) {
+    const int li = kKd2 + (2 - l);
+    const Layer& L = LT[li];
+    const int h = height >> l, w = width >> l;
+    const int64_t m = (int64_t)views * h * w;
+    const float* wl = n->master + param_offset(LT, li);
+    k_predict<kTaps + 1, 2><<<blocks_of(m), 256, ((kTaps + 1) * L.ci + kTaps + 1) * 4, s>>>(
+        (const __bf16*)tensor(kHidden[l]), L.ci, wl, wl + (kTaps + 1) * L.ci, m, wk, av);
+    float* bl = (float*)(ws + p.blend);
+    k_blend<<<blocks_of(m), 256, 0, s>>>((const float*)(ws + p.je[l]), jc, av, views, h, w, bl);
+    float* dst = l ? (float*)(ws + p.jd[l]) : out_rgb;
+    k_apply<<<blocks_of(m), 256, 0, s>>>(wk, bl, views, h, w, dst);
+    if ((st = launch_status("wnet: K decoder")) != FV_OK) return st;
+    jc = dst;
+  }
+  return FV_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
-size_t fv_wnet_param_count(void) { return (size_t)param_offset(kLayersAll); }
+size_t fv_wnet_param_count(void) { return (size_t)param_offset(kL, kLayersAll); }
+size_t fv_wnet_param_count_recurrent(void) { return (size_t)param_offset(kLR, kLayersAll); }
 
 fv_status fv_wnet_create(const float* host_params, size_t n_params, fv_wnet** out) {
   clear_error();
   if (!host_params || !out) return fail(FV_ERR_INVALID_ARG, "fv_wnet_create: null pointer");
-  const int64_t P = param_offset(kLayersAll);
-  if ((int64_t)n_params != P)
-    return fail(FV_ERR_INVALID_ARG, "fv_wnet_create: %zu parameters, expected %lld", n_params,
-                (long long)P);
+  const int64_t P0 = param_offset(kL, kLayersAll), P1 = param_offset(kLR, kLayersAll);
+  if ((int64_t)n_params != P0 && (int64_t)n_params != P1)
+    return fail(FV_ERR_INVALID_ARG,
+                "fv_wnet_create: %zu parameters, expected %lld (plain) or %lld (recurrent)",
+                n_params, (long long)P0, (long long)P1);
   fv_wnet* n = new fv_wnet();
   std::memset(n->w_bf16, 0, sizeof n->w_bf16);
+  n->recurrent = (int64_t)n_params == P1;
+  n->L = n->recurrent ? kLR : kL;
+  n->master = nullptr;
+  const int64_t P = (int64_t)n_params;
   if (hipGetDevice(&n->device) != hipSuccess) {
     delete n;
     return fail(FV_ERR_DEVICE, "fv_wnet_create: hipGetDevice");
   }
   bool ok = hipMalloc(&n->master, P * sizeof(float)) == hipSuccess;
   for (int l = 0; ok && l < kConv; ++l)
-    ok = hipMalloc(&n->w_bf16[l], net::swizzled_elems(kL[l].ci, kL[l].co) * 2) == hipSuccess;
+    ok = hipMalloc(&n->w_bf16[l], net::swizzled_elems(n->L[l].ci, n->L[l].co) * 2) ==
+         hipSuccess;
   if (!ok) {
     fv_wnet_destroy(n);
     return fail(FV_ERR_NOMEM, "fv_wnet_create: allocation");
@@ -295,8 +478,8 @@ fv_status fv_wnet_create(const float* host_params, size_t n_params, fv_wnet** ou
   fv_status st = hip_status(hipMemcpy(n->master, host_params, P * sizeof(float),
                                       hipMemcpyHostToDevice), "fv_wnet_create: upload");
   for (int l = 0; st == FV_OK && l < kConv; ++l)
-    st = net::swizzle_bf16(n->master + param_offset(l), kL[l].ci, kL[l].co, 0, n->w_bf16[l],
-                           nullptr);
+    st = net::swizzle_bf16(n->master + param_offset(n->L, l), n->L[l].ci, n->L[l].co, 0,
+                           n->w_bf16[l], nullptr);
   if (st == FV_OK) st = hip_status(hipDeviceSynchronize(), "fv_wnet_create: sync");
   if (st != FV_OK) {
     fv_wnet_destroy(n);
@@ -315,6 +498,8 @@ fv_status fv_wnet_destroy(fv_wnet* n) {
   return FV_OK;
 }
 
+int fv_wnet_is_recurrent(const fv_wnet* n) { return n && n->recurrent ? 1 : 0; }
+
 fv_status fv_wnet_workspace(int views, int width, int height, size_t* bytes) {
   clear_error();
   if (!bytes) return fail(FV_ERR_INVALID_ARG, "fv_wnet_workspace: null bytes");
@@ -324,96 +509,50 @@ fv_status fv_wnet_workspace(int views, int width, int height, size_t* bytes) {
   return FV_OK;
 }
 
+fv_status fv_wnet_state_bytes(int views, int width, int height, size_t* bytes) {
+  clear_error();
+  if (!bytes) return fail(FV_ERR_INVALID_ARG, "fv_wnet_state_bytes: null bytes");
+  fv_status st = net::check_frame(views, width, height, "fv_wnet_state_bytes");
+  if (st != FV_OK) return st;
+  *bytes = make_state_plan(views, height, width).bytes;
+  return FV_OK;
+}
+
+fv_status fv_wnet_state_layout(int views, int width, int height, size_t* od_offset,
+                               size_t* d2_offset, size_t* d1_offset, size_t* d0_offset) {
+  clear_error();
+  if (!od_offset || !d2_offset || !d1_offset || !d0_offset)
+    return fail(FV_ERR_INVALID_ARG, "fv_wnet_state_layout: null pointer");
+  fv_status st = net::check_frame(views, width, height, "fv_wnet_state_layout");
+  if (st != FV_OK) return st;
+  const StatePlan sp = make_state_plan(views, height, width);
+  *od_offset = sp.od;
+  *d2_offset = sp.t[T_D2B];
+  *d1_offset = sp.t[T_D1B];
+  *d0_offset = sp.t[T_D0B];
+  return FV_OK;
+}
+
 fv_status fv_wnet_reconstruct(const fv_wnet* n, const float* frame_rgba, const uint8_t* mask,
                               const float* frame_depth, int views, int width, int height,
                               float* out_rgb, float* out_direct, void* workspace,
                               size_t ws_bytes, void* stream) {
   clear_error();
-  const char* fn = "fv_wnet_reconstruct";
-  if (!n || !frame_rgba || !mask || !out_rgb || !workspace)
-    return fail(FV_ERR_INVALID_ARG, "%s: null pointer", fn);
-  fv_status st = net::check_frame(views, width, height, fn);
-  if (st != FV_OK) return st;
-  const Plan p = make_plan(views, height, width);
-  if (ws_bytes < p.bytes)
-    return fail(FV_ERR_CAPACITY, "%s: workspace %zu < %zu bytes", fn, ws_bytes, p.bytes);
-  if ((uintptr_t)workspace % 256)
-    return fail(FV_ERR_INVALID_ARG, "%s: workspace not 256-byte aligned", fn);
-  hipStream_t s = (hipStream_t)stream;
-  uint8_t* ws = (uint8_t*)workspace;
-  const int64_t npx = (int64_t)views * height * width;
-  // D: the packed input, the 14 convs (pooling fused into e0b, e1b, e2b), O_d
-  st = net::pack_input_bf16(frame_rgba, mask, frame_depth, ws + p.t[T_IN], npx, s);
-  if (st != FV_OK) return st;
-  for (int l = 0; l < kConv; ++l) {
-    const Layer& L = kL[l];
-    ConvArgs a{};
-    a.src0 = ws + p.t[kIO[l][0]];
-    a.src1 = kIO[l][1] >= 0 ? ws + p.t[kIO[l][1]] : nullptr;
-    a.c0 = L.c0;
-    a.c1 = L.c1;
-    a.cip = net::cip_of(L.c0 + L.c1);
-    a.up0 = L.up0;
-    a.n = views;
-    a.h = height >> L.level;
-    a.w = width >> L.level;
-    a.kc = net::kchunks_of(L.c0 + L.c1);
-    a.wsw = (const uint8_t*)n->w_bf16[l];
-    a.bias = n->master + param_offset(l) + (int64_t)L.co * L.ci * 9;
-    a.co = L.co;
-    a.relu = 1;
-    a.out = ws + p.t[kIO[l][2]];
-    a.out_ch = L.co;
-    a.pool_out = kIO[l][3] >= 0 ? ws + p.t[kIO[l][3]] : nullptr;
-    st = net::launch_conv<BF16>(a, net::nblocks_of(L.co), s);
-    if (st != FV_OK) return st;
-  }
-  float* od = out_direct ? out_direct : (float*)(ws + p.od);
-  {
-    const Layer& L = kL[kHead];
-    const float* w = n->master + param_offset(kHead);
-    k_predict<3, 0><<<blocks_of(npx), 256, (3 * L.ci + 3) * 4, s>>>(
-        (const __bf16*)(ws + p.t[T_D0B]), L.ci, w, w + 3 * L.ci, npx, od, nullptr);
-    if ((st = launch_status("wnet: O_d")) != FV_OK) return st;
-  }
-  // K, encoder: J_0 = O_d; filter J_l with ke_l; pool into J_(l+1)
-  float* wk = (float*)(ws + p.wk);
-  float* av = (float*)(ws + p.av);
-  const float* jin = od;
-  for (int l = 0; l < 4; ++l) {
-    const Layer& L = kL[kKe0 + l];
-    const int h = height >> l, w = width >> l;
-    const int64_t m = (int64_t)views * h * w;
-    const float* wl = n->master + param_offset(kKe0 + l);
-    k_predict<kTaps, 1><<<blocks_of(m), 256, (kTaps * L.ci + kTaps) * 4, s>>>(
-        (const __bf16*)(ws + p.t[kHidden[l]]), L.ci, wl, wl + kTaps * L.ci, m, wk, nullptr);
-    float* je = (float*)(ws + p.je[l]);
-    k_apply<<<blocks_of(m), 256, 0, s>>>(wk, jin, views, h, w, je);
-    if (l < 3) {
-      float* nxt = (float*)(ws + p.jin[l + 1]);
-      k_pool3<<<blocks_of(m / 4), 256, 0, s>>>(je, views, h, w, nxt);
-      jin = nxt;
-    }
-    if ((st = launch_status("wnet: K encoder")) != FV_OK) return st;
-  }
-  // K, decoder: from J_3 = Je_3 up to J_0 = the output
-  const float* jc = (const float*)(ws + p.je[3]);
-  for (int l = 2; l >= 0; --l) {
-    const int li = kKd2 + (2 - l);
-    const Layer& L = kL[li];
-    const int h = height >> l, w = width >> l;
-    const int64_t m = (int64_t)views * h * w;
-    const float* wl = n->master + param_offset(li);
-    k_predict<kTaps + 1, 2><<<blocks_of(m), 256, ((kTaps + 1) * L.ci + kTaps + 1) * 4, s>>>(
-        (const __bf16*)(ws + p.t[kHidden[l]]), L.ci, wl, wl + (kTaps + 1) * L.ci, m, wk, av);
-    float* bl = (float*)(ws + p.blend);
-    k_blend<<<blocks_of(m), 256, 0, s>>>((const float*)(ws + p.je[l]), jc, av, views, h, w, bl);
-    float* dst = l ? (float*)(ws + p.jd[l]) : out_rgb;
-    k_apply<<<blocks_of(m), 256, 0, s>>>(wk, bl, views, h, w, dst);
-    if ((st = launch_status("wnet: K decoder")) != FV_OK) return st;
-    jc = dst;
-  }
-  return FV_OK;
+  return reconstruct(n, frame_rgba, mask, frame_depth, nullptr, 0, 0, views, width, height,
+                     out_rgb, out_direct, workspace, ws_bytes, stream, "fv_wnet_reconstruct");
+}
+
+fv_status fv_wnet_reconstruct_recurrent(const fv_wnet* n, const float* frame_rgba,
+                                        const uint8_t* mask, const float* frame_depth,
+                                        void* state, size_t state_bytes, int reset, int views,
+                                        int width, int height, float* out_rgb,
+                                        float* out_direct, void* workspace, size_t ws_bytes,
+                                        void* stream) {
+  clear_error();
+  if (!state) return fail(FV_ERR_INVALID_ARG, "fv_wnet_reconstruct_recurrent: null state");
+  return reconstruct(n, frame_rgba, mask, frame_depth, state, state_bytes, reset, views, width,
+                     height, out_rgb, out_direct, workspace, ws_bytes, stream,
+                     "fv_wnet_reconstruct_recurrent");
 }
 
 }  // extern "C"

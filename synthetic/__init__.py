@@ -319,13 +319,20 @@ WNET_SHAPES = [
 ]
 
 
-def wnet_init(seed):
+# the recurrent form: e0a also reads the previous O_d (3 channels), each
+# decoder block's first conv its own previous output
+WNET_SHAPES_RECURRENT = [(8, 64, 3)] + WNET_SHAPES[1:8] + [(256, 80, 3), (80, 80, 3),
+                                                          (208, 64, 3), (64, 64, 3),
+                                                          (192, 64, 3)] + WNET_SHAPES[13:]
+
+
+def wnet_init(seed, recurrent=False):
     """Initial W-Net parameters (flat float32): He-normal 3x3 convs, the O_d
     head N(0, 1/fan_in), kernel predictors N(0, 0.01^2) with a +2 bias on the
     centre tap (and a zero blend bias); biases otherwise zero."""
     r = _rng(seed, 6)
     parts = []
-    for ci, co, k in WNET_SHAPES:
+    for ci, co, k in (WNET_SHAPES_RECURRENT if recurrent else WNET_SHAPES):
         fan = ci * k * k
         std = math.sqrt(2.0 / fan) if k == 3 else (math.sqrt(1.0 / fan) if co == 3 else 0.01)
         parts.append(r.normal(0.0, std, size=co * ci * k * k))

@@ -117,3 +117,230 @@ def test_wnet_batch_of_identical_views(dev):
     (o1, d1), (o2, d2) = outs
     assert np.array_equal(o2[0], o2[1]) and np.array_equal(d2[0], d2[1])
     assert np.array_equal(o2[0], o1[0]) and np.array_equal(d2[0], d1[0])
+
+
+# ------------------------------------------------ recurrent form (paper Sec. 3.2.4)
+
+def _theta_rec(seed):
+    rng = np.random.default_rng(seed)
+    parts = []
+    for name, ci, co, k in WN.layers(recurrent=True):
+        parts.append(rng.normal(0, np.sqrt(2.0 / (ci * k * k)), co * ci * k * k))
+        b = rng.normal(0, 0.05, co)
+        if name.startswith("k"):
+            b[12] += 2.0
+        parts.append(b)
+    return np.concatenate(parts).astype(np.float32)
+
+
+def _bf16_d_weights_rec(theta):
+    th = theta.astype(np.float64).copy()
+    off = 0
+    for name, ci, co, k in WN.layers(recurrent=True):
+        nw = co * ci * k * k
+        if k == 3:
+            th[off:off + nw] = N.bf16_round(th[off:off + nw])
+        off += nw + co
+    return th
+
+
+_STATE_KEYS = ("od", "d2b", "d1b", "d0b")
+
+
+def _state_put(b, state_t, st, views, H, W):
+    """Writes an oracle state (NCHW arrays) into the library's state buffer."""
+    offs = b.WNet.state_layout(views, W, H)
+    for key, off in zip(_STATE_KEYS, offs):
+        a = np.ascontiguousarray(st[key].transpose(0, 2, 3, 1))
+        if key == "od":
+            t = torch.from_numpy(a.astype(np.float32)).reshape(-1)
+        else:
+            t = torch.from_numpy(a).to(torch.bfloat16).reshape(-1)
+        raw = t.view(torch.uint8)
+        state_t[off:off + raw.numel()].copy_(raw.to(state_t.device))
+
+
+def _state_get(b, state_t, views, H, W):
+    """The library's state as NCHW float64 arrays."""
+    offs = b.WNet.state_layout(views, W, H)
+    ch = {"od": (3, 0), "d2b": (80, 2), "d1b": (64, 1), "d0b": (64, 0)}
+    out = {}
+    for key, off in zip(_STATE_KEYS, offs):
+        c, lv = ch[key]
+        h, w = H >> lv, W >> lv
+        n = views * h * w * c
+        if key == "od":
+            t = state_t[off:off + 4 * n].view(torch.float32)
+        else:
+            t = state_t[off:off + 2 * n].view(torch.bfloat16).float()
+        out[key] = t.cpu().numpy().astype(np.float64).reshape(views, h, w, c).transpose(0, 3, 1, 2)
+    return out
+
+
+def test_recurrent_param_count_and_form():
+    from paper_2209_09965_amd import binding as b
+    assert b.wnet_param_count(recurrent=True) == WN.n_params(recurrent=True) == 931397
+    net = b.WNet(_theta_rec(1))
+    plain = b.WNet(_theta(1))
+    try:
+        assert net.recurrent and not plain.recurrent
+    finally:
+        net.close()
+        plain.close()
+
+
+def test_recurrent_host_errors(dev):
+    """Each form refuses the other's call; a short or unaligned state."""
+    from paper_2209_09965_amd import binding as b
+    V, H, W = 1, 16, 16
+    rng = np.random.default_rng(2)
+    rgba, mask, depth = _frame(rng, V, H, W)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).reshape(-1).to(dev)
+    out = torch.zeros(V * H * W * 3, device=dev)
+    sb = b.WNet.state_bytes(V, W, H)
+    state = torch.zeros(sb + 256, dtype=torch.uint8, device=dev)
+    net, plain = b.WNet(_theta_rec(3)), b.WNet(_theta(3))
+    try:
+        with pytest.raises(b.FvError):
+            net.reconstruct(t(rgba), t(mask), t(depth), V, W, H, out)
+        with pytest.raises(b.FvError):
+            plain.reconstruct_recurrent(t(rgba), t(mask), t(depth), state, True, V, W, H, out)
+        with pytest.raises(b.FvError) as e:
+            net.reconstruct_recurrent(t(rgba), t(mask), t(depth), state[:sb - 256], True, V, W,
+                                      H, out)
+        assert e.value.status == b.FV_ERR_CAPACITY
+        with pytest.raises(b.FvError):
+            net.reconstruct_recurrent(t(rgba), t(mask), t(depth), state[8:8 + sb], True, V, W, H,
+                                      out)
+        torch.cuda.synchronize()
+    finally:
+        net.close()
+        plain.close()
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("views,H,W", [(1, 64, 64), (2, 40, 56)])
+def test_recurrent_wnet_frame_by_frame(views, H, W, dev):
+    """Three frames; before each, the oracle's state (its own emulated one)
+    is installed in the library's state buffer, so each frame is compared on
+    equal inputs: out and O_d as for the plain form, and the state the frame
+    leaves (O_d and the three decoder outputs) against the oracle's next
+    state."""
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(70 + views + H)
+    theta = _theta_rec(17 + H)
+    thq, thx = _bf16_d_weights_rec(theta), theta.astype(np.float64)
+    net = b.WNet(theta)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).reshape(-1).to(dev)
+    state = torch.zeros(b.WNet.state_bytes(views, W, H), dtype=torch.uint8, device=dev)
+    st = WN.zero_state(views, H, W)
+    out = torch.full((views * H * W * 3,), float("nan"), device=dev)
+    od = torch.full_like(out, float("nan"))
+    for f in range(3):
+        rgba, mask, depth = _frame(rng, views, H, W)
+        _state_put(b, state, st, views, H, W)
+        net.reconstruct_recurrent(t(rgba), t(mask), t(depth), state, False, views, W, H, out, od)
+        torch.cuda.synchronize()
+        x = oracle.pack_input(rgba, mask, depth).reshape(views, H, W, 5).transpose(0, 3, 1, 2)
+        x = np.ascontiguousarray(x)
+        want, want_od, nxt = WN.forward_recurrent(thq, x, st, act_round=N.bf16_round)
+        exact, exact_od, nxt_x = WN.forward_recurrent(thx, x, st)
+        to = lambda a: a.cpu().numpy().reshape(views, H, W, 3).transpose(0, 3, 1, 2)
+        gs = _state_get(b, state, views, H, W)
+        cases = [("out", to(out), want, exact, 0.5), ("O_d", to(od), want_od, exact_od, 0.75)]
+        cases += [(k, gs[k], nxt[k], nxt_x[k], 0.75) for k in _STATE_KEYS]
+        for label, g, w, e, frac in cases:
+            err = np.abs(g - w)
+            scale = np.abs(w).mean()
+            fmt = np.abs(w - e).mean()
+            print("frame %d %s %dx%dx%d: |w| %.3g | vs emulated mean %.3g max %.3g | BF16 vs "
+                  "FP64 mean %.3g" % (f, label, views, H, W, scale, err.mean(), err.max(), fmt),
+                  flush=True)
+            assert np.isfinite(g).all()
+            assert err.mean() < frac * fmt, label
+            assert err.max() < 2e-2 * max(scale, 1.0), label
+        st = nxt
+    net.close()
+
+
+@pytest.mark.timeout(300)
+def test_recurrent_wnet_sequence_from_reset(dev):
+    """Four frames from a reset, the library carrying its own state: each
+    frame against the oracle's sequence (emulated BF16, its own state)."""
+    from paper_2209_09965_amd import binding as b
+    views, H, W = 1, 48, 64
+    rng = np.random.default_rng(80)
+    theta = _theta_rec(81)
+    thq = _bf16_d_weights_rec(theta)
+    net = b.WNet(theta)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).reshape(-1).to(dev)
+    state = torch.full((b.WNet.state_bytes(views, W, H),), 0x7f, dtype=torch.uint8, device=dev)
+    frames = [_frame(rng, views, H, W) for _ in range(4)]
+    xs = [np.ascontiguousarray(oracle.pack_input(*fr).reshape(views, H, W, 5).transpose(0, 3, 1, 2))
+          for fr in frames]
+    outs, ods = WN.forward_sequence(thq, xs, act_round=N.bf16_round)
+    outs_x, _ = WN.forward_sequence(theta.astype(np.float64), xs)
+    out = torch.empty(views * H * W * 3, device=dev)
+    for f, fr in enumerate(frames):
+        net.reconstruct_recurrent(t(fr[0]), t(fr[1]), t(fr[2]), state, f == 0, views, W, H, out)
+        g = out.cpu().numpy().reshape(views, H, W, 3).transpose(0, 3, 1, 2)
+        err = np.abs(g - outs[f])
+        fmt = np.abs(outs[f] - outs_x[f]).mean()
+        print("frame %d: vs emulated mean %.3g max %.3g | BF16 vs FP64 mean %.3g"
+              % (f, err.mean(), err.max(), fmt), flush=True)
+        assert err.mean() < 0.5 * fmt
+        assert err.max() < 2e-2 * max(np.abs(outs[f]).mean(), 1.0)
+    net.close()
+
+
+@pytest.mark.timeout(120)
+def test_recurrent_wnet_state_carry_is_exact(dev):
+    """Decoder blocks that permute their fed-back output (the oracle's closed
+    form): the library's state after k frames is perm^k of the installed one,
+    bit for bit, and O_d = hd(d0b) of it; a reset frame starts from zero."""
+    from paper_2209_09965_amd import binding as b
+    views, H, W = 2, 32, 48
+    P = WN.unflatten(_theta_rec(90).astype(np.float64), recurrent=True)
+    rng = np.random.default_rng(91)
+    perms = {}
+    for blk in ("d2", "d1", "d0"):
+        wa, _ = P[blk + "a"]
+        co, ci = wa.shape[:2]
+        perm = rng.permutation(co)
+        wa = np.zeros_like(wa)
+        wa[np.arange(co), ci - co + perm, 1, 1] = 1.0
+        wb = np.zeros((co, co, 3, 3))
+        wb[np.arange(co), np.arange(co), 1, 1] = 1.0
+        P[blk + "a"] = (wa, np.zeros(co))
+        P[blk + "b"] = (wb, np.zeros(co))
+        perms[blk + "b"] = perm
+    theta = WN.flatten(P, recurrent=True).astype(np.float32)
+    whd, bhd = (a.astype(np.float32).astype(np.float64) for a in P["hd"])
+    net = b.WNet(theta)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).reshape(-1).to(dev)
+    state = torch.zeros(b.WNet.state_bytes(views, W, H), dtype=torch.uint8, device=dev)
+    st0 = WN.zero_state(views, H, W)
+    st0 = {k: (N.bf16_round(rng.random(v.shape)) if k != "od" else rng.normal(size=v.shape))
+           for k, v in st0.items()}
+    _state_put(b, state, st0, views, H, W)
+    want = {k: st0[k] for k in perms}
+    out = torch.empty(views * H * W * 3, device=dev)
+    od = torch.empty_like(out)
+    for f in range(3):
+        rgba, mask, depth = _frame(rng, views, H, W)
+        net.reconstruct_recurrent(t(rgba), t(mask), t(depth), state, False, views, W, H, out, od)
+        gs = _state_get(b, state, views, H, W)
+        want = {k: v[:, perms[k]] for k, v in want.items()}
+        for k in perms:
+            assert np.array_equal(gs[k], want[k]), (f, k)
+        od_want = np.einsum("oc,nchw->nohw", whd[:, :, 0, 0], want["d0b"]) + bhd[None, :, None, None]
+        g_od = od.cpu().numpy().reshape(views, H, W, 3).transpose(0, 3, 1, 2)
+        assert np.abs(g_od - od_want).max() <= 1e-5 * max(1.0, np.abs(od_want).max())
+        assert np.array_equal(gs["od"], g_od)
+    net.reconstruct_recurrent(t(rgba), t(mask), t(depth), state, True, views, W, H, out, od)
+    gs = _state_get(b, state, views, H, W)
+    for k in perms:
+        assert not gs[k].any()
+    assert np.allclose(gs["od"], np.broadcast_to(bhd[None, :, None, None], gs["od"].shape),
+                       rtol=0, atol=1e-6)
+    net.close()
