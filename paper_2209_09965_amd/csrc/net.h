@@ -90,7 +90,8 @@ struct TrainPlan {
   size_t target;          // FP32 copy of the target RGB (loss)
   size_t dout;            // FP32 d loss / d out [n h w 3]
   size_t ssim;            // SSIM maps: 5 filtered row maps + 3 partial maps
-  size_t part;            // weight-gradient partial sums
+  size_t part;            // weight-gradient partial sums (per pixel chunk)
+  size_t part2;           // their first-stage sums (per slice of chunks)
   size_t red;             // loss partial sums
   size_t bytes;
   int chunks[kNumConv];   // pixel chunks of each layer's weight gradient

@@ -25,6 +25,10 @@ fv_status check_frame(int views, int W, int H, const char* fn);
 
 static size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
+constexpr int kWgRows = 8;         // tile rows of the weight-gradient kernel (x 16 columns)
+constexpr int kHeadChunks = 1024;  // pixel chunks of the heads' weight gradient
+constexpr int kReduceSlices = 32;  // first-stage slices of the weight-gradient reduction
+
 static int64_t px_at(const Plan& p, int level) {
   return (int64_t)p.n * (p.h >> level) * (p.w >> level);
 }
@@ -45,11 +49,17 @@ TrainPlan make_train_plan(int n, int h, int w) {
     tmp = std::max(tmp, (size_t)px * L.ci * 4);
     dz = std::max(dz, (size_t)px * L.co * 2);
     const int64_t tiles =
-        (int64_t)n * (((h >> L.level) + 7) / 8) * (((w >> L.level) + 15) / 16);
-    t.chunks[l] = (int)std::max<int64_t>(1, std::min<int64_t>(64, tiles / 8));
+        (int64_t)n * (((h >> L.level) + kWgRows - 1) / kWgRows) * (((w >> L.level) + 15) / 16);
+    // about 2048 blocks per weight-gradient launch (channel groups x chunks)
+    const int64_t groups = (int64_t)((L.ci + 31) / 32) * ((L.co + 31) / 32);
+    t.chunks[l] = (int)std::max<int64_t>(1, std::min<int64_t>(tiles, 2048 / groups));
     part = std::max(part, (size_t)t.chunks[l] * (9 * (size_t)L.ci * L.co + L.co) * 4);
   }
-  part = std::max(part, (size_t)64 * 28 * 33 * 4);
+  part = std::max(part, (size_t)kHeadChunks * 28 * 33 * 4);
+  size_t part2 = 0;
+  for (int l = 0; l < kNumConv; ++l)
+    part2 = std::max(part2, (size_t)kReduceSlices * (9 * (size_t)kLayers[l].ci * kLayers[l].co +
+                                                     kLayers[l].co) * 4);
   t.tmp = off;
   off += al(tmp);
   t.dz = off;
@@ -64,6 +74,8 @@ TrainPlan make_train_plan(int n, int h, int w) {
          al(q * h * (w - 10) * 4 * 3);
   t.part = off;
   off += al(part);
+  t.part2 = off;
+  off += al(part2);
   t.red = off;
   const int64_t vblocks = ((int64_t)q * (h - 10) * (w - 10) + 255) / 256;
   const int64_t lblocks = ((int64_t)q * h * w + 255) / 256;
@@ -391,6 +403,7 @@ __global__ void __launch_bounds__(256) k_heads_wgrad(const float* __restrict__ d
       if (o >= 28 * 33) break;
       const int qq = o / 33, k = o % 33;
       float sacc = acc[j];
+#pragma unroll 8
       for (int pp = 0; pp < 64; ++pp) sacc = fmaf(sd[pp * 28 + qq], shv[pp * 33 + k], sacc);
       acc[j] = sacc;
     }
@@ -428,96 +441,180 @@ __global__ void __launch_bounds__(256) k_relu_mask(const float* __restrict__ g,
   BF16::store8(dz + e * 16, v);
 }
 
-// One input value of a conv layer (concat of upsampled source 0 and source
-// 1, zero outside the image), as the forward kernel's patch fill defines it.
-__device__ __forceinline__ float conv_input(const ConvArgs& a, int b, int y, int x, int ch) {
-  if (y < 0 || y >= a.h || x < 0 || x >= a.w || ch >= a.c0 + a.c1) return 0.f;
+// Input channels ch..ch+7 of a conv layer at pixel (y, x) of image b, as the
+// forward kernel's patch fill defines them (concat of the bilinearly
+// upsampled source 0, rounded to BF16 as the forward pass stores it, and
+// source 1; zero outside the image), as BF16 bits.  ch is a multiple of 8
+// and so is c0, so a group never straddles the two sources.
+__device__ __forceinline__ uint4 conv_input8(const ConvArgs& a, int b, int y, int x, int ch) {
+  const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
+  if (y < 0 || y >= a.h || x < 0 || x >= a.w || ch >= a.c0 + a.c1) return zero;
+  if (ch >= a.c0)
+    return *(const uint4*)((const uint16_t*)a.src1 +
+                           (((int64_t)b * a.h + y) * a.w + x) * a.c1 + (ch - a.c0));
   const uint16_t* s0 = (const uint16_t*)a.src0;
-  if (ch < a.c0) {
-    if (!a.up0) return bf16_bits_to_f(s0[(((int64_t)b * a.h + y) * a.w + x) * a.c0 + ch]);
-    const int hh = a.h >> 1, ww = a.w >> 1;
-    const float sy = fminf(fmaxf((y + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(hh - 1));
-    const float sx = fminf(fmaxf((x + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(ww - 1));
-    const int ly0 = (int)sy, lx0 = (int)sx;
-    const int ly1 = min(ly0 + 1, hh - 1), lx1 = min(lx0 + 1, ww - 1);
-    const float fy = sy - (float)ly0, fx = sx - (float)lx0;
-    const int64_t base = (int64_t)b * hh * ww;
-    const float v00 = bf16_bits_to_f(s0[(base + (int64_t)ly0 * ww + lx0) * a.c0 + ch]);
-    const float v01 = bf16_bits_to_f(s0[(base + (int64_t)ly0 * ww + lx1) * a.c0 + ch]);
-    const float v10 = bf16_bits_to_f(s0[(base + (int64_t)ly1 * ww + lx0) * a.c0 + ch]);
-    const float v11 = bf16_bits_to_f(s0[(base + (int64_t)ly1 * ww + lx1) * a.c0 + ch]);
-    const float top = fmaf(fx, v01 - v00, v00), bot = fmaf(fx, v11 - v10, v10);
-    // the forward pass stores the blended value in BF16
-    return (float)(__bf16)fmaf(fy, bot - top, top);
+  if (!a.up0) return *(const uint4*)(s0 + (((int64_t)b * a.h + y) * a.w + x) * a.c0 + ch);
+  const int hh = a.h >> 1, ww = a.w >> 1;
+  const float sy = fminf(fmaxf((y + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(hh - 1));
+  const float sx = fminf(fmaxf((x + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(ww - 1));
+  const int ly0 = (int)sy, lx0 = (int)sx;
+  const int ly1 = min(ly0 + 1, hh - 1), lx1 = min(lx0 + 1, ww - 1);
+  const float fy = sy - (float)ly0, fx = sx - (float)lx0;
+  const int64_t base = (int64_t)b * hh * ww;
+  const uint4 q00 = *(const uint4*)(s0 + (base + (int64_t)ly0 * ww + lx0) * a.c0 + ch);
+  const uint4 q01 = *(const uint4*)(s0 + (base + (int64_t)ly0 * ww + lx1) * a.c0 + ch);
+  const uint4 q10 = *(const uint4*)(s0 + (base + (int64_t)ly1 * ww + lx0) * a.c0 + ch);
+  const uint4 q11 = *(const uint4*)(s0 + (base + (int64_t)ly1 * ww + lx1) * a.c0 + ch);
+  const uint32_t w00[4] = {q00.x, q00.y, q00.z, q00.w}, w01[4] = {q01.x, q01.y, q01.z, q01.w};
+  const uint32_t w10[4] = {q10.x, q10.y, q10.z, q10.w}, w11[4] = {q11.x, q11.y, q11.z, q11.w};
+  uint32_t o[4];
+  for (int i = 0; i < 4; ++i) {
+    uint32_t packed = 0;
+    for (int hi = 0; hi < 2; ++hi) {
+      const int sh = 16 * hi;
+      const float v00 = bf16_bits_to_f((w00[i] >> sh) & 0xffffu);
+      const float v01 = bf16_bits_to_f((w01[i] >> sh) & 0xffffu);
+      const float v10 = bf16_bits_to_f((w10[i] >> sh) & 0xffffu);
+      const float v11 = bf16_bits_to_f((w11[i] >> sh) & 0xffffu);
+      const float top = fmaf(fx, v01 - v00, v00), bot = fmaf(fx, v11 - v10, v10);
+      // the forward pass stores the blended value in BF16
+      const __bf16 v = (__bf16)fmaf(fy, bot - top, top);
+      packed |= (uint32_t)__builtin_bit_cast(uint16_t, v) << sh;
+    }
+    o[i] = packed;
   }
-  return bf16_bits_to_f(((const uint16_t*)a.src1)[(((int64_t)b * a.h + y) * a.w + x) * a.c1 +
-                                                  (ch - a.c0)]);
+  return make_uint4(o[0], o[1], o[2], o[3]);
 }
 
-// Weight gradient of a 3x3 layer, FP32 on the vector units.  Block = one
-// (16 output channels) x (16 input channels) pair for all 9 taps and one
-// pixel chunk; thread (co_j, ci_j) accumulates its 9 taps (and the bias for
-// ci block 0) over 8x16-pixel tiles staged in LDS.
+// Weight gradient of a 3x3 layer on MFMA: per tap, dW[co][ci] = sum over
+// pixels p of dz[p][co] x[p + tap][ci], a GEMM whose K dimension is the
+// pixels (BF16 operands as stored by the forward pass and the ReLU mask,
+// FP32 accumulation).  Block = 32 output x 32 input channels for all 9 taps
+// and one chunk of 8 x 16-pixel tiles; wave w owns the 16 x 16 channel pair
+// (w / 2, w % 2) and keeps its 9 tap accumulators (plus the bias, sum of dz,
+// as an MFMA against ones) in registers.  Each tile's dz and input patch
+// (10 x 18 pixels) are staged in LDS transposed, channel-major, so a lane's
+// MFMA operand (8 consecutive pixels of one channel) is one 16-byte read;
+// the three horizontal taps of one row share a 10-pixel window (a 16- and a
+// 4-byte read, shifted by one and two pixels in registers).  K step s of a
+// tile is rows 2s, 2s+1: lane group g takes row 2s + g/2, columns 8 (g%2)
+// .. +7, the same pixels in both operands.  Partial sums go to part[chunk]
+// and are summed in chunk order by k_wgrad_reduce, so the result is
+// deterministic.
+constexpr int kWgXRow = 24;                             // patch row in LDS (18 used)
+constexpr int kWgXStride = (kWgRows + 2) * kWgXRow * 2 + 16;  // bytes per input channel
+constexpr int kWgDStride = kWgRows * 16 * 2 + 16;              // bytes per output channel
+
 __global__ void __launch_bounds__(256) k_wgrad(ConvArgs a, const uint8_t* __restrict__ dz,
-                                               int ci_total, int co_total, int chunks,
-                                               float* __restrict__ part) {
-  __shared__ float sx[10 * 18 * 17];
-  __shared__ float sd[128 * 17];
-  const int cib = blockIdx.x % ((ci_total + 15) / 16), cob = blockIdx.x / ((ci_total + 15) / 16);
+                                               int ci_total, int co_total, int cig_n,
+                                               int chunks, float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) uint8_t sx[32 * kWgXStride];
+  __shared__ __attribute__((aligned(16))) uint8_t sd[32 * kWgDStride];
+  const int cig = blockIdx.x % cig_n, cog = blockIdx.x / cig_n;
   const int chunk = blockIdx.y;
-  const int tid = threadIdx.x;
-  const int coj = tid >> 4, cij = tid & 15;
-  const int co = cob * 16 + coj, ci = cib * 16 + cij;
-  const int tiles_x = (a.w + 15) / 16, tiles_y = (a.h + 7) / 8;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int mt = wave >> 1, ns = wave & 1;
+  const int g = lane >> 4, li = lane & 15, c8 = 8 * (g & 1);
+  const int ci0 = cig * 32, co0 = cog * 32;
+  const int tiles_x = (a.w + 15) / 16, tiles_y = (a.h + kWgRows - 1) / kWgRows;
   const int64_t tiles = (int64_t)a.n * tiles_x * tiles_y;
   const int64_t t0 = tiles * chunk / chunks, t1 = tiles * (chunk + 1) / chunks;
-  float acc[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  float accb = 0.f;
-  const uint16_t* dz16 = (const uint16_t*)dz;
+  const bool bias = cig == 0 && ns == 0;
+  f32x4_t acc[9], accb = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 9; ++t) acc[t] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+  const bf16x8_t ones = __builtin_bit_cast(bf16x8_t, make_uint4(0x3f803f80u, 0x3f803f80u,
+                                                               0x3f803f80u, 0x3f803f80u));
+  const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
   for (int64_t t = t0; t < t1; ++t) {
     const int tx = (int)(t % tiles_x);
     const int64_t rr = t / tiles_x;
     const int ty = (int)(rr % tiles_y), b = (int)(rr / tiles_y);
-    const int x0 = tx * 16, y0 = ty * 8;
+    const int x0 = tx * 16, y0 = ty * kWgRows;
     __syncthreads();
-    for (int e = tid; e < 10 * 18 * 16; e += 256) {
-      const int c = e & 15, pix = e >> 4;
-      const int r = pix / 18, cc = pix % 18;
-      const int chn = cib * 16 + c;
-      sx[pix * 17 + c] = chn < ci_total ? conv_input(a, b, y0 - 1 + r, x0 - 1 + cc, chn) : 0.f;
+    for (int e = tid; e < (kWgRows + 2) * 18 * 4; e += 256) {
+      const int grp = e & 3, pix = e >> 2;
+      const int r = pix / 18, c = pix - r * 18;
+      const int ch = ci0 + 8 * grp;
+      const uint4 v = ch < ci_total ? conv_input8(a, b, y0 - 1 + r, x0 - 1 + c, ch) : zero;
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+      uint8_t* dst = sx + (8 * grp) * kWgXStride + (r * kWgXRow + c) * 2;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        *(uint16_t*)(dst + j * kWgXStride) = (uint16_t)(w[j >> 1] >> (16 * (j & 1)));
     }
-    for (int e = tid; e < 128 * 16; e += 256) {
-      const int c = e & 15, pix = e >> 4;
-      const int y = y0 + (pix >> 4), x = x0 + (pix & 15);
-      const int chn = cob * 16 + c;
-      float v = 0.f;
-      if (y < a.h && x < a.w && chn < co_total)
-        v = bf16_bits_to_f(dz16[(((int64_t)b * a.h + y) * a.w + x) * co_total + chn]);
-      sd[pix * 17 + c] = v;
+    for (int e = tid; e < kWgRows * 16 * 4; e += 256) {
+      const int grp = e & 3, pix = e >> 2;
+      const int r = pix >> 4, c = pix & 15;
+      const int y = y0 + r, x = x0 + c, co = co0 + 8 * grp;
+      uint4 v = zero;
+      if (y < a.h && x < a.w && co < co_total)
+        v = *(const uint4*)(dz + ((((int64_t)b * a.h + y) * a.w + x) * co_total + co) * 2);
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+      uint8_t* dst = sd + (8 * grp) * kWgDStride + (r * 16 + c) * 2;
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        *(uint16_t*)(dst + j * kWgDStride) = (uint16_t)(w[j >> 1] >> (16 * (j & 1)));
     }
     __syncthreads();
-    for (int pix = 0; pix < 128; ++pix) {
-      const float d = sd[pix * 17 + coj];
-      accb += d;
-      const int py = pix >> 4, pxx = pix & 15;
-      for (int ky = 0; ky < 3; ++ky)
-        for (int kx = 0; kx < 3; ++kx)
-          acc[ky * 3 + kx] = fmaf(d, sx[((py + ky) * 18 + pxx + kx) * 17 + cij], acc[ky * 3 + kx]);
+#pragma unroll
+    for (int ks = 0; ks < kWgRows / 2; ++ks) {
+      const int row = 2 * ks + (g >> 1);
+      const bf16x8_t af =
+          *(const bf16x8_t*)(sd + (mt * 16 + li) * kWgDStride + (row * 16 + c8) * 2);
+      if (bias) accb = BF16::mma(af, ones, accb);
+      const uint8_t* xb = sx + (ns * 16 + li) * kWgXStride + c8 * 2;
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const uint8_t* p = xb + (row + dy) * kWgXRow * 2;
+        const uint4 v = *(const uint4*)p;
+        const uint32_t e4 = *(const uint32_t*)(p + 16);
+        const uint4 v1 = make_uint4(__builtin_amdgcn_alignbit(v.y, v.x, 16),
+                                    __builtin_amdgcn_alignbit(v.z, v.y, 16),
+                                    __builtin_amdgcn_alignbit(v.w, v.z, 16),
+                                    __builtin_amdgcn_alignbit(e4, v.w, 16));
+        const uint4 v2 = make_uint4(v.y, v.z, v.w, e4);
+        acc[3 * dy] = BF16::mma(af, __builtin_bit_cast(bf16x8_t, v), acc[3 * dy]);
+        acc[3 * dy + 1] = BF16::mma(af, __builtin_bit_cast(bf16x8_t, v1), acc[3 * dy + 1]);
+        acc[3 * dy + 2] = BF16::mma(af, __builtin_bit_cast(bf16x8_t, v2), acc[3 * dy + 2]);
+      }
     }
   }
-  if (co < co_total && ci < ci_total) {
-    float* pp = part + (int64_t)chunk * (9 * (int64_t)ci_total * co_total + co_total);
-    for (int tp = 0; tp < 9; ++tp) pp[((int64_t)co * ci_total + ci) * 9 + tp] = acc[tp];
-    if (cib == 0 && cij == 0) pp[9 * (int64_t)ci_total * co_total + co] = accb;
+  // lane (g, li) holds D[4 g + r][li] of its pair: output channel
+  // co0 + 16 mt + 4 g + r, input channel ci0 + 16 ns + li
+  float* pp = part + (int64_t)chunk * (9 * (int64_t)ci_total * co_total + co_total);
+  const int ci = ci0 + ns * 16 + li;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int co = co0 + mt * 16 + 4 * g + r;
+    if (co < co_total && ci < ci_total)
+#pragma unroll
+      for (int tp = 0; tp < 9; ++tp) pp[((int64_t)co * ci_total + ci) * 9 + tp] = acc[tp][r];
+    if (bias && li == 0 && co < co_total) pp[9 * (int64_t)ci_total * co_total + co] = accb[r];
   }
 }
 
+// Sum of the chunk partials in two fixed-order stages: slice s of
+// kReduceSlices sums chunks [s chunks / S, (s + 1) chunks / S) in order,
+// then the slices are summed in order (deterministic for any hardware).
 __global__ void __launch_bounds__(256) k_wgrad_reduce(const float* __restrict__ part, int chunks,
-                                                      int64_t count, float* __restrict__ grad) {
+                                                      int64_t count, float* __restrict__ part2) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int sl = blockIdx.y;
+  if (e >= count) return;
+  const int c0 = (int)((int64_t)chunks * sl / kReduceSlices);
+  const int c1 = (int)((int64_t)chunks * (sl + 1) / kReduceSlices);
+  float s = 0.f;
+  for (int c = c0; c < c1; ++c) s += part[(int64_t)c * count + e];
+  part2[(int64_t)sl * count + e] = s;
+}
+
+__global__ void __launch_bounds__(256) k_wgrad_reduce2(const float* __restrict__ part2,
+                                                       int64_t count, float* __restrict__ grad) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= count) return;
   float s = 0.f;
-  for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * count + e];
+  for (int sl = 0; sl < kReduceSlices; ++sl) s += part2[(int64_t)sl * count + e];
   grad[e] = s;
 }
 
@@ -770,7 +867,7 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
   k_heads_bwd<<<nblk(npx), 256, 0, s>>>(dloss_dout, (const float*)(ws + p.od),
                                         (const float*)(ws + p.wk), p.n, p.h, p.w, n->master,
                                         param_offset(14), param_offset(15), tmp, G(T_D0B));
-  const int hchunks = 64;
+  const int hchunks = kHeadChunks;
   k_heads_wgrad<<<hchunks, 256, 0, s>>>(tmp, ws + p.t[T_D0B], npx, hchunks, part);
   k_heads_reduce<<<4, 256, 0, s>>>(part, hchunks, param_offset(14), param_offset(15), grad);
   if ((st = launch_status("heads backward")) != FV_OK) return st;
@@ -793,10 +890,13 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
     in.h = hh;
     in.w = ww;
     const int ci_tot = l == 0 ? L.ci : L.c0 + L.c1;
-    dim3 gw((unsigned)(((ci_tot + 15) / 16) * ((L.co + 15) / 16)), (unsigned)tp.chunks[l]);
-    k_wgrad<<<gw, 256, 0, s>>>(in, dz, ci_tot, L.co, tp.chunks[l], part);
+    const int cig_n = (ci_tot + 31) / 32;
+    dim3 gw((unsigned)(cig_n * ((L.co + 31) / 32)), (unsigned)tp.chunks[l]);
+    k_wgrad<<<gw, 256, 0, s>>>(in, dz, ci_tot, L.co, cig_n, tp.chunks[l], part);
     const int64_t cnt = 9 * (int64_t)ci_tot * L.co + L.co;
-    k_wgrad_reduce<<<nblk(cnt), 256, 0, s>>>(part, tp.chunks[l], cnt, grad + param_offset(l));
+    float* part2 = (float*)(ws + tp.part2);
+    k_wgrad_reduce<<<dim3(nblk(cnt), kReduceSlices), 256, 0, s>>>(part, tp.chunks[l], cnt, part2);
+    k_wgrad_reduce2<<<nblk(cnt), 256, 0, s>>>(part2, cnt, grad + param_offset(l));
     if ((st = launch_status("wgrad")) != FV_OK) return st;
     if (l == 0) break;  // no gradient w.r.t. the network input
     // input gradient: conv with transposed weights, FP32 output
