@@ -189,6 +189,16 @@ typedef struct fv_volume fv_volume;
 
 fv_status fv_volume_create(const void* dev_data, int nx, int ny, int nz,
                            fv_dtype dt, void* stream, fv_volume** out);
+/* The same volume in the bricked layout: cells grouped in 16^3 bricks, each
+ * stored whole with the apron its samples' stencils read (19^3 voxels, x
+ * fastest), bricks in z, y, x order; (ceil((n+1)/16))^3 x 19^3 elements,
+ * about 1.7 x the grid.  A sample's voxels then lie within one brick: fewer
+ * cache lines per sample and neighbouring samples on the same lines, for
+ * volumes beyond the caches.  Every march reads the same voxel values in
+ * either layout (bit-identical results).  Errors as fv_volume_create (the
+ * bricked copy must be < 4 GiB). */
+fv_status fv_volume_create_bricked(const void* dev_data, int nx, int ny, int nz,
+                                   fv_dtype dt, void* stream, fv_volume** out);
 fv_status fv_volume_destroy(fv_volume* v);
 
 /* ------------------------------------------------------------------------

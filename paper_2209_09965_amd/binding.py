@@ -83,6 +83,7 @@ _SIGS = {
     "fv_fovea_mask_tiles": (_i, [ctypes.POINTER(FoveaParams), _vp, _i, _i, _i, _i, _i, _i, _vp,
                                  _vp, _u32, _vp, _vp, _sz, _vp]),
     "fv_volume_create": (_i, [_vp, _i, _i, _i, _i, _vp, ctypes.POINTER(_vp)]),
+    "fv_volume_create_bricked": (_i, [_vp, _i, _i, _i, _i, _vp, ctypes.POINTER(_vp)]),
     "fv_volume_destroy": (_i, [_vp]),
     "fv_raymarch_dense": (_i, [_vp, _vp, _i, ctypes.POINTER(Camera), _i, _i, _i,
                                ctypes.POINTER(MarchParams), _vp, _vp, _vp, _vp]),
@@ -298,16 +299,19 @@ def fovea_mask_tiles(params, tiles, width, height, views, ray_idx, count, mask=N
 # ---------------------------------------------------------------------- volume
 
 class Volume:
-    """Library-owned copy of a [nz, ny, nx] device tensor (uint8 / float16 / float32)."""
+    """Library-owned copy of a [nz, ny, nx] device tensor (uint8 / float16 /
+    float32), in the linear or the bricked layout."""
 
-    def __init__(self, data, stream=None):
+    def __init__(self, data, stream=None, bricked=False):
         if data.dim() != 3 or not data.is_cuda or data.dtype not in DTYPE_CODES:
             raise ValueError("volume must be a 3-D uint8/float16/float32 CUDA tensor")
         data = data.contiguous()
         nz, ny, nx = data.shape
         h = ctypes.c_void_p()
-        check(_lib.fv_volume_create(ctypes.c_void_p(data.data_ptr()), nx, ny, nz,
-                                    DTYPE_CODES[data.dtype], _stream(stream), ctypes.byref(h)))
+        create = _lib.fv_volume_create_bricked if bricked else _lib.fv_volume_create
+        check(create(ctypes.c_void_p(data.data_ptr()), nx, ny, nz, DTYPE_CODES[data.dtype],
+                     _stream(stream), ctypes.byref(h)))
+        self.bricked = bricked
         self.handle = h
         self.shape = (nz, ny, nx)
         self.dtype = data.dtype

@@ -41,6 +41,91 @@ __global__ void __launch_bounds__(256) k_pad_copy(const T* __restrict__ src, T* 
   dst[e] = src[(sk * ny + sj) * nx + si];
 }
 
+// Fills the bricked copy: every destination element reads its clamped source
+// voxel.  One thread per destination element.
+template <typename T>
+__global__ void __launch_bounds__(256) k_brick_copy(const T* __restrict__ src,
+                                                    T* __restrict__ dst, int nx, int ny, int nz,
+                                                    int nbx, int nby, int64_t total) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int64_t b = e / kBrickVox;
+  const int r = (int)(e - b * kBrickVox);
+  const int sx = r % kBrickRow, sy = (r / kBrickRow) % kBrickRow, sz = r / (kBrickRow * kBrickRow);
+  const int bx = (int)(b % nbx), by = (int)((b / nbx) % nby), bz = (int)(b / ((int64_t)nbx * nby));
+  const int64_t i = min(max(kBrick * bx - 2 + sx, 0), nx - 1);
+  const int64_t j = min(max(kBrick * by - 2 + sy, 0), ny - 1);
+  const int64_t k = min(max(kBrick * bz - 2 + sz, 0), nz - 1);
+  dst[e] = src[(k * ny + j) * nx + i];
+}
+
+fv_status volume_create(const void* dev_data, int nx, int ny, int nz, fv_dtype dt, int brick,
+                        void* stream, fv_volume** out, const char* fn) {
+  clear_error();
+  if (!dev_data || !out) return fail(FV_ERR_INVALID_ARG, "%s: null pointer", fn);
+  *out = nullptr;
+  if (nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096)
+    return fail(FV_ERR_INVALID_ARG, "%s: dims %d x %d x %d outside [1, 4096]", fn, nx, ny, nz);
+  if (dt != FV_U8 && dt != FV_F16 && dt != FV_F32)
+    return fail(FV_ERR_UNSUPPORTED, "%s: unknown dtype %d", fn, (int)dt);
+  fv_volume* v = new fv_volume();
+  v->n[0] = nx;
+  v->n[1] = ny;
+  v->n[2] = nz;
+  v->dt = dt;
+  v->px = nx + 4;
+  v->py = ny + 4;
+  v->pz = nz + 4;
+  v->brick = brick;
+  for (int a = 0; a < 3; ++a) v->nb[a] = (v->n[a] + 1 + kBrick - 1) / kBrick;
+  if (hipGetDevice(&v->device) != hipSuccess) {
+    delete v;
+    return fail(FV_ERR_DEVICE, "%s: hipGetDevice failed", fn);
+  }
+  const int64_t total = brick ? (int64_t)v->nb[0] * v->nb[1] * v->nb[2] * kBrickVox
+                              : v->px * v->py * v->pz;
+  const size_t bytes = (size_t)total * dtype_bytes(dt);
+  if (bytes >= ((size_t)1 << 32) - 1) {
+    delete v;
+    return fail(FV_ERR_UNSUPPORTED, "%s: the volume copy must be < 4 GiB (%zu bytes)", fn, bytes);
+  }
+  v->bytes = bytes;
+  if (hipMalloc(&v->data, bytes) != hipSuccess) {
+    delete v;
+    return fail(FV_ERR_NOMEM, "%s: cannot allocate %zu bytes", fn, bytes);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const unsigned grid = (unsigned)((total + 255) / 256);
+  auto launch = [&](auto tag) {
+    using T = decltype(tag);
+    if (brick)
+      k_brick_copy<T><<<grid, 256, 0, s>>>((const T*)dev_data, (T*)v->data, nx, ny, nz,
+                                           v->nb[0], v->nb[1], total);
+    else
+      k_pad_copy<T><<<grid, 256, 0, s>>>((const T*)dev_data, (T*)v->data, nx, ny, nz, v->px,
+                                         v->py, total);
+  };
+  switch (dt) {
+    case FV_U8:
+      launch(uint8_t{});
+      break;
+    case FV_F16:
+      launch(uint16_t{});
+      break;
+    default:
+      launch(float{});
+  }
+  fv_status st = launch_status("volume copy kernel");
+  if (st == FV_OK) st = hip_status(hipStreamSynchronize(s), "volume copy: sync");
+  if (st != FV_OK) {
+    (void)hipFree(v->data);
+    delete v;
+    return st;
+  }
+  *out = v;
+  return FV_OK;
+}
+
 }  // namespace fv
 
 extern "C" {
@@ -51,63 +136,12 @@ int fv_abi_version(void) { return FV_ABI_VERSION; }
 
 fv_status fv_volume_create(const void* dev_data, int nx, int ny, int nz, fv_dtype dt,
                            void* stream, fv_volume** out) {
-  fv::clear_error();
-  if (!dev_data || !out) return fv::fail(FV_ERR_INVALID_ARG, "fv_volume_create: null pointer");
-  *out = nullptr;
-  if (nx < 1 || ny < 1 || nz < 1 || nx > 4096 || ny > 4096 || nz > 4096)
-    return fv::fail(FV_ERR_INVALID_ARG, "fv_volume_create: dims %d x %d x %d outside [1, 4096]",
-                    nx, ny, nz);
-  if (dt != FV_U8 && dt != FV_F16 && dt != FV_F32)
-    return fv::fail(FV_ERR_UNSUPPORTED, "fv_volume_create: unknown dtype %d", (int)dt);
-  fv_volume* v = new fv_volume();
-  v->n[0] = nx;
-  v->n[1] = ny;
-  v->n[2] = nz;
-  v->dt = dt;
-  v->px = nx + 4;
-  v->py = ny + 4;
-  v->pz = nz + 4;
-  if (hipGetDevice(&v->device) != hipSuccess) {
-    delete v;
-    return fv::fail(FV_ERR_DEVICE, "fv_volume_create: hipGetDevice failed");
-  }
-  int64_t total = v->px * v->py * v->pz;
-  size_t bytes = (size_t)total * fv::dtype_bytes(dt);
-  if (bytes >= ((size_t)1 << 32) - 1) {
-    delete v;
-    return fv::fail(FV_ERR_UNSUPPORTED,
-                    "fv_volume_create: the padded copy must be < 4 GiB "
-                    "((nx+4)(ny+4)(nz+4) x bytes per voxel)");
-  }
-  if (hipMalloc(&v->data, bytes) != hipSuccess) {
-    delete v;
-    return fv::fail(FV_ERR_NOMEM, "fv_volume_create: cannot allocate %zu bytes", bytes);
-  }
-  hipStream_t s = (hipStream_t)stream;
-  unsigned grid = (unsigned)((total + 255) / 256);
-  switch (dt) {
-    case FV_U8:
-      fv::k_pad_copy<uint8_t><<<grid, 256, 0, s>>>((const uint8_t*)dev_data, (uint8_t*)v->data,
-                                                    nx, ny, nz, v->px, v->py, total);
-      break;
-    case FV_F16:
-      fv::k_pad_copy<uint16_t><<<grid, 256, 0, s>>>((const uint16_t*)dev_data,
-                                                     (uint16_t*)v->data, nx, ny, nz, v->px,
-                                                     v->py, total);
-      break;
-    default:
-      fv::k_pad_copy<float><<<grid, 256, 0, s>>>((const float*)dev_data, (float*)v->data, nx, ny,
-                                                  nz, v->px, v->py, total);
-  }
-  fv_status st = fv::launch_status("fv_volume_create: copy kernel");
-  if (st == FV_OK) st = fv::hip_status(hipStreamSynchronize(s), "fv_volume_create: sync");
-  if (st != FV_OK) {
-    (void)hipFree(v->data);
-    delete v;
-    return st;
-  }
-  *out = v;
-  return FV_OK;
+  return fv::volume_create(dev_data, nx, ny, nz, dt, 0, stream, out, "fv_volume_create");
+}
+
+fv_status fv_volume_create_bricked(const void* dev_data, int nx, int ny, int nz, fv_dtype dt,
+                                   void* stream, fv_volume** out) {
+  return fv::volume_create(dev_data, nx, ny, nz, dt, 1, stream, out, "fv_volume_create_bricked");
 }
 
 fv_status fv_volume_destroy(fv_volume* v) {

@@ -48,14 +48,27 @@ fv_status pullpush_run(const float* frame_rgba, const uint8_t* mask, int views, 
 
 }  // namespace fv
 
-// Library-owned volume copy.  Storage: the scalar grid with a 2-voxel apron
-// of replicated edge voxels on every side (so clamp-to-edge sampling needs no
-// index clamps), x fastest.  Element (i, j, k) for i in [-2, nx+1] lives at
-// data[((k + 2) * py + (j + 2)) * px + (i + 2)], px = nx + 4, py = ny + 4.
+// Library-owned volume copy, clamp-to-edge built in (no index clamps when
+// sampling).  Two layouts:
+//  linear  the grid with a 2-voxel apron of replicated edge voxels on every
+//          side, x fastest: element (i, j, k), i in [-2, nx+1], at
+//          data[((k + 2) * py + (j + 2)) * px + (i + 2)], px = nx + 4, py = ny + 4;
+//  bricks  cells j = i + 1 in [0, n] grouped 16 per axis into bricks, each
+//          stored whole with the voxels its cells' stencils read: brick b
+//          holds voxels [16 b - 2, 16 b + 17) per axis (clamped to the grid),
+//          19^3 elements x fastest, bricks in (bz, by, bx) order.  Every
+//          sample's 4^3 stencil lies inside one brick, so the gather keeps
+//          uniform row / slice strides (19, 361 elements).
+constexpr int kBrick = 16;       // cells per brick edge
+constexpr int kBrickRow = kBrick + 3;  // stored voxels per brick edge
+constexpr int kBrickVox = kBrickRow * kBrickRow * kBrickRow;
 struct fv_volume {
   int n[3];
   fv_dtype dt;
   int device;
   void* data;
-  int64_t px, py, pz;
+  int64_t px, py, pz;  // linear layout pitches
+  int brick;           // 1: the bricked layout
+  int nb[3];           // bricks per axis (bricked layout)
+  uint64_t bytes;      // size of the copy
 };

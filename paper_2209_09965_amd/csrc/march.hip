@@ -17,6 +17,12 @@ namespace {
 
 constexpr int kMaxViews = 8;
 
+// The kernels' DT template argument: the voxel dtype (fv_dtype), plus
+// kBricked for a volume in the bricked layout.
+constexpr int kBricked = 4;
+template <int DT>
+using Vx = Voxel<DT & 3>;
+
 struct CamD {
   double o[3], f[3], r[3], u[3];
   double sx, sy;  // tan(fovy/2) * W/H, tan(fovy/2)
@@ -25,7 +31,8 @@ struct CamD {
 struct MarchArgs {
   const void* vol;
   uint32_t vol_bytes;  // size of the padded copy (< 2^32)
-  int64_t px, py;  // padded row / slice pitch in elements
+  int64_t px, py;  // row / slice pitch in elements (of the bricks when brick)
+  int nb[2];        // bricks along x and y (bricked layout)
   int n[3];
   double h;        // voxel edge in world units
   double half[3];  // box half extents
@@ -152,6 +159,24 @@ __device__ __forceinline__ bool ray_setup(const MarchArgs& a, int view, int x, i
   return true;
 }
 
+// Element offset of the stencil's first voxel, (i - 1, j - 1, k - 1) for the
+// cell (i, j, k) with each index in [-1, n - 1]; the other stencil voxels
+// follow at the uniform row / slice pitches a.px, a.px a.py.  Bricked
+// layout: cell index c = i + 1 lies in brick c / 16, whose stored voxel
+// (c mod 16) along that axis is voxel i - 1.
+template <int DT>
+__device__ __forceinline__ uint32_t stencil_base(const MarchArgs& a, const int ii[3]) {
+  const uint32_t c0 = (uint32_t)(ii[0] + 1), c1 = (uint32_t)(ii[1] + 1),
+                 c2 = (uint32_t)(ii[2] + 1);
+  if constexpr ((DT & kBricked) != 0) {
+    const uint32_t b = ((c2 / kBrick) * (uint32_t)a.nb[1] + c1 / kBrick) * (uint32_t)a.nb[0] +
+                       c0 / kBrick;
+    return b * (uint32_t)kBrickVox +
+           ((c2 % kBrick) * kBrickRow + c1 % kBrick) * kBrickRow + c0 % kBrick;
+  }
+  return c2 * (uint32_t)(a.px * a.py) + c1 * (uint32_t)a.px + c0;
+}
+
 // The voxels one sample reads, as stored (converted to float when used):
 // the 8 corners of its cell and, when shading, the 24 more voxels of the
 // one-voxel central differences (the 4 x 2 x 2, 2 x 4 x 2 and 2 x 2 x 4 arms).
@@ -159,8 +184,8 @@ __device__ __forceinline__ bool ray_setup(const MarchArgs& a, int view, int x, i
 // minimum corner.
 template <int DT, bool SHADE>
 struct Stencil {
-  typename Voxel<DT>::T c[8];            // centre cell, index x + 2 y + 4 z
-  typename Voxel<DT>::T g[SHADE ? 24 : 1];  // arms: x-, x+, y-, y+, z-, z+ (4 each)
+  typename Vx<DT>::T c[8];            // centre cell, index x + 2 y + 4 z
+  typename Vx<DT>::T g[SHADE ? 24 : 1];  // arms: x-, x+, y-, y+, z-, z+ (4 each)
   float w[3];                            // trilinear weights
 };
 
@@ -174,7 +199,7 @@ struct Stencil {
 template <int DT, bool SHADE>
 __device__ __forceinline__ void gather(const MarchArgs& a, const RayState& s, int k,
                                        Stencil<DT, SHADE>& st, bool live = true) {
-  using VT = typename Voxel<DT>::T;
+  using VT = typename Vx<DT>::T;
   const double kk = k == s.N - 1 ? s.klast : (double)k;
   int ii[3];
   for (int i = 0; i < 3; ++i) {
@@ -191,8 +216,7 @@ __device__ __forceinline__ void gather(const MarchArgs& a, const RayState& s, in
   const __amdgpu_buffer_rsrc_t rs =
       __builtin_amdgcn_make_buffer_rsrc((void*)a.vol, (short)0, (int)a.vol_bytes, 0x00020000);
   const int sy = (int)a.px * EB, sz = (int)(a.px * a.py) * EB;
-  const uint32_t oi = ((uint32_t)(ii[2] + 1) * (uint32_t)(a.px * a.py) +
-                       (uint32_t)(ii[1] + 1) * (uint32_t)a.px + (uint32_t)(ii[0] + 1)) * EB;
+  const uint32_t oi = stencil_base<DT>(a, ii) * EB;
   const int o = (int)(live ? oi : a.vol_bytes);
 #define FV_V(x, y, z) buffer_voxel<VT>(rs, o + (x) * EB, (y) * sy + (z) * sz)
   for (int z = 0; z < 2; ++z)
@@ -242,7 +266,7 @@ template <int DT>
 __device__ __forceinline__ float shadow_transmittance(const MarchArgs& a,
                                                       const float4* __restrict__ tfs,
                                                       const double q[3]) {
-  using VT = typename Voxel<DT>::T;
+  using VT = typename Vx<DT>::T;
   double L = INFINITY;
   for (int i = 0; i < 3; ++i) {
     const double l = a.lightd[i];
@@ -273,8 +297,7 @@ __device__ __forceinline__ float shadow_transmittance(const MarchArgs& a,
       cl.w[i] = (float)(p - fp);
       ii[i] = min(max((int)fp, -1), a.n[i] - 1);
     }
-    const int o = (int)(((uint32_t)(ii[2] + 1) * (uint32_t)(a.px * a.py) +
-                         (uint32_t)(ii[1] + 1) * (uint32_t)a.px + (uint32_t)(ii[0] + 1)) * EB);
+    const int o = (int)(stencil_base<DT>(a, ii) * EB);
     for (int z = 0; z < 2; ++z)
       for (int y = 0; y < 2; ++y)
         for (int x = 0; x < 2; ++x)
@@ -282,7 +305,7 @@ __device__ __forceinline__ float shadow_transmittance(const MarchArgs& a,
               buffer_voxel<VT>(rs, o + (1 + x) * EB, (1 + y) * sy + (1 + z) * sz);
   };
   auto sigma = [&](const Cell& cl) {
-#define FV_C(x, y, z) Voxel<DT>::f(cl.c[(x) + 2 * (y) + 4 * (z)])
+#define FV_C(x, y, z) Vx<DT>::f(cl.c[(x) + 2 * (y) + 4 * (z)])
     const float v = tri(FV_C(0, 0, 0), FV_C(1, 0, 0), FV_C(0, 1, 0), FV_C(1, 1, 0),
                         FV_C(0, 0, 1), FV_C(1, 0, 1), FV_C(0, 1, 1), FV_C(1, 1, 1), cl.w[0],
                         cl.w[1], cl.w[2]);
@@ -336,7 +359,7 @@ __device__ __forceinline__ Segment shade(const MarchArgs& a, const float4* __res
     t = fmaf((float)k, s.tstep, s.t0);
   }
   const float wx = st.w[0], wy = st.w[1], wz = st.w[2];
-#define FV_C(x, y, z) Voxel<DT>::f(st.c[(x) + 2 * (y) + 4 * (z)])
+#define FV_C(x, y, z) Vx<DT>::f(st.c[(x) + 2 * (y) + 4 * (z)])
   const float v000 = FV_C(0, 0, 0), v100 = FV_C(1, 0, 0);
   const float v010 = FV_C(0, 1, 0), v110 = FV_C(1, 1, 0);
   const float v001 = FV_C(0, 0, 1), v101 = FV_C(1, 0, 1);
@@ -355,7 +378,7 @@ __device__ __forceinline__ Segment shade(const MarchArgs& a, const float4* __res
   if (SHADE) {
     // one-voxel central differences of the interpolated field; arm entry j
     // holds the voxel at (u, v) = (j & 1, j >> 1) across the arm's axis
-#define FV_G(i) Voxel<DT>::f(st.g[i])
+#define FV_G(i) Vx<DT>::f(st.g[i])
     const float xm00 = FV_G(0), xm10 = FV_G(1), xm01 = FV_G(2), xm11 = FV_G(3);
     const float xp00 = FV_G(4), xp10 = FV_G(5), xp01 = FV_G(6), xp11 = FV_G(7);
     const float ym00 = FV_G(8), ym10 = FV_G(9), ym01 = FV_G(10), ym11 = FV_G(11);
@@ -810,9 +833,11 @@ fv_status fill_args(const fv_volume* v, const float* tf, int tf_n, const fv_came
   if (mp->shading != 0 && mp->shading != 1)
     return fail(FV_ERR_UNSUPPORTED, "%s: shading must be 0 or 1", fn);
   a->vol = v->data;
-  a->vol_bytes = (uint32_t)((uint64_t)v->px * v->py * v->pz * dtype_bytes(v->dt));
-  a->px = v->px;
-  a->py = v->py;
+  a->vol_bytes = (uint32_t)v->bytes;
+  a->nb[0] = v->nb[0];
+  a->nb[1] = v->nb[1];
+  a->px = v->brick ? kBrickRow : v->px;
+  a->py = v->brick ? kBrickRow : v->py;
   int nmax = 0;
   for (int i = 0; i < 3; ++i) {
     a->n[i] = v->n[i];
@@ -907,15 +932,24 @@ fv_status dense_entry(const char* who, const fv_volume* v, const float* tf_rgba,
   (mode == 0   ? launch_dense<DT, false, false>(a, mask, frame_rgba, frame_depth, sample_count, s) \
    : mode == 1 ? launch_dense<DT, true, false>(a, mask, frame_rgba, frame_depth, sample_count, s)  \
                : launch_dense<DT, true, true>(a, mask, frame_rgba, frame_depth, sample_count, s))
-  switch (v->dt) {
+  switch (v->dt + (v->brick ? kBricked : 0)) {
     case FV_U8:
       FV_DENSE(FV_U8);
       break;
     case FV_F16:
       FV_DENSE(FV_F16);
       break;
-    default:
+    case FV_F32:
       FV_DENSE(FV_F32);
+      break;
+    case FV_U8 + kBricked:
+      FV_DENSE(FV_U8 + kBricked);
+      break;
+    case FV_F16 + kBricked:
+      FV_DENSE(FV_F16 + kBricked);
+      break;
+    default:
+      FV_DENSE(FV_F32 + kBricked);
   }
 #undef FV_DENSE
   return launch_status(who);
@@ -1011,15 +1045,24 @@ fv_status fv_raymarch_sparse(const fv_volume* v, const float* tf_rgba, int tf_n,
 #define FV_SPARSE(DT)                                                                     \
   (mode == 0 ? FV_SPARSE_M(DT, false, false)                                            \
              : mode == 1 ? FV_SPARSE_M(DT, true, false) : FV_SPARSE_M(DT, true, true))
-  switch (v->dt) {
+  switch (v->dt + (v->brick ? fv::kBricked : 0)) {
     case FV_U8:
       FV_SPARSE(FV_U8);
       break;
     case FV_F16:
       FV_SPARSE(FV_F16);
       break;
-    default:
+    case FV_F32:
       FV_SPARSE(FV_F32);
+      break;
+    case FV_U8 + fv::kBricked:
+      FV_SPARSE(FV_U8 + fv::kBricked);
+      break;
+    case FV_F16 + fv::kBricked:
+      FV_SPARSE(FV_F16 + fv::kBricked);
+      break;
+    default:
+      FV_SPARSE(FV_F32 + fv::kBricked);
   }
 #undef FV_SPARSE
 #undef FV_SPARSE_M
