@@ -477,9 +477,10 @@ def main():
                 "bytes_model": {"bytes_per_sample": bytes_per_sample,
                                 "achieved_gbs": round(ach_gbs, 1),
                                 "frac_of_hbm_peak": round(ach_gbs / HBM_PEAK_GBS, 4)},
-                "note": "the stencil voxels are served by L2/MALL (L2 hit rate 0.94); the HBM "
-                        "bytes actually moved (`traffic`) are a few % of the HBM peak, so "
-                        "the bound is the vector ALU issue, not DRAM"}
+                "note": "the stencil voxels are served by L2/MALL (L2 hit rate 0.94 with the "
+                        "linear copy, 0.67 of half as many requests with the bricked one); "
+                        "the HBM bytes actually moved (`traffic`) are under 10 % of the HBM "
+                        "peak, so the bound is the vector ALU issue, not DRAM"}
     dn_avg = sum(dense_kernel_ms) / len(dense_kernel_ms)
     dense_ach = dense_samples / args.steps * bytes_per_sample / (dn_avg * 1e-3) / 1e9
 
