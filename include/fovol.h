@@ -704,6 +704,35 @@ fv_status fv_wnet_reconstruct_recurrent(const fv_wnet* n, const float* frame_rgb
                                         float* out_direct, void* workspace, size_t ws_bytes,
                                         void* stream);
 
+/* Training of the (plain) W-Net on the GPU, BF16 like fv_train_step: the
+ * forward keeps D's activations and K's per-level kernels, blend weights and
+ * blends; the loss is fv_net_loss's (0.9 (1 - SSIM) + 0.1 L1); the backward
+ * pass computes every parameter's gradient (D's convs on MFMA as
+ * fv_net_backward; K's 5x5 applications, softmax, blends, pooling,
+ * upsampling and 1x1 predictors in FP32), and fv_wnet_adam takes one Adam
+ * step on the FP32 master (then rebuilds D's BF16 copies).  Reductions use
+ * fixed orders, so a step is deterministic.  Frames at least 16 x 16,
+ * multiples of 8.  Arguments and layouts as the fv_net training calls
+ * (grad_out: dev float [FV_WNET_PARAMS] or NULL).  Errors: those of the
+ * fv_net training calls, FV_ERR_UNSUPPORTED for a recurrent handle.
+ * fv_wnet_get_params / fv_wnet_set_params copy the FP32 master to / from
+ * the host (set rebuilds the BF16 copies and synchronises). */
+fv_status fv_wnet_train_workspace(const fv_wnet* n, int batch, int width, int height,
+                                  size_t* bytes);
+fv_status fv_wnet_forward_train(fv_wnet* n, const float* frame_rgba, const uint8_t* mask,
+                                const float* frame_depth, int batch, int width, int height,
+                                float* out_rgb, void* workspace, size_t ws_bytes, void* stream);
+fv_status fv_wnet_backward(fv_wnet* n, const float* dloss_dout, int batch, int width,
+                           int height, float* grad_out, void* workspace, size_t ws_bytes,
+                           void* stream);
+fv_status fv_wnet_adam(fv_wnet* n, float lr, float beta1, float beta2, float eps, void* stream);
+fv_status fv_wnet_train_step(fv_wnet* n, const float* frame_rgba, const uint8_t* mask,
+                             const float* frame_depth, const float* target_rgba, int batch,
+                             int width, int height, float lr, float* loss3, void* workspace,
+                             size_t ws_bytes, void* stream);
+fv_status fv_wnet_get_params(const fv_wnet* n, float* host_out, size_t n_params);
+fv_status fv_wnet_set_params(fv_wnet* n, const float* host_params, size_t n_params);
+
 /* ------------------------------------------------------------------------
  * 5. Training of the reconstruction network (paper: "Loss", "Training")
  * ------------------------------------------------------------------------

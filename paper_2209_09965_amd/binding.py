@@ -130,6 +130,15 @@ _SIGS = {
     "fv_wnet_state_layout": (_i, [_i, _i, _i] + [ctypes.POINTER(_sz)] * 4),
     "fv_wnet_reconstruct_recurrent": (_i, [_vp, _vp, _vp, _vp, _vp, _sz, _i, _i, _i, _i, _vp,
                                            _vp, _vp, _sz, _vp]),
+    "fv_wnet_train_workspace": (_i, [_vp, _i, _i, _i, ctypes.POINTER(_sz)]),
+    "fv_wnet_forward_train": (_i, [_vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp, _sz, _vp]),
+    "fv_wnet_backward": (_i, [_vp, _vp, _i, _i, _i, _vp, _vp, _sz, _vp]),
+    "fv_wnet_adam": (_i, [_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                          _vp]),
+    "fv_wnet_train_step": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, ctypes.c_float, _vp, _vp,
+                                _sz, _vp]),
+    "fv_wnet_get_params": (_i, [_vp, _vp, _sz]),
+    "fv_wnet_set_params": (_i, [_vp, _vp, _sz]),
     "fv_reconstruct_tensor": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(_sz),
                                    ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "fv_reconstruct_steps": (_i, [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _i, _i, _i, _vp, _vp,
@@ -491,14 +500,22 @@ class WNet:
             check(_lib.fv_wnet_destroy(self.handle))
             self.handle = None
 
+    @property
+    def n_params(self):
+        return self.PARAMS_RECURRENT if self.recurrent else self.PARAMS
+
     @staticmethod
-    def workspace_bytes(views, width, height):
+    def workspace_bytes(views, width, height, precision="bf16"):
+        if precision != "bf16":
+            raise ValueError("the W-Net runs in BF16")
         b = _sz()
         check(_lib.fv_wnet_workspace(views, width, height, ctypes.byref(b)))
         return b.value
 
     def reconstruct(self, frame_rgba, mask, frame_depth, views, width, height, out_rgb,
-                    out_direct=None, workspace=None, stream=None):
+                    out_direct=None, workspace=None, stream=None, precision="bf16"):
+        if precision != "bf16":
+            raise ValueError("the W-Net runs in BF16")
         npx = views * width * height
         if workspace is None:
             workspace = torch.empty(self.workspace_bytes(views, width, height), dtype=torch.uint8,
@@ -509,6 +526,58 @@ class WNet:
             _dev(frame_depth, "frame_depth", F32, npx, False), views, width, height,
             _dev(out_rgb, "out_rgb", F32, npx * 3),
             _dev(out_direct, "out_direct", F32, npx * 3, False), wp, wb, _stream(stream)))
+
+
+    # ---- training (plain form)
+    def train_workspace_bytes(self, batch, width, height):
+        b = _sz()
+        check(_lib.fv_wnet_train_workspace(self.handle, batch, width, height, ctypes.byref(b)))
+        return b.value
+
+    def _frame_args(self, frame_rgba, mask, frame_depth, batch, width, height):
+        npx = batch * width * height
+        return (_dev(frame_rgba, "frame_rgba", F32, npx * 4), _dev(mask, "mask", U8, npx),
+                _dev(frame_depth, "frame_depth", F32, npx, False))
+
+    def forward_train(self, frame_rgba, mask, frame_depth, batch, width, height, out_rgb,
+                      workspace, stream=None):
+        fa = self._frame_args(frame_rgba, mask, frame_depth, batch, width, height)
+        wp, wb = _ws(workspace)
+        check(_lib.fv_wnet_forward_train(self.handle, *fa, batch, width, height,
+                                         _dev(out_rgb, "out_rgb", F32, batch * width * height * 3),
+                                         wp, wb, _stream(stream)))
+
+    def backward(self, dloss, batch, width, height, workspace, grad_out=None, stream=None):
+        wp, wb = _ws(workspace)
+        check(_lib.fv_wnet_backward(self.handle,
+                                    _dev(dloss, "dloss", F32, batch * width * height * 3), batch,
+                                    width, height,
+                                    _dev(grad_out, "grad_out", F32, self.n_params, False), wp,
+                                    wb, _stream(stream)))
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        check(_lib.fv_wnet_adam(self.handle, lr, beta1, beta2, eps, _stream(stream)))
+
+    def train_step(self, frame_rgba, mask, frame_depth, target_rgba, batch, width, height, lr,
+                   loss3, workspace, stream=None):
+        npx = batch * width * height
+        fa = self._frame_args(frame_rgba, mask, frame_depth, batch, width, height)
+        wp, wb = _ws(workspace)
+        check(_lib.fv_wnet_train_step(self.handle, *fa,
+                                      _dev(target_rgba, "target_rgba", F32, npx * 4), batch,
+                                      width, height, lr, _dev(loss3, "loss3", F32, 3), wp, wb,
+                                      _stream(stream)))
+
+    def get_params(self):
+        import numpy as np
+        out = np.zeros(self.n_params, dtype=np.float32)
+        check(_lib.fv_wnet_get_params(self.handle, ctypes.c_void_p(out.ctypes.data), out.size))
+        return out
+
+    def set_params(self, params):
+        import numpy as np
+        arr = np.ascontiguousarray(params, dtype=np.float32)
+        check(_lib.fv_wnet_set_params(self.handle, ctypes.c_void_p(arr.ctypes.data), arr.size))
 
 
 def wnet_param_count(recurrent=False):

@@ -108,6 +108,30 @@ fv_status pack_input_bf16(const float* frame, const uint8_t* mask, const float* 
                           const float* prev, uint8_t* out, int64_t npx, hipStream_t s);
 fv_status check_frame(int views, int W, int H, const char* fn);
 
+// Training pieces shared with the W-Net (net_train.hip): the loss (SSIM +
+// L1, its scratch: target RGB, SSIM maps, partial sums), the backward
+// elementwise kernels, the MFMA weight gradient of a 3x3 conv (with its
+// chunk count and partial-sum sizes) and Adam.
+size_t loss_ssim_bytes(int n, int h, int w);
+size_t loss_red_bytes(int n, int h, int w);
+fv_status loss_run(const float* out_rgb, const float* target_rgba, int n, int h, int w,
+                   float* loss3, float* dloss_dout, float* tgt, uint8_t* ssim, double* red,
+                   hipStream_t s);
+void launch_relu_mask(const float* g, const uint8_t* y, uint8_t* dz, int64_t n8, hipStream_t s);
+void launch_upsample_bwd(const float* gup, int ch_stride, int c0, int n, int hl, int wl,
+                         float* glow, int acc, hipStream_t s);
+void launch_split_skip(const float* tmp, int ch_stride, int c0, int c1, int64_t npx,
+                       float* gskip, hipStream_t s);
+void launch_pool_bwd_add(const float* gp, int n, int h, int w, int c, float* g, hipStream_t s);
+int wgrad_chunks(int n, int h, int w, int ci, int co);
+size_t wgrad_part_bytes(int chunks, int ci, int co);
+size_t wgrad_part2_bytes(int ci, int co);
+struct ConvArgs;
+fv_status conv_wgrad(const ConvArgs& in, const uint8_t* dz, int ci, int co, int chunks,
+                     float* part, float* part2, float* grad, hipStream_t s);
+fv_status adam_run(float* th, float* m, float* v, const float* g, int64_t n, float lr, float b1,
+                   float b2, float eps, int64_t step, hipStream_t s);
+
 }  // namespace net
 }  // namespace fv
 

@@ -483,7 +483,24 @@ fv_status launch_conv(const ConvArgs& args, int nb, hipStream_t s) {
     case 6: conv_nb<E, 6>(a, R, s); break;
     case 7: conv_nb<E, 7>(a, R, s); break;
     case 10: conv_nb<E, 10>(a, R, s); break;
-    default: return fail(FV_ERR_UNSUPPORTED, "conv: %d output blocks", nb);
+    default:
+      // 8, 9 and 11 blocks (128, 144, 176 channels): the W-Net's input-
+      // gradient convolutions, BF16 only
+      if constexpr (E::kBytes == 2) {
+        if (nb == 8) {
+          conv_nb<E, 8>(a, R, s);
+          break;
+        }
+        if (nb == 9) {
+          conv_nb<E, 9>(a, R, s);
+          break;
+        }
+        if (nb == 11) {
+          conv_nb<E, 11>(a, R, s);
+          break;
+        }
+      }
+      return fail(FV_ERR_UNSUPPORTED, "conv: %d output blocks", nb);
   }
   if (pool_out && !a.pool_out) {
     const int64_t total = (int64_t)a.n * (a.h / 2) * (a.w / 2) * (a.co / 8);

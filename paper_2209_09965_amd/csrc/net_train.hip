@@ -630,7 +630,7 @@ __device__ __forceinline__ float up_weight(int o, int q, int nlow) {
 
 __global__ void __launch_bounds__(256) k_upsample_bwd(const float* __restrict__ gup, int ch_stride,
                                                       int c0, int n, int hl, int wl,
-                                                      float* __restrict__ glow) {
+                                                      float* __restrict__ glow, int acc) {
   const int64_t total = (int64_t)n * hl * wl * c0;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= total) return;
@@ -652,7 +652,7 @@ __global__ void __launch_bounds__(256) k_upsample_bwd(const float* __restrict__ 
       s = fmaf(wy * wx, gup[(((int64_t)b * h + y) * w + x) * ch_stride + c], s);
     }
   }
-  glow[e] = s;
+  glow[e] = acc ? glow[e] + s : s;
 }
 
 // copy channels [c0, c0 + c1) of the transposed-conv output into the skip
@@ -725,6 +725,102 @@ static fv_status upload_gauss() {
   return st;
 }
 
+// ---------------------------------------------------- shared with the W-Net
+
+namespace fv {
+namespace net {
+
+size_t loss_ssim_bytes(int n, int h, int w) {
+  const size_t q = (size_t)n * 3;
+  return al(q * h * (w - 10) * 4 * 5) + al(q * (h - 10) * (w - 10) * 4 * 3) +
+         al(q * h * (w - 10) * 4 * 3);
+}
+
+size_t loss_red_bytes(int n, int h, int w) {
+  const int64_t q = (int64_t)n * 3;
+  const int64_t vblocks = (q * (h - 10) * (w - 10) + 255) / 256;
+  const int64_t lblocks = (q * h * w + 255) / 256;
+  return al((size_t)(vblocks + lblocks) * 8);
+}
+
+fv_status loss_run(const float* out_rgb, const float* target_rgba, int n, int h, int w,
+                   float* loss3, float* dloss_dout, float* tgt, uint8_t* ssim, double* red,
+                   hipStream_t s) {
+  fv_status st = upload_gauss();
+  if (st != FV_OK) return st;
+  const int64_t npx = (int64_t)n * h * w;
+  k_rgb_of_rgba<<<nblk(npx), 256, 0, s>>>((const float4*)target_rgba, tgt, npx);
+  const int64_t q = (int64_t)n * 3;
+  const int64_t htot = q * h * (w - 10), vtot = q * (h - 10) * (w - 10);
+  float* hq = (float*)ssim;
+  float* dmap = (float*)(ssim + al(htot * 4 * 5));
+  float* va = (float*)(ssim + al(htot * 4 * 5) + al(vtot * 4 * 3));
+  const unsigned nbv = nblk(vtot), nbl = nblk(q * h * w);
+  k_ssim_h<<<nblk(htot), 256, 0, s>>>(out_rgb, tgt, n, h, w, hq);
+  k_ssim_v<<<nbv, 256, 0, s>>>(hq, n, h, w, dmap, red);
+  k_ssim_vt<<<nblk(htot), 256, 0, s>>>(dmap, n, h, w, va);
+  const double ssim_scale = 1.0 / (double)vtot, l1_scale = 1.0 / (double)(q * h * w);
+  k_ssim_ht<<<nbl, 256, 0, s>>>(va, out_rgb, tgt, n, h, w, (float)ssim_scale, (float)l1_scale,
+                                dloss_dout, red + nbv);
+  k_loss_final<<<1, 256, 0, s>>>(red, (int)nbv, red + nbv, (int)nbl, ssim_scale, l1_scale, loss3);
+  return launch_status("loss");
+}
+
+void launch_relu_mask(const float* g, const uint8_t* y, uint8_t* dz, int64_t n8, hipStream_t s) {
+  k_relu_mask<<<nblk(n8), 256, 0, s>>>(g, y, dz, n8);
+}
+
+void launch_upsample_bwd(const float* gup, int ch_stride, int c0, int n, int hl, int wl,
+                         float* glow, int acc, hipStream_t s) {
+  k_upsample_bwd<<<nblk((int64_t)n * hl * wl * c0), 256, 0, s>>>(gup, ch_stride, c0, n, hl, wl,
+                                                                 glow, acc);
+}
+
+void launch_split_skip(const float* tmp, int ch_stride, int c0, int c1, int64_t npx,
+                       float* gskip, hipStream_t s) {
+  k_split_skip<<<nblk(npx * c1), 256, 0, s>>>(tmp, ch_stride, c0, c1, npx, gskip);
+}
+
+void launch_pool_bwd_add(const float* gp, int n, int h, int w, int c, float* g, hipStream_t s) {
+  k_pool_bwd_add<<<nblk((int64_t)n * h * w * c), 256, 0, s>>>(gp, n, h, w, c, g);
+}
+
+int wgrad_chunks(int n, int h, int w, int ci, int co) {
+  const int64_t tiles = (int64_t)n * ((h + kWgRows - 1) / kWgRows) * ((w + 15) / 16);
+  const int64_t groups = (int64_t)((ci + 31) / 32) * ((co + 31) / 32);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(tiles, 2048 / groups));
+}
+
+size_t wgrad_part_bytes(int chunks, int ci, int co) {
+  return (size_t)chunks * (9 * (size_t)ci * co + co) * 4;
+}
+
+size_t wgrad_part2_bytes(int ci, int co) {
+  return (size_t)kReduceSlices * (9 * (size_t)ci * co + co) * 4;
+}
+
+fv_status conv_wgrad(const ConvArgs& in, const uint8_t* dz, int ci, int co, int chunks,
+                     float* part, float* part2, float* grad, hipStream_t s) {
+  const int cig_n = (ci + 31) / 32;
+  dim3 gw((unsigned)(cig_n * ((co + 31) / 32)), (unsigned)chunks);
+  k_wgrad<<<gw, 256, 0, s>>>(in, dz, ci, co, cig_n, chunks, part);
+  const int64_t cnt = 9 * (int64_t)ci * co + co;
+  k_wgrad_reduce<<<dim3(nblk(cnt), kReduceSlices), 256, 0, s>>>(part, chunks, cnt, part2);
+  k_wgrad_reduce2<<<nblk(cnt), 256, 0, s>>>(part2, cnt, grad);
+  return launch_status("wgrad");
+}
+
+fv_status adam_run(float* th, float* m, float* v, const float* g, int64_t n, float lr, float b1,
+                   float b2, float eps, int64_t step, hipStream_t s) {
+  const float c1 = (float)(1.0 - std::pow((double)b1, (double)step));
+  const float c2 = (float)(1.0 - std::pow((double)b2, (double)step));
+  k_adam<<<nblk(n), 256, 0, s>>>(th, m, v, g, n, lr, b1, b2, eps, c1, c2);
+  return launch_status("adam");
+}
+
+}  // namespace net
+}  // namespace fv
+
 extern "C" {
 
 fv_status fv_train_workspace(const fv_net* n, int batch, int width, int height, size_t* bytes) {
@@ -794,27 +890,10 @@ fv_status fv_net_loss(const fv_net* n, const float* out_rgb, const float* target
   if (st != FV_OK) return st;
   if (!out_rgb || !target_rgba || !loss3 || !dloss_dout)
     return fail(FV_ERR_INVALID_ARG, "fv_net_loss: null pointer");
-  if ((st = upload_gauss()) != FV_OK) return st;
-  hipStream_t s = (hipStream_t)stream;
   uint8_t* ws = (uint8_t*)workspace;
-  const int64_t npx = (int64_t)batch * height * width;
-  float* tgt = (float*)(ws + tp.target);
-  k_rgb_of_rgba<<<nblk(npx), 256, 0, s>>>((const float4*)target_rgba, tgt, npx);
-  const int64_t q = (int64_t)batch * 3;
-  const int64_t htot = q * height * (width - 10), vtot = q * (height - 10) * (width - 10);
-  float* hq = (float*)(ws + tp.ssim);
-  float* dmap = (float*)(ws + tp.ssim + al(htot * 4 * 5));
-  float* va = (float*)(ws + tp.ssim + al(htot * 4 * 5) + al(vtot * 4 * 3));
-  double* red = (double*)(ws + tp.red);
-  const unsigned nbv = nblk(vtot), nbl = nblk(q * height * width);
-  k_ssim_h<<<nblk(htot), 256, 0, s>>>(out_rgb, tgt, batch, height, width, hq);
-  k_ssim_v<<<nbv, 256, 0, s>>>(hq, batch, height, width, dmap, red);
-  k_ssim_vt<<<nblk(htot), 256, 0, s>>>(dmap, batch, height, width, va);
-  const double ssim_scale = 1.0 / (double)vtot, l1_scale = 1.0 / (double)(q * height * width);
-  k_ssim_ht<<<nbl, 256, 0, s>>>(va, out_rgb, tgt, batch, height, width, (float)ssim_scale,
-                                (float)l1_scale, dloss_dout, red + nbv);
-  k_loss_final<<<1, 256, 0, s>>>(red, (int)nbv, red + nbv, (int)nbl, ssim_scale, l1_scale, loss3);
-  return launch_status("fv_net_loss");
+  return loss_run(out_rgb, target_rgba, batch, height, width, loss3, dloss_dout,
+                  (float*)(ws + tp.target), ws + tp.ssim, (double*)(ws + tp.red),
+                  (hipStream_t)stream);
 }
 
 fv_status fv_net_loss_temporal(const fv_net* n, const float* out_rgb, const float* target_rgba,
@@ -925,7 +1004,7 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
     if (concat) {
       const int hl = hh / 2, wl = ww / 2;
       k_upsample_bwd<<<nblk((int64_t)p.n * hl * wl * L.c0), 256, 0, s>>>(
-          tmp, L.c0 + L.c1, L.c0, p.n, hl, wl, G(io[0]));
+          tmp, L.c0 + L.c1, L.c0, p.n, hl, wl, G(io[0]), 0);
       k_split_skip<<<nblk(px * L.c1), 256, 0, s>>>(tmp, L.c0 + L.c1, L.c0, L.c1, px, G(io[1]));
     }
     // the pooled input's gradient flows back to the pooled tensor's source

@@ -305,6 +305,200 @@ __global__ void __launch_bounds__(256) k_blend(const float* __restrict__ je,
 
 static unsigned blocks_of(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// ------------------------------------------------------- K, backward pass
+
+// Adjoint of out(p) = sum_k wk[p][k] img(clamp(p + d_k)) with respect to the
+// kernel weights: dwk[p][k] = sum_c dout[p][c] img(clamp(p + d_k))[c].
+__global__ void __launch_bounds__(256) k_apply_bwd_w(const float* __restrict__ dout,
+                                                     const float* __restrict__ img, int n, int h,
+                                                     int w, float* __restrict__ dwk) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= (int64_t)n * h * w) return;
+  const int x = (int)(p % w);
+  const int64_t r = p / w;
+  const int y = (int)(r % h);
+  const int64_t base = (r / h) * h * w;
+  const float g0 = dout[p * 3], g1 = dout[p * 3 + 1], g2 = dout[p * 3 + 2];
+  for (int dy = -2; dy <= 2; ++dy) {
+    const int yy = min(max(y + dy, 0), h - 1);
+    for (int dx = -2; dx <= 2; ++dx) {
+      const int xx = min(max(x + dx, 0), w - 1);
+      const float* q = img + (base + (int64_t)yy * w + xx) * 3;
+      dwk[p * kTaps + 5 * (dy + 2) + (dx + 2)] = fmaf(g0, q[0], fmaf(g1, q[1], g2 * q[2]));
+    }
+  }
+}
+
+// Rows (columns) p of an axis of length n whose tap d, clamped, lands on q:
+// q - d inside the image, widened to the image edge when q is an edge.
+__device__ __forceinline__ void tap_range(int q, int d, int n, int* lo, int* hi) {
+  *lo = max(q == 0 ? 0 : q - d, 0);
+  *hi = min(q == n - 1 ? n - 1 : q - d, n - 1);
+}
+
+// Adjoint with respect to the image: dimg(q) = sum over (p, k) with
+// clamp(p + d_k) = q of wk[p][k] dout[p], in a fixed order.
+__global__ void __launch_bounds__(256) k_apply_bwd_img(const float* __restrict__ wk,
+                                                       const float* __restrict__ dout, int n,
+                                                       int h, int w, float* __restrict__ dimg) {
+  const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (q >= (int64_t)n * h * w) return;
+  const int qx = (int)(q % w);
+  const int64_t r = q / w;
+  const int qy = (int)(r % h);
+  const int64_t base = (r / h) * h * w;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+  for (int dy = -2; dy <= 2; ++dy) {
+    int ylo, yhi;
+    tap_range(qy, dy, h, &ylo, &yhi);
+    for (int dx = -2; dx <= 2; ++dx) {
+      int xlo, xhi;
+      tap_range(qx, dx, w, &xlo, &xhi);
+      const int k = 5 * (dy + 2) + (dx + 2);
+      for (int py = ylo; py <= yhi; ++py)
+        for (int px = xlo; px <= xhi; ++px) {
+          const int64_t pp = base + (int64_t)py * w + px;
+          const float c = wk[pp * kTaps + k];
+          a0 = fmaf(c, dout[pp * 3], a0);
+          a1 = fmaf(c, dout[pp * 3 + 1], a1);
+          a2 = fmaf(c, dout[pp * 3 + 2], a2);
+        }
+    }
+  }
+  dimg[q * 3] = a0;
+  dimg[q * 3 + 1] = a1;
+  dimg[q * 3 + 2] = a2;
+}
+
+// Softmax backward of the 25 kernel logits: dz[k] = wk[k] (dwk[k] - sum_j
+// wk[j] dwk[j]); dz has `stride` values per pixel (25, or 26 with the blend).
+__global__ void __launch_bounds__(256) k_softmax_bwd(const float* __restrict__ wk,
+                                                     const float* __restrict__ dwk, int64_t npx,
+                                                     int stride, float* __restrict__ dz) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= npx) return;
+  float dot = 0.f;
+  for (int k = 0; k < kTaps; ++k) dot = fmaf(wk[p * kTaps + k], dwk[p * kTaps + k], dot);
+  for (int k = 0; k < kTaps; ++k)
+    dz[p * stride + k] = wk[p * kTaps + k] * (dwk[p * kTaps + k] - dot);
+}
+
+// Blend backward at a decoder level (h x w; jc the coarser image):
+// B = (1 - a) je + a U with U = up(jc): dje = (1 - a) dB, dU = a dB and the
+// blend logit's gradient sum_c (U - je) dB times a (1 - a) into dz[p][25].
+__global__ void __launch_bounds__(256) k_blend_bwd(const float* __restrict__ je,
+                                                   const float* __restrict__ jc,
+                                                   const float* __restrict__ a,
+                                                   const float* __restrict__ dB, int n, int h,
+                                                   int w, float* __restrict__ dje,
+                                                   float* __restrict__ dU,
+                                                   float* __restrict__ dz) {
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= (int64_t)n * h * w) return;
+  const int x = (int)(p % w);
+  const int64_t r = p / w;
+  const int y = (int)(r % h);
+  const int64_t b = r / h;
+  const int hc = h / 2, wc = w / 2;
+  int y0, y1, x0, x1;
+  float fy, fx;
+  up_axis(y, hc, &y0, &y1, &fy);
+  up_axis(x, wc, &x0, &x1, &fx);
+  const float* c00 = jc + ((b * hc + y0) * wc + x0) * 3;
+  const float* c01 = jc + ((b * hc + y0) * wc + x1) * 3;
+  const float* c10 = jc + ((b * hc + y1) * wc + x0) * 3;
+  const float* c11 = jc + ((b * hc + y1) * wc + x1) * 3;
+  const float av = a[p];
+  float da = 0.f;
+  for (int c = 0; c < 3; ++c) {
+    const float top = c00[c] * (1.0f - fx) + c01[c] * fx;
+    const float bot = c10[c] * (1.0f - fx) + c11[c] * fx;
+    const float u = top * (1.0f - fy) + bot * fy;
+    const float g = dB[p * 3 + c];
+    da = fmaf(u - je[p * 3 + c], g, da);
+    dje[p * 3 + c] = (1.0f - av) * g;
+    dU[p * 3 + c] = av * g;
+  }
+  dz[p * (kTaps + 1) + kTaps] = da * av * (1.0f - av);
+}
+
+// 1x1 layer backward, input side: dH[p][c] (+)= sum_t W[t][c] dz[p][t].
+__global__ void __launch_bounds__(256) k_predict_bwd_h(const float* __restrict__ dz, int T,
+                                                       const float* __restrict__ W, int C,
+                                                       int64_t npx, float* __restrict__ dh,
+                                                       int acc) {
+  extern __shared__ float sw[];  // W [T][C]
+  for (int i = threadIdx.x; i < T * C; i += 256) sw[i] = W[i];
+  __syncthreads();
+  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (p >= npx) return;
+  float g[kTaps + 1];
+  for (int t = 0; t < T; ++t) g[t] = dz[p * T + t];
+  for (int c = 0; c < C; ++c) {
+    float v = 0.f;
+    for (int t = 0; t < T; ++t) v = fmaf(sw[t * C + c], g[t], v);
+    dh[p * C + c] = acc ? dh[p * C + c] + v : v;
+  }
+}
+
+// 1x1 layer backward, weight side: per pixel chunk, part[t][c] = sum_p
+// dz[p][t] H[p][c] and part[t][C] = sum_p dz[p][t]; 64 pixels at a time in
+// LDS, up to 10 outputs per thread.
+constexpr int kPredChunkOut = 10;
+__global__ void __launch_bounds__(256) k_predict_wgrad(const float* __restrict__ dz, int T,
+                                                       const __bf16* __restrict__ hb, int C,
+                                                       int64_t npx, int chunks,
+                                                       float* __restrict__ part) {
+  __shared__ float sd[64 * (kTaps + 1)];
+  __shared__ float sh[64 * 97];
+  const int chunk = blockIdx.x, tid = threadIdx.x;
+  const int64_t p0 = npx * chunk / chunks, p1 = npx * (chunk + 1) / chunks;
+  const int C1 = C + 1, nout = T * C1;
+  float acc[kPredChunkOut];
+  for (int j = 0; j < kPredChunkOut; ++j) acc[j] = 0.f;
+  const uint16_t* h16 = (const uint16_t*)hb;
+  for (int64_t base = p0; base < p1; base += 64) {
+    const int cnt = (int)min((int64_t)64, p1 - base);
+    __syncthreads();
+    for (int e = tid; e < 64 * T; e += 256) {
+      const int pp = e / T;
+      sd[e] = pp < cnt ? dz[(base + pp) * T + e % T] : 0.f;
+    }
+    for (int e = tid; e < 64 * C1; e += 256) {
+      const int pp = e / C1, k = e % C1;
+      sh[e] = pp < cnt ? (k < C ? net::bf16_bits_to_f(h16[(base + pp) * C + k]) : 1.0f) : 0.f;
+    }
+    __syncthreads();
+    for (int j = 0; j < kPredChunkOut; ++j) {
+      const int o = tid + 256 * j;
+      if (o >= nout) break;
+      const int t = o / C1, k = o % C1;
+      float sacc = acc[j];
+#pragma unroll 8
+      for (int pp = 0; pp < 64; ++pp) sacc = fmaf(sd[pp * T + t], sh[pp * C1 + k], sacc);
+      acc[j] = sacc;
+    }
+  }
+  for (int j = 0; j < kPredChunkOut; ++j) {
+    const int o = tid + 256 * j;
+    if (o < nout) part[(int64_t)chunk * nout + o] = acc[j];
+  }
+}
+
+// Sum of the chunk partials (in chunk order) into the layer's gradient:
+// weight [T][C] then bias [T].
+__global__ void __launch_bounds__(256) k_predict_reduce(const float* __restrict__ part,
+                                                        int chunks, int T, int C,
+                                                        float* __restrict__ grad) {
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  const int C1 = C + 1;
+  if (o >= T * C1) return;
+  float s = 0.f;
+  for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * T * C1 + o];
+  const int t = o / C1, k = o % C1;
+  grad[k < C ? t * C + k : T * C + t] = s;
+}
+
 }  // namespace wnet
 }  // namespace fv
 
@@ -314,6 +508,13 @@ struct fv_wnet {
   const fv::wnet::Layer* L;            // its layer table
   float* master;                       // FP32 parameters, the order of the layer table
   void* w_bf16[fv::wnet::kConv];       // D's convs as swizzled BF16 MFMA fragments
+  // training (plain form): gradient, Adam moments and step, the transposed
+  // BF16 weights of D's input-gradient convolutions
+  float* grad;
+  float* adam_m;
+  float* adam_v;
+  int64_t step;
+  void* w_bf16t[fv::wnet::kConv];
 };
 
 using namespace fv;
@@ -321,10 +522,35 @@ using namespace fv::wnet;
 
 namespace {
 
+// D's BF16 weight fragments from the FP32 master (and, for training, the
+// transposed ones of the input-gradient convolutions).
+fv_status refresh_bf16(fv_wnet* n, hipStream_t s) {
+  fv_status st = FV_OK;
+  for (int l = 0; st == FV_OK && l < kConv; ++l) {
+    st = net::swizzle_bf16(n->master + param_offset(n->L, l), n->L[l].ci, n->L[l].co, 0,
+                           n->w_bf16[l], s);
+    if (st == FV_OK && n->w_bf16t[l])
+      st = net::swizzle_bf16(n->master + param_offset(n->L, l), n->L[l].ci, n->L[l].co, 1,
+                             n->w_bf16t[l], s);
+  }
+  return st;
+}
+
+// What a training forward keeps of K for the backward pass: per level the
+// encoder's kernel weights, and the decoder's kernel weights, blend weights
+// and blends (inference reuses one buffer of each across levels).
+struct KKeep {
+  float* wke[4];
+  float* wkd[3];
+  float* av[3];
+  float* bl[3];
+};
+
 fv_status reconstruct(const fv_wnet* n, const float* frame_rgba, const uint8_t* mask,
                       const float* frame_depth, void* state, size_t state_bytes, int reset,
                       int views, int width, int height, float* out_rgb, float* out_direct,
-                      void* workspace, size_t ws_bytes, void* stream, const char* fn) {
+                      void* workspace, size_t ws_bytes, void* stream, const char* fn,
+                      const KKeep* keep = nullptr) {
   if (!n || !frame_rgba || !mask || !out_rgb || !workspace)
     return fail(FV_ERR_INVALID_ARG, "%s: null pointer", fn);
   const bool rec = state != nullptr;
@@ -411,10 +637,11 @@ fv_status reconstruct(const fv_wnet* n, const float* frame_rgba, const uint8_t* 
     const int h = height >> l, w = width >> l;
     const int64_t m = (int64_t)views * h * w;
     const float* wl = n->master + param_offset(LT, kKe0 + l);
+    float* wkl = keep ? keep->wke[l] : wk;
     k_predict<kTaps, 1><<<blocks_of(m), 256, (kTaps * L.ci + kTaps) * 4, s>>>(
-        (const __bf16*)tensor(kHidden[l]), L.ci, wl, wl + kTaps * L.ci, m, wk, nullptr);
+        (const __bf16*)tensor(kHidden[l]), L.ci, wl, wl + kTaps * L.ci, m, wkl, nullptr);
     float* je = (float*)(ws + p.je[l]);
-    k_apply<<<blocks_of(m), 256, 0, s>>>(wk, jin, views, h, w, je);
+    k_apply<<<blocks_of(m), 256, 0, s>>>(wkl, jin, views, h, w, je);
     if (l < 3) {
       float* nxt = (float*)(ws + p.jin[l + 1]);
       k_pool3<<<blocks_of(m / 4), 256, 0, s>>>(je, views, h, w, nxt);
@@ -430,16 +657,278 @@ fv_status reconstruct(const fv_wnet* n, const float* frame_rgba, const uint8_t* 
     const int h = height >> l, w = width >> l;
     const int64_t m = (int64_t)views * h * w;
     const float* wl = n->master + param_offset(LT, li);
+    float* wkl = keep ? keep->wkd[l] : wk;
+    float* avl = keep ? keep->av[l] : av;
+    float* bl = keep ? keep->bl[l] : (float*)(ws + p.blend);
     k_predict<kTaps + 1, 2><<<blocks_of(m), 256, ((kTaps + 1) * L.ci + kTaps + 1) * 4, s>>>(
-        (const __bf16*)tensor(kHidden[l]), L.ci, wl, wl + (kTaps + 1) * L.ci, m, wk, av);
-    float* bl = (float*)(ws + p.blend);
-    k_blend<<<blocks_of(m), 256, 0, s>>>((const float*)(ws + p.je[l]), jc, av, views, h, w, bl);
+        (const __bf16*)tensor(kHidden[l]), L.ci, wl, wl + (kTaps + 1) * L.ci, m, wkl, avl);
+    k_blend<<<blocks_of(m), 256, 0, s>>>((const float*)(ws + p.je[l]), jc, avl, views, h, w, bl);
     float* dst = l ? (float*)(ws + p.jd[l]) : out_rgb;
-    k_apply<<<blocks_of(m), 256, 0, s>>>(wk, bl, views, h, w, dst);
+    k_apply<<<blocks_of(m), 256, 0, s>>>(wkl, bl, views, h, w, dst);
     if ((st = launch_status("wnet: K decoder")) != FV_OK) return st;
     jc = dst;
   }
   return FV_OK;
+}
+
+// ---------------------------------------------------------------- training
+
+// Workspace of a training step: the forward plan, what the forward keeps of
+// K per level, FP32 gradients of D's tensors, the input-gradient conv output
+// (tmp), the masked BF16 output gradient (dz), K's image gradients, the
+// weight-gradient partial sums and the loss scratch.
+struct TPlan {
+  Plan f;
+  size_t wke[4], wkd[3], av[3], bl[3];
+  size_t g[kTensors];
+  size_t tmp, dz, w0;
+  size_t dja, djb, dje[3], db, du, dwk, dzk;
+  size_t kpart, part, part2;
+  size_t out, dout, tgt, ssim, red;
+  size_t bytes;
+  int chunks[kConv];
+  int kchunks;
+};
+
+TPlan make_tplan(int n, int h, int w) {
+  TPlan t;
+  t.f = make_plan(n, h, w);
+  size_t off = t.f.bytes;
+  auto px = [&](int lv) { return (size_t)n * (h >> lv) * (w >> lv); };
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += al(bytes);
+    return o;
+  };
+  for (int l = 0; l < 4; ++l) t.wke[l] = take(px(l) * kTaps * 4);
+  for (int l = 0; l < 3; ++l) {
+    t.wkd[l] = take(px(l) * kTaps * 4);
+    t.av[l] = take(px(l) * 4);
+    t.bl[l] = take(px(l) * 3 * 4);
+  }
+  t.g[T_IN] = 0;
+  for (int k = 1; k < kTensors; ++k) t.g[k] = take(px(kTC[k][1]) * kTC[k][0] * 4);
+  size_t tmp = 0, dz = 0, part = 0, part2 = 0;
+  for (int l = 0; l < kConv; ++l) {
+    const Layer& L = kL[l];
+    const int ci = L.c0 + L.c1;
+    tmp = std::max(tmp, px(L.level) * ci * 4);
+    dz = std::max(dz, px(L.level) * L.co * 2);
+    t.chunks[l] = net::wgrad_chunks(n, h >> L.level, w >> L.level, ci, L.co);
+    part = std::max(part, net::wgrad_part_bytes(t.chunks[l], ci, L.co));
+    part2 = std::max(part2, net::wgrad_part2_bytes(ci, L.co));
+  }
+  t.tmp = take(tmp);
+  t.dz = take(dz);
+  t.w0 = take((size_t)(9 * kL[0].c0 * kL[0].co + kL[0].co) * 4);
+  t.dja = take(px(0) * 3 * 4);
+  t.djb = take(px(0) * 3 * 4);
+  for (int l = 0; l < 3; ++l) t.dje[l] = take(px(l) * 3 * 4);
+  t.db = take(px(0) * 3 * 4);
+  t.du = take(px(0) * 3 * 4);
+  t.dwk = take(px(0) * kTaps * 4);
+  t.dzk = take(px(0) * (kTaps + 1) * 4);
+  t.kchunks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (int64_t)px(0) / 256));
+  t.kpart = take((size_t)t.kchunks * (kTaps + 1) * 97 * 4);
+  t.part = take(part);
+  t.part2 = take(part2);
+  t.out = take(px(0) * 3 * 4);
+  t.dout = take(px(0) * 3 * 4);
+  t.tgt = take(px(0) * 3 * 4);
+  t.ssim = take(net::loss_ssim_bytes(n, h, w));
+  t.red = take(net::loss_red_bytes(n, h, w));
+  t.bytes = off;
+  return t;
+}
+
+fv_status train_check(const fv_wnet* n, int batch, int width, int height, const void* ws,
+                      size_t ws_bytes, TPlan* tp, const char* fn) {
+  if (!n || !ws) return fail(FV_ERR_INVALID_ARG, "%s: null pointer", fn);
+  if (n->recurrent)
+    return fail(FV_ERR_UNSUPPORTED, "%s: training is built for the plain W-Net only", fn);
+  fv_status st = net::check_frame(batch, width, height, fn);
+  if (st != FV_OK) return st;
+  if (width < 16 || height < 16)
+    return fail(FV_ERR_INVALID_ARG, "%s: training frames must be at least 16 x 16", fn);
+  *tp = make_tplan(batch, height, width);
+  if (ws_bytes < tp->bytes)
+    return fail(FV_ERR_CAPACITY, "%s: workspace %zu < %zu bytes", fn, ws_bytes, tp->bytes);
+  if ((uintptr_t)ws % 256) return fail(FV_ERR_INVALID_ARG, "%s: workspace not aligned", fn);
+  return FV_OK;
+}
+
+KKeep keep_of(const TPlan& t, uint8_t* ws) {
+  KKeep k;
+  for (int l = 0; l < 4; ++l) k.wke[l] = (float*)(ws + t.wke[l]);
+  for (int l = 0; l < 3; ++l) {
+    k.wkd[l] = (float*)(ws + t.wkd[l]);
+    k.av[l] = (float*)(ws + t.av[l]);
+    k.bl[l] = (float*)(ws + t.bl[l]);
+  }
+  return k;
+}
+
+// Gradient of a 1x1 layer applied to H (BF16, C channels) from dz (T per
+// pixel): its weights and bias into grad, and dH (+)= W^T dz.
+fv_status predict_backward(const fv_wnet* n, const TPlan& tp, uint8_t* ws, int layer,
+                           const uint8_t* hten, float* gh, int acc, const float* dz, int T,
+                           int64_t m, hipStream_t s) {
+  const Layer& L = kL[layer];
+  const float* W = n->master + param_offset(kL, layer);
+  float* part = (float*)(ws + tp.kpart);
+  const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(tp.kchunks, m / 64));
+  k_predict_bwd_h<<<blocks_of(m), 256, T * L.ci * 4, s>>>(dz, T, W, L.ci, m, gh, acc);
+  k_predict_wgrad<<<chunks, 256, 0, s>>>(dz, T, (const __bf16*)hten, L.ci, m, chunks, part);
+  k_predict_reduce<<<blocks_of((int64_t)T * (L.ci + 1)), 256, 0, s>>>(
+      part, chunks, T, L.ci, n->grad + param_offset(kL, layer));
+  return launch_status("wnet: 1x1 backward");
+}
+
+fv_status backward(fv_wnet* n, const float* dloss_dout, int views, int width, int height,
+                   void* workspace, hipStream_t s) {
+  const TPlan tp = make_tplan(views, height, width);
+  const Plan& p = tp.f;
+  uint8_t* ws = (uint8_t*)workspace;
+  auto G = [&](int t) { return (float*)(ws + tp.g[t]); };
+  auto px = [&](int lv) { return (int64_t)views * (height >> lv) * (width >> lv); };
+  fv_status st = FV_OK;
+  // ---- K decoder, finest level first: dJ is the gradient of J_l
+  float* dj = (float*)(ws + tp.dja);
+  float* djn = (float*)(ws + tp.djb);
+  float* dB = (float*)(ws + tp.db);
+  float* dU = (float*)(ws + tp.du);
+  float* dwk = (float*)(ws + tp.dwk);
+  float* dzk = (float*)(ws + tp.dzk);
+  const float* djcur = dloss_dout;
+  for (int l = 0; l < 3; ++l) {
+    const int h = height >> l, w = width >> l;
+    const int64_t m = px(l);
+    const float* wk = (const float*)(ws + tp.wkd[l]);
+    const float* B = (const float*)(ws + tp.bl[l]);
+    const float* jc = l < 2 ? (const float*)(ws + p.jd[l + 1]) : (const float*)(ws + p.je[3]);
+    k_apply_bwd_w<<<blocks_of(m), 256, 0, s>>>(djcur, B, views, h, w, dwk);
+    k_apply_bwd_img<<<blocks_of(m), 256, 0, s>>>(wk, djcur, views, h, w, dB);
+    k_softmax_bwd<<<blocks_of(m), 256, 0, s>>>(wk, dwk, m, kTaps + 1, dzk);
+    k_blend_bwd<<<blocks_of(m), 256, 0, s>>>((const float*)(ws + p.je[l]), jc,
+                                             (const float*)(ws + tp.av[l]), dB, views, h, w,
+                                             (float*)(ws + tp.dje[l]), dU, dzk);
+    if ((st = launch_status("wnet: K decoder backward")) != FV_OK) return st;
+    // predictor kd_l reads H_l; the first contribution to its gradient
+    st = predict_backward(n, tp, ws, kKd2 + (2 - l), ws + p.t[kHidden[l]], G(kHidden[l]), 0,
+                          dzk, kTaps + 1, m, s);
+    if (st != FV_OK) return st;
+    // gradient of the coarser image J_(l+1) through the upsampling
+    net::launch_upsample_bwd(dU, 3, 3, views, h / 2, w / 2, djn, 0, s);
+    djcur = djn;
+    std::swap(dj, djn);
+  }
+  // ---- K encoder, coarsest level first: d is the gradient of Je_l
+  // (djcur holds that of J_3 = Je_3)
+  float* d = (float*)djcur;
+  for (int l = 3; l >= 0; --l) {
+    const int h = height >> l, w = width >> l;
+    const int64_t m = px(l);
+    if (l < 3) {
+      // Je_l feeds the decoder's blend (dje) and, pooled, the next level
+      float* de = (float*)(ws + tp.dje[l]);
+      net::launch_pool_bwd_add(d, views, h, w, 3, de, s);
+      d = de;
+    }
+    const float* wk = (const float*)(ws + tp.wke[l]);
+    const float* jin = l ? (const float*)(ws + p.jin[l]) : (const float*)(ws + p.od);
+    float* dnext = (d == dj) ? djn : dj;
+    k_apply_bwd_w<<<blocks_of(m), 256, 0, s>>>(d, jin, views, h, w, dwk);
+    k_apply_bwd_img<<<blocks_of(m), 256, 0, s>>>(wk, d, views, h, w, dnext);
+    k_softmax_bwd<<<blocks_of(m), 256, 0, s>>>(wk, dwk, m, kTaps, dzk);
+    if ((st = launch_status("wnet: K encoder backward")) != FV_OK) return st;
+    // H_3 has no decoder predictor: ke3 is its first contribution
+    st = predict_backward(n, tp, ws, kKe0 + l, ws + p.t[kHidden[l]], G(kHidden[l]), l < 3, dzk,
+                          kTaps, m, s);
+    if (st != FV_OK) return st;
+    d = dnext;
+  }
+  // d is the gradient of O_d: the head hd (64 -> 3) on d0b
+  st = predict_backward(n, tp, ws, kHead, ws + p.t[T_D0B], G(T_D0B), 1, d, 3, px(0), s);
+  if (st != FV_OK) return st;
+  // ---- D, last conv first
+  float* tmp = (float*)(ws + tp.tmp);
+  uint8_t* dz = ws + tp.dz;
+  float* part = (float*)(ws + tp.part);
+  float* part2 = (float*)(ws + tp.part2);
+  for (int l = kConv - 1; l >= 0; --l) {
+    const Layer& L = kL[l];
+    const int hh = height >> L.level, ww = width >> L.level;
+    const int64_t m = px(L.level);
+    const int ci = L.c0 + L.c1;
+    net::launch_relu_mask(G(kIO[l][2]), ws + p.t[kIO[l][2]], dz, m * L.co / 8, s);
+    ConvArgs in{};
+    in.src0 = ws + p.t[kIO[l][0]];
+    in.src1 = kIO[l][1] >= 0 ? ws + p.t[kIO[l][1]] : nullptr;
+    in.c0 = L.c0;
+    in.c1 = L.c1;
+    in.up0 = L.up0;
+    in.n = views;
+    in.h = hh;
+    in.w = ww;
+    if (l == 0) {
+      // the packed input has 8 channels; the layer's parameters cover 5
+      float* g0 = (float*)(ws + tp.w0);
+      if ((st = net::conv_wgrad(in, dz, ci, L.co, tp.chunks[l], part, part2, g0, s)) != FV_OK)
+        return st;
+      float* gdst = n->grad + param_offset(kL, 0);
+      st = hip_status(hipMemcpy2DAsync(gdst, L.ci * 9 * sizeof(float), g0, ci * 9 * sizeof(float),
+                                       L.ci * 9 * sizeof(float), L.co, hipMemcpyDeviceToDevice,
+                                       s), "wnet: e0a gradient");
+      if (st == FV_OK)
+        st = hip_status(hipMemcpyAsync(gdst + (int64_t)L.co * L.ci * 9,
+                                       g0 + (int64_t)L.co * ci * 9, L.co * sizeof(float),
+                                       hipMemcpyDeviceToDevice, s), "wnet: e0a bias gradient");
+      return st;
+    }
+    st = net::conv_wgrad(in, dz, ci, L.co, tp.chunks[l], part, part2,
+                         n->grad + param_offset(kL, l), s);
+    if (st != FV_OK) return st;
+    // input gradient: conv with the transposed weights, FP32 output
+    ConvArgs a{};
+    a.src0 = dz;
+    a.c0 = L.co;
+    a.cip = net::cip_of(L.co);
+    a.n = views;
+    a.h = hh;
+    a.w = ww;
+    a.wsw = (const uint8_t*)n->w_bf16t[l];
+    a.kc = net::kchunks_of(L.co);
+    a.co = ci;
+    a.out_fp32 = 1;
+    a.out_ch = ci;
+    const bool concat = kIO[l][1] >= 0;
+    uint8_t* obase = (uint8_t*)(concat ? tmp : G(kIO[l][0]));
+    // in groups of images whose FP32 output stays below the conv's 2 GiB
+    // buffer range (the conv works image by image)
+    const int64_t img_out = (int64_t)hh * ww * ci * 4, img_in = (int64_t)hh * ww * L.co * 2;
+    const int grp = (int)std::max<int64_t>(
+        1, std::min<int64_t>(views, ((((int64_t)1) << 31) - 64 - 1) / img_out));
+    for (int b0 = 0; b0 < views; b0 += grp) {
+      a.n = std::min(grp, views - b0);
+      a.src0 = dz + b0 * img_in;
+      a.out = obase + b0 * img_out;
+      if ((st = net::launch_conv<BF16>(a, net::nblocks_of(ci), s)) != FV_OK) return st;
+    }
+    if (concat) {
+      // the upsampled source (e3b, d2b, d1b) is also one of K's inputs,
+      // whose gradient K has already written: add to it
+      net::launch_upsample_bwd(tmp, ci, L.c0, views, hh / 2, ww / 2, G(kIO[l][0]), 1, s);
+      net::launch_split_skip(tmp, ci, L.c0, L.c1, m, G(kIO[l][1]), s);
+    }
+    // a pooled input's gradient flows back to the pooled tensor's source
+    int src = -1;
+    if (kIO[l][0] == T_P0) src = T_E0B;
+    if (kIO[l][0] == T_P1) src = T_E1B;
+    if (kIO[l][0] == T_P2) src = T_E2B;
+    if (src >= 0) net::launch_pool_bwd_add(G(kIO[l][0]), views, hh * 2, ww * 2, L.c0, G(src), s);
+    if ((st = launch_status("wnet: D backward")) != FV_OK) return st;
+  }
+  return st;
 }
 
 }  // namespace
@@ -459,6 +948,9 @@ fv_status fv_wnet_create(const float* host_params, size_t n_params, fv_wnet** ou
                 n_params, (long long)P0, (long long)P1);
   fv_wnet* n = new fv_wnet();
   std::memset(n->w_bf16, 0, sizeof n->w_bf16);
+  std::memset(n->w_bf16t, 0, sizeof n->w_bf16t);
+  n->grad = n->adam_m = n->adam_v = nullptr;
+  n->step = 0;
   n->recurrent = (int64_t)n_params == P1;
   n->L = n->recurrent ? kLR : kL;
   n->master = nullptr;
@@ -471,15 +963,25 @@ fv_status fv_wnet_create(const float* host_params, size_t n_params, fv_wnet** ou
   for (int l = 0; ok && l < kConv; ++l)
     ok = hipMalloc(&n->w_bf16[l], net::swizzled_elems(n->L[l].ci, n->L[l].co) * 2) ==
          hipSuccess;
+  if (!n->recurrent) {
+    ok = ok && hipMalloc(&n->grad, P * sizeof(float)) == hipSuccess &&
+         hipMalloc(&n->adam_m, P * sizeof(float)) == hipSuccess &&
+         hipMalloc(&n->adam_v, P * sizeof(float)) == hipSuccess;
+    for (int l = 1; ok && l < kConv; ++l)
+      ok = hipMalloc(&n->w_bf16t[l], net::swizzled_elems(n->L[l].co, n->L[l].ci) * 2) ==
+           hipSuccess;
+    if (ok)
+      ok = hipMemset(n->adam_m, 0, P * sizeof(float)) == hipSuccess &&
+           hipMemset(n->adam_v, 0, P * sizeof(float)) == hipSuccess &&
+           hipMemset(n->grad, 0, P * sizeof(float)) == hipSuccess;
+  }
   if (!ok) {
     fv_wnet_destroy(n);
     return fail(FV_ERR_NOMEM, "fv_wnet_create: allocation");
   }
   fv_status st = hip_status(hipMemcpy(n->master, host_params, P * sizeof(float),
                                       hipMemcpyHostToDevice), "fv_wnet_create: upload");
-  for (int l = 0; st == FV_OK && l < kConv; ++l)
-    st = net::swizzle_bf16(n->master + param_offset(n->L, l), n->L[l].ci, n->L[l].co, 0,
-                           n->w_bf16[l], nullptr);
+  if (st == FV_OK) st = refresh_bf16(n, nullptr);
   if (st == FV_OK) st = hip_status(hipDeviceSynchronize(), "fv_wnet_create: sync");
   if (st != FV_OK) {
     fv_wnet_destroy(n);
@@ -493,7 +995,13 @@ fv_status fv_wnet_destroy(fv_wnet* n) {
   clear_error();
   if (!n) return FV_OK;
   (void)hipFree(n->master);
-  for (int l = 0; l < kConv; ++l) (void)hipFree(n->w_bf16[l]);
+  (void)hipFree(n->grad);
+  (void)hipFree(n->adam_m);
+  (void)hipFree(n->adam_v);
+  for (int l = 0; l < kConv; ++l) {
+    (void)hipFree(n->w_bf16[l]);
+    (void)hipFree(n->w_bf16t[l]);
+  }
   delete n;
   return FV_OK;
 }
@@ -553,6 +1061,117 @@ fv_status fv_wnet_reconstruct_recurrent(const fv_wnet* n, const float* frame_rgb
   return reconstruct(n, frame_rgba, mask, frame_depth, state, state_bytes, reset, views, width,
                      height, out_rgb, out_direct, workspace, ws_bytes, stream,
                      "fv_wnet_reconstruct_recurrent");
+}
+
+}  // extern "C"
+
+extern "C" {
+
+fv_status fv_wnet_train_workspace(const fv_wnet* n, int batch, int width, int height,
+                                  size_t* bytes) {
+  clear_error();
+  if (!n || !bytes) return fail(FV_ERR_INVALID_ARG, "fv_wnet_train_workspace: null pointer");
+  if (n->recurrent)
+    return fail(FV_ERR_UNSUPPORTED, "fv_wnet_train_workspace: plain W-Net only");
+  fv_status st = net::check_frame(batch, width, height, "fv_wnet_train_workspace");
+  if (st != FV_OK) return st;
+  *bytes = make_tplan(batch, height, width).bytes;
+  return FV_OK;
+}
+
+fv_status fv_wnet_forward_train(fv_wnet* n, const float* frame_rgba, const uint8_t* mask,
+                                const float* frame_depth, int batch, int width, int height,
+                                float* out_rgb, void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  TPlan tp;
+  fv_status st = train_check(n, batch, width, height, workspace, ws_bytes, &tp,
+                             "fv_wnet_forward_train");
+  if (st != FV_OK) return st;
+  const KKeep k = keep_of(tp, (uint8_t*)workspace);
+  return reconstruct(n, frame_rgba, mask, frame_depth, nullptr, 0, 0, batch, width, height,
+                     out_rgb, nullptr, workspace, ws_bytes, stream, "fv_wnet_forward_train", &k);
+}
+
+fv_status fv_wnet_backward(fv_wnet* n, const float* dloss_dout, int batch, int width,
+                           int height, float* grad_out, void* workspace, size_t ws_bytes,
+                           void* stream) {
+  clear_error();
+  TPlan tp;
+  fv_status st = train_check(n, batch, width, height, workspace, ws_bytes, &tp,
+                             "fv_wnet_backward");
+  if (st != FV_OK) return st;
+  if (!dloss_dout) return fail(FV_ERR_INVALID_ARG, "fv_wnet_backward: null dloss_dout");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = backward(n, dloss_dout, batch, width, height, workspace, s)) != FV_OK) return st;
+  if (grad_out)
+    st = hip_status(hipMemcpyAsync(grad_out, n->grad, param_offset(kL, kLayersAll) * 4,
+                                   hipMemcpyDeviceToDevice, s), "fv_wnet_backward: copy");
+  return st;
+}
+
+fv_status fv_wnet_adam(fv_wnet* n, float lr, float beta1, float beta2, float eps, void* stream) {
+  clear_error();
+  if (!n) return fail(FV_ERR_INVALID_ARG, "fv_wnet_adam: null net");
+  if (n->recurrent) return fail(FV_ERR_UNSUPPORTED, "fv_wnet_adam: plain W-Net only");
+  if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
+      !(eps > 0.f))
+    return fail(FV_ERR_INVALID_ARG, "fv_wnet_adam: bad hyper-parameters");
+  hipStream_t s = (hipStream_t)stream;
+  n->step += 1;
+  fv_status st = net::adam_run(n->master, n->adam_m, n->adam_v, n->grad,
+                               param_offset(kL, kLayersAll), lr, beta1, beta2, eps, n->step, s);
+  if (st == FV_OK) st = refresh_bf16(n, s);
+  return st;
+}
+
+fv_status fv_wnet_train_step(fv_wnet* n, const float* frame_rgba, const uint8_t* mask,
+                             const float* frame_depth, const float* target_rgba, int batch,
+                             int width, int height, float lr, float* loss3, void* workspace,
+                             size_t ws_bytes, void* stream) {
+  clear_error();
+  TPlan tp;
+  fv_status st = train_check(n, batch, width, height, workspace, ws_bytes, &tp,
+                             "fv_wnet_train_step");
+  if (st != FV_OK) return st;
+  if (!target_rgba || !loss3) return fail(FV_ERR_INVALID_ARG, "fv_wnet_train_step: null pointer");
+  uint8_t* ws = (uint8_t*)workspace;
+  hipStream_t s = (hipStream_t)stream;
+  float* out = (float*)(ws + tp.out);
+  float* dout = (float*)(ws + tp.dout);
+  if ((st = fv_wnet_forward_train(n, frame_rgba, mask, frame_depth, batch, width, height, out,
+                                  workspace, ws_bytes, stream)) != FV_OK)
+    return st;
+  if ((st = net::loss_run(out, target_rgba, batch, height, width, loss3, dout,
+                          (float*)(ws + tp.tgt), ws + tp.ssim, (double*)(ws + tp.red), s)) !=
+      FV_OK)
+    return st;
+  if ((st = backward(n, dout, batch, width, height, workspace, s)) != FV_OK) return st;
+  return fv_wnet_adam(n, lr, 0.9f, 0.999f, 1e-8f, stream);
+}
+
+fv_status fv_wnet_get_params(const fv_wnet* n, float* host_out, size_t n_params) {
+  clear_error();
+  if (!n || !host_out) return fail(FV_ERR_INVALID_ARG, "fv_wnet_get_params: null pointer");
+  const int64_t P = param_offset(n->L, kLayersAll);
+  if ((int64_t)n_params != P)
+    return fail(FV_ERR_INVALID_ARG, "fv_wnet_get_params: %zu parameters, the network has %lld",
+                n_params, (long long)P);
+  return hip_status(hipMemcpy(host_out, n->master, P * sizeof(float), hipMemcpyDeviceToHost),
+                    "fv_wnet_get_params");
+}
+
+fv_status fv_wnet_set_params(fv_wnet* n, const float* host_params, size_t n_params) {
+  clear_error();
+  if (!n || !host_params) return fail(FV_ERR_INVALID_ARG, "fv_wnet_set_params: null pointer");
+  const int64_t P = param_offset(n->L, kLayersAll);
+  if ((int64_t)n_params != P)
+    return fail(FV_ERR_INVALID_ARG, "fv_wnet_set_params: %zu parameters, the network has %lld",
+                n_params, (long long)P);
+  fv_status st = hip_status(hipMemcpy(n->master, host_params, P * sizeof(float),
+                                      hipMemcpyHostToDevice), "fv_wnet_set_params");
+  if (st == FV_OK) st = refresh_bf16(n, nullptr);
+  if (st == FV_OK) st = hip_status(hipDeviceSynchronize(), "fv_wnet_set_params: sync");
+  return st;
 }
 
 }  // extern "C"

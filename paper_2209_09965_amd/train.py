@@ -221,6 +221,9 @@ def main():
                     help="train the recurrent form (previous frame's O_d fed back)")
     ap.add_argument("--noise", choices=["hash", "blue"], default="hash",
                     help="sample-map noise: seeded hash or a 64-tile blue-noise stack")
+    ap.add_argument("--wnet", action="store_true",
+                    help="train the two-stage W-Net (networks D and K) instead of the "
+                         "single-stage network (single frames, BF16)")
     args = ap.parse_args()
     logf = open(args.log, "a") if args.log else None
 
@@ -249,13 +252,18 @@ def main():
     te = np.flatnonzero(pair_role == "test")
     log("pairs: %d train / %d val / %d test" % (tr.size, va.size, te.size))
 
-    if args.init:
-        theta = np.load(args.init)
-        if args.recurrent and theta.size == b.Net.PARAMS:
-            theta = widen_recurrent(theta)
+    if args.wnet:
+        assert not temporal and not args.recurrent, "the W-Net trains on single frames"
+        theta = np.load(args.init) if args.init else synthetic.wnet_init(args.seed)
+        net = b.WNet(theta)
     else:
-        theta = synthetic.net_init(args.seed, recurrent=args.recurrent)
-    net = b.Net(theta)
+        if args.init:
+            theta = np.load(args.init)
+            if args.recurrent and theta.size == b.Net.PARAMS:
+                theta = widen_recurrent(theta)
+        else:
+            theta = synthetic.net_init(args.seed, recurrent=args.recurrent)
+        net = b.Net(theta)
     assert net.recurrent == args.recurrent
     B = args.batch
     if temporal:
@@ -366,6 +374,8 @@ def main():
                history=hist,
                pairs=dict(train=int(tr.size), val=int(va.size), test=int(te.size)))
     try:
+        if args.wnet:
+            raise RuntimeError("the W-Net runs in BF16 only")
         # FP8 after calibration on training frames
         cal = torch.from_numpy(tr[:1]).to(dev)
         cw = torch.empty(net.workspace_bytes(1, W, H, "bf16"), dtype=torch.uint8, device=dev)

@@ -1,0 +1,117 @@
+"""Training of the two-stage W-Net on the GPU against the FP64 oracle
+(oracle/wnet.py, whose backward pass is pinned by finite differences): the
+full parameter gradient against the oracle's exact backward of the
+BF16-emulated forward (D's 3x3 weights and stored activations rounded to
+BF16), per layer; determinism; that Adam steps reduce the loss; parameter
+round trip and the plain-form-only refusal."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synthetic
+from oracle import net as N
+from oracle import wnet as WN
+from tests.test_gpu_wnet import _bf16_d_weights, _frame, _theta, _theta_rec
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).reshape(-1).to(dev)
+
+
+def _grads(theta, rgba, mask, depth, dloss, n, H, W, dev):
+    from paper_2209_09965_amd import binding as b
+    net = b.WNet(theta)
+    ws = torch.empty(net.train_workspace_bytes(n, W, H), dtype=torch.uint8, device=dev)
+    out = torch.empty(n * H * W * 3, device=dev)
+    net.forward_train(_t(rgba, dev), _t(mask, dev), _t(depth, dev), n, W, H, out, ws)
+    g = torch.zeros(WN.n_params(), device=dev)
+    net.backward(_t(dloss, dev), n, W, H, ws, grad_out=g)
+    torch.cuda.synchronize()
+    net.close()
+    return out.cpu().numpy(), g.cpu().numpy()
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("n,H,W", [(1, 16, 16), (2, 32, 48)])
+def test_wnet_backward_matches_oracle(n, H, W, dev):
+    rng = np.random.default_rng(11)
+    theta = _theta(12)
+    rgba, mask, depth = _frame(rng, n, H, W, density=0.3)
+    dloss = rng.normal(0, 1.0, (n, H, W, 3)).astype(np.float32)
+    out, g = _grads(theta, rgba, mask, depth, dloss, n, H, W, dev)
+    x = np.ascontiguousarray(oracle.pack_input(rgba, mask, depth).reshape(n, H, W, 5)
+                             .transpose(0, 3, 1, 2))
+    thq = _bf16_d_weights(theta)
+    want, _, cache = WN.forward(thq, x, keep=True, act_round=N.bf16_round)
+    gw = WN.backward(thq, cache, dloss.astype(np.float64).transpose(0, 3, 1, 2))
+    assert np.abs(out.reshape(n, H, W, 3).transpose(0, 3, 1, 2) - want).max() < 2e-2
+    off = 0
+    worst_d = worst_k = 0.0
+    for name, ci, co, k in WN.layers():
+        nw = co * ci * k * k + co
+        a, r = g[off:off + nw], gw[off:off + nw]
+        rel = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
+        print("%-4s grad rel L2 err %.5f  |g| %.3g" % (name, rel, np.linalg.norm(r)), flush=True)
+        if k == 3:
+            worst_d = max(worst_d, rel)
+        else:
+            worst_k = max(worst_k, rel)
+        off += nw
+    # D: BF16 output gradients on the MFMA input-gradient convs, as the
+    # single-stage network's training (there <= 1 % at 16 x 16, 10 % where
+    # BF16 rounding flips of the forward move the oracle itself; measured
+    # 0.35 % and 4.1 %); K and the O_d head run in FP32 on D's BF16 states,
+    # which a few flips in D's 64-96-channel layers already reach at 16 x 16
+    # (measured 0.11 % and 0.65 %)
+    small = H * W <= 256
+    assert worst_d < (0.01 if small else 0.10)
+    assert worst_k < (0.005 if small else 0.10)
+    g2 = _grads(theta, rgba, mask, depth, dloss, n, H, W, dev)[1]
+    assert np.array_equal(g, g2), "backward is not deterministic"
+
+
+@pytest.mark.timeout(300)
+def test_wnet_adam_steps_reduce_loss(dev):
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(3)
+    n, H, W = 4, 32, 32
+    rgba, mask, depth = _frame(rng, n, H, W, density=0.3)
+    tgt = rgba.copy()
+    net = b.WNet(synthetic.wnet_init(5))
+    ws = torch.empty(net.train_workspace_bytes(n, W, H), dtype=torch.uint8, device=dev)
+    loss3 = torch.zeros(3, device=dev)
+    losses = []
+    fr, m, d, t = _t(rgba, dev), _t(mask, dev), _t(depth, dev), _t(tgt, dev)
+    for _ in range(30):
+        net.train_step(fr, m, d, t, n, W, H, 1e-3, loss3, ws)
+        losses.append(float(loss3[0].item()))
+    print("losses", ["%.4f" % v for v in losses[::5]], "%.4f" % losses[-1])
+    assert all(np.isfinite(losses))
+    # the W-Net (near-identity kernels at the start) falls more slowly than
+    # the single-stage network at this rate: measured 0.944 -> 0.868
+    assert losses[-1] < 0.95 * losses[0]
+    assert np.mean(losses[-5:]) < np.mean(losses[:5])
+    p = net.get_params()
+    assert p.shape == (WN.n_params(),) and np.isfinite(p).all()
+    net.close()
+
+
+def test_wnet_params_round_trip_and_plain_only(dev):
+    from paper_2209_09965_amd import binding as b
+    theta = _theta(21)
+    net = b.WNet(theta)
+    assert np.array_equal(net.get_params(), theta)
+    th2 = _theta(22)
+    net.set_params(th2)
+    assert np.array_equal(net.get_params(), th2)
+    with pytest.raises(b.FvError):
+        net.set_params(th2[:-1])
+    net.close()
+    rec = b.WNet(_theta_rec(23))
+    with pytest.raises(b.FvError) as e:
+        rec.train_workspace_bytes(1, 16, 16)
+    assert e.value.status == b.FV_ERR_UNSUPPORTED
+    rec.close()
