@@ -221,6 +221,8 @@ def main():
                     help="train the recurrent form (previous frame's O_d fed back)")
     ap.add_argument("--noise", choices=["hash", "blue"], default="hash",
                     help="sample-map noise: seeded hash or a 64-tile blue-noise stack")
+    ap.add_argument("--warmup-epochs", type=float, default=0.0,
+                    help="linear learning-rate warm-up over this many epochs")
     ap.add_argument("--wnet", action="store_true",
                     help="train the two-stage W-Net (networks D and K) instead of the "
                          "single-stage network (single frames, BF16)")
@@ -314,6 +316,9 @@ def main():
                 fr = augment_colours(fr, arng, group=2 if temporal else 1)
             lr = args.lr if args.schedule == "constant" else cosine_lr(
                 args.lr, args.lr_min, max(step / total_steps, (time.time() - t_train) / budget))
+            warm = args.warmup_epochs * (tr.size // per0)
+            if step < warm:
+                lr *= (step + 1) / warm
             if not temporal:
                 net.train_step(fr, m, d, fr, B, W, H, lr, loss3, ws)
             elif args.recurrent:

@@ -162,3 +162,37 @@ def test_network_gain_full_hd_benchmark_frame(dev):
     scores = [_frame_scores(b, net, "fp8", vol, tf, cam, mp, W, H, fp, dev, calibrate=True)]
     net.close()
     _assert_gain(scores, "1920x1080 fp8", False)
+
+
+@pytest.mark.timeout(300)
+def test_trained_wnet_gain_on_heldout_volumes(dev):
+    """The trained two-stage W-Net (weights/wnet.npy, BF16) on the same
+    held-out frames: its output (K's kernels applied in sequence to D's
+    direct prediction) beats pull-push, the sparse frame and D's direct
+    prediction alone."""
+    from paper_2209_09965_amd import binding as b
+    net = b.WNet(np.load(os.path.join(WEIGHTS, "wnet.npy")))
+    scores = []
+    for kind, vol, tf, cam, mp, W, H, fp in _heldout_cases():
+        frame, mask, depth, cnt = _sparse_frame(b, vol, tf, cam, mp, W, H, fp, dev)
+        npx = W * H
+        pp = torch.empty(npx * 3, dtype=torch.float32, device=dev)
+        b.reconstruct_pullpush(frame, mask, 1, W, H, pp)
+        out = torch.empty(npx * 3, dtype=torch.float32, device=dev)
+        od = torch.empty(npx * 3, dtype=torch.float32, device=dev)
+        net.reconstruct(frame, mask, depth, 1, W, H, out, od)
+        torch.cuda.synchronize()
+        ref = oracle.march(vol, tf, [cam], W, H, mp)["rgba"][:, :3]
+        sparse = frame.cpu().numpy().reshape(-1, 4)[:, :3]
+        s = [_psnr(sparse, ref), _psnr(pp.cpu().numpy(), ref), _psnr(od.cpu().numpy(), ref),
+             _psnr(out.cpu().numpy(), ref)]
+        print("  W-Net %s: sparse %.2f | pull-push %.2f | D direct %.2f | W-Net %.2f dB"
+              % (kind, *s), flush=True)
+        scores.append(s)
+    net.close()
+    s = np.mean(np.asarray(scores), axis=0)
+    print("W-Net held-out mean: sparse %.2f | pull-push %.2f | direct %.2f | output %.2f dB"
+          % tuple(s), flush=True)
+    sparse, pullpush, direct, hybrid = s
+    assert hybrid >= 30.0
+    assert hybrid > pullpush > sparse and hybrid > direct
