@@ -49,6 +49,9 @@ struct BF16 {
     const __bf16 h = (__bf16)v;
     return (uint32_t)__builtin_bit_cast(uint16_t, h);
   }
+  static __device__ __forceinline__ void store8_inrange(uint8_t* p, const float v[8]) {
+    store8(p, v);
+  }
   static __device__ __forceinline__ void store8(uint8_t* p, const float v[8]) {
     uint4 u;
     u.x = enc_bits(v[0]) | (enc_bits(v[1]) << 16);
@@ -125,16 +128,30 @@ struct FP8 {
   static __device__ __forceinline__ uint8_t enc(float v) {
     return (uint8_t)(__builtin_amdgcn_cvt_pk_fp8_f32(sat(v), 0.0f, 0, false) & 0xff);
   }
+  // two bytes per conversion (bytes 0, 1 of the selected 16-bit word)
   static __device__ __forceinline__ void load8(const uint8_t* p, float v[8]) {
     const uint2 u = *(const uint2*)p;
-    v[0] = __builtin_amdgcn_cvt_f32_fp8((int)u.x, 0);
-    v[1] = __builtin_amdgcn_cvt_f32_fp8((int)u.x, 1);
-    v[2] = __builtin_amdgcn_cvt_f32_fp8((int)u.x, 2);
-    v[3] = __builtin_amdgcn_cvt_f32_fp8((int)u.x, 3);
-    v[4] = __builtin_amdgcn_cvt_f32_fp8((int)u.y, 0);
-    v[5] = __builtin_amdgcn_cvt_f32_fp8((int)u.y, 1);
-    v[6] = __builtin_amdgcn_cvt_f32_fp8((int)u.y, 2);
-    v[7] = __builtin_amdgcn_cvt_f32_fp8((int)u.y, 3);
+    const auto a = __builtin_amdgcn_cvt_pk_f32_fp8((int)u.x, false);
+    const auto b = __builtin_amdgcn_cvt_pk_f32_fp8((int)u.x, true);
+    const auto c = __builtin_amdgcn_cvt_pk_f32_fp8((int)u.y, false);
+    const auto d = __builtin_amdgcn_cvt_pk_f32_fp8((int)u.y, true);
+    v[0] = a[0];
+    v[1] = a[1];
+    v[2] = b[0];
+    v[3] = b[1];
+    v[4] = c[0];
+    v[5] = c[1];
+    v[6] = d[0];
+    v[7] = d[1];
+  }
+  // store8 for values known to lie in the E4M3 range (no clamp)
+  static __device__ __forceinline__ void store8_inrange(uint8_t* p, const float v[8]) {
+    int lo = 0, hi = 0;
+    lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], lo, false);
+    lo = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], lo, true);
+    hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[4], v[5], hi, false);
+    hi = __builtin_amdgcn_cvt_pk_fp8_f32(v[6], v[7], hi, true);
+    *(uint2*)p = make_uint2((uint32_t)lo, (uint32_t)hi);
   }
   static __device__ __forceinline__ void store8(uint8_t* p, const float v[8]) {
     int lo = 0, hi = 0;
@@ -719,7 +736,8 @@ __global__ void __launch_bounds__(256)
           float o[8];
 #pragma unroll
           for (int k = 0; k < 8; ++k) o[k] = fmaf(fy, bot[k] - top[k], top[k]);
-          E::store8(dst, o);
+          // a convex blend of stored values stays in the format's range
+          E::store8_inrange(dst, o);
         }
       }
     }
