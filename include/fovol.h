@@ -564,14 +564,14 @@ fv_status fv_reconstruct_pullpush(const float* frame_rgba, const uint8_t* mask, 
                                   size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
- * 4c. The foveated frame in one call, with the dense march as judge and
- *     fallback
+ * 4c. The foveated frame in one call, with the dense march as quality
+ *     reference and fallback
  * ------------------------------------------------------------------------
  * The paper's pipeline (Sec. 3, Fig. 2): sample map and compaction
  * (fv_fovea_mask), sparse march with back-projection (fv_raymarch_sparse),
  * full-frame reconstruction (fv_reconstruct with the policy's precision).
  * The conventional renderer it replaces, the dense march, stays available
- * as the judge of the reconstruction and as its fallback:
+ * as the quality reference of the reconstruction and as its fallback:
  *   - frame f is a check frame when check_every > 0 and f mod check_every
  *     == 0 (f counts the renderer's frames from 0); a check frame renders
  *     the foveated frame and the dense frame and scores the reconstruction

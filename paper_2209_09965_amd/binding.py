@@ -826,7 +826,7 @@ class Net:
 # --------------------------------------------------------- foveated renderer
 
 class Renderer:
-    """The foveated frame in one call with the dense march as judge and
+    """The foveated frame in one call with the dense march as quality reference and
     fallback (fv_render_frame): every check_every-th frame is scored against
     the dense frame, and below min_psnr_db the dense frame replaces it until
     a later check passes."""

@@ -1,5 +1,5 @@
-// The foveated frame as one call, with the dense march kept as the judge and
-// the fallback of the reconstruction (paper Sec. 3, the pipeline of
+// The foveated frame as one call, with the dense march kept as the quality
+// reference and the fallback of the reconstruction (paper Sec. 3, the pipeline of
 // Fig. 2: sample map -> compaction -> sparse march -> back-projection ->
 // reconstruction; the conventional renderer it replaces is the dense march).
 //

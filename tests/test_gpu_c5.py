@@ -76,7 +76,7 @@ def test_c5_stereo_sparse_dense_and_oracle(c5, dev):
     assert np.array_equal(idx, io)
     per_view = np.bincount(idx // (W * H), minlength=views)
     print("sampled rays per view:", per_view.tolist(), flush=True)
-    assert np.all(np.abs(per_view - 571077) < 5000)  # the survey's expectation, 12.24 %
+    assert np.all(np.abs(per_view - 571077) < 5000)  # the expected count for this fovea: 12.24 % of a view
     # sparse == dense at every listed pixel, nothing else written
     fr = frame.cpu().numpy().reshape(-1, 4)
     fd = fdepth.cpu().numpy()

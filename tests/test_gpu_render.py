@@ -1,4 +1,4 @@
-"""The foveated renderer with the dense march as judge and fallback
+"""The foveated renderer with the dense march as quality reference and fallback
 (fv_render_frame), through the C ABI: with trained weights its output is the
 foveated pipeline's, bit for bit, and its PSNR the one the host computes from
 the same frames; with corrupted weights (or a threshold above what the
