@@ -713,8 +713,9 @@ fv_status fv_wnet_reconstruct_recurrent(const fv_wnet* n, const float* frame_rgb
  * step on the FP32 master (then rebuilds D's BF16 copies).  Reductions use
  * fixed orders, so a step is deterministic.  Frames at least 16 x 16,
  * multiples of 8.  Arguments and layouts as the fv_net training calls
- * (grad_out: dev float [FV_WNET_PARAMS] or NULL).  Errors: those of the
- * fv_net training calls, FV_ERR_UNSUPPORTED for a recurrent handle.
+ * (grad_out: dev float [the handle's parameter count] or NULL).  Errors:
+ * those of the fv_net training calls; the state-less calls refuse a
+ * recurrent handle (it has its own, below).
  * fv_wnet_get_params / fv_wnet_set_params copy the FP32 master to / from
  * the host (set rebuilds the BF16 copies and synchronises). */
 fv_status fv_wnet_train_workspace(const fv_wnet* n, int batch, int width, int height,
@@ -730,6 +731,31 @@ fv_status fv_wnet_train_step(fv_wnet* n, const float* frame_rgba, const uint8_t*
                              const float* frame_depth, const float* target_rgba, int batch,
                              int width, int height, float lr, float* loss3, void* workspace,
                              size_t ws_bytes, void* stream);
+/* The recurrent form trains on frames with their fed-back state given as
+ * an input (the state is carried over one step, detached, as the
+ * single-stage network's recurrent training): state has the layout of
+ * fv_wnet_state_layout for `batch` views, entry b the state frame b reads;
+ * it is only read, and must be passed unchanged to the backward call.
+ * fv_wnet_loss (fv_wnet_loss_temporal) is fv_net_loss (fv_net_loss_temporal)
+ * on the W-Net's training workspace (either form).  Errors: those above; a state for a plain handle or none for a
+ * recurrent one. */
+fv_status fv_wnet_forward_train_recurrent(fv_wnet* n, const float* frame_rgba,
+                                          const uint8_t* mask, const float* frame_depth,
+                                          const void* state, size_t state_bytes, int batch,
+                                          int width, int height, float* out_rgb,
+                                          void* workspace, size_t ws_bytes, void* stream);
+fv_status fv_wnet_backward_recurrent(fv_wnet* n, const float* dloss_dout, const void* state,
+                                     size_t state_bytes, int batch, int width, int height,
+                                     float* grad_out, void* workspace, size_t ws_bytes,
+                                     void* stream);
+fv_status fv_wnet_loss(const fv_wnet* n, const float* out_rgb, const float* target_rgba,
+                       int batch, int width, int height, float* loss3, float* dloss_dout,
+                       void* workspace, size_t ws_bytes, void* stream);
+/* fv_net_loss_temporal on the W-Net's training workspace. */
+fv_status fv_wnet_loss_temporal(const fv_wnet* n, const float* out_rgb,
+                                const float* target_rgba, int batch, int width, int height,
+                                float weight, float* loss, float* dloss_dout, void* workspace,
+                                size_t ws_bytes, void* stream);
 fv_status fv_wnet_get_params(const fv_wnet* n, float* host_out, size_t n_params);
 fv_status fv_wnet_set_params(fv_wnet* n, const float* host_params, size_t n_params);
 

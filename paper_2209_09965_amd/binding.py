@@ -138,6 +138,12 @@ _SIGS = {
     "fv_wnet_train_step": (_i, [_vp, _vp, _vp, _vp, _vp, _i, _i, _i, ctypes.c_float, _vp, _vp,
                                 _sz, _vp]),
     "fv_wnet_get_params": (_i, [_vp, _vp, _sz]),
+    "fv_wnet_forward_train_recurrent": (_i, [_vp, _vp, _vp, _vp, _vp, _sz, _i, _i, _i, _vp, _vp,
+                                             _sz, _vp]),
+    "fv_wnet_backward_recurrent": (_i, [_vp, _vp, _vp, _sz, _i, _i, _i, _vp, _vp, _sz, _vp]),
+    "fv_wnet_loss": (_i, [_vp, _vp, _vp, _i, _i, _i, _vp, _vp, _vp, _sz, _vp]),
+    "fv_wnet_loss_temporal": (_i, [_vp, _vp, _vp, _i, _i, _i, ctypes.c_float, _vp, _vp, _vp,
+                                   _sz, _vp]),
     "fv_wnet_set_params": (_i, [_vp, _vp, _sz]),
     "fv_reconstruct_tensor": (_i, [_i, _i, _i, _i, _i, ctypes.POINTER(_sz),
                                    ctypes.POINTER(_i), ctypes.POINTER(_i)]),
@@ -557,6 +563,43 @@ class WNet:
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         check(_lib.fv_wnet_adam(self.handle, lr, beta1, beta2, eps, _stream(stream)))
+
+    def forward_train_recurrent(self, frame_rgba, mask, frame_depth, state, batch, width,
+                                height, out_rgb, workspace, stream=None):
+        fa = self._frame_args(frame_rgba, mask, frame_depth, batch, width, height)
+        wp, wb = _ws(workspace)
+        sp, sb = _ws(state)
+        check(_lib.fv_wnet_forward_train_recurrent(
+            self.handle, *fa, sp, sb, batch, width, height,
+            _dev(out_rgb, "out_rgb", F32, batch * width * height * 3), wp, wb, _stream(stream)))
+
+    def backward_recurrent(self, dloss, state, batch, width, height, workspace, grad_out=None,
+                           stream=None):
+        wp, wb = _ws(workspace)
+        sp, sb = _ws(state)
+        check(_lib.fv_wnet_backward_recurrent(
+            self.handle, _dev(dloss, "dloss", F32, batch * width * height * 3), sp, sb, batch,
+            width, height, _dev(grad_out, "grad_out", F32, self.n_params, False), wp, wb,
+            _stream(stream)))
+
+    def loss(self, out_rgb, target_rgba, batch, width, height, loss3, dloss, workspace,
+             stream=None):
+        npx = batch * width * height
+        wp, wb = _ws(workspace)
+        check(_lib.fv_wnet_loss(self.handle, _dev(out_rgb, "out_rgb", F32, npx * 3),
+                                _dev(target_rgba, "target_rgba", F32, npx * 4), batch, width,
+                                height, _dev(loss3, "loss3", F32, 3),
+                                _dev(dloss, "dloss", F32, npx * 3), wp, wb, _stream(stream)))
+
+    def loss_temporal(self, out_rgb, target_rgba, batch, width, height, weight, loss, dloss,
+                      workspace, stream=None):
+        npx = batch * width * height
+        wp, wb = _ws(workspace)
+        check(_lib.fv_wnet_loss_temporal(self.handle, _dev(out_rgb, "out_rgb", F32, npx * 3),
+                                         _dev(target_rgba, "target_rgba", F32, npx * 4), batch,
+                                         width, height, weight, _dev(loss, "loss", F32, 1),
+                                         _dev(dloss, "dloss", F32, npx * 3), wp, wb,
+                                         _stream(stream)))
 
     def train_step(self, frame_rgba, mask, frame_depth, target_rgba, batch, width, height, lr,
                    loss3, workspace, stream=None):

@@ -102,7 +102,10 @@ TrainPlan make_train_plan(int n, int h, int w);
 // their element count, the 8-channel BF16 input packing (the last three the
 // previous O_d, [n h w 3] FP32, or zero when prev is null) and the frame
 // checks of the reconstruction entry points.
-fv_status swizzle_bf16(const float* w, int ci, int co, int transposed, void* out, hipStream_t s);
+// (out_limit: build only the first out_limit output channels of the GEMM,
+// the input channels of a transposed conv whose other gradients are unused)
+fv_status swizzle_bf16(const float* w, int ci, int co, int transposed, void* out, hipStream_t s,
+                       int out_limit = 1 << 30);
 size_t swizzled_elems(int in_ch, int out_ch);
 fv_status pack_input_bf16(const float* frame, const uint8_t* mask, const float* depth,
                           const float* prev, uint8_t* out, int64_t npx, hipStream_t s);
@@ -117,6 +120,10 @@ size_t loss_red_bytes(int n, int h, int w);
 fv_status loss_run(const float* out_rgb, const float* target_rgba, int n, int h, int w,
                    float* loss3, float* dloss_dout, float* tgt, uint8_t* ssim, double* red,
                    hipStream_t s);
+// the temporal finite-difference loss over batch pairs (2i, 2i + 1); its
+// block partial sums fit in loss_red_bytes' region
+fv_status tloss_run(const float* out_rgb, const float* target_rgba, int pairs, int h, int w,
+                    float weight, float* loss, float* dloss_dout, double* red, hipStream_t s);
 void launch_relu_mask(const float* g, const uint8_t* y, uint8_t* dz, int64_t n8, hipStream_t s);
 void launch_upsample_bwd(const float* gup, int ch_stride, int c0, int n, int hl, int wl,
                          float* glow, int acc, hipStream_t s);

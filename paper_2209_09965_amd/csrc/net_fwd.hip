@@ -346,7 +346,7 @@ __global__ void k_swizzle_heads(const float* __restrict__ hd, const float* __res
 // (in/out channels swapped, taps mirrored).
 __global__ void __launch_bounds__(256) k_swizzle_bf16(const float* __restrict__ w, int ci, int co,
                                                       int transposed, int kc, int nb,
-                                                      __bf16* __restrict__ out) {
+                                                      int out_limit, __bf16* __restrict__ out) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t total = (int64_t)kc * nb * 512;
   if (e >= total) return;
@@ -354,7 +354,7 @@ __global__ void __launch_bounds__(256) k_swizzle_bf16(const float* __restrict__ 
   const int nbi = (int)((e >> 9) % nb);
   const int c = (int)(e / (512 * (int64_t)nb));
   // GEMM view: input channels (K side) and output channels (N side)
-  const int in_ch = transposed ? co : ci, out_ch = transposed ? ci : co;
+  const int in_ch = transposed ? co : ci, out_ch = min(transposed ? ci : co, out_limit);
   const int cip = cip_of(in_ch);
   const int kk = c * 32 + 8 * (l >> 4) + j;
   const int tap = kk / cip, kin = kk - tap * cip;
@@ -513,12 +513,14 @@ fv_status launch_conv(const ConvArgs& args, int nb, hipStream_t s) {
 template fv_status launch_conv<BF16>(const ConvArgs&, int, hipStream_t);
 template fv_status launch_conv<FP8>(const ConvArgs&, int, hipStream_t);
 
-fv_status swizzle_bf16(const float* w, int ci, int co, int transposed, void* out, hipStream_t s) {
-  const int in_ch = transposed ? co : ci, out_ch = transposed ? ci : co;
+fv_status swizzle_bf16(const float* w, int ci, int co, int transposed, void* out, hipStream_t s,
+                       int out_limit) {
+  const int in_ch = transposed ? co : ci;
+  const int out_ch = std::min(transposed ? ci : co, out_limit);
   const int kc = kchunks_of(in_ch), nb = nblocks_of(out_ch);
   const int64_t total = (int64_t)kc * nb * 512;
   k_swizzle_bf16<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(w, ci, co, transposed, kc, nb,
-                                                                 (__bf16*)out);
+                                                                 out_ch, (__bf16*)out);
   return launch_status("swizzle");
 }
 

@@ -443,12 +443,16 @@ __global__ void __launch_bounds__(256) k_relu_mask(const float* __restrict__ g,
 
 // Input channels ch..ch+7 of a conv layer at pixel (y, x) of image b, as the
 // forward kernel's patch fill defines them (concat of the bilinearly
-// upsampled source 0, rounded to BF16 as the forward pass stores it, and
-// source 1; zero outside the image), as BF16 bits.  ch is a multiple of 8
-// and so is c0, so a group never straddles the two sources.
+// upsampled source 0, rounded to BF16 as the forward pass stores it, source
+// 1 and source 2; zero outside the image), as BF16 bits.  ch is a multiple
+// of 8 and so are c0 and c0 + c1, so a group never straddles two sources.
 __device__ __forceinline__ uint4 conv_input8(const ConvArgs& a, int b, int y, int x, int ch) {
   const uint4 zero = make_uint4(0u, 0u, 0u, 0u);
-  if (y < 0 || y >= a.h || x < 0 || x >= a.w || ch >= a.c0 + a.c1) return zero;
+  const int c01 = a.c0 + a.c1;
+  if (y < 0 || y >= a.h || x < 0 || x >= a.w || ch >= c01 + (a.src2 ? a.c2 : 0)) return zero;
+  if (ch >= c01)  // the third source (a fed-back state), c2 channels
+    return *(const uint4*)((const uint16_t*)a.src2 +
+                           (((int64_t)b * a.h + y) * a.w + x) * a.c2 + (ch - c01));
   if (ch >= a.c0)
     return *(const uint4*)((const uint16_t*)a.src1 +
                            (((int64_t)b * a.h + y) * a.w + x) * a.c1 + (ch - a.c0));
@@ -697,7 +701,6 @@ __global__ void __launch_bounds__(256) k_adam(float* __restrict__ th, float* __r
 
 static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-fv_status swizzle_bf16(const float* w, int ci, int co, int transposed, void* out, hipStream_t s);
 
 }  // namespace net
 }  // namespace fv
@@ -764,6 +767,16 @@ fv_status loss_run(const float* out_rgb, const float* target_rgba, int n, int h,
                                 dloss_dout, red + nbv);
   k_loss_final<<<1, 256, 0, s>>>(red, (int)nbv, red + nbv, (int)nbl, ssim_scale, l1_scale, loss3);
   return launch_status("loss");
+}
+
+fv_status tloss_run(const float* out_rgb, const float* target_rgba, int pairs, int h, int w,
+                    float weight, float* loss, float* dloss_dout, double* red, hipStream_t s) {
+  const int64_t hw = (int64_t)h * w, cnt = (int64_t)pairs * hw * 3;
+  const unsigned nb = nblk(cnt);
+  k_tloss<<<nb, 256, 0, s>>>(out_rgb, (const float4*)target_rgba, pairs, hw,
+                             (float)((double)weight / (double)cnt), dloss_dout, red);
+  k_tloss_final<<<1, 256, 0, s>>>(red, (int)nb, 1.0 / (double)cnt, loss);
+  return launch_status("temporal loss");
 }
 
 void launch_relu_mask(const float* g, const uint8_t* y, uint8_t* dz, int64_t n8, hipStream_t s) {

@@ -22,6 +22,7 @@
 // blocks write their outputs straight into the state (after the first conv
 // has read the old one), so it costs no copies.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -531,7 +532,7 @@ fv_status refresh_bf16(fv_wnet* n, hipStream_t s) {
                            n->w_bf16[l], s);
     if (st == FV_OK && n->w_bf16t[l])
       st = net::swizzle_bf16(n->master + param_offset(n->L, l), n->L[l].ci, n->L[l].co, 1,
-                             n->w_bf16t[l], s);
+                             n->w_bf16t[l], s, n->L[l].c0 + n->L[l].c1);
   }
   return st;
 }
@@ -575,12 +576,15 @@ fv_status reconstruct(const fv_wnet* n, const float* frame_rgba, const uint8_t* 
   uint8_t* ws = (uint8_t*)workspace;
   uint8_t* sb = (uint8_t*)state;
   const int64_t npx = (int64_t)views * height * width;
-  // D's tensors: the decoder outputs of the recurrent form live in the state
+  // Inference writes the new state over the one it reads (decoder outputs
+  // and O_d go straight into it); a training forward leaves it as its input
+  // and keeps everything in the workspace
+  const bool state_out = rec && !keep;
   auto tensor = [&](int t) -> uint8_t* {
-    if (rec && (t == T_D2B || t == T_D1B || t == T_D0B)) return sb + sp.t[t];
+    if (state_out && (t == T_D2B || t == T_D1B || t == T_D0B)) return sb + sp.t[t];
     return ws + p.t[t];
   };
-  if (rec && reset) {
+  if (state_out && reset) {
     const int64_t n16 = (int64_t)(sp.bytes / 16);
     k_zero<<<blocks_of(n16), 256, 0, s>>>((uint4*)sb, n16);
     if ((st = launch_status("wnet: state reset")) != FV_OK) return st;
@@ -596,7 +600,7 @@ fv_status reconstruct(const fv_wnet* n, const float* frame_rgba, const uint8_t* 
     ConvArgs a{};
     a.src0 = tensor(kIO[l][0]);
     a.src1 = kIO[l][1] >= 0 ? tensor(kIO[l][1]) : nullptr;
-    a.src2 = rec && kFeed[l] >= 0 ? tensor(kFeed[l]) : nullptr;
+    a.src2 = rec && kFeed[l] >= 0 ? sb + sp.t[kFeed[l]] : nullptr;
     a.c0 = L.c0;
     a.c1 = L.c1;
     a.c2 = a.src2 ? L.c2 : 0;
@@ -616,7 +620,7 @@ fv_status reconstruct(const fv_wnet* n, const float* frame_rgba, const uint8_t* 
     st = net::launch_conv<BF16>(a, net::nblocks_of(L.co), s);
     if (st != FV_OK) return st;
   }
-  float* od = rec ? od_state : out_direct ? out_direct : (float*)(ws + p.od);
+  float* od = state_out ? od_state : (out_direct && !keep) ? out_direct : (float*)(ws + p.od);
   {
     const Layer& L = LT[kHead];
     const float* w = n->master + param_offset(LT, kHead);
@@ -624,7 +628,7 @@ fv_status reconstruct(const fv_wnet* n, const float* frame_rgba, const uint8_t* 
         (const __bf16*)tensor(T_D0B), L.ci, w, w + 3 * L.ci, npx, od, nullptr);
     if ((st = launch_status("wnet: O_d")) != FV_OK) return st;
   }
-  if (rec && out_direct &&
+  if (state_out && out_direct &&
       (st = hip_status(hipMemcpyAsync(out_direct, od, npx * 3 * sizeof(float),
                                       hipMemcpyDeviceToDevice, s), "wnet: O_d copy")) != FV_OK)
     return st;
@@ -690,7 +694,7 @@ struct TPlan {
   int kchunks;
 };
 
-TPlan make_tplan(int n, int h, int w) {
+TPlan make_tplan(int n, int h, int w, const Layer* LT) {
   TPlan t;
   t.f = make_plan(n, h, w);
   size_t off = t.f.bytes;
@@ -710,9 +714,9 @@ TPlan make_tplan(int n, int h, int w) {
   for (int k = 1; k < kTensors; ++k) t.g[k] = take(px(kTC[k][1]) * kTC[k][0] * 4);
   size_t tmp = 0, dz = 0, part = 0, part2 = 0;
   for (int l = 0; l < kConv; ++l) {
-    const Layer& L = kL[l];
-    const int ci = L.c0 + L.c1;
-    tmp = std::max(tmp, px(L.level) * ci * 4);
+    const Layer& L = LT[l];
+    const int ci = L.c0 + L.c1 + L.c2;
+    tmp = std::max(tmp, px(L.level) * (L.c0 + L.c1) * 4);
     dz = std::max(dz, px(L.level) * L.co * 2);
     t.chunks[l] = net::wgrad_chunks(n, h >> L.level, w >> L.level, ci, L.co);
     part = std::max(part, net::wgrad_part_bytes(t.chunks[l], ci, L.co));
@@ -742,15 +746,25 @@ TPlan make_tplan(int n, int h, int w) {
 }
 
 fv_status train_check(const fv_wnet* n, int batch, int width, int height, const void* ws,
-                      size_t ws_bytes, TPlan* tp, const char* fn) {
+                      size_t ws_bytes, TPlan* tp, const char* fn, const void* state = nullptr,
+                      size_t state_bytes = 0) {
   if (!n || !ws) return fail(FV_ERR_INVALID_ARG, "%s: null pointer", fn);
-  if (n->recurrent)
-    return fail(FV_ERR_UNSUPPORTED, "%s: training is built for the plain W-Net only", fn);
+  if ((state != nullptr) != (n->recurrent != 0))
+    return fail(FV_ERR_INVALID_ARG,
+                n->recurrent ? "%s: a recurrent network trains with a state (_recurrent call)"
+                             : "%s: the plain network takes no state",
+                fn);
+  if (state) {
+    const StatePlan sp = make_state_plan(batch, height, width);
+    if (state_bytes < sp.bytes)
+      return fail(FV_ERR_CAPACITY, "%s: state %zu < %zu bytes", fn, state_bytes, sp.bytes);
+    if ((uintptr_t)state % 256) return fail(FV_ERR_INVALID_ARG, "%s: state not aligned", fn);
+  }
   fv_status st = net::check_frame(batch, width, height, fn);
   if (st != FV_OK) return st;
   if (width < 16 || height < 16)
     return fail(FV_ERR_INVALID_ARG, "%s: training frames must be at least 16 x 16", fn);
-  *tp = make_tplan(batch, height, width);
+  *tp = make_tplan(batch, height, width, n->L);
   if (ws_bytes < tp->bytes)
     return fail(FV_ERR_CAPACITY, "%s: workspace %zu < %zu bytes", fn, ws_bytes, tp->bytes);
   if ((uintptr_t)ws % 256) return fail(FV_ERR_INVALID_ARG, "%s: workspace not aligned", fn);
@@ -773,20 +787,21 @@ KKeep keep_of(const TPlan& t, uint8_t* ws) {
 fv_status predict_backward(const fv_wnet* n, const TPlan& tp, uint8_t* ws, int layer,
                            const uint8_t* hten, float* gh, int acc, const float* dz, int T,
                            int64_t m, hipStream_t s) {
-  const Layer& L = kL[layer];
-  const float* W = n->master + param_offset(kL, layer);
+  const Layer& L = n->L[layer];
+  const float* W = n->master + param_offset(n->L, layer);
   float* part = (float*)(ws + tp.kpart);
   const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(tp.kchunks, m / 64));
   k_predict_bwd_h<<<blocks_of(m), 256, T * L.ci * 4, s>>>(dz, T, W, L.ci, m, gh, acc);
   k_predict_wgrad<<<chunks, 256, 0, s>>>(dz, T, (const __bf16*)hten, L.ci, m, chunks, part);
   k_predict_reduce<<<blocks_of((int64_t)T * (L.ci + 1)), 256, 0, s>>>(
-      part, chunks, T, L.ci, n->grad + param_offset(kL, layer));
+      part, chunks, T, L.ci, n->grad + param_offset(n->L, layer));
   return launch_status("wnet: 1x1 backward");
 }
 
 fv_status backward(fv_wnet* n, const float* dloss_dout, int views, int width, int height,
-                   void* workspace, hipStream_t s) {
-  const TPlan tp = make_tplan(views, height, width);
+                   void* workspace, hipStream_t s, const uint8_t* state = nullptr) {
+  const TPlan tp = make_tplan(views, height, width, n->L);
+  const StatePlan sp = make_state_plan(views, height, width);
   const Plan& p = tp.f;
   uint8_t* ws = (uint8_t*)workspace;
   auto G = [&](int t) { return (float*)(ws + tp.g[t]); };
@@ -856,26 +871,35 @@ fv_status backward(fv_wnet* n, const float* dloss_dout, int views, int width, in
   float* part = (float*)(ws + tp.part);
   float* part2 = (float*)(ws + tp.part2);
   for (int l = kConv - 1; l >= 0; --l) {
-    const Layer& L = kL[l];
+    const Layer& L = n->L[l];
     const int hh = height >> L.level, ww = width >> L.level;
     const int64_t m = px(L.level);
-    const int ci = L.c0 + L.c1;
+    const bool feed = state && kFeed[l] >= 0;  // reads a fed-back state
+    const int ci = L.c0 + L.c1;                 // the channels whose gradient flows on
     net::launch_relu_mask(G(kIO[l][2]), ws + p.t[kIO[l][2]], dz, m * L.co / 8, s);
     ConvArgs in{};
     in.src0 = ws + p.t[kIO[l][0]];
     in.src1 = kIO[l][1] >= 0 ? ws + p.t[kIO[l][1]] : nullptr;
     in.c0 = L.c0;
     in.c1 = L.c1;
+    in.src2 = feed ? state + sp.t[kFeed[l]] : nullptr;
+    in.c2 = feed ? L.c2 : 0;
     in.up0 = L.up0;
     in.n = views;
     in.h = hh;
     in.w = ww;
+    const int ci_w = ci + in.c2;  // the weight gradient's input channels
+    if (l == 0 && L.ci == ci) {
+      // the recurrent form's first conv reads all 8 packed channels
+      return net::conv_wgrad(in, dz, ci, L.co, tp.chunks[l], part, part2,
+                             n->grad + param_offset(n->L, 0), s);
+    }
     if (l == 0) {
       // the packed input has 8 channels; the layer's parameters cover 5
       float* g0 = (float*)(ws + tp.w0);
       if ((st = net::conv_wgrad(in, dz, ci, L.co, tp.chunks[l], part, part2, g0, s)) != FV_OK)
         return st;
-      float* gdst = n->grad + param_offset(kL, 0);
+      float* gdst = n->grad + param_offset(n->L, 0);
       st = hip_status(hipMemcpy2DAsync(gdst, L.ci * 9 * sizeof(float), g0, ci * 9 * sizeof(float),
                                        L.ci * 9 * sizeof(float), L.co, hipMemcpyDeviceToDevice,
                                        s), "wnet: e0a gradient");
@@ -885,8 +909,8 @@ fv_status backward(fv_wnet* n, const float* dloss_dout, int views, int width, in
                                        hipMemcpyDeviceToDevice, s), "wnet: e0a bias gradient");
       return st;
     }
-    st = net::conv_wgrad(in, dz, ci, L.co, tp.chunks[l], part, part2,
-                         n->grad + param_offset(kL, l), s);
+    st = net::conv_wgrad(in, dz, ci_w, L.co, tp.chunks[l], part, part2,
+                         n->grad + param_offset(n->L, l), s);
     if (st != FV_OK) return st;
     // input gradient: conv with the transposed weights, FP32 output
     ConvArgs a{};
@@ -963,12 +987,15 @@ fv_status fv_wnet_create(const float* host_params, size_t n_params, fv_wnet** ou
   for (int l = 0; ok && l < kConv; ++l)
     ok = hipMalloc(&n->w_bf16[l], net::swizzled_elems(n->L[l].ci, n->L[l].co) * 2) ==
          hipSuccess;
-  if (!n->recurrent) {
+  {
     ok = ok && hipMalloc(&n->grad, P * sizeof(float)) == hipSuccess &&
          hipMalloc(&n->adam_m, P * sizeof(float)) == hipSuccess &&
          hipMalloc(&n->adam_v, P * sizeof(float)) == hipSuccess;
+    // transposed weights of the input-gradient convs: only the gradients of
+    // [upsampled, skip] are used (a fed-back state is an input)
     for (int l = 1; ok && l < kConv; ++l)
-      ok = hipMalloc(&n->w_bf16t[l], net::swizzled_elems(n->L[l].co, n->L[l].ci) * 2) ==
+      ok = hipMalloc(&n->w_bf16t[l],
+                     net::swizzled_elems(n->L[l].co, n->L[l].c0 + n->L[l].c1) * 2) ==
            hipSuccess;
     if (ok)
       ok = hipMemset(n->adam_m, 0, P * sizeof(float)) == hipSuccess &&
@@ -1071,11 +1098,9 @@ fv_status fv_wnet_train_workspace(const fv_wnet* n, int batch, int width, int he
                                   size_t* bytes) {
   clear_error();
   if (!n || !bytes) return fail(FV_ERR_INVALID_ARG, "fv_wnet_train_workspace: null pointer");
-  if (n->recurrent)
-    return fail(FV_ERR_UNSUPPORTED, "fv_wnet_train_workspace: plain W-Net only");
   fv_status st = net::check_frame(batch, width, height, "fv_wnet_train_workspace");
   if (st != FV_OK) return st;
-  *bytes = make_tplan(batch, height, width).bytes;
+  *bytes = make_tplan(batch, height, width, n->L).bytes;
   return FV_OK;
 }
 
@@ -1104,15 +1129,90 @@ fv_status fv_wnet_backward(fv_wnet* n, const float* dloss_dout, int batch, int w
   hipStream_t s = (hipStream_t)stream;
   if ((st = backward(n, dloss_dout, batch, width, height, workspace, s)) != FV_OK) return st;
   if (grad_out)
-    st = hip_status(hipMemcpyAsync(grad_out, n->grad, param_offset(kL, kLayersAll) * 4,
+    st = hip_status(hipMemcpyAsync(grad_out, n->grad, param_offset(n->L, kLayersAll) * 4,
                                    hipMemcpyDeviceToDevice, s), "fv_wnet_backward: copy");
   return st;
+}
+
+fv_status fv_wnet_forward_train_recurrent(fv_wnet* n, const float* frame_rgba,
+                                          const uint8_t* mask, const float* frame_depth,
+                                          const void* state, size_t state_bytes, int batch,
+                                          int width, int height, float* out_rgb,
+                                          void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  TPlan tp;
+  fv_status st = train_check(n, batch, width, height, workspace, ws_bytes, &tp,
+                             "fv_wnet_forward_train_recurrent", state, state_bytes);
+  if (st != FV_OK) return st;
+  const KKeep k = keep_of(tp, (uint8_t*)workspace);
+  return reconstruct(n, frame_rgba, mask, frame_depth, const_cast<void*>(state), state_bytes, 0,
+                     batch, width, height, out_rgb, nullptr, workspace, ws_bytes, stream,
+                     "fv_wnet_forward_train_recurrent", &k);
+}
+
+fv_status fv_wnet_backward_recurrent(fv_wnet* n, const float* dloss_dout, const void* state,
+                                     size_t state_bytes, int batch, int width, int height,
+                                     float* grad_out, void* workspace, size_t ws_bytes,
+                                     void* stream) {
+  clear_error();
+  TPlan tp;
+  fv_status st = train_check(n, batch, width, height, workspace, ws_bytes, &tp,
+                             "fv_wnet_backward_recurrent", state, state_bytes);
+  if (st != FV_OK) return st;
+  if (!dloss_dout) return fail(FV_ERR_INVALID_ARG, "fv_wnet_backward_recurrent: null dloss");
+  hipStream_t s = (hipStream_t)stream;
+  if ((st = backward(n, dloss_dout, batch, width, height, workspace, s,
+                     (const uint8_t*)state)) != FV_OK)
+    return st;
+  if (grad_out)
+    st = hip_status(hipMemcpyAsync(grad_out, n->grad, param_offset(n->L, kLayersAll) * 4,
+                                   hipMemcpyDeviceToDevice, s), "fv_wnet_backward: copy");
+  return st;
+}
+
+fv_status fv_wnet_loss_temporal(const fv_wnet* n, const float* out_rgb,
+                                const float* target_rgba, int batch, int width, int height,
+                                float weight, float* loss, float* dloss_dout, void* workspace,
+                                size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!n || !workspace || !out_rgb || !target_rgba || !loss || !dloss_dout)
+    return fail(FV_ERR_INVALID_ARG, "fv_wnet_loss_temporal: null pointer");
+  fv_status st = net::check_frame(batch, width, height, "fv_wnet_loss_temporal");
+  if (st != FV_OK) return st;
+  if (batch % 2)
+    return fail(FV_ERR_INVALID_ARG, "fv_wnet_loss_temporal: batch %d is not a set of pairs",
+                batch);
+  if (!(weight >= 0.0f && std::isfinite(weight)))
+    return fail(FV_ERR_INVALID_ARG, "fv_wnet_loss_temporal: weight must be finite and >= 0");
+  const TPlan tp = make_tplan(batch, height, width, n->L);
+  if (ws_bytes < tp.bytes)
+    return fail(FV_ERR_CAPACITY, "fv_wnet_loss_temporal: workspace %zu < %zu bytes", ws_bytes,
+                tp.bytes);
+  return net::tloss_run(out_rgb, target_rgba, batch / 2, height, width, weight, loss,
+                        dloss_dout, (double*)((uint8_t*)workspace + tp.red),
+                        (hipStream_t)stream);
+}
+
+fv_status fv_wnet_loss(const fv_wnet* n, const float* out_rgb, const float* target_rgba,
+                       int batch, int width, int height, float* loss3, float* dloss_dout,
+                       void* workspace, size_t ws_bytes, void* stream) {
+  clear_error();
+  if (!n || !workspace || !out_rgb || !target_rgba || !loss3 || !dloss_dout)
+    return fail(FV_ERR_INVALID_ARG, "fv_wnet_loss: null pointer");
+  fv_status st = net::check_frame(batch, width, height, "fv_wnet_loss");
+  if (st != FV_OK) return st;
+  const TPlan tp = make_tplan(batch, height, width, n->L);
+  if (ws_bytes < tp.bytes)
+    return fail(FV_ERR_CAPACITY, "fv_wnet_loss: workspace %zu < %zu bytes", ws_bytes, tp.bytes);
+  uint8_t* ws = (uint8_t*)workspace;
+  return net::loss_run(out_rgb, target_rgba, batch, height, width, loss3, dloss_dout,
+                       (float*)(ws + tp.tgt), ws + tp.ssim, (double*)(ws + tp.red),
+                       (hipStream_t)stream);
 }
 
 fv_status fv_wnet_adam(fv_wnet* n, float lr, float beta1, float beta2, float eps, void* stream) {
   clear_error();
   if (!n) return fail(FV_ERR_INVALID_ARG, "fv_wnet_adam: null net");
-  if (n->recurrent) return fail(FV_ERR_UNSUPPORTED, "fv_wnet_adam: plain W-Net only");
   if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) ||
       !(eps > 0.f))
     return fail(FV_ERR_INVALID_ARG, "fv_wnet_adam: bad hyper-parameters");

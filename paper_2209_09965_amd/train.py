@@ -151,6 +151,36 @@ def widen_recurrent(theta):
     return np.concatenate([w8, theta[32 * 5 * 9:]]).astype(np.float32)
 
 
+def widen_wnet_recurrent(theta):
+    """Recurrent W-Net parameters from plain ones: the same weights, zeros on
+    the fed-back input channels (e0a's previous O_d, each decoder block's
+    previous output), so the widened network starts as the plain one."""
+    out, off = [], 0
+    for (ci, co, k), (cr, _, _) in zip(synthetic.WNET_SHAPES, synthetic.WNET_SHAPES_RECURRENT):
+        w = theta[off:off + co * ci * k * k].reshape(co, ci, k, k)
+        off += co * ci * k * k
+        if cr != ci:
+            w = np.concatenate([w, np.zeros((co, cr - ci, k, k), w.dtype)], axis=1)
+        out += [w.reshape(-1), theta[off:off + co]]
+        off += co
+    assert off == theta.size
+    return np.concatenate(out).astype(np.float32)
+
+
+def interleave_state(dst, src, per, W, H):
+    """The state of a training batch of per (first frame, second frame)
+    pairs: the first frames from zero, the second from src, the state the
+    recurrent inference of the first frames left (per views)."""
+    od, d2, d1, d0 = b.WNet.state_layout(2 * per, W, H)
+    so = b.WNet.state_layout(per, W, H)
+    sizes = [H * W * 3 * 4, (H // 4) * (W // 4) * 80 * 2, (H // 2) * (W // 2) * 64 * 2,
+             H * W * 64 * 2]
+    dst.zero_()
+    for o_dst, o_src, sz in zip((od, d2, d1, d0), so, sizes):
+        dv = dst[o_dst:o_dst + 2 * per * sz].view(2 * per, sz)
+        dv[1::2].copy_(src[o_src:o_src + per * sz].view(per, sz))
+
+
 def psnr_t(x, ref):
     mse = torch.mean((x.clamp(0, 1) - ref.clamp(0, 1)) ** 2).item()
     return float("inf") if mse == 0 else 10 * math.log10(1.0 / mse)
@@ -165,6 +195,8 @@ def evaluate(net, data, idx, dev, precision="bf16", temporal=False, seq_len=2):
     out = torch.empty(H * W * 3, device=dev)
     od = torch.empty(H * W * 3, device=dev)
     ws = torch.empty(net.workspace_bytes(1, W, H, precision), dtype=torch.uint8, device=dev)
+    wstate = (torch.empty(b.WNet.state_bytes(1, W, H), dtype=torch.uint8, device=dev)
+              if isinstance(net, b.WNet) and net.recurrent else None)
     res = {"hybrid": [], "direct": [], "sparse": []}
     if temporal:
         res["tpsnr"] = []
@@ -172,7 +204,11 @@ def evaluate(net, data, idx, dev, precision="bf16", temporal=False, seq_len=2):
         outs = []
         for t, j in enumerate(range(i, i + seq_len) if temporal else (i,)):
             fr = data["rgba"][j]
-            if net.recurrent:
+            if wstate is not None:
+                # the W-Net's state: O_d and the decoder outputs, zero at t = 0
+                net.reconstruct_recurrent(fr, data["mask"][j], data["depth"][j], wstate, t == 0,
+                                          1, W, H, out, od, workspace=ws)
+            elif net.recurrent:
                 # O_d is written over the previous frame's, which it reads first
                 net.reconstruct_recurrent(fr, data["mask"][j], data["depth"][j],
                                           od if t > 0 else None, 1, W, H, out, od,
@@ -255,8 +291,12 @@ def main():
     log("pairs: %d train / %d val / %d test" % (tr.size, va.size, te.size))
 
     if args.wnet:
-        assert not temporal and not args.recurrent, "the W-Net trains on single frames"
-        theta = np.load(args.init) if args.init else synthetic.wnet_init(args.seed)
+        if args.init:
+            theta = np.load(args.init)
+            if args.recurrent and theta.size == b.WNet.PARAMS:
+                theta = widen_wnet_recurrent(theta)
+        else:
+            theta = synthetic.wnet_init(args.seed, recurrent=args.recurrent)
         net = b.WNet(theta)
     else:
         if args.init:
@@ -279,6 +319,10 @@ def main():
         iws = torch.empty(net.workspace_bytes(per, W, H, "bf16"), dtype=torch.uint8, device=dev)
         iout = torch.empty(per * H * W * 3, device=dev)
         prev = torch.zeros(B, H * W * 3, device=dev)
+        if args.wnet and args.recurrent:
+            assert L == 2, "the W-Net's state is carried over pairs (--seq-len 2)"
+            ist = torch.empty(b.WNet.state_bytes(per, W, H), dtype=torch.uint8, device=dev)
+            bst = torch.empty(b.WNet.state_bytes(B, W, H), dtype=torch.uint8, device=dev)
     lt = torch.zeros(1, device=dev)
     dl = torch.empty(B * H * W * 3, device=dev)
     out = torch.empty(B * H * W * 3, device=dev)
@@ -321,6 +365,20 @@ def main():
                 lr *= (step + 1) / warm
             if not temporal:
                 net.train_step(fr, m, d, fr, B, W, H, lr, loss3, ws)
+            elif args.wnet and args.recurrent:
+                # the second frames' state by inference on the first frames
+                st0 = torch.from_numpy(first).to(dev)
+                net.reconstruct_recurrent(data["rgba"].index_select(0, st0).reshape(-1),
+                                          data["mask"].index_select(0, st0).reshape(-1),
+                                          data["depth"].index_select(0, st0).reshape(-1),
+                                          ist, True, per, W, H, iout, workspace=iws)
+                interleave_state(bst, ist, per, W, H)
+                net.forward_train_recurrent(fr, m, d, bst, B, W, H, out, ws)
+                net.loss(out, fr, B, W, H, loss3, dl, ws)
+                if args.temporal > 0:
+                    net.loss_temporal(out, fr, B, W, H, args.temporal, lt, dl, ws)
+                net.backward_recurrent(dl, bst, B, W, H, ws)
+                net.adam(lr)
             elif args.recurrent:
                 # the fed-back O_d of every frame of the pairs, by inference
                 # along the sequences with the current weights
@@ -347,7 +405,8 @@ def main():
             else:
                 net.forward_train(fr, m, d, B, W, H, out, ws)
                 net.loss(out, fr, B, W, H, loss3, dl, ws)
-                net.loss_temporal(out, fr, B, W, H, args.temporal, lt, dl, ws)
+                if args.temporal > 0:
+                    net.loss_temporal(out, fr, B, W, H, args.temporal, lt, dl, ws)
                 net.backward(dl, B, W, H, ws)
                 net.adam(lr)
             step += 1

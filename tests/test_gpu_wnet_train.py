@@ -3,7 +3,7 @@
 full parameter gradient against the oracle's exact backward of the
 BF16-emulated forward (D's 3x3 weights and stored activations rounded to
 BF16), per layer; determinism; that Adam steps reduce the loss; parameter
-round trip and the plain-form-only refusal."""
+round trip; the recurrent form with its fed-back state as a constant input."""
 import numpy as np
 import pytest
 import torch
@@ -12,7 +12,8 @@ import oracle
 import synthetic
 from oracle import net as N
 from oracle import wnet as WN
-from tests.test_gpu_wnet import _bf16_d_weights, _frame, _theta, _theta_rec
+from tests.test_gpu_wnet import (_bf16_d_weights, _bf16_d_weights_rec, _frame, _state_put,
+                                 _theta, _theta_rec)
 
 pytestmark = pytest.mark.gpu
 
@@ -110,8 +111,62 @@ def test_wnet_params_round_trip_and_plain_only(dev):
     with pytest.raises(b.FvError):
         net.set_params(th2[:-1])
     net.close()
+    # the recurrent form trains through the calls that take its state
     rec = b.WNet(_theta_rec(23))
+    ws = torch.empty(rec.train_workspace_bytes(1, 16, 16), dtype=torch.uint8, device=dev)
+    z = torch.zeros(16 * 16 * 4, device=dev)
     with pytest.raises(b.FvError) as e:
-        rec.train_workspace_bytes(1, 16, 16)
-    assert e.value.status == b.FV_ERR_UNSUPPORTED
+        rec.train_step(z, torch.zeros(256, dtype=torch.uint8, device=dev), None, z, 1, 16, 16,
+                       1e-3, torch.zeros(3, device=dev), ws)
+    assert e.value.status == b.FV_ERR_INVALID_ARG
     rec.close()
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("n,H,W", [(1, 16, 16), (2, 32, 48)])
+def test_recurrent_wnet_backward_matches_oracle(n, H, W, dev):
+    """The recurrent form's gradient with a random fed-back state (O_d and
+    the decoder outputs, as BF16) installed on both sides and held constant,
+    against the oracle's backward of the BF16-emulated forward."""
+    from paper_2209_09965_amd import binding as b
+    rng = np.random.default_rng(31)
+    theta = _theta_rec(32)
+    rgba, mask, depth = _frame(rng, n, H, W, density=0.3)
+    dloss = rng.normal(0, 1.0, (n, H, W, 3)).astype(np.float32)
+    st = WN.zero_state(n, H, W)
+    st = {k: (rng.normal(0, 0.3, v.shape) if k == "od" else N.bf16_round(rng.random(v.shape)))
+          for k, v in st.items()}
+    st["od"] = st["od"].astype(np.float32).astype(np.float64)
+    net = b.WNet(theta)
+    state = torch.zeros(b.WNet.state_bytes(n, W, H), dtype=torch.uint8, device=dev)
+    _state_put(b, state, st, n, H, W)
+    ws = torch.empty(net.train_workspace_bytes(n, W, H), dtype=torch.uint8, device=dev)
+    out = torch.empty(n * H * W * 3, device=dev)
+    net.forward_train_recurrent(_t(rgba, dev), _t(mask, dev), _t(depth, dev), state, n, W, H,
+                                out, ws)
+    g = torch.zeros(WN.n_params(recurrent=True), device=dev)
+    net.backward_recurrent(_t(dloss, dev), state, n, W, H, ws, grad_out=g)
+    torch.cuda.synchronize()
+    g = g.cpu().numpy()
+    net.close()
+    x = np.ascontiguousarray(oracle.pack_input(rgba, mask, depth).reshape(n, H, W, 5)
+                             .transpose(0, 3, 1, 2))
+    thq = _bf16_d_weights_rec(theta)
+    want, _, _, cache = WN.forward_recurrent(thq, x, st, keep=True, act_round=N.bf16_round)
+    gw = WN.backward(thq, cache, dloss.astype(np.float64).transpose(0, 3, 1, 2))
+    assert np.abs(out.cpu().numpy().reshape(n, H, W, 3).transpose(0, 3, 1, 2) - want).max() < 2e-2
+    off = 0
+    worst_d = worst_k = 0.0
+    for name, ci, co, k in WN.layers(recurrent=True):
+        nw = co * ci * k * k + co
+        a, r = g[off:off + nw], gw[off:off + nw]
+        rel = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
+        print("%-4s grad rel L2 err %.5f  |g| %.3g" % (name, rel, np.linalg.norm(r)), flush=True)
+        if k == 3:
+            worst_d = max(worst_d, rel)
+        else:
+            worst_k = max(worst_k, rel)
+        off += nw
+    small = H * W <= 256
+    assert worst_d < (0.01 if small else 0.10)
+    assert worst_k < (0.005 if small else 0.10)
