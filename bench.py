@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--noise", default="hash", choices=["hash", "blue"],
                     help="sample-map noise: the seeded hash, or a stack of 64 blue-noise "
                          "tiles of 64 x 64 (void-and-cluster), one tile per frame")
+    ap.add_argument("--lanes-per-ray", type=int, default=0, choices=[0, 1, 2, 4, 8],
+                    help="sparse march: lanes marching one ray together (0 = chosen per "
+                         "launch; a forced value reproduces the group-size timings)")
     ap.add_argument("--layout", default=None, choices=["linear", "bricked"],
                     help="volume copy layout (default: bricked)")
     ap.add_argument("--tpsnr-frames", type=int, default=12,
@@ -144,8 +147,9 @@ def compression_sweep(args):
         sys.exit("the sweep runs single-view workloads")
     vol, tf, _ = make_inputs(wl)
     mp = synthetic.march_params(shading=wl["shading"], shadow_step=args.shadow_step)
+    mp["lanes_per_ray"] = args.lanes_per_ray
     vol_t = torch.from_numpy(vol).to(dev)
-    volh = b.Volume(vol_t)
+    volh = b.Volume(vol_t, bricked=(args.layout or "bricked") == "bricked")
     del vol_t
     tf_t = torch.from_numpy(tf).reshape(-1).to(dev)
     total = W * H
@@ -250,6 +254,7 @@ def main():
     W, H, V = wl["width"], wl["height"], wl["views"]
     vol, tf, vol_dev = make_inputs(wl, dev)
     mp = synthetic.march_params(shading=wl["shading"], shadow_step=args.shadow_step)
+    mp["lanes_per_ray"] = args.lanes_per_ray
     sig_frac = wl.get("sigma_frac", 0.15)
     eye_off = wl.get("eye_offset", 0.0)
 

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define FV_ABI_VERSION 1
+#define FV_ABI_VERSION 2
 
 typedef enum {
   FV_OK = 0,
@@ -259,6 +259,10 @@ typedef struct {
   float shadow_step; /* global shadows (shading only): 0 = none, else the
                         shadow-ray segment length in voxels, in [1/64, 64];
                         the paper's renderer uses 4 x step_vox           */
+  int32_t lanes_per_ray; /* sparse march: 0 = chosen per launch from the
+                        rays that reach the volume and the resident lanes;
+                        1, 2, 4 or 8 forces that many lanes per ray (for
+                        timing; every choice gives the same pixels)      */
 } fv_march_params;
 
 #define FV_TF_ENTRIES 256
@@ -275,7 +279,7 @@ typedef struct {
  * views > 8, views*W*H >= 2^32, W or H > 65535, tf_n != 256, step_vox
  * outside [1/64, 64], alpha_stop outside (0,1], a zero light_dir or a
  * shininess outside [0, 1024] with shading, shadow_step not 0 and outside
- * [1/64, 64], shading not 0/1
+ * [1/64, 64], lanes_per_ray not 0, 1, 2, 4 or 8, shading not 0/1
  * (FV_ERR_UNSUPPORTED), non-finite camera, fovy outside (0,180), eye ==
  * target or up parallel to the view direction. */
 fv_status fv_raymarch_dense(const fv_volume* v, const float* tf_rgba, int tf_n,

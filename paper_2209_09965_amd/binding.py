@@ -46,7 +46,7 @@ class MarchParams(ctypes.Structure):
                 ("shading", ctypes.c_int32), ("light_dir", ctypes.c_float * 3),
                 ("ka", ctypes.c_float), ("kd", ctypes.c_float), ("ks", ctypes.c_float),
                 ("shininess", ctypes.c_float), ("bg", ctypes.c_float * 3),
-                ("shadow_step", ctypes.c_float)]
+                ("shadow_step", ctypes.c_float), ("lanes_per_ray", ctypes.c_int32)]
 
 
 class RenderPolicy(ctypes.Structure):
@@ -245,6 +245,7 @@ def march_params(m):
     mp.ka, mp.kd, mp.ks = float(m.get("ka", 0.2)), float(m.get("kd", 0.7)), float(m.get("ks", 0.3))
     mp.shininess = float(m.get("shininess", 32.0))
     mp.shadow_step = float(m.get("shadow_step", 0.0))
+    mp.lanes_per_ray = int(m.get("lanes_per_ray", 0))
     mp.bg[:] = [float(v) for v in m.get("bg", (0.0, 0.0, 0.0))]
     return mp
 

@@ -44,6 +44,7 @@ struct MarchArgs {
   float light[3];  // normalised, towards the light
   double lightd[3];  // the same in FP64 (shadow-ray positions)
   double shadow_step;  // shadow-ray segment length in voxels (0: no shadows)
+  int lanes;           // lanes per ray of the sparse march (0: chosen per launch)
   float ka, kd, ks, shininess;
   float bg[3];
   CamD cam[kMaxViews];
@@ -787,9 +788,13 @@ k_march_sparse(
   uint32_t hc = lane < kHitCounters ? queue[32 * (1 + lane)] : 0u;
   for (int off = 32; off; off >>= 1) hc += __shfl_xor(hc, off, 64);
   const uint64_t hits = hc, lanes = (uint64_t)gridDim.x * 256u;
-  int g = 1;
-  while (g < 8 && hits * (uint64_t)(4 * g * g) <= lanes * (SHADOW ? kGroupRuleShadow : kGroupRule))
-    g *= 2;
+  int g = a.lanes;
+  if (g == 0) {
+    g = 1;
+    while (g < 8 &&
+           hits * (uint64_t)(4 * g * g) <= lanes * (SHADOW ? kGroupRuleShadow : kGroupRule))
+      g *= 2;
+  }
   uint32_t ns = 0;
   switch (g) {
     case 8:
@@ -861,6 +866,10 @@ fv_status fill_args(const fv_volume* v, const float* tf, int tf_n, const fv_came
   if (!(mp->shadow_step == 0.0f || (mp->shadow_step >= 1.0f / 64.0f && mp->shadow_step <= 64.0f)))
     return fail(FV_ERR_INVALID_ARG, "%s: shadow_step must be 0 or in [1/64, 64]", fn);
   a->shadow_step = mp->shading ? (double)mp->shadow_step : 0.0;
+  if (!(mp->lanes_per_ray == 0 || mp->lanes_per_ray == 1 || mp->lanes_per_ray == 2 ||
+        mp->lanes_per_ray == 4 || mp->lanes_per_ray == 8))
+    return fail(FV_ERR_INVALID_ARG, "%s: lanes_per_ray must be 0, 1, 2, 4 or 8", fn);
+  a->lanes = mp->lanes_per_ray;
   a->ka = mp->ka;
   a->kd = mp->kd;
   a->ks = mp->ks;

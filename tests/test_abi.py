@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version():
     from paper_2209_09965_amd import binding
-    assert binding.lib().fv_abi_version() == 1
+    assert binding.lib().fv_abi_version() == 2
 
 
 def _fp(**kw):

@@ -430,3 +430,34 @@ def test_shadow_step_out_of_range_rejected(dev):
         with pytest.raises(b.FvError, match="shadow_step"):
             b.raymarch_dense(vol, tf_t, [synthetic.orbit_camera(0)], 8, 8, mp, frame)
     vol.close()
+
+
+@pytest.mark.parametrize("g", [1, 2, 4, 8])
+def test_forced_lanes_per_ray_equal_dense(g, noise256, dev):
+    """Every forced number of lanes per ray (lanes_per_ray) gives the dense
+    march's pixels bit for bit on the benchmark frame's list."""
+    from paper_2209_09965_amd import binding as b
+    vol, tf = noise256
+    W, H = 1920, 1080
+    cams = [synthetic.orbit_camera(13)]
+    mp = dict(synthetic.march_params(shading=True), lanes_per_ray=g)
+    fp = synthetic.fovea_params(W, H, seed=77, frame=13)
+    vt, tt = torch.from_numpy(vol).to(dev), _tf_t(tf, dev)
+    sp = _sparse_run(b, vt, tt, cams, W, H, mp, fp, dev)
+    drgba, ddepth, _ = gpu_dense(b, vt, tt, cams, W, H, synthetic.march_params(shading=True), dev)
+    idx = sp["idx"]
+    assert np.array_equal(sp["frame"][idx], drgba[idx]) and np.array_equal(sp["fdepth"][idx],
+                                                                          ddepth[idx])
+
+
+def test_lanes_per_ray_out_of_range_rejected(dev):
+    from paper_2209_09965_amd import binding as b
+    vol = torch.zeros((8, 8, 8), dtype=torch.uint8, device=dev)
+    mp = dict(synthetic.march_params(shading=False), lanes_per_ray=3)
+    rgba = torch.zeros(16 * 16 * 4, device=dev)
+    vh = b.Volume(vol)
+    with pytest.raises(b.FvError) as e:
+        b.raymarch_dense(vh, _tf_t(synthetic.tf_blob(1), dev), [synthetic.orbit_camera(0)], 16, 16,
+                         mp, rgba)
+    vh.close()
+    assert e.value.status == b.FV_ERR_INVALID_ARG
