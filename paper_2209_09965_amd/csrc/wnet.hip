@@ -21,6 +21,14 @@
 // as a third concatenated source after [upsampled, skip].  The decoder
 // blocks write their outputs straight into the state (after the first conv
 // has read the old one), so it costs no copies.
+//
+// Training (either form): the forward keeps K's per-level kernels, blend
+// weights and blends; the backward runs K's adjoints in FP32 (finest
+// decoder level to coarsest encoder level), adds K's gradients into D's
+// states, then D's backward on the single-stage network's kernels (ReLU
+// mask, MFMA weight gradient, input-gradient conv); Adam on the FP32 master.
+// A recurrent form's state is a read-only input there (carried over one
+// step, no gradient through it).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
