@@ -319,6 +319,11 @@ __global__ void __launch_bounds__(256) k_heads_bwd(const float* __restrict__ dou
                                                    int64_t off_hd, int64_t off_hk,
                                                    float* __restrict__ d28,
                                                    float* __restrict__ gh) {
+  // the BF16-rounded head weights (the forward's), [28 outputs][32 inputs]
+  __shared__ float sw[28 * 32];
+  for (int i = threadIdx.x; i < 28 * 32; i += 256)
+    sw[i] = (float)(__bf16)(i < 3 * 32 ? params[off_hd + i] : params[off_hk + i - 3 * 32]);
+  __syncthreads();
   const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t npx = (int64_t)n * h * w;
   if (p >= npx) return;
@@ -339,37 +344,33 @@ __global__ void __launch_bounds__(256) k_heads_bwd(const float* __restrict__ dou
     }
   float d[28];
   for (int k = 0; k < 25; ++k) d[3 + k] = wl[k] * (dw[k] - dot);
+  // d O_d(p): every pixel q whose clamped tap k lands on p, in the order
+  // (dy, dx, qy, qx); per axis the q are p - d inside the image, widened to
+  // the edge when p is an edge pixel
   float a0 = 0.f, a1 = 0.f, a2 = 0.f;
   for (int dy = -2; dy <= 2; ++dy) {
-    const int ylo = (y == 0) ? 0 : y - dy, yhi = (y == h - 1) ? h - 1 : y - dy;
+    const int ylo = max(y == 0 ? 0 : y - dy, 0), yhi = min(y == h - 1 ? h - 1 : y - dy, h - 1);
     for (int dx = -2; dx <= 2; ++dx) {
-      const int xlo = (x == 0) ? 0 : x - dx, xhi = (x == w - 1) ? w - 1 : x - dx;
+      const int xlo = max(x == 0 ? 0 : x - dx, 0), xhi = min(x == w - 1 ? w - 1 : x - dx, w - 1);
       const int k = 5 * (dy + 2) + (dx + 2);
-      for (int py = max(ylo, 0); py <= min(yhi, h - 1); ++py) {
-        if (min(max(py + dy, 0), h - 1) != y) continue;
-        for (int px = max(xlo, 0); px <= min(xhi, w - 1); ++px) {
-          if (min(max(px + dx, 0), w - 1) != x) continue;
+      for (int py = ylo; py <= yhi; ++py)
+        for (int px = xlo; px <= xhi; ++px) {
           const int64_t q = ((int64_t)b * h + py) * w + px;
           const float wq = wk[q * 25 + k];
           a0 = fmaf(wq, dout[q * 3], a0);
           a1 = fmaf(wq, dout[q * 3 + 1], a1);
           a2 = fmaf(wq, dout[q * 3 + 2], a2);
         }
-      }
     }
   }
   d[0] = a0;
   d[1] = a1;
   d[2] = a2;
   for (int j = 0; j < 28; ++j) d28[p * 28 + j] = d[j];
-  const float* whd = params + off_hd;
-  const float* whk = params + off_hk;
   for (int k = 0; k < 32; ++k) {
-    float s = 0.f;
-    // the forward used the BF16-rounded head weights
-    for (int c = 0; c < 3; ++c) s = fmaf((float)(__bf16)whd[c * 32 + k], d[c], s);
-    for (int qq = 0; qq < 25; ++qq) s = fmaf((float)(__bf16)whk[qq * 32 + k], d[3 + qq], s);
-    gh[p * 32 + k] = s;
+    float sacc = 0.f;
+    for (int c = 0; c < 28; ++c) sacc = fmaf(sw[c * 32 + k], d[c], sacc);
+    gh[p * 32 + k] = sacc;
   }
 }
 

@@ -56,6 +56,52 @@ def _grads(theta, rgba, mask, depth, dloss, n, H, W, dev):
     return out.cpu().numpy(), g.cpu().numpy()
 
 
+def oracle_self_noise(run, trials=2, seed=9):
+    """The oracle's own sensitivity to the rounding points of its BF16
+    emulation: ``run(act_round)`` returns the flat gradient with every stored
+    activation passed through ``act_round``.  Each trial rounds after an
+    FP32-sized relative perturbation (uniform within +-2^-23), which flips
+    the BF16 roundings of values lying that close to a rounding boundary, as
+    the kernels' FP32 arithmetic does against the FP64 oracle.  Returns the
+    perturbed gradients."""
+    prng = np.random.default_rng(seed)
+
+    def jitter(t):
+        return bf16_round(t * (1.0 + prng.uniform(-2.0 ** -23, 2.0 ** -23, t.shape)))
+
+    return [run(jitter) for _ in range(trials)]
+
+
+def check_layer_grads(g, gw, noise, layers, small):
+    """Per layer, the relative L2 distance between the kernel gradient g and
+    the oracle's gw must stay within 0.35 % plus the largest distance of the
+    oracle's own perturbed gradients (``noise``).  The 0.35 % is the BF16
+    storage of the output gradients on the MFMA input-gradient convs (~2^-9
+    relative per layer when the oracle rounds dZ the same way).  Flips of
+    the forward's BF16 roundings move a layer's gradient by up to ~11 % at
+    2 x 32 x 48 in the oracle itself.  On the small cases (<= 256 pixels) the
+    kernels flip none, and every layer must also be within 1 %.  Returns
+    the distance per layer name."""
+    off = 0
+    worst = 0.0
+    rels = {}
+    for name, ci, co, k in layers:
+        nw = co * ci * k * k + co
+        a, r = g[off:off + nw], gw[off:off + nw]
+        norm = max(np.linalg.norm(r), 1e-30)
+        rel = np.linalg.norm(a - r) / norm
+        self_rel = max(np.linalg.norm(q[off:off + nw] - r) / norm for q in noise)
+        print("%-4s grad rel L2 err %.5f  oracle self %.5f  |g| %.3g"
+              % (name, rel, self_rel, np.linalg.norm(r)), flush=True)
+        assert rel < 0.0035 + self_rel, name
+        worst = max(worst, rel)
+        rels[name] = rel
+        off += nw
+    if small:
+        assert worst < 0.01
+    return rels
+
+
 @pytest.mark.parametrize("n,H,W", [(1, 16, 16), (2, 32, 48)])
 def test_backward_matches_oracle(n, H, W, dev):
     rng = np.random.default_rng(1)
@@ -66,25 +112,12 @@ def test_backward_matches_oracle(n, H, W, dev):
     x = _oracle_input(rgba, mask, depth, n, H, W)
     th16 = _bf16_weights(theta)
     want, _, cache = N.forward(th16, x, keep=True, act_round=bf16_round)
-    gw = N.backward(th16, cache, dloss.astype(np.float64).transpose(0, 3, 1, 2))
     assert np.abs(out.reshape(n, H, W, 3).transpose(0, 3, 1, 2) - want).max() < 2e-2
-    off = 0
-    worst = 0.0
-    for name, ci, co, k in N.LAYERS:
-        nw = co * ci * k * k + co
-        a, r = g[off:off + nw], gw[off:off + nw]
-        rel = np.linalg.norm(a - r) / max(np.linalg.norm(r), 1e-30)
-        print("%-4s grad rel L2 err %.4f  |g| %.3g" % (name, rel, np.linalg.norm(r)))
-        worst = max(worst, rel)
-        off += nw
-    # BF16 storage of the output gradients (MFMA input-gradient convs) adds
-    # ~2^-9 relative noise per layer: <= 0.35% per layer when the oracle rounds
-    # dZ the same way.  At 16 x 16 the BF16 forward has no rounding flips and the
-    # bound is tight.  Larger frames do flip a few BF16 roundings (FP32 vs FP64
-    # values on a rounding boundary); the oracle's own gradients move by 5-9% per
-    # layer under FP32-level perturbations of its activations before rounding,
-    # which sets the looser bound.
-    assert worst < (0.01 if H * W <= 256 else 0.10)
+    dl64 = dloss.astype(np.float64).transpose(0, 3, 1, 2)
+    gw = N.backward(th16, cache, dl64)
+    noise = oracle_self_noise(
+        lambda rnd: N.backward(th16, N.forward(th16, x, keep=True, act_round=rnd)[2], dl64))
+    check_layer_grads(g, gw, noise, N.LAYERS, small=H * W <= 256)
     g2 = _grads(theta, rgba, mask, depth, dloss, n, H, W, dev)[1]
     assert np.array_equal(g, g2), "backward is not deterministic"
 
