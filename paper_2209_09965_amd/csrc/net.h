@@ -86,7 +86,9 @@ struct TrainPlan {
   Plan f;
   size_t g[kNumTensors];  // FP32 gradient of each activation tensor (not T_IN)
   size_t tmp;             // FP32 [px at level][Ci] of the current layer
-  size_t dz;              // BF16 masked gradient of the current layer output
+  size_t dz, dz2;         // BF16 masked gradient of the current layer output
+                          // (two buffers: an input-gradient conv reads one
+                          // and stores the next layer's into the other)
   size_t target;          // FP32 copy of the target RGB (loss)
   size_t dout;            // FP32 d loss / d out [n h w 3]
   size_t ssim;            // SSIM maps: 5 filtered row maps + 3 partial maps

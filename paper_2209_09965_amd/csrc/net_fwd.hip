@@ -436,6 +436,8 @@ fv_status launch_conv(const ConvArgs& args, int nb, hipStream_t s) {
                 (long long)bo);
   a.out_bytes = (uint32_t)bo;
   a.pool_bytes = (uint32_t)bp;
+  if (a.gate && (E::kBytes != 2 || a.out_fp32 || a.pool_out || a.relu || a.absmax))
+    return fail(FV_ERR_UNSUPPORTED, "conv: a gated output is a plain BF16 store");
   auto magic = [](uint32_t d) { return d > 1 ? (uint32_t)(((uint64_t)1 << 32) / d + 1) : 0u; };
   if (a.up0 && (a.c0 % 8 || a.c0 < 16 || (a.h | a.w) & 1))
     return fail(FV_ERR_UNSUPPORTED, "conv: upsampled source with %d channels at %d x %d", a.c0,

@@ -252,6 +252,11 @@ struct ConvArgs {
   float* absmax;        // per-tensor running maximum (calibration), or null
   uint8_t* pool_out;    // 2x2 average of the stored output (half resolution,
                         // out_ch stride), or null
+  // BF16 only: the stored value is v * [gate > 0], gate being a BF16 tensor
+  // laid out as the output (out_ch stride): an input-gradient conv storing
+  // the next layer's masked output gradient (the ReLU derivative of the
+  // forward activation gate), or null
+  const uint8_t* gate;
   uint32_t out_bytes, pool_bytes;  // set by launch_conv (buffer-store range checks)
   uint32_t src0_bytes, src1_bytes, src2_bytes;  // sizes for the buffer-load range checks
   // set by launch_conv: e / ng == umulhi(e, gmagic) for the ng fill-item
@@ -831,6 +836,7 @@ __global__ void __launch_bounds__(256)
     const int ob = a.out_fp32 ? 4 : E::kBytes;
     const int cpad = (a.co + 3) & ~3;
     const __amdgpu_buffer_rsrc_t ro = make_rsrc(a.out, a.out_bytes);
+    const __amdgpu_buffer_rsrc_t rg = make_rsrc(a.gate ? a.gate : a.out, a.out_bytes);
     const int rowb = a.w * a.out_ch * ob;
     const int vo = x < a.w ? (((b * a.h + yb) * a.w + x) * a.out_ch + 4 * grp) * ob : kOutside;
     const bool pool = R >= 2 && a.pool_out;
@@ -874,6 +880,18 @@ __global__ void __launch_bounds__(256)
                                  f4{v[0], v[1], v[2], v[3]}),
               ro, vn, rr * rowb, 0);
         } else {
+          if constexpr (E::kBytes == 2) {
+            if (a.gate) {
+              const uint2 gb = __builtin_bit_cast(
+                  uint2, __builtin_amdgcn_raw_buffer_load_b64(rg, vn, rr * rowb, 0));
+              const uint32_t gw[2] = {gb.x, gb.y};
+#pragma unroll
+              for (int i = 0; i < 4; ++i) {
+                const float y = bf16_bits_to_f(i & 1 ? gw[i >> 1] >> 16 : gw[i >> 1] & 0xffffu);
+                v[i] = y > 0.f ? v[i] : 0.f;
+              }
+            }
+          }
           E::bstore4(ro, vn, rr * rowb, v);
         }
       }

@@ -7,6 +7,7 @@
 // pixel chunk reduced in a fixed order, so a step is deterministic), the
 // bilinear upsampling and the average pooling; Adam on FP32 master weights.
 #include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "net.h"
@@ -63,6 +64,8 @@ TrainPlan make_train_plan(int n, int h, int w) {
   t.tmp = off;
   off += al(tmp);
   t.dz = off;
+  off += al(dz);
+  t.dz2 = off;
   off += al(dz);
   t.target = off;
   off += al((size_t)n * h * w * 3 * 4);
@@ -953,7 +956,9 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
   const int64_t npx = (int64_t)p.n * p.h * p.w;
   float* grad = n->grad;
   float* tmp = (float*)(ws + tp.tmp);
-  uint8_t* dz = ws + tp.dz;
+  uint8_t* dz = ws + tp.dz;       // masked output gradient of layer l
+  uint8_t* dz_next = ws + tp.dz2;  // of layer l - 1, when the dgrad stores it
+  bool dz_ready = false;           // dz already holds layer l's masked gradient
   float* part = (float*)(ws + tp.part);
   auto G = [&](int t) { return (float*)(ws + tp.g[t]); };
   // heads
@@ -969,9 +974,12 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
     const int* io = kLayerIO[l];
     const int hh = p.h >> L.level, ww = p.w >> L.level;
     const int64_t px = (int64_t)p.n * hh * ww;
-    // ReLU derivative, BF16 copy of the output gradient
-    k_relu_mask<<<nblk(px * L.co / 8), 256, 0, s>>>(G(io[2]), ws + p.t[io[2]], dz,
-                                                    px * L.co / 8);
+    // ReLU derivative, BF16 copy of the output gradient (unless the input
+    // gradient conv of layer l + 1 stored it)
+    if (!dz_ready)
+      k_relu_mask<<<nblk(px * L.co / 8), 256, 0, s>>>(G(io[2]), ws + p.t[io[2]], dz,
+                                                      px * L.co / 8);
+    dz_ready = false;
     // weight + bias gradient
     ConvArgs in{};
     in.src0 = ws + p.t[io[0]];
@@ -1014,7 +1022,20 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
     a.absmax = nullptr;
     const bool concat = io[1] >= 0;
     a.out = (uint8_t*)(concat ? tmp : G(io[0]));
+    // The input is layer l - 1's output with no other consumer: the conv
+    // stores that layer's masked BF16 gradient directly (the same bits as
+    // the FP32 gradient through k_relu_mask).
+    const bool gated = !concat && io[0] == kLayerIO[l - 1][2];
+    if (gated) {
+      a.out_fp32 = 0;
+      a.out = dz_next;
+      a.gate = ws + p.t[io[0]];
+    }
     if ((st = launch_conv<BF16>(a, nblocks_of(L.c0 + L.c1), s)) != FV_OK) return st;
+    if (gated) {
+      std::swap(dz, dz_next);
+      dz_ready = true;
+    }
     if (concat) {
       const int hl = hh / 2, wl = ww / 2;
       k_upsample_bwd<<<nblk((int64_t)p.n * hl * wl * L.c0), 256, 0, s>>>(

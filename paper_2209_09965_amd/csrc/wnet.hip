@@ -32,6 +32,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "net.h"
@@ -693,7 +694,7 @@ struct TPlan {
   Plan f;
   size_t wke[4], wkd[3], av[3], bl[3];
   size_t g[kTensors];
-  size_t tmp, dz, w0;
+  size_t tmp, dz, dz2, w0;
   size_t dja, djb, dje[3], db, du, dwk, dzk;
   size_t kpart, part, part2;
   size_t out, dout, tgt, ssim, red;
@@ -732,6 +733,7 @@ TPlan make_tplan(int n, int h, int w, const Layer* LT) {
   }
   t.tmp = take(tmp);
   t.dz = take(dz);
+  t.dz2 = take(dz);
   t.w0 = take((size_t)(9 * kL[0].c0 * kL[0].co + kL[0].co) * 4);
   t.dja = take(px(0) * 3 * 4);
   t.djb = take(px(0) * 3 * 4);
@@ -875,7 +877,9 @@ fv_status backward(fv_wnet* n, const float* dloss_dout, int views, int width, in
   if (st != FV_OK) return st;
   // ---- D, last conv first
   float* tmp = (float*)(ws + tp.tmp);
-  uint8_t* dz = ws + tp.dz;
+  uint8_t* dz = ws + tp.dz;       // masked output gradient of conv l
+  uint8_t* dz_next = ws + tp.dz2;  // of conv l - 1, when the dgrad stores it
+  bool dz_ready = false;
   float* part = (float*)(ws + tp.part);
   float* part2 = (float*)(ws + tp.part2);
   for (int l = kConv - 1; l >= 0; --l) {
@@ -884,7 +888,8 @@ fv_status backward(fv_wnet* n, const float* dloss_dout, int views, int width, in
     const int64_t m = px(L.level);
     const bool feed = state && kFeed[l] >= 0;  // reads a fed-back state
     const int ci = L.c0 + L.c1;                 // the channels whose gradient flows on
-    net::launch_relu_mask(G(kIO[l][2]), ws + p.t[kIO[l][2]], dz, m * L.co / 8, s);
+    if (!dz_ready) net::launch_relu_mask(G(kIO[l][2]), ws + p.t[kIO[l][2]], dz, m * L.co / 8, s);
+    dz_ready = false;
     ConvArgs in{};
     in.src0 = ws + p.t[kIO[l][0]];
     in.src1 = kIO[l][1] >= 0 ? ws + p.t[kIO[l][1]] : nullptr;
@@ -934,17 +939,29 @@ fv_status backward(fv_wnet* n, const float* dloss_dout, int views, int width, in
     a.out_fp32 = 1;
     a.out_ch = ci;
     const bool concat = kIO[l][1] >= 0;
-    uint8_t* obase = (uint8_t*)(concat ? tmp : G(kIO[l][0]));
-    // in groups of images whose FP32 output stays below the conv's 2 GiB
-    // buffer range (the conv works image by image)
-    const int64_t img_out = (int64_t)hh * ww * ci * 4, img_in = (int64_t)hh * ww * L.co * 2;
+    // The input is conv l - 1's output with no other consumer (not one of
+    // K's inputs): the conv stores that conv's masked BF16 gradient directly,
+    // the same bits as the FP32 gradient through the ReLU mask.
+    const bool gated = !concat && kIO[l][0] == kIO[l - 1][2];
+    uint8_t* obase = gated ? dz_next : (uint8_t*)(concat ? tmp : G(kIO[l][0]));
+    const uint8_t* gbase = ws + p.t[kIO[l][0]];
+    if (gated) a.out_fp32 = 0;
+    // in groups of images whose output stays below the conv's 2 GiB buffer
+    // range (the conv works image by image)
+    const int64_t img_out = (int64_t)hh * ww * ci * (gated ? 2 : 4);
+    const int64_t img_in = (int64_t)hh * ww * L.co * 2;
     const int grp = (int)std::max<int64_t>(
         1, std::min<int64_t>(views, ((((int64_t)1) << 31) - 64 - 1) / img_out));
     for (int b0 = 0; b0 < views; b0 += grp) {
       a.n = std::min(grp, views - b0);
       a.src0 = dz + b0 * img_in;
       a.out = obase + b0 * img_out;
+      a.gate = gated ? gbase + b0 * img_out : nullptr;
       if ((st = net::launch_conv<BF16>(a, net::nblocks_of(ci), s)) != FV_OK) return st;
+    }
+    if (gated) {
+      std::swap(dz, dz_next);
+      dz_ready = true;
     }
     if (concat) {
       // the upsampled source (e3b, d2b, d1b) is also one of K's inputs,
