@@ -733,25 +733,27 @@ def training_step_bench(args, wl):
                      "duration": "HIP events around fv_train_step, %.3f ms" % avg},
     }
     net.close()
-    # the two-stage W-Net's training step on the same batch (fv_wnet_train_step)
-    wn = b.WNet(synthetic.wnet_init(0))
-    wws = torch.empty(wn.train_workspace_bytes(B, W, H), dtype=torch.uint8, device=dev)
-    for _ in range(max(1, args.warmup)):
-        wn.train_step(fr, mk, dp, fr, B, W, H, 1e-4, loss3, wws)
-    torch.cuda.synchronize()
-    wev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
-    for e in wev:
-        e[0].record()
-        wn.train_step(fr, mk, dp, fr, B, W, H, 1e-4, loss3, wws)
-        e[1].record()
-    torch.cuda.synchronize()
-    wms = sum(e[0].elapsed_time(e[1]) for e in wev) / len(wev)
-    wflop = 3 * 2 * WNET_MACS_PER_PX * B * W * H
-    out["wnet_train_step"] = {"ms_per_step": round(wms, 3),
-                              "achieved_tflops": round(wflop / (wms * 1e-3) / 1e12, 1),
-                              "model": "3 x 2 x 223660.5 FLOP/px (forward, input and weight "
-                                       "gradients) x %d px" % (B * W * H)}
-    wn.close()
+    if not args.no_wnet:
+        # the two-stage W-Net's training step on the same batch (fv_wnet_train_step)
+        wn = b.WNet(synthetic.wnet_init(0))
+        wws = torch.empty(wn.train_workspace_bytes(B, W, H), dtype=torch.uint8, device=dev)
+        for _ in range(max(1, args.warmup)):
+            wn.train_step(fr, mk, dp, fr, B, W, H, 1e-4, loss3, wws)
+        torch.cuda.synchronize()
+        wev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)]
+               for _ in range(args.steps)]
+        for e in wev:
+            e[0].record()
+            wn.train_step(fr, mk, dp, fr, B, W, H, 1e-4, loss3, wws)
+            e[1].record()
+        torch.cuda.synchronize()
+        wms = sum(e[0].elapsed_time(e[1]) for e in wev) / len(wev)
+        wflop = 3 * 2 * WNET_MACS_PER_PX * B * W * H
+        out["wnet_train_step"] = {"ms_per_step": round(wms, 3),
+                                  "achieved_tflops": round(wflop / (wms * 1e-3) / 1e12, 1),
+                                  "model": "3 x 2 x 223660.5 FLOP/px (forward, input and weight "
+                                           "gradients) x %d px" % (B * W * H)}
+        wn.close()
     print(json.dumps(out), flush=True)
 
 

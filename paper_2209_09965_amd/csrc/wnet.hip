@@ -432,79 +432,176 @@ __global__ void __launch_bounds__(256) k_blend_bwd(const float* __restrict__ je,
   dz[p * (kTaps + 1) + kTaps] = da * av * (1.0f - av);
 }
 
-// 1x1 layer backward, input side: dH[p][c] (+)= sum_t W[t][c] dz[p][t].
+// 1x1 layer backward, input side: dH[p][c] (+)= sum_t W[t][c] dz[p][t],
+// summed over t in order.  A thread computes 4 consecutive channels of one
+// pixel, so a wave loads and stores whole cache lines of dH; the dz rows of
+// the block's pixels are staged in LDS with the weights.  C % 4 == 0.
 __global__ void __launch_bounds__(256) k_predict_bwd_h(const float* __restrict__ dz, int T,
                                                        const float* __restrict__ W, int C,
                                                        int64_t npx, float* __restrict__ dh,
                                                        int acc) {
-  extern __shared__ float sw[];  // W [T][C]
+  extern __shared__ float sm[];  // W [T][C], then dz [pixels of the block][T]
+  float* sw = sm;
+  float* sd = sm + T * C;
+  const int G = C >> 2;
+  const int64_t e0 = (int64_t)blockIdx.x * 256, p0 = e0 / G;
+  const int np = (int)(min((e0 + 255) / G, npx - 1) - p0 + 1);
   for (int i = threadIdx.x; i < T * C; i += 256) sw[i] = W[i];
+  for (int i = threadIdx.x; i < np * T; i += 256) sd[i] = dz[p0 * T + i];
   __syncthreads();
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t e = e0 + threadIdx.x, p = e / G;
   if (p >= npx) return;
-  float g[kTaps + 1];
-  for (int t = 0; t < T; ++t) g[t] = dz[p * T + t];
-  for (int c = 0; c < C; ++c) {
-    float v = 0.f;
-    for (int t = 0; t < T; ++t) v = fmaf(sw[t * C + c], g[t], v);
-    dh[p * C + c] = acc ? dh[p * C + c] + v : v;
+  const int c = (int)(e - p * G) * 4;
+  const float* g = sd + (p - p0) * T;
+  float v0 = 0.f, v1 = 0.f, v2 = 0.f, v3 = 0.f;
+  for (int t = 0; t < T; ++t) {
+    const float gt = g[t];
+    const float4 w = *(const float4*)(sw + t * C + c);
+    v0 = fmaf(w.x, gt, v0);
+    v1 = fmaf(w.y, gt, v1);
+    v2 = fmaf(w.z, gt, v2);
+    v3 = fmaf(w.w, gt, v3);
   }
+  float4* o = (float4*)(dh + p * C + c);
+  if (acc) {
+    const float4 d = *o;
+    v0 += d.x;
+    v1 += d.y;
+    v2 += d.z;
+    v3 += d.w;
+  }
+  *o = make_float4(v0, v1, v2, v3);
 }
 
 // 1x1 layer backward, weight side: per pixel chunk, part[t][c] = sum_p
-// dz[p][t] H[p][c] and part[t][C] = sum_p dz[p][t]; 64 pixels at a time in
-// LDS, up to 10 outputs per thread.
-constexpr int kPredChunkOut = 10;
+// dz[p][t] H[p][c] and part[t][C] = sum_p dz[p][t], each summed over the
+// chunk's pixels in order.  64 pixels at a time in LDS (dz rows padded to an
+// even Tp, H rows with the ones column and zeros to a multiple of 4); a
+// thread owns tiles of 2 t x 4 outputs, one 8-byte and one 16-byte LDS read
+// per pixel for 8 FMAs.  T <= 26, C % 8 == 0, C <= 96.
+constexpr int kPwTp = 26, kPwKp = 100;
 __global__ void __launch_bounds__(256) k_predict_wgrad(const float* __restrict__ dz, int T,
                                                        const __bf16* __restrict__ hb, int C,
                                                        int64_t npx, int chunks,
                                                        float* __restrict__ part) {
-  __shared__ float sd[64 * (kTaps + 1)];
-  __shared__ float sh[64 * 97];
+  __shared__ __attribute__((aligned(16))) float sd[64 * kPwTp];
+  __shared__ __attribute__((aligned(16))) float sh[64 * kPwKp];
   const int chunk = blockIdx.x, tid = threadIdx.x;
   const int64_t p0 = npx * chunk / chunks, p1 = npx * (chunk + 1) / chunks;
-  const int C1 = C + 1, nout = T * C1;
-  float acc[kPredChunkOut];
-  for (int j = 0; j < kPredChunkOut; ++j) acc[j] = 0.f;
+  const int Tp = (T + 1) & ~1, C1 = C + 1, Kp = (C1 + 3) & ~3, G8 = C >> 3, X = Kp - C;
+  const int nkq = Kp >> 2, ntiles = (Tp >> 1) * nkq;
   const uint16_t* h16 = (const uint16_t*)hb;
+  // this thread's fill items, the same in every batch: dz entries (pixel,
+  // offset in the batch's rows or -1 for padding), H groups of 8 channels,
+  // and one entry of the ones / zero columns
+  constexpr int kD = (64 * kPwTp + 255) / 256, kH = (64 * 12 + 255) / 256;
+  int dpp[kD], dsrc[kD];
+#pragma unroll
+  for (int u = 0; u < kD; ++u) {
+    const int e = tid + 256 * u, pp = e / Tp, t = e - pp * Tp;
+    dpp[u] = pp;
+    dsrc[u] = e < 64 * Tp && t < T ? pp * T + t : -1;
+  }
+  const int xpp = tid / X, xk = C + tid - xpp * X;
+  float acc[2][8];
+#pragma unroll
+  for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[jj][i] = 0.f;
   for (int64_t base = p0; base < p1; base += 64) {
     const int cnt = (int)min((int64_t)64, p1 - base);
     __syncthreads();
-    for (int e = tid; e < 64 * T; e += 256) {
-      const int pp = e / T;
-      sd[e] = pp < cnt ? dz[(base + pp) * T + e % T] : 0.f;
+#pragma unroll
+    for (int u = 0; u < kD; ++u) {
+      const int e = tid + 256 * u;
+      if (e < 64 * Tp)
+        sd[e] = dsrc[u] >= 0 && dpp[u] < cnt ? dz[base * T + dsrc[u]] : 0.f;
     }
-    for (int e = tid; e < 64 * C1; e += 256) {
-      const int pp = e / C1, k = e % C1;
-      sh[e] = pp < cnt ? (k < C ? net::bf16_bits_to_f(h16[(base + pp) * C + k]) : 1.0f) : 0.f;
+#pragma unroll
+    for (int u = 0; u < kH; ++u) {
+      const int i = tid + 256 * u;
+      if (i >= 64 * G8) break;
+      const int pp = i / G8, g = i - pp * G8;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (pp < cnt) v = *(const uint4*)(h16 + (base + pp) * C + 8 * g);
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+      float f[8];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        f[2 * q] = net::bf16_bits_to_f(w[q] & 0xffffu);
+        f[2 * q + 1] = net::bf16_bits_to_f(w[q] >> 16);
+      }
+      float4* d = (float4*)(sh + pp * Kp + 8 * g);
+      d[0] = make_float4(f[0], f[1], f[2], f[3]);
+      d[1] = make_float4(f[4], f[5], f[6], f[7]);
     }
+    if (tid < 64 * X) sh[xpp * Kp + xk] = xk == C && xpp < cnt ? 1.0f : 0.f;
     __syncthreads();
-    for (int j = 0; j < kPredChunkOut; ++j) {
-      const int o = tid + 256 * j;
-      if (o >= nout) break;
-      const int t = o / C1, k = o % C1;
-      float sacc = acc[j];
-#pragma unroll 8
-      for (int pp = 0; pp < 64; ++pp) sacc = fmaf(sd[pp * T + t], sh[pp * C1 + k], sacc);
-      acc[j] = sacc;
+#pragma unroll
+    for (int jj = 0; jj < 2; ++jj) {
+      const int j = tid + 256 * jj;
+      if (j >= ntiles) break;
+      const int tp = j / nkq, kq = j - tp * nkq;
+      float a[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a[i] = acc[jj][i];
+      const float2* d2 = (const float2*)sd + tp;
+      const float4* h4 = (const float4*)sh + kq;
+#pragma unroll 4
+      for (int pp = 0; pp < 64; ++pp) {
+        const float2 d = d2[pp * (Tp >> 1)];
+        const float4 h = h4[pp * nkq];
+        a[0] = fmaf(d.x, h.x, a[0]);
+        a[1] = fmaf(d.x, h.y, a[1]);
+        a[2] = fmaf(d.x, h.z, a[2]);
+        a[3] = fmaf(d.x, h.w, a[3]);
+        a[4] = fmaf(d.y, h.x, a[4]);
+        a[5] = fmaf(d.y, h.y, a[5]);
+        a[6] = fmaf(d.y, h.z, a[6]);
+        a[7] = fmaf(d.y, h.w, a[7]);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) acc[jj][i] = a[i];
     }
   }
-  for (int j = 0; j < kPredChunkOut; ++j) {
-    const int o = tid + 256 * j;
-    if (o < nout) part[(int64_t)chunk * nout + o] = acc[j];
+  const int nout = T * C1;
+#pragma unroll
+  for (int jj = 0; jj < 2; ++jj) {
+    const int j = tid + 256 * jj;
+    if (j >= ntiles) break;
+    const int tp = j / nkq, kq = j - tp * nkq;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int t = 2 * tp + (i >> 2), k = 4 * kq + (i & 3);
+      if (t < T && k < C1) part[(int64_t)chunk * nout + t * C1 + k] = acc[jj][i];
+    }
   }
 }
 
-// Sum of the chunk partials (in chunk order) into the layer's gradient:
-// weight [T][C] then bias [T].
+constexpr int kPredSlices = 32;  // first-stage slices of the chunk partials
+
+// The chunk partials summed in a fixed order (deterministic): slice sl of
+// the chunks first, then the slices in order (k_predict_reduce2).
 __global__ void __launch_bounds__(256) k_predict_reduce(const float* __restrict__ part,
-                                                        int chunks, int T, int C,
-                                                        float* __restrict__ grad) {
-  const int o = blockIdx.x * 256 + threadIdx.x;
-  const int C1 = C + 1;
-  if (o >= T * C1) return;
+                                                        int chunks, int nout,
+                                                        float* __restrict__ part2) {
+  const int o = blockIdx.x * 256 + threadIdx.x, sl = blockIdx.y;
+  if (o >= nout) return;
+  const int c0 = chunks * sl / kPredSlices, c1 = chunks * (sl + 1) / kPredSlices;
   float s = 0.f;
-  for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * T * C1 + o];
+  for (int c = c0; c < c1; ++c) s += part[(int64_t)c * nout + o];
+  part2[sl * nout + o] = s;
+}
+
+// ... then the slices, stored in the parameter order (weights [t][c], then
+// the T biases)
+__global__ void __launch_bounds__(256) k_predict_reduce2(const float* __restrict__ part2, int T,
+                                                         int C, float* __restrict__ grad) {
+  const int o = blockIdx.x * 256 + threadIdx.x;
+  const int C1 = C + 1, nout = T * C1;
+  if (o >= nout) return;
+  float s = 0.f;
+  for (int sl = 0; sl < kPredSlices; ++sl) s += part2[sl * nout + o];
   const int t = o / C1, k = o % C1;
   grad[k < C ? t * C + k : T * C + t] = s;
 }
@@ -745,6 +842,8 @@ TPlan make_tplan(int n, int h, int w, const Layer* LT) {
   t.kchunks = (int)std::max<int64_t>(1, std::min<int64_t>(1024, (int64_t)px(0) / 256));
   t.kpart = take((size_t)t.kchunks * (kTaps + 1) * 97 * 4);
   t.part = take(part);
+  // (also the 1x1 layers' first-stage sums: up to 26 x 97 outputs)
+  part2 = std::max(part2, (size_t)kPredSlices * (kTaps + 1) * 97 * 4);
   t.part2 = take(part2);
   t.out = take(px(0) * 3 * 4);
   t.dout = take(px(0) * 3 * 4);
@@ -801,10 +900,17 @@ fv_status predict_backward(const fv_wnet* n, const TPlan& tp, uint8_t* ws, int l
   const float* W = n->master + param_offset(n->L, layer);
   float* part = (float*)(ws + tp.kpart);
   const int chunks = (int)std::max<int64_t>(1, std::min<int64_t>(tp.kchunks, m / 64));
-  k_predict_bwd_h<<<blocks_of(m), 256, T * L.ci * 4, s>>>(dz, T, W, L.ci, m, gh, acc);
+  if (T > kPwTp || L.ci % 8 || L.ci + 1 > kPwKp)
+    return fail(FV_ERR_UNSUPPORTED, "wnet: 1x1 layer %d -> %d", L.ci, T);
+  const int groups = L.ci / 4;
+  const size_t lds = ((size_t)T * L.ci + (size_t)(256 / groups + 2) * T) * 4;
+  k_predict_bwd_h<<<blocks_of(m * groups), 256, lds, s>>>(dz, T, W, L.ci, m, gh, acc);
   k_predict_wgrad<<<chunks, 256, 0, s>>>(dz, T, (const __bf16*)hten, L.ci, m, chunks, part);
-  k_predict_reduce<<<blocks_of((int64_t)T * (L.ci + 1)), 256, 0, s>>>(
-      part, chunks, T, L.ci, n->grad + param_offset(n->L, layer));
+  const int nout = T * (L.ci + 1);
+  float* part2 = (float*)(ws + tp.part2);
+  k_predict_reduce<<<dim3(blocks_of(nout), kPredSlices), 256, 0, s>>>(part, chunks, nout, part2);
+  k_predict_reduce2<<<blocks_of(nout), 256, 0, s>>>(part2, T, L.ci,
+                                                    n->grad + param_offset(n->L, layer));
   return launch_status("wnet: 1x1 backward");
 }
 
