@@ -311,25 +311,13 @@ __global__ void __launch_bounds__(256) k_rgb_of_rgba(const float4* __restrict__ 
 
 // ----------------------------------------------------------- heads backward
 
-// Per pixel: d w_k = sum_c dout_c(p) O_d,c(clamp(p + delta_k)); d logits by
-// the softmax Jacobian; d O_d(p) gathered from every pixel whose clamped tap
-// lands on p; d H_d = W_heads^T [d O_d; d logits].  Writes d28 = [d O_d,
-// d logits] (for the heads' weight gradient) and the FP32 gradient of H_d.
-__global__ void __launch_bounds__(256) k_heads_bwd(const float* __restrict__ dout,
-                                                   const float* __restrict__ od,
-                                                   const float* __restrict__ wk, int n, int h,
-                                                   int w, const float* __restrict__ params,
-                                                   int64_t off_hd, int64_t off_hk,
-                                                   float* __restrict__ d28,
-                                                   float* __restrict__ gh) {
-  // the BF16-rounded head weights (the forward's), [28 outputs][32 inputs]
-  __shared__ float sw[28 * 32];
-  for (int i = threadIdx.x; i < 28 * 32; i += 256)
-    sw[i] = (float)(__bf16)(i < 3 * 32 ? params[off_hd + i] : params[off_hk + i - 3 * 32]);
-  __syncthreads();
-  const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t npx = (int64_t)n * h * w;
-  if (p >= npx) return;
+// The 28 head-input gradients of pixel p: the direct head's (the gradient of
+// O_d at p, gathered over every pixel whose clamped 5x5 tap lands on p) and
+// the 25 kernel logits' (softmax backward of dw = dout . O_d(tap)).
+__device__ __forceinline__ void head_grad28(const float* __restrict__ dout,
+                                            const float* __restrict__ od,
+                                            const float* __restrict__ wk, int h, int w,
+                                            int64_t p, float d[28]) {
   const int x = (int)(p % w);
   const int64_t r = p / w;
   const int y = (int)(r % h), b = (int)(r / h);
@@ -345,7 +333,6 @@ __global__ void __launch_bounds__(256) k_heads_bwd(const float* __restrict__ dou
       wl[k] = wk[p * 25 + k];
       dot = fmaf(wl[k], dw[k], dot);
     }
-  float d[28];
   for (int k = 0; k < 25; ++k) d[3 + k] = wl[k] * (dw[k] - dot);
   // d O_d(p): every pixel q whose clamped tap k lands on p, in the order
   // (dy, dx, qy, qx); per axis the q are p - d inside the image, widened to
@@ -369,61 +356,134 @@ __global__ void __launch_bounds__(256) k_heads_bwd(const float* __restrict__ dou
   d[0] = a0;
   d[1] = a1;
   d[2] = a2;
-  for (int j = 0; j < 28; ++j) d28[p * 28 + j] = d[j];
-  for (int k = 0; k < 32; ++k) {
-    float sacc = 0.f;
-    for (int c = 0; c < 28; ++c) sacc = fmaf(sw[c * 32 + k], d[c], sacc);
-    gh[p * 32 + k] = sacc;
-  }
 }
 
+// Per pixel: d w_k = sum_c dout_c(p) O_d,c(clamp(p + delta_k)); d logits by
+// the softmax Jacobian; d O_d(p) gathered from every pixel whose clamped tap
+// lands on p; d H_d = W_heads^T [d O_d; d logits].  Writes d28 = [d O_d,
+// d logits] (for the heads' weight gradient) and the FP32 gradient of H_d.
+__global__ void __launch_bounds__(256) k_heads_bwd(const float* __restrict__ dout,
+                                                   const float* __restrict__ od,
+                                                   const float* __restrict__ wk, int n, int h,
+                                                   int w, const float* __restrict__ params,
+                                                   int64_t off_hd, int64_t off_hk,
+                                                   float* __restrict__ d28,
+                                                   float* __restrict__ gh) {
+  // the BF16-rounded head weights (the forward's), [28 outputs][32 inputs]
+  __shared__ float sw[28 * 32];
+  // the block's outputs, staged so that they leave in whole 16-byte units:
+  // d28 in its global layout (28 floats a pixel), then gh (32 floats a
+  // pixel, rows padded to 36 against bank conflicts)
+  __shared__ __attribute__((aligned(16))) float so[256 * 36];
+  for (int i = threadIdx.x; i < 28 * 32; i += 256)
+    sw[i] = (float)(__bf16)(i < 3 * 32 ? params[off_hd + i] : params[off_hk + i - 3 * 32]);
+  __syncthreads();
+  const int64_t p0 = (int64_t)blockIdx.x * 256, p = p0 + threadIdx.x;
+  const int64_t npx = (int64_t)n * h * w;
+  const int np = (int)min((int64_t)256, npx - p0);
+  float d[28];
+  if (p < npx) head_grad28(dout, od, wk, h, w, p, d);
+  else
+    for (int j = 0; j < 28; ++j) d[j] = 0.f;
+  float4* so4 = (float4*)so;
+  for (int q = 0; q < 7; ++q)
+    so4[threadIdx.x * 7 + q] = make_float4(d[4 * q], d[4 * q + 1], d[4 * q + 2], d[4 * q + 3]);
+  __syncthreads();
+  float4* o28 = (float4*)(d28 + p0 * 28);
+  for (int e = threadIdx.x; e < np * 7; e += 256) o28[e] = so4[e];
+  __syncthreads();
+  for (int k4 = 0; k4 < 8; ++k4) {
+    float v[4];
+    for (int i = 0; i < 4; ++i) {
+      float sacc = 0.f;
+      for (int c = 0; c < 28; ++c) sacc = fmaf(sw[c * 32 + 4 * k4 + i], d[c], sacc);
+      v[i] = sacc;
+    }
+    so4[threadIdx.x * 9 + k4] = make_float4(v[0], v[1], v[2], v[3]);
+  }
+  __syncthreads();
+  float4* og = (float4*)(gh + p0 * 32);
+  for (int e = threadIdx.x; e < np * 8; e += 256) og[e] = so4[(e >> 3) * 9 + (e & 7)];
+}
+
+
 // Heads weight gradient partials: per chunk of pixels, d W[q][k] = sum d28[q] h[k]
-// and d b[q] = sum d28[q] (28 x 33 outputs); pixels are staged 64 at a time
-// in LDS and every thread owns up to four outputs.
+// and d b[q] = sum d28[q] (28 x 33 outputs), each summed over the chunk's
+// pixels in order.  Pixels are staged 64 at a time in LDS (h rows with the
+// ones column, padded with zeros to 36); a thread owns 4 consecutive
+// outputs of one q: one 4-byte and one 16-byte LDS read per pixel for 4
+// FMAs (28 x 9 = 252 tiles).
 __global__ void __launch_bounds__(256) k_heads_wgrad(const float* __restrict__ d28,
                                                      const uint8_t* __restrict__ hdec,
                                                      int64_t npx, int chunks,
                                                      float* __restrict__ part) {
-  __shared__ float sd[64 * 28];
-  __shared__ float shv[64 * 33];
+  constexpr int Kp = 36, NKQ = Kp / 4;
+  __shared__ __attribute__((aligned(16))) float sd[64 * 28];
+  __shared__ __attribute__((aligned(16))) float shv[64 * Kp];
   const int chunk = blockIdx.x, tid = threadIdx.x;
   const int64_t p0 = npx * chunk / chunks, p1 = npx * (chunk + 1) / chunks;
+  const int qq = tid / NKQ, kq = tid - qq * NKQ;  // this thread's tile (tid < 252)
   float acc[4] = {0.f, 0.f, 0.f, 0.f};
   const uint16_t* h16 = (const uint16_t*)hdec;
+  // fill items: pixel tid / 4's channel group tid % 4 (8 channels), and one
+  // entry of columns 32..35 (ones for the bias, then zeros)
+  const int hpp = tid >> 2, hg = tid & 3;
+  const int xpp = tid >> 2, xk = 32 + (tid & 3);
   for (int64_t base = p0; base < p1; base += 64) {
     const int cnt = (int)min((int64_t)64, p1 - base);
     __syncthreads();
-    for (int e = tid; e < 64 * 28; e += 256) {
-      const int pp = e / 28;
-      sd[e] = pp < cnt ? d28[(base + pp) * 28 + e % 28] : 0.f;
-    }
-    for (int e = tid; e < 64 * 33; e += 256) {
-      const int pp = e / 33, k = e % 33;
-      shv[e] = pp < cnt ? (k < 32 ? bf16_bits_to_f(h16[(base + pp) * 32 + k]) : 1.0f) : 0.f;
+    for (int e = tid; e < 64 * 28; e += 256) sd[e] = e < cnt * 28 ? d28[base * 28 + e] : 0.f;
+    {
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (hpp < cnt) v = *(const uint4*)(h16 + (base + hpp) * 32 + 8 * hg);
+      const uint32_t wv[4] = {v.x, v.y, v.z, v.w};
+      float f[8];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        f[2 * i] = bf16_bits_to_f(wv[i] & 0xffffu);
+        f[2 * i + 1] = bf16_bits_to_f(wv[i] >> 16);
+      }
+      float4* dst = (float4*)(shv + hpp * Kp + 8 * hg);
+      dst[0] = make_float4(f[0], f[1], f[2], f[3]);
+      dst[1] = make_float4(f[4], f[5], f[6], f[7]);
+      shv[xpp * Kp + xk] = xk == 32 && xpp < cnt ? 1.0f : 0.f;
     }
     __syncthreads();
-    for (int j = 0; j < 4; ++j) {
-      const int o = tid + 256 * j;
-      if (o >= 28 * 33) break;
-      const int qq = o / 33, k = o % 33;
-      float sacc = acc[j];
+    if (tid < 28 * NKQ) {
+      float a0 = acc[0], a1 = acc[1], a2 = acc[2], a3 = acc[3];
+      const float4* h4 = (const float4*)shv + kq;
 #pragma unroll 8
-      for (int pp = 0; pp < 64; ++pp) sacc = fmaf(sd[pp * 28 + qq], shv[pp * 33 + k], sacc);
-      acc[j] = sacc;
+      for (int pp = 0; pp < 64; ++pp) {
+        const float d = sd[pp * 28 + qq];
+        const float4 hv = h4[pp * NKQ];
+        a0 = fmaf(d, hv.x, a0);
+        a1 = fmaf(d, hv.y, a1);
+        a2 = fmaf(d, hv.z, a2);
+        a3 = fmaf(d, hv.w, a3);
+      }
+      acc[0] = a0;
+      acc[1] = a1;
+      acc[2] = a2;
+      acc[3] = a3;
     }
   }
-  for (int j = 0; j < 4; ++j) {
-    const int o = tid + 256 * j;
-    if (o < 28 * 33) part[(int64_t)chunk * 28 * 33 + o] = acc[j];
+  if (tid < 28 * NKQ) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int k = 4 * kq + i;
+      if (k < 33) part[(int64_t)chunk * 28 * 33 + qq * 33 + k] = acc[i];
+    }
   }
 }
 
-__global__ void k_heads_reduce(const float* __restrict__ part, int chunks, int64_t off_hd,
-                               int64_t off_hk, float* __restrict__ grad) {
+// The heads' gradient: the first-stage sums of the chunk partials (slices
+// of chunks, by k_wgrad_reduce) summed in slice order, into the parameters.
+__global__ void k_heads_reduce(const float* __restrict__ part2, int64_t off_hd, int64_t off_hk,
+                               float* __restrict__ grad) {
   const int o = blockIdx.x * 256 + threadIdx.x;
   if (o >= 28 * 33) return;
   float s = 0.f;
-  for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * 28 * 33 + o];
+  for (int sl = 0; sl < kReduceSlices; ++sl) s += part2[sl * 28 * 33 + o];
   const int qq = o / 33, k = o % 33;
   if (qq < 3)
     grad[k < 32 ? off_hd + qq * 32 + k : off_hd + 96 + qq] = s;
@@ -626,67 +686,113 @@ __global__ void __launch_bounds__(256) k_wgrad_reduce2(const float* __restrict__
   grad[e] = s;
 }
 
-// gradient of a bilinear x2 upsampling (half-pixel centres, edge clamp):
-// each low-resolution pixel gathers from the output rows/columns
-// [2q-1, 2q+2] with the weights the forward blend gave it
-__device__ __forceinline__ float up_weight(int o, int q, int nlow) {
-  const float s = fminf(fmaxf((o + 0.5f) * 0.5f - 0.5f, 0.0f), (float)(nlow - 1));
-  const int i0 = (int)s, i1 = min(i0 + 1, nlow - 1);
-  const float f = s - (float)i0;
-  return (i0 == q ? 1.0f - f : 0.0f) + (i1 == q ? f : 0.0f);
+// Gradient of a bilinear x2 upsampling (half-pixel centres, edge clamp):
+// low-resolution pixel q gathers output rows (columns) 2q - 1 .. 2q + 2 with
+// the weights the forward blend gave it, 1/4, 3/4, 3/4, 1/4, where the edge
+// clamp turns the 3/4 of the first (last) sample into 1 and drops the tap
+// outside the image.  These are exactly the values of the clamped formula.
+__device__ __forceinline__ float up_tap(int j, int q, int nlow) {
+  if (j == 0) return q > 0 ? 0.25f : 0.0f;
+  if (j == 1) return q == 0 ? 1.0f : 0.75f;
+  if (j == 2) return q == nlow - 1 ? 1.0f : 0.75f;
+  return q < nlow - 1 ? 0.25f : 0.0f;
 }
 
+// V consecutive channels per thread (V = 4 when the channel counts allow
+// 16-byte accesses); taps in row, then column order
+template <int V>
 __global__ void __launch_bounds__(256) k_upsample_bwd(const float* __restrict__ gup, int ch_stride,
                                                       int c0, int n, int hl, int wl,
                                                       float* __restrict__ glow, int acc) {
-  const int64_t total = (int64_t)n * hl * wl * c0;
+  const int cg = c0 / V;
+  const int64_t total = (int64_t)n * hl * wl * cg;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= total) return;
-  const int c = (int)(e % c0);
-  const int64_t pix = e / c0;
+  const int c = (int)(e % cg) * V;
+  const int64_t pix = e / cg;
   const int qx = (int)(pix % wl);
   const int64_t r = pix / wl;
   const int qy = (int)(r % hl), b = (int)(r / hl);
   const int h = 2 * hl, w = 2 * wl;
-  float s = 0.f;
-  for (int y = 2 * qy - 1; y <= 2 * qy + 2; ++y) {
-    if (y < 0 || y >= h) continue;
-    const float wy = up_weight(y, qy, hl);
+  float s[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) s[v] = 0.f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float wy = up_tap(j, qy, hl);
     if (wy == 0.f) continue;
-    for (int x = 2 * qx - 1; x <= 2 * qx + 2; ++x) {
-      if (x < 0 || x >= w) continue;
-      const float wx = up_weight(x, qx, wl);
+    const int y = 2 * qy - 1 + j;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float wx = up_tap(i, qx, wl);
       if (wx == 0.f) continue;
-      s = fmaf(wy * wx, gup[(((int64_t)b * h + y) * w + x) * ch_stride + c], s);
+      const int x = 2 * qx - 1 + i;
+      const float* g = gup + (((int64_t)b * h + y) * w + x) * ch_stride + c;
+      float gv[V];
+      if constexpr (V == 4) {
+        const float4 t = *(const float4*)g;
+        gv[0] = t.x;
+        gv[1] = t.y;
+        gv[2] = t.z;
+        gv[3] = t.w;
+      } else {
+        gv[0] = g[0];
+      }
+#pragma unroll
+      for (int v = 0; v < V; ++v) s[v] = fmaf(wy * wx, gv[v], s[v]);
     }
   }
-  glow[e] = acc ? glow[e] + s : s;
+  float* o = glow + pix * c0 + c;
+#pragma unroll
+  for (int v = 0; v < V; ++v) o[v] = acc ? o[v] + s[v] : s[v];
 }
 
 // copy channels [c0, c0 + c1) of the transposed-conv output into the skip
-// tensor's gradient (first contribution)
+// tensor's gradient (first contribution), V channels per thread
+template <int V>
 __global__ void __launch_bounds__(256) k_split_skip(const float* __restrict__ tmp, int ch_stride,
                                                     int c0, int c1, int64_t npx,
                                                     float* __restrict__ gskip) {
+  const int cg = c1 / V;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= npx * c1) return;
-  const int c = (int)(e % c1);
-  const int64_t p = e / c1;
-  gskip[e] = tmp[p * ch_stride + c0 + c];
+  if (e >= npx * cg) return;
+  const int c = (int)(e % cg) * V;
+  const int64_t p = e / cg;
+  const float* src = tmp + p * ch_stride + c0 + c;
+  float* dst = gskip + p * c1 + c;
+  if constexpr (V == 4)
+    *(float4*)dst = *(const float4*)src;
+  else
+    *dst = *src;
 }
 
-// gradient of 2x2 average pooling, added to the pooled tensor's source
+// gradient of 2x2 average pooling, added to the pooled tensor's source, V
+// channels per thread
+template <int V>
 __global__ void __launch_bounds__(256) k_pool_bwd_add(const float* __restrict__ gp, int n, int h,
                                                       int w, int c, float* __restrict__ g) {
-  const int64_t total = (int64_t)n * h * w * c;
+  const int cg = c / V;
+  const int64_t total = (int64_t)n * h * w * cg;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= total) return;
-  const int ch = (int)(e % c);
-  const int64_t pix = e / c;
+  const int ch = (int)(e % cg) * V;
+  const int64_t pix = e / cg;
   const int x = (int)(pix % w);
   const int64_t r = pix / w;
   const int y = (int)(r % h), b = (int)(r / h);
-  g[e] += 0.25f * gp[(((int64_t)b * (h / 2) + y / 2) * (w / 2) + x / 2) * c + ch];
+  const float* src = gp + (((int64_t)b * (h / 2) + y / 2) * (w / 2) + x / 2) * c + ch;
+  float* dst = g + pix * c + ch;
+  if constexpr (V == 4) {
+    const float4 t = *(const float4*)src;
+    float4 d = *(float4*)dst;
+    d.x += 0.25f * t.x;
+    d.y += 0.25f * t.y;
+    d.z += 0.25f * t.z;
+    d.w += 0.25f * t.w;
+    *(float4*)dst = d;
+  } else {
+    *dst += 0.25f * *src;
+  }
 }
 
 __global__ void __launch_bounds__(256) k_adam(float* __restrict__ th, float* __restrict__ m,
@@ -787,19 +893,31 @@ void launch_relu_mask(const float* g, const uint8_t* y, uint8_t* dz, int64_t n8,
   k_relu_mask<<<nblk(n8), 256, 0, s>>>(g, y, dz, n8);
 }
 
+// (the 4-channel forms need 16-byte aligned tensors, which workspace
+// offsets are, and channel counts that are multiples of 4)
 void launch_upsample_bwd(const float* gup, int ch_stride, int c0, int n, int hl, int wl,
                          float* glow, int acc, hipStream_t s) {
-  k_upsample_bwd<<<nblk((int64_t)n * hl * wl * c0), 256, 0, s>>>(gup, ch_stride, c0, n, hl, wl,
-                                                                 glow, acc);
+  if (c0 % 4 == 0 && ch_stride % 4 == 0)
+    k_upsample_bwd<4><<<nblk((int64_t)n * hl * wl * c0 / 4), 256, 0, s>>>(gup, ch_stride, c0, n,
+                                                                         hl, wl, glow, acc);
+  else
+    k_upsample_bwd<1><<<nblk((int64_t)n * hl * wl * c0), 256, 0, s>>>(gup, ch_stride, c0, n, hl,
+                                                                      wl, glow, acc);
 }
 
 void launch_split_skip(const float* tmp, int ch_stride, int c0, int c1, int64_t npx,
                        float* gskip, hipStream_t s) {
-  k_split_skip<<<nblk(npx * c1), 256, 0, s>>>(tmp, ch_stride, c0, c1, npx, gskip);
+  if (c0 % 4 == 0 && c1 % 4 == 0 && ch_stride % 4 == 0)
+    k_split_skip<4><<<nblk(npx * c1 / 4), 256, 0, s>>>(tmp, ch_stride, c0, c1, npx, gskip);
+  else
+    k_split_skip<1><<<nblk(npx * c1), 256, 0, s>>>(tmp, ch_stride, c0, c1, npx, gskip);
 }
 
 void launch_pool_bwd_add(const float* gp, int n, int h, int w, int c, float* g, hipStream_t s) {
-  k_pool_bwd_add<<<nblk((int64_t)n * h * w * c), 256, 0, s>>>(gp, n, h, w, c, g);
+  if (c % 4 == 0)
+    k_pool_bwd_add<4><<<nblk((int64_t)n * h * w * c / 4), 256, 0, s>>>(gp, n, h, w, c, g);
+  else
+    k_pool_bwd_add<1><<<nblk((int64_t)n * h * w * c), 256, 0, s>>>(gp, n, h, w, c, g);
 }
 
 int wgrad_chunks(int n, int h, int w, int ci, int co) {
@@ -967,7 +1085,10 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
                                         param_offset(14), param_offset(15), tmp, G(T_D0B));
   const int hchunks = kHeadChunks;
   k_heads_wgrad<<<hchunks, 256, 0, s>>>(tmp, ws + p.t[T_D0B], npx, hchunks, part);
-  k_heads_reduce<<<4, 256, 0, s>>>(part, hchunks, param_offset(14), param_offset(15), grad);
+  float* part2 = (float*)(ws + tp.part2);
+  k_wgrad_reduce<<<dim3(nblk(28 * 33), kReduceSlices), 256, 0, s>>>(part, hchunks, 28 * 33,
+                                                                    part2);
+  k_heads_reduce<<<4, 256, 0, s>>>(part2, param_offset(14), param_offset(15), grad);
   if ((st = launch_status("heads backward")) != FV_OK) return st;
   for (int l = kNumConv - 1; l >= 0; --l) {
     const LayerDesc& L = kLayers[l];
@@ -995,7 +1116,6 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
     dim3 gw((unsigned)(cig_n * ((L.co + 31) / 32)), (unsigned)tp.chunks[l]);
     k_wgrad<<<gw, 256, 0, s>>>(in, dz, ci_tot, L.co, cig_n, tp.chunks[l], part);
     const int64_t cnt = 9 * (int64_t)ci_tot * L.co + L.co;
-    float* part2 = (float*)(ws + tp.part2);
     k_wgrad_reduce<<<dim3(nblk(cnt), kReduceSlices), 256, 0, s>>>(part, tp.chunks[l], cnt, part2);
     k_wgrad_reduce2<<<nblk(cnt), 256, 0, s>>>(part2, cnt, grad + param_offset(l));
     if ((st = launch_status("wgrad")) != FV_OK) return st;
@@ -1038,9 +1158,8 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
     }
     if (concat) {
       const int hl = hh / 2, wl = ww / 2;
-      k_upsample_bwd<<<nblk((int64_t)p.n * hl * wl * L.c0), 256, 0, s>>>(
-          tmp, L.c0 + L.c1, L.c0, p.n, hl, wl, G(io[0]), 0);
-      k_split_skip<<<nblk(px * L.c1), 256, 0, s>>>(tmp, L.c0 + L.c1, L.c0, L.c1, px, G(io[1]));
+      launch_upsample_bwd(tmp, L.c0 + L.c1, L.c0, p.n, hl, wl, G(io[0]), 0, s);
+      launch_split_skip(tmp, L.c0 + L.c1, L.c0, L.c1, px, G(io[1]), s);
     }
     // the pooled input's gradient flows back to the pooled tensor's source
     int src = -1;
@@ -1048,8 +1167,7 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
     if (io[0] == T_P1) src = T_E1B;
     if (io[0] == T_P2) src = T_E2B;
     if (src >= 0)
-      k_pool_bwd_add<<<nblk(px * 4 * L.c0), 256, 0, s>>>(G(io[0]), p.n, hh * 2, ww * 2, L.c0,
-                                                          G(src));
+      launch_pool_bwd_add(G(io[0]), p.n, hh * 2, ww * 2, L.c0, G(src), s);
     if ((st = launch_status("dgrad")) != FV_OK) return st;
   }
   if (grad_out) {
