@@ -120,35 +120,61 @@ __global__ void __launch_bounds__(256) k_ssim_h(const float* __restrict__ out,
 
 // vertical filter -> SSIM map and its partial derivatives w.r.t. mu_x,
 // E[x^2] and E[x t]; block sums of the map (double) for the loss value
+// A thread of the vertical passes computes kSsimRows consecutive output rows
+// of one column, sliding over the input rows it shares between them; every
+// output sums its 11 taps in tap order.
+constexpr int kSsimRows = 8;
+
 __global__ void __launch_bounds__(256) k_ssim_v(const float* __restrict__ hq, int n, int h, int w,
                                                 float* __restrict__ dmap,
                                                 double* __restrict__ red) {
   __shared__ double sh[256];
-  const int wv = w - 10, hv = h - 10;
+  const int wv = w - 10, hv = h - 10, nyb = (hv + kSsimRows - 1) / kSsimRows;
   const int64_t q = (int64_t)n * 3;
   const int64_t htot = q * h * wv, vtot = q * hv * wv;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double sval = 0.0;
-  if (e < vtot) {
+  if (e < q * nyb * wv) {
     const int x = (int)(e % wv);
     const int64_t r = e / wv;
-    const int y = (int)(r % hv);
-    const int64_t pl = r / hv;
-    float m[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-    for (int k = 0; k < 11; ++k) {
-      const int64_t hi = (pl * h + y + k) * wv + x;
-      for (int j = 0; j < 5; ++j) m[j] = fmaf(c_gauss[k], hq[j * htot + hi], m[j]);
+    const int y0 = (int)(r % nyb) * kSsimRows;
+    const int64_t pl = r / nyb;
+    float m[kSsimRows][5];
+#pragma unroll
+    for (int o = 0; o < kSsimRows; ++o)
+#pragma unroll
+      for (int j = 0; j < 5; ++j) m[o][j] = 0.f;
+    // input row y0 + t feeds output y0 + o with tap k = t - o
+#pragma unroll
+    for (int t = 0; t < kSsimRows + 10; ++t) {
+      if (y0 + t >= h) break;
+      const int64_t hi = (pl * h + y0 + t) * wv + x;
+      float v[5];
+#pragma unroll
+      for (int j = 0; j < 5; ++j) v[j] = hq[j * htot + hi];
+#pragma unroll
+      for (int o = 0; o < kSsimRows; ++o) {
+        const int k = t - o;
+        if (k >= 0 && k < 11)
+#pragma unroll
+          for (int j = 0; j < 5; ++j) m[o][j] = fmaf(c_gauss[k], v[j], m[o][j]);
+      }
     }
     const float C1 = 1e-4f, C2 = 9e-4f;
-    const float mx = m[0], my = m[1];
-    const float vx = m[2] - mx * mx, vy = m[3] - my * my, cxy = m[4] - mx * my;
-    const float A1 = 2 * mx * my + C1, A2 = 2 * cxy + C2;
-    const float B1 = mx * mx + my * my + C1, B2 = vx + vy + C2;
-    const float S = A1 * A2 / (B1 * B2);
-    sval = S;
-    dmap[e] = (2 * my * A2 - 2 * my * A1) / (B1 * B2) - S * (2 * mx / B1 - 2 * mx / B2);
-    dmap[vtot + e] = -S / B2;
-    dmap[2 * vtot + e] = 2 * A1 / (B1 * B2);
+#pragma unroll
+    for (int o = 0; o < kSsimRows; ++o) {
+      if (y0 + o >= hv) break;
+      const float mx = m[o][0], my = m[o][1];
+      const float vx = m[o][2] - mx * mx, vy = m[o][3] - my * my, cxy = m[o][4] - mx * my;
+      const float A1 = 2 * mx * my + C1, A2 = 2 * cxy + C2;
+      const float B1 = mx * mx + my * my + C1, B2 = vx + vy + C2;
+      const float S = A1 * A2 / (B1 * B2);
+      sval += S;
+      const int64_t ev = (pl * hv + y0 + o) * wv + x;
+      dmap[ev] = (2 * my * A2 - 2 * my * A1) / (B1 * B2) - S * (2 * mx / B1 - 2 * mx / B2);
+      dmap[vtot + ev] = -S / B2;
+      dmap[2 * vtot + ev] = 2 * A1 / (B1 * B2);
+    }
   }
   sh[threadIdx.x] = sval;
   __syncthreads();
@@ -162,23 +188,45 @@ __global__ void __launch_bounds__(256) k_ssim_v(const float* __restrict__ hq, in
 // adjoint of the vertical filter for the three partial maps
 __global__ void __launch_bounds__(256) k_ssim_vt(const float* __restrict__ dmap, int n, int h,
                                                  int w, float* __restrict__ va) {
-  const int wv = w - 10, hv = h - 10;
+  const int wv = w - 10, hv = h - 10, nyb = (h + kSsimRows - 1) / kSsimRows;
   const int64_t q = (int64_t)n * 3;
   const int64_t htot = q * h * wv, vtot = q * hv * wv;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= htot) return;
+  if (e >= q * nyb * wv) return;
   const int x = (int)(e % wv);
   const int64_t r = e / wv;
-  const int y = (int)(r % h);
-  const int64_t pl = r / h;
-  float s[3] = {0.f, 0.f, 0.f};
-  for (int k = 0; k < 11; ++k) {
-    const int yy = y - k;
+  const int y0 = (int)(r % nyb) * kSsimRows;
+  const int64_t pl = r / nyb;
+  float s[kSsimRows][3];
+#pragma unroll
+  for (int o = 0; o < kSsimRows; ++o)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) s[o][j] = 0.f;
+  // map row yy = y0 + kSsimRows - 1 - t feeds output y0 + o with tap
+  // k = y0 + o - yy, increasing with t as each output's sum requires
+#pragma unroll
+  for (int t = 0; t < kSsimRows + 10; ++t) {
+    const int yy = y0 + kSsimRows - 1 - t;
     if (yy < 0 || yy >= hv) continue;
     const int64_t vi = (pl * hv + yy) * wv + x;
-    for (int j = 0; j < 3; ++j) s[j] = fmaf(c_gauss[k], dmap[j * vtot + vi], s[j]);
+    float v[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) v[j] = dmap[j * vtot + vi];
+#pragma unroll
+    for (int o = 0; o < kSsimRows; ++o) {
+      const int k = o - (kSsimRows - 1) + t;
+      if (k >= 0 && k < 11)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) s[o][j] = fmaf(c_gauss[k], v[j], s[o][j]);
+    }
   }
-  for (int j = 0; j < 3; ++j) va[j * htot + e] = s[j];
+#pragma unroll
+  for (int o = 0; o < kSsimRows; ++o) {
+    if (y0 + o >= h) break;
+    const int64_t ev = (pl * h + y0 + o) * wv + x;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) va[j * htot + ev] = s[o][j];
+  }
 }
 
 // adjoint of the horizontal filter, combined into d loss / d out, plus the
@@ -225,16 +273,18 @@ __global__ void __launch_bounds__(256) k_ssim_ht(const float* __restrict__ va,
 }
 
 // fixed-order sums of the block partials -> [loss, ssim, l1]
-__global__ void k_loss_final(const double* __restrict__ rs, int ns, const double* __restrict__ rl,
-                             int nl, double ssim_scale, double l1_scale, float* __restrict__ out) {
-  __shared__ double a[256], c[256];
+__global__ void __launch_bounds__(1024) k_loss_final(const double* __restrict__ rs, int ns,
+                                                     const double* __restrict__ rl, int nl,
+                                                     double ssim_scale, double l1_scale,
+                                                     float* __restrict__ out) {
+  __shared__ double a[1024], c[1024];
   double sa = 0.0, sc = 0.0;
-  for (int i = threadIdx.x; i < ns; i += 256) sa += rs[i];
-  for (int i = threadIdx.x; i < nl; i += 256) sc += rl[i];
+  for (int i = threadIdx.x; i < ns; i += 1024) sa += rs[i];
+  for (int i = threadIdx.x; i < nl; i += 1024) sc += rl[i];
   a[threadIdx.x] = sa;
   c[threadIdx.x] = sc;
   __syncthreads();
-  for (int st = 128; st; st >>= 1) {
+  for (int st = 512; st; st >>= 1) {
     if (threadIdx.x < st) {
       a[threadIdx.x] += a[threadIdx.x + st];
       c[threadIdx.x] += c[threadIdx.x + st];
@@ -311,57 +361,16 @@ __global__ void __launch_bounds__(256) k_rgb_of_rgba(const float4* __restrict__ 
 
 // ----------------------------------------------------------- heads backward
 
-// The 28 head-input gradients of pixel p: the direct head's (the gradient of
-// O_d at p, gathered over every pixel whose clamped 5x5 tap lands on p) and
-// the 25 kernel logits' (softmax backward of dw = dout . O_d(tap)).
-__device__ __forceinline__ void head_grad28(const float* __restrict__ dout,
-                                            const float* __restrict__ od,
-                                            const float* __restrict__ wk, int h, int w,
-                                            int64_t p, float d[28]) {
-  const int x = (int)(p % w);
-  const int64_t r = p / w;
-  const int y = (int)(r % h), b = (int)(r / h);
-  const float g0 = dout[p * 3], g1 = dout[p * 3 + 1], g2 = dout[p * 3 + 2];
-  float dw[25], wl[25];
-  float dot = 0.f;
-  for (int dy = -2; dy <= 2; ++dy)
-    for (int dx = -2; dx <= 2; ++dx) {
-      const int k = 5 * (dy + 2) + (dx + 2);
-      const int yy = min(max(y + dy, 0), h - 1), xx = min(max(x + dx, 0), w - 1);
-      const int64_t q = ((int64_t)b * h + yy) * w + xx;
-      dw[k] = g0 * od[q * 3] + g1 * od[q * 3 + 1] + g2 * od[q * 3 + 2];
-      wl[k] = wk[p * 25 + k];
-      dot = fmaf(wl[k], dw[k], dot);
-    }
-  for (int k = 0; k < 25; ++k) d[3 + k] = wl[k] * (dw[k] - dot);
-  // d O_d(p): every pixel q whose clamped tap k lands on p, in the order
-  // (dy, dx, qy, qx); per axis the q are p - d inside the image, widened to
-  // the edge when p is an edge pixel
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-  for (int dy = -2; dy <= 2; ++dy) {
-    const int ylo = max(y == 0 ? 0 : y - dy, 0), yhi = min(y == h - 1 ? h - 1 : y - dy, h - 1);
-    for (int dx = -2; dx <= 2; ++dx) {
-      const int xlo = max(x == 0 ? 0 : x - dx, 0), xhi = min(x == w - 1 ? w - 1 : x - dx, w - 1);
-      const int k = 5 * (dy + 2) + (dx + 2);
-      for (int py = ylo; py <= yhi; ++py)
-        for (int px = xlo; px <= xhi; ++px) {
-          const int64_t q = ((int64_t)b * h + py) * w + px;
-          const float wq = wk[q * 25 + k];
-          a0 = fmaf(wq, dout[q * 3], a0);
-          a1 = fmaf(wq, dout[q * 3 + 1], a1);
-          a2 = fmaf(wq, dout[q * 3 + 2], a2);
-        }
-    }
-  }
-  d[0] = a0;
-  d[1] = a1;
-  d[2] = a2;
-}
-
 // Per pixel: d w_k = sum_c dout_c(p) O_d,c(clamp(p + delta_k)); d logits by
 // the softmax Jacobian; d O_d(p) gathered from every pixel whose clamped tap
 // lands on p; d H_d = W_heads^T [d O_d; d logits].  Writes d28 = [d O_d,
 // d logits] (for the heads' weight gradient) and the FP32 gradient of H_d.
+// Block = one 16 x 16 tile of one image.  The kernel weights, O_d and dout
+// of the tile and its 2-pixel border are staged in LDS, rows and columns
+// clamped to the image (what the clamped taps read; every pixel a gather
+// visits lies inside the image and within 2 pixels of the tile).  The
+// outputs then leave through the same LDS in whole 16-byte units.
+constexpr int kHT = 16, kHH = kHT + 4;  // tile side, tile + border
 __global__ void __launch_bounds__(256) k_heads_bwd(const float* __restrict__ dout,
                                                    const float* __restrict__ od,
                                                    const float* __restrict__ wk, int n, int h,
@@ -371,26 +380,103 @@ __global__ void __launch_bounds__(256) k_heads_bwd(const float* __restrict__ dou
                                                    float* __restrict__ gh) {
   // the BF16-rounded head weights (the forward's), [28 outputs][32 inputs]
   __shared__ float sw[28 * 32];
-  // the block's outputs, staged so that they leave in whole 16-byte units:
-  // d28 in its global layout (28 floats a pixel), then gh (32 floats a
-  // pixel, rows padded to 36 against bank conflicts)
-  __shared__ __attribute__((aligned(16))) float so[256 * 36];
-  for (int i = threadIdx.x; i < 28 * 32; i += 256)
+  // kernel weights of the bordered tile [20 x 20 pixels][25]; afterwards the
+  // outputs: d28 (28 floats a pixel), then gh (rows padded to 36 floats)
+  __shared__ __attribute__((aligned(16))) float swk[kHH * kHH * 25];
+  __shared__ float sod[kHH * kHH * 3], sdo[kHH * kHH * 3];
+  const int tid = threadIdx.x;
+  const int x0 = blockIdx.x * kHT, y0 = blockIdx.y * kHT, b = blockIdx.z;
+  for (int i = tid; i < 28 * 32; i += 256)
     sw[i] = (float)(__bf16)(i < 3 * 32 ? params[off_hd + i] : params[off_hk + i - 3 * 32]);
+  // every staging load is issued before the first LDS store (one memory
+  // round trip per block): 40 kernel-weight values and 10 of O_d / dout per
+  // thread
+  constexpr int kNW = kHH * kHH * 25, kNO = kHH * kHH * 3;
+  constexpr int kUW = (kNW + 255) / 256, kUO = (kNO + 255) / 256;
+  float vw[kUW], vo[kUO], vd[kUO];
+#pragma unroll
+  for (int u = 0; u < kUW; ++u) {
+    const int e = tid + 256 * u;
+    if (e < kNW) {
+      const int pix = e / 25, k = e - 25 * pix, r = pix / kHH, c = pix - r * kHH;
+      const int yy = min(max(y0 - 2 + r, 0), h - 1), xx = min(max(x0 - 2 + c, 0), w - 1);
+      vw[u] = wk[(((int64_t)b * h + yy) * w + xx) * 25 + k];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kUO; ++u) {
+    const int e = tid + 256 * u;
+    if (e < kNO) {
+      const int pix = e / 3, j = e - 3 * pix, r = pix / kHH, c = pix - r * kHH;
+      const int yy = min(max(y0 - 2 + r, 0), h - 1), xx = min(max(x0 - 2 + c, 0), w - 1);
+      const int64_t q = ((int64_t)b * h + yy) * w + xx;
+      vo[u] = od[q * 3 + j];
+      vd[u] = dout[q * 3 + j];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kUW; ++u)
+    if (tid + 256 * u < kNW) swk[tid + 256 * u] = vw[u];
+#pragma unroll
+  for (int u = 0; u < kUO; ++u)
+    if (tid + 256 * u < kNO) {
+      sod[tid + 256 * u] = vo[u];
+      sdo[tid + 256 * u] = vd[u];
+    }
   __syncthreads();
-  const int64_t p0 = (int64_t)blockIdx.x * 256, p = p0 + threadIdx.x;
-  const int64_t npx = (int64_t)n * h * w;
-  const int np = (int)min((int64_t)256, npx - p0);
+  const int tx = tid & 15, ty = tid >> 4, x = x0 + tx, y = y0 + ty;
   float d[28];
-  if (p < npx) head_grad28(dout, od, wk, h, w, p, d);
-  else
+  if (x < w && y < h) {
+    const int c0 = (ty + 2) * kHH + tx + 2;  // this pixel in the bordered tile
+    const float g0 = sdo[c0 * 3], g1 = sdo[c0 * 3 + 1], g2 = sdo[c0 * 3 + 2];
+    float dw[25], wl[25];
+    float dot = 0.f;
+    for (int dy = -2; dy <= 2; ++dy)
+      for (int dx = -2; dx <= 2; ++dx) {
+        const int k = 5 * (dy + 2) + (dx + 2);
+        const int qn = c0 + dy * kHH + dx;  // clamp(p + delta_k), as staged
+        dw[k] = g0 * sod[qn * 3] + g1 * sod[qn * 3 + 1] + g2 * sod[qn * 3 + 2];
+        wl[k] = swk[c0 * 25 + k];
+        dot = fmaf(wl[k], dw[k], dot);
+      }
+    for (int k = 0; k < 25; ++k) d[3 + k] = wl[k] * (dw[k] - dot);
+    // d O_d(p): every pixel q whose clamped tap k lands on p, in the order
+    // (dy, dx, qy, qx); per axis the q are p - d inside the image, widened to
+    // the edge when p is an edge pixel
+    float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+    for (int dy = -2; dy <= 2; ++dy) {
+      const int ylo = max(y == 0 ? 0 : y - dy, 0), yhi = min(y == h - 1 ? h - 1 : y - dy, h - 1);
+      for (int dx = -2; dx <= 2; ++dx) {
+        const int xlo = max(x == 0 ? 0 : x - dx, 0), xhi = min(x == w - 1 ? w - 1 : x - dx, w - 1);
+        const int k = 5 * (dy + 2) + (dx + 2);
+        for (int py = ylo; py <= yhi; ++py)
+          for (int px = xlo; px <= xhi; ++px) {
+            const int qn = (py - y0 + 2) * kHH + (px - x0 + 2);
+            const float wq = swk[qn * 25 + k];
+            a0 = fmaf(wq, sdo[qn * 3], a0);
+            a1 = fmaf(wq, sdo[qn * 3 + 1], a1);
+            a2 = fmaf(wq, sdo[qn * 3 + 2], a2);
+          }
+      }
+    }
+    d[0] = a0;
+    d[1] = a1;
+    d[2] = a2;
+  } else {
     for (int j = 0; j < 28; ++j) d[j] = 0.f;
-  float4* so4 = (float4*)so;
+  }
+  __syncthreads();  // the kernel weights are no longer needed: stage outputs
+  const int nx = min(kHT, w - x0), ny = min(kHT, h - y0);
+  float4* so4 = (float4*)swk;
   for (int q = 0; q < 7; ++q)
-    so4[threadIdx.x * 7 + q] = make_float4(d[4 * q], d[4 * q + 1], d[4 * q + 2], d[4 * q + 3]);
+    so4[tid * 7 + q] = make_float4(d[4 * q], d[4 * q + 1], d[4 * q + 2], d[4 * q + 3]);
   __syncthreads();
-  float4* o28 = (float4*)(d28 + p0 * 28);
-  for (int e = threadIdx.x; e < np * 7; e += 256) o28[e] = so4[e];
+  // d28: per tile row 7 nx units of 16 bytes, contiguous in memory
+  for (int e = tid; e < ny * 7 * kHT; e += 256) {
+    const int r = e / (7 * kHT), u = e - r * 7 * kHT;
+    if (u < 7 * nx)
+      ((float4*)(d28 + (((int64_t)b * h + y0 + r) * w + x0) * 28))[u] = so4[r * 7 * kHT + u];
+  }
   __syncthreads();
   for (int k4 = 0; k4 < 8; ++k4) {
     float v[4];
@@ -399,13 +485,16 @@ __global__ void __launch_bounds__(256) k_heads_bwd(const float* __restrict__ dou
       for (int c = 0; c < 28; ++c) sacc = fmaf(sw[c * 32 + 4 * k4 + i], d[c], sacc);
       v[i] = sacc;
     }
-    so4[threadIdx.x * 9 + k4] = make_float4(v[0], v[1], v[2], v[3]);
+    so4[tid * 9 + k4] = make_float4(v[0], v[1], v[2], v[3]);
   }
   __syncthreads();
-  float4* og = (float4*)(gh + p0 * 32);
-  for (int e = threadIdx.x; e < np * 8; e += 256) og[e] = so4[(e >> 3) * 9 + (e & 7)];
+  for (int e = tid; e < ny * 8 * kHT; e += 256) {
+    const int r = e / (8 * kHT), u = e - r * 8 * kHT;
+    if (u < 8 * nx)
+      ((float4*)(gh + (((int64_t)b * h + y0 + r) * w + x0) * 32))[u] =
+          so4[(r * kHT + (u >> 3)) * 9 + (u & 7)];
+  }
 }
-
 
 // Heads weight gradient partials: per chunk of pixels, d W[q][k] = sum d28[q] h[k]
 // and d b[q] = sum d28[q] (28 x 33 outputs), each summed over the chunk's
@@ -868,14 +957,16 @@ fv_status loss_run(const float* out_rgb, const float* target_rgba, int n, int h,
   float* hq = (float*)ssim;
   float* dmap = (float*)(ssim + al(htot * 4 * 5));
   float* va = (float*)(ssim + al(htot * 4 * 5) + al(vtot * 4 * 3));
-  const unsigned nbv = nblk(vtot), nbl = nblk(q * h * w);
+  const int64_t nyv = (h - 10 + kSsimRows - 1) / kSsimRows, nyt = (h + kSsimRows - 1) / kSsimRows;
+  const unsigned nbv = nblk(q * nyv * (w - 10)), nbl = nblk(q * h * w);
   k_ssim_h<<<nblk(htot), 256, 0, s>>>(out_rgb, tgt, n, h, w, hq);
   k_ssim_v<<<nbv, 256, 0, s>>>(hq, n, h, w, dmap, red);
-  k_ssim_vt<<<nblk(htot), 256, 0, s>>>(dmap, n, h, w, va);
+  k_ssim_vt<<<nblk(q * nyt * (w - 10)), 256, 0, s>>>(dmap, n, h, w, va);
   const double ssim_scale = 1.0 / (double)vtot, l1_scale = 1.0 / (double)(q * h * w);
   k_ssim_ht<<<nbl, 256, 0, s>>>(va, out_rgb, tgt, n, h, w, (float)ssim_scale, (float)l1_scale,
                                 dloss_dout, red + nbv);
-  k_loss_final<<<1, 256, 0, s>>>(red, (int)nbv, red + nbv, (int)nbl, ssim_scale, l1_scale, loss3);
+  k_loss_final<<<1, 1024, 0, s>>>(red, (int)nbv, red + nbv, (int)nbl, ssim_scale, l1_scale,
+                                   loss3);
   return launch_status("loss");
 }
 
@@ -1080,9 +1171,9 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
   float* part = (float*)(ws + tp.part);
   auto G = [&](int t) { return (float*)(ws + tp.g[t]); };
   // heads
-  k_heads_bwd<<<nblk(npx), 256, 0, s>>>(dloss_dout, (const float*)(ws + p.od),
-                                        (const float*)(ws + p.wk), p.n, p.h, p.w, n->master,
-                                        param_offset(14), param_offset(15), tmp, G(T_D0B));
+  k_heads_bwd<<<dim3((p.w + kHT - 1) / kHT, (p.h + kHT - 1) / kHT, p.n), 256, 0, s>>>(
+      dloss_dout, (const float*)(ws + p.od), (const float*)(ws + p.wk), p.n, p.h, p.w, n->master,
+      param_offset(14), param_offset(15), tmp, G(T_D0B));
   const int hchunks = kHeadChunks;
   k_heads_wgrad<<<hchunks, 256, 0, s>>>(tmp, ws + p.t[T_D0B], npx, hchunks, part);
   float* part2 = (float*)(ws + tp.part2);
