@@ -127,11 +127,17 @@ fv_status loss_run(const float* out_rgb, const float* target_rgba, int n, int h,
 fv_status tloss_run(const float* out_rgb, const float* target_rgba, int pairs, int h, int w,
                     float weight, float* loss, float* dloss_dout, double* red, hipStream_t s);
 void launch_relu_mask(const float* g, const uint8_t* y, uint8_t* dz, int64_t n8, hipStream_t s);
+// With dz set, the upsample and pool backward do not store the finished
+// FP32 gradient but dz = BF16(gradient x [gate > 0]), the masked output
+// gradient the ReLU mask pass would make from it (gate: the forward
+// activation, BF16, same layout).
 void launch_upsample_bwd(const float* gup, int ch_stride, int c0, int n, int hl, int wl,
-                         float* glow, int acc, hipStream_t s);
+                         float* glow, int acc, hipStream_t s, const uint8_t* gate = nullptr,
+                         uint8_t* dz = nullptr);
 void launch_split_skip(const float* tmp, int ch_stride, int c0, int c1, int64_t npx,
                        float* gskip, hipStream_t s);
-void launch_pool_bwd_add(const float* gp, int n, int h, int w, int c, float* g, hipStream_t s);
+void launch_pool_bwd_add(const float* gp, int n, int h, int w, int c, float* g, hipStream_t s,
+                         const uint8_t* gate = nullptr, uint8_t* dz = nullptr);
 int wgrad_chunks(int n, int h, int w, int ci, int co);
 size_t wgrad_part_bytes(int chunks, int ci, int co);
 size_t wgrad_part2_bytes(int ci, int co);

@@ -359,12 +359,36 @@ __global__ void __launch_bounds__(256) k_rgb_of_rgba(const float4* __restrict__ 
   dst[p * 3 + 2] = v.z;
 }
 
+// A finished output gradient stored as the next layer back needs it: dz =
+// BF16(v x [gate > 0]), the ReLU derivative of the forward activation gate
+// (BF16), exactly as the ReLU mask pass would store it.
+__device__ __forceinline__ float relu_gate(const uint8_t* gate, int64_t i, float v) {
+  return bf16_bits_to_f(((const uint16_t*)gate)[i]) > 0.f ? v : 0.f;
+}
+// the same for V consecutive channels from element i (V = 4: 8-byte accesses)
+template <int V>
+__device__ __forceinline__ void store_gated(uint8_t* dz, const uint8_t* gate, int64_t i,
+                                            const float* v) {
+  if constexpr (V == 4) {
+    const uint2 gb = *(const uint2*)(gate + i * 2);
+    const float r[4] = {bf16_bits_to_f(gb.x & 0xffffu) > 0.f ? v[0] : 0.f,
+                        bf16_bits_to_f(gb.x >> 16) > 0.f ? v[1] : 0.f,
+                        bf16_bits_to_f(gb.y & 0xffffu) > 0.f ? v[2] : 0.f,
+                        bf16_bits_to_f(gb.y >> 16) > 0.f ? v[3] : 0.f};
+    BF16::store4(dz + i * 2, r);
+  } else {
+    BF16::store1(dz + i * 2, relu_gate(gate, i, v[0]));
+  }
+}
+
 // ----------------------------------------------------------- heads backward
 
 // Per pixel: d w_k = sum_c dout_c(p) O_d,c(clamp(p + delta_k)); d logits by
 // the softmax Jacobian; d O_d(p) gathered from every pixel whose clamped tap
 // lands on p; d H_d = W_heads^T [d O_d; d logits].  Writes d28 = [d O_d,
-// d logits] (for the heads' weight gradient) and the FP32 gradient of H_d.
+// d logits] (for the heads' weight gradient) and, as H_d has no other
+// consumer, the last conv's masked output gradient: dz = BF16(d H_d x
+// [H_d > 0]) (H_d: the stored BF16 activation).
 // Block = one 16 x 16 tile of one image.  The kernel weights, O_d and dout
 // of the tile and its 2-pixel border are staged in LDS, rows and columns
 // clamped to the image (what the clamped taps read; every pixel a gather
@@ -377,7 +401,8 @@ __global__ void __launch_bounds__(256) k_heads_bwd(const float* __restrict__ dou
                                                    int w, const float* __restrict__ params,
                                                    int64_t off_hd, int64_t off_hk,
                                                    float* __restrict__ d28,
-                                                   float* __restrict__ gh) {
+                                                   const uint8_t* __restrict__ hd_act,
+                                                   uint8_t* __restrict__ dz) {
   // the BF16-rounded head weights (the forward's), [28 outputs][32 inputs]
   __shared__ float sw[28 * 32];
   // kernel weights of the bordered tile [20 x 20 pixels][25]; afterwards the
@@ -490,9 +515,11 @@ __global__ void __launch_bounds__(256) k_heads_bwd(const float* __restrict__ dou
   __syncthreads();
   for (int e = tid; e < ny * 8 * kHT; e += 256) {
     const int r = e / (8 * kHT), u = e - r * 8 * kHT;
-    if (u < 8 * nx)
-      ((float4*)(gh + (((int64_t)b * h + y0 + r) * w + x0) * 32))[u] =
-          so4[(r * kHT + (u >> 3)) * 9 + (u & 7)];
+    if (u < 8 * nx) {
+      const float4 g4 = so4[(r * kHT + (u >> 3)) * 9 + (u & 7)];
+      const float g[4] = {g4.x, g4.y, g4.z, g4.w};
+      store_gated<4>(dz, hd_act, (((int64_t)b * h + y0 + r) * w + x0) * 32 + 4 * u, g);
+    }
   }
 }
 
@@ -789,10 +816,13 @@ __device__ __forceinline__ float up_tap(int j, int q, int nlow) {
 
 // V consecutive channels per thread (V = 4 when the channel counts allow
 // 16-byte accesses); taps in row, then column order
+// (with dz set: the masked BF16 gradient instead of glow, see store_gated)
 template <int V>
 __global__ void __launch_bounds__(256) k_upsample_bwd(const float* __restrict__ gup, int ch_stride,
                                                       int c0, int n, int hl, int wl,
-                                                      float* __restrict__ glow, int acc) {
+                                                      float* __restrict__ glow, int acc,
+                                                      const uint8_t* __restrict__ gate,
+                                                      uint8_t* __restrict__ dz) {
   const int cg = c0 / V;
   const int64_t total = (int64_t)n * hl * wl * cg;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -833,7 +863,13 @@ __global__ void __launch_bounds__(256) k_upsample_bwd(const float* __restrict__ 
   }
   float* o = glow + pix * c0 + c;
 #pragma unroll
-  for (int v = 0; v < V; ++v) o[v] = acc ? o[v] + s[v] : s[v];
+  for (int v = 0; v < V; ++v) s[v] = acc ? o[v] + s[v] : s[v];
+  if (dz) {
+    store_gated<V>(dz, gate, pix * c0 + c, s);
+  } else {
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = s[v];
+  }
 }
 
 // copy channels [c0, c0 + c1) of the transposed-conv output into the skip
@@ -859,7 +895,9 @@ __global__ void __launch_bounds__(256) k_split_skip(const float* __restrict__ tm
 // channels per thread
 template <int V>
 __global__ void __launch_bounds__(256) k_pool_bwd_add(const float* __restrict__ gp, int n, int h,
-                                                      int w, int c, float* __restrict__ g) {
+                                                      int w, int c, float* __restrict__ g,
+                                                      const uint8_t* __restrict__ gate,
+                                                      uint8_t* __restrict__ dz) {
   const int cg = c / V;
   const int64_t total = (int64_t)n * h * w * cg;
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -871,6 +909,7 @@ __global__ void __launch_bounds__(256) k_pool_bwd_add(const float* __restrict__ 
   const int y = (int)(r % h), b = (int)(r / h);
   const float* src = gp + (((int64_t)b * (h / 2) + y / 2) * (w / 2) + x / 2) * c + ch;
   float* dst = g + pix * c + ch;
+  float res[V];
   if constexpr (V == 4) {
     const float4 t = *(const float4*)src;
     float4 d = *(float4*)dst;
@@ -878,9 +917,19 @@ __global__ void __launch_bounds__(256) k_pool_bwd_add(const float* __restrict__ 
     d.y += 0.25f * t.y;
     d.z += 0.25f * t.z;
     d.w += 0.25f * t.w;
-    *(float4*)dst = d;
+    res[0] = d.x;
+    res[1] = d.y;
+    res[2] = d.z;
+    res[3] = d.w;
   } else {
-    *dst += 0.25f * *src;
+    res[0] = *dst + 0.25f * *src;
+  }
+  if (dz) {
+    store_gated<V>(dz, gate, pix * c + ch, res);
+  } else if constexpr (V == 4) {
+    *(float4*)dst = make_float4(res[0], res[1], res[2], res[3]);
+  } else {
+    *dst = res[0];
   }
 }
 
@@ -987,13 +1036,13 @@ void launch_relu_mask(const float* g, const uint8_t* y, uint8_t* dz, int64_t n8,
 // (the 4-channel forms need 16-byte aligned tensors, which workspace
 // offsets are, and channel counts that are multiples of 4)
 void launch_upsample_bwd(const float* gup, int ch_stride, int c0, int n, int hl, int wl,
-                         float* glow, int acc, hipStream_t s) {
+                         float* glow, int acc, hipStream_t s, const uint8_t* gate, uint8_t* dz) {
   if (c0 % 4 == 0 && ch_stride % 4 == 0)
-    k_upsample_bwd<4><<<nblk((int64_t)n * hl * wl * c0 / 4), 256, 0, s>>>(gup, ch_stride, c0, n,
-                                                                         hl, wl, glow, acc);
+    k_upsample_bwd<4><<<nblk((int64_t)n * hl * wl * c0 / 4), 256, 0, s>>>(
+        gup, ch_stride, c0, n, hl, wl, glow, acc, gate, dz);
   else
-    k_upsample_bwd<1><<<nblk((int64_t)n * hl * wl * c0), 256, 0, s>>>(gup, ch_stride, c0, n, hl,
-                                                                      wl, glow, acc);
+    k_upsample_bwd<1><<<nblk((int64_t)n * hl * wl * c0), 256, 0, s>>>(
+        gup, ch_stride, c0, n, hl, wl, glow, acc, gate, dz);
 }
 
 void launch_split_skip(const float* tmp, int ch_stride, int c0, int c1, int64_t npx,
@@ -1004,11 +1053,13 @@ void launch_split_skip(const float* tmp, int ch_stride, int c0, int c1, int64_t 
     k_split_skip<1><<<nblk(npx * c1), 256, 0, s>>>(tmp, ch_stride, c0, c1, npx, gskip);
 }
 
-void launch_pool_bwd_add(const float* gp, int n, int h, int w, int c, float* g, hipStream_t s) {
+void launch_pool_bwd_add(const float* gp, int n, int h, int w, int c, float* g, hipStream_t s,
+                         const uint8_t* gate, uint8_t* dz) {
   if (c % 4 == 0)
-    k_pool_bwd_add<4><<<nblk((int64_t)n * h * w * c / 4), 256, 0, s>>>(gp, n, h, w, c, g);
+    k_pool_bwd_add<4><<<nblk((int64_t)n * h * w * c / 4), 256, 0, s>>>(gp, n, h, w, c, g, gate,
+                                                                       dz);
   else
-    k_pool_bwd_add<1><<<nblk((int64_t)n * h * w * c), 256, 0, s>>>(gp, n, h, w, c, g);
+    k_pool_bwd_add<1><<<nblk((int64_t)n * h * w * c), 256, 0, s>>>(gp, n, h, w, c, g, gate, dz);
 }
 
 int wgrad_chunks(int n, int h, int w, int ci, int co) {
@@ -1166,14 +1217,14 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
   float* grad = n->grad;
   float* tmp = (float*)(ws + tp.tmp);
   uint8_t* dz = ws + tp.dz;       // masked output gradient of layer l
-  uint8_t* dz_next = ws + tp.dz2;  // of layer l - 1, when the dgrad stores it
-  bool dz_ready = false;           // dz already holds layer l's masked gradient
+  uint8_t* dz_next = ws + tp.dz2;  // of layer l - 1, when layer l's kernels store it
+  bool dz_ready = true;            // dz already holds layer l's masked gradient
   float* part = (float*)(ws + tp.part);
   auto G = [&](int t) { return (float*)(ws + tp.g[t]); };
-  // heads
+  // heads (they also store the last conv's masked output gradient in dz)
   k_heads_bwd<<<dim3((p.w + kHT - 1) / kHT, (p.h + kHT - 1) / kHT, p.n), 256, 0, s>>>(
       dloss_dout, (const float*)(ws + p.od), (const float*)(ws + p.wk), p.n, p.h, p.w, n->master,
-      param_offset(14), param_offset(15), tmp, G(T_D0B));
+      param_offset(14), param_offset(15), tmp, ws + p.t[T_D0B], dz);
   const int hchunks = kHeadChunks;
   k_heads_wgrad<<<hchunks, 256, 0, s>>>(tmp, ws + p.t[T_D0B], npx, hchunks, part);
   float* part2 = (float*)(ws + tp.part2);
@@ -1186,8 +1237,8 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
     const int* io = kLayerIO[l];
     const int hh = p.h >> L.level, ww = p.w >> L.level;
     const int64_t px = (int64_t)p.n * hh * ww;
-    // ReLU derivative, BF16 copy of the output gradient (unless the input
-    // gradient conv of layer l + 1 stored it)
+    // ReLU derivative, BF16 copy of the output gradient (unless a kernel of
+    // layer l + 1 or the heads stored it)
     if (!dz_ready)
       k_relu_mask<<<nblk(px * L.co / 8), 256, 0, s>>>(G(io[2]), ws + p.t[io[2]], dz,
                                                       px * L.co / 8);
@@ -1247,9 +1298,16 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
       std::swap(dz, dz_next);
       dz_ready = true;
     }
+    // The upsampled source (e3b, d2b, d1b) is layer l - 1's output with no
+    // other consumer, and the pooled source (e0b, e1b, e2b) gets its last
+    // contribution (its skip gradient came earlier): either kernel stores
+    // layer l - 1's masked BF16 gradient instead of the FP32 one.
+    bool next_ready = false;
     if (concat) {
       const int hl = hh / 2, wl = ww / 2;
-      launch_upsample_bwd(tmp, L.c0 + L.c1, L.c0, p.n, hl, wl, G(io[0]), 0, s);
+      next_ready = io[0] == kLayerIO[l - 1][2];
+      launch_upsample_bwd(tmp, L.c0 + L.c1, L.c0, p.n, hl, wl, G(io[0]), 0, s,
+                          next_ready ? ws + p.t[io[0]] : nullptr, next_ready ? dz_next : nullptr);
       launch_split_skip(tmp, L.c0 + L.c1, L.c0, L.c1, px, G(io[1]), s);
     }
     // the pooled input's gradient flows back to the pooled tensor's source
@@ -1257,8 +1315,15 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
     if (io[0] == T_P0) src = T_E0B;
     if (io[0] == T_P1) src = T_E1B;
     if (io[0] == T_P2) src = T_E2B;
-    if (src >= 0)
-      launch_pool_bwd_add(G(io[0]), p.n, hh * 2, ww * 2, L.c0, G(src), s);
+    if (src >= 0) {
+      next_ready = src == kLayerIO[l - 1][2];
+      launch_pool_bwd_add(G(io[0]), p.n, hh * 2, ww * 2, L.c0, G(src), s,
+                          next_ready ? ws + p.t[src] : nullptr, next_ready ? dz_next : nullptr);
+    }
+    if (next_ready) {
+      std::swap(dz, dz_next);
+      dz_ready = true;
+    }
     if ((st = launch_status("dgrad")) != FV_OK) return st;
   }
   if (grad_out) {
