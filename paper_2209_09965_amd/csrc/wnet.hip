@@ -1069,10 +1069,17 @@ fv_status backward(fv_wnet* n, const float* dloss_dout, int views, int width, in
       std::swap(dz, dz_next);
       dz_ready = true;
     }
+    // The last contribution to conv l - 1's output gradient (the upsample
+    // backward for e3b, d2b, d1b after K's; the pool backward for e0b, e1b,
+    // e2b after the skip's) stores that conv's masked BF16 gradient instead.
+    bool next_ready = false;
     if (concat) {
       // the upsampled source (e3b, d2b, d1b) is also one of K's inputs,
       // whose gradient K has already written: add to it
-      net::launch_upsample_bwd(tmp, ci, L.c0, views, hh / 2, ww / 2, G(kIO[l][0]), 1, s);
+      next_ready = kIO[l][0] == kIO[l - 1][2];
+      net::launch_upsample_bwd(tmp, ci, L.c0, views, hh / 2, ww / 2, G(kIO[l][0]), 1, s,
+                               next_ready ? ws + p.t[kIO[l][0]] : nullptr,
+                               next_ready ? dz_next : nullptr);
       net::launch_split_skip(tmp, ci, L.c0, L.c1, m, G(kIO[l][1]), s);
     }
     // a pooled input's gradient flows back to the pooled tensor's source
@@ -1080,7 +1087,16 @@ fv_status backward(fv_wnet* n, const float* dloss_dout, int views, int width, in
     if (kIO[l][0] == T_P0) src = T_E0B;
     if (kIO[l][0] == T_P1) src = T_E1B;
     if (kIO[l][0] == T_P2) src = T_E2B;
-    if (src >= 0) net::launch_pool_bwd_add(G(kIO[l][0]), views, hh * 2, ww * 2, L.c0, G(src), s);
+    if (src >= 0) {
+      next_ready = src == kIO[l - 1][2];
+      net::launch_pool_bwd_add(G(kIO[l][0]), views, hh * 2, ww * 2, L.c0, G(src), s,
+                               next_ready ? ws + p.t[src] : nullptr,
+                               next_ready ? dz_next : nullptr);
+    }
+    if (next_ready) {
+      std::swap(dz, dz_next);
+      dz_ready = true;
+    }
     if ((st = launch_status("wnet: D backward")) != FV_OK) return st;
   }
   return st;
