@@ -26,7 +26,7 @@ fv_status check_frame(int views, int W, int H, const char* fn);
 
 static size_t al(size_t v) { return (v + 255) / 256 * 256; }
 
-constexpr int kWgRows = 8;         // tile rows of the weight-gradient kernel (x 16 columns)
+constexpr int kWgRows = 16;        // tile rows of the weight-gradient kernel (x 16 columns)
 constexpr int kHeadChunks = 1024;  // pixel chunks of the heads' weight gradient
 constexpr int kReduceSlices = 32;  // first-stage slices of the weight-gradient reduction
 
@@ -674,10 +674,10 @@ __device__ __forceinline__ uint4 conv_input8(const ConvArgs& a, int b, int y, in
 // pixels p of dz[p][co] x[p + tap][ci], a GEMM whose K dimension is the
 // pixels (BF16 operands as stored by the forward pass and the ReLU mask,
 // FP32 accumulation).  Block = 32 output x 32 input channels for all 9 taps
-// and one chunk of 8 x 16-pixel tiles; wave w owns the 16 x 16 channel pair
+// and one chunk of 16 x 16-pixel tiles; wave w owns the 16 x 16 channel pair
 // (w / 2, w % 2) and keeps its 9 tap accumulators (plus the bias, sum of dz,
 // as an MFMA against ones) in registers.  Each tile's dz and input patch
-// (10 x 18 pixels) are staged in LDS transposed, channel-major, so a lane's
+// (18 x 18 pixels) are staged in LDS transposed, channel-major, so a lane's
 // MFMA operand (8 consecutive pixels of one channel) is one 16-byte read;
 // the three horizontal taps of one row share a 10-pixel window (a 16- and a
 // 4-byte read, shifted by one and two pixels in registers).  K step s of a
