@@ -483,11 +483,12 @@ def main():
                                 "achieved_gbs": round(ach_gbs, 1),
                                 "frac_of_hbm_peak": round(ach_gbs / HBM_PEAK_GBS, 4)},
                 "note": "the stencil voxels are served by L2/MALL (L2 hit rate 0.94 with the "
-                        "linear copy, 0.67 of half as many requests with the bricked one); "
+                        "linear copy, 0.65 of half as many requests with the bricked one); "
                         "the HBM bytes actually moved (`traffic`) are under 10 % of the HBM "
                         "peak, so the bound is the vector ALU issue, not DRAM"}
     dn_avg = sum(dense_kernel_ms) / len(dense_kernel_ms)
     dense_ach = dense_samples / args.steps * bytes_per_sample / (dn_avg * 1e-3) / 1e9
+    dense_tflops = dense_samples / args.steps * flop_per_sample / (dn_avg * 1e-3) / 1e12
 
     out = {
         "metric": METRIC, "value": round(fov_ms, 4), "unit": "ms/frame", "n_gpus": 1,
@@ -533,7 +534,13 @@ def main():
                      "achieved_tflops": round(167968.0 * total / (sum(recon_ms) / len(recon_ms)
                                                                    * 1e-3) / 1e12, 1),
                      "peak_tflops": 5000.0 if args.precision == "fp8" else 2500.0},
-        "dense_roofline_frac": round(dense_ach / HBM_PEAK_GBS, 4),
+        "dense_roofline": {"bound": "alu", "kernel": "k_march_dense",
+                           "achieved": round(dense_tflops, 2), "peak": FP32_PEAK_TFLOPS,
+                           "unit": "TFLOP/s", "frac": round(dense_tflops / FP32_PEAK_TFLOPS, 4),
+                           "bytes_model": {"bytes_per_sample": bytes_per_sample,
+                                           "achieved_gbs": round(dense_ach, 1),
+                                           "frac_of_hbm_peak": round(dense_ach / HBM_PEAK_GBS,
+                                                                     4)}},
         "roofline": roofline,
     }
 
