@@ -451,17 +451,20 @@ fv_status launch_conv(const ConvArgs& args, int nb, hipStream_t s) {
   a.umagic = magic(g0);
   a.umagic8 = magic((uint32_t)a.c0 >> 3);  // (exact for the 2 x 2 block items too)
   // rows per wave: the largest R that still gives at least two blocks per CU
-  // (256 CUs) and whose patch fits in 48 KB of LDS; the weights are staged in
-  // LDS only while the block's LDS stays within 40 KB (four blocks per CU)
+  // (256 CUs) and whose patch fits in 48 KB of LDS (64 KB for BF16, whose
+  // wide concatenating layers would otherwise drop to one row per wave); the
+  // weights are staged in LDS only while the block's LDS stays within 40 KB
+  // (four blocks per CU)
   auto lds_of = [&](int r, int bl) {
     return r == 4 ? conv_lds_bytes<E, 4>(a.cip, a.c0, a.up0, a.kc, nb, a.co, bl)
                   : r == 2 ? conv_lds_bytes<E, 2>(a.cip, a.c0, a.up0, a.kc, nb, a.co, bl)
                            : conv_lds_bytes<E, 1>(a.cip, a.c0, a.up0, a.kc, nb, a.co, bl);
   };
+  const size_t patch_max = (E::kBytes == 2 ? 64 : 48) * 1024;
   int R = 4;
   while (R > 1) {
     const int64_t blocks = (int64_t)((a.w + 15) / 16) * ((a.h + 4 * R - 1) / (4 * R)) * a.n;
-    if (lds_of(R, 0) <= 48 * 1024 && blocks >= 512) break;
+    if (lds_of(R, 0) <= patch_max && blocks >= 512) break;
     R >>= 1;
   }
   if (nb >= 7 && R == 4) R = 2;  // 112+ accumulators per lane would spill
