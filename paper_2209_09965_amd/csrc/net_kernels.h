@@ -381,7 +381,6 @@ __device__ __forceinline__ void fuse0_fill(const ConvArgs& a, uint8_t* smem, int
   constexpr int PR = 4 * R + 2, PC = 18;       // this conv's patch
   constexpr int IR = 4 * R + 4, IC = 20;       // the packed-input patch
   constexpr int NBLK = (PR * PC + 15) / 16;    // 16-pixel blocks of the patch
-  constexpr int kOutside = (int)0x80000000u;
   typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int col = lane & 15, grp = lane >> 4;
@@ -538,7 +537,6 @@ __global__ void __launch_bounds__(256)
   constexpr int kPF = E::kBytes == 1 ? 6 : 8;  // fill items per thread in the first batch
   constexpr int kPW = 6;                      // weight loads (16 B) per thread in flight
   constexpr int kOutside = (int)0x80000000u;  // beyond every source (< 2 GiB)
-  using C8 = Chunk8<E>;
   using Item = uint4;  // 16 bytes: 16 FP8 channels (wide), else 8 channels
   typedef __attribute__((__vector_size__(4 * sizeof(int)))) int i4;
   const int S = patch_stride<E>(a.cip);  // patch pixel stride in elements

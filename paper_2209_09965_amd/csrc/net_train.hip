@@ -397,8 +397,8 @@ __device__ __forceinline__ void store_gated(uint8_t* dz, const uint8_t* gate, in
 constexpr int kHT = 16, kHH = kHT + 4;  // tile side, tile + border
 __global__ void __launch_bounds__(256) k_heads_bwd(const float* __restrict__ dout,
                                                    const float* __restrict__ od,
-                                                   const float* __restrict__ wk, int n, int h,
-                                                   int w, const float* __restrict__ params,
+                                                   const float* __restrict__ wk, int h, int w,
+                                                   const float* __restrict__ params,
                                                    int64_t off_hd, int64_t off_hk,
                                                    float* __restrict__ d28,
                                                    const uint8_t* __restrict__ hd_act,
@@ -1223,7 +1223,7 @@ fv_status fv_net_backward(fv_net* n, const float* dloss_dout, int batch, int wid
   auto G = [&](int t) { return (float*)(ws + tp.g[t]); };
   // heads (they also store the last conv's masked output gradient in dz)
   k_heads_bwd<<<dim3((p.w + kHT - 1) / kHT, (p.h + kHT - 1) / kHT, p.n), 256, 0, s>>>(
-      dloss_dout, (const float*)(ws + p.od), (const float*)(ws + p.wk), p.n, p.h, p.w, n->master,
+      dloss_dout, (const float*)(ws + p.od), (const float*)(ws + p.wk), p.h, p.w, n->master,
       param_offset(14), param_offset(15), tmp, ws + p.t[T_D0B], dz);
   const int hchunks = kHeadChunks;
   k_heads_wgrad<<<hchunks, 256, 0, s>>>(tmp, ws + p.t[T_D0B], npx, hchunks, part);
