@@ -92,30 +92,44 @@ TrainPlan make_train_plan(int n, int h, int w) {
 __constant__ float c_gauss[11];
 
 // horizontal 11-tap filter of x, t, x^2, t^2, x t (valid columns)
+// One thread per output pixel and all 3 colour planes (12 contiguous bytes
+// of each image per tap, lanes adjacent in x); every output sums its 11 taps
+// in tap order.
 __global__ void __launch_bounds__(256) k_ssim_h(const float* __restrict__ out,
                                                 const float* __restrict__ tgt, int n, int h, int w,
                                                 float* __restrict__ hq) {
   const int wv = w - 10;
   const int64_t q = (int64_t)n * 3;
   const int64_t total = q * h * wv;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= total) return;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;  // (image, row, column)
+  if (e >= (int64_t)n * h * wv) return;
   const int x = (int)(e % wv);
   const int64_t r = e / wv;
-  const int y = (int)(r % h);
-  const int64_t pl = r / h;
-  const int c = (int)(pl % 3), b = (int)(pl / 3);
-  float s[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  const int y = (int)(r % h), b = (int)(r / h);
+  float s[3][5];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) s[c][j] = 0.f;
   for (int k = 0; k < 11; ++k) {
     const int64_t p = ((int64_t)b * h + y) * w + x + k;
-    const float a = out[p * 3 + c], t = tgt[p * 3 + c], g = c_gauss[k];
-    s[0] = fmaf(g, a, s[0]);
-    s[1] = fmaf(g, t, s[1]);
-    s[2] = fmaf(g, a * a, s[2]);
-    s[3] = fmaf(g, t * t, s[3]);
-    s[4] = fmaf(g, a * t, s[4]);
+    const float g = c_gauss[k];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float a = out[p * 3 + c], t = tgt[p * 3 + c];
+      s[c][0] = fmaf(g, a, s[c][0]);
+      s[c][1] = fmaf(g, t, s[c][1]);
+      s[c][2] = fmaf(g, a * a, s[c][2]);
+      s[c][3] = fmaf(g, t * t, s[c][3]);
+      s[c][4] = fmaf(g, a * t, s[c][4]);
+    }
   }
-  for (int k = 0; k < 5; ++k) hq[k * total + e] = s[k];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t eo = (((int64_t)b * 3 + c) * h + y) * wv + x;  // plane b*3+c
+#pragma unroll
+    for (int k = 0; k < 5; ++k) hq[k * total + eo] = s[c][k];
+  }
 }
 
 // vertical filter -> SSIM map and its partial derivatives w.r.t. mu_x,
@@ -1008,7 +1022,7 @@ fv_status loss_run(const float* out_rgb, const float* target_rgba, int n, int h,
   float* va = (float*)(ssim + al(htot * 4 * 5) + al(vtot * 4 * 3));
   const int64_t nyv = (h - 10 + kSsimRows - 1) / kSsimRows, nyt = (h + kSsimRows - 1) / kSsimRows;
   const unsigned nbv = nblk(q * nyv * (w - 10)), nbl = nblk(q * h * w);
-  k_ssim_h<<<nblk(htot), 256, 0, s>>>(out_rgb, tgt, n, h, w, hq);
+  k_ssim_h<<<nblk((int64_t)n * h * (w - 10)), 256, 0, s>>>(out_rgb, tgt, n, h, w, hq);
   k_ssim_v<<<nbv, 256, 0, s>>>(hq, n, h, w, dmap, red);
   k_ssim_vt<<<nblk(q * nyt * (w - 10)), 256, 0, s>>>(dmap, n, h, w, va);
   const double ssim_scale = 1.0 / (double)vtot, l1_scale = 1.0 / (double)(q * h * w);
