@@ -245,6 +245,7 @@ __global__ void __launch_bounds__(256) k_ssim_vt(const float* __restrict__ dmap,
 
 // adjoint of the horizontal filter, combined into d loss / d out, plus the
 // L1 term and its block sums
+// one thread per pixel and all 3 colour planes, like k_ssim_h
 __global__ void __launch_bounds__(256) k_ssim_ht(const float* __restrict__ va,
                                                  const float* __restrict__ out,
                                                  const float* __restrict__ tgt, int n, int h,
@@ -254,28 +255,37 @@ __global__ void __launch_bounds__(256) k_ssim_ht(const float* __restrict__ va,
   __shared__ double sh[256];
   const int wv = w - 10;
   const int64_t q = (int64_t)n * 3;
-  const int64_t htot = q * h * wv, total = q * h * w;
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t htot = q * h * wv;
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;  // (image, row, column)
   double l1 = 0.0;
-  if (e < total) {
+  if (e < (int64_t)n * h * w) {
     const int x = (int)(e % w);
     const int64_t r = e / w;
-    const int y = (int)(r % h);
-    const int64_t pl = r / h;
-    const int c = (int)(pl % 3), b = (int)(pl / 3);
-    float s[3] = {0.f, 0.f, 0.f};
+    const int y = (int)(r % h), b = (int)(r / h);
+    float s[3][3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int j = 0; j < 3; ++j) s[c][j] = 0.f;
     for (int k = 0; k < 11; ++k) {
       const int xx = x - k;
       if (xx < 0 || xx >= wv) continue;
-      const int64_t hi = (pl * h + y) * wv + xx;
-      for (int j = 0; j < 3; ++j) s[j] = fmaf(c_gauss[k], va[j * htot + hi], s[j]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int64_t hi = (((int64_t)b * 3 + c) * h + y) * wv + xx;  // plane b*3+c
+#pragma unroll
+        for (int j = 0; j < 3; ++j) s[c][j] = fmaf(c_gauss[k], va[j * htot + hi], s[c][j]);
+      }
     }
     const int64_t p = ((int64_t)b * h + y) * w + x;
-    const float a = out[p * 3 + c], t = tgt[p * 3 + c];
-    const float dssim = s[0] + 2.0f * a * s[1] + t * s[2];
-    const float sg = (a > t) ? 1.0f : (a < t ? -1.0f : 0.0f);
-    dout[p * 3 + c] = -0.9f * ssim_scale * dssim + 0.1f * l1_scale * sg;
-    l1 = fabs((double)a - (double)t);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float a = out[p * 3 + c], t = tgt[p * 3 + c];
+      const float dssim = s[c][0] + 2.0f * a * s[c][1] + t * s[c][2];
+      const float sg = (a > t) ? 1.0f : (a < t ? -1.0f : 0.0f);
+      dout[p * 3 + c] = -0.9f * ssim_scale * dssim + 0.1f * l1_scale * sg;
+      l1 += fabs((double)a - (double)t);
+    }
   }
   sh[threadIdx.x] = l1;
   __syncthreads();
@@ -1021,7 +1031,7 @@ fv_status loss_run(const float* out_rgb, const float* target_rgba, int n, int h,
   float* dmap = (float*)(ssim + al(htot * 4 * 5));
   float* va = (float*)(ssim + al(htot * 4 * 5) + al(vtot * 4 * 3));
   const int64_t nyv = (h - 10 + kSsimRows - 1) / kSsimRows, nyt = (h + kSsimRows - 1) / kSsimRows;
-  const unsigned nbv = nblk(q * nyv * (w - 10)), nbl = nblk(q * h * w);
+  const unsigned nbv = nblk(q * nyv * (w - 10)), nbl = nblk((int64_t)n * h * w);
   k_ssim_h<<<nblk((int64_t)n * h * (w - 10)), 256, 0, s>>>(out_rgb, tgt, n, h, w, hq);
   k_ssim_v<<<nbv, 256, 0, s>>>(hq, n, h, w, dmap, red);
   k_ssim_vt<<<nblk(q * nyt * (w - 10)), 256, 0, s>>>(dmap, n, h, w, va);
